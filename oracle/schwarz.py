@@ -468,7 +468,7 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
     while True:
         r = b - A @ x
         beta = np.linalg.norm(r)
-        if fixed_iters == 0 and beta <= rtol * bnorm:
+        if beta == 0.0 or (fixed_iters == 0 and beta <= rtol * bnorm):
             status = OK
             break
         m = restart
@@ -490,7 +490,8 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
             for i in range(j + 1):
                 H[i, j] = V[i] @ w
                 w = w - H[i, j] * V[i]
-            H[j + 1, j] = np.linalg.norm(w)
+            hnext = np.linalg.norm(w)
+            H[j + 1, j] = hnext
             hcol = np.linalg.norm(H[: j + 2, j])
             for i in range(j):
                 t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
@@ -506,7 +507,7 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
             its += 1
             j_end = j + 1
             hist.append(abs(g[j + 1]) / bnorm)
-            breakdown = np.linalg.norm(w) <= BREAKDOWN_TOL * hcol
+            breakdown = hnext <= BREAKDOWN_TOL * hcol
             if fixed_iters:
                 if its >= fixed_iters:
                     stop = "fixed"
@@ -520,14 +521,14 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
             if breakdown:
                 stop = "breakdown"
                 break
-            V[j + 1] = w / H[j + 1, j]
+            V[j + 1] = w / hnext
         y = sla.solve_triangular(H[:j_end, :j_end], g[:j_end])
         if flexible:
             x = x + Zs[:j_end].T @ y
         else:
             x = x + Mv(V[:j_end].T @ y)
         if fixed_iters:
-            if stop == "fixed":
+            if stop in ("fixed", "breakdown"):
                 status = OK
                 break
             continue
