@@ -1,0 +1,288 @@
+"""ctypes binding of the ads C interface (include/ads.h).
+
+Argument marshalling only: every computational step runs in the library's HIP
+kernels.  The functions keep the C names; `Context` is a small convenience
+wrapper used by the tests and the benchmark.  Device buffers are passed as raw
+pointers (for example torch tensors' data_ptr()); host arrays as numpy arrays.
+Loading fails loudly when the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libads.so")
+
+ADS_ABI_VERSION = 1
+ADS_MAX_RESULTS = 64
+ADS_OK, ADS_KSP_MAXIT, ADS_KSP_BREAKDOWN = 0, 1, 2
+ADS_ERR_ARG, ADS_ERR_HIP, ADS_ERR_OOM, ADS_ERR_SINGULAR = -1, -2, -3, -4
+ADS_ERR_EIG_NOCONV, ADS_ERR_NAN, ADS_ERR_UNSUPPORTED = -5, -6, -7
+ADS_VARIANT_DEFLATED, ADS_VARIANT_RAS = 0, 1
+ADS_PREC_FP64, ADS_PREC_FP32, ADS_PREC_BF16 = 0, 1, 2
+
+# every symbol declared in include/ads.h
+SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_solve", "ads_get_info",
+           "ads_export_maps", "ads_export_splitting", "ads_export_coarse", "ads_partition_bfs",
+           "ads_destroy", "ads_status_string", "ads_last_error"]
+
+
+class ads_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class ads_options(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("overlap", C.c_int32), ("nev", C.c_int32),
+                ("tau", C.c_double), ("variant", C.c_int32), ("precision", C.c_int32),
+                ("warm_start", C.c_int32), ("eig_tol", C.c_double), ("eig_max_sweeps", C.c_int32),
+                ("gnn_weights_path", C.c_char_p)]
+
+
+class ads_ksp_options(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("flexible", C.c_int32), ("rtol", C.c_double),
+                ("maxit", C.c_int32), ("fixed_iters", C.c_int32)]
+
+
+class ads_ksp_result(C.Structure):
+    _fields_ = [("its", C.c_int32 * ADS_MAX_RESULTS), ("relres", C.c_double * ADS_MAX_RESULTS),
+                ("status", C.c_int32 * ADS_MAX_RESULTS), ("t_setup_ms", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+
+class ads_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("omega_total", C.c_int64), ("factor_bytes", C.c_int64),
+                ("nsys", C.c_int32), ("nsub", C.c_int32), ("n0", C.c_int32),
+                ("eig_sweeps_max", C.c_int32), ("eig_unconverged", C.c_int32),
+                ("eig_fallbacks", C.c_int32), ("t_phase_ms", C.c_double * 8),
+                ("nev_i", C.c_void_p), ("kernel_dim", C.c_void_p), ("n_i", C.c_void_p),
+                ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libads.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ads_setup.argtypes = [C.POINTER(ads_csr), P, I32, C.POINTER(ads_options), P, C.POINTER(P)]
+        L.ads_setup_batched.argtypes = [I32, C.POINTER(ads_csr), P, P, C.POINTER(ads_options), P,
+                                        C.POINTER(P)]
+        L.ads_apply.argtypes = [P, P, P, I32, P]
+        L.ads_solve.argtypes = [P, P, P, I32, C.POINTER(ads_ksp_options), C.POINTER(ads_ksp_result), P]
+        L.ads_get_info.argtypes = [P, C.POINTER(ads_info)]
+        L.ads_export_maps.argtypes = [P, P, P, P, P]
+        L.ads_export_splitting.argtypes = [P, P]
+        L.ads_export_coarse.argtypes = [P, P, P, P, P]
+        L.ads_partition_bfs.argtypes = [C.POINTER(ads_csr), I32, P, P, P]
+        L.ads_destroy.argtypes = [P]
+        L.ads_status_string.argtypes = [C.c_int]
+        L.ads_status_string.restype = C.c_char_p
+        L.ads_last_error.argtypes = []
+        L.ads_last_error.restype = C.c_char_p
+        for name in SYMBOLS:
+            if name not in ("ads_status_string", "ads_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class AdsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{ads_status_string(status)}: {msg}")
+        self.status = status
+
+
+def ads_status_string(status: int) -> str:
+    return lib().ads_status_string(status).decode()
+
+
+def ads_last_error() -> str:
+    return lib().ads_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise AdsError(status, ads_last_error())
+    return status
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None else None
+
+
+def make_csr(A):
+    """Host CSR (workloads.CSR or scipy.sparse) -> (ads_csr, keep-alive arrays)."""
+    if hasattr(A, "tocsr"):
+        A = A.tocsr()
+        A.sort_indices()
+        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+        v = np.ascontiguousarray(A.data, dtype=np.float64)
+        n = A.shape[0]
+    else:
+        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+        v = np.ascontiguousarray(A.data, dtype=np.float64)
+        n = A.n
+    s = ads_csr(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 0)
+    return s, (rp, ci, v)
+
+
+def options(overlap, nev, variant=ADS_VARIANT_DEFLATED, precision=ADS_PREC_FP64, tau=0.0,
+            eig_tol=0.0, eig_max_sweeps=0, warm_start=0, gnn_weights_path=None):
+    return ads_options(ADS_ABI_VERSION, overlap, nev, tau, variant, precision, warm_start, eig_tol,
+                       eig_max_sweeps, gnn_weights_path)
+
+
+def ads_setup(A, part, nparts, opts, stream=None):
+    return ads_setup_batched([A], [part], [nparts], opts, stream)
+
+
+def ads_setup_batched(As, parts, nparts, opts, stream=None):
+    nsys = len(As)
+    arr = (ads_csr * nsys)()
+    keep = []
+    pp = (C.c_void_p * nsys)()
+    parts_c = []
+    for k, (A, p) in enumerate(zip(As, parts)):
+        s, kk = make_csr(A)
+        arr[k] = s
+        keep.append(kk)
+        pc = np.ascontiguousarray(p, dtype=np.int32)
+        parts_c.append(pc)
+        pp[k] = pc.ctypes.data
+    npc = np.ascontiguousarray(nparts, dtype=np.int32)
+    out = C.c_void_p()
+    _check(lib().ads_setup_batched(nsys, arr, C.cast(pp, C.c_void_p), npc.ctypes.data,
+                                   C.byref(opts), stream, C.byref(out)))
+    return out
+
+
+def ads_apply(ctx, r_ptr, z_ptr, nrhs, stream=None):
+    return _check(lib().ads_apply(ctx, r_ptr, z_ptr, nrhs, stream))
+
+
+def ads_solve(ctx, b_ptr, x_ptr, nrhs, kopts, stream=None):
+    res = ads_ksp_result()
+    st = _check(lib().ads_solve(ctx, b_ptr, x_ptr, nrhs, C.byref(kopts), C.byref(res), stream))
+    return st, res
+
+
+def ads_get_info(ctx):
+    info = ads_info()
+    _check(lib().ads_get_info(ctx, C.byref(info)))
+    nsub = info.nsub
+    arrays = {k: np.zeros(nsub, np.int32) for k in ("nev_i", "kernel_dim", "n_i", "n_interior",
+                                                     "sweeps", "block")}
+    for k, a in arrays.items():
+        setattr(info, k, a.ctypes.data)
+    _check(lib().ads_get_info(ctx, C.byref(info)))
+    out = {f[0]: getattr(info, f[0]) for f in ads_info._fields_ if f[0] not in arrays}
+    out["t_phase_ms"] = list(info.t_phase_ms)
+    out.update(arrays)
+    return out
+
+
+def ads_export_maps(ctx):
+    info = ads_get_info(ctx)
+    tot, nsub = info["omega_total"], info["nsub"]
+    om = np.zeros(tot, np.int32)
+    off = np.zeros(nsub + 1, np.int64)
+    nI = np.zeros(nsub, np.int32)
+    lay = np.zeros(tot, np.int32)
+    _check(lib().ads_export_maps(ctx, om.ctypes.data, off.ctypes.data, nI.ctypes.data, lay.ctypes.data))
+    return om, off, nI, lay
+
+
+def ads_export_splitting(ctx):
+    info = ads_get_info(ctx)
+    s = np.zeros(info["omega_total"], np.float64)
+    _check(lib().ads_export_splitting(ctx, s.ctypes.data))
+    return s
+
+
+def ads_export_coarse(ctx):
+    info = ads_get_info(ctx)
+    nsub = info["nsub"]
+    woff = np.zeros(nsub + 1, np.int64)
+    _check(lib().ads_export_coarse(ctx, None, woff.ctypes.data, None, None))
+    W = np.zeros(max(int(woff[-1]), 1), np.float64)
+    lr = np.zeros(max(info["n0"], 1))
+    li = np.zeros(max(info["n0"], 1))
+    _check(lib().ads_export_coarse(ctx, W.ctypes.data, woff.ctypes.data, lr.ctypes.data, li.ctypes.data))
+    return W, woff, lr[: info["n0"]] + 1j * li[: info["n0"]], info
+
+
+def ads_partition_bfs(A, seeds, stream=None):
+    s, keep = make_csr(A)
+    sd = np.ascontiguousarray(seeds, dtype=np.int32)
+    out = np.zeros(s.n, np.int32)
+    _check(lib().ads_partition_bfs(C.byref(s), len(sd), sd.ctypes.data, out.ctypes.data, stream))
+    return out
+
+
+def ads_destroy(ctx):
+    if ctx is not None and ctx.value:
+        lib().ads_destroy(ctx)
+
+
+def ksp_options(restart=30, flexible=False, rtol=1e-8, maxit=1000, fixed_iters=0):
+    return ads_ksp_options(restart, int(flexible), rtol, maxit, fixed_iters)
+
+
+class Context:
+    """Owns an ads context; apply/solve take torch CUDA tensors (FP64)."""
+
+    def __init__(self, As, parts, nparts, overlap, nev, variant=ADS_VARIANT_DEFLATED,
+                 precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None):
+        if not isinstance(As, (list, tuple)):
+            As, parts, nparts = [As], [parts], [nparts]
+        self.opts = options(overlap, nev, variant, precision, tau, eig_tol, eig_max_sweeps)
+        self.stream = stream
+        self.ctx = ads_setup_batched(As, parts, nparts, self.opts, stream)
+        self.info = ads_get_info(self.ctx)
+        self.n = self.info["n"]
+        self.nsys = self.info["nsys"]
+
+    def apply(self, r, z=None):
+        import torch
+        nrhs = 1 if r.dim() == 1 else r.shape[1]
+        assert r.dtype == torch.float64 and r.is_cuda
+        rr = r if r.dim() == 1 else r.t().contiguous()  # column-major n x nrhs
+        zz = torch.empty_like(rr)
+        ads_apply(self.ctx, rr.data_ptr(), zz.data_ptr(), nrhs, self.stream)
+        return zz if r.dim() == 1 else zz.reshape(nrhs, self.n).t()
+
+    def solve(self, b, restart=30, flexible=False, rtol=1e-8, maxit=1000, fixed_iters=0):
+        import torch
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        bb = b if b.dim() == 1 else b.t().contiguous()
+        xx = torch.empty_like(bb)
+        st, res = ads_solve(self.ctx, bb.data_ptr(), xx.data_ptr(), nrhs,
+                            ksp_options(restart, flexible, rtol, maxit, fixed_iters), self.stream)
+        q = self.nsys * nrhs
+        out = dict(status=st, its=list(res.its[:q]), relres=list(res.relres[:q]),
+                   statuses=list(res.status[:q]), t_setup_ms=res.t_setup_ms,
+                   t_solve_ms=res.t_solve_ms)
+        x = xx if b.dim() == 1 else xx.reshape(nrhs, self.n).t()
+        return x, out
+
+    def close(self):
+        ads_destroy(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                self.close()
+        except Exception:
+            pass

@@ -1,0 +1,409 @@
+// C interface of the ads library (declared in include/ads.h): argument
+// validation, setup orchestration, exports.  No exception crosses the
+// interface; errors become status codes plus a thread-local message.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ads_internal.h"
+
+namespace ads {
+
+static thread_local std::string g_last_error;
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+static int handle(const Error& e) {
+  g_last_error = e.msg;
+  return e.code;
+}
+
+struct Timer {
+  hipStream_t s;
+  std::chrono::steady_clock::time_point t;
+  explicit Timer(hipStream_t st) : s(st) {
+    ADS_HIP(hipStreamSynchronize(s));
+    t = std::chrono::steady_clock::now();
+  }
+  double lap() {
+    ADS_HIP(hipStreamSynchronize(s));
+    auto now = std::chrono::steady_clock::now();
+    double ms = std::chrono::duration<double, std::milli>(now - t).count();
+    t = now;
+    return ms;
+  }
+};
+
+static void check_csr_host(const ads_csr& A, int sys) {
+  const std::string w = "system " + std::to_string(sys) + ": ";
+  if (A.n <= 0 || A.n >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, w + "n out of range");
+  if (A.nnz < 0 || A.nnz >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, w + "nnz out of range");
+  if (!A.row_ptr || !A.col || !A.val) fail(ADS_ERR_ARG, w + "null CSR array");
+  if (A.row_ptr[0] != 0 || A.row_ptr[A.n] != A.nnz) fail(ADS_ERR_ARG, w + "row_ptr bounds");
+  for (int64_t r = 0; r < A.n; ++r) {
+    if (A.row_ptr[r + 1] < A.row_ptr[r]) fail(ADS_ERR_ARG, w + "row_ptr not monotone");
+    for (int64_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
+      if (A.col[k] < 0 || A.col[k] >= A.n) fail(ADS_ERR_ARG, w + "column index out of range");
+      if (k > A.row_ptr[r] && A.col[k] <= A.col[k - 1])
+        fail(ADS_ERR_ARG, w + "columns not sorted/unique in row " + std::to_string(r));
+      if (!std::isfinite(A.val[k])) fail(ADS_ERR_NAN, w + "non-finite matrix entry");
+    }
+  }
+}
+
+// brings one system's CSR to the host (device input is copied back once)
+struct HostCSR {
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  ads_csr view{};
+};
+
+static void to_host(const ads_csr& A, HostCSR& h, hipStream_t s) {
+  if (!A.on_device) {
+    h.view = A;
+    return;
+  }
+  if (A.n <= 0 || A.nnz < 0) fail(ADS_ERR_ARG, "bad CSR sizes");
+  h.rp.resize(A.n + 1);
+  h.ci.resize(A.nnz);
+  h.v.resize(A.nnz);
+  ADS_HIP(hipMemcpyAsync(h.rp.data(), A.row_ptr, (A.n + 1) * 8, hipMemcpyDeviceToHost, s));
+  if (A.nnz) {
+    ADS_HIP(hipMemcpyAsync(h.ci.data(), A.col, A.nnz * 4, hipMemcpyDeviceToHost, s));
+    ADS_HIP(hipMemcpyAsync(h.v.data(), A.val, A.nnz * 8, hipMemcpyDeviceToHost, s));
+  }
+  ADS_HIP(hipStreamSynchronize(s));
+  h.view = A;
+  h.view.row_ptr = h.rp.data();
+  h.view.col = h.ci.data();
+  h.view.val = h.v.data();
+  h.view.on_device = 0;
+}
+
+static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, const int32_t* nparts,
+                       const ads_options* opts, hipStream_t st) {
+  if (nsys <= 0) fail(ADS_ERR_ARG, "nsys must be positive");
+  if (!A || !part || !nparts || !opts) fail(ADS_ERR_ARG, "null argument");
+  if (opts->abi_version != ADS_ABI_VERSION) fail(ADS_ERR_ARG, "abi_version mismatch");
+  if (opts->overlap < 0 || opts->overlap > 16) fail(ADS_ERR_ARG, "overlap must be in [0, 16]");
+  if (opts->nev < 0 || opts->nev > 30) fail(ADS_ERR_ARG, "nev must be in [0, 30]");
+  if (opts->variant != ADS_VARIANT_DEFLATED && opts->variant != ADS_VARIANT_RAS)
+    fail(ADS_ERR_ARG, "unknown variant");
+  if (opts->precision < ADS_PREC_FP64 || opts->precision > ADS_PREC_BF16)
+    fail(ADS_ERR_ARG, "unknown precision");
+  if (opts->warm_start != 0) fail(ADS_ERR_UNSUPPORTED, "warm_start requires the learned model");
+  auto c = new Ctx();
+  try {
+    c->stream = st;
+    c->opt = *opts;
+    c->prec = opts->precision;
+    c->nsys = nsys;
+    Timer tm(st);
+    auto t_start = std::chrono::steady_clock::now();
+    // concatenate the systems (block-diagonal matrix), validate, upload
+    c->sys_row.assign(nsys + 1, 0);
+    c->sys_sub.assign(nsys + 1, 0);
+    int64_t nnz = 0;
+    std::vector<HostCSR> hs(nsys);
+    for (int s = 0; s < nsys; ++s) {
+      to_host(A[s], hs[s], st);
+      check_csr_host(hs[s].view, s);
+      if (!part[s]) fail(ADS_ERR_ARG, "null partition");
+      if (nparts[s] <= 0) fail(ADS_ERR_ARG, "nparts must be positive");
+      c->sys_row[s + 1] = c->sys_row[s] + hs[s].view.n;
+      c->sys_sub[s + 1] = c->sys_sub[s] + nparts[s];
+      nnz += hs[s].view.nnz;
+    }
+    c->n = c->sys_row[nsys];
+    c->nnz = nnz;
+    c->nsub = c->sys_sub[nsys];
+    if (c->n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31))
+      fail(ADS_ERR_UNSUPPORTED, "total n and nnz must be < 2^31");
+    std::vector<int32_t> rp(c->n + 1), ci(nnz), pg(c->n);
+    std::vector<double> v(nnz);
+    c->sub_sys.resize(c->nsub);
+    for (int s = 0; s < nsys; ++s) {
+      const ads_csr& a = hs[s].view;
+      const int64_t r0 = c->sys_row[s], k0 = a.row_ptr[0];
+      int64_t base = 0;
+      for (int q = 0; q < s; ++q) base += hs[q].view.nnz;
+      for (int64_t r = 0; r < a.n; ++r) {
+        rp[r0 + r] = (int32_t)(base + a.row_ptr[r] - k0);
+        const int32_t p = part[s][r];
+        if (p < 0 || p >= nparts[s]) fail(ADS_ERR_ARG, "part value out of range in system " + std::to_string(s));
+        pg[r0 + r] = p + c->sys_sub[s];
+      }
+      for (int64_t k = 0; k < a.nnz; ++k) {
+        ci[base + k] = (int32_t)(a.col[k] + r0);
+        v[base + k] = a.val[k];
+      }
+      for (int q = c->sys_sub[s]; q < c->sys_sub[s + 1]; ++q) c->sub_sys[q] = s;
+    }
+    rp[c->n] = (int32_t)nnz;
+    c->rowptr = upload(c->mem, rp.data(), c->n + 1, st);
+    c->col = upload(c->mem, ci.data(), nnz, st);
+    c->val = upload(c->mem, v.data(), nnz, st);
+    c->sub_sys_d = upload(c->mem, c->sub_sys.data(), c->nsub, st);
+    c->t_phase_ms[5] += tm.lap();
+    build_maps(*c, pg);
+    c->t_phase_ms[0] = tm.lap();
+    extract_local(*c);
+    c->t_phase_ms[1] = tm.lap();
+    factor_local(*c);
+    c->t_phase_ms[2] = tm.lap();
+    const bool coarse = opts->variant == ADS_VARIANT_DEFLATED && opts->nev > 0;
+    if (coarse) {
+      eigensolve(*c);
+      c->t_phase_ms[3] = tm.lap();
+      if (c->n0 > 0) {
+        assemble_coarse(*c);
+        c->t_phase_ms[4] = tm.lap();
+      }
+      if (c->facT) {
+        c->mem.release(c->facT);
+        c->facT = nullptr;
+      }
+    } else {
+      c->n0 = 0;
+      c->h_nev.assign(c->nsub, 0);
+    }
+    ensure_work(*c, 1);
+    ADS_HIP(hipStreamSynchronize(st));
+    c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    delete c;
+    throw;
+  }
+  return c;
+}
+
+}  // namespace ads
+
+using namespace ads;
+
+struct ads_ctx {
+  Ctx* c;
+};
+
+extern "C" {
+
+int ads_setup(const ads_csr* A, const int32_t* part, int32_t nparts, const ads_options* opts,
+              void* hip_stream, ads_ctx** out) {
+  return ads_setup_batched(1, A, &part, &nparts, opts, hip_stream, out);
+}
+
+int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part,
+                      const int32_t* nparts, const ads_options* opts, void* hip_stream,
+                      ads_ctx** out) {
+  if (!out) {
+    g_last_error = "out is NULL";
+    return ADS_ERR_ARG;
+  }
+  *out = nullptr;
+  try {
+    Ctx* c = setup_impl(nsys, A, part, nparts, opts, (hipStream_t)hip_stream);
+    *out = new ads_ctx{c};
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return ADS_ERR_OOM;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return ADS_ERR_HIP;
+  }
+}
+
+int ads_apply(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, void* hip_stream) {
+  try {
+    if (!ctx || !r_dev || !z_dev) fail(ADS_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > 64) fail(ADS_ERR_ARG, "nrhs must be in [1, 64]");
+    if (r_dev == z_dev) fail(ADS_ERR_ARG, "r and z must not alias");
+    apply_prec(*ctx->c, r_dev, z_dev, nrhs, (hipStream_t)hip_stream);
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  } catch (...) {
+    g_last_error = "unknown error";
+    return ADS_ERR_HIP;
+  }
+}
+
+int ads_solve(ads_ctx* ctx, const double* b_dev, double* x_dev, int32_t nrhs,
+              const ads_ksp_options* kopts, ads_ksp_result* res, void* hip_stream) {
+  try {
+    if (!ctx || !b_dev || !x_dev || !kopts) fail(ADS_ERR_ARG, "null argument");
+    if (nrhs < 1 || ctx->c->nsys * nrhs > ADS_MAX_RESULTS)
+      fail(ADS_ERR_ARG, "nsys * nrhs must be in [1, 64]");
+    if (kopts->restart < 1 || kopts->restart > 64) fail(ADS_ERR_ARG, "restart must be in [1, 64]");
+    if (!(kopts->rtol >= 0.0)) fail(ADS_ERR_ARG, "rtol must be >= 0");
+    if (b_dev == x_dev) fail(ADS_ERR_ARG, "b and x must not alias");
+    if (res) std::memset(res, 0, sizeof(*res));
+    return gmres_solve(*ctx->c, b_dev, x_dev, nrhs, *kopts, res, (hipStream_t)hip_stream);
+  } catch (const Error& e) {
+    return handle(e);
+  } catch (...) {
+    g_last_error = "unknown error";
+    return ADS_ERR_HIP;
+  }
+}
+
+int ads_get_info(const ads_ctx* ctx, ads_info* info) {
+  try {
+    if (!ctx || !info) fail(ADS_ERR_ARG, "null argument");
+    const Ctx& c = *ctx->c;
+    info->n = c.n;
+    info->omega_total = c.omega_total;
+    info->factor_bytes = c.factor_bytes;
+    info->nsys = c.nsys;
+    info->nsub = c.nsub;
+    info->n0 = c.n0;
+    info->eig_sweeps_max = c.eig_sweeps_max;
+    info->eig_unconverged = c.eig_unconverged;
+    info->eig_fallbacks = c.eig_fallbacks;
+    for (int k = 0; k < 8; ++k) info->t_phase_ms[k] = c.t_phase_ms[k];
+    for (int i = 0; i < c.nsub; ++i) {
+      if (info->nev_i) info->nev_i[i] = c.h_nev.empty() ? 0 : c.h_nev[i];
+      if (info->kernel_dim) info->kernel_dim[i] = c.h_kdim[i];
+      if (info->n_i) info->n_i[i] = c.h_ni[i];
+      if (info->n_interior) info->n_interior[i] = c.h_nI[i];
+      if (info->sweeps) info->sweeps[i] = c.h_sweeps.empty() ? 0 : c.h_sweeps[i];
+      if (info->block) info->block[i] = c.h_bs[i];
+    }
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  }
+}
+
+int ads_export_maps(const ads_ctx* ctx, int32_t* omega_concat, int64_t* omega_off,
+                    int32_t* n_interior, int32_t* layer) {
+  try {
+    if (!ctx) fail(ADS_ERR_ARG, "null context");
+    const Ctx& c = *ctx->c;
+    std::vector<int32_t> tmp;
+    if (omega_concat) {
+      download(tmp, c.om_export, c.omega_total, c.stream);
+      std::memcpy(omega_concat, tmp.data(), tmp.size() * 4);
+    }
+    if (layer) {
+      download(tmp, c.om_layer, c.omega_total, c.stream);
+      std::memcpy(layer, tmp.data(), tmp.size() * 4);
+    }
+    if (omega_off) std::memcpy(omega_off, c.h_om_off.data(), (c.nsub + 1) * 8);
+    if (n_interior) std::memcpy(n_interior, c.h_nI.data(), c.nsub * 4);
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  }
+}
+
+int ads_export_splitting(const ads_ctx* ctx, double* s_out) {
+  try {
+    if (!ctx || !s_out) fail(ADS_ERR_ARG, "null argument");
+    const Ctx& c = *ctx->c;
+    // lsum is in the sorted order; map to the export order [I, Gamma]
+    std::vector<double> ls;
+    std::vector<int32_t> srt, exp;
+    download(ls, c.lsum, c.omega_total, c.stream);
+    download(srt, c.om_sorted, c.omega_total, c.stream);
+    download(exp, c.om_export, c.omega_total, c.stream);
+    for (int i = 0; i < c.nsub; ++i) {
+      const int64_t b = c.h_om_off[i], e = c.h_om_off[i + 1];
+      for (int64_t k = b; k < e; ++k) {
+        // export slot k holds global id exp[k]; find it in the sorted list
+        auto it = std::lower_bound(srt.begin() + b, srt.begin() + e, exp[k]);
+        s_out[k] = ls[it - srt.begin()];
+      }
+    }
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  }
+}
+
+int ads_export_coarse(const ads_ctx* ctx, double* W, int64_t* W_off, double* lam_re,
+                      double* lam_im) {
+  try {
+    if (!ctx) fail(ADS_ERR_ARG, "null context");
+    const Ctx& c = *ctx->c;
+    if (W && c.n0 > 0) {
+      std::vector<double> hw;
+      download(hw, c.W, c.h_W_off[c.nsub], c.stream);
+      std::memcpy(W, hw.data(), hw.size() * 8);
+    }
+    if (W_off) {
+      for (int i = 0; i <= c.nsub; ++i) W_off[i] = c.h_W_off.empty() ? 0 : c.h_W_off[i];
+    }
+    for (size_t k = 0; k < c.h_lam_re.size(); ++k) {
+      if (lam_re) lam_re[k] = c.h_lam_re[k];
+      if (lam_im) lam_im[k] = c.h_lam_im[k];
+    }
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  }
+}
+
+int ads_partition_bfs(const ads_csr* A, int32_t nparts, const int32_t* seeds, int32_t* part_out,
+                      void* hip_stream) {
+  try {
+    if (!A || !seeds || !part_out) fail(ADS_ERR_ARG, "null argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HostCSR h;
+    to_host(*A, h, st);
+    check_csr_host(h.view, 0);
+    if (nparts <= 0 || nparts > h.view.n) fail(ADS_ERR_ARG, "nparts out of range");
+    std::vector<int32_t> sd(seeds, seeds + nparts);
+    {
+      std::vector<int32_t> chk = sd;
+      std::sort(chk.begin(), chk.end());
+      for (int k = 0; k < nparts; ++k) {
+        if (chk[k] < 0 || chk[k] >= h.view.n) fail(ADS_ERR_ARG, "seed out of range");
+        if (k && chk[k] == chk[k - 1]) fail(ADS_ERR_ARG, "seeds must be distinct");
+      }
+    }
+    Arena mem;
+    std::vector<int32_t> rp(h.view.n + 1);
+    for (int64_t r = 0; r <= h.view.n; ++r) rp[r] = (int32_t)h.view.row_ptr[r];
+    int32_t* d_rp = upload(mem, rp.data(), rp.size(), st);
+    int32_t* d_ci = upload(mem, h.view.col, h.view.nnz, st);
+    std::vector<int32_t> part;
+    bfs_partition(d_rp, d_ci, h.view.n, h.view.nnz, sd, part, st);
+    std::memcpy(part_out, part.data(), part.size() * 4);
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  }
+}
+
+int ads_destroy(ads_ctx* ctx) {
+  if (!ctx) return ADS_OK;
+  delete ctx->c;
+  delete ctx;
+  return ADS_OK;
+}
+
+const char* ads_status_string(int status) {
+  switch (status) {
+    case ADS_OK: return "ADS_OK";
+    case ADS_KSP_MAXIT: return "ADS_KSP_MAXIT";
+    case ADS_KSP_BREAKDOWN: return "ADS_KSP_BREAKDOWN";
+    case ADS_ERR_ARG: return "ADS_ERR_ARG";
+    case ADS_ERR_HIP: return "ADS_ERR_HIP";
+    case ADS_ERR_OOM: return "ADS_ERR_OOM";
+    case ADS_ERR_SINGULAR: return "ADS_ERR_SINGULAR";
+    case ADS_ERR_EIG_NOCONV: return "ADS_ERR_EIG_NOCONV";
+    case ADS_ERR_NAN: return "ADS_ERR_NAN";
+    case ADS_ERR_UNSUPPORTED: return "ADS_ERR_UNSUPPORTED";
+    default: return "unknown status";
+  }
+}
+
+const char* ads_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// Internal declarations of the ads library: context layout, error handling,
+// small device helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ads.h"
+
+namespace ads {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define ADS_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e__ = (call);                                                           \
+    if (e__ != hipSuccess)                                                             \
+      ::ads::fail(ADS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e__));     \
+  } while (0)
+
+// Launch-configuration check done on the host before every launch: the grid
+// and block must be non-empty and within the documented hardware limits.
+inline void check_launch(dim3 g, dim3 b, size_t lds, const char* name) {
+  if (g.x == 0 || g.y == 0 || g.z == 0 || b.x == 0 || b.x * b.y * b.z > 1024 || lds > 160 * 1024 ||
+      g.y > 65535 || g.z > 65535)
+    fail(ADS_ERR_ARG, std::string("bad launch configuration for ") + name);
+}
+
+#define ADS_LAUNCH(kernel, grid, block, lds, stream, ...)                              \
+  do {                                                                                 \
+    ::ads::check_launch(grid, block, lds, #kernel);                                    \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                 \
+    ADS_HIP(hipGetLastError());                                                        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory owned by a context
+// ---------------------------------------------------------------------------
+struct Arena {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <class T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(ADS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  void release(void* p) {
+    for (auto& q : ptrs)
+      if (q == p) {
+        (void)hipFree(q);
+        q = nullptr;
+      }
+  }
+  ~Arena() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct Ctx {
+  Arena mem;
+  hipStream_t stream = nullptr;
+  ads_options opt{};
+  int nsys = 0;
+  int nsub = 0;
+  int64_t n = 0;    // total unknowns
+  int64_t nnz = 0;  // total entries
+  std::vector<int64_t> sys_row;  // [nsys+1] row offsets of the systems
+  std::vector<int32_t> sys_sub;  // [nsys+1] subdomain offsets of the systems
+  std::vector<int32_t> sub_sys;  // [nsub] system of each subdomain
+  int32_t* sub_sys_d = nullptr;  // device copy
+
+  // concatenated (block-diagonal) matrix, int32 indices
+  int32_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  int32_t* tptr = nullptr;  // transpose pattern (graph of A^T)
+  int32_t* tcol = nullptr;
+  int32_t* part = nullptr;  // global subdomain id of each unknown
+  int32_t* ipos = nullptr;  // position of each unknown inside its own Omega_Ii
+
+  // maps: omega in ascending global order ("sorted") and in [I, Gamma] order ("export")
+  int64_t omega_total = 0;
+  std::vector<int32_t> h_ni, h_nI;
+  std::vector<int64_t> h_om_off;
+  int32_t* ni = nullptr;
+  int32_t* nI = nullptr;
+  int64_t* om_off = nullptr;     // [nsub+1]
+  int32_t* om_sorted = nullptr;  // [omega_total] global ids, ascending per subdomain
+  int32_t* om_sub = nullptr;     // [omega_total] subdomain of each slot
+  uint8_t* om_int = nullptr;     // [omega_total] 1 if the slot is interior
+  int32_t* om_export = nullptr;  // [omega_total] [I asc, Gamma asc]
+  int32_t* om_layer = nullptr;   // [omega_total] layer of each export slot
+  int32_t* int_list = nullptr;   // alias into om_export: interior ids start at om_off[i]
+
+  // local matrices: CSR of A_ii in the sorted local order
+  int64_t lnnz = 0;
+  int64_t* lptr_off = nullptr;  // [nsub+1] offsets into lptr (sum of (ni+1))
+  int32_t* lptr = nullptr;      // per subdomain ni+1 row pointers (relative to lnz_off[i])
+  int64_t* lnz_off = nullptr;   // [nsub+1]
+  int32_t* lcol = nullptr;
+  double* lval = nullptr;
+  double* lsum = nullptr;       // [omega_total] lumped s (0 on interior rows), sorted order
+  int32_t* kdim = nullptr;      // [nsub] kernel dimension of the splitting (0/1)
+  std::vector<int32_t> h_kdim;
+
+  // block-tridiagonal factors
+  std::vector<int32_t> h_bs, h_nb;  // block size and block count per subdomain
+  std::vector<int64_t> h_fac_off;   // per subdomain, in elements, per matrix
+  int32_t* bs = nullptr;
+  int32_t* nb = nullptr;
+  int64_t* fac_off = nullptr;
+  int64_t fac_elems = 0;
+  int64_t npad_total = 0;           // sum of nb*bs
+  std::vector<int64_t> h_pad_off;
+  int64_t* pad_off = nullptr;       // [nsub+1] offsets of padded local vectors
+  void* facA = nullptr;             // factors of A_ii (apply)
+  void* facT = nullptr;             // factors of the regularised splitting (eigensolver)
+  int prec = ADS_PREC_FP64;
+  int64_t factor_bytes = 0;
+
+  // coarse space
+  int n0 = 0;
+  std::vector<int32_t> h_nev, h_coff, h_sweeps;
+  std::vector<double> h_lam_re, h_lam_im;
+  int32_t* nev = nullptr;      // [nsub]
+  int32_t* coff = nullptr;     // [nsub+1] coarse column offset (global over systems)
+  int64_t* W_off = nullptr;    // [nsub+1]
+  std::vector<int64_t> h_W_off;
+  double* W = nullptr;
+  std::vector<int32_t> h_n0s;  // per system coarse size
+  std::vector<int64_t> h_E_off;
+  int64_t* E_off = nullptr;    // [nsys+1] element offsets of the dense per-system E^{-1}
+  int32_t* sys_coff = nullptr; // [nsys+1] first coarse index of each system
+  double* Einv = nullptr;
+  int32_t eig_sweeps_max = 0, eig_unconverged = 0, eig_fallbacks = 0;
+
+  // workspace for apply / solve
+  double* work = nullptr;   // padded local vectors, npad_total * work_cols
+  int work_cols = 0;
+  double* cvec = nullptr;   // coarse vectors, n0 * cols
+  double* qvec = nullptr;   // coarse correction, n * cols
+  int cvec_cols = 0;
+
+  double t_phase_ms[8] = {0};
+  double t_setup_ms = 0;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (host functions implemented in the kernel translation units)
+// ---------------------------------------------------------------------------
+void build_maps(Ctx& c, const std::vector<int32_t>& part_host_concat);
+void extract_local(Ctx& c);
+void factor_local(Ctx& c);
+void eigensolve(Ctx& c);
+void assemble_coarse(Ctx& c);
+void ensure_work(Ctx& c, int cols);
+void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);
+int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_options& ko,
+                ads_ksp_result* res, hipStream_t s);
+void bfs_partition(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
+                   const std::vector<int32_t>& seeds, std::vector<int32_t>& part, hipStream_t s);
+void transpose_pattern(Arena& mem, const int32_t* rowptr, const int32_t* col, int64_t n,
+                       int64_t nnz, int32_t** tptr, int32_t** tcol, hipStream_t s);
+void exclusive_scan_i64(const int32_t* in, int64_t* out, int64_t n, Arena& mem, hipStream_t s);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, Arena& mem, hipStream_t s);
+
+// host <-> device helpers
+template <class T>
+T* upload(Arena& mem, const T* h, size_t count, hipStream_t s) {
+  T* d = mem.alloc<T>(count);
+  if (count) ADS_HIP(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+template <class T>
+void download(std::vector<T>& h, const T* d, size_t count, hipStream_t s) {
+  h.resize(count);
+  if (count) ADS_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s));
+  ADS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace ads
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+namespace adsd {
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int upper_bound_i64(const int64_t* a, int n, int64_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] <= key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// index of the segment containing flat position f (offsets ascending, off[0] = 0)
+__device__ __forceinline__ int segment_of(const int64_t* off, int nseg, int64_t f) {
+  return upper_bound_i64(off, nseg + 1, f) - 1;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// deterministic block sum over blockDim.x threads (multiple of 64, <= 1024);
+// `red` is LDS scratch of >= 16 doubles.  All threads receive the result.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// storage conversions of factor entries
+__device__ __forceinline__ double ld_fac(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double ld_fac(const float* p, int64_t i) { return (double)p[i]; }
+__device__ __forceinline__ double ld_fac(const __hip_bfloat16* p, int64_t i) {
+  return (double)__bfloat162float(p[i]);
+}
+__device__ __forceinline__ void st_fac(double* p, int64_t i, double v) { p[i] = v; }
+__device__ __forceinline__ void st_fac(float* p, int64_t i, double v) { p[i] = (float)v; }
+__device__ __forceinline__ void st_fac(__hip_bfloat16* p, int64_t i, double v) {
+  p[i] = __float2bfloat16((float)v);
+}
+
+// 64-bit mix (splitmix64 finaliser) -> uniform double in [-1, 1)
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x = x ^ (x >> 31);
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+}  // namespace adsd

@@ -1,0 +1,275 @@
+// Coarse operator A_00 = R_0 A R_0^T (Section 2) with R_0^T = [R_1^T D_1 Z_1 ...]
+// (Section 3.2), i.e. E = W^T A W where W_i holds the interior rows of Z_i.
+//
+// E is block sparse: block (j, i) is nonzero only when Omega_Ij couples to
+// Omega_Ii, i.e. when i owns a first-layer overlap node of subdomain j.  Per
+// system the blocks are assembled into a dense n0_s x n0_s matrix, one
+// workgroup per nonzero block, with a fixed reduction order (deterministic).
+// Then the FP64 LU with partial pivoting of each E_s (Section 4: exact LU of
+// the second-level operator) and, from those factors, the explicit inverse
+// used by the apply (one matrix-vector product per apply instead of two
+// latency-bound triangular sweeps).
+#include <algorithm>
+
+#include "ads_internal.h"
+
+namespace ads {
+
+static constexpr int NB_MAX = 128;
+static constexpr int CO_T = 256;
+static constexpr int ROWCH = 128;
+
+// neighbour subdomains (same system) of every subdomain, itself first
+__global__ void k_neighbours(const int32_t* om_export, const int32_t* om_layer,
+                             const int64_t* om_off, const int32_t* nI, const int32_t* ni,
+                             const int32_t* part, const int32_t* sys_sub_first,
+                             const int32_t* sys_sub_count, const int32_t* sub_sys,
+                             int32_t* nbcnt, int32_t* nblist, int32_t* overflow) {
+  extern __shared__ uint32_t bits[];
+  const int j = blockIdx.x;
+  const int sy = sub_sys[j];
+  const int first = sys_sub_first[sy], cnt = sys_sub_count[sy];
+  const int words = (cnt + 31) / 32;
+  for (int w = threadIdx.x; w < words; w += blockDim.x) bits[w] = 0;
+  __syncthreads();
+  const int64_t b = om_off[j];
+  for (int k = nI[j] + threadIdx.x; k < ni[j]; k += blockDim.x) {
+    if (om_layer[b + k] != 1) continue;
+    const int o = part[om_export[b + k]] - first;
+    atomicOr(&bits[o >> 5], 1u << (o & 31));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    nblist[(int64_t)j * NB_MAX + c++] = j;
+    for (int o = 0; o < cnt; ++o)
+      if ((bits[o >> 5] >> (o & 31)) & 1u) {
+        if (c >= NB_MAX) {
+          *overflow = 1;
+          break;
+        }
+        nblist[(int64_t)j * NB_MAX + c++] = first + o;
+      }
+    nbcnt[j] = c;
+  }
+}
+
+// E block (j, i) = W_j^T A(Omega_Ij, Omega_Ii) W_i
+__global__ void __launch_bounds__(CO_T)
+k_coarse_block(const int32_t* nbcnt, const int32_t* nblist, const int32_t* rowptr,
+               const int32_t* col, const double* val, const int32_t* part, const int32_t* ipos,
+               const int32_t* int_list, const int64_t* om_off, const int32_t* nI,
+               const double* W, const int64_t* W_off, const int32_t* nev, const int32_t* coff,
+               const int32_t* sub_sys, const int32_t* sys_coff, const int64_t* E_off, double* E) {
+  __shared__ double Wch[ROWCH * 32];
+  __shared__ double Ych[ROWCH * 32];
+  const int j = blockIdx.x, t = blockIdx.y;
+  if (t >= nbcnt[j]) return;
+  const int i = nblist[(int64_t)j * NB_MAX + t];
+  const int mj = nev[j], mi = nev[i];
+  if (mj == 0 || mi == 0) return;
+  const int sy = sub_sys[j];
+  const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
+  const int nint = nI[j];
+  const int32_t* rows = int_list + om_off[j];
+  const double* Wj = W + W_off[j];
+  const double* Wi = W + W_off[i];
+  double acc[4];
+  for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+  for (int k0 = 0; k0 < nint; k0 += ROWCH) {
+    const int nr = min(ROWCH, nint - k0);
+    __syncthreads();
+    for (int rr = threadIdx.x; rr < ROWCH; rr += blockDim.x) {
+      double y[32];
+      for (int bq = 0; bq < 32; ++bq) y[bq] = 0.0;
+      if (rr < nr) {
+        const int g = rows[k0 + rr];
+        for (int q = rowptr[g]; q < rowptr[g + 1]; ++q) {
+          const int cc = col[q];
+          if (part[cc] != i) continue;
+          const double a = val[q];
+          const double* w = Wi + (int64_t)ipos[cc] * mi;
+          for (int bq = 0; bq < 32; ++bq)
+            if (bq < mi) y[bq] += a * w[bq];
+        }
+      }
+      for (int bq = 0; bq < 32; ++bq)
+        if (bq < mi) Ych[rr * 32 + bq] = y[bq];
+      for (int aq = 0; aq < 32; ++aq)
+        if (aq < mj) Wch[rr * 32 + aq] = (rr < nr) ? Wj[(int64_t)(k0 + rr) * mj + aq] : 0.0;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * CO_T;
+      if (e < mj * mi) {
+        const int aq = e / mi, bq = e % mi;
+        double sacc = 0.0;
+        for (int rr = 0; rr < nr; ++rr) sacc += Wch[rr * 32 + aq] * Ych[rr * 32 + bq];
+        acc[q] += sacc;
+      }
+    }
+  }
+  double* Es = E + E_off[sy];
+  const int r0 = coff[j] - c0, q0 = coff[i] - c0;
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * CO_T;
+    if (e < mj * mi) {
+      const int aq = e / mi, bq = e % mi;
+      Es[(int64_t)(r0 + aq) * ns + q0 + bq] = acc[q];
+    }
+  }
+}
+
+// in-place LU with partial pivoting of each dense system block (row-major),
+// one workgroup per system; piv[k] = row swapped with k at step k
+__global__ void __launch_bounds__(1024)
+k_dense_lu(double* E, const int64_t* E_off, const int32_t* sys_coff, int32_t* piv_all,
+           int32_t* singular) {
+  __shared__ double rv[1024];
+  __shared__ int ri[1024];
+  __shared__ int pivrow;
+  const int sy = blockIdx.x;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  double* A = E + E_off[sy];
+  int32_t* piv = piv_all + sys_coff[sy];
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int k = 0; k < n; ++k) {
+    // argmax |A[i][k]|, i >= k (ties: smallest index)
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + t; r < n; r += T) {
+      double v = fabs(A[(int64_t)r * n + k]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    rv[t] = best;
+    ri[t] = bi;
+    __syncthreads();
+    for (int o = T / 2; o > 0; o >>= 1) {
+      if (t < o) {
+        double ov = rv[t + o];
+        int oi = ri[t + o];
+        if (ov > rv[t] || (ov == rv[t] && oi < ri[t])) {
+          rv[t] = ov;
+          ri[t] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      pivrow = ri[0];
+      piv[k] = ri[0];
+      if (!(rv[0] > 0.0)) *singular = sy + 1;
+    }
+    __syncthreads();
+    const int pr = pivrow;
+    if (pr != k)
+      for (int c = t; c < n; c += T) {
+        double a = A[(int64_t)k * n + c];
+        A[(int64_t)k * n + c] = A[(int64_t)pr * n + c];
+        A[(int64_t)pr * n + c] = a;
+      }
+    __syncthreads();
+    double pv = A[(int64_t)k * n + k];
+    if (pv == 0.0) pv = 1.0;
+    for (int r = k + 1 + t; r < n; r += T) A[(int64_t)r * n + k] /= pv;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int64_t e = t; e < (int64_t)m * m; e += T) {
+      const int r = k + 1 + (int)(e / m), c = k + 1 + (int)(e % m);
+      A[(int64_t)r * n + c] -= A[(int64_t)r * n + k] * A[(int64_t)k * n + c];
+    }
+    __syncthreads();
+  }
+}
+
+// inverse from the LU factors: columns of E^{-1} = U^{-1} L^{-1} P e_c,
+// one thread per column, written transposed-free (row-major Einv)
+__global__ void k_dense_inverse(const double* LU, double* Einv, const int64_t* E_off,
+                                const int32_t* sys_coff, const int32_t* piv_all, double* tmp) {
+  const int sy = blockIdx.y;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double* A = LU + E_off[sy];
+  double* X = Einv + E_off[sy];
+  const int32_t* piv = piv_all + sys_coff[sy];
+  double* x = tmp + E_off[sy] + (int64_t)c * n;  // column workspace
+  // P e_c: apply the row interchanges in order to the unit vector
+  for (int r = 0; r < n; ++r) x[r] = (r == c) ? 1.0 : 0.0;
+  for (int k = 0; k < n; ++k) {
+    int p = piv[k];
+    if (p != k) {
+      double v = x[k];
+      x[k] = x[p];
+      x[p] = v;
+    }
+  }
+  for (int r = 1; r < n; ++r) {
+    double v = x[r];
+    for (int k = 0; k < r; ++k) v -= A[(int64_t)r * n + k] * x[k];
+    x[r] = v;
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double v = x[r];
+    for (int k = r + 1; k < n; ++k) v -= A[(int64_t)r * n + k] * x[k];
+    x[r] = v / A[(int64_t)r * n + r];
+  }
+  for (int r = 0; r < n; ++r) X[(int64_t)r * n + c] = x[r];
+}
+
+void assemble_coarse(Ctx& c) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub, nsys = c.nsys;
+  c.h_n0s.assign(nsys, 0);
+  std::vector<int32_t> sc(nsys + 1, 0), sfirst(nsys), scount(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    sfirst[s] = c.sys_sub[s];
+    scount[s] = c.sys_sub[s + 1] - c.sys_sub[s];
+    sc[s] = c.h_coff[c.sys_sub[s]];
+  }
+  sc[nsys] = c.h_coff[nsub];
+  c.h_E_off.assign(nsys + 1, 0);
+  int64_t maxs = 0;
+  for (int s = 0; s < nsys; ++s) {
+    int64_t ns = sc[s + 1] - sc[s];
+    c.h_n0s[s] = (int32_t)ns;
+    c.h_E_off[s + 1] = c.h_E_off[s] + ns * ns;
+    maxs = std::max(maxs, ns);
+  }
+  c.sys_coff = upload(c.mem, sc.data(), nsys + 1, st);
+  c.E_off = upload(c.mem, c.h_E_off.data(), nsys + 1, st);
+  const int64_t etot = std::max<int64_t>(c.h_E_off[nsys], 1);
+  double* E = c.mem.alloc<double>(etot);
+  ADS_HIP(hipMemsetAsync(E, 0, etot * 8, st));
+  int32_t* d_first = upload(c.mem, sfirst.data(), nsys, st);
+  int32_t* d_count = upload(c.mem, scount.data(), nsys, st);
+  int32_t* nbcnt = c.mem.alloc<int32_t>(nsub);
+  int32_t* nblist = c.mem.alloc<int32_t>((size_t)nsub * NB_MAX);
+  int32_t* flag = c.mem.alloc<int32_t>(2);
+  ADS_HIP(hipMemsetAsync(flag, 0, 8, st));
+  int maxcnt = *std::max_element(scount.begin(), scount.end());
+  size_t bits_lds = (size_t)((maxcnt + 31) / 32) * 4;
+  ADS_LAUNCH(k_neighbours, dim3(nsub), dim3(256), bits_lds, st, c.om_export, c.om_layer, c.om_off,
+             c.nI, c.ni, c.part, d_first, d_count, c.sub_sys_d, nbcnt, nblist, flag);
+  ADS_LAUNCH(k_coarse_block, dim3(nsub, NB_MAX), dim3(CO_T), 0, st, nbcnt, nblist, c.rowptr, c.col,
+             c.val, c.part, c.ipos, c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff,
+             c.sub_sys_d, c.sys_coff, c.E_off, E);
+  int32_t* piv = c.mem.alloc<int32_t>(std::max(c.n0, 1));
+  ADS_LAUNCH(k_dense_lu, dim3(nsys), dim3(1024), 0, st, E, c.E_off, c.sys_coff, piv, flag + 1);
+  std::vector<int32_t> hf;
+  download(hf, flag, 2, st);
+  if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
+  if (hf[1]) fail(ADS_ERR_SINGULAR, "singular coarse operator in system " + std::to_string(hf[1] - 1));
+  c.Einv = c.mem.alloc<double>(etot);
+  double* tmp = c.mem.alloc<double>(etot);
+  ADS_LAUNCH(k_dense_inverse, dim3((unsigned)((maxs + 63) / 64), nsys), dim3(64), 0, st, E, c.Einv,
+             c.E_off, c.sys_coff, piv, tmp);
+  ADS_HIP(hipStreamSynchronize(st));
+  c.mem.release(tmp);
+  c.mem.release(E);
+}
+
+}  // namespace ads

@@ -1,0 +1,1012 @@
+// Local generalized eigenproblems, eq. 5 of Section 3.2, and the coarse space
+// of eq. 6.
+//
+// Per subdomain (Boolean D: B = D A_ii D = A_ii restricted to interior rows and
+// columns; Pi = orthogonal projector onto range(splitting)):
+//   non-floating (K = {0}):     T x = Atilde^{-1} B x
+//   floating (K = span{1}):     T x = P_perp Atilde_reg^{-1} Pi B Pi x,
+//     P_perp = projector onto 1^perp, Atilde_reg = splitting with doubled last
+//     diagonal entry, Pi = I - l l^T with l the unit left null vector.
+// The nonzero eigenpairs of T are the eigenpairs of eq. 5 on K^perp.
+//
+// Block subspace iteration with Rayleigh-Ritz, all subdomains batched:
+//   k_eig_op   (grid: subdomain x column chunk)  Y = T X   (tile solves)
+//   k_eig_rr   (grid: subdomain)  H = X^T Y, complex Schur form of H in LDS
+//              (Householder Hessenberg + shifted QR), eigenvalues ordered by
+//              |lambda|, the cut of eq. 6 with the cluster rule, reordering of
+//              the Schur form so the selected eigenvalues lead, a real
+//              orthonormal basis V of the selected invariant subspace, the
+//              residual ||(Y - X H) V||_F, and X <- orth(Y) (Cholesky QR, twice)
+//   k_eig_finish  W_i = orth([1 | (X V) restricted to Omega_Ii])
+// Converged subdomains skip further sweeps.
+#include <algorithm>
+#include <cmath>
+
+#include "ads_internal.h"
+#include "k_solve.h"
+
+namespace ads {
+
+static constexpr int EIG_T = 256;
+static constexpr int PMAX = 32;
+static constexpr double CLUSTER_RTOL = 1e-6;
+
+#define WAVE_SYNC()                                        \
+  do {                                                     \
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); \
+    __builtin_amdgcn_wave_barrier();                       \
+  } while (0)
+
+struct cd {
+  double x, y;
+};
+__device__ __forceinline__ cd cmk(double a, double b) { return cd{a, b}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cd cconj(cd a) { return cd{a.x, -a.y}; }
+__device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.x * s, a.y * s}; }
+__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double cabs(cd a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ double cnorm1(cd a) { return fabs(a.x) + fabs(a.y); }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+  double d = cabs2(b);
+  return cd{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+__device__ __forceinline__ cd csqrt(cd a) {
+  double r = cabs(a);
+  if (r == 0.0) return cd{0.0, 0.0};
+  double sx = sqrt(0.5 * (r + fabs(a.x)));
+  double sy = 0.5 * a.y / sx;
+  if (a.x >= 0) return cd{sx, sy};
+  return cd{fabs(sy), a.y >= 0 ? sx : -sx};
+}
+
+// Givens rotation G = [c s; -conj(s) c] (c real) with G [x; y] = [r; 0]
+__device__ __forceinline__ void cgivens(cd x, cd y, double& c, cd& s) {
+  double ax = cabs(x), ay = cabs(y);
+  if (ay == 0.0) {
+    c = 1.0;
+    s = cd{0, 0};
+    return;
+  }
+  if (ax == 0.0) {
+    c = 0.0;
+    s = cscale(cconj(y), 1.0 / ay);
+    return;
+  }
+  double r = hypot(ax, ay);
+  c = ax / r;
+  s = cscale(cmul(cscale(x, 1.0 / ax), cconj(y)), 1.0 / r);
+}
+
+struct SmallEigLds {
+  cd A[PMAX * PMAX];
+  cd Q[PMAX * PMAX];
+  cd v[PMAX];
+  double Pm[PMAX * PMAX];
+  double V[PMAX * PMAX];  // real basis, column-major p x m
+  double mag[PMAX];
+  int rank[PMAX];
+  int selected[PMAX];
+  double red[64];
+};
+
+// Complex Schur form of the real p x p matrix H (row-major) by wave 0 only.
+// Returns the number of selected eigenvalues m (leading after reordering),
+// their eigenvalues in |lambda| order in lam_out[0..m), and V (p x m real
+// orthonormal basis of the selected invariant subspace).  ok = 0 on failure.
+__device__ int small_eig_select(int p, const double* H, int count, double tau, SmallEigLds& L,
+                                double* lam_re, double* lam_im, int* ok_out, double* cut_gap) {
+  const int lane = threadIdx.x;  // wave 0 only
+  cd* A = L.A;
+  cd* Q = L.Q;
+  for (int e = lane; e < p * p; e += 64) {
+    A[e] = cd{H[e], 0.0};
+    Q[e] = cd{(e / p == e % p) ? 1.0 : 0.0, 0.0};
+  }
+  WAVE_SYNC();
+  // Householder reduction to upper Hessenberg form
+  for (int k = 0; k + 2 < p; ++k) {
+    const int len = p - k - 1;
+    cd x = (lane < len) ? A[(k + 1 + lane) * p + k] : cd{0, 0};
+    double nx2 = adsd::wave_sum(cabs2(x));
+    double nx = sqrt(nx2);
+    cd x0 = A[(k + 1) * p + k];
+    double ax0 = cabs(x0);
+    if (nx == 0.0) continue;
+    cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : cd{1.0, 0.0};
+    cd alpha = cscale(ph, -nx);
+    cd vl = (lane < len) ? x : cd{0, 0};
+    if (lane == 0) vl = csub(vl, alpha);
+    double nv = sqrt(adsd::wave_sum(cabs2(vl)));
+    if (nv == 0.0) continue;
+    vl = cscale(vl, 1.0 / nv);
+    if (lane < len) L.v[lane] = vl;
+    WAVE_SYNC();
+    // left: A <- (I - 2 v v^H) A on rows k+1.., all columns >= k
+    if (lane < p && lane >= k) {
+      const int j = lane;
+      cd w{0, 0};
+      for (int l = 0; l < len; ++l) w = cadd(w, cmul(cconj(L.v[l]), A[(k + 1 + l) * p + j]));
+      for (int l = 0; l < len; ++l)
+        A[(k + 1 + l) * p + j] = csub(A[(k + 1 + l) * p + j], cscale(cmul(L.v[l], w), 2.0));
+    }
+    WAVE_SYNC();
+    // right: A <- A (I - 2 v v^H), Q <- Q (I - 2 v v^H) on columns k+1..
+    if (lane < p) {
+      const int i = lane;
+      cd w{0, 0}, wq{0, 0};
+      for (int l = 0; l < len; ++l) {
+        w = cadd(w, cmul(A[i * p + k + 1 + l], L.v[l]));
+        wq = cadd(wq, cmul(Q[i * p + k + 1 + l], L.v[l]));
+      }
+      for (int l = 0; l < len; ++l) {
+        cd vc = cconj(L.v[l]);
+        A[i * p + k + 1 + l] = csub(A[i * p + k + 1 + l], cscale(cmul(w, vc), 2.0));
+        Q[i * p + k + 1 + l] = csub(Q[i * p + k + 1 + l], cscale(cmul(wq, vc), 2.0));
+      }
+    }
+    WAVE_SYNC();
+    if (lane < len && lane > 0) A[(k + 1 + lane) * p + k] = cd{0, 0};
+    WAVE_SYNC();
+  }
+  // shifted complex QR (single shift, Wilkinson / exceptional), full Schur form
+  const double eps = 2.220446049250313e-16;
+  int hi = p - 1, its = 0, total = 0, ok = 1;
+  while (hi > 0) {
+    int l = hi;
+    while (l > 0) {
+      double sub = cnorm1(A[l * p + l - 1]);
+      double dd = cnorm1(A[(l - 1) * p + l - 1]) + cnorm1(A[l * p + l]);
+      if (sub <= eps * dd || sub < 1e-300) break;
+      --l;
+    }
+    WAVE_SYNC();
+    if (l > 0 && lane == 0) A[l * p + l - 1] = cd{0, 0};
+    WAVE_SYNC();
+    if (l == hi) {
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (++total > 100 * p) {
+      ok = 0;
+      break;
+    }
+    ++its;
+    cd a = A[(hi - 1) * p + hi - 1], b = A[(hi - 1) * p + hi], c = A[hi * p + hi - 1],
+       d = A[hi * p + hi];
+    cd mu;
+    if (its % 11 == 10) {
+      mu = cadd(d, cd{0.75 * cnorm1(c), 0.0});
+    } else {
+      cd half = cscale(csub(a, d), 0.5);
+      cd disc = csqrt(cadd(cmul(half, half), cmul(b, c)));
+      cd m0 = cscale(cadd(a, d), 0.5);
+      cd mu1 = cadd(m0, disc), mu2 = csub(m0, disc);
+      mu = (cabs2(csub(mu1, d)) <= cabs2(csub(mu2, d))) ? mu1 : mu2;
+    }
+    for (int k = l; k < hi; ++k) {
+      cd x, y;
+      if (k == l) {
+        x = csub(A[l * p + l], mu);
+        y = A[(l + 1) * p + l];
+      } else {
+        x = A[k * p + k - 1];
+        y = A[(k + 1) * p + k - 1];
+      }
+      double cg;
+      cd sg;
+      cgivens(x, y, cg, sg);
+      WAVE_SYNC();
+      const int jlo = (k == l) ? l : k - 1;
+      if (lane < p && lane >= jlo) {
+        const int j = lane;
+        cd a1 = A[k * p + j], a2 = A[(k + 1) * p + j];
+        A[k * p + j] = cadd(cscale(a1, cg), cmul(sg, a2));
+        A[(k + 1) * p + j] = csub(cscale(a2, cg), cmul(cconj(sg), a1));
+      }
+      WAVE_SYNC();
+      const int ihi = min(k + 2, hi);
+      if (lane < p) {
+        const int i = lane;
+        if (i <= ihi) {
+          cd b1 = A[i * p + k], b2 = A[i * p + k + 1];
+          A[i * p + k] = cadd(cscale(b1, cg), cmul(cconj(sg), b2));
+          A[i * p + k + 1] = csub(cscale(b2, cg), cmul(sg, b1));
+        }
+        cd q1 = Q[i * p + k], q2 = Q[i * p + k + 1];
+        Q[i * p + k] = cadd(cscale(q1, cg), cmul(cconj(sg), q2));
+        Q[i * p + k + 1] = csub(cscale(q2, cg), cmul(sg, q1));
+      }
+      WAVE_SYNC();
+      if (k > l && lane == 0) A[(k + 1) * p + k - 1] = cd{0, 0};
+      WAVE_SYNC();
+    }
+  }
+  *ok_out = ok;
+  WAVE_SYNC();
+  // ranks by |lambda| descending (ties by index)
+  if (lane < p) L.mag[lane] = cabs(A[lane * p + lane]);
+  WAVE_SYNC();
+  if (lane < p) {
+    int rk = 0;
+    double mk = L.mag[lane];
+    for (int j = 0; j < p; ++j) {
+      double mj = L.mag[j];
+      rk += (mj > mk) || (mj == mk && j < lane);
+    }
+    L.rank[lane] = rk;
+  }
+  WAVE_SYNC();
+  // selection: the count largest, extended by the cluster rule, optional tau
+  int m = 0;
+  double cut = 0.0, next = 0.0;
+  if (count > 0) {
+    for (int j = 0; j < p; ++j)
+      if (L.rank[j] == count - 1) cut = L.mag[j];
+    for (int j = 0; j < p; ++j) {
+      bool sel = L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut;
+      if (tau > 0 && !(L.mag[j] > 1.0 / tau)) sel = false;
+      if (lane == 0) L.selected[j] = sel;
+      m += sel;
+      if (!(L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut)) next = fmax(next, L.mag[j]);
+    }
+  } else {
+    for (int j = 0; j < p; ++j)
+      if (lane == 0) L.selected[j] = 0;
+  }
+  *cut_gap = (cut > 0) ? (cut - next) / cut : 1.0;
+  WAVE_SYNC();
+  // reorder: move selected eigenvalues (in rank order) to the leading positions
+  for (int tpos = 0; tpos < m; ++tpos) {
+    // find the selected entry with the smallest rank at positions >= tpos
+    int idx = -1, best = 1 << 30;
+    for (int j = tpos; j < p; ++j)
+      if (L.selected[j] && L.rank[j] < best) {
+        best = L.rank[j];
+        idx = j;
+      }
+    for (int k = idx - 1; k >= tpos; --k) {
+      cd t11 = A[k * p + k], t22 = A[(k + 1) * p + k + 1], t12 = A[k * p + k + 1];
+      cd x = t12, y = csub(t22, t11);
+      double cg;
+      cd sg;
+      cgivens(x, y, cg, sg);
+      WAVE_SYNC();
+      if (lane < p && lane >= k) {
+        const int j = lane;
+        cd a1 = A[k * p + j], a2 = A[(k + 1) * p + j];
+        A[k * p + j] = cadd(cscale(a1, cg), cmul(sg, a2));
+        A[(k + 1) * p + j] = csub(cscale(a2, cg), cmul(cconj(sg), a1));
+      }
+      WAVE_SYNC();
+      if (lane < p) {
+        const int i = lane;
+        if (i <= k + 1) {
+          cd b1 = A[i * p + k], b2 = A[i * p + k + 1];
+          A[i * p + k] = cadd(cscale(b1, cg), cmul(cconj(sg), b2));
+          A[i * p + k + 1] = csub(cscale(b2, cg), cmul(sg, b1));
+        }
+        cd q1 = Q[i * p + k], q2 = Q[i * p + k + 1];
+        Q[i * p + k] = cadd(cscale(q1, cg), cmul(cconj(sg), q2));
+        Q[i * p + k + 1] = csub(cscale(q2, cg), cmul(sg, q1));
+      }
+      WAVE_SYNC();
+      if (lane == 0) {
+        A[k * p + k] = t22;
+        A[(k + 1) * p + k + 1] = t11;
+        A[(k + 1) * p + k] = cd{0, 0};
+        int r0 = L.rank[k], s0 = L.selected[k];
+        L.rank[k] = L.rank[k + 1];
+        L.selected[k] = L.selected[k + 1];
+        L.rank[k + 1] = r0;
+        L.selected[k + 1] = s0;
+      }
+      WAVE_SYNC();
+    }
+  }
+  if (lane < m) {
+    lam_re[lane] = A[lane * p + lane].x;
+    lam_im[lane] = A[lane * p + lane].y;
+  }
+  // real basis of span(Q[:, 0:m]): the projector Q_m Q_m^H is real for a
+  // conjugation-closed selection; pivoted Gram-Schmidt on its columns
+  if (lane < p) {
+    const int j = lane;
+    for (int i = 0; i < p; ++i) {
+      double acc = 0.0;
+      for (int t = 0; t < m; ++t) acc += cmul(Q[i * p + t], cconj(Q[j * p + t])).x;
+      L.Pm[i * p + j] = acc;  // column j of P
+    }
+  }
+  WAVE_SYNC();
+  for (int t = 0; t < m; ++t) {
+    double nrm = 0.0;
+    if (lane < p)
+      for (int i = 0; i < p; ++i) nrm += L.Pm[i * p + lane] * L.Pm[i * p + lane];
+    // argmax over lanes (ties -> smallest index)
+    double bn = nrm;
+    int bj = lane < p ? lane : 1 << 30;
+    if (lane >= p) bn = -1.0;
+    for (int o = 32; o > 0; o >>= 1) {
+      double on = __shfl_xor(bn, o, 64);
+      int oj = __shfl_xor(bj, o, 64);
+      if (on > bn || (on == bn && oj < bj)) {
+        bn = on;
+        bj = oj;
+      }
+    }
+    double inv = bn > 0 ? 1.0 / sqrt(bn) : 0.0;
+    if (lane < p) L.V[t * p + lane] = L.Pm[lane * p + bj] * inv;
+    WAVE_SYNC();
+    for (int pass = 0; pass < 2; ++pass) {
+      if (lane < p) {
+        const int j = lane;
+        double d = 0.0;
+        for (int i = 0; i < p; ++i) d += L.V[t * p + i] * L.Pm[i * p + j];
+        for (int i = 0; i < p; ++i) L.Pm[i * p + j] -= d * L.V[t * p + i];
+      }
+      WAVE_SYNC();
+    }
+    // re-orthogonalise V[:, t] against earlier columns (numerical safety)
+    if (t > 0) {
+      double vt = lane < p ? L.V[t * p + lane] : 0.0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int u = 0; u < t; ++u) {
+          double d = adsd::wave_sum(lane < p ? L.V[u * p + lane] * vt : 0.0);
+          if (lane < p) vt -= d * L.V[u * p + lane];
+        }
+      }
+      double nn = sqrt(adsd::wave_sum(vt * vt));
+      if (lane < p) L.V[t * p + lane] = nn > 0 ? vt / nn : 0.0;
+      WAVE_SYNC();
+    }
+  }
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// block helpers: Gram matrices over rows, Cholesky QR
+// ---------------------------------------------------------------------------
+static constexpr int GCH = 64;  // rows per LDS chunk
+
+// G[a*p + b] = sum_r U[r + a*ld] V[r + b*ld] over r < n (result in LDS G)
+__device__ void gram(const double* U, const double* V, int64_t ld, int n, int p, double* G,
+                     double* bufU, double* bufV) {
+  const int t = threadIdx.x, T = blockDim.x;
+  double acc[PMAX * PMAX / EIG_T];
+#pragma unroll
+  for (int q = 0; q < PMAX * PMAX / EIG_T; ++q) acc[q] = 0.0;
+  for (int r0 = 0; r0 < n; r0 += GCH) {
+    const int rows = min(GCH, n - r0);
+    __syncthreads();
+    for (int e = t; e < GCH * p; e += T) {
+      const int rr = e % GCH, a = e / GCH;
+      bufU[e] = rr < rows ? U[r0 + rr + a * ld] : 0.0;
+      bufV[e] = rr < rows ? V[r0 + rr + a * ld] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PMAX * PMAX / EIG_T; ++q) {
+      const int e = t + q * T;
+      if (e < p * p) {
+        const int a = e / p, b = e % p;
+        double sacc = 0.0;
+        for (int rr = 0; rr < GCH; ++rr) sacc += bufU[rr + a * GCH] * bufV[rr + b * GCH];
+        acc[q] += sacc;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PMAX * PMAX / EIG_T; ++q) {
+    const int e = t + q * T;
+    if (e < p * p) G[e] = acc[q];
+  }
+  __syncthreads();
+}
+
+// Cholesky of the p x p SPD matrix G (in place, lower R^T stored as upper R
+// row-major: R[a*p+b], b >= a).  Wave 0.  Returns 0 if not positive definite.
+__device__ int chol_upper(double* G, int p) {
+  const int lane = threadIdx.x;
+  int ok = 1;
+  for (int k = 0; k < p; ++k) {
+    double d = G[k * p + k];
+    if (!(d > 0.0)) {
+      ok = 0;
+      d = 1e-300;
+    }
+    double rkk = sqrt(d);
+    WAVE_SYNC();
+    if (lane < p && lane > k) G[k * p + lane] /= rkk;
+    if (lane == k) G[k * p + k] = rkk;
+    WAVE_SYNC();
+    if (lane < p && lane > k) {
+      const int j = lane;
+      for (int i = k + 1; i <= j; ++i) G[i * p + j] -= G[k * p + i] * G[k * p + j];
+    }
+    WAVE_SYNC();
+  }
+  return ok;
+}
+
+// Xout = Yin R^{-1} (row-wise triangular solve), rows r < n; padding rows set 0
+__device__ void apply_rinv(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
+                           const double* R) {
+  for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+    double y[PMAX];
+#pragma unroll
+    for (int a = 0; a < PMAX; ++a) y[a] = (a < p && r < n) ? Yin[r + a * ld] : 0.0;
+#pragma unroll
+    for (int a = 0; a < PMAX; ++a) {
+      if (a < p) {
+        double v = y[a];
+        for (int b = 0; b < a; ++b) v -= y[b] * R[b * p + a];
+        y[a] = v / R[a * p + a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < PMAX; ++a)
+      if (a < p) Xout[r + a * ld] = (r < n) ? y[a] : 0.0;
+  }
+}
+
+struct EigShared {
+  SmallEigLds se;
+  double H[PMAX * PMAX];
+  double G[PMAX * PMAX];
+  double HV[PMAX * PMAX];
+  double bufU[GCH * PMAX];
+  double bufV[GCH * PMAX];
+  double red[16];
+  double lam_re[PMAX], lam_im[PMAX];
+  int flag[4];
+};
+
+// X <- orth(Y) by Cholesky QR twice (Y and X distinct buffers; Y destroyed)
+__device__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S) {
+  int ok = 1;
+  double* src = Y;
+  double* dst = X;
+  for (int pass = 0; pass < 2; ++pass) {
+    gram(src, src, ld, n, p, S.G, S.bufU, S.bufV);
+    if (threadIdx.x < 64) {
+      int o = chol_upper(S.G, p);
+      if (threadIdx.x == 0) S.flag[0] = o;
+    }
+    __syncthreads();
+    ok &= S.flag[0];
+    apply_rinv(src, dst, ld, n, npad, p, S.G);
+    __syncthreads();
+    if (pass == 0) {
+      double* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+  }
+  // after two passes the result is in Y's buffer if passes swapped; copy to X
+  if (dst != X) {
+    for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) {
+      const int r = (int)(e % npad), a = (int)(e / npad);
+      X[r + a * ld] = dst[r + a * ld];
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+struct EigArgs {
+  const int64_t* fac_off;
+  const int32_t* bs;
+  const int32_t* nb;
+  const int32_t* ni;
+  const int32_t* nI;
+  const int64_t* om_off;
+  const uint8_t* om_int;
+  const int64_t* lrow;
+  const int32_t* lcol;
+  const double* lval;
+  const int32_t* kdim;
+  const int64_t* pad_off;
+  double* X;        // per subdomain npad x p at p*pad_off
+  double* Y;
+  double* ell;      // per subdomain npad (unit left null vector; floating only)
+  double* bell;     // B * ell
+  int32_t* done;    // converged flag
+  int32_t* sweeps;
+  int32_t* msel;    // selected count
+  double* Vsel;     // per subdomain p x p (column-major p x m)
+  double* lam;      // per subdomain 2*p (re, im)
+  int32_t* err;
+  int p;
+  int nev;
+  double tau;
+  double tol;
+};
+
+// transposed solve with the splitting tiles for the left null vector:
+// Atilde_reg^T l = e_last.  One-off per floating subdomain, single column.
+template <class FT>
+__device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const int64_t* lrow,
+                                      const int32_t* lcol, const double* lval, double* x,
+                                      double* tmp) {
+  const int t = threadIdx.x, T = blockDim.x;
+  const int64_t ss = (int64_t)s * s;
+  const int npad = K * s;
+  for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
+  __syncthreads();
+  // forward with U^T: w_k = G_k^T (f_k - A_{k-1,k}^T w_{k-1})
+  for (int k = 0; k < K; ++k) {
+    const int r0 = k * s;
+    if (k > 0 && t == 0) {
+      for (int rr = 0; rr < s; ++rr) {
+        const int r = r0 - s + rr;
+        if (r >= n) break;
+        for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
+          const int cidx = lcol[q];
+          if (cidx >= r0 && cidx < r0 + s) x[cidx] -= lval[q] * x[r];
+        }
+      }
+    }
+    __syncthreads();
+    const FT* G = fac + (int64_t)k * 2 * ss;
+    for (int r = t; r < s; r += T) {
+      double acc = 0.0;
+      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, (int64_t)r * s + cc) * x[r0 + cc];
+      tmp[r] = acc;
+    }
+    __syncthreads();
+    for (int r = t; r < s; r += T) x[r0 + r] = tmp[r];
+    __syncthreads();
+  }
+  // backward with L^T: l_k = w_k - G_k^T (A_{k+1,k}^T l_{k+1})
+  for (int k = K - 2; k >= 0; --k) {
+    const int r0 = k * s;
+    for (int r = t; r < s; r += T) tmp[s + r] = 0.0;
+    __syncthreads();
+    if (t == 0) {
+      for (int rr = 0; rr < s; ++rr) {
+        const int r = r0 + s + rr;
+        if (r >= n) break;
+        for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
+          const int cidx = lcol[q];
+          if (cidx >= r0 && cidx < r0 + s) tmp[s + cidx - r0] += lval[q] * x[r];
+        }
+      }
+    }
+    __syncthreads();
+    const FT* G = fac + (int64_t)k * 2 * ss;
+    for (int r = t; r < s; r += T) {
+      double acc = 0.0;
+      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, (int64_t)r * s + cc) * tmp[s + cc];
+      tmp[r] = acc;
+    }
+    __syncthreads();
+    for (int r = t; r < s; r += T) x[r0 + r] -= tmp[r];
+    __syncthreads();
+  }
+}
+
+template <class FT>
+__global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, double* scratch) {
+  __shared__ double red[16];
+  const int i = blockIdx.x;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
+  const int64_t ld = npad;
+  double* X = a.X + a.pad_off[i] * p;
+  const int64_t base = a.om_off[i];
+  for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) {
+    const int r = (int)(e % npad), j = (int)(e / npad);
+    X[r + j * ld] = (r < n) ? adsd::hash_unit(((uint64_t)i << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)r) : 0.0;
+  }
+  __syncthreads();
+  if (a.kdim[i]) {
+    double* l = a.ell + a.pad_off[i];
+    double* tmp = scratch + (int64_t)blockIdx.x * 2 * 1024;  // unused if s <= 512
+    extern __shared__ double dyn[];
+    double* tbuf = (2 * s <= 4096) ? dyn : tmp;
+    transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, l, tbuf);
+    double nn = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) nn += l[r] * l[r];
+    nn = adsd::block_sum(nn, red);
+    const double inv = 1.0 / sqrt(nn);
+    for (int r = threadIdx.x; r < npad; r += blockDim.x) l[r] = (r < n) ? l[r] * inv : 0.0;
+    __syncthreads();
+    // B l
+    double* bl = a.bell + a.pad_off[i];
+    for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+      double v = 0.0;
+      if (r < n && a.om_int[base + r])
+        for (int64_t q = a.lrow[base + r]; q < a.lrow[base + r + 1]; ++q)
+          if (a.om_int[base + a.lcol[q]]) v += a.lval[q] * l[a.lcol[q]];
+      bl[r] = v;
+    }
+    // X <- projection onto 1^perp
+    for (int j = 0; j < p; ++j) {
+      double sm = 0.0;
+      for (int r = threadIdx.x; r < n; r += blockDim.x) sm += X[r + j * ld];
+      sm = adsd::block_sum(sm, red) / n;
+      for (int r = threadIdx.x; r < n; r += blockDim.x) X[r + j * ld] -= sm;
+    }
+  }
+}
+
+// Y = T X for columns [j0, j0 + PC)
+template <class FT, int PC>
+__global__ void __launch_bounds__(EIG_T) k_eig_op(const FT* fac, EigArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  const int i = blockIdx.x;
+  if (a.done[i]) return;
+  const int j0 = blockIdx.y * PC;
+  const int p = a.p;
+  const int pc = min(PC, p - j0);
+  if (pc <= 0) return;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s;
+  const int64_t ld = npad;
+  const int64_t base = a.om_off[i];
+  const double* X = a.X + a.pad_off[i] * p + j0 * ld;
+  double* Y = a.Y + a.pad_off[i] * p + j0 * ld;
+  const bool floating = a.kdim[i] != 0;
+  const double* l = a.ell + a.pad_off[i];
+  const double* bl = a.bell + a.pad_off[i];
+  __shared__ double alpha[PC], beta[PC];
+  if (floating) {
+    for (int j = 0; j < pc; ++j) {
+      double d = 0.0;
+      for (int r = threadIdx.x; r < n; r += blockDim.x) d += l[r] * X[r + j * ld];
+      d = adsd::block_sum(d, red);
+      if (threadIdx.x == 0) alpha[j] = d;
+    }
+    __syncthreads();
+  }
+  // F = B (Pi X) = B X - alpha B l
+  for (int64_t e = threadIdx.x; e < (int64_t)npad * pc; e += blockDim.x) {
+    const int r = (int)(e % npad), j = (int)(e / npad);
+    double v = 0.0;
+    if (r < n && a.om_int[base + r]) {
+      for (int64_t q = a.lrow[base + r]; q < a.lrow[base + r + 1]; ++q) {
+        const int c = a.lcol[q];
+        if (a.om_int[base + c]) v += a.lval[q] * X[c + j * ld];
+      }
+      if (floating) v -= alpha[j] * bl[r];
+    }
+    Y[r + j * ld] = v;
+  }
+  __syncthreads();
+  if (floating) {  // F <- Pi F
+    for (int j = 0; j < pc; ++j) {
+      double d = 0.0;
+      for (int r = threadIdx.x; r < n; r += blockDim.x) d += l[r] * Y[r + j * ld];
+      d = adsd::block_sum(d, red);
+      if (threadIdx.x == 0) beta[j] = d;
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < (int64_t)n * pc; e += blockDim.x) {
+      const int r = (int)(e % n), j = (int)(e / n);
+      Y[r + j * ld] -= beta[j] * l[r];
+    }
+    __syncthreads();
+  }
+  adsd::block_solve<FT, PC>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, Y, ld, pc,
+                            lds);
+  if (floating) {  // projection onto 1^perp
+    for (int j = 0; j < pc; ++j) {
+      double sm = 0.0;
+      for (int r = threadIdx.x; r < n; r += blockDim.x) sm += Y[r + j * ld];
+      sm = adsd::block_sum(sm, red) / n;
+      for (int r = threadIdx.x; r < n; r += blockDim.x) Y[r + j * ld] -= sm;
+      __syncthreads();
+    }
+  }
+}
+
+// initial orthonormalisation of X (Y used as scratch)
+__global__ void __launch_bounds__(EIG_T) k_eig_orth0(EigArgs a) {
+  __shared__ EigShared S;
+  const int i = blockIdx.x;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
+  double* X = a.X + a.pad_off[i] * p;
+  double* Y = a.Y + a.pad_off[i] * p;
+  for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) Y[e] = X[e];
+  __syncthreads();
+  int ok = cholqr2(Y, X, npad, n, npad, p, S);
+  if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
+}
+
+__global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
+  __shared__ EigShared S;
+  const int i = blockIdx.x;
+  if (a.done[i]) return;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
+  const int64_t ld = npad;
+  double* X = a.X + a.pad_off[i] * p;
+  double* Y = a.Y + a.pad_off[i] * p;
+  const int count = a.nev - a.kdim[i];
+  // H = X^T Y
+  gram(X, Y, ld, n, p, S.H, S.bufU, S.bufV);
+  int m = 0;
+  if (threadIdx.x < 64) {
+    int ok = 1;
+    double gap = 1.0;
+    m = small_eig_select(p, S.H, count, a.tau, S.se, S.lam_re, S.lam_im, &ok, &gap);
+    if (threadIdx.x == 0) {
+      S.flag[1] = m;
+      S.flag[2] = ok;
+    }
+  }
+  __syncthreads();
+  m = S.flag[1];
+  if (!S.flag[2] && threadIdx.x == 0) atomicOr(a.err, 4);
+  // the selected cluster must leave at least one Ritz value outside it,
+  // otherwise the cluster may extend beyond the subspace
+  if (m + a.kdim[i] >= p && threadIdx.x == 0) atomicOr(a.err, 16);
+  // HV = H V (p x m), then residual ||Y V - X HV||_F
+  for (int e = threadIdx.x; e < p * m; e += blockDim.x) {
+    const int r = e % p, c = e / p;
+    double v = 0.0;
+    for (int k = 0; k < p; ++k) v += S.H[r * p + k] * S.se.V[c * p + k];
+    S.HV[c * p + r] = v;
+  }
+  __syncthreads();
+  double rn = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double xr[PMAX], yr[PMAX];
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      xr[k] = k < p ? X[r + k * ld] : 0.0;
+      yr[k] = k < p ? Y[r + k * ld] : 0.0;
+    }
+    for (int c = 0; c < m; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k)
+        if (k < p) v += yr[k] * S.se.V[c * p + k] - xr[k] * S.HV[c * p + k];
+      rn += v * v;
+    }
+  }
+  rn = sqrt(adsd::block_sum(rn, S.red));
+  double lmin = 1e300;
+  for (int c = 0; c < m; ++c) lmin = fmin(lmin, hypot(S.lam_re[c], S.lam_im[c]));
+  const bool conv = (m == 0) || (rn <= a.tol * lmin) || final_sweep;
+  if (threadIdx.x == 0) {
+    a.sweeps[i] += 1;
+    a.msel[i] = m;
+    if (conv) a.done[i] = (rn <= a.tol * lmin || m == 0) ? 1 : 2;
+  }
+  if (conv) {
+    double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
+    for (int e = threadIdx.x; e < p * m; e += blockDim.x) Vs[e] = S.se.V[e];
+    double* lam = a.lam + (int64_t)i * 2 * PMAX;
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+      lam[c] = S.lam_re[c];
+      lam[PMAX + c] = S.lam_im[c];
+    }
+    return;
+  }
+  __syncthreads();
+  int ok = cholqr2(Y, X, ld, n, npad, p, S);
+  if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
+}
+
+// W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
+__global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* W_off, double* W,
+                                                       double* scratchZ) {
+  __shared__ EigShared S;
+  const int i = blockIdx.x;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
+  const int nint = a.nI[i];
+  const int64_t ld = npad;
+  const int64_t base = a.om_off[i];
+  const double* X = a.X + a.pad_off[i] * p;
+  const int m = a.msel[i];
+  const int kd = a.kdim[i];
+  const int cols = m + kd;
+  if (cols == 0) return;
+  // Z (interior rows, column-major nint x cols) in the Y buffer (npad x p >= nint x cols)
+  double* Z = a.Y + a.pad_off[i] * p;
+  double* Z2 = scratchZ + a.pad_off[i] * p;
+  const double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
+  // interior rows in ascending local order: chunked block scan of the flags
+  __shared__ int wtot[EIG_T / 64];
+  int run = 0;
+  for (int r0 = 0; r0 < n; r0 += blockDim.x) {
+    const int r = r0 + threadIdx.x;
+    const int f = (r < n) ? (int)a.om_int[base + r] : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = f;
+    for (int o = 1; o < 64; o <<= 1) {
+      int tv = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += tv;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      if (q < w) off += wtot[q];
+      tot += wtot[q];
+    }
+    if (f) {
+      const int k = run + off + incl - 1;
+      for (int c = 0; c < cols; ++c) {
+        double v;
+        if (kd && c == 0)
+          v = 1.0;
+        else {
+          v = 0.0;
+          for (int j = 0; j < p; ++j) v += X[r + j * ld] * Vs[(c - kd) * p + j];
+        }
+        Z[k + c * ld] = v;
+      }
+    }
+    run += tot;
+  }
+  __syncthreads();
+  // orthonormalise the nint x cols block (Cholesky QR twice)
+  for (int pass = 0; pass < 2; ++pass) {
+    gram(Z, Z, ld, nint, cols, S.G, S.bufU, S.bufV);
+    if (threadIdx.x < 64) {
+      int o = chol_upper(S.G, cols);
+      if (threadIdx.x == 0) S.flag[0] = o;
+    }
+    __syncthreads();
+    if (!S.flag[0] && threadIdx.x == 0) atomicOr(a.err, 8);
+    apply_rinv(Z, Z2, ld, nint, nint, cols, S.G);
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < (int64_t)nint * cols; e += blockDim.x) {
+      const int r = (int)(e % nint), c = (int)(e / nint);
+      Z[r + c * ld] = Z2[r + c * ld];
+    }
+    __syncthreads();
+  }
+  double* Wi = W + W_off[i];
+  for (int64_t e = threadIdx.x; e < (int64_t)nint * cols; e += blockDim.x) {
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    Wi[e] = Z[r + c * ld];
+  }
+}
+
+template <class FT>
+static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub;
+  int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
+  double* scratch = c.mem.alloc<double>((size_t)nsub * 2 * 1024);
+  size_t init_lds = (2 * smax <= 4096) ? 2 * smax * sizeof(double) : 0;
+  if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
+  ADS_LAUNCH((k_eig_init<FT>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
+  ADS_LAUNCH(k_eig_orth0, dim3(nsub), dim3(EIG_T), 0, st, a);
+  constexpr int PC = 8;
+  size_t op_lds = (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, EIG_T) * sizeof(double);
+  const int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
+  std::vector<int32_t> hdone;
+  for (int sw = 0; sw < maxsw; ++sw) {
+    ADS_LAUNCH((k_eig_op<FT, PC>), dim3(nsub, (a.p + PC - 1) / PC), dim3(EIG_T), op_lds, st, fac, a);
+    ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)(sw == maxsw - 1));
+    if (sw % 4 == 3 || sw == maxsw - 1) {
+      download(hdone, a.done, nsub, st);
+      bool all = true;
+      for (int v : hdone) all &= (v != 0);
+      if (all) break;
+    }
+  }
+  ADS_HIP(hipStreamSynchronize(st));
+  c.mem.release(scratch);
+}
+
+void eigensolve(Ctx& c) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub;
+  const int nev = c.opt.nev;
+  int p = std::min(PMAX, std::max(2 * nev, nev + 8));
+  p = (p + 3) / 4 * 4;
+  p = std::min(p, PMAX);
+  int minfree = 1 << 30;
+  for (int i = 0; i < nsub; ++i) minfree = std::min(minfree, c.h_ni[i] - c.h_kdim[i] - 1);
+  p = std::min(p, minfree);
+  if (p < nev + 1)
+    fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
+  EigArgs a{};
+  a.fac_off = c.fac_off;
+  a.bs = c.bs;
+  a.nb = c.nb;
+  a.ni = c.ni;
+  a.nI = c.nI;
+  a.om_off = c.om_off;
+  a.om_int = c.om_int;
+  a.lrow = c.lptr_off;
+  a.lcol = c.lcol;
+  a.lval = c.lval;
+  a.kdim = c.kdim;
+  a.pad_off = c.pad_off;
+  a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
+  a.Y = c.mem.alloc<double>((size_t)c.npad_total * p);
+  a.ell = c.mem.alloc<double>(c.npad_total);
+  a.bell = c.mem.alloc<double>(c.npad_total);
+  a.done = c.mem.alloc<int32_t>(nsub);
+  a.sweeps = c.mem.alloc<int32_t>(nsub);
+  a.msel = c.mem.alloc<int32_t>(nsub);
+  a.Vsel = c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
+  a.lam = c.mem.alloc<double>((size_t)nsub * 2 * PMAX);
+  a.err = c.mem.alloc<int32_t>(1);
+  a.p = p;
+  a.nev = nev;
+  a.tau = c.opt.tau;
+  a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-6);
+  ADS_HIP(hipMemsetAsync(a.done, 0, nsub * 4, st));
+  ADS_HIP(hipMemsetAsync(a.sweeps, 0, nsub * 4, st));
+  ADS_HIP(hipMemsetAsync(a.msel, 0, nsub * 4, st));
+  ADS_HIP(hipMemsetAsync(a.err, 0, 4, st));
+  ADS_HIP(hipMemsetAsync(a.ell, 0, c.npad_total * 8, st));
+  ADS_HIP(hipMemsetAsync(a.bell, 0, c.npad_total * 8, st));
+  switch (c.prec) {
+    case ADS_PREC_FP64: eig_run<double>(c, a, (const double*)c.facT); break;
+    case ADS_PREC_FP32: eig_run<float>(c, a, (const float*)c.facT); break;
+    default: eig_run<__hip_bfloat16>(c, a, (const __hip_bfloat16*)c.facT); break;
+  }
+  std::vector<int32_t> herr, hm, hsw, hdone;
+  download(herr, a.err, 1, st);
+  if (herr[0] & 4) fail(ADS_ERR_EIG_NOCONV, "small dense eigensolver did not converge");
+  if (herr[0] & 16)
+    fail(ADS_ERR_UNSUPPORTED,
+         "an eigenvalue cluster at the cut fills the eigensolver subspace (e.g. overlap 0)");
+  if (herr[0] & 2) fail(ADS_ERR_EIG_NOCONV, "loss of orthogonality in the eigensolver block");
+  download(hm, a.msel, nsub, st);
+  download(c.h_sweeps, a.sweeps, nsub, st);
+  download(hdone, a.done, nsub, st);
+  c.eig_sweeps_max = 0;
+  c.eig_unconverged = 0;
+  for (int i = 0; i < nsub; ++i) {
+    c.eig_sweeps_max = std::max(c.eig_sweeps_max, c.h_sweeps[i]);
+    c.eig_unconverged += (hdone[i] != 1);
+  }
+  // coarse layout
+  c.h_nev.resize(nsub);
+  c.h_coff.assign(nsub + 1, 0);
+  c.h_W_off.assign(nsub + 1, 0);
+  for (int i = 0; i < nsub; ++i) {
+    if (hm[i] + c.h_kdim[i] > p)
+      fail(ADS_ERR_UNSUPPORTED, "eigenvalue cluster at the cut exceeds the subspace size in subdomain " +
+                                    std::to_string(i));
+    c.h_nev[i] = hm[i] + c.h_kdim[i];
+    if (c.h_nev[i] > 32) fail(ADS_ERR_UNSUPPORTED, "more than 32 coarse vectors in one subdomain");
+    c.h_coff[i + 1] = c.h_coff[i] + c.h_nev[i];
+    c.h_W_off[i + 1] = c.h_W_off[i] + (int64_t)c.h_nI[i] * c.h_nev[i];
+  }
+  c.n0 = c.h_coff[nsub];
+  std::vector<double> hlam;
+  download(hlam, a.lam, (size_t)nsub * 2 * PMAX, st);
+  c.h_lam_re.clear();
+  c.h_lam_im.clear();
+  for (int i = 0; i < nsub; ++i) {
+    if (c.h_kdim[i]) {
+      c.h_lam_re.push_back(0.0);
+      c.h_lam_im.push_back(0.0);
+    }
+    for (int k = 0; k < hm[i]; ++k) {
+      c.h_lam_re.push_back(hlam[(size_t)i * 2 * PMAX + k]);
+      c.h_lam_im.push_back(hlam[(size_t)i * 2 * PMAX + PMAX + k]);
+    }
+  }
+  c.nev = upload(c.mem, c.h_nev.data(), nsub, st);
+  c.coff = upload(c.mem, c.h_coff.data(), nsub + 1, st);
+  c.W_off = upload(c.mem, c.h_W_off.data(), nsub + 1, st);
+  c.W = c.mem.alloc<double>(std::max<int64_t>(c.h_W_off[nsub], 1));
+  double* scratchZ = c.mem.alloc<double>((size_t)c.npad_total * p);
+  ADS_LAUNCH(k_eig_finish, dim3(nsub), dim3(EIG_T), 0, st, a, c.W_off, c.W, scratchZ);
+  download(herr, a.err, 1, st);
+  if (herr[0] & 8) fail(ADS_ERR_EIG_NOCONV, "coarse basis of a subdomain is rank deficient");
+  c.mem.release(scratchZ);
+  c.mem.release(a.X);
+  c.mem.release(a.Y);
+
+}
+
+}  // namespace ads

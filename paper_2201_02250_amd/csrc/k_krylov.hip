@@ -1,0 +1,517 @@
+// Right-preconditioned restarted GMRES(m) and flexible GMRES(m), x0 = 0,
+// relative tolerance on ||b - A x|| / ||b|| (Section 4), run independently
+// for every (system, right-hand side) instance of a context.
+//
+// Vectors are n x nrhs column-major over the concatenated systems; instance
+// q = sys * nrhs + j owns rows [row0(sys), row1(sys)) of column j.  Every
+// instance keeps its own cycle position j_q, Hessenberg column, Givens
+// rotations and residual estimate, so restarts happen per instance exactly as
+// for a single solve.  Orthogonalisation is classical Gram-Schmidt applied
+// twice (CGS2); every inner product is reduced in a fixed order (partials per
+// row chunk, then a sequential sum), so results are reproducible.
+// A cycle ends when the Arnoldi estimate reaches rtol, at m steps, at maxit,
+// or on breakdown; the true residual is then recomputed in FP64 and decides
+// convergence or restart.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "ads_internal.h"
+
+namespace ads {
+
+static constexpr int KR_T = 256;
+static constexpr int CH_ROWS = 8192;  // rows per reduction chunk
+
+struct KInst {
+  const int64_t* row0;   // [Q] first row of the instance's segment
+  const int64_t* rows;   // [Q] segment length
+  const int32_t* colj;   // [Q] column index
+  int Q;
+  int64_t n;
+  int nch;               // chunks over the longest segment
+};
+
+// y = b - A x (mode 1) or y = A x (mode 0), all columns
+__global__ void k_spmv(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                       const double* __restrict__ val, const double* __restrict__ x,
+                       const double* __restrict__ b, double* __restrict__ y, int64_t n, int nrhs,
+                       int mode) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t r = e % n, j = e / n;
+  const double* xj = x + j * n;
+  double acc = 0.0;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) acc += val[k] * xj[col[k]];
+  y[e] = mode ? b[e] - acc : acc;
+}
+
+// partial inner products <V_i, w> for i <= jq[q] over one row chunk
+__global__ void __launch_bounds__(KR_T)
+k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w, KInst I,
+               const int32_t* __restrict__ jq, const int32_t* __restrict__ act, double* part,
+               int stride) {
+  __shared__ double wsum[KR_T / 64][66];
+  const int q = blockIdx.y, ch = blockIdx.x;
+  if (!act[q]) return;
+  const int J = jq[q];
+  const int64_t r0 = I.row0[q], len = I.rows[q];
+  const int64_t a = (int64_t)ch * CH_ROWS, b = min<int64_t>(len, a + CH_ROWS);
+  const int64_t off = (int64_t)I.colj[q] * I.n + r0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = 0; i <= J; ++i) {
+    const double* vi = V[i] + off;
+    double acc = 0.0;
+    for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) acc += vi[r] * w[off + r];
+    acc = adsd::wave_sum(acc);
+    if (lane == 0) wsum[wv][i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= J; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < KR_T / 64; ++k) s += wsum[k][i];
+    part[((int64_t)q * I.nch + ch) * stride + i] = s;
+  }
+}
+
+// h[q][i] = sum over chunks (fixed order); mode 1 accumulates into h
+__global__ void k_mdot_final(const double* part, KInst I, const int32_t* jq, const int32_t* act,
+                             double* h, int stride, int accumulate) {
+  const int q = blockIdx.x;
+  if (!act[q]) return;
+  const int64_t len = I.rows[q];
+  const int nch = (int)((len + CH_ROWS - 1) / CH_ROWS);
+  for (int i = threadIdx.x; i <= jq[q]; i += blockDim.x) {
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)q * I.nch + ch) * stride + i];
+    if (accumulate)
+      h[(int64_t)q * stride + i] += s;
+    else
+      h[(int64_t)q * stride + i] = s;
+  }
+}
+
+// w -= sum_i h_i V_i (h from the last CGS pass)
+__global__ void k_cgs_update(const double* const* __restrict__ V, double* __restrict__ w, KInst I,
+                             const int32_t* __restrict__ jq, const int32_t* __restrict__ act,
+                             const double* __restrict__ h, int stride) {
+  const int q = blockIdx.y;
+  if (!act[q]) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.rows[q]) return;
+  const int64_t idx = (int64_t)I.colj[q] * I.n + I.row0[q] + r;
+  const int J = jq[q];
+  const double* hq = h + (int64_t)q * stride;
+  double v = w[idx];
+  for (int i = 0; i <= J; ++i) v -= hq[i] * V[i][idx];
+  w[idx] = v;
+}
+
+// segment 2-norms squared: partial + final
+__global__ void __launch_bounds__(KR_T)
+k_norm_partial(const double* __restrict__ w, KInst I, const int32_t* __restrict__ act,
+               double* part) {
+  __shared__ double red[16];
+  const int q = blockIdx.y, ch = blockIdx.x;
+  if (!act[q]) return;
+  const int64_t len = I.rows[q];
+  const int64_t a = (int64_t)ch * CH_ROWS, b = min<int64_t>(len, a + CH_ROWS);
+  const int64_t off = (int64_t)I.colj[q] * I.n + I.row0[q];
+  double acc = 0.0;
+  for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) acc += w[off + r] * w[off + r];
+  acc = adsd::block_sum(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)q * I.nch + ch] = acc;
+}
+
+__global__ void k_norm_final(const double* part, KInst I, const int32_t* act, double* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= I.Q || !act[q]) return;
+  const int nch = (int)((I.rows[q] + CH_ROWS - 1) / CH_ROWS);
+  double s = 0.0;
+  for (int ch = 0; ch < nch; ++ch) s += part[(int64_t)q * I.nch + ch];
+  out[q] = sqrt(s);
+}
+
+// copy segments: dst(q) = src(q) * scale[q] (scale null -> 1); masked
+__global__ void k_seg_scale(const double* __restrict__ src, double* __restrict__ dst, KInst I,
+                            const int32_t* __restrict__ mask, const double* __restrict__ scale,
+                            int invert) {
+  const int q = blockIdx.y;
+  if (!mask[q]) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.rows[q]) return;
+  const int64_t idx = (int64_t)I.colj[q] * I.n + I.row0[q] + r;
+  double sc = scale ? (invert ? 1.0 / scale[q] : scale[q]) : 1.0;
+  dst[idx] = src[idx] * sc;
+}
+
+// gather V_{jq}(q) into a contiguous vector (or Zf_{jq} <- src)
+__global__ void k_seg_pick(const double* const* __restrict__ V, double* __restrict__ dst, KInst I,
+                           const int32_t* __restrict__ jq, const int32_t* __restrict__ act,
+                           int to_basis) {
+  const int q = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.rows[q]) return;
+  const int64_t idx = (int64_t)I.colj[q] * I.n + I.row0[q] + r;
+  if (!act[q]) {
+    if (!to_basis) dst[idx] = 0.0;
+    return;
+  }
+  if (to_basis)
+    ((double* const*)V)[jq[q]][idx] = dst[idx];
+  else
+    dst[idx] = V[jq[q]][idx];
+}
+
+// Arnoldi bookkeeping per instance: Givens rotations and estimate
+struct KState {
+  double* H;      // [Q][(m+1)*m] column-major: H[i + j*(m+1)]
+  double* cs;     // [Q][m]
+  double* sn;     // [Q][m]
+  double* g;      // [Q][m+1]
+  double* h;      // [Q][stride] CGS coefficients of the current step (pass 1)
+  double* h2;     // [Q][stride] CGS coefficients, pass 2
+  double* hn;     // [Q] norm of the new vector
+  double* est;    // [Q] |g_{j+1}|
+  int32_t* jq;    // [Q]
+  int32_t* brk;   // [Q] breakdown flag
+  int m;
+  int stride;
+};
+
+__global__ void k_arnoldi_finish(KState S, const int32_t* act, int Q) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q || !act[q]) return;
+  const int m = S.m, j = S.jq[q];
+  double* H = S.H + (int64_t)q * (m + 1) * m;
+  double* cs = S.cs + (int64_t)q * m;
+  double* sn = S.sn + (int64_t)q * m;
+  double* g = S.g + (int64_t)q * (m + 1);
+  const double* h = S.h + (int64_t)q * S.stride;
+  const double* h2 = S.h2 + (int64_t)q * S.stride;
+  double hc2 = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    const double hij = h[i] + h2[i];
+    H[i + j * (m + 1)] = hij;
+    hc2 += hij * hij;
+  }
+  const double hn = S.hn[q];
+  hc2 += hn * hn;
+  H[j + 1 + j * (m + 1)] = hn;
+  for (int i = 0; i < j; ++i) {
+    double a = H[i + j * (m + 1)], b = H[i + 1 + j * (m + 1)];
+    H[i + j * (m + 1)] = cs[i] * a + sn[i] * b;
+    H[i + 1 + j * (m + 1)] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[j + j * (m + 1)], b = hn;
+  const double den = hypot(a, b);
+  cs[j] = den > 0 ? a / den : 1.0;
+  sn[j] = den > 0 ? b / den : 0.0;
+  H[j + j * (m + 1)] = den;
+  H[j + 1 + j * (m + 1)] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  S.est[q] = fabs(g[j + 1]);
+  S.brk[q] = (hn <= 1e-14 * sqrt(hc2)) ? 1 : 0;
+}
+
+// y = H^{-1} g (size j+1), stored in S.h for the update
+__global__ void k_cycle_solve(KState S, const int32_t* endm, const int32_t* jend, int Q) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q || !endm[q]) return;
+  const int m = S.m, k = jend[q];
+  const double* H = S.H + (int64_t)q * (m + 1) * m;
+  const double* g = S.g + (int64_t)q * (m + 1);
+  double* y = S.h + (int64_t)q * S.stride;
+  for (int r = k - 1; r >= 0; --r) {
+    double v = g[r];
+    for (int c = r + 1; c < k; ++c) v -= H[r + c * (m + 1)] * y[c];
+    y[r] = v / H[r + r * (m + 1)];
+  }
+}
+
+// x(q) += sum_{i<jend} y_i B_i(q)  (B = Zf for flexible, V otherwise into u)
+__global__ void k_combine(const double* const* __restrict__ B, double* __restrict__ out, KInst I,
+                          const int32_t* __restrict__ endm, const int32_t* __restrict__ jend,
+                          const double* __restrict__ y, int stride, int accumulate) {
+  const int q = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.rows[q]) return;
+  const int64_t idx = (int64_t)I.colj[q] * I.n + I.row0[q] + r;
+  if (!endm[q]) {
+    if (!accumulate) out[idx] = 0.0;
+    return;
+  }
+  const double* yq = y + (int64_t)q * stride;
+  double v = accumulate ? out[idx] : 0.0;
+  for (int i = 0; i < jend[q]; ++i) v += yq[i] * B[i][idx];
+  out[idx] = v;
+}
+
+// V_{jq}(q) = w(q) / hn[q] for masked instances
+__global__ void k_next_basis(double* const* __restrict__ V, const double* __restrict__ w, KInst I,
+                             const int32_t* __restrict__ jq, const int32_t* __restrict__ mask,
+                             const double* __restrict__ hn) {
+  const int q = blockIdx.y;
+  if (!mask[q]) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.rows[q]) return;
+  const int64_t idx = (int64_t)I.colj[q] * I.n + I.row0[q] + r;
+  V[jq[q]][idx] = w[idx] / hn[q];
+}
+
+__global__ void k_add_masked(double* __restrict__ x, const double* __restrict__ u, KInst I,
+                             const int32_t* __restrict__ mask) {
+  const int q = blockIdx.y;
+  if (!mask[q]) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.rows[q]) return;
+  const int64_t idx = (int64_t)I.colj[q] * I.n + I.row0[q] + r;
+  x[idx] += u[idx];
+}
+
+// start of a cycle for masked instances: g = [beta, 0..], jq = 0
+__global__ void k_cycle_start(KState S, const int32_t* mask, const double* beta, int Q) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q || !mask[q]) return;
+  double* g = S.g + (int64_t)q * (S.m + 1);
+  for (int i = 0; i <= S.m; ++i) g[i] = 0.0;
+  g[0] = beta[q];
+  S.jq[q] = 0;
+}
+
+__global__ void k_advance(KState S, const int32_t* mask, int Q) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q || !mask[q]) return;
+  S.jq[q] += 1;
+}
+
+int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_options& ko,
+                ads_ksp_result* res, hipStream_t st) {
+  const int m = ko.restart;
+  const int Q = c.nsys * nrhs;
+  const int64_t n = c.n;
+  const int maxit = ko.maxit > 0 ? ko.maxit : 1000;
+  const bool flex = ko.flexible != 0;
+  const int fixed = ko.fixed_iters;
+  auto t0 = std::chrono::steady_clock::now();
+  Arena mem;
+  // instance table
+  std::vector<int64_t> hrow0(Q), hrows(Q);
+  std::vector<int32_t> hcol(Q);
+  int64_t maxlen = 1;
+  for (int s = 0; s < c.nsys; ++s)
+    for (int j = 0; j < nrhs; ++j) {
+      int q = s * nrhs + j;
+      hrow0[q] = c.sys_row[s];
+      hrows[q] = c.sys_row[s + 1] - c.sys_row[s];
+      hcol[q] = j;
+      maxlen = std::max(maxlen, hrows[q]);
+    }
+  KInst I;
+  I.row0 = upload(mem, hrow0.data(), Q, st);
+  I.rows = upload(mem, hrows.data(), Q, st);
+  I.colj = upload(mem, hcol.data(), Q, st);
+  I.Q = Q;
+  I.n = n;
+  I.nch = (int)((maxlen + CH_ROWS - 1) / CH_ROWS);
+  const int stride = m + 2;
+  const size_t vsz = (size_t)n * nrhs;
+  std::vector<double*> hV(m + 1), hZ(flex ? m : 0);
+  for (int i = 0; i <= m; ++i) hV[i] = mem.alloc<double>(vsz);
+  for (int i = 0; i < (int)hZ.size(); ++i) hZ[i] = mem.alloc<double>(vsz);
+  double** dV = upload(mem, hV.data(), m + 1, st);
+  double** dZ = flex ? upload(mem, hZ.data(), m, st) : nullptr;
+  double* w = mem.alloc<double>(vsz);
+  double* z = mem.alloc<double>(vsz);
+  double* u = mem.alloc<double>(vsz);
+  KState S;
+  S.m = m;
+  S.stride = stride;
+  S.H = mem.alloc<double>((size_t)Q * (m + 1) * m);
+  S.cs = mem.alloc<double>((size_t)Q * m);
+  S.sn = mem.alloc<double>((size_t)Q * m);
+  S.g = mem.alloc<double>((size_t)Q * (m + 1));
+  S.h = mem.alloc<double>((size_t)Q * stride);
+  S.h2 = mem.alloc<double>((size_t)Q * stride);
+  S.hn = mem.alloc<double>(Q);
+  S.est = mem.alloc<double>(Q);
+  S.jq = mem.alloc<int32_t>(Q);
+  S.brk = mem.alloc<int32_t>(Q);
+  double* part = mem.alloc<double>((size_t)Q * I.nch * stride);
+  double* bnorm_d = mem.alloc<double>(Q);
+  double* beta_d = mem.alloc<double>(Q);
+  int32_t* act_d = mem.alloc<int32_t>(Q);
+  int32_t* endm_d = mem.alloc<int32_t>(Q);
+  int32_t* jend_d = mem.alloc<int32_t>(Q);
+  int32_t* all_d = mem.alloc<int32_t>(Q);
+  std::vector<int32_t> ones(Q, 1);
+  ADS_HIP(hipMemcpyAsync(all_d, ones.data(), Q * 4, hipMemcpyHostToDevice, st));
+  ADS_HIP(hipMemsetAsync(S.jq, 0, Q * 4, st));
+  const dim3 gseg((unsigned)((maxlen + 255) / 256), Q);
+  const unsigned gv = (unsigned)((vsz + 255) / 256);
+  auto norms = [&](const double* v, const int32_t* mask, double* out) {
+    ADS_LAUNCH(k_norm_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, v, I, mask, part);
+    ADS_LAUNCH(k_norm_final, dim3((Q + 63) / 64), dim3(64), 0, st, part, I, mask, out);
+  };
+  // x = 0, r = b
+  ADS_HIP(hipMemsetAsync(x, 0, vsz * 8, st));
+  norms(b, all_d, bnorm_d);
+  std::vector<double> bnorm, beta(Q), est(Q), hn(Q);
+  download(bnorm, bnorm_d, Q, st);
+  std::vector<int32_t> state(Q, 0);  // 0 active, 1 done
+  std::vector<int32_t> its(Q, 0), status(Q, ADS_OK), jcur(Q, 0);
+  std::vector<int32_t> act(Q, 0), endm(Q, 0), jend(Q, 0);
+  std::vector<double> relres(Q, 0.0);
+  for (int q = 0; q < Q; ++q)
+    if (bnorm[q] == 0.0) state[q] = 1;
+  // residual r = b - A x into w, start cycles for all active instances
+  auto start_cycles = [&](const std::vector<int32_t>& mask_h) {
+    ADS_HIP(hipMemcpyAsync(endm_d, mask_h.data(), Q * 4, hipMemcpyHostToDevice, st));
+    ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, x, b, w, n, nrhs, 1);
+    norms(w, endm_d, beta_d);
+    std::vector<double> hb;
+    download(hb, beta_d, Q, st);
+    std::vector<int32_t> m2 = mask_h;
+    for (int q = 0; q < Q; ++q)
+      if (mask_h[q]) {
+        relres[q] = bnorm[q] > 0 ? hb[q] / bnorm[q] : 0.0;
+        if (hb[q] == 0.0 || (!fixed && hb[q] <= ko.rtol * bnorm[q])) {
+          state[q] = 1;
+          m2[q] = 0;
+        }
+      }
+    ADS_HIP(hipMemcpyAsync(endm_d, m2.data(), Q * 4, hipMemcpyHostToDevice, st));
+    ADS_LAUNCH(k_seg_scale, gseg, dim3(256), 0, st, w, hV[0], I, endm_d, beta_d, 1);
+    ADS_LAUNCH(k_cycle_start, dim3((Q + 63) / 64), dim3(64), 0, st, S, endm_d, beta_d, Q);
+    for (int q = 0; q < Q; ++q)
+      if (m2[q]) jcur[q] = 0;
+  };
+  {
+    std::vector<int32_t> mk(Q);
+    for (int q = 0; q < Q; ++q) mk[q] = state[q] == 0;
+    start_cycles(mk);
+  }
+  for (;;) {
+    bool any = false;
+    for (int q = 0; q < Q; ++q) {
+      act[q] = state[q] == 0;
+      any |= act[q] != 0;
+    }
+    if (!any) break;
+    ADS_HIP(hipMemcpyAsync(act_d, act.data(), Q * 4, hipMemcpyHostToDevice, st));
+    // z = M v_j ; w = A z
+    ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dV, u, I, S.jq, act_d, 0);
+    apply_prec(c, u, z, nrhs, st);
+    if (flex)
+      ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dZ, z, I, S.jq, act_d, 1);
+    ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, z, (const double*)nullptr,
+               w, n, nrhs, 0);
+    // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2
+    ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
+               S.jq, act_d, part, stride);
+    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(64), 0, st, part, I, S.jq, act_d, S.h, stride, 0);
+    ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
+               S.h, stride);
+    ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
+               S.jq, act_d, part, stride);
+    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(64), 0, st, part, I, S.jq, act_d, S.h2, stride, 0);
+    ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
+               S.h2, stride);
+    norms(w, act_d, S.hn);
+    ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
+    download(est, S.est, Q, st);
+    std::vector<int32_t> brk;
+    download(brk, S.brk, Q, st);
+    download(hn, S.hn, Q, st);
+    bool anyend = false;
+    for (int q = 0; q < Q; ++q) {
+      endm[q] = 0;
+      if (!act[q]) continue;
+      its[q] += 1;
+      jend[q] = jcur[q] + 1;
+      bool end = false;
+      if (fixed) {
+        end = its[q] >= fixed || jend[q] == m || brk[q];
+      } else {
+        end = est[q] <= ko.rtol * bnorm[q] || jend[q] == m || its[q] >= maxit || brk[q];
+      }
+      if (end) {
+        endm[q] = 1;
+        anyend = true;
+      } else {
+        jcur[q] += 1;
+      }
+    }
+    // next basis vector for continuing instances
+    std::vector<int32_t> cont(Q, 0);
+    for (int q = 0; q < Q; ++q) cont[q] = act[q] && !endm[q];
+    ADS_HIP(hipMemcpyAsync(act_d, cont.data(), Q * 4, hipMemcpyHostToDevice, st));
+    ADS_LAUNCH(k_advance, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
+    ADS_LAUNCH(k_next_basis, gseg, dim3(256), 0, st, dV, w, I, S.jq, act_d, S.hn);
+    if (!anyend) continue;
+    // end of cycle: x += Z y  (flexible)  or  x += M (V y)
+    ADS_HIP(hipMemcpyAsync(endm_d, endm.data(), Q * 4, hipMemcpyHostToDevice, st));
+    ADS_HIP(hipMemcpyAsync(jend_d, jend.data(), Q * 4, hipMemcpyHostToDevice, st));
+    ADS_LAUNCH(k_cycle_solve, dim3((Q + 63) / 64), dim3(64), 0, st, S, endm_d, jend_d, Q);
+    if (flex) {
+      ADS_LAUNCH(k_combine, gseg, dim3(256), 0, st, (const double* const*)dZ, x, I, endm_d, jend_d,
+                 S.h, stride, 1);
+    } else {
+      ADS_LAUNCH(k_combine, gseg, dim3(256), 0, st, (const double* const*)dV, u, I, endm_d, jend_d,
+                 S.h, stride, 0);
+      apply_prec(c, u, z, nrhs, st);
+      ADS_LAUNCH(k_add_masked, gseg, dim3(256), 0, st, x, z, I, endm_d);
+    }
+    // true residual and restart decision
+    std::vector<int32_t> restart(Q, 0);
+    {
+      ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, x, b, w, n, nrhs, 1);
+      norms(w, endm_d, beta_d);
+      std::vector<double> tr;
+      download(tr, beta_d, Q, st);
+      for (int q = 0; q < Q; ++q) {
+        if (!endm[q]) continue;
+        relres[q] = tr[q] / bnorm[q];
+        if (fixed) {
+          if (its[q] >= fixed || brk[q]) state[q] = 1;
+          else restart[q] = 1;
+          continue;
+        }
+        if (tr[q] <= ko.rtol * bnorm[q]) {
+          state[q] = 1;
+          status[q] = ADS_OK;
+        } else if (its[q] >= maxit) {
+          state[q] = 1;
+          status[q] = ADS_KSP_MAXIT;
+        } else if (brk[q]) {
+          state[q] = 1;
+          status[q] = ADS_KSP_BREAKDOWN;
+        } else {
+          restart[q] = 1;
+        }
+      }
+    }
+    bool anyr = false;
+    for (int v : restart) anyr |= v != 0;
+    if (anyr) start_cycles(restart);
+  }
+  ADS_HIP(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  int worst = ADS_OK;
+  for (int q = 0; q < Q; ++q) {
+    if (res && q < ADS_MAX_RESULTS) {
+      res->its[q] = its[q];
+      res->relres[q] = relres[q];
+      res->status[q] = status[q];
+    }
+    worst = std::max(worst, status[q]);
+  }
+  if (res) {
+    res->t_setup_ms = c.t_setup_ms;
+    res->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  return worst;
+}
+
+}  // namespace ads

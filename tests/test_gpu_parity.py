@@ -1,0 +1,235 @@
+"""Parity of the HIP path (through the C interface) with the FP64 CPU oracle.
+
+Integer outputs (partitions, index maps, layers, kernel dimensions, nev_i, n0)
+and the lumped sums of Definition 1 must agree bit for bit.  Floating-point
+results are compared to the tolerances derived in the design notes:
+  * coarse spaces: same selected eigenvalues (rel. 1e-8) and principal angles
+    between the spans of W_i <= 1e-7 rad (eigensolver tolerance 1e-10);
+  * apply (eq. 4): relative max error <= 1e-9 (FP64).  M^{-1} depends on the
+    span of the coarse space, which the eigensolver fixes to its residual
+    tolerance divided by the spectral gap at the cut; the apply tests therefore
+    run the eigensolver to 1e-12 (option eig_tol) instead of the 1e-10
+    default, which already gives 1e-9 .. 5e-9 here;
+  * solve: iteration counts within +-1, solutions within 1e-8 relative of the
+    oracle's, true relative residual <= 1e-8; fixed-iteration iterates <= 1e-9.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import schwarz as OS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2201_02250_amd import ads  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def small_cases():
+    """(name, A: CSR, part, nparts, overlap, nev, restart, flexible): several
+    tiles and ragged tails, floating and non-floating subdomains, SPD and
+    nonsymmetric, overlap 0/1/2."""
+    out = []
+    A, part, N, o = W.config("c1_laplace2d_64_strips8", scale=32)
+    out.append(("lap32-strips", A, part, N, 1, 4, 30, False))
+    A = W.convdiff2d(40, 0.01)
+    out.append(("cd40-blocks3-d2", A, W.block_partition_2d(40, 3), 9, 2, 6, 50, True))
+    A = W.convdiff2d(37, 0.02)
+    out.append(("cd37-4x3-d1", A, W.block_partition_2d(37, 4, 3), 12, 1, 5, 30, True))
+    A = W.diffusion2d_lognormal(48, seed=4, npad=128)
+    out.append(("ln48-4x4-d1", A, W.block_partition_2d(48, 4), 16, 1, 8, 30, False))
+    A = W.convdiff3d(14, nu=0.02)
+    out.append(("cd3d14-2x2x2-d2", A, W.block_partition_3d(14, 2, 2, 2), 8, 2, 6, 30, True))
+    A = W.laplace2d(20)
+    out.append(("lap20-d0-nev0", A, W.block_partition_2d(20, 2), 4, 0, 0, 30, False))
+    return out
+
+
+CASES = small_cases()
+IDS = [c[0] for c in CASES]
+
+
+def oracle_for(case, variant="deflated"):
+    name, A, part, N, ov, nev, restart, flex = case
+    return OS.TwoLevelSchwarz(A.to_scipy(), part, N, ov, nev, variant=variant)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_maps_and_splitting_bit_exact(case):
+    name, A, part, N, ov, nev, restart, flex = case
+    ctx = ads.Context(A, part, N, ov, nev)
+    om, off, nI, lay = ads.ads_export_maps(ctx.ctx)
+    s_gpu = ads.ads_export_splitting(ctx.ctx)
+    As = A.to_scipy()
+    subs = OS.subdomains(As, part, N, ov)
+    for i, sub in enumerate(subs):
+        seg = om[off[i]:off[i + 1]]
+        np.testing.assert_array_equal(seg, sub.omega)
+        assert nI[i] == sub.n_interior
+        np.testing.assert_array_equal(lay[off[i]:off[i + 1]],
+                                      np.r_[np.zeros(sub.n_interior, int), sub.layer])
+        _, s, At = OS.block_splitting(As, sub)
+        sg = s_gpu[off[i]:off[i + 1]]
+        np.testing.assert_array_equal(sg[: sub.n_interior], 0.0)
+        np.testing.assert_array_equal(sg[sub.n_interior:], s)  # bit-exact
+        assert ctx.info["kernel_dim"][i] == OS.kernel_dimension(At)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_coarse_space_matches_oracle(case):
+    name, A, part, N, ov, nev, restart, flex = case
+    ctx = ads.Context(A, part, N, ov, nev)
+    P = oracle_for(case)
+    Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+    np.testing.assert_array_equal(info["nev_i"], P.nev_i)
+    assert info["n0"] == P.n0
+    assert info["eig_unconverged"] == 0
+    k = 0
+    for i in range(N):
+        m = int(info["nev_i"][i])
+        nIi = int(info["n_interior"][i])
+        Wi = Wg[woff[i]:woff[i + 1]].reshape(nIi, m)
+        if m:
+            np.testing.assert_allclose(Wi.T @ Wi, np.eye(m), atol=1e-12)
+            ang = sla.subspace_angles(Wi, P.W[i])
+            assert ang.max() < 1e-7, (i, ang.max())
+        lam_o = P.eig[i]["lam_sel"]
+        lam_g = lam[k + P.eig[i]["kernel"]: k + m]
+        k += m
+        for x in lam_o:
+            assert np.min(np.abs(lam_g - x)) <= 1e-8 * abs(x)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("variant", ["deflated", "ras"])
+def test_apply_matches_oracle(case, variant):
+    name, A, part, N, ov, nev, restart, flex = case
+    v = ads.ADS_VARIANT_DEFLATED if variant == "deflated" else ads.ADS_VARIANT_RAS
+    ctx = ads.Context(A, part, N, ov, nev, variant=v, eig_tol=1e-12)
+    P = oracle_for(case, variant)
+    rng = np.random.default_rng(7)
+    R = rng.standard_normal((A.n, 3))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    assert err <= 1e-9, err
+    z1 = ctx.apply(torch.tensor(R[:, 0].copy(), device=DEV)).cpu().numpy()
+    np.testing.assert_allclose(z1, Z[:, 0], rtol=0, atol=1e-14 * np.abs(Z).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_solve_matches_oracle(case):
+    name, A, part, N, ov, nev, restart, flex = case
+    ctx = ads.Context(A, part, N, ov, nev)
+    P = oracle_for(case)
+    As = A.to_scipy()
+    b = W.rhs(A.n, 0)
+    x, info = ctx.solve(torch.tensor(b, device=DEV), restart=restart, flexible=flex, rtol=1e-8)
+    xo, io = OS.gmres(As, b, P.apply, restart=restart, rtol=1e-8, flexible=flex)
+    x = x.cpu().numpy()
+    assert info["status"] == 0
+    assert abs(info["its"][0] - io["its"]) <= 1, (info["its"], io["its"])
+    assert np.linalg.norm(b - As @ x) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-7
+    # fixed-iteration mode: same iterates
+    k = max(2, io["its"] // 2)
+    xg, _ = ctx.solve(torch.tensor(b, device=DEV), restart=restart, flexible=flex, rtol=0.0,
+                      fixed_iters=k)
+    xk, _ = OS.gmres(As, b, P.apply, restart=restart, rtol=0.0, flexible=flex, fixed_iters=k)
+    assert np.linalg.norm(xg.cpu().numpy() - xk) / np.linalg.norm(xk) <= 1e-9
+    ctx.close()
+
+
+def test_bfs_partition_bit_exact():
+    A = W.convdiff3d(24, nu=0.02)
+    seeds = W.bfs_seeds_3d(24, (6, 6, 6), seed=3)
+    part_gpu = ads.ads_partition_bfs(A, seeds)
+    part_cpu = OS.bfs_partition(A.to_scipy(), seeds)
+    np.testing.assert_array_equal(part_gpu, part_cpu)
+
+
+def test_batched_systems_match_individual_oracles():
+    """Several independent systems of uneven sizes in one context (one launch
+    per phase); each system's apply and solve equal its own oracle's."""
+    sizes = [16, 23, 31, 40]
+    As, parts, Ns = [], [], []
+    for m in sizes:
+        As.append(W.convdiff2d(m, 0.01))
+        p = max(2, round(m / 12))
+        parts.append(W.block_partition_2d(m, p))
+        Ns.append(p * p)
+    ctx = ads.Context(As, parts, Ns, 2, 5, eig_tol=1e-12)
+    offs = np.cumsum([0] + [A.n for A in As])
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(offs[-1])
+    z = ctx.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    b = np.concatenate([W.rhs(A.n, k) for k, A in enumerate(As)])
+    x, info = ctx.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    x = x.cpu().numpy()
+    for k, (A, p, N) in enumerate(zip(As, parts, Ns)):
+        P = OS.TwoLevelSchwarz(A.to_scipy(), p, N, 2, 5)
+        sl = slice(offs[k], offs[k + 1])
+        zo = P.apply(r[sl])
+        assert np.abs(z[sl] - zo).max() <= 1e-9 * np.abs(zo).max()
+        xo, io = OS.gmres(A.to_scipy(), b[sl], P.apply, restart=30, rtol=1e-8, flexible=True)
+        assert abs(info["its"][k] - io["its"]) <= 1
+        assert np.linalg.norm(x[sl] - xo) / np.linalg.norm(xo) <= 1e-7
+    ctx.close()
+
+
+def test_multiple_rhs_solve():
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64", scale=40)
+    ctx = ads.Context(A, part, N, 2, 6)
+    P = OS.TwoLevelSchwarz(A.to_scipy(), part, N, 2, 6)
+    B = np.stack([W.rhs(A.n, s) for s in range(5)], axis=1)
+    X, info = ctx.solve(torch.tensor(B, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    X = X.cpu().numpy()
+    for j in range(5):
+        xo, io = OS.gmres(A.to_scipy(), B[:, j], P.apply, restart=30, rtol=1e-8, flexible=True)
+        assert abs(info["its"][j] - io["its"]) <= 1
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-7
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [ads.ADS_PREC_FP32, ads.ADS_PREC_BF16])
+def test_reduced_precision_factors_still_solve_to_tolerance(prec):
+    """Mixed precision (local factors FP32/BF16, FP64 Krylov, residual and
+    coarse operator): FGMRES still reaches 1e-8 and the solution agrees with
+    the FP64 oracle within the conditioning of the problem."""
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64", scale=64)
+    As = A.to_scipy()
+    ctx = ads.Context(A, part, N, 2, 8, precision=prec)
+    b = W.rhs(A.n, 0)
+    x, info = ctx.solve(torch.tensor(b, device=DEV), restart=50, flexible=True, rtol=1e-8)
+    x = x.cpu().numpy()
+    assert info["status"] == 0
+    assert np.linalg.norm(b - As @ x) / np.linalg.norm(b) <= 1e-8
+    P = OS.TwoLevelSchwarz(As, part, N, 2, 8)
+    xo, io = OS.gmres(As, b, P.apply, restart=50, rtol=1e-8, flexible=True)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-6
+    ctx.close()
+
+
+def test_overlap0_coarse_space_is_unsupported():
+    """Without overlap the splitting equals A_ii and every eigenvalue of eq. 5
+    is 1: the cluster rule would take the whole subdomain.  The library
+    reports it instead of returning an arbitrary subspace."""
+    A = W.laplace2d(20)
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(A, W.block_partition_2d(20, 2), 4, 0, 3)
+    assert e.value.status == ads.ADS_ERR_UNSUPPORTED
+
+
+def test_errors_are_reported_not_raised():
+    A = W.laplace2d(8)
+    part = np.zeros(A.n, np.int32)
+    part[0] = 3  # parts 1 and 2 empty
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(A, part, 4, 1, 2)
+    assert e.value.status == ads.ADS_ERR_ARG
