@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-level Schwarz hot path on one MI355X.
+
+Workload: 2D first-order upwind convection-diffusion on a 512 x 512 grid
+(n = 262144), velocity (cos 2 pi y, sin 2 pi x), Peclet 100, 8 x 8 block
+partition, overlap 2, nev = 8, right-preconditioned flexible GMRES(50) to a
+relative residual of 1e-8, x0 = 0, rhs ~ N(0, 1) (seed 0).
+
+One step = the whole hot path on that input: setup (overlap maps, Definition-1
+splitting, local factorizations, local eigenproblems of eq. 5, coarse operator
+and its LU) plus the FGMRES solve with the eq. 4 preconditioner.  The matrix
+and right-hand side are resident in device memory before the timed region;
+the partition (int32 per unknown) is a host array by interface and its upload
+is timed.  The production form stores the local factors in FP32 (products
+accumulated in FP64; Arnoldi, residuals and the coarse operator in FP64); the
+plain FP64 form is timed beside it ("vs plain FP64").
+
+Printed: one JSON line with the metric, the per-step time, the plain-FP64 time
+and speedup, the apply kernel's roofline (algorithmic bytes / live hipEvent
+duration) and the FP64 CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+WORKLOAD = "c2_convdiff2d_512_blocks64"
+
+
+def apply_bytes(A, part, info, om, off, elem):
+    """Algorithmic bytes of one local-solve launch and of one whole apply
+    (nrhs = 1); see the design notes for the accounting."""
+    import numpy as np
+    S = A.to_scipy()
+    rl = np.diff(S.indptr)
+    nsub = info["nsub"]
+    tiles = 0
+    lcsr = 0
+    gather = 0
+    for i in range(nsub):
+        ni = int(info["n_i"][i])
+        s = int(info["block"][i])
+        K = -(-ni // s)
+        tiles += (2 * K - 1) * s * s * elem
+        omega = np.sort(om[off[i]:off[i + 1]])
+        sub = S[omega][:, omega]
+        lcsr += sub.nnz * 12 + ni * 8
+        gather += ni * (4 + 4 + 8 + 8) + int(rl[omega].sum()) * 12
+    n = A.n
+    local = tiles + lcsr + gather + n * 8
+    n0 = info["n0"]
+    nev_tot = int((info["nev_i"] * info["n_interior"]).sum())
+    coarse = nev_tot * 8 * 2 + n * (4 + 8) * 2 + n0 * n0 * 8 + n * 8
+    return local, local + coarse, tiles
+
+
+def cpu_baseline():
+    """The FP64 oracle, as it stands, on the full workload, one host thread."""
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle import schwarz as OS
+    A, part, N, o = W.config(WORKLOAD)
+    As = A.to_scipy()
+    b = W.rhs(A.n, 0)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        P = OS.TwoLevelSchwarz(As, part, N, o["overlap"], o["nev"])
+        x, info = OS.gmres(As, b, P.apply, restart=o["restart"], rtol=1e-8, flexible=True)
+        t = time.perf_counter() - t0
+    return dict(value=round(t * 1e3, 1), unit="ms per setup+solve", cores=1, kind="oracle",
+                sample="full workload, one setup+solve (oracle its %d, n0 %d)" % (info["its"], P.n0),
+                host_cpus=os.cpu_count())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--apply-reps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_02250_amd import ads
+
+    dev = torch.device("cuda:0")
+    A, part, N, o = W.config(WORKLOAD)
+    Ad = ads.DeviceCSR(A, dev)
+    b = torch.tensor(W.rhs(A.n, 0), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+    precs = {"fp64": ads.ADS_PREC_FP64, "fp32": ads.ADS_PREC_FP32, "bf16": ads.ADS_PREC_BF16}
+    prec = precs[args.precision]
+
+    def step(p):
+        ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=p, stream=sp)
+        x, info = ctx.solve(b, restart=o["restart"], flexible=True, rtol=1e-8)
+        return ctx, x, info
+
+    def timed(p, steps, warmup, label):
+        for _ in range(warmup):
+            c, x, info = step(p)
+            c.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [step(p) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        for c, x, info in runs:
+            assert info["status"] == 0, (label, info)
+        c, x, info = runs[-1]
+        xh, bh = x.cpu().numpy(), b.cpu().numpy()
+        relres = float(np.linalg.norm(bh - A.to_scipy() @ xh) / np.linalg.norm(bh))
+        meta = dict(its=info["its"][0], relres=relres, setup_ms=info["t_setup_ms"],
+                    solve_ms=info["t_solve_ms"], phases=c.info["t_phase_ms"][:6],
+                    n0=c.info["n0"], eig_sweeps_max=c.info["eig_sweeps_max"])
+        for c, x, info in runs:
+            c.close()
+        print("[bench] %s: %.2f ms/step its %d relres %.2e" % (label, dt * 1e3, meta["its"], relres),
+              file=sys.stderr, flush=True)
+        return dt, meta
+
+    t_prod, m_prod = timed(prec, args.steps, args.warmup, args.precision)
+    t_fp64, m_fp64 = timed(ads.ADS_PREC_FP64, args.steps, 1, "fp64")
+
+    # apply: live hipEvent timing of the local-solve kernel and of the whole apply
+    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=prec, stream=sp, profile=1)
+    om, off, nI, lay = ads.ads_export_maps(ctx.ctx)
+    r = torch.randn(A.n, dtype=torch.float64, device=dev)
+    z = torch.empty_like(r)
+    for _ in range(args.apply_reps):
+        ads.ads_apply(ctx.ctx, r.data_ptr(), z.data_ptr(), 1, sp)
+    torch.cuda.synchronize()
+    info = ads.ads_get_info(ctx.ctx)
+    t_local = info["t_kernel_ms"][0] / max(info["n_kernel"][0], 1)
+    t_apply = info["t_kernel_ms"][3] / max(info["n_kernel"][3], 1)
+    elem = {ads.ADS_PREC_FP64: 8, ads.ADS_PREC_FP32: 4, ads.ADS_PREC_BF16: 2}[prec]
+    b_local, b_apply, b_tiles = apply_bytes(A, part, info, om, off, elem)
+    ctx.close()
+    ach_local = b_local / (t_local * 1e-3) / 1e9
+    ach_apply = b_apply / (t_apply * 1e-3) / 1e9
+
+    out = {
+        "metric": "setup+GMRES time to 1e-8 rel. residual vs plain FP64; apply HBM GB/s",
+        "value": round(t_prod * 1e3, 3),
+        "unit": "ms per setup+solve",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_prod * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32-factors/f64", "bf16": "bf16-factors/f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": A.n, "nnz": A.nnz, "subdomains": N,
+                   "overlap": o["overlap"], "nev": o["nev"], "krylov": "FGMRES(50)", "rtol": 1e-8,
+                   "precision": args.precision},
+        "plain_fp64_ms": round(t_fp64 * 1e3, 3),
+        "speedup_vs_plain_fp64": round(t_fp64 / t_prod, 3),
+        "production": m_prod,
+        "plain_fp64": m_fp64,
+        "roofline": {"kernel": "k_local_solve", "bound": "hbm", "achieved": round(ach_local, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_local / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": int(b_local),
+                     "avg_launch_us": round(t_local * 1e3, 2)},
+        "apply": {"achieved_GBs": round(ach_apply, 1), "frac": round(ach_apply / HBM_PEAK_GBS, 4),
+                  "bytes_per_apply": int(b_apply), "avg_us": round(t_apply * 1e3, 2),
+                  "factor_tile_bytes": int(b_tiles)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,10 +93,12 @@ typedef struct {
                              (0 -> 1e-10 in FP64, 1e-6 otherwise)                    */
   int32_t eig_max_sweeps; /* 0 -> 400                                                 */
   const char* gnn_weights_path; /* weights file for warm_start = 1 (NULL otherwise)  */
+  int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream
+                             (reported in ads_info.t_kernel_ms / n_kernel)           */
 } ads_options;
 
 typedef struct {
-  int32_t restart;        /* m of GMRES(m), 1..256                                    */
+  int32_t restart;        /* m of GMRES(m), 1..64                                     */
   int32_t flexible;       /* 0: right-preconditioned GMRES; 1: flexible GMRES         */
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (Arnoldi estimate and
                              recomputed true residual), x0 = 0 (Section 4)           */
@@ -121,6 +123,9 @@ typedef struct {
   int32_t eig_unconverged;/* subdomains that hit eig_max_sweeps                       */
   int32_t eig_fallbacks;  /* warm starts rejected in favour of the cold start         */
   double t_phase_ms[8];   /* maps, extract, factor, eig, coarse, other, -, -          */
+  double t_kernel_ms[4];  /* profile = 1: summed device time of the apply kernels:
+                             local solve, coarse restrict, coarse prolong, total apply */
+  int64_t n_kernel[4];    /* number of timed launches of each                         */
   /* optional caller-owned host arrays of length nsub (NULL to skip): */
   int32_t* nev_i;         /* coarse vectors per subdomain                             */
   int32_t* kernel_dim;    /* dim ker(splitting) per subdomain (0 or 1)                */

@@ -39,7 +39,7 @@ class ads_options(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("overlap", C.c_int32), ("nev", C.c_int32),
                 ("tau", C.c_double), ("variant", C.c_int32), ("precision", C.c_int32),
                 ("warm_start", C.c_int32), ("eig_tol", C.c_double), ("eig_max_sweeps", C.c_int32),
-                ("gnn_weights_path", C.c_char_p)]
+                ("gnn_weights_path", C.c_char_p), ("profile", C.c_int32)]
 
 
 class ads_ksp_options(C.Structure):
@@ -58,8 +58,21 @@ class ads_info(C.Structure):
                 ("nsys", C.c_int32), ("nsub", C.c_int32), ("n0", C.c_int32),
                 ("eig_sweeps_max", C.c_int32), ("eig_unconverged", C.c_int32),
                 ("eig_fallbacks", C.c_int32), ("t_phase_ms", C.c_double * 8),
+                ("t_kernel_ms", C.c_double * 4), ("n_kernel", C.c_int64 * 4),
                 ("nev_i", C.c_void_p), ("kernel_dim", C.c_void_p), ("n_i", C.c_void_p),
                 ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p)]
+
+
+class DeviceCSR:
+    """CSR already resident in device memory (torch tensors on a GPU)."""
+
+    def __init__(self, A, device="cuda:0"):
+        import torch
+        self.n = A.n
+        self.nnz = A.nnz
+        self.indptr = torch.tensor(np.asarray(A.indptr, np.int64), device=device)
+        self.indices = torch.tensor(np.asarray(A.indices, np.int32), device=device)
+        self.data = torch.tensor(np.asarray(A.data, np.float64), device=device)
 
 
 _lib = None
@@ -120,7 +133,10 @@ def _ptr(a):
 
 
 def make_csr(A):
-    """Host CSR (workloads.CSR or scipy.sparse) -> (ads_csr, keep-alive arrays)."""
+    """Host CSR (workloads.CSR or scipy.sparse) or a DeviceCSR -> (ads_csr, keep-alive)."""
+    if isinstance(A, DeviceCSR):
+        return ads_csr(A.n, A.nnz, A.indptr.data_ptr(), A.indices.data_ptr(), A.data.data_ptr(),
+                       1), (A,)
     if hasattr(A, "tocsr"):
         A = A.tocsr()
         A.sort_indices()
@@ -138,9 +154,9 @@ def make_csr(A):
 
 
 def options(overlap, nev, variant=ADS_VARIANT_DEFLATED, precision=ADS_PREC_FP64, tau=0.0,
-            eig_tol=0.0, eig_max_sweeps=0, warm_start=0, gnn_weights_path=None):
+            eig_tol=0.0, eig_max_sweeps=0, warm_start=0, gnn_weights_path=None, profile=0):
     return ads_options(ADS_ABI_VERSION, overlap, nev, tau, variant, precision, warm_start, eig_tol,
-                       eig_max_sweeps, gnn_weights_path)
+                       eig_max_sweeps, gnn_weights_path, profile)
 
 
 def ads_setup(A, part, nparts, opts, stream=None):
@@ -188,6 +204,8 @@ def ads_get_info(ctx):
     _check(lib().ads_get_info(ctx, C.byref(info)))
     out = {f[0]: getattr(info, f[0]) for f in ads_info._fields_ if f[0] not in arrays}
     out["t_phase_ms"] = list(info.t_phase_ms)
+    out["t_kernel_ms"] = list(info.t_kernel_ms)
+    out["n_kernel"] = list(info.n_kernel)
     out.update(arrays)
     return out
 
@@ -243,10 +261,12 @@ class Context:
     """Owns an ads context; apply/solve take torch CUDA tensors (FP64)."""
 
     def __init__(self, As, parts, nparts, overlap, nev, variant=ADS_VARIANT_DEFLATED,
-                 precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None):
+                 precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None,
+                 profile=0):
         if not isinstance(As, (list, tuple)):
             As, parts, nparts = [As], [parts], [nparts]
-        self.opts = options(overlap, nev, variant, precision, tau, eig_tol, eig_max_sweeps)
+        self.opts = options(overlap, nev, variant, precision, tau, eig_tol, eig_max_sweeps,
+                            profile=profile)
         self.stream = stream
         self.ctx = ads_setup_batched(As, parts, nparts, self.opts, stream)
         self.info = ads_get_info(self.ctx)

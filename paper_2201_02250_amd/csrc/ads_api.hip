@@ -82,6 +82,54 @@ static void to_host(const ads_csr& A, HostCSR& h, hipStream_t s) {
   h.view.on_device = 0;
 }
 
+// copy one system's CSR into the concatenated arrays (row offset r0, entry
+// offset k0), shifting column indices; flags: 1 bad row pointers, 2 column
+// out of range, 4 columns not strictly increasing, 8 non-finite value
+__global__ void k_import_csr(const int64_t* rp, const int32_t* ci, const double* v, int64_t n,
+                             int64_t nnz, int64_t r0, int64_t k0, int32_t* rowptr, int32_t* col,
+                             double* val, int32_t* bad) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n) return;
+  const int64_t base = rp[0];
+  if (r == n) {
+    if (base != 0 || rp[n] != nnz) atomicOr(bad, 1);
+    rowptr[r0 + n] = (int32_t)(k0 + nnz);
+    return;
+  }
+  const int64_t a = rp[r], b = rp[r + 1];
+  rowptr[r0 + r] = (int32_t)(k0 + a);
+  if (b < a || a < 0 || b > nnz) {
+    atomicOr(bad, 1);
+    return;
+  }
+  int prev = -1;
+  for (int64_t k = a; k < b; ++k) {
+    const int c = ci[k];
+    if (c < 0 || c >= n) atomicOr(bad, 2);
+    if (c <= prev) atomicOr(bad, 4);
+    prev = c;
+    if (!isfinite(v[k])) atomicOr(bad, 8);
+    col[k0 + k] = (int32_t)(c + r0);
+    val[k0 + k] = v[k];
+  }
+}
+
+static void import_csr(Ctx& c, const ads_csr& A, int64_t r0, int64_t k0, int32_t* bad,
+                       hipStream_t st) {
+  const int64_t* rp = A.row_ptr;
+  const int32_t* ci = A.col;
+  const double* v = A.val;
+  Arena tmp;
+  if (!A.on_device) {
+    rp = upload(tmp, A.row_ptr, A.n + 1, st);
+    ci = upload(tmp, A.col, A.nnz, st);
+    v = upload(tmp, A.val, A.nnz, st);
+  }
+  ADS_LAUNCH(k_import_csr, dim3((unsigned)((A.n + 256) / 256)), dim3(256), 0, st, rp, ci, v, A.n,
+             A.nnz, r0, k0, c.rowptr, c.col, c.val, bad);
+  ADS_HIP(hipStreamSynchronize(st));
+}
+
 static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, const int32_t* nparts,
                        const ads_options* opts, hipStream_t st) {
   if (nsys <= 0) fail(ADS_ERR_ARG, "nsys must be positive");
@@ -102,49 +150,50 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->nsys = nsys;
     Timer tm(st);
     auto t_start = std::chrono::steady_clock::now();
-    // concatenate the systems (block-diagonal matrix), validate, upload
+    // concatenate the systems (block-diagonal matrix): each CSR (host or
+    // device) is imported by a kernel that shifts indices and validates it
     c->sys_row.assign(nsys + 1, 0);
     c->sys_sub.assign(nsys + 1, 0);
-    int64_t nnz = 0;
-    std::vector<HostCSR> hs(nsys);
+    std::vector<int64_t> sys_nnz(nsys + 1, 0);
     for (int s = 0; s < nsys; ++s) {
-      to_host(A[s], hs[s], st);
-      check_csr_host(hs[s].view, s);
+      if (A[s].n <= 0 || A[s].n >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "n out of range");
+      if (A[s].nnz < 0 || A[s].nnz >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "nnz out of range");
+      if (!A[s].row_ptr || !A[s].col || !A[s].val) fail(ADS_ERR_ARG, "null CSR array");
       if (!part[s]) fail(ADS_ERR_ARG, "null partition");
       if (nparts[s] <= 0) fail(ADS_ERR_ARG, "nparts must be positive");
-      c->sys_row[s + 1] = c->sys_row[s] + hs[s].view.n;
+      c->sys_row[s + 1] = c->sys_row[s] + A[s].n;
       c->sys_sub[s + 1] = c->sys_sub[s] + nparts[s];
-      nnz += hs[s].view.nnz;
+      sys_nnz[s + 1] = sys_nnz[s] + A[s].nnz;
     }
     c->n = c->sys_row[nsys];
-    c->nnz = nnz;
+    c->nnz = sys_nnz[nsys];
     c->nsub = c->sys_sub[nsys];
-    if (c->n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31))
+    if (c->n >= (int64_t(1) << 31) || c->nnz >= (int64_t(1) << 31))
       fail(ADS_ERR_UNSUPPORTED, "total n and nnz must be < 2^31");
-    std::vector<int32_t> rp(c->n + 1), ci(nnz), pg(c->n);
-    std::vector<double> v(nnz);
+    c->rowptr = c->mem.alloc<int32_t>(c->n + 1);
+    c->col = c->mem.alloc<int32_t>(c->nnz);
+    c->val = c->mem.alloc<double>(c->nnz);
+    int32_t* bad = c->mem.alloc<int32_t>(1);
+    ADS_HIP(hipMemsetAsync(bad, 0, 4, st));
+    std::vector<int32_t> pg(c->n);
     c->sub_sys.resize(c->nsub);
     for (int s = 0; s < nsys; ++s) {
-      const ads_csr& a = hs[s].view;
-      const int64_t r0 = c->sys_row[s], k0 = a.row_ptr[0];
-      int64_t base = 0;
-      for (int q = 0; q < s; ++q) base += hs[q].view.nnz;
-      for (int64_t r = 0; r < a.n; ++r) {
-        rp[r0 + r] = (int32_t)(base + a.row_ptr[r] - k0);
+      import_csr(*c, A[s], c->sys_row[s], sys_nnz[s], bad, st);
+      for (int64_t r = 0; r < A[s].n; ++r) {
         const int32_t p = part[s][r];
-        if (p < 0 || p >= nparts[s]) fail(ADS_ERR_ARG, "part value out of range in system " + std::to_string(s));
-        pg[r0 + r] = p + c->sys_sub[s];
-      }
-      for (int64_t k = 0; k < a.nnz; ++k) {
-        ci[base + k] = (int32_t)(a.col[k] + r0);
-        v[base + k] = a.val[k];
+        if (p < 0 || p >= nparts[s])
+          fail(ADS_ERR_ARG, "part value out of range in system " + std::to_string(s));
+        pg[c->sys_row[s] + r] = p + c->sys_sub[s];
       }
       for (int q = c->sys_sub[s]; q < c->sys_sub[s + 1]; ++q) c->sub_sys[q] = s;
     }
-    rp[c->n] = (int32_t)nnz;
-    c->rowptr = upload(c->mem, rp.data(), c->n + 1, st);
-    c->col = upload(c->mem, ci.data(), nnz, st);
-    c->val = upload(c->mem, v.data(), nnz, st);
+    {
+      int32_t h = 0;
+      ADS_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
+      ADS_HIP(hipStreamSynchronize(st));
+      if (h & 8) fail(ADS_ERR_NAN, "non-finite matrix entry");
+      if (h) fail(ADS_ERR_ARG, "invalid CSR (row pointers, column range or column order)");
+    }
     c->sub_sys_d = upload(c->mem, c->sub_sys.data(), c->nsub, st);
     c->t_phase_ms[5] += tm.lap();
     build_maps(*c, pg);
@@ -266,6 +315,11 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
     info->eig_unconverged = c.eig_unconverged;
     info->eig_fallbacks = c.eig_fallbacks;
     for (int k = 0; k < 8; ++k) info->t_phase_ms[k] = c.t_phase_ms[k];
+    ctx->c->prof_resolve();
+    for (int k = 0; k < 4; ++k) {
+      info->t_kernel_ms[k] = c.prof_ms[k];
+      info->n_kernel[k] = c.prof_n[k];
+    }
     for (int i = 0; i < c.nsub; ++i) {
       if (info->nev_i) info->nev_i[i] = c.h_nev.empty() ? 0 : c.h_nev[i];
       if (info->kernel_dim) info->kernel_dim[i] = c.h_kdim[i];

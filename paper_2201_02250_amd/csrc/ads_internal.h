@@ -134,6 +134,12 @@ struct Ctx {
   int64_t npad_total = 0;           // sum of nb*bs
   std::vector<int64_t> h_pad_off;
   int64_t* pad_off = nullptr;       // [nsub+1] offsets of padded local vectors
+  int32_t* cpl_col = nullptr;       // [npad_total * 4] couplings to the previous block
+  double* cpl_val = nullptr;
+  int32_t* ucpl_row = nullptr;      // [npad_total * 4] A_k,k+1 by column: rows of the previous block
+  double* ucpl_val = nullptr;
+  bool cpl_ok = false;              // both coupling lists complete (<= 4 per row / column)
+  bool solve_fast = false;          // every subdomain fits the prefetching tile solve
   void* facA = nullptr;             // factors of A_ii (apply)
   void* facT = nullptr;             // factors of the regularised splitting (eigensolver)
   int prec = ADS_PREC_FP64;
@@ -157,12 +163,19 @@ struct Ctx {
 
   // workspace for apply / solve
   double* work = nullptr;   // padded local vectors, npad_total * work_cols
+  double* dummy = nullptr;  // per-thread discard slots of the tile solves
   int work_cols = 0;
   double* cvec = nullptr;   // coarse vectors, n0 * cols
   double* qvec = nullptr;   // coarse correction, n * cols
   int cvec_cols = 0;
 
   double t_phase_ms[8] = {0};
+  // apply profiling (opt.profile): event pairs per kernel, resolved lazily
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];
+  double prof_ms[4] = {0};
+  int64_t prof_n[4] = {0};
+  void prof_resolve();
+  ~Ctx();
   double t_setup_ms = 0;
 };
 
@@ -252,6 +265,21 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   for (int i = 0; i < nw; ++i) s += red[i];
   __syncthreads();
   return s;
+}
+
+// Packed tile format of the local factors: element (r, c) of an s x s tile is
+// stored at ((c / V) * s + r) * V + (c % V) with V = 16 bytes / element size,
+// columns padded with zeros to a multiple of V.  A thread that owns row r and
+// a run of columns then fetches V entries with one 16-byte load, and lanes
+// with consecutive rows read consecutive 16-byte words (fully coalesced).
+template <class FT>
+struct TileV {
+  static constexpr int V = 16 / (int)sizeof(FT);
+};
+__host__ __device__ inline int tile_cols(int s, int V) { return V * ((s + V - 1) / V); }
+__host__ __device__ inline int64_t tile_size(int s, int V) { return (int64_t)s * tile_cols(s, V); }
+__host__ __device__ inline int64_t tile_at(int r, int c, int s, int V) {
+  return ((int64_t)(c / V) * s + r) * V + (c % V);
 }
 
 // storage conversions of factor entries

@@ -92,28 +92,14 @@ k_coarse_prolong(const double* __restrict__ c, int n0, const double* __restrict_
   }
 }
 
-template <class FT, int P>
-__global__ void __launch_bounds__(APPLY_T)
-k_local_solve(const FT* __restrict__ fac, const int64_t* __restrict__ fac_off,
-              const int32_t* __restrict__ bsz, const int32_t* __restrict__ nblk,
-              const int32_t* __restrict__ ni, const int64_t* __restrict__ om_off,
-              const int32_t* __restrict__ om_sorted, const uint8_t* __restrict__ om_int,
-              const int64_t* __restrict__ lrow, const int32_t* __restrict__ lcol,
-              const double* __restrict__ lval, const int32_t* __restrict__ rowptr,
-              const int32_t* __restrict__ col, const double* __restrict__ val,
-              const double* __restrict__ r, const double* __restrict__ q, double* __restrict__ z,
-              int64_t n, int nrhs, double* __restrict__ work, const int64_t* __restrict__ pad_off,
-              int64_t ldw) {
-  extern __shared__ double lds[];
-  const int i = blockIdx.x;
-  const int j0 = blockIdx.y * P;
-  const int pc = min(P, nrhs - j0);
-  const int s = bsz[i], K = nblk[i], ns = ni[i];
-  const int64_t base = om_off[i];
-  const int32_t* om = om_sorted + base;
-  double* X = work + pad_off[i] + (int64_t)j0 * ldw;
-  const int npad = K * s;
-  // gather t = r - A q on Omega_i (zero on the padding)
+// gather t = r - A q on Omega_i (zero on the padding) into X (column jj at X + jj*ld)
+__device__ __forceinline__ void gather_local(const int32_t* __restrict__ om, int ns, int npad,
+                                             const int32_t* __restrict__ rowptr,
+                                             const int32_t* __restrict__ col,
+                                             const double* __restrict__ val,
+                                             const double* __restrict__ r,
+                                             const double* __restrict__ q, int64_t n, int j0, int pc,
+                                             double* X, int64_t ld) {
   for (int e = threadIdx.x; e < npad * pc; e += blockDim.x) {
     const int lr = e % npad, jj = e / npad;
     double v = 0.0;
@@ -127,20 +113,101 @@ k_local_solve(const FT* __restrict__ fac, const int64_t* __restrict__ fac_off,
         v -= aq;
       }
     }
-    X[lr + (int64_t)jj * ldw] = v;
+    X[lr + (int64_t)jj * ld] = v;
   }
-  __syncthreads();
-  adsd::block_solve<FT, P>(fac + fac_off[i], s, K, ns, lrow + base, lcol, lval, X, ldw, pc, lds);
-  // z = q + R_i^T D_i x_i (interior rows only)
+}
+
+// z = q + R_i^T D_i x_i on the interior rows (Boolean partition of unity)
+__device__ __forceinline__ void scatter_local(const int32_t* __restrict__ om,
+                                              const uint8_t* __restrict__ om_int, int ns,
+                                              const double* __restrict__ q, double* __restrict__ z,
+                                              int64_t n, int j0, int pc, const double* X,
+                                              int64_t ld) {
   for (int e = threadIdx.x; e < ns * pc; e += blockDim.x) {
     const int lr = e % ns, jj = e / ns;
-    if (!om_int[base + lr]) continue;
+    if (!om_int[lr]) continue;
     const int g = om[lr];
     const int64_t off = (int64_t)(j0 + jj) * n;
-    double v = X[lr + (int64_t)jj * ldw];
+    double v = X[lr + (int64_t)jj * ld];
     if (q) v += q[off + g];
     z[off + g] = v;
   }
+}
+
+struct LocalArgs {
+  const int64_t* fac_off;
+  const int32_t* bs;
+  const int32_t* nb;
+  const int32_t* ni;
+  const int64_t* om_off;
+  const int32_t* om_sorted;
+  const uint8_t* om_int;
+  const int64_t* lrow;
+  const int32_t* lcol;
+  const double* lval;
+  const int32_t* cpl_col;
+  const double* cpl_val;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const int64_t* pad_off;
+  double* work;
+  int64_t ldw;
+  int64_t n;
+  int64_t vec_lds_off;  // doubles before the LDS-resident vector
+  double* dummy;        // one slot per thread of the launch (stores of idle threads)
+};
+
+// fast path (prefetching tile solve, 1024 threads); LDSX keeps the local
+// vector of one column in LDS
+template <class FT, int P, int D, bool LDSX>
+__global__ void __launch_bounds__(adsd::SOLVE_T)
+k_local_solve_fast(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
+                   const double* __restrict__ q, double* __restrict__ z, int nrhs) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x;
+  const int j0 = blockIdx.y * P;
+  const int pc = min(P, nrhs - j0);
+  const int s = a.bs[i], K = a.nb[i], ns = a.ni[i];
+  const int npad = K * s;
+  const int64_t base = a.om_off[i];
+  const int32_t* om = a.om_sorted + base;
+  double* X;
+  int64_t ld;
+  if (LDSX) {
+    X = lds + a.vec_lds_off;
+    ld = npad;
+  } else {
+    X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
+    ld = a.ldw;
+  }
+  gather_local(om, ns, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, ld);
+  __syncthreads();
+  double* dummy = a.dummy + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+  adsd::block_solve<FT, P, D, LDSX>(fac + a.fac_off[i], s, K, a.cpl_col + a.pad_off[i] * adsd::NCPL,
+                                    a.cpl_val + a.pad_off[i] * adsd::NCPL, X, ld, pc, lds, dummy);
+  scatter_local(om, a.om_int + base, ns, q, z, a.n, j0, pc, X, ld);
+}
+
+// general path (any block size / coupling count)
+template <class FT, int P>
+__global__ void __launch_bounds__(APPLY_T)
+k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
+              const double* __restrict__ q, double* __restrict__ z, int nrhs) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x;
+  const int j0 = blockIdx.y * P;
+  const int pc = min(P, nrhs - j0);
+  const int s = a.bs[i], K = a.nb[i], ns = a.ni[i];
+  const int npad = K * s;
+  const int64_t base = a.om_off[i];
+  const int32_t* om = a.om_sorted + base;
+  double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
+  gather_local(om, ns, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
+  __syncthreads();
+  adsd::block_solve_general<FT, P>(fac + a.fac_off[i], s, K, ns, a.lrow + base, a.lcol, a.lval, X,
+                                   a.ldw, pc, lds);
+  scatter_local(om, a.om_int + base, ns, q, z, a.n, j0, pc, X, a.ldw);
 }
 
 void ensure_work(Ctx& c, int cols) {
@@ -149,43 +216,135 @@ void ensure_work(Ctx& c, int cols) {
   if (c.cvec) c.mem.release(c.cvec);
   if (c.qvec) c.mem.release(c.qvec);
   c.work = c.mem.alloc<double>((size_t)c.npad_total * cols);
+  if (!c.dummy) c.dummy = c.mem.alloc<double>((size_t)c.nsub * 8 * adsd::SOLVE_T);
   c.cvec = c.mem.alloc<double>((size_t)std::max(c.n0, 1) * cols);
   c.qvec = c.mem.alloc<double>((size_t)c.n * cols);
   c.work_cols = cols;
 }
 
-template <class FT, int P>
-static void launch_local(Ctx& c, const double* r, const double* q, double* z, int nrhs,
-                         hipStream_t s) {
-  size_t lds = (size_t)adsd::solve_lds_doubles<P>(c.h_bs, APPLY_T) * sizeof(double);
-  dim3 grid(c.nsub, (nrhs + P - 1) / P);
-  ADS_LAUNCH((k_local_solve<FT, P>), grid, dim3(APPLY_T), lds, s, (const FT*)c.facA, c.fac_off,
-             c.bs, c.nb, c.ni, c.om_off, c.om_sorted, c.om_int, c.lptr_off, c.lcol, c.lval,
-             c.rowptr, c.col, c.val, r, q, z, c.n, nrhs, c.work, c.pad_off, c.npad_total);
+static LocalArgs local_args(Ctx& c) {
+  LocalArgs a;
+  a.fac_off = c.fac_off;
+  a.bs = c.bs;
+  a.nb = c.nb;
+  a.ni = c.ni;
+  a.om_off = c.om_off;
+  a.om_sorted = c.om_sorted;
+  a.om_int = c.om_int;
+  a.lrow = c.lptr_off;
+  a.lcol = c.lcol;
+  a.lval = c.lval;
+  a.cpl_col = c.cpl_col;
+  a.cpl_val = c.cpl_val;
+  a.rowptr = c.rowptr;
+  a.col = c.col;
+  a.val = c.val;
+  a.pad_off = c.pad_off;
+  a.work = c.work;
+  a.ldw = c.npad_total;
+  a.n = c.n;
+  a.vec_lds_off = 0;
+  a.dummy = c.dummy;
+  return a;
 }
 
 template <class FT>
 static void local_dispatch(Ctx& c, const double* r, const double* q, double* z, int nrhs,
                            hipStream_t s) {
-  if (nrhs == 1)
-    launch_local<FT, 1>(c, r, q, z, nrhs, s);
-  else if (nrhs <= 4)
-    launch_local<FT, 4>(c, r, q, z, nrhs, s);
-  else
-    launch_local<FT, 8>(c, r, q, z, nrhs, s);
+  LocalArgs a = local_args(c);
+  constexpr int D = 2;
+  constexpr int DM = 2;  // multi-column variants: shallower prefetch, fewer registers
+  if (c.solve_fast) {
+    int64_t npad_max = 0;
+    for (int i = 0; i < c.nsub; ++i) npad_max = std::max<int64_t>(npad_max, (int64_t)c.h_nb[i] * c.h_bs[i]);
+    const int64_t sd1 = adsd::solve_lds_doubles<1>(c.h_bs, adsd::SOLVE_T);
+    if (nrhs == 1 && (sd1 + npad_max) * 8 <= 150 * 1024) {
+      a.vec_lds_off = sd1;
+      ADS_LAUNCH((k_local_solve_fast<FT, 1, D, true>), dim3(c.nsub, 1), dim3(adsd::SOLVE_T),
+                 (size_t)(sd1 + npad_max) * 8, s, (const FT*)c.facA, a, r, q, z, nrhs);
+    } else if (nrhs <= 4) {
+      const int64_t sd = adsd::solve_lds_doubles<4>(c.h_bs, adsd::SOLVE_T);
+      ADS_LAUNCH((k_local_solve_fast<FT, 4, DM, false>), dim3(c.nsub, 1), dim3(adsd::SOLVE_T),
+                 (size_t)sd * 8, s, (const FT*)c.facA, a, r, q, z, nrhs);
+    } else {
+      const int64_t sd = adsd::solve_lds_doubles<8>(c.h_bs, adsd::SOLVE_T);
+      ADS_LAUNCH((k_local_solve_fast<FT, 8, DM, false>), dim3(c.nsub, (nrhs + 7) / 8),
+                 dim3(adsd::SOLVE_T), (size_t)sd * 8, s, (const FT*)c.facA, a, r, q, z, nrhs);
+    }
+    return;
+  }
+  if (nrhs == 1) {
+    size_t lds = (size_t)adsd::solve_lds_doubles_general<1>(c.h_bs, APPLY_T) * 8;
+    ADS_LAUNCH((k_local_solve<FT, 1>), dim3(c.nsub, 1), dim3(APPLY_T), lds, s, (const FT*)c.facA, a,
+               r, q, z, nrhs);
+  } else {
+    size_t lds = (size_t)adsd::solve_lds_doubles_general<8>(c.h_bs, APPLY_T) * 8;
+    ADS_LAUNCH((k_local_solve<FT, 8>), dim3(c.nsub, (nrhs + 7) / 8), dim3(APPLY_T), lds, s,
+               (const FT*)c.facA, a, r, q, z, nrhs);
+  }
+}
+
+// records a hipEvent pair around a launch when profiling is on
+struct ProfScope {
+  Ctx& c;
+  int k;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(Ctx& cc, int kk, hipStream_t ss) : c(cc), k(kk), s(ss) {
+    if (!c.opt.profile) return;
+    ADS_HIP(hipEventCreate(&a));
+    ADS_HIP(hipEventCreate(&b));
+    ADS_HIP(hipEventRecord(a, s));
+  }
+  ~ProfScope() {
+    if (!c.opt.profile) return;
+    (void)hipEventRecord(b, s);
+    c.prof_ev[k].push_back({a, b});
+  }
+};
+
+void Ctx::prof_resolve() {
+  for (int k = 0; k < 4; ++k) {
+    for (auto& e : prof_ev[k]) {
+      float ms = 0.f;
+      ADS_HIP(hipEventSynchronize(e.second));
+      ADS_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      prof_ms[k] += ms;
+      prof_n[k] += 1;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    prof_ev[k].clear();
+  }
+}
+
+Ctx::~Ctx() {
+  for (int k = 0; k < 4; ++k)
+    for (auto& e : prof_ev[k]) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
 }
 
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
   ensure_work(c, nrhs);
+  ProfScope all(c, 3, s);
   const double* q = nullptr;
   if (c.n0 > 0) {
-    ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nrhs), dim3(APPLY_T), 0, s, r, c.n, c.int_list,
-               c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, c.cvec, c.n0);
-    ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nrhs), dim3(APPLY_T), 0, s, c.cvec, c.n0, c.Einv,
-               c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev,
-               c.coff, c.qvec, c.n);
+    {
+      ProfScope p1(c, 1, s);
+      ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nrhs), dim3(APPLY_T), 0, s, r, c.n, c.int_list,
+                 c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, c.cvec, c.n0);
+    }
+    {
+      ProfScope p2(c, 2, s);
+      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nrhs), dim3(APPLY_T), 0, s, c.cvec, c.n0, c.Einv,
+                 c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W, c.W_off,
+                 c.nev, c.coff, c.qvec, c.n);
+    }
     q = c.qvec;
   }
+  ProfScope p0(c, 0, s);
   switch (c.prec) {
     case ADS_PREC_FP64: local_dispatch<double>(c, r, q, z, nrhs, s); break;
     case ADS_PREC_FP32: local_dispatch<float>(c, r, q, z, nrhs, s); break;

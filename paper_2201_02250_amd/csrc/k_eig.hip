@@ -27,7 +27,7 @@
 
 namespace ads {
 
-static constexpr int EIG_T = 256;
+static constexpr int EIG_T = 1024;
 static constexpr int PMAX = 32;
 static constexpr double CLUSTER_RTOL = 1e-6;
 
@@ -370,46 +370,35 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
 // ---------------------------------------------------------------------------
 // block helpers: Gram matrices over rows, Cholesky QR
 // ---------------------------------------------------------------------------
-static constexpr int GCH = 64;  // rows per LDS chunk
+static constexpr int GCH = 64;       // rows per LDS chunk
+static constexpr int GLD = GCH + 1;  // padded leading dimension (no LDS bank conflicts)
 
-// G[a*p + b] = sum_r U[r + a*ld] V[r + b*ld] over r < n (result in LDS G)
+// G[a*p + b] = sum_{r<n} U[r + a*ld] V[r + b*ld]; one entry per thread (p*p <= blockDim)
 __device__ void gram(const double* U, const double* V, int64_t ld, int n, int p, double* G,
                      double* bufU, double* bufV) {
   const int t = threadIdx.x, T = blockDim.x;
-  double acc[PMAX * PMAX / EIG_T];
-#pragma unroll
-  for (int q = 0; q < PMAX * PMAX / EIG_T; ++q) acc[q] = 0.0;
+  const int a = t / p, b = t % p;
+  const bool own = t < p * p;
+  double acc = 0.0;
   for (int r0 = 0; r0 < n; r0 += GCH) {
     const int rows = min(GCH, n - r0);
     __syncthreads();
     for (int e = t; e < GCH * p; e += T) {
-      const int rr = e % GCH, a = e / GCH;
-      bufU[e] = rr < rows ? U[r0 + rr + a * ld] : 0.0;
-      bufV[e] = rr < rows ? V[r0 + rr + a * ld] : 0.0;
+      const int rr = e % GCH, cc = e / GCH;
+      bufU[rr + cc * GLD] = rr < rows ? U[r0 + rr + cc * ld] : 0.0;
+      bufV[rr + cc * GLD] = rr < rows ? V[r0 + rr + cc * ld] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PMAX * PMAX / EIG_T; ++q) {
-      const int e = t + q * T;
-      if (e < p * p) {
-        const int a = e / p, b = e % p;
-        double sacc = 0.0;
-        for (int rr = 0; rr < GCH; ++rr) sacc += bufU[rr + a * GCH] * bufV[rr + b * GCH];
-        acc[q] += sacc;
-      }
-    }
+    if (own)
+      for (int rr = 0; rr < GCH; ++rr) acc += bufU[rr + a * GLD] * bufV[rr + b * GLD];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PMAX * PMAX / EIG_T; ++q) {
-    const int e = t + q * T;
-    if (e < p * p) G[e] = acc[q];
-  }
+  if (own) G[t] = acc;
   __syncthreads();
 }
 
-// Cholesky of the p x p SPD matrix G (in place, lower R^T stored as upper R
-// row-major: R[a*p+b], b >= a).  Wave 0.  Returns 0 if not positive definite.
+// Cholesky of the p x p SPD matrix G in place (upper factor R, row-major,
+// R[a*p+b] for b >= a).  Wave 0 only.  Returns 0 if not positive definite.
 __device__ int chol_upper(double* G, int p) {
   const int lane = threadIdx.x;
   int ok = 1;
@@ -433,67 +422,70 @@ __device__ int chol_upper(double* G, int p) {
   return ok;
 }
 
-// Xout = Yin R^{-1} (row-wise triangular solve), rows r < n; padding rows set 0
-__device__ void apply_rinv(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
-                           const double* R) {
-  for (int r = threadIdx.x; r < npad; r += blockDim.x) {
-    double y[PMAX];
-#pragma unroll
-    for (int a = 0; a < PMAX; ++a) y[a] = (a < p && r < n) ? Yin[r + a * ld] : 0.0;
-#pragma unroll
-    for (int a = 0; a < PMAX; ++a) {
-      if (a < p) {
-        double v = y[a];
-        for (int b = 0; b < a; ++b) v -= y[b] * R[b * p + a];
-        y[a] = v / R[a * p + a];
-      }
+// Rinv = R^{-1} for the upper triangular R (row-major p x p); wave 0, lane j
+// solves column j
+__device__ void tri_inverse(const double* R, double* Rinv, int p) {
+  const int j = threadIdx.x;
+  if (j < p) {
+    for (int i = p - 1; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) v -= R[i * p + k] * Rinv[k * p + j];
+      Rinv[i * p + j] = (i <= j) ? v / R[i * p + i] : 0.0;
     }
-#pragma unroll
-    for (int a = 0; a < PMAX; ++a)
-      if (a < p) Xout[r + a * ld] = (r < n) ? y[a] : 0.0;
   }
+  WAVE_SYNC();
+}
+
+// Xout[:, 0:p] = Yin[:, 0:p] Rinv over rows r < n (zero on rows n..npad-1);
+// Xout may alias Yin (each chunk is staged in LDS first)
+__device__ void right_mul_upper(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
+                                const double* Rinv, double* buf) {
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int r0 = 0; r0 < npad; r0 += GCH) {
+    const int rows = min(GCH, npad - r0);
+    __syncthreads();
+    for (int e = t; e < GCH * p; e += T) {
+      const int rr = e % GCH, cc = e / GCH;
+      buf[rr + cc * GLD] = (rr < rows && r0 + rr < n) ? Yin[r0 + rr + cc * ld] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < GCH * p; e += T) {
+      const int rr = e % GCH, a = e / GCH;
+      if (rr >= rows) continue;
+      double v = 0.0;
+      for (int b = 0; b <= a; ++b) v += buf[rr + b * GLD] * Rinv[b * p + a];
+      Xout[r0 + rr + a * ld] = v;
+    }
+  }
+  __syncthreads();
 }
 
 struct EigShared {
   SmallEigLds se;
   double H[PMAX * PMAX];
   double G[PMAX * PMAX];
+  double Ri[PMAX * PMAX];
   double HV[PMAX * PMAX];
-  double bufU[GCH * PMAX];
-  double bufV[GCH * PMAX];
+  double bufU[GLD * PMAX];
+  double bufV[GLD * PMAX];
   double red[16];
   double lam_re[PMAX], lam_im[PMAX];
   int flag[4];
 };
 
-// X <- orth(Y) by Cholesky QR twice (Y and X distinct buffers; Y destroyed)
+// Cholesky QR twice: X <- orth(Y) over rows < n (Y is overwritten)
 __device__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S) {
   int ok = 1;
-  double* src = Y;
-  double* dst = X;
   for (int pass = 0; pass < 2; ++pass) {
-    gram(src, src, ld, n, p, S.G, S.bufU, S.bufV);
+    gram(Y, Y, ld, n, p, S.G, S.bufU, S.bufV);
     if (threadIdx.x < 64) {
       int o = chol_upper(S.G, p);
+      tri_inverse(S.G, S.Ri, p);
       if (threadIdx.x == 0) S.flag[0] = o;
     }
     __syncthreads();
     ok &= S.flag[0];
-    apply_rinv(src, dst, ld, n, npad, p, S.G);
-    __syncthreads();
-    if (pass == 0) {
-      double* tmp = src;
-      src = dst;
-      dst = tmp;
-    }
-  }
-  // after two passes the result is in Y's buffer if passes swapped; copy to X
-  if (dst != X) {
-    for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) {
-      const int r = (int)(e % npad), a = (int)(e / npad);
-      X[r + a * ld] = dst[r + a * ld];
-    }
-    __syncthreads();
+    right_mul_upper(Y, pass == 0 ? Y : X, ld, n, npad, p, S.Ri, S.bufU);
   }
   return ok;
 }
@@ -514,6 +506,9 @@ struct EigArgs {
   const double* lval;
   const int32_t* kdim;
   const int64_t* pad_off;
+  const int32_t* cpl_col;
+  const double* cpl_val;
+  double* dummy;    // per-thread discard slots (subdomain x chunk x thread)
   double* X;        // per subdomain npad x p at p*pad_off
   double* Y;
   double* ell;      // per subdomain npad (unit left null vector; floating only)
@@ -537,7 +532,8 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
                                       const int32_t* lcol, const double* lval, double* x,
                                       double* tmp) {
   const int t = threadIdx.x, T = blockDim.x;
-  const int64_t ss = (int64_t)s * s;
+  constexpr int V = adsd::TileV<FT>::V;
+  const int64_t TS = adsd::tile_size(s, V);
   const int npad = K * s;
   for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
   __syncthreads();
@@ -555,10 +551,10 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
       }
     }
     __syncthreads();
-    const FT* G = fac + (int64_t)k * 2 * ss;
+    const FT* G = fac + (int64_t)k * 2 * TS;
     for (int r = t; r < s; r += T) {
       double acc = 0.0;
-      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, (int64_t)r * s + cc) * x[r0 + cc];
+      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, adsd::tile_at(cc, r, s, V)) * x[r0 + cc];
       tmp[r] = acc;
     }
     __syncthreads();
@@ -581,10 +577,10 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
       }
     }
     __syncthreads();
-    const FT* G = fac + (int64_t)k * 2 * ss;
+    const FT* G = fac + (int64_t)k * 2 * TS;
     for (int r = t; r < s; r += T) {
       double acc = 0.0;
-      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, (int64_t)r * s + cc) * tmp[s + cc];
+      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, adsd::tile_at(cc, r, s, V)) * tmp[s + cc];
       tmp[r] = acc;
     }
     __syncthreads();
@@ -637,9 +633,9 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   }
 }
 
-// Y = T X for columns [j0, j0 + PC)
-template <class FT, int PC>
-__global__ void __launch_bounds__(EIG_T) k_eig_op(const FT* fac, EigArgs a) {
+// Y = T X for columns [j0, j0 + PC); FAST selects the prefetching tile solve
+template <class FT, int PC, bool FAST>
+__global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[16];
   const int i = blockIdx.x;
@@ -694,8 +690,16 @@ __global__ void __launch_bounds__(EIG_T) k_eig_op(const FT* fac, EigArgs a) {
     }
     __syncthreads();
   }
-  adsd::block_solve<FT, PC>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, Y, ld, pc,
-                            lds);
+  if constexpr (FAST) {
+    constexpr int D = 2;
+    double* dummy = a.dummy + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+    adsd::block_solve<FT, PC, D, false>(fac + a.fac_off[i], s, K,
+                                        a.cpl_col + a.pad_off[i] * adsd::NCPL,
+                                        a.cpl_val + a.pad_off[i] * adsd::NCPL, Y, ld, pc, lds, dummy);
+  } else {
+    adsd::block_solve_general<FT, PC>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval,
+                                      Y, ld, pc, lds);
+  }
   if (floating) {  // projection onto 1^perp
     for (int j = 0; j < pc; ++j) {
       double sm = 0.0;
@@ -716,7 +720,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_orth0(EigArgs a) {
   double* Y = a.Y + a.pad_off[i] * p;
   for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) Y[e] = X[e];
   __syncthreads();
-  int ok = cholqr2(Y, X, npad, n, npad, p, S);
+  int ok = cholqr2(Y, X, npad, n, npad, p, S);  // Y is scratch
   if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
 }
 
@@ -756,18 +760,20 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
   }
   __syncthreads();
   double rn = 0.0;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    double xr[PMAX], yr[PMAX];
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      xr[k] = k < p ? X[r + k * ld] : 0.0;
-      yr[k] = k < p ? Y[r + k * ld] : 0.0;
+  for (int r0 = 0; r0 < n; r0 += GCH) {
+    const int rows = min(GCH, n - r0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < GCH * p; e += blockDim.x) {
+      const int rr = e % GCH, cc = e / GCH;
+      S.bufU[rr + cc * GLD] = rr < rows ? X[r0 + rr + cc * ld] : 0.0;
+      S.bufV[rr + cc * GLD] = rr < rows ? Y[r0 + rr + cc * ld] : 0.0;
     }
-    for (int c = 0; c < m; ++c) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < GCH * m; e += blockDim.x) {
+      const int rr = e % GCH, c = e / GCH;
       double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < PMAX; ++k)
-        if (k < p) v += yr[k] * S.se.V[c * p + k] - xr[k] * S.HV[c * p + k];
+      for (int k = 0; k < p; ++k)
+        v += S.bufV[rr + k * GLD] * S.se.V[c * p + k] - S.bufU[rr + k * GLD] * S.HV[c * p + k];
       rn += v * v;
     }
   }
@@ -796,8 +802,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
 }
 
 // W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
-__global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* W_off, double* W,
-                                                       double* scratchZ) {
+__global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* W_off, double* W) {
   __shared__ EigShared S;
   const int i = blockIdx.x;
   const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
@@ -811,7 +816,6 @@ __global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* 
   if (cols == 0) return;
   // Z (interior rows, column-major nint x cols) in the Y buffer (npad x p >= nint x cols)
   double* Z = a.Y + a.pad_off[i] * p;
-  double* Z2 = scratchZ + a.pad_off[i] * p;
   const double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
   // interior rows in ascending local order: chunked block scan of the flags
   __shared__ int wtot[EIG_T / 64];
@@ -849,22 +853,17 @@ __global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* 
     run += tot;
   }
   __syncthreads();
-  // orthonormalise the nint x cols block (Cholesky QR twice)
+  // orthonormalise the nint x cols block (Cholesky QR twice, in place)
   for (int pass = 0; pass < 2; ++pass) {
     gram(Z, Z, ld, nint, cols, S.G, S.bufU, S.bufV);
     if (threadIdx.x < 64) {
       int o = chol_upper(S.G, cols);
+      tri_inverse(S.G, S.Ri, cols);
       if (threadIdx.x == 0) S.flag[0] = o;
     }
     __syncthreads();
     if (!S.flag[0] && threadIdx.x == 0) atomicOr(a.err, 8);
-    apply_rinv(Z, Z2, ld, nint, nint, cols, S.G);
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < (int64_t)nint * cols; e += blockDim.x) {
-      const int r = (int)(e % nint), c = (int)(e / nint);
-      Z[r + c * ld] = Z2[r + c * ld];
-    }
-    __syncthreads();
+    right_mul_upper(Z, Z, ld, nint, nint, cols, S.Ri, S.bufU);
   }
   double* Wi = W + W_off[i];
   for (int64_t e = threadIdx.x; e < (int64_t)nint * cols; e += blockDim.x) {
@@ -884,11 +883,19 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   ADS_LAUNCH((k_eig_init<FT>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
   ADS_LAUNCH(k_eig_orth0, dim3(nsub), dim3(EIG_T), 0, st, a);
   constexpr int PC = 8;
-  size_t op_lds = (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, EIG_T) * sizeof(double);
+  const bool fast = c.solve_fast;
+  size_t op_lds = fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
+                       : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
+  const unsigned op_t = fast ? adsd::SOLVE_T : EIG_T;
   const int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
   std::vector<int32_t> hdone;
   for (int sw = 0; sw < maxsw; ++sw) {
-    ADS_LAUNCH((k_eig_op<FT, PC>), dim3(nsub, (a.p + PC - 1) / PC), dim3(EIG_T), op_lds, st, fac, a);
+    if (fast)
+      ADS_LAUNCH((k_eig_op<FT, PC, true>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
+                 fac, a);
+    else
+      ADS_LAUNCH((k_eig_op<FT, PC, false>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
+                 fac, a);
     ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)(sw == maxsw - 1));
     if (sw % 4 == 3 || sw == maxsw - 1) {
       download(hdone, a.done, nsub, st);
@@ -926,6 +933,9 @@ void eigensolve(Ctx& c) {
   a.lval = c.lval;
   a.kdim = c.kdim;
   a.pad_off = c.pad_off;
+  a.cpl_col = c.cpl_col;
+  a.cpl_val = c.cpl_val;
+  a.dummy = c.mem.alloc<double>((size_t)nsub * ((p + 7) / 8) * 1024);
   a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
   a.Y = c.mem.alloc<double>((size_t)c.npad_total * p);
   a.ell = c.mem.alloc<double>(c.npad_total);
@@ -999,11 +1009,9 @@ void eigensolve(Ctx& c) {
   c.coff = upload(c.mem, c.h_coff.data(), nsub + 1, st);
   c.W_off = upload(c.mem, c.h_W_off.data(), nsub + 1, st);
   c.W = c.mem.alloc<double>(std::max<int64_t>(c.h_W_off[nsub], 1));
-  double* scratchZ = c.mem.alloc<double>((size_t)c.npad_total * p);
-  ADS_LAUNCH(k_eig_finish, dim3(nsub), dim3(EIG_T), 0, st, a, c.W_off, c.W, scratchZ);
+  ADS_LAUNCH(k_eig_finish, dim3(nsub), dim3(EIG_T), 0, st, a, c.W_off, c.W);
   download(herr, a.err, 1, st);
   if (herr[0] & 8) fail(ADS_ERR_EIG_NOCONV, "coarse basis of a subdomain is rank deficient");
-  c.mem.release(scratchZ);
   c.mem.release(a.X);
   c.mem.release(a.Y);
 

@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "ads_internal.h"
+#include "k_solve.h"
 
 namespace ads {
 
@@ -87,6 +88,90 @@ __global__ void k_kernel_dim(const int32_t* nfail, int nsub, int32_t* kdim) {
   if (i < nsub) kdim[i] = (nfail[i] == 0) ? 1 : 0;
 }
 
+// per padded local row: the (column in the previous block, value) couplings
+// A_k,k-1 of the block-tridiagonal form, at most NCPL of them
+__global__ void k_couplings(const int64_t* pad_off, int nsub, const int32_t* bs, const int32_t* ni,
+                            const int64_t* om_off, const int64_t* lrow, const int32_t* lcol,
+                            const double* lval, int64_t total, int32_t* ccol, double* cval,
+                            int32_t* overflow) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  const int i = adsd::segment_of(pad_off, nsub, f);
+  const int r = (int)(f - pad_off[i]);
+  const int s = bs[i];
+  const int k = r / s;
+  int cnt = 0;
+  if (r < ni[i] && k > 0) {
+    const int64_t row = om_off[i] + r;
+    for (int64_t q = lrow[row]; q < lrow[row + 1]; ++q) {
+      const int cc = lcol[q] - (k - 1) * s;
+      if (cc < 0 || cc >= s) continue;
+      if (cnt < adsd::NCPL) {
+        ccol[f * adsd::NCPL + cnt] = cc;
+        cval[f * adsd::NCPL + cnt] = lval[q];
+      }
+      ++cnt;
+    }
+  }
+  if (cnt > adsd::NCPL) atomicOr(overflow, 1);
+  for (int m = cnt; m < adsd::NCPL; ++m) {
+    ccol[f * adsd::NCPL + m] = -1;
+    cval[f * adsd::NCPL + m] = 0.0;
+  }
+}
+
+// per padded local row c' (as a column of its block): the entries a_{r,c'} of
+// the rows r of the previous block, at most NCPL, sorted by r (deterministic)
+__global__ void k_upper_couplings(const int64_t* pad_off, int nsub, const int32_t* bs,
+                                  const int32_t* ni, const int64_t* om_off, const int64_t* lrow,
+                                  const int32_t* lcol, const double* lval, int64_t total,
+                                  int32_t* ucnt, int32_t* urow, double* uval) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  const int i = adsd::segment_of(pad_off, nsub, f);
+  const int r = (int)(f - pad_off[i]);
+  const int s = bs[i];
+  const int k = r / s;
+  if (r >= ni[i]) return;
+  const int64_t row = om_off[i] + r;
+  for (int64_t q = lrow[row]; q < lrow[row + 1]; ++q) {
+    const int cp = lcol[q];
+    if (cp / s != k + 1) continue;
+    const int64_t fc = pad_off[i] + cp;  // padded slot of column c'
+    const int slot = atomicAdd(&ucnt[fc], 1);
+    if (slot < adsd::NCPL) {
+      urow[fc * adsd::NCPL + slot] = r - k * s;
+      uval[fc * adsd::NCPL + slot] = lval[q];
+    }
+  }
+}
+
+__global__ void k_upper_sort(int64_t total, int32_t* ucnt, int32_t* urow, double* uval,
+                             int32_t* overflow) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  int n = ucnt[f];
+  if (n > adsd::NCPL) {
+    atomicOr(overflow, 1);
+    n = adsd::NCPL;
+  }
+  int32_t* rr = urow + f * adsd::NCPL;
+  double* vv = uval + f * adsd::NCPL;
+  for (int a = 1; a < n; ++a)  // insertion sort by row
+    for (int b = a; b > 0 && rr[b - 1] > rr[b]; --b) {
+      int tr = rr[b];
+      rr[b] = rr[b - 1];
+      rr[b - 1] = tr;
+      double tv = vv[b];
+      vv[b] = vv[b - 1];
+      vv[b - 1] = tv;
+    }
+  for (int m = n; m < adsd::NCPL; ++m) {
+    rr[m] = -1;
+    vv[m] = 0.0;
+  }
+}
+
 void extract_local(Ctx& c) {
   hipStream_t s = c.stream;
   const int64_t T = c.omega_total;
@@ -130,6 +215,33 @@ void extract_local(Ctx& c) {
   c.nb = upload(c.mem, c.h_nb.data(), nsub, s);
   c.pad_off = upload(c.mem, c.h_pad_off.data(), nsub + 1, s);
   c.mem.release(cnt);
+  // couplings for the prefetching tile solve
+  c.cpl_col = c.mem.alloc<int32_t>((size_t)c.npad_total * adsd::NCPL);
+  c.cpl_val = c.mem.alloc<double>((size_t)c.npad_total * adsd::NCPL);
+  int32_t* ovf = c.mem.alloc<int32_t>(1);
+  ADS_HIP(hipMemsetAsync(ovf, 0, 4, s));
+  ADS_LAUNCH(k_couplings, dim3((unsigned)((c.npad_total + 255) / 256)), dim3(256), 0, s, c.pad_off,
+             nsub, c.bs, c.ni, c.om_off, c.lptr_off, c.lcol, c.lval, c.npad_total, c.cpl_col,
+             c.cpl_val, ovf);
+  int32_t* ucnt = c.mem.alloc<int32_t>(c.npad_total);
+  c.ucpl_row = c.mem.alloc<int32_t>((size_t)c.npad_total * adsd::NCPL);
+  c.ucpl_val = c.mem.alloc<double>((size_t)c.npad_total * adsd::NCPL);
+  int32_t* uovf = c.mem.alloc<int32_t>(1);
+  ADS_HIP(hipMemsetAsync(ucnt, 0, c.npad_total * 4, s));
+  ADS_HIP(hipMemsetAsync(uovf, 0, 4, s));
+  ADS_LAUNCH(k_upper_couplings, dim3((unsigned)((c.npad_total + 255) / 256)), dim3(256), 0, s,
+             c.pad_off, nsub, c.bs, c.ni, c.om_off, c.lptr_off, c.lcol, c.lval, c.npad_total, ucnt,
+             c.ucpl_row, c.ucpl_val);
+  ADS_LAUNCH(k_upper_sort, dim3((unsigned)((c.npad_total + 255) / 256)), dim3(256), 0, s,
+             c.npad_total, ucnt, c.ucpl_row, c.ucpl_val, uovf);
+  std::vector<int32_t> hov, huov;
+  download(hov, ovf, 1, s);
+  download(huov, uovf, 1, s);
+  c.mem.release(ucnt);
+  c.cpl_ok = hov[0] == 0 && huov[0] == 0;
+  c.solve_fast = hov[0] == 0;
+  const int V = c.prec == ADS_PREC_FP64 ? 2 : (c.prec == ADS_PREC_FP32 ? 4 : 8);
+  for (int b : c.h_bs) c.solve_fast = c.solve_fast && adsd::solve_fast_ok(b, adsd::SOLVE_T, 1, V);
   ADS_HIP(hipStreamSynchronize(s));
 }
 

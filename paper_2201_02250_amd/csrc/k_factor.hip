@@ -25,10 +25,23 @@
 #include <algorithm>
 
 #include "ads_internal.h"
+#include "k_solve.h"
 
 namespace ads {
 
 static constexpr int FAC_T = 256;
+
+// store the row-major s x s matrix M (LDS or scratch) as a packed tile
+template <class FT>
+__device__ __forceinline__ void store_tile(FT* dst, const double* M, int s, int V) {
+  const int64_t TS = adsd::tile_size(s, V);
+  for (int64_t e = threadIdx.x; e < TS; e += blockDim.x) {
+    const int v = (int)(e % V);
+    const int64_t rest = e / V;
+    const int r = (int)(rest % s), c = (int)(rest / s) * V + v;
+    adsd::st_fac(dst, e, c < s ? M[(int64_t)r * s + c] : 0.0);
+  }
+}
 
 template <class FT>
 __global__ void __launch_bounds__(FAC_T)
@@ -48,6 +61,8 @@ k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, con
   const bool regularise = splitting && kdim[i];
   FT* F = fac + fac_off[i];
   const int64_t ss = (int64_t)s * s;
+  constexpr int V = adsd::TileV<FT>::V;
+  const int64_t TS = adsd::tile_size(s, V);
 
   for (int k = 0; k < K; ++k) {
     const int r0 = k * s;
@@ -109,12 +124,9 @@ k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, con
       }
     }
     __syncthreads();
-    // store G_k column-major: element (r, c) at r + c*s
-    FT* G = F + (int64_t)k * 2 * ss;
-    for (int64_t e = t; e < ss; e += T) {
-      const int cc = (int)(e / s), rr = (int)(e - (int64_t)cc * s);
-      adsd::st_fac(G, e, D[(int64_t)rr * s + cc]);
-    }
+    // store G_k in the packed tile format
+    FT* G = F + (int64_t)k * 2 * TS;
+    store_tile(G, D, s, V);
     if (k + 1 < K) {
       // P_k = G_k A_k,k+1: thread owns rows rho
       for (int64_t e = t; e < ss; e += T) Pp[e] = 0.0;
@@ -131,14 +143,151 @@ k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, con
         }
       }
       __syncthreads();
-      FT* P = G + ss;
-      for (int64_t e = t; e < ss; e += T) {
-        const int cc = (int)(e / s), rr = (int)(e - (int64_t)cc * s);
-        adsd::st_fac(P, e, Pp[(int64_t)rr * s + cc]);
-      }
+      store_tile(G + TS, Pp, s, V);
     }
     __syncthreads();
   }
+}
+
+// Same factorization, element-parallel: 1024 threads, the Schur update and
+// P_k use the fixed-width coupling lists (A_k,k-1 by row, A_k,k+1 by column),
+// Gauss-Jordan takes two barriers per pivot.  blockIdx.y selects the matrix
+// (0: A_ii, 1: splitting), so both are factored in one launch.
+template <class FT>
+__global__ void __launch_bounds__(1024)
+k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval,
+                    const double* lsum, const uint8_t* om_int, const int64_t* om_off,
+                    const int32_t* ni, const int32_t* bsz, const int32_t* nblk,
+                    const int64_t* fac_off, const int32_t* kdim, const int64_t* pad_off,
+                    const int32_t* ccol, const double* cval, const int32_t* urow,
+                    const double* uval, FT* facA, FT* facT, double* gscr, int64_t gscr_stride,
+                    int use_lds, int32_t* bad_pivot) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x;
+  const int splitting = blockIdx.y;
+  FT* fac = splitting ? facT : facA;
+  const int s = bsz[i], K = nblk[i], n = ni[i];
+  const int t = threadIdx.x, T = blockDim.x;
+  double* D = use_lds ? lds : gscr + ((int64_t)splitting * gridDim.x + i) * gscr_stride;
+  double* Pp = D + (int64_t)s * s;
+  double* rowp = Pp + (int64_t)s * s;
+  double* colp = rowp + s;
+  const int64_t rbase = om_off[i];
+  const int64_t pbase = pad_off[i];
+  const bool regularise = splitting && kdim[i];
+  FT* F = fac + fac_off[i];
+  const int64_t ss = (int64_t)s * s;
+  constexpr int V = adsd::TileV<FT>::V;
+  const int64_t TS = adsd::tile_size(s, V);
+  for (int k = 0; k < K; ++k) {
+    const int r0 = k * s;
+    __syncthreads();
+    for (int64_t e = t; e < ss; e += T) D[e] = 0.0;
+    __syncthreads();
+    for (int rr = t; rr < s; rr += T) {
+      const int r = r0 + rr;
+      if (r >= n) {
+        D[(int64_t)rr * s + rr] = 1.0;
+        continue;
+      }
+      const int64_t f = rbase + r;
+      for (int64_t q = lrow[f]; q < lrow[f + 1]; ++q) {
+        const int cc = lcol[q] - r0;
+        if (cc < 0 || cc >= s) continue;
+        double a = lval[q];
+        if (cc == rr && splitting) {
+          if (!om_int[f]) a -= lsum[f];
+          if (regularise && r == n - 1) a *= 2.0;
+        }
+        D[(int64_t)rr * s + cc] = a;
+      }
+    }
+    __syncthreads();
+    if (k > 0) {  // D -= A_k,k-1 P_{k-1}
+      for (int64_t e = t; e < ss; e += T) {
+        const int rr = (int)(e / s), j = (int)(e - (int64_t)rr * s);
+        const int64_t cb = (pbase + r0 + rr) * adsd::NCPL;
+        double v = D[e];
+#pragma unroll
+        for (int m = 0; m < adsd::NCPL; ++m) {
+          const int cc = ccol[cb + m];
+          if (cc >= 0) v -= cval[cb + m] * Pp[(int64_t)cc * s + j];
+        }
+        D[e] = v;
+      }
+    }
+    // Gauss-Jordan inversion in place, no pivoting (2 barriers per pivot)
+    for (int p = 0; p < s; ++p) {
+      __syncthreads();
+      for (int e = t; e < s; e += T) {
+        rowp[e] = D[(int64_t)p * s + e];
+        colp[e] = D[(int64_t)e * s + p];
+      }
+      __syncthreads();
+      double piv = rowp[p];
+      if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
+        if (t == 0) atomicMax(bad_pivot, i + 1);
+        piv = 1.0;
+      }
+      const double inv = 1.0 / piv;
+      for (int64_t e = t; e < ss; e += T) {
+        const int rr = (int)(e / s), j = (int)(e - (int64_t)rr * s);
+        double v;
+        if (rr == p)
+          v = (j == p) ? inv : rowp[j] * inv;
+        else if (j == p)
+          v = -colp[rr] * inv;
+        else
+          v = D[e] - colp[rr] * rowp[j] * inv;
+        D[e] = v;
+      }
+    }
+    __syncthreads();
+    FT* G = F + (int64_t)k * 2 * TS;
+    store_tile(G, D, s, V);
+    if (k + 1 < K) {  // P_k = G_k A_k,k+1 (by columns of block k+1)
+      for (int64_t e = t; e < ss; e += T) {
+        const int cp = (int)(e / s), rho = (int)(e - (int64_t)cp * s);
+        const int64_t ub = (pbase + r0 + s + cp) * adsd::NCPL;
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < adsd::NCPL; ++m) {
+          const int rr = urow[ub + m];
+          if (rr >= 0) v += D[(int64_t)rho * s + rr] * uval[ub + m];
+        }
+        Pp[(int64_t)rho * s + cp] = v;
+      }
+      __syncthreads();
+      store_tile(G + TS, Pp, s, V);
+    }
+  }
+}
+
+template <class FT>
+static void factor_fast(Ctx& c, bool both) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub;
+  FT* fa = c.mem.alloc<FT>(c.fac_elems);
+  FT* ft = both ? c.mem.alloc<FT>(c.fac_elems) : nullptr;
+  c.facA = fa;
+  c.facT = ft;
+  int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
+  size_t need = ((size_t)2 * smax * smax + 2 * smax) * sizeof(double);
+  int use_lds = need <= 150 * 1024;
+  int64_t stride = (int64_t)2 * smax * smax + 2 * smax;
+  double* gscr = use_lds ? nullptr : c.mem.alloc<double>((size_t)stride * nsub * 2);
+  int32_t* bad = c.mem.alloc<int32_t>(1);
+  ADS_HIP(hipMemsetAsync(bad, 0, 4, st));
+  ADS_LAUNCH((k_block_factor_fast<FT>), dim3(nsub, both ? 2 : 1), dim3(1024), use_lds ? need : 0,
+             st, c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb,
+             c.fac_off, c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, fa, ft,
+             gscr, stride, use_lds, bad);
+  std::vector<int32_t> hb;
+  download(hb, bad, 1, st);
+  if (gscr) c.mem.release(gscr);
+  if (hb[0])
+    fail(ADS_ERR_SINGULAR, "zero pivot in the local matrix or splitting of subdomain " +
+                               std::to_string(hb[0] - 1));
 }
 
 template <class FT>
@@ -169,13 +318,22 @@ static void factor_one(Ctx& c, int splitting, void** out) {
 void factor_local(Ctx& c) {
   const int nsub = c.nsub;
   c.h_fac_off.assign(nsub + 1, 0);
+  const int V = c.prec == ADS_PREC_FP64 ? 2 : (c.prec == ADS_PREC_FP32 ? 4 : 8);
   for (int i = 0; i < nsub; ++i)
-    c.h_fac_off[i + 1] = c.h_fac_off[i] + (int64_t)2 * c.h_nb[i] * c.h_bs[i] * c.h_bs[i];
+    c.h_fac_off[i + 1] = c.h_fac_off[i] + (int64_t)2 * c.h_nb[i] * adsd::tile_size(c.h_bs[i], V);
   c.fac_elems = c.h_fac_off[nsub];
   c.fac_off = upload(c.mem, c.h_fac_off.data(), nsub + 1, c.stream);
   const bool need_split = c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0;
   size_t esz = c.prec == ADS_PREC_FP64 ? 8 : (c.prec == ADS_PREC_FP32 ? 4 : 2);
   c.factor_bytes = (int64_t)(c.fac_elems * esz);
+  if (c.cpl_ok) {
+    switch (c.prec) {
+      case ADS_PREC_FP64: factor_fast<double>(c, need_split); break;
+      case ADS_PREC_FP32: factor_fast<float>(c, need_split); break;
+      default: factor_fast<__hip_bfloat16>(c, need_split); break;
+    }
+    return;
+  }
   switch (c.prec) {
     case ADS_PREC_FP64:
       factor_one<double>(c, 0, &c.facA);

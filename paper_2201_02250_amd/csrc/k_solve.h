@@ -1,50 +1,262 @@
 // Block-tridiagonal solve with the stored tiles G_k = D_k^{-1}, P_k = G_k A_k,k+1
-// (see k_factor.hip), for P right-hand sides at once, executed by one
-// workgroup.  Used by the preconditioner apply (local solves of eq. 3/eq. 4)
-// and by the eigensolver (the operator of eq. 5).
+// (see k_factor.hip), for up to P right-hand sides, executed by one workgroup.
+// Used by the preconditioner apply (local solves of eq. 3 / eq. 4) and by the
+// eigensolver (the operator of eq. 5).
 //
 // X (padded local vectors, column j at X + j*ldx) is overwritten in place:
-// forward  y_k = f_k - A_k,k-1 h_{k-1},  h_k = G_k y_k   (h_k stored in X)
-// backward x_{K-1} = h_{K-1},  x_k = h_k - P_k x_{k+1}.
-// The sparse couplings A_k,k-1 come from the local CSR of A_ii (identical for
-// the splitting: Definition 1 only changes the diagonal).
+//   forward   y_k = f_k - A_k,k-1 h_{k-1},   h_k = G_k y_k   (h_k stored in X)
+//   backward  x_{K-1} = h_{K-1},   x_k = h_k - P_k x_{k+1}.
+// The couplings A_k,k-1 (Definition 1 changes only the diagonal, so A_ii and the
+// splitting share them) are stored per local row in a fixed-width list of at
+// most NCPL (column in the previous block, value) pairs.
 //
-// Thread mapping of a dense tile product out = M v (M s x s column-major):
-// thread t handles row r = t mod s and column chunk g = t / s; with G chunks,
-// partial sums meet in LDS.  Consecutive threads read consecutive rows of a
-// tile column (coalesced), the vector entry is an LDS broadcast.
+// Latency hiding: the 2K-1 tiles form one sequence.  Thread t owns row
+// r = t mod s and column chunk g = t / s of every tile; it loads exactly the
+// tile entries it multiplies into registers D tiles ahead, so no step waits on
+// a global load; the couplings and the forward inputs f_k are prefetched the
+// same way.  With LDSX the whole local vector lives in LDS (apply, one column);
+// otherwise the backward sweep reads h_k at the start of its step.
 #pragma once
 #include "ads_internal.h"
 
 namespace adsd {
 
-// LDS doubles needed by block_solve<P> with blockDim T, maximised over every
-// block size in `sizes` (a smaller block can use more column chunks).
-template <int P>
-inline int64_t solve_lds_doubles(const std::vector<int32_t>& sizes, int T);
+constexpr int NCPL = 4;     // couplings per row kept by the fast path
+constexpr int SOLVE_T = 1024;
+constexpr int SOLVE_CH = 8; // max tile columns per thread in the fast path
 
-template <int P>
-struct SolveLds {
-  // doubles needed: ybuf (s*P) + hbuf (s*P) + partial (G*s*P)
-  static __host__ __device__ int64_t doubles(int s, int T) {
-    int G = (2 * s <= T) ? (T / s) : 1;
-    return (int64_t)s * P * (2 + (G > 1 ? G : 0));
-  }
-};
+// columns of a tile handled by one thread of the fast path: the even split of
+// s columns over T / s groups, rounded up to whole 16-byte vectors
+__host__ __device__ inline int solve_chunk(int s, int T, int V) {
+  const int G = T / s;
+  const int chunk = (s + G - 1) / G;
+  return V * ((chunk + V - 1) / V);
+}
 
+// fast path applies when every block size s satisfies this (and the couplings fit)
+__host__ __device__ inline bool solve_fast_ok(int s, int T = SOLVE_T, int P = 1, int V = 8) {
+  if (s < 1 || s > T || (P == 1 ? 4 : 1) * s * P > T) return false;
+  return solve_chunk(s, T, V) <= SOLVE_CH;
+}
+
+// LDS doubles of the fast path (ybuf, hbuf, partial sums), excluding an
+// LDS-resident vector
 template <int P>
 inline int64_t solve_lds_doubles(const std::vector<int32_t>& sizes, int T) {
   int64_t m = 0;
-  for (int s : sizes) m = m > SolveLds<P>::doubles(s, T) ? m : SolveLds<P>::doubles(s, T);
+  for (int s : sizes) {
+    const int G = T / s;
+    const int64_t d = (int64_t)s * P * (2 + G);
+    m = m > d ? m : d;
+  }
   return m;
 }
 
-// out[r + j*s] (LDS) = sum_c M[r + c*s] vin[c + j*s]  (+ combine)
-// mode 0: out = M v; mode 1: out = base - M v where base[r + j*s] given (global, ld)
+template <class FT>
+__device__ __forceinline__ float to_f(FT v);
+template <>
+__device__ __forceinline__ float to_f<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
+
+template <class FT>
+struct TileReg {
+  using T = float;  // FP32 / BF16 tiles are held as float
+};
+template <>
+struct TileReg<double> {
+  using T = double;
+};
+// one 16-byte load of V consecutive tile entries, widened to the register type
+template <class FT>
+__device__ __forceinline__ void tile_load_vec(const FT* p, typename TileReg<FT>::T* out);
+template <>
+__device__ __forceinline__ void tile_load_vec<double>(const double* p, double* out) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  out[0] = v.x;
+  out[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void tile_load_vec<float>(const float* p, float* out) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  out[0] = v.x;
+  out[1] = v.y;
+  out[2] = v.z;
+  out[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void tile_load_vec<__hip_bfloat16>(const __hip_bfloat16* p, float* out) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    out[2 * i] = __uint_as_float(w[i] << 16);            // low half (element 2i)
+    out[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);  // high half (element 2i+1)
+  }
+}
+
+// In-place solve.  ccol/cval: couplings of this subdomain's padded rows
+// (row-major, NCPL per row).  X: padded vectors (global or LDS, see LDSX).
+// The LDS work vectors are row-major [row * P + column] so that the column
+// index is an immediate offset of the LDS instruction.
+// dummy: a private scratch slot of this thread (global vector only): threads
+// that own no vector entry store there, so every store is unconditional.
+// Requires LPE * s * pc <= blockDim.x (LPE lanes per entry in phase C).
+template <class FT, int P, int D, bool LDSX>
+__device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int32_t* __restrict__ ccol,
+                            const double* __restrict__ cval, double* X, int64_t ldx, int pc,
+                            double* lds, double* dummy) {
+  using RT = typename TileReg<FT>::T;
+  constexpr int V = TileV<FT>::V;         // elements per 16-byte vector
+  constexpr int NV = SOLVE_CH / V;        // vectors per thread per tile
+  const int t = threadIdx.x, T = blockDim.x;
+  const int chV = solve_chunk(s, T, V);   // columns per thread (multiple of V)
+  const int G = (s + chV - 1) / chV;      // column groups in use
+  const int nq = (s + V - 1) / V;         // vectors per tile row
+  const int r = t % s, g = t / s;
+  const int c0 = g * chV;
+  const int clen = (g < G) ? max(0, min(chV, s - c0)) : 0;
+  const int64_t ss = tile_size(s, V);     // tile stride
+  const int NT = 2 * K - 1;
+  const bool pa = t < s * pc;  // phase-A owner of (prr, pj)
+  const int prr = t % s, pj = t / s;
+  double* ybuf = lds;
+  double* hbuf = ybuf + (int64_t)s * P;
+  double* part = hbuf + (int64_t)s * P;
+
+  static_assert(D % 2 == 0, "the tile ring depth must be even");
+  RT treg[D][SOLVE_CH];
+  int creg_c[2][NCPL];  // couplings and forward inputs: a 2-deep ring of their own
+  double creg_v[2][NCPL];
+  double xreg[2];
+  const int pjc = min(pj, pc - 1);  // clamped column for the unconditional prefetch
+
+  // All prefetch loads are unconditional with clamped, in-bounds addresses:
+  // branch-free issue keeps the compiler's wait counts exact, so a step only
+  // waits for its own tile, not for the tiles prefetched behind it.
+  auto blk = [&](int q) { return q < K ? q : 2 * K - 2 - q; };
+  auto issue_tile = [&](int q, int d) {
+    const int qq = min(q, NT - 1);
+    const int k = blk(qq);
+    const FT* M = fac + (int64_t)k * 2 * ss + (qq < K ? 0 : ss);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int qi = min(c0 / V + v, nq - 1);
+      tile_load_vec<FT>(M + ((int64_t)qi * s + r) * V, &treg[d][v * V]);
+    }
+  };
+  auto issue_aux = [&](int q, int e) {
+    if (!pa) return;  // only the phase-A owners need couplings and inputs
+    const int qq = min(q, NT - 1);
+    const int row = blk(qq) * s + prr;
+    if (!LDSX) xreg[e] = X[row + pjc * ldx];
+#pragma unroll
+    for (int m = 0; m < NCPL; ++m) {
+      creg_c[e][m] = ccol[(int64_t)row * NCPL + m];
+      creg_v[e][m] = cval[(int64_t)row * NCPL + m];
+    }
+  };
+
+  // one step of the sequence with its tile in slot d
+  // phase-C mapping: LPE consecutive lanes per output entry (e = t / LPE), each
+  // summing a strided share of the G partials, combined by shuffles
+  constexpr int LPE = (P == 1) ? 4 : 1;
+  const int ce = t / LPE, cq = t % LPE;
+  const bool cown = ce < s * pc;
+  const int crr = ce % s, cj = min(ce / s, pc - 1);
+  auto step = [&](int q, int d) {
+    const int e = d & 1;  // aux slot (q and d have the same parity: q0 is a multiple of D)
+    const int k = blk(q);
+    const int r0 = k * s;
+    const bool fwd = q < K;
+    // h_k for the backward sweep, read by the phase-C owner (unconditional)
+    double hk = LDSX ? 0.0 : X[r0 + crr + (int64_t)cj * ldx];
+    // phase A: the vector the tile multiplies (branch-free coupling reads)
+    if (pa) {
+      if (fwd) {
+        double y = LDSX ? X[r0 + prr + pj * ldx] : xreg[e];
+#pragma unroll
+        for (int m = 0; m < NCPL; ++m) {
+          const int cc = creg_c[e][m];
+          const double w = cc >= 0 ? creg_v[e][m] : 0.0;
+          y -= w * hbuf[max(cc, 0) * P + pj];
+        }
+        ybuf[prr * P + pj] = y;
+      } else {
+        ybuf[prr * P + pj] = hbuf[prr * P + pj];  // x_{k+1}
+      }
+    }
+    __syncthreads();
+    // phase B: partial products with the tile in registers (groups without
+    // columns write zeros so the reduction reads defined values)
+    if (g < G) {
+      double acc[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] = 0.0;
+#pragma unroll
+      for (int c = 0; c < SOLVE_CH; ++c) {
+        const double m = (c < clen) ? (double)treg[d][c] : 0.0;
+        const int cc = min(c0 + c, s - 1);
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[j] += m * ybuf[cc * P + j];
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) part[((int64_t)g * s + r) * P + j] = acc[j];
+    }
+    issue_tile(q + D, d);
+    issue_aux(q + 2, e);
+    __syncthreads();
+    // phase C: reduce, store
+    constexpr int UNR = 8;  // unrolled share; the tail loop covers larger G
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int gg = cq + LPE * u;
+      if (gg < G) v += part[((int64_t)gg * s + crr) * P + cj];
+    }
+    for (int gg = cq + LPE * UNR; gg < G; gg += LPE)  // small block sizes
+      v += part[((int64_t)gg * s + crr) * P + cj];
+    if (LPE >= 2) v += __shfl_xor(v, 1, 64);
+    if (LPE >= 4) v += __shfl_xor(v, 2, 64);
+    if (!fwd) v = (LDSX ? X[r0 + crr + (int64_t)cj * ldx] : hk) - v;
+    const bool wr = cown && cq == 0;
+    if (wr) hbuf[crr * P + cj] = v;
+    if (LDSX) {
+      if (wr) X[r0 + crr + (int64_t)cj * ldx] = v;
+    } else {
+      double* dst = wr ? X + (r0 + crr + (int64_t)cj * ldx) : dummy;
+      *dst = v;
+    }
+    __syncthreads();
+  };
+
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue_tile(d, d);
+  issue_aux(0, 0);
+  issue_aux(1, 1);
+  // main part: whole groups of D steps, no per-step guard (exact wait counts)
+  const int NTmain = NT - NT % D;
+  for (int q0 = 0; q0 < NTmain; q0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) step(q0 + d, d);
+  }
+  // tail
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (NTmain + d < NT) step(NTmain + d, d);
+}
+
+}  // namespace adsd
+
+namespace adsd {
+
+// General path (any block size, any number of couplings): the tile entries
+// are read directly (no prefetch) and the couplings come from the local CSR.
 template <class FT, int P>
-__device__ __forceinline__ void tile_product(const FT* __restrict__ M, int s, const double* vin,
-                                             double* part, double* out, int mode,
-                                             const double* base, int64_t ldb, int pc) {
+__device__ __forceinline__ void tile_product_general(const FT* __restrict__ M, int s,
+                                                     const double* vin, double* part, double* out,
+                                                     int mode, const double* base, int64_t ldb,
+                                                     int pc) {
   const int t = threadIdx.x, T = blockDim.x;
   const int G = (2 * s <= T) ? (T / s) : 1;
   if (G > 1) {
@@ -56,7 +268,7 @@ __device__ __forceinline__ void tile_product(const FT* __restrict__ M, int s, co
       for (int j = 0; j < P; ++j) acc[j] = 0.0;
       const int c0 = g * chunk, c1 = min(s, c0 + chunk);
       for (int cidx = c0; cidx < c1; ++cidx) {
-        const double m = ld_fac(M, (int64_t)cidx * s + r);
+        const double m = ld_fac(M, tile_at(r, cidx, s, TileV<FT>::V));
 #pragma unroll
         for (int j = 0; j < P; ++j) acc[j] += m * vin[cidx + j * s];
       }
@@ -76,7 +288,7 @@ __device__ __forceinline__ void tile_product(const FT* __restrict__ M, int s, co
 #pragma unroll
       for (int j = 0; j < P; ++j) acc[j] = 0.0;
       for (int cidx = 0; cidx < s; ++cidx) {
-        const double m = ld_fac(M, (int64_t)cidx * s + r);
+        const double m = ld_fac(M, tile_at(r, cidx, s, TileV<FT>::V));
 #pragma unroll
         for (int j = 0; j < P; ++j) acc[j] += m * vin[cidx + j * s];
       }
@@ -85,19 +297,28 @@ __device__ __forceinline__ void tile_product(const FT* __restrict__ M, int s, co
   }
 }
 
-// In-place solve on X (padded length K*s per column, pc <= P columns).
-// lrow/lcol/lval: local CSR rows of this subdomain (lrow points at row 0).
+template <int P>
+inline int64_t solve_lds_doubles_general(const std::vector<int32_t>& sizes, int T) {
+  int64_t m = 0;
+  for (int s : sizes) {
+    const int G = (2 * s <= T) ? (T / s) : 1;
+    const int64_t d = (int64_t)s * P * (2 + (G > 1 ? G : 0));
+    m = m > d ? m : d;
+  }
+  return m;
+}
+
 template <class FT, int P>
-__device__ void block_solve(const FT* __restrict__ fac, int s, int K, int n,
-                            const int64_t* __restrict__ lrow, const int32_t* __restrict__ lcol,
-                            const double* __restrict__ lval, double* X, int64_t ldx, int pc,
-                            double* lds) {
+__device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, int n,
+                                    const int64_t* __restrict__ lrow,
+                                    const int32_t* __restrict__ lcol,
+                                    const double* __restrict__ lval, double* X, int64_t ldx, int pc,
+                                    double* lds) {
   const int t = threadIdx.x, T = blockDim.x;
-  const int64_t ss = (int64_t)s * s;
+  const int64_t ss = tile_size(s, TileV<FT>::V);  // tile stride
   double* ybuf = lds;
   double* hbuf = ybuf + (int64_t)s * P;
   double* part = hbuf + (int64_t)s * P;
-  // forward sweep
   for (int k = 0; k < K; ++k) {
     const int r0 = k * s;
     __syncthreads();
@@ -114,20 +335,20 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, int n,
       ybuf[rr + j * s] = y;
     }
     __syncthreads();
-    tile_product<FT, P>(fac + (int64_t)k * 2 * ss, s, ybuf, part, hbuf, 0, nullptr, 0, pc);
+    tile_product_general<FT, P>(fac + (int64_t)k * 2 * ss, s, ybuf, part, hbuf, 0, nullptr, 0, pc);
     __syncthreads();
     for (int e = t; e < s * pc; e += T) {
       const int rr = e % s, j = e / s;
       X[r0 + rr + j * ldx] = hbuf[rr + j * s];
     }
   }
-  // backward sweep: hbuf holds x_{K-1}
   for (int k = K - 2; k >= 0; --k) {
     const int r0 = k * s;
     __syncthreads();
-    for (int e = t; e < s * pc; e += T) ybuf[e] = hbuf[e];  // x_{k+1}
+    for (int e = t; e < s * pc; e += T) ybuf[e] = hbuf[e];
     __syncthreads();
-    tile_product<FT, P>(fac + (int64_t)k * 2 * ss + ss, s, ybuf, part, hbuf, 1, X + r0, ldx, pc);
+    tile_product_general<FT, P>(fac + (int64_t)k * 2 * ss + ss, s, ybuf, part, hbuf, 1, X + r0,
+                                ldx, pc);
     __syncthreads();
     for (int e = t; e < s * pc; e += T) {
       const int rr = e % s, j = e / s;
