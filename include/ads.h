@@ -133,6 +133,8 @@ typedef struct {
   int32_t* n_interior;    /* |Omega_Ii|                                               */
   int32_t* sweeps;        /* eigensolver sweeps per subdomain                         */
   int32_t* block;         /* block size of the local factorization                    */
+  double* eig_resid;      /* final ||(T X - X H) V||_F / min |lambda| of the selected
+                             invariant subspace per subdomain (eigensolver residual)  */
 } ads_info;
 
 /* Setup for one system (Sections 2 and 3): overlapping subdomains from the

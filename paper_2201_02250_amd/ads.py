@@ -60,7 +60,8 @@ class ads_info(C.Structure):
                 ("eig_fallbacks", C.c_int32), ("t_phase_ms", C.c_double * 8),
                 ("t_kernel_ms", C.c_double * 4), ("n_kernel", C.c_int64 * 4),
                 ("nev_i", C.c_void_p), ("kernel_dim", C.c_void_p), ("n_i", C.c_void_p),
-                ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p)]
+                ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p),
+                ("eig_resid", C.c_void_p)]
 
 
 class DeviceCSR:
@@ -199,6 +200,7 @@ def ads_get_info(ctx):
     nsub = info.nsub
     arrays = {k: np.zeros(nsub, np.int32) for k in ("nev_i", "kernel_dim", "n_i", "n_interior",
                                                      "sweeps", "block")}
+    arrays["eig_resid"] = np.zeros(nsub, np.float64)
     for k, a in arrays.items():
         setattr(info, k, a.ctypes.data)
     _check(lib().ads_get_info(ctx, C.byref(info)))

@@ -327,6 +327,7 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
       if (info->n_interior) info->n_interior[i] = c.h_nI[i];
       if (info->sweeps) info->sweeps[i] = c.h_sweeps.empty() ? 0 : c.h_sweeps[i];
       if (info->block) info->block[i] = c.h_bs[i];
+      if (info->eig_resid) info->eig_resid[i] = c.h_eig_res.empty() ? 0.0 : c.h_eig_res[i];
     }
     return ADS_OK;
   } catch (const Error& e) {

@@ -148,7 +148,7 @@ struct Ctx {
   // coarse space
   int n0 = 0;
   std::vector<int32_t> h_nev, h_coff, h_sweeps;
-  std::vector<double> h_lam_re, h_lam_im;
+  std::vector<double> h_lam_re, h_lam_im, h_eig_res;
   int32_t* nev = nullptr;      // [nsub]
   int32_t* coff = nullptr;     // [nsub+1] coarse column offset (global over systems)
   int64_t* W_off = nullptr;    // [nsub+1]

@@ -5,10 +5,10 @@
 // Omega_Ii, i.e. when i owns a first-layer overlap node of subdomain j.  Per
 // system the blocks are assembled into a dense n0_s x n0_s matrix, one
 // workgroup per nonzero block, with a fixed reduction order (deterministic).
-// Then the FP64 LU with partial pivoting of each E_s (Section 4: exact LU of
-// the second-level operator) and, from those factors, the explicit inverse
-// used by the apply (one matrix-vector product per apply instead of two
-// latency-bound triangular sweeps).
+// Then the exact FP64 inverse of each E_s (Section 4 solves the second-level
+// system exactly) by Gauss-Jordan elimination with partial pivoting: the apply
+// then needs one matrix-vector product instead of two latency-bound
+// triangular sweeps.
 #include <algorithm>
 
 #include "ads_internal.h"
@@ -120,104 +120,217 @@ k_coarse_block(const int32_t* nbcnt, const int32_t* nblist, const int32_t* rowpt
   }
 }
 
-// in-place LU with partial pivoting of each dense system block (row-major),
-// one workgroup per system; piv[k] = row swapped with k at step k
-__global__ void __launch_bounds__(1024)
-k_dense_lu(double* E, const int64_t* E_off, const int32_t* sys_coff, int32_t* piv_all,
-           int32_t* singular) {
-  __shared__ double rv[1024];
-  __shared__ int ri[1024];
-  __shared__ int pivrow;
-  const int sy = blockIdx.x;
-  const int n = sys_coff[sy + 1] - sys_coff[sy];
-  double* A = E + E_off[sy];
-  int32_t* piv = piv_all + sys_coff[sy];
-  const int t = threadIdx.x, T = blockDim.x;
-  for (int k = 0; k < n; ++k) {
-    // argmax |A[i][k]|, i >= k (ties: smallest index)
-    double best = -1.0;
-    int bi = k;
-    for (int r = k + t; r < n; r += T) {
-      double v = fabs(A[(int64_t)r * n + k]);
-      if (v > best) {
-        best = v;
-        bi = r;
-      }
-    }
-    rv[t] = best;
-    ri[t] = bi;
-    __syncthreads();
-    for (int o = T / 2; o > 0; o >>= 1) {
-      if (t < o) {
-        double ov = rv[t + o];
-        int oi = ri[t + o];
-        if (ov > rv[t] || (ov == rv[t] && oi < ri[t])) {
-          rv[t] = ov;
-          ri[t] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    if (t == 0) {
-      pivrow = ri[0];
-      piv[k] = ri[0];
-      if (!(rv[0] > 0.0)) *singular = sy + 1;
-    }
-    __syncthreads();
-    const int pr = pivrow;
-    if (pr != k)
-      for (int c = t; c < n; c += T) {
-        double a = A[(int64_t)k * n + c];
-        A[(int64_t)k * n + c] = A[(int64_t)pr * n + c];
-        A[(int64_t)pr * n + c] = a;
-      }
-    __syncthreads();
-    double pv = A[(int64_t)k * n + k];
-    if (pv == 0.0) pv = 1.0;
-    for (int r = k + 1 + t; r < n; r += T) A[(int64_t)r * n + k] /= pv;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int64_t e = t; e < (int64_t)m * m; e += T) {
-      const int r = k + 1 + (int)(e / m), c = k + 1 + (int)(e % m);
-      A[(int64_t)r * n + c] -= A[(int64_t)r * n + k] * A[(int64_t)k * n + c];
-    }
-    __syncthreads();
+// ---------------------------------------------------------------------------
+// Explicit inverse of each dense E_s by blocked Gauss-Jordan elimination with
+// partial pivoting (row interchanges, the usual column un-permutation at the
+// end).  Column blocks of width nb are processed in turn:
+//   panel kernel : one workgroup per system runs the unblocked in-place
+//                  Gauss-Jordan steps on the n x nb column panel held in LDS,
+//                  records the pivots, writes the panel result S (the panel
+//                  columns of the accumulated transform) and the composed row
+//                  source map src of the block's interchanges;
+//   update kernel: every other column receives the same transform as a rank-nb
+//                  product, out(i, j) = in(src i, j) + sum_l (S(i,l) - [i = k0+l]) in(src(k0+l), j),
+//                  written to the other buffer of a ping-pong pair (no in-place
+//                  races between tiles); the panel columns receive S.
+// Every reduction has a fixed order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+static constexpr int GJ_T = 1024;
+static constexpr int GJ_UT = 256;
+static constexpr int GJ_TILE = 32;
+static constexpr size_t GJ_LDS_MAX = 150 * 1024;
+
+// largest power-of-two panel width <= 32 whose panel fits the LDS budget
+static int gj_panel_width(int64_t n) {
+  int nb = 32;
+  while (nb > 1 && (size_t)n * (nb * 8 + 8 + 4) + 4096 > GJ_LDS_MAX) nb >>= 1;
+  return ((size_t)n * (nb * 8 + 8 + 4) + 4096 > GJ_LDS_MAX) ? 0 : nb;
+}
+
+// (value, index) max with ties to the smaller index; NaN never wins
+__device__ __forceinline__ void gj_better(double& bv, int& bi, double v, int i) {
+  if (v > bv || (v == bv && i < bi)) {
+    bv = v;
+    bi = i;
   }
 }
 
-// inverse from the LU factors: columns of E^{-1} = U^{-1} L^{-1} P e_c,
-// one thread per column, written transposed-free (row-major Einv)
-__global__ void k_dense_inverse(const double* LU, double* Einv, const int64_t* E_off,
-                                const int32_t* sys_coff, const int32_t* piv_all, double* tmp) {
-  const int sy = blockIdx.y;
+__global__ void __launch_bounds__(GJ_T)
+k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int nb,
+           double* Sbuf, int32_t* src_all, int32_t* piv_all, int32_t* singular) {
+  extern __shared__ double gj_lds[];
+  __shared__ double rowk[32], rowkold[32];
+  __shared__ double pval[GJ_T / 64];
+  __shared__ int pidx[GJ_T / 64];
+  __shared__ int swp[32];
+  const int sy = blockIdx.x;
   const int n = sys_coff[sy + 1] - sys_coff[sy];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const double* A = LU + E_off[sy];
-  double* X = Einv + E_off[sy];
-  const int32_t* piv = piv_all + sys_coff[sy];
-  double* x = tmp + E_off[sy] + (int64_t)c * n;  // column workspace
-  // P e_c: apply the row interchanges in order to the unit vector
-  for (int r = 0; r < n; ++r) x[r] = (r == c) ? 1.0 : 0.0;
-  for (int k = 0; k < n; ++k) {
-    int p = piv[k];
-    if (p != k) {
-      double v = x[k];
-      x[k] = x[p];
-      x[p] = v;
+  if (k0 >= n) return;
+  const int kb = min(nb, n - k0);
+  const int t = threadIdx.x, T = blockDim.x, lane = t & 63, wv = t >> 6;
+  double* P = gj_lds;                 // n x nb panel, row-major
+  double* fcol = P + (size_t)n * nb;  // saved pivot column
+  int* src = reinterpret_cast<int*>(fcol + n);
+  const double* A = Ain + E_off[sy];
+  const int lnb = __ffs(nb) - 1;  // nb is a power of two
+  const int ne = n * nb;
+  for (int e = t; e < ne; e += T) {
+    const int i = e >> lnb, l = e & (nb - 1);
+    P[e] = l < kb ? A[(int64_t)i * n + k0 + l] : 0.0;
+  }
+  for (int i = t; i < n; i += T) src[i] = i;
+  __syncthreads();
+  // pivot candidates of the first panel column
+  double bv = -1.0;
+  int bi = n;
+  for (int i = k0 + t; i < n; i += T) gj_better(bv, bi, fabs(P[(int64_t)i * nb]), i);
+  for (int l = 0; l < kb; ++l) {
+    // block-wide argmax of the candidates (wave shuffles, then the partials)
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      gj_better(bv, bi, ov, oi);
+    }
+    if (lane == 0) {
+      pval[wv] = bv;
+      pidx[wv] = bi;
+    }
+    __syncthreads();
+    bv = -1.0;
+    bi = n;
+    for (int w = 0; w < T / 64; ++w) gj_better(bv, bi, pval[w], pidx[w]);
+    const int k = k0 + l;
+    int p = bi;
+    if (!(bv > 0.0) || p >= n) {
+      if (t == 0) atomicMax(singular, sy + 1);
+      p = k;
+    }
+    if (t == 0) {
+      swp[l] = p;
+      piv_all[sys_coff[sy] + k] = p;
+    }
+    // save the pivot column (rows k and p interchanged) and both rows
+    for (int i = t; i < n; i += T) {
+      const int si = i == k ? p : (i == p ? k : i);
+      fcol[i] = P[(int64_t)si * nb + l];
+    }
+    if (t < nb) {
+      rowk[t] = P[(int64_t)p * nb + t];
+      rowkold[t] = P[(int64_t)k * nb + t];
+    }
+    __syncthreads();
+    const double v = fcol[k];
+    const double d = (v != 0.0) ? 1.0 / v : 1.0;
+    bv = -1.0;
+    bi = n;
+    for (int e = t; e < ne; e += T) {
+      const int i = e >> lnb, j = e & (nb - 1);
+      const double old = i == k ? rowk[j] : (i == p ? rowkold[j] : P[e]);
+      double nw;
+      if (i == k)
+        nw = j == l ? d : old * d;
+      else
+        nw = j == l ? -fcol[i] * d : old - fcol[i] * (rowk[j] * d);
+      P[e] = nw;
+      if (j == l + 1 && i > k) gj_better(bv, bi, fabs(nw), i);
     }
   }
-  for (int r = 1; r < n; ++r) {
-    double v = x[r];
-    for (int k = 0; k < r; ++k) v -= A[(int64_t)r * n + k] * x[k];
-    x[r] = v;
+  __syncthreads();
+  if (t == 0)
+    for (int l = 0; l < kb; ++l) {
+      const int k = k0 + l, p = swp[l];
+      const int tmp = src[k];
+      src[k] = src[p];
+      src[p] = tmp;
+    }
+  __syncthreads();
+  double* S = Sbuf + (int64_t)nb * sys_coff[sy];
+  for (int e = t; e < ne; e += T) S[e] = P[e];
+  int32_t* so = src_all + sys_coff[sy];
+  for (int i = t; i < n; i += T) so[i] = src[i];
+}
+
+// out = transform of in for the column block [k0, k0 + kb) (see above);
+// systems whose order is <= k0 are copied unchanged
+__global__ void __launch_bounds__(GJ_UT)
+k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff, int k0,
+            int nb, const double* Sbuf, const int32_t* src_all) {
+  __shared__ double Ssh[GJ_TILE][33];
+  __shared__ double Rsh[32][GJ_TILE];
+  __shared__ int srow[GJ_TILE];
+  const int sy = blockIdx.z;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int i0 = blockIdx.y * GJ_TILE, j0 = blockIdx.x * GJ_TILE;
+  if (i0 >= n || j0 >= n) return;
+  const double* A = Ain + E_off[sy];
+  double* B = Aout + E_off[sy];
+  const int t = threadIdx.x, tr = t / 16, tc = t % 16;
+  if (k0 >= n) {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+        if (i < n && j < n) B[(int64_t)i * n + j] = A[(int64_t)i * n + j];
+      }
+    return;
   }
-  for (int r = n - 1; r >= 0; --r) {
-    double v = x[r];
-    for (int k = r + 1; k < n; ++k) v -= A[(int64_t)r * n + k] * x[k];
-    x[r] = v / A[(int64_t)r * n + r];
+  const int kb = min(nb, n - k0);
+  const double* S = Sbuf + (int64_t)nb * sys_coff[sy];
+  const int32_t* src = src_all + sys_coff[sy];
+  for (int e = t; e < GJ_TILE * 32; e += GJ_UT) {
+    const int r = e / 32, l = e % 32;
+    const int i = i0 + r;
+    double v = 0.0;
+    if (i < n && l < kb) v = S[(int64_t)i * nb + l] - (i == k0 + l ? 1.0 : 0.0);
+    Ssh[r][l] = v;
+    const int rl = e / GJ_TILE, cc = e % GJ_TILE;
+    const int j = j0 + cc;
+    Rsh[rl][cc] = (rl < kb && j < n) ? A[(int64_t)src[k0 + rl] * n + j] : 0.0;
   }
-  for (int r = 0; r < n; ++r) X[(int64_t)r * n + c] = x[r];
+  if (t < GJ_TILE) srow[t] = (i0 + t < n) ? src[i0 + t] : 0;
+  __syncthreads();
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int r = tr + 16 * a, cc = tc + 16 * b;
+      const int i = i0 + r, j = j0 + cc;
+      if (i >= n || j >= n) continue;
+      double v;
+      if (j >= k0 && j < k0 + kb) {
+        v = S[(int64_t)i * nb + (j - k0)];
+      } else {
+        v = A[(int64_t)srow[r] * n + j];
+        for (int l = 0; l < kb; ++l) v += Ssh[r][l] * Rsh[l][cc];
+      }
+      B[(int64_t)i * n + j] = v;
+    }
+}
+
+// Einv(:, j) = W(:, c_j), c = the identity with the recorded interchanges
+// applied to positions in reverse order
+__global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_off,
+                               const int32_t* sys_coff, const int32_t* piv_all, int rows_per_block) {
+  extern __shared__ int cmap[];
+  const int sy = blockIdx.y;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int r0 = blockIdx.x * rows_per_block;
+  if (r0 >= n) return;
+  const int32_t* piv = piv_all + sys_coff[sy];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) cmap[j] = j;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = piv[k];
+      const int tmp = cmap[k];
+      cmap[k] = cmap[p];
+      cmap[p] = tmp;
+    }
+  __syncthreads();
+  const double* W = Win + E_off[sy];
+  double* X = Out + E_off[sy];
+  const int r1 = min(n, r0 + rows_per_block);
+  for (int64_t e = threadIdx.x; e < (int64_t)(r1 - r0) * n; e += blockDim.x) {
+    const int i = r0 + (int)(e / n), j = (int)(e % n);
+    X[(int64_t)i * n + j] = W[(int64_t)i * n + cmap[j]];
+  }
 }
 
 void assemble_coarse(Ctx& c) {
@@ -257,19 +370,39 @@ void assemble_coarse(Ctx& c) {
   ADS_LAUNCH(k_coarse_block, dim3(nsub, NB_MAX), dim3(CO_T), 0, st, nbcnt, nblist, c.rowptr, c.col,
              c.val, c.part, c.ipos, c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff,
              c.sub_sys_d, c.sys_coff, c.E_off, E);
-  int32_t* piv = c.mem.alloc<int32_t>(std::max(c.n0, 1));
-  ADS_LAUNCH(k_dense_lu, dim3(nsys), dim3(1024), 0, st, E, c.E_off, c.sys_coff, piv, flag + 1);
   std::vector<int32_t> hf;
-  download(hf, flag, 2, st);
+  download(hf, flag, 1, st);
   if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
+  const int nb = gj_panel_width(maxs);
+  if (nb == 0)
+    fail(ADS_ERR_UNSUPPORTED, "coarse system of order " + std::to_string(maxs) +
+                                  " exceeds the dense inverse limit");
+  const int n0t = std::max(c.n0, 1);
+  int32_t* piv = c.mem.alloc<int32_t>(n0t);
+  int32_t* src = c.mem.alloc<int32_t>(n0t);
+  double* S = c.mem.alloc<double>((int64_t)n0t * nb);
+  double* F = c.mem.alloc<double>(etot);
+  double* bufs[2] = {E, F};
+  const size_t plds = (size_t)maxs * (nb * 8 + 8 + 4);
+  const unsigned tiles = (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
+    ADS_LAUNCH(k_gj_panel, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], c.E_off, c.sys_coff,
+               (int)k0, nb, S, src, piv, flag + 1);
+    ADS_LAUNCH(k_gj_update, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur], bufs[1 - cur],
+               c.E_off, c.sys_coff, (int)k0, nb, S, src);
+    cur = 1 - cur;
+  }
+  const int rpb = 16;
+  ADS_LAUNCH(k_gj_unpermute, dim3((unsigned)((maxs + rpb - 1) / rpb), nsys), dim3(256),
+             (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], c.E_off, c.sys_coff, piv, rpb);
+  download(hf, flag, 2, st);
   if (hf[1]) fail(ADS_ERR_SINGULAR, "singular coarse operator in system " + std::to_string(hf[1] - 1));
-  c.Einv = c.mem.alloc<double>(etot);
-  double* tmp = c.mem.alloc<double>(etot);
-  ADS_LAUNCH(k_dense_inverse, dim3((unsigned)((maxs + 63) / 64), nsys), dim3(64), 0, st, E, c.Einv,
-             c.E_off, c.sys_coff, piv, tmp);
-  ADS_HIP(hipStreamSynchronize(st));
-  c.mem.release(tmp);
-  c.mem.release(E);
+  c.Einv = bufs[1 - cur];
+  c.mem.release(bufs[cur]);
+  c.mem.release(S);
+  c.mem.release(src);
+  c.mem.release(piv);
 }
 
 }  // namespace ads

@@ -370,31 +370,60 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
 // ---------------------------------------------------------------------------
 // block helpers: Gram matrices over rows, Cholesky QR
 // ---------------------------------------------------------------------------
-static constexpr int GCH = 64;       // rows per LDS chunk
-static constexpr int GLD = GCH + 1;  // padded leading dimension (no LDS bank conflicts)
+// Row passes over an n x p block stage CR rows at a time in LDS, with
+// CR * p <= GBUF: 4096 entries per buffer, so every thread issues several
+// independent loads per round trip.
+static constexpr int GBUF = 4096;
+__device__ __forceinline__ int chunk_rows(int p) { return GBUF / p; }
 
-// G[a*p + b] = sum_{r<n} U[r + a*ld] V[r + b*ld]; one entry per thread (p*p <= blockDim)
-__device__ void gram(const double* U, const double* V, int64_t ld, int n, int p, double* G,
-                     double* bufU, double* bufV) {
+// H[a*p+b] = sum_r U[r,a] V[r,b] and, if G != nullptr, G[a*p+b] = sum_r V[r,a] V[r,b]
+// over r < n.  TPE threads share an entry (partial sums joined by shuffles).
+__device__ void gram2(const double* U, const double* V, int64_t ld, int n, int p, double* H,
+                      double* G, double* bufU, double* bufV) {
   const int t = threadIdx.x, T = blockDim.x;
-  const int a = t / p, b = t % p;
-  const bool own = t < p * p;
-  double acc = 0.0;
-  for (int r0 = 0; r0 < n; r0 += GCH) {
-    const int rows = min(GCH, n - r0);
+  const int CR = chunk_rows(p), LDB = CR + 1;
+  int tpe = T / (p * p);
+  tpe = tpe >= 4 ? 4 : (tpe >= 2 ? 2 : 1);
+  const int ent = t / tpe, sub = t % tpe;
+  const bool own = ent < p * p;
+  const int a = ent / p, b = ent % p;
+  double accH = 0.0, accG = 0.0;
+  for (int r0 = 0; r0 < n; r0 += CR) {
+    const int rows = min(CR, n - r0);
     __syncthreads();
-    for (int e = t; e < GCH * p; e += T) {
-      const int rr = e % GCH, cc = e / GCH;
-      bufU[rr + cc * GLD] = rr < rows ? U[r0 + rr + cc * ld] : 0.0;
-      bufV[rr + cc * GLD] = rr < rows ? V[r0 + rr + cc * ld] : 0.0;
+    for (int e = t; e < CR * p; e += T) {
+      const int rr = e % CR, cc = e / CR;
+      bufU[rr + cc * LDB] = rr < rows ? U[r0 + rr + cc * ld] : 0.0;
+      bufV[rr + cc * LDB] = rr < rows ? V[r0 + rr + cc * ld] : 0.0;
     }
     __syncthreads();
-    if (own)
-      for (int rr = 0; rr < GCH; ++rr) acc += bufU[rr + a * GLD] * bufV[rr + b * GLD];
+    if (own) {
+      for (int rr = sub; rr < rows; rr += tpe) {
+        const double vb = bufV[rr + b * LDB];
+        accH += bufU[rr + a * LDB] * vb;
+        if (G) accG += bufV[rr + a * LDB] * vb;
+      }
+    }
+  }
+  if (tpe >= 2) {
+    accH += __shfl_xor(accH, 1, 64);
+    accG += __shfl_xor(accG, 1, 64);
+  }
+  if (tpe >= 4) {
+    accH += __shfl_xor(accH, 2, 64);
+    accG += __shfl_xor(accG, 2, 64);
   }
   __syncthreads();
-  if (own) G[t] = acc;
+  if (own && sub == 0) {
+    H[ent] = accH;
+    if (G) G[ent] = accG;
+  }
   __syncthreads();
+}
+
+__device__ void gram(const double* U, const double* V, int64_t ld, int n, int p, double* G,
+                     double* bufU, double* bufV) {
+  gram2(U, V, ld, n, p, G, nullptr, bufU, bufV);
 }
 
 // Cholesky of the p x p SPD matrix G in place (upper factor R, row-major,
@@ -441,19 +470,20 @@ __device__ void tri_inverse(const double* R, double* Rinv, int p) {
 __device__ void right_mul_upper(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
                                 const double* Rinv, double* buf) {
   const int t = threadIdx.x, T = blockDim.x;
-  for (int r0 = 0; r0 < npad; r0 += GCH) {
-    const int rows = min(GCH, npad - r0);
+  const int CR = chunk_rows(p), LDB = CR + 1;
+  for (int r0 = 0; r0 < npad; r0 += CR) {
+    const int rows = min(CR, npad - r0);
     __syncthreads();
-    for (int e = t; e < GCH * p; e += T) {
-      const int rr = e % GCH, cc = e / GCH;
-      buf[rr + cc * GLD] = (rr < rows && r0 + rr < n) ? Yin[r0 + rr + cc * ld] : 0.0;
+    for (int e = t; e < CR * p; e += T) {
+      const int rr = e % CR, cc = e / CR;
+      buf[rr + cc * LDB] = (rr < rows && r0 + rr < n) ? Yin[r0 + rr + cc * ld] : 0.0;
     }
     __syncthreads();
-    for (int e = t; e < GCH * p; e += T) {
-      const int rr = e % GCH, a = e / GCH;
+    for (int e = t; e < CR * p; e += T) {
+      const int rr = e % CR, a = e / CR;
       if (rr >= rows) continue;
       double v = 0.0;
-      for (int b = 0; b <= a; ++b) v += buf[rr + b * GLD] * Rinv[b * p + a];
+      for (int b = 0; b <= a; ++b) v += buf[rr + b * LDB] * Rinv[b * p + a];
       Xout[r0 + rr + a * ld] = v;
     }
   }
@@ -464,20 +494,28 @@ struct EigShared {
   SmallEigLds se;
   double H[PMAX * PMAX];
   double G[PMAX * PMAX];
+  double Gy[PMAX * PMAX];
   double Ri[PMAX * PMAX];
   double HV[PMAX * PMAX];
-  double bufU[GLD * PMAX];
-  double bufV[GLD * PMAX];
+  double bufU[GBUF + PMAX];
+  double bufV[GBUF + PMAX];
   double red[16];
   double lam_re[PMAX], lam_im[PMAX];
   int flag[4];
 };
 
-// Cholesky QR twice: X <- orth(Y) over rows < n (Y is overwritten)
-__device__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S) {
+// Cholesky QR twice: X <- orth(Y) over rows < n (Y is overwritten); G0, if
+// given, already holds Y^T Y
+__device__ int cholqr2_g(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S,
+                         const double* G0) {
   int ok = 1;
   for (int pass = 0; pass < 2; ++pass) {
-    gram(Y, Y, ld, n, p, S.G, S.bufU, S.bufV);
+    if (pass == 0 && G0) {
+      for (int e = threadIdx.x; e < p * p; e += blockDim.x) S.G[e] = G0[e];
+      __syncthreads();
+    } else {
+      gram(Y, Y, ld, n, p, S.G, S.bufU, S.bufV);
+    }
     if (threadIdx.x < 64) {
       int o = chol_upper(S.G, p);
       tri_inverse(S.G, S.Ri, p);
@@ -488,6 +526,10 @@ __device__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p,
     right_mul_upper(Y, pass == 0 ? Y : X, ld, n, npad, p, S.Ri, S.bufU);
   }
   return ok;
+}
+
+__device__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S) {
+  return cholqr2_g(Y, X, ld, n, npad, p, S, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,6 +560,9 @@ struct EigArgs {
   int32_t* msel;    // selected count
   double* Vsel;     // per subdomain p x p (column-major p x m)
   double* lam;      // per subdomain 2*p (re, im)
+  double* rres;     // per subdomain relative residual of the last Rayleigh-Ritz step
+  double* rbest;    // best relative residual so far (stagnation test)
+  int32_t* stall;   // consecutive Rayleigh-Ritz steps without a gain on rbest
   int32_t* err;
   int p;
   int nev;
@@ -733,8 +778,8 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
   double* X = a.X + a.pad_off[i] * p;
   double* Y = a.Y + a.pad_off[i] * p;
   const int count = a.nev - a.kdim[i];
-  // H = X^T Y
-  gram(X, Y, ld, n, p, S.H, S.bufU, S.bufV);
+  // H = X^T Y and G = Y^T Y (the first Cholesky QR Gram) in one pass
+  gram2(X, Y, ld, n, p, S.H, S.Gy, S.bufU, S.bufV);
   int m = 0;
   if (threadIdx.x < 64) {
     int ok = 1;
@@ -760,31 +805,47 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
   }
   __syncthreads();
   double rn = 0.0;
-  for (int r0 = 0; r0 < n; r0 += GCH) {
-    const int rows = min(GCH, n - r0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < GCH * p; e += blockDim.x) {
-      const int rr = e % GCH, cc = e / GCH;
-      S.bufU[rr + cc * GLD] = rr < rows ? X[r0 + rr + cc * ld] : 0.0;
-      S.bufV[rr + cc * GLD] = rr < rows ? Y[r0 + rr + cc * ld] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < GCH * m; e += blockDim.x) {
-      const int rr = e % GCH, c = e / GCH;
-      double v = 0.0;
-      for (int k = 0; k < p; ++k)
-        v += S.bufV[rr + k * GLD] * S.se.V[c * p + k] - S.bufU[rr + k * GLD] * S.HV[c * p + k];
-      rn += v * v;
+  {
+    const int CR = chunk_rows(p), LDB = CR + 1;
+    for (int r0 = 0; r0 < n; r0 += CR) {
+      const int rows = min(CR, n - r0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < CR * p; e += blockDim.x) {
+        const int rr = e % CR, cc = e / CR;
+        S.bufU[rr + cc * LDB] = rr < rows ? X[r0 + rr + cc * ld] : 0.0;
+        S.bufV[rr + cc * LDB] = rr < rows ? Y[r0 + rr + cc * ld] : 0.0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < CR * m; e += blockDim.x) {
+        const int rr = e % CR, c = e / CR;
+        if (rr >= rows) continue;
+        double v = 0.0;
+        for (int k = 0; k < p; ++k)
+          v += S.bufV[rr + k * LDB] * S.se.V[c * p + k] - S.bufU[rr + k * LDB] * S.HV[c * p + k];
+        rn += v * v;
+      }
     }
   }
   rn = sqrt(adsd::block_sum(rn, S.red));
   double lmin = 1e300;
   for (int c = 0; c < m; ++c) lmin = fmin(lmin, hypot(S.lam_re[c], S.lam_im[c]));
-  const bool conv = (m == 0) || (rn <= a.tol * lmin) || final_sweep;
+  // converged: residual below the tolerance, or stagnated within 100x of it
+  // (the rounding floor of the operator on strongly non-normal subdomains):
+  // three Rayleigh-Ritz steps in a row without a 5% gain on the best residual
+  const double rel = m ? rn / lmin : 0.0;
+  const double best = a.rbest[i];
+  const bool gain = !(best > 0.0) || rel < 0.95 * best;
+  const int stall = (m && !gain) ? a.stall[i] + 1 : 0;
+  const bool ok_tol = (m == 0) || (rel <= a.tol) || (rel <= 100.0 * a.tol && stall >= 3);
+  const bool conv = ok_tol || final_sweep;
+  __syncthreads();
   if (threadIdx.x == 0) {
     a.sweeps[i] += 1;
     a.msel[i] = m;
-    if (conv) a.done[i] = (rn <= a.tol * lmin || m == 0) ? 1 : 2;
+    a.rres[i] = rel;
+    if (gain) a.rbest[i] = rel;
+    a.stall[i] = stall;
+    if (conv) a.done[i] = ok_tol ? 1 : 2;
   }
   if (conv) {
     double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
@@ -797,7 +858,19 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
     return;
   }
   __syncthreads();
-  int ok = cholqr2(Y, X, ld, n, npad, p, S);
+  int ok = cholqr2_g(Y, X, ld, n, npad, p, S, S.Gy);
+  if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
+}
+
+// orthonormalisation only (sweeps without a Rayleigh-Ritz step)
+__global__ void __launch_bounds__(EIG_T) k_eig_orth(EigArgs a) {
+  __shared__ EigShared S;
+  const int i = blockIdx.x;
+  if (a.done[i]) return;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
+  double* X = a.X + a.pad_off[i] * p;
+  double* Y = a.Y + a.pad_off[i] * p;
+  int ok = cholqr2(Y, X, npad, n, npad, p, S);
   if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
 }
 
@@ -896,7 +969,13 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     else
       ADS_LAUNCH((k_eig_op<FT, PC, false>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
                  fac, a);
-    ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)(sw == maxsw - 1));
+    // Rayleigh-Ritz (and the convergence test) on every other sweep after a
+    // short warm-up; the other sweeps only re-orthonormalise
+    const bool last = sw == maxsw - 1;
+    if (last || (sw >= 5 && sw % 2 == 1))
+      ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)last);
+    else
+      ADS_LAUNCH(k_eig_orth, dim3(nsub), dim3(EIG_T), 0, st, a);
     if (sw % 4 == 3 || sw == maxsw - 1) {
       download(hdone, a.done, nsub, st);
       bool all = true;
@@ -945,6 +1024,11 @@ void eigensolve(Ctx& c) {
   a.msel = c.mem.alloc<int32_t>(nsub);
   a.Vsel = c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
   a.lam = c.mem.alloc<double>((size_t)nsub * 2 * PMAX);
+  a.rres = c.mem.alloc<double>(nsub);
+  a.rbest = c.mem.alloc<double>(nsub);
+  a.stall = c.mem.alloc<int32_t>(nsub);
+  ADS_HIP(hipMemsetAsync(a.rbest, 0, nsub * 8, st));
+  ADS_HIP(hipMemsetAsync(a.stall, 0, nsub * 4, st));
   a.err = c.mem.alloc<int32_t>(1);
   a.p = p;
   a.nev = nev;
@@ -970,6 +1054,7 @@ void eigensolve(Ctx& c) {
   if (herr[0] & 2) fail(ADS_ERR_EIG_NOCONV, "loss of orthogonality in the eigensolver block");
   download(hm, a.msel, nsub, st);
   download(c.h_sweeps, a.sweeps, nsub, st);
+  download(c.h_eig_res, a.rres, nsub, st);
   download(hdone, a.done, nsub, st);
   c.eig_sweeps_max = 0;
   c.eig_unconverged = 0;
