@@ -11,12 +11,13 @@
 //
 // Block subspace iteration with Rayleigh-Ritz, all subdomains batched:
 //   k_eig_op   (grid: subdomain x column chunk)  Y = T X   (tile solves)
-//   k_eig_rr   (grid: subdomain)  H = X^T Y, complex Schur form of H in LDS
-//              (Householder Hessenberg + shifted QR), eigenvalues ordered by
-//              |lambda|, the cut of eq. 6 with the cluster rule, reordering of
-//              the Schur form so the selected eigenvalues lead, a real
-//              orthonormal basis V of the selected invariant subspace, the
-//              residual ||(Y - X H) V||_F, and X <- orth(Y) (Cholesky QR, twice)
+//   k_eig_step (grid: subdomain)  X <- orth(Y) (Cholesky QR, twice) or, on the
+//              sweeps a per-subdomain schedule selects, first the Rayleigh-Ritz
+//              step: H = X^T Y, complex Schur form of H in LDS (Householder
+//              Hessenberg + shifted QR), eigenvalues ordered by |lambda|, the
+//              cut of eq. 6 with the cluster rule, reordering of the Schur form
+//              so the selected eigenvalues lead, a real orthonormal basis V of
+//              the selected invariant subspace and the residual ||(Y - X H) V||_F
 //   k_eig_finish  W_i = orth([1 | (X V) restricted to Omega_Ii])
 // Converged subdomains skip further sweeps.
 #include <algorithm>
@@ -29,6 +30,7 @@ namespace ads {
 
 static constexpr int EIG_T = 1024;
 static constexpr int PMAX = 32;
+static constexpr int EIG_PC = 4;  // columns per workgroup of the operator kernel
 static constexpr double CLUSTER_RTOL = 1e-6;
 
 #define WAVE_SYNC()                                        \
@@ -371,64 +373,158 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
 // block helpers: Gram matrices over rows, Cholesky QR
 // ---------------------------------------------------------------------------
 // Row passes over an n x p block stage CR rows at a time in LDS, with
-// CR * p <= GBUF: 4096 entries per buffer, so every thread issues several
-// independent loads per round trip.
+// CR * p <= GBUF: 4096 entries per buffer, GNPT per thread.  The next chunk is
+// loaded into registers while the current one is processed.
 static constexpr int GBUF = 4096;
+static constexpr int GNPT = GBUF / EIG_T;
 __device__ __forceinline__ int chunk_rows(int p) { return GBUF / p; }
 
-// H[a*p+b] = sum_r U[r,a] V[r,b] and, if G != nullptr, G[a*p+b] = sum_r V[r,a] V[r,b]
-// over r < n.  TPE threads share an entry (partial sums joined by shuffles).
-__device__ void gram2(const double* U, const double* V, int64_t ld, int n, int p, double* H,
-                      double* G, double* bufU, double* bufV) {
-  const int t = threadIdx.x, T = blockDim.x;
+// body(r0, rows, LDB) runs once per chunk with rows [r0, r0 + rows) of U (and
+// V if TWO) staged column-major in bufU (bufV), leading dimension LDB
+template <bool TWO, class Body>
+__device__ __forceinline__ void chunk_pass(const double* U, const double* V, int64_t ld, int n,
+                                           int p, double* bufU, double* bufV, Body&& body) {
+  const int t = threadIdx.x;
   const int CR = chunk_rows(p), LDB = CR + 1;
-  int tpe = T / (p * p);
-  tpe = tpe >= 4 ? 4 : (tpe >= 2 ? 2 : 1);
-  const int ent = t / tpe, sub = t % tpe;
-  const bool own = ent < p * p;
-  const int a = ent / p, b = ent % p;
-  double accH = 0.0, accG = 0.0;
+  double ru[GNPT], rv[GNPT];
+  auto load = [&](int r0) {
+    const int rows = min(CR, n - r0);
+#pragma unroll
+    for (int k = 0; k < GNPT; ++k) {
+      const int e = t + k * EIG_T;
+      const int rr = e % CR, cc = e / CR;
+      const bool ok = cc < p && rr < rows;
+      const int64_t idx = ok ? (int64_t)r0 + rr + cc * ld : 0;  // clamped, branch-free
+      const double u = U[idx];
+      ru[k] = ok ? u : 0.0;
+      if (TWO) {
+        const double v = V[idx];
+        rv[k] = ok ? v : 0.0;
+      }
+    }
+  };
+  if (n > 0) load(0);
   for (int r0 = 0; r0 < n; r0 += CR) {
     const int rows = min(CR, n - r0);
     __syncthreads();
-    for (int e = t; e < CR * p; e += T) {
+#pragma unroll
+    for (int k = 0; k < GNPT; ++k) {
+      const int e = t + k * EIG_T;
       const int rr = e % CR, cc = e / CR;
-      bufU[rr + cc * LDB] = rr < rows ? U[r0 + rr + cc * ld] : 0.0;
-      bufV[rr + cc * LDB] = rr < rows ? V[r0 + rr + cc * ld] : 0.0;
-    }
-    __syncthreads();
-    if (own) {
-      for (int rr = sub; rr < rows; rr += tpe) {
-        const double vb = bufV[rr + b * LDB];
-        accH += bufU[rr + a * LDB] * vb;
-        if (G) accG += bufV[rr + a * LDB] * vb;
+      if (cc < p) {
+        bufU[rr + cc * LDB] = ru[k];
+        if (TWO) bufV[rr + cc * LDB] = rv[k];
       }
     }
-  }
-  if (tpe >= 2) {
-    accH += __shfl_xor(accH, 1, 64);
-    accG += __shfl_xor(accG, 1, 64);
-  }
-  if (tpe >= 4) {
-    accH += __shfl_xor(accH, 2, 64);
-    accG += __shfl_xor(accG, 2, 64);
-  }
-  __syncthreads();
-  if (own && sub == 0) {
-    H[ent] = accH;
-    if (G) G[ent] = accG;
+    __syncthreads();
+    if (r0 + CR < n) load(r0 + CR);
+    body(r0, rows, LDB);
   }
   __syncthreads();
 }
 
-__device__ void gram(const double* U, const double* V, int64_t ld, int n, int p, double* G,
-                     double* bufU, double* bufV) {
-  gram2(U, V, ld, n, p, G, nullptr, bufU, bufV);
+// thread -> Gram entry map: TPE threads share an entry (partial sums joined
+// by shuffles)
+struct GramMap {
+  int tpe, ent, sub, a, b;
+  bool own;
+  __device__ GramMap(int p) {
+    const int t = threadIdx.x;
+    tpe = EIG_T / (p * p);
+    tpe = tpe >= 4 ? 4 : (tpe >= 2 ? 2 : 1);
+    ent = t / tpe;
+    sub = t % tpe;
+    own = ent < p * p;
+    a = ent / p;
+    b = ent % p;
+  }
+  __device__ double join(double v) const {
+    if (tpe >= 2) v += __shfl_xor(v, 1, 64);
+    if (tpe >= 4) v += __shfl_xor(v, 2, 64);
+    return v;
+  }
+};
+
+// H[a*p+b] = sum_r U[r,a] V[r,b] and, if G != nullptr, G[a*p+b] = sum_r V[r,a] V[r,b]
+// over r < n
+__device__ __forceinline__ void gram2(const double* U, const double* V, int64_t ld, int n, int p, double* H,
+                      double* G, double* bufU, double* bufV) {
+  const GramMap gm(p);
+  double accH = 0.0, accG = 0.0;
+  chunk_pass<true>(U, V, ld, n, p, bufU, bufV, [&](int, int rows, int LDB) {
+    if (gm.own)
+#pragma unroll 4
+      for (int rr = gm.sub; rr < rows; rr += gm.tpe) {
+        const double vb = bufV[rr + gm.b * LDB];
+        accH += bufU[rr + gm.a * LDB] * vb;
+        if (G) accG += bufV[rr + gm.a * LDB] * vb;
+      }
+  });
+  accH = gm.join(accH);
+  accG = gm.join(accG);
+  if (gm.own && gm.sub == 0) {
+    H[gm.ent] = accH;
+    if (G) G[gm.ent] = accG;
+  }
+  __syncthreads();
+}
+
+// G = Y^T Y over rows < n
+__device__ __forceinline__ void gram(const double* Y, int64_t ld, int n, int p, double* G, double* bufU) {
+  const GramMap gm(p);
+  double acc = 0.0;
+  chunk_pass<false>(Y, nullptr, ld, n, p, bufU, nullptr, [&](int, int rows, int LDB) {
+    if (gm.own)
+#pragma unroll 4
+      for (int rr = gm.sub; rr < rows; rr += gm.tpe)
+        acc += bufU[rr + gm.a * LDB] * bufU[rr + gm.b * LDB];
+  });
+  acc = gm.join(acc);
+  if (gm.own && gm.sub == 0) G[gm.ent] = acc;
+  __syncthreads();
+}
+
+// Xout = Yin Rinv over rows r < n (zero on rows n..npad-1) with Rinv upper
+// triangular (row-major p x p); if G != nullptr also G = Xout^T Xout.  Xout
+// may alias Yin (each chunk is staged before it is overwritten).
+__device__ __forceinline__ void right_mul_upper(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
+                                const double* Rinv, double* G, double* bufU, double* bufV) {
+  const int t = threadIdx.x;
+  const int CR = chunk_rows(p);
+  const GramMap gm(p);
+  double acc = 0.0;
+  chunk_pass<false>(Yin, nullptr, ld, n, p, bufU, nullptr, [&](int r0, int rows, int LDB) {
+    for (int e = t; e < CR * p; e += EIG_T) {
+      const int rr = e % CR, a = e / CR;
+      if (rr >= rows) continue;
+      double v = 0.0;
+#pragma unroll 4
+      for (int b = 0; b <= a; ++b) v += bufU[rr + b * LDB] * Rinv[b * p + a];
+      Xout[r0 + rr + a * ld] = v;
+      if (G) bufV[rr + a * LDB] = v;
+    }
+    if (G) {
+      __syncthreads();
+      if (gm.own)
+#pragma unroll 4
+        for (int rr = gm.sub; rr < rows; rr += gm.tpe)
+          acc += bufV[rr + gm.a * LDB] * bufV[rr + gm.b * LDB];
+    }
+  });
+  for (int e = t; e < (npad - n) * p; e += EIG_T) {
+    const int rr = e % (npad - n), a = e / (npad - n);
+    Xout[n + rr + a * ld] = 0.0;
+  }
+  if (G) {
+    acc = gm.join(acc);
+    if (gm.own && gm.sub == 0) G[gm.ent] = acc;
+  }
+  __syncthreads();
 }
 
 // Cholesky of the p x p SPD matrix G in place (upper factor R, row-major,
 // R[a*p+b] for b >= a).  Wave 0 only.  Returns 0 if not positive definite.
-__device__ int chol_upper(double* G, int p) {
+__device__ __forceinline__ int chol_upper(double* G, int p) {
   const int lane = threadIdx.x;
   int ok = 1;
   for (int k = 0; k < p; ++k) {
@@ -453,7 +549,7 @@ __device__ int chol_upper(double* G, int p) {
 
 // Rinv = R^{-1} for the upper triangular R (row-major p x p); wave 0, lane j
 // solves column j
-__device__ void tri_inverse(const double* R, double* Rinv, int p) {
+__device__ __forceinline__ void tri_inverse(const double* R, double* Rinv, int p) {
   const int j = threadIdx.x;
   if (j < p) {
     for (int i = p - 1; i >= 0; --i) {
@@ -463,31 +559,6 @@ __device__ void tri_inverse(const double* R, double* Rinv, int p) {
     }
   }
   WAVE_SYNC();
-}
-
-// Xout[:, 0:p] = Yin[:, 0:p] Rinv over rows r < n (zero on rows n..npad-1);
-// Xout may alias Yin (each chunk is staged in LDS first)
-__device__ void right_mul_upper(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
-                                const double* Rinv, double* buf) {
-  const int t = threadIdx.x, T = blockDim.x;
-  const int CR = chunk_rows(p), LDB = CR + 1;
-  for (int r0 = 0; r0 < npad; r0 += CR) {
-    const int rows = min(CR, npad - r0);
-    __syncthreads();
-    for (int e = t; e < CR * p; e += T) {
-      const int rr = e % CR, cc = e / CR;
-      buf[rr + cc * LDB] = (rr < rows && r0 + rr < n) ? Yin[r0 + rr + cc * ld] : 0.0;
-    }
-    __syncthreads();
-    for (int e = t; e < CR * p; e += T) {
-      const int rr = e % CR, a = e / CR;
-      if (rr >= rows) continue;
-      double v = 0.0;
-      for (int b = 0; b <= a; ++b) v += buf[rr + b * LDB] * Rinv[b * p + a];
-      Xout[r0 + rr + a * ld] = v;
-    }
-  }
-  __syncthreads();
 }
 
 struct EigShared {
@@ -505,17 +576,18 @@ struct EigShared {
 };
 
 // Cholesky QR twice: X <- orth(Y) over rows < n (Y is overwritten); G0, if
-// given, already holds Y^T Y
-__device__ int cholqr2_g(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S,
+// given, already holds Y^T Y.  The first product by R^{-1} also forms the
+// Gram matrix of the second pass.
+__device__ __forceinline__ int cholqr2_g(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S,
                          const double* G0) {
+  if (G0) {
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) S.G[e] = G0[e];
+    __syncthreads();
+  } else {
+    gram(Y, ld, n, p, S.G, S.bufU);
+  }
   int ok = 1;
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 0 && G0) {
-      for (int e = threadIdx.x; e < p * p; e += blockDim.x) S.G[e] = G0[e];
-      __syncthreads();
-    } else {
-      gram(Y, Y, ld, n, p, S.G, S.bufU, S.bufV);
-    }
     if (threadIdx.x < 64) {
       int o = chol_upper(S.G, p);
       tri_inverse(S.G, S.Ri, p);
@@ -523,12 +595,16 @@ __device__ int cholqr2_g(double* Y, double* X, int64_t ld, int n, int npad, int 
     }
     __syncthreads();
     ok &= S.flag[0];
-    right_mul_upper(Y, pass == 0 ? Y : X, ld, n, npad, p, S.Ri, S.bufU);
+    __syncthreads();
+    if (pass == 0)
+      right_mul_upper(Y, Y, ld, n, npad, p, S.Ri, S.G, S.bufU, S.bufV);
+    else
+      right_mul_upper(Y, X, ld, n, npad, p, S.Ri, nullptr, S.bufU, S.bufV);
   }
   return ok;
 }
 
-__device__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S) {
+__device__ __forceinline__ int cholqr2(double* Y, double* X, int64_t ld, int n, int npad, int p, EigShared& S) {
   return cholqr2_g(Y, X, ld, n, npad, p, S, nullptr);
 }
 
@@ -563,6 +639,9 @@ struct EigArgs {
   double* rres;     // per subdomain relative residual of the last Rayleigh-Ritz step
   double* rbest;    // best relative residual so far (stagnation test)
   int32_t* stall;   // consecutive Rayleigh-Ritz steps without a gain on rbest
+  double* rlast;    // residual of the last Rayleigh-Ritz step
+  int32_t* swlast;  // its sweep
+  int32_t* next_rr; // sweep of the next Rayleigh-Ritz step
   int32_t* err;
   int p;
   int nev;
@@ -678,17 +757,42 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   }
 }
 
-// Y = T X for columns [j0, j0 + PC); FAST selects the prefetching tile solve
+// per-column block sums of PC partial values (wave shuffles, then the wave
+// partials in a fixed order); out[j] for j < pc
+template <int PC>
+__device__ __forceinline__ void block_sum_cols(double (&v)[PC], double (*red)[16], double* out,
+                                               int pc) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < PC; ++j) {
+    double x = v[j];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[j][wv] = x;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < pc) {
+    double x = 0.0;
+    for (int w = 0; w < nw; ++w) x += red[threadIdx.x][w];
+    out[threadIdx.x] = x;
+  }
+  __syncthreads();
+}
+
+// Y = T X for columns [j0, j0 + PC); FAST selects the prefetching tile solve.
+// T = Pi_1 Atilde^{-1} Pi B Pi on floating subdomains (Pi = I - l l^T, Pi_1 the
+// projection onto 1^perp), Atilde^{-1} B otherwise; B = D A_ii D.
 template <class FT, int PC, bool FAST>
 __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[16];
+  __shared__ double red[PC][16];
+  __shared__ double alpha[PC], beta[PC];
   const int i = blockIdx.x;
   if (a.done[i]) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
   if (pc <= 0) return;
+  const int t = threadIdx.x, T = blockDim.x;
   const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s;
   const int64_t ld = npad;
   const int64_t base = a.om_off[i];
@@ -697,44 +801,61 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   const bool floating = a.kdim[i] != 0;
   const double* l = a.ell + a.pad_off[i];
   const double* bl = a.bell + a.pad_off[i];
-  __shared__ double alpha[PC], beta[PC];
-  if (floating) {
-    for (int j = 0; j < pc; ++j) {
-      double d = 0.0;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) d += l[r] * X[r + j * ld];
-      d = adsd::block_sum(d, red);
-      if (threadIdx.x == 0) alpha[j] = d;
+  const uint8_t* oi = a.om_int + base;
+  const int64_t* lrow = a.lrow + base;
+  double acc[PC];
+  if (floating) {  // alpha = l^T X
+#pragma unroll
+    for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+    for (int r = t; r < n; r += T) {
+      const double lr = l[r];
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) acc[j] += lr * X[r + j * ld];
     }
-    __syncthreads();
+    block_sum_cols<PC>(acc, red, alpha, pc);
   }
-  // F = B (Pi X) = B X - alpha B l
-  for (int64_t e = threadIdx.x; e < (int64_t)npad * pc; e += blockDim.x) {
-    const int r = (int)(e % npad), j = (int)(e / npad);
-    double v = 0.0;
-    if (r < n && a.om_int[base + r]) {
-      for (int64_t q = a.lrow[base + r]; q < a.lrow[base + r + 1]; ++q) {
+  // F = B (Pi X) = B X - alpha B l, row-parallel over all PC columns;
+  // beta = l^T F on the way
+#pragma unroll
+  for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+  for (int r = t; r < npad; r += T) {
+    double v[PC];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) v[j] = 0.0;
+    if (r < n && oi[r]) {
+      const int64_t q1 = lrow[r + 1];
+      for (int64_t q = lrow[r]; q < q1; ++q) {
         const int c = a.lcol[q];
-        if (a.om_int[base + c]) v += a.lval[q] * X[c + j * ld];
+        if (!oi[c]) continue;
+        const double av = a.lval[q];
+#pragma unroll
+        for (int j = 0; j < PC; ++j)
+          if (j < pc) v[j] += av * X[c + j * ld];
       }
-      if (floating) v -= alpha[j] * bl[r];
+      if (floating) {
+        const double br = bl[r], lr = l[r];
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+          v[j] -= alpha[j < pc ? j : 0] * br;
+          acc[j] += lr * v[j];
+        }
+      }
     }
-    Y[r + j * ld] = v;
+#pragma unroll
+    for (int j = 0; j < PC; ++j)
+      if (j < pc) Y[r + j * ld] = v[j];
+  }
+  if (floating) {  // F <- Pi F
+    block_sum_cols<PC>(acc, red, beta, pc);
+    for (int r = t; r < n; r += T) {
+      const double lr = l[r];
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) Y[r + j * ld] -= beta[j] * lr;
+    }
   }
   __syncthreads();
-  if (floating) {  // F <- Pi F
-    for (int j = 0; j < pc; ++j) {
-      double d = 0.0;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) d += l[r] * Y[r + j * ld];
-      d = adsd::block_sum(d, red);
-      if (threadIdx.x == 0) beta[j] = d;
-    }
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < (int64_t)n * pc; e += blockDim.x) {
-      const int r = (int)(e % n), j = (int)(e / n);
-      Y[r + j * ld] -= beta[j] * l[r];
-    }
-    __syncthreads();
-  }
   if constexpr (FAST) {
     constexpr int D = 2;
     double* dummy = a.dummy + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
@@ -746,12 +867,19 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
                                       Y, ld, pc, lds);
   }
   if (floating) {  // projection onto 1^perp
-    for (int j = 0; j < pc; ++j) {
-      double sm = 0.0;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) sm += Y[r + j * ld];
-      sm = adsd::block_sum(sm, red) / n;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) Y[r + j * ld] -= sm;
-      __syncthreads();
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+    for (int r = t; r < n; r += T) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) acc[j] += Y[r + j * ld];
+    }
+    block_sum_cols<PC>(acc, red, alpha, pc);
+    for (int r = t; r < n; r += T) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) Y[r + j * ld] -= alpha[j] / n;
     }
   }
 }
@@ -769,7 +897,11 @@ __global__ void __launch_bounds__(EIG_T) k_eig_orth0(EigArgs a) {
   if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
 }
 
-__global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
+// One sweep's second half for subdomain i: X <- orth(Y) or, on the sweeps
+// its schedule selects (and on the final sweep), the Rayleigh-Ritz step with
+// the convergence test first.  The next Rayleigh-Ritz sweep is predicted from
+// the residual decay observed between the last two (at most 8 sweeps ahead).
+__global__ void __launch_bounds__(EIG_T) k_eig_step(EigArgs a, int sw, int final_sweep) {
   __shared__ EigShared S;
   const int i = blockIdx.x;
   if (a.done[i]) return;
@@ -777,6 +909,11 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
   const int64_t ld = npad;
   double* X = a.X + a.pad_off[i] * p;
   double* Y = a.Y + a.pad_off[i] * p;
+  if (!final_sweep && sw < a.next_rr[i]) {
+    const int ok = cholqr2(Y, X, ld, n, npad, p, S);
+    if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
+    return;
+  }
   const int count = a.nev - a.kdim[i];
   // H = X^T Y and G = Y^T Y (the first Cholesky QR Gram) in one pass
   gram2(X, Y, ld, n, p, S.H, S.Gy, S.bufU, S.bufV);
@@ -806,17 +943,9 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
   __syncthreads();
   double rn = 0.0;
   {
-    const int CR = chunk_rows(p), LDB = CR + 1;
-    for (int r0 = 0; r0 < n; r0 += CR) {
-      const int rows = min(CR, n - r0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < CR * p; e += blockDim.x) {
-        const int rr = e % CR, cc = e / CR;
-        S.bufU[rr + cc * LDB] = rr < rows ? X[r0 + rr + cc * ld] : 0.0;
-        S.bufV[rr + cc * LDB] = rr < rows ? Y[r0 + rr + cc * ld] : 0.0;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < CR * m; e += blockDim.x) {
+    const int CR = chunk_rows(p);
+    chunk_pass<true>(X, Y, ld, n, p, S.bufU, S.bufV, [&](int, int rows, int LDB) {
+      for (int e = threadIdx.x; e < CR * m; e += EIG_T) {
         const int rr = e % CR, c = e / CR;
         if (rr >= rows) continue;
         double v = 0.0;
@@ -824,7 +953,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
           v += S.bufV[rr + k * LDB] * S.se.V[c * p + k] - S.bufU[rr + k * LDB] * S.HV[c * p + k];
         rn += v * v;
       }
-    }
+    });
   }
   rn = sqrt(adsd::block_sum(rn, S.red));
   double lmin = 1e300;
@@ -846,6 +975,20 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
     if (gain) a.rbest[i] = rel;
     a.stall[i] = stall;
     if (conv) a.done[i] = ok_tol ? 1 : 2;
+    // schedule: sweeps still needed at the observed per-sweep decay rate
+    int next = 2;
+    const double rl = a.rlast[i];
+    const int dsw = sw - a.swlast[i];
+    if (rl > 0.0 && rel > 0.0 && dsw > 0) {
+      const double rate = pow(rel / rl, 1.0 / dsw);
+      if (rate < 0.97) {
+        const double need = log(a.tol / rel) / log(rate);
+        next = need < 1.0 ? 1 : (need > 8.0 ? 8 : (int)ceil(need));
+      }
+    }
+    a.next_rr[i] = sw + next;
+    a.rlast[i] = rel;
+    a.swlast[i] = sw;
   }
   if (conv) {
     double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
@@ -859,18 +1002,6 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a, int final_sweep) {
   }
   __syncthreads();
   int ok = cholqr2_g(Y, X, ld, n, npad, p, S, S.Gy);
-  if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
-}
-
-// orthonormalisation only (sweeps without a Rayleigh-Ritz step)
-__global__ void __launch_bounds__(EIG_T) k_eig_orth(EigArgs a) {
-  __shared__ EigShared S;
-  const int i = blockIdx.x;
-  if (a.done[i]) return;
-  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
-  double* X = a.X + a.pad_off[i] * p;
-  double* Y = a.Y + a.pad_off[i] * p;
-  int ok = cholqr2(Y, X, npad, n, npad, p, S);
   if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
 }
 
@@ -927,17 +1058,8 @@ __global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* 
   }
   __syncthreads();
   // orthonormalise the nint x cols block (Cholesky QR twice, in place)
-  for (int pass = 0; pass < 2; ++pass) {
-    gram(Z, Z, ld, nint, cols, S.G, S.bufU, S.bufV);
-    if (threadIdx.x < 64) {
-      int o = chol_upper(S.G, cols);
-      tri_inverse(S.G, S.Ri, cols);
-      if (threadIdx.x == 0) S.flag[0] = o;
-    }
-    __syncthreads();
-    if (!S.flag[0] && threadIdx.x == 0) atomicOr(a.err, 8);
-    right_mul_upper(Z, Z, ld, nint, nint, cols, S.Ri, S.bufU);
-  }
+  const int okz = cholqr2(Z, Z, ld, nint, nint, cols, S);
+  if (!okz && threadIdx.x == 0) atomicOr(a.err, 8);
   double* Wi = W + W_off[i];
   for (int64_t e = threadIdx.x; e < (int64_t)nint * cols; e += blockDim.x) {
     const int r = (int)(e / cols), c = (int)(e % cols);
@@ -955,7 +1077,7 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
   ADS_LAUNCH((k_eig_init<FT>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
   ADS_LAUNCH(k_eig_orth0, dim3(nsub), dim3(EIG_T), 0, st, a);
-  constexpr int PC = 8;
+  constexpr int PC = EIG_PC;
   const bool fast = c.solve_fast;
   size_t op_lds = fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
                        : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
@@ -969,13 +1091,7 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     else
       ADS_LAUNCH((k_eig_op<FT, PC, false>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
                  fac, a);
-    // Rayleigh-Ritz (and the convergence test) on every other sweep after a
-    // short warm-up; the other sweeps only re-orthonormalise
-    const bool last = sw == maxsw - 1;
-    if (last || (sw >= 5 && sw % 2 == 1))
-      ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)last);
-    else
-      ADS_LAUNCH(k_eig_orth, dim3(nsub), dim3(EIG_T), 0, st, a);
+    ADS_LAUNCH(k_eig_step, dim3(nsub), dim3(EIG_T), 0, st, a, sw, (int)(sw == maxsw - 1));
     if (sw % 4 == 3 || sw == maxsw - 1) {
       download(hdone, a.done, nsub, st);
       bool all = true;
@@ -1014,7 +1130,7 @@ void eigensolve(Ctx& c) {
   a.pad_off = c.pad_off;
   a.cpl_col = c.cpl_col;
   a.cpl_val = c.cpl_val;
-  a.dummy = c.mem.alloc<double>((size_t)nsub * ((p + 7) / 8) * 1024);
+  a.dummy = c.mem.alloc<double>((size_t)nsub * ((p + EIG_PC - 1) / EIG_PC) * 1024);
   a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
   a.Y = c.mem.alloc<double>((size_t)c.npad_total * p);
   a.ell = c.mem.alloc<double>(c.npad_total);
@@ -1028,6 +1144,12 @@ void eigensolve(Ctx& c) {
   a.rbest = c.mem.alloc<double>(nsub);
   a.stall = c.mem.alloc<int32_t>(nsub);
   ADS_HIP(hipMemsetAsync(a.rbest, 0, nsub * 8, st));
+  a.rlast = c.mem.alloc<double>(nsub);
+  a.swlast = c.mem.alloc<int32_t>(nsub);
+  ADS_HIP(hipMemsetAsync(a.rlast, 0, nsub * 8, st));
+  ADS_HIP(hipMemsetAsync(a.swlast, 0, nsub * 4, st));
+  const std::vector<int32_t> first_rr(nsub, 3);  // first Rayleigh-Ritz step after 4 sweeps
+  a.next_rr = upload(c.mem, first_rr.data(), nsub, st);
   ADS_HIP(hipMemsetAsync(a.stall, 0, nsub * 4, st));
   a.err = c.mem.alloc<int32_t>(1);
   a.p = p;
