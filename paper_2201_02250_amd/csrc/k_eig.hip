@@ -11,13 +11,14 @@
 //
 // Block subspace iteration with Rayleigh-Ritz, all subdomains batched:
 //   k_eig_op   (grid: subdomain x column chunk)  Y = T X   (tile solves)
-//   k_eig_step (grid: subdomain)  X <- orth(Y) (Cholesky QR, twice) or, on the
-//              sweeps a per-subdomain schedule selects, first the Rayleigh-Ritz
-//              step: H = X^T Y, complex Schur form of H in LDS (Householder
-//              Hessenberg + shifted QR), eigenvalues ordered by |lambda|, the
-//              cut of eq. 6 with the cluster rule, reordering of the Schur form
-//              so the selected eigenvalues lead, a real orthonormal basis V of
-//              the selected invariant subspace and the residual ||(Y - X H) V||_F
+//   X <- orth(Y) by Cholesky QR twice over row blocks (k_eig_gram, k_eig_orth)
+//   on the sweeps the schedule selects, first the Rayleigh-Ritz step:
+//     k_eig_rr (grid: subdomain) H = X^T Y, complex Schur form of H in LDS
+//              (Householder Hessenberg + shifted QR), eigenvalues ordered by
+//              |lambda|, the cut of eq. 6 with the cluster rule, reordering of
+//              the Schur form so the selected eigenvalues lead, a real
+//              orthonormal basis V of the selected invariant subspace;
+//     k_eig_resid / k_eig_decide: ||(Y - X H) V||_F and the convergence test
 //   k_eig_finish  W_i = orth([1 | (X V) restricted to Omega_Ii])
 // Converged subdomains skip further sweeps.
 #include <algorithm>
@@ -377,22 +378,33 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
 // loaded into registers while the current one is processed.
 static constexpr int GBUF = 4096;
 static constexpr int GNPT = GBUF / EIG_T;
-__device__ __forceinline__ int chunk_rows(int p) { return GBUF / p; }
 
-// body(r0, rows, LDB) runs once per chunk with rows [r0, r0 + rows) of U (and
-// V if TWO) staged column-major in bufU (bufV), leading dimension LDB
+// Chunk geometry: CR rows (a power of two, CR * p <= GBUF); staged entry
+// e = t + k * EIG_T of a chunk is row e & (CR - 1), column e >> lcr.
+struct ChunkMap {
+  int CR, lcr, LDB;
+  __device__ ChunkMap(int p) {
+    lcr = 31 - __clz(GBUF / p);
+    CR = 1 << lcr;
+    LDB = CR + 1;
+  }
+  __device__ int rr(int e) const { return e & (CR - 1); }
+  __device__ int cc(int e) const { return e >> lcr; }
+};
+
+// body(r0, rows) runs once per chunk with rows [r0, r0 + rows) of U (and V if
+// TWO) staged column-major in bufU (bufV), leading dimension cm.LDB
 template <bool TWO, class Body>
-__device__ __forceinline__ void chunk_pass(const double* U, const double* V, int64_t ld, int n,
-                                           int p, double* bufU, double* bufV, Body&& body) {
-  const int t = threadIdx.x;
-  const int CR = chunk_rows(p), LDB = CR + 1;
+__device__ __forceinline__ void chunk_pass(const ChunkMap& cm, const double* U, const double* V,
+                                           int64_t ld, int n, int p, double* bufU, double* bufV,
+                                           Body&& body) {
   double ru[GNPT], rv[GNPT];
+  const int t = threadIdx.x;
   auto load = [&](int r0) {
-    const int rows = min(CR, n - r0);
+    const int rows = min(cm.CR, n - r0);
 #pragma unroll
     for (int k = 0; k < GNPT; ++k) {
-      const int e = t + k * EIG_T;
-      const int rr = e % CR, cc = e / CR;
+      const int e = t + k * EIG_T, rr = cm.rr(e), cc = cm.cc(e);
       const bool ok = cc < p && rr < rows;
       const int64_t idx = ok ? (int64_t)r0 + rr + cc * ld : 0;  // clamped, branch-free
       const double u = U[idx];
@@ -404,21 +416,20 @@ __device__ __forceinline__ void chunk_pass(const double* U, const double* V, int
     }
   };
   if (n > 0) load(0);
-  for (int r0 = 0; r0 < n; r0 += CR) {
-    const int rows = min(CR, n - r0);
+  for (int r0 = 0; r0 < n; r0 += cm.CR) {
+    const int rows = min(cm.CR, n - r0);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < GNPT; ++k) {
-      const int e = t + k * EIG_T;
-      const int rr = e % CR, cc = e / CR;
+      const int e = t + k * EIG_T, rr = cm.rr(e), cc = cm.cc(e);
       if (cc < p) {
-        bufU[rr + cc * LDB] = ru[k];
-        if (TWO) bufV[rr + cc * LDB] = rv[k];
+        bufU[rr + cc * cm.LDB] = ru[k];
+        if (TWO) bufV[rr + cc * cm.LDB] = rv[k];
       }
     }
     __syncthreads();
-    if (r0 + CR < n) load(r0 + CR);
-    body(r0, rows, LDB);
+    if (r0 + cm.CR < n) load(r0 + cm.CR);
+    body(r0, rows);
   }
   __syncthreads();
 }
@@ -450,8 +461,10 @@ struct GramMap {
 __device__ __forceinline__ void gram2(const double* U, const double* V, int64_t ld, int n, int p, double* H,
                       double* G, double* bufU, double* bufV) {
   const GramMap gm(p);
+  const ChunkMap cm(p);
+  const int LDB = cm.LDB;
   double accH = 0.0, accG = 0.0;
-  chunk_pass<true>(U, V, ld, n, p, bufU, bufV, [&](int, int rows, int LDB) {
+  chunk_pass<true>(cm, U, V, ld, n, p, bufU, bufV, [&](int, int rows) {
     if (gm.own)
 #pragma unroll 4
       for (int rr = gm.sub; rr < rows; rr += gm.tpe) {
@@ -472,8 +485,10 @@ __device__ __forceinline__ void gram2(const double* U, const double* V, int64_t 
 // G = Y^T Y over rows < n
 __device__ __forceinline__ void gram(const double* Y, int64_t ld, int n, int p, double* G, double* bufU) {
   const GramMap gm(p);
+  const ChunkMap cm(p);
+  const int LDB = cm.LDB;
   double acc = 0.0;
-  chunk_pass<false>(Y, nullptr, ld, n, p, bufU, nullptr, [&](int, int rows, int LDB) {
+  chunk_pass<false>(cm, Y, nullptr, ld, n, p, bufU, nullptr, [&](int, int rows) {
     if (gm.own)
 #pragma unroll 4
       for (int rr = gm.sub; rr < rows; rr += gm.tpe)
@@ -490,13 +505,15 @@ __device__ __forceinline__ void gram(const double* Y, int64_t ld, int n, int p, 
 __device__ __forceinline__ void right_mul_upper(const double* Yin, double* Xout, int64_t ld, int n, int npad, int p,
                                 const double* Rinv, double* G, double* bufU, double* bufV) {
   const int t = threadIdx.x;
-  const int CR = chunk_rows(p);
   const GramMap gm(p);
+  const ChunkMap cm(p);
+  const int LDB = cm.LDB;
   double acc = 0.0;
-  chunk_pass<false>(Yin, nullptr, ld, n, p, bufU, nullptr, [&](int r0, int rows, int LDB) {
-    for (int e = t; e < CR * p; e += EIG_T) {
-      const int rr = e % CR, a = e / CR;
-      if (rr >= rows) continue;
+  chunk_pass<false>(cm, Yin, nullptr, ld, n, p, bufU, nullptr, [&](int r0, int rows) {
+#pragma unroll 1
+    for (int e = t; e < GBUF; e += EIG_T) {
+      const int rr = cm.rr(e), a = cm.cc(e);
+      if (a >= p || rr >= rows) continue;
       double v = 0.0;
 #pragma unroll 4
       for (int b = 0; b <= a; ++b) v += bufU[rr + b * LDB] * Rinv[b * p + a];
@@ -520,6 +537,55 @@ __device__ __forceinline__ void right_mul_upper(const double* Yin, double* Xout,
     if (gm.own && gm.sub == 0) G[gm.ent] = acc;
   }
   __syncthreads();
+}
+
+// Cholesky factor R (upper, R^T R = G) of the p x p SPD matrix G (row-major,
+// read only) and Rinv = R^{-1} (row-major, upper), by wave 0 with lane j
+// holding column j in registers; rows are exchanged by shuffles.  Returns 0
+// (on every lane) if G is not numerically positive definite.
+template <int PM>
+__device__ __forceinline__ int chol_inv_wave_t(const double* G, double* Rinv, int p) {
+  const int j = threadIdx.x;
+  double g[PM];
+#pragma unroll
+  for (int i = 0; i < PM; ++i) g[i] = (j < p && i < p) ? G[i * p + j] : 0.0;
+  int ok = 1;
+#pragma unroll
+  for (int k = 0; k < PM; ++k) {
+    if (k < p) {
+      double d = __shfl(g[k], k, 64);
+      if (!(d > 0.0)) {
+        ok = 0;
+        d = 1e-300;
+      }
+      const double rkk = sqrt(d);
+      g[k] = (j == k) ? rkk : (j > k ? g[k] / rkk : g[k]);  // row k of R
+#pragma unroll
+      for (int i = k + 1; i < PM; ++i) {
+        const double rki = __shfl(g[k], i, 64);
+        if (j >= i && i < p) g[i] -= rki * g[k];
+      }
+    }
+  }
+  // column j of R^{-1} by back substitution; x_i overwrites g[i] once row i
+  // of R has been used
+#pragma unroll
+  for (int i = PM - 1; i >= 0; --i) {
+    const double rii = __shfl(g[i], i, 64);
+    double sacc = 0.0;
+#pragma unroll
+    for (int k = i + 1; k < PM; ++k) {
+      const double rik = __shfl(g[i], k, 64);
+      if (k <= j && k < p) sacc += rik * g[k];
+    }
+    if (i < p) g[i] = (j == i) ? 1.0 / rii : (j > i ? -sacc / rii : 0.0);
+  }
+  if (j < p)
+#pragma unroll
+    for (int i = 0; i < PM; ++i)
+      if (i < p) Rinv[i * p + j] = g[i];
+  WAVE_SYNC();
+  return ok;
 }
 
 // Cholesky of the p x p SPD matrix G in place (upper factor R, row-major,
@@ -561,17 +627,21 @@ __device__ __forceinline__ void tri_inverse(const double* R, double* Rinv, int p
   WAVE_SYNC();
 }
 
+// R^T R = G and Rinv = R^{-1}: registers for p <= 16, else in LDS (G is
+// overwritten then).  Wave 0 only.
+__device__ __forceinline__ int chol_inv_wave(double* G, double* Rinv, int p) {
+  if (p <= 16) return chol_inv_wave_t<16>(G, Rinv, p);
+  const int ok = chol_upper(G, p);
+  tri_inverse(G, Rinv, p);
+  return ok;
+}
+
 struct EigShared {
-  SmallEigLds se;
-  double H[PMAX * PMAX];
   double G[PMAX * PMAX];
-  double Gy[PMAX * PMAX];
   double Ri[PMAX * PMAX];
-  double HV[PMAX * PMAX];
   double bufU[GBUF + PMAX];
   double bufV[GBUF + PMAX];
   double red[16];
-  double lam_re[PMAX], lam_im[PMAX];
   int flag[4];
 };
 
@@ -589,8 +659,7 @@ __device__ __forceinline__ int cholqr2_g(double* Y, double* X, int64_t ld, int n
   int ok = 1;
   for (int pass = 0; pass < 2; ++pass) {
     if (threadIdx.x < 64) {
-      int o = chol_upper(S.G, p);
-      tri_inverse(S.G, S.Ri, p);
+      const int o = chol_inv_wave(S.G, S.Ri, p);
       if (threadIdx.x == 0) S.flag[0] = o;
     }
     __syncthreads();
@@ -642,6 +711,15 @@ struct EigArgs {
   double* rlast;    // residual of the last Rayleigh-Ritz step
   int32_t* swlast;  // its sweep
   int32_t* next_rr; // sweep of the next Rayleigh-Ritz step
+  double* HVs;      // per subdomain H V (p x m)
+  const int32_t* blk_sub;   // row block -> subdomain
+  const int32_t* blk_r0;    // row block -> first row
+  const int32_t* sub_blk0;  // subdomain -> first row block (nsub + 1)
+  double* partA;    // per row block p x p partial products (PMAX^2 stride)
+  double* partB;
+  double* partH;
+  double* partR;    // per row block partial squared residual
+  int lrb;          // log2 of the row-block height
   int32_t* err;
   int p;
   int nev;
@@ -719,7 +797,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   const int i = blockIdx.x;
   const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
   const int64_t ld = npad;
-  double* X = a.X + a.pad_off[i] * p;
+  double* X = a.Y + a.pad_off[i] * p;  // random start block, orthonormalised into X
   const int64_t base = a.om_off[i];
   for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) {
     const int r = (int)(e % npad), j = (int)(e / npad);
@@ -884,125 +962,291 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   }
 }
 
-// initial orthonormalisation of X (Y used as scratch)
-__global__ void __launch_bounds__(EIG_T) k_eig_orth0(EigArgs a) {
-  __shared__ EigShared S;
-  const int i = blockIdx.x;
-  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
-  double* X = a.X + a.pad_off[i] * p;
-  double* Y = a.Y + a.pad_off[i] * p;
-  for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) Y[e] = X[e];
-  __syncthreads();
-  int ok = cholqr2(Y, X, npad, n, npad, p, S);  // Y is scratch
-  if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
+// ---------------------------------------------------------------------------
+// Row-block kernels of a sweep: every subdomain's rows are cut into blocks of
+// RB rows (RB a power of two, RB * pq <= RBE, pq = p rounded up to 4), one
+// workgroup per block, the block staged whole in LDS.  Partial p x p products
+// per block are summed by their consumers in block order (deterministic).
+//   orthonormalisation (Cholesky QR twice):  k_eig_gram -> k_eig_orth(0) -> k_eig_orth(1)
+//   Rayleigh-Ritz sweeps: k_eig_gram(rr) -> k_eig_rr -> k_eig_resid -> k_eig_decide,
+//                         then the orthonormalisation of the unconverged ones
+// ---------------------------------------------------------------------------
+static constexpr int RBE = 8192;
+static constexpr int RB_NPT = RBE / EIG_T;
+
+// log2 of the row-block height for a block of width p
+__host__ __device__ inline int rb_log2(int p) {
+  const int pq = (p + 3) & ~3;
+  int l = 0;
+  while ((2 << l) * pq <= RBE) ++l;
+  return l;
 }
 
-// One sweep's second half for subdomain i: X <- orth(Y) or, on the sweeps
-// its schedule selects (and on the final sweep), the Rayleigh-Ritz step with
-// the convergence test first.  The next Rayleigh-Ritz sweep is predicted from
-// the residual decay observed between the last two (at most 8 sweeps ahead).
-__global__ void __launch_bounds__(EIG_T) k_eig_step(EigArgs a, int sw, int final_sweep) {
-  __shared__ EigShared S;
+// rows [r0, r0 + rows) of the column-major block M (leading dimension ld, p
+// columns) into S[r + c * RB] for c < pq, zero outside; loads issued first
+__device__ __forceinline__ void stage_rows(const double* M, int64_t ld, int r0, int rows, int p,
+                                           int pq, int lrb, double* S) {
+  const int t = threadIdx.x, RB = 1 << lrb;
+  double v[RB_NPT];
+#pragma unroll
+  for (int k = 0; k < RB_NPT; ++k) {
+    const int e = t + k * EIG_T, r = e & (RB - 1), c = e >> lrb;
+    const bool ok = c < p && r < rows;
+    const double x = M[ok ? (int64_t)r0 + r + c * ld : 0];
+    v[k] = ok ? x : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < RB_NPT; ++k) {
+    const int e = t + k * EIG_T;
+    if ((e >> lrb) < pq) S[e] = v[k];
+  }
+}
+
+// out[a * p + b] = sum_{r < rows} U[r + a RB] V[r + b RB] for a, b < p.  Wave w
+// takes the 4 x 4 tiles w, w + 16, ...; its lanes split the rows; the lane
+// sums are joined by a butterfly (same order on every run).
+__device__ __forceinline__ void block_gram(const double* U, const double* V, int rows, int p,
+                                           int pq, int RB, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = pq >> 2;
+  for (int tile = wv; tile < q * q; tile += EIG_T / 64) {
+    const int ta = tile / q, tb = tile % q;
+    const double* Ua = U + 4 * ta * RB;
+    const double* Vb = V + 4 * tb * RB;
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int r = lane; r < rows; r += 64) {
+      double u[4], v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        u[x] = Ua[r + x * RB];
+        v[x] = Vb[r + x * RB];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x * 4 + y] += u[x] * v[y];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[k] += __shfl_xor(acc[k], o, 64);
+    if (lane < 16) {
+      const int x = lane >> 2, y = lane & 3;
+      const int ra = 4 * ta + x, cb = 4 * tb + y;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k == lane) v = acc[k];
+      if (ra < p && cb < p) out[ra * p + cb] = v;
+    }
+  }
+}
+
+// sum of the per-block partial p x p products of a subdomain (blocks
+// b0..b1-1): EIG_T / p^2 thread groups take every G-th block, then the group
+// sums are added in group order; tmp holds EIG_T doubles of LDS
+__device__ __forceinline__ void sum_parts(const double* part, int b0, int b1, int p, double* out,
+                                          double* tmp) {
+  const int t = threadIdx.x, pp = p * p;
+  const int G = EIG_T / pp;
+  const int e = t % pp, g = t / pp;
+  if (g < G) {
+    double sacc = 0.0;
+#pragma unroll 4
+    for (int bb = b0 + g; bb < b1; bb += G) sacc += part[(int64_t)bb * PMAX * PMAX + e];
+    tmp[g * pp + e] = sacc;
+  }
+  __syncthreads();
+  if (t < pp) {
+    double sacc = 0.0;
+    for (int k = 0; k < G; ++k) sacc += tmp[k * pp + t];
+    out[t] = sacc;
+  }
+  __syncthreads();
+}
+
+// partial Gram matrices of one row block: Y^T Y (and X^T Y for Rayleigh-Ritz)
+__global__ void __launch_bounds__(EIG_T) k_eig_gram(EigArgs a, int rr) {
+  extern __shared__ double rbuf[];
+  const int b = blockIdx.x, i = a.blk_sub[b];
+  if (a.done[i]) return;
+  const int p = a.p, pq = (p + 3) & ~3, lrb = a.lrb, RB = 1 << lrb;
+  const int r0 = a.blk_r0[b], rows = min(RB, a.ni[i] - r0);
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  double* Ys = rbuf;
+  double* Xs = rbuf + RB * pq;
+  stage_rows(a.Y + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Ys);
+  if (rr) stage_rows(a.X + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Xs);
+  __syncthreads();
+  block_gram(Ys, Ys, rows, p, pq, RB, a.partA + (int64_t)b * PMAX * PMAX);
+  if (rr) block_gram(Xs, Ys, rows, p, pq, RB, a.partH + (int64_t)b * PMAX * PMAX);
+}
+
+// one Cholesky QR pass on a row block: R^T R = sum of the partial Gram
+// matrices, then Y <- Y R^{-1} with the new block's partial Gram (pass 0), or
+// X <- Y R^{-1} (pass 1)
+__global__ void __launch_bounds__(EIG_T) k_eig_orth(EigArgs a, int pass) {
+  extern __shared__ double rbuf[];
+  __shared__ double Gs[PMAX * PMAX];
+  __shared__ double Ri[PMAX * PMAX];
+  __shared__ int okf;
+  const int b = blockIdx.x, i = a.blk_sub[b];
+  if (a.done[i]) return;
+  const int p = a.p, pq = (p + 3) & ~3, lrb = a.lrb, RB = 1 << lrb;
+  const int r0 = a.blk_r0[b], rows = min(RB, a.ni[i] - r0);
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  double* Y = a.Y + a.pad_off[i] * p;
+  double* Ys = rbuf;
+  double* Ws = rbuf + RB * pq;
+  stage_rows(Y, ld, r0, rows, p, pq, lrb, Ys);
+  sum_parts(pass == 0 ? a.partA : a.partB, a.sub_blk0[i], a.sub_blk0[i + 1], p, Gs, Ws);
+  if (threadIdx.x < 64) {
+    const int o = chol_inv_wave(Gs, Ri, p);
+    if (threadIdx.x == 0) okf = o;
+  }
+  __syncthreads();
+  if (!okf && threadIdx.x == 0) atomicOr(a.err, 2);
+  double* out = pass == 0 ? Y : a.X + a.pad_off[i] * p;
+#pragma unroll 1
+  for (int k = 0; k < RB_NPT; ++k) {
+    const int e = threadIdx.x + k * EIG_T, r = e & (RB - 1), c = e >> lrb;
+    if (c >= pq) continue;
+    double v = 0.0;
+    if (c < p && r < rows) {
+      for (int q = 0; q <= c; ++q) v += Ys[r + q * RB] * Ri[q * p + c];
+      out[r0 + r + c * ld] = v;
+    }
+    Ws[e] = v;
+  }
+  if (pass == 0) {
+    __syncthreads();
+    block_gram(Ws, Ws, rows, p, pq, RB, a.partB + (int64_t)b * PMAX * PMAX);
+  }
+}
+
+// Rayleigh-Ritz on H = X^T Y (one workgroup per subdomain): the selected
+// invariant subspace V, H V and the eigenvalues
+__global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a) {
+  __shared__ SmallEigLds se;
+  __shared__ double H[PMAX * PMAX];
+  __shared__ double tmp[EIG_T];
+  __shared__ double lam_re[PMAX], lam_im[PMAX];
+  __shared__ int flag[2];
   const int i = blockIdx.x;
   if (a.done[i]) return;
-  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
-  const int64_t ld = npad;
-  double* X = a.X + a.pad_off[i] * p;
-  double* Y = a.Y + a.pad_off[i] * p;
-  if (!final_sweep && sw < a.next_rr[i]) {
-    const int ok = cholqr2(Y, X, ld, n, npad, p, S);
-    if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
-    return;
-  }
+  const int p = a.p;
   const int count = a.nev - a.kdim[i];
-  // H = X^T Y and G = Y^T Y (the first Cholesky QR Gram) in one pass
-  gram2(X, Y, ld, n, p, S.H, S.Gy, S.bufU, S.bufV);
-  int m = 0;
+  sum_parts(a.partH, a.sub_blk0[i], a.sub_blk0[i + 1], p, H, tmp);
   if (threadIdx.x < 64) {
     int ok = 1;
     double gap = 1.0;
-    m = small_eig_select(p, S.H, count, a.tau, S.se, S.lam_re, S.lam_im, &ok, &gap);
+    const int m = small_eig_select(p, H, count, a.tau, se, lam_re, lam_im, &ok, &gap);
     if (threadIdx.x == 0) {
-      S.flag[1] = m;
-      S.flag[2] = ok;
+      flag[0] = m;
+      flag[1] = ok;
     }
   }
   __syncthreads();
-  m = S.flag[1];
-  if (!S.flag[2] && threadIdx.x == 0) atomicOr(a.err, 4);
-  // the selected cluster must leave at least one Ritz value outside it,
-  // otherwise the cluster may extend beyond the subspace
-  if (m + a.kdim[i] >= p && threadIdx.x == 0) atomicOr(a.err, 16);
-  // HV = H V (p x m), then residual ||Y V - X HV||_F
+  const int m = flag[0];
+  if (threadIdx.x == 0) {
+    if (!flag[1]) atomicOr(a.err, 4);
+    // the selected cluster must leave at least one Ritz value outside it,
+    // otherwise the cluster may extend beyond the subspace
+    if (m + a.kdim[i] >= p) atomicOr(a.err, 16);
+    a.msel[i] = m;
+  }
+  double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
+  double* HV = a.HVs + (int64_t)i * PMAX * PMAX;
   for (int e = threadIdx.x; e < p * m; e += blockDim.x) {
     const int r = e % p, c = e / p;
     double v = 0.0;
-    for (int k = 0; k < p; ++k) v += S.H[r * p + k] * S.se.V[c * p + k];
-    S.HV[c * p + r] = v;
+    for (int k = 0; k < p; ++k) v += H[r * p + k] * se.V[c * p + k];
+    HV[e] = v;
+    Vs[e] = se.V[e];
   }
+  double* lam = a.lam + (int64_t)i * 2 * PMAX;
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    lam[c] = lam_re[c];
+    lam[PMAX + c] = lam_im[c];
+  }
+}
+
+// partial ||Y V - X (H V)||_F^2 of one row block
+__global__ void __launch_bounds__(EIG_T) k_eig_resid(EigArgs a) {
+  extern __shared__ double rbuf[];
+  __shared__ double Vs[PMAX * PMAX], HV[PMAX * PMAX];
+  __shared__ double red[16];
+  const int b = blockIdx.x, i = a.blk_sub[b];
+  if (a.done[i]) return;
+  const int p = a.p, pq = (p + 3) & ~3, lrb = a.lrb, RB = 1 << lrb;
+  const int r0 = a.blk_r0[b], rows = min(RB, a.ni[i] - r0);
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  const int m = a.msel[i];
+  for (int e = threadIdx.x; e < p * m; e += blockDim.x) {
+    Vs[e] = a.Vsel[(int64_t)i * PMAX * PMAX + e];
+    HV[e] = a.HVs[(int64_t)i * PMAX * PMAX + e];
+  }
+  double* Ys = rbuf;
+  double* Xs = rbuf + RB * pq;
+  stage_rows(a.Y + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Ys);
+  stage_rows(a.X + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Xs);
   __syncthreads();
   double rn = 0.0;
-  {
-    const int CR = chunk_rows(p);
-    chunk_pass<true>(X, Y, ld, n, p, S.bufU, S.bufV, [&](int, int rows, int LDB) {
-      for (int e = threadIdx.x; e < CR * m; e += EIG_T) {
-        const int rr = e % CR, c = e / CR;
-        if (rr >= rows) continue;
-        double v = 0.0;
-        for (int k = 0; k < p; ++k)
-          v += S.bufV[rr + k * LDB] * S.se.V[c * p + k] - S.bufU[rr + k * LDB] * S.HV[c * p + k];
-        rn += v * v;
-      }
-    });
+#pragma unroll 1
+  for (int k = 0; k < RB_NPT; ++k) {
+    const int e = threadIdx.x + k * EIG_T, r = e & (RB - 1), c = e >> lrb;
+    if (c >= m || r >= rows) continue;
+    double v = 0.0;
+    for (int q = 0; q < p; ++q) v += Ys[r + q * RB] * Vs[c * p + q] - Xs[r + q * RB] * HV[c * p + q];
+    rn += v * v;
   }
-  rn = sqrt(adsd::block_sum(rn, S.red));
+  rn = adsd::block_sum(rn, red);
+  if (threadIdx.x == 0) a.partR[b] = rn;
+}
+
+// convergence test and schedule, one thread per subdomain.  Converged: the
+// relative residual ||Y V - X H V||_F / min |lambda| is below the tolerance,
+// or has stagnated within 100x of it (the rounding floor of the operator on
+// strongly non-normal subdomains: three Rayleigh-Ritz steps in a row without a
+// 5% gain on the best residual).  The next Rayleigh-Ritz sweep is predicted
+// from the residual decay since the last one (1 to 8 sweeps ahead).
+__global__ void k_eig_decide(EigArgs a, int nsub, int sw, int final_sweep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsub || a.done[i]) return;
+  const int m = a.msel[i];
+  double rn = 0.0;
+  for (int bb = a.sub_blk0[i]; bb < a.sub_blk0[i + 1]; ++bb) rn += a.partR[bb];
+  rn = sqrt(rn);
+  const double* lam = a.lam + (int64_t)i * 2 * PMAX;
   double lmin = 1e300;
-  for (int c = 0; c < m; ++c) lmin = fmin(lmin, hypot(S.lam_re[c], S.lam_im[c]));
-  // converged: residual below the tolerance, or stagnated within 100x of it
-  // (the rounding floor of the operator on strongly non-normal subdomains):
-  // three Rayleigh-Ritz steps in a row without a 5% gain on the best residual
+  for (int c = 0; c < m; ++c) lmin = fmin(lmin, hypot(lam[c], lam[PMAX + c]));
   const double rel = m ? rn / lmin : 0.0;
   const double best = a.rbest[i];
   const bool gain = !(best > 0.0) || rel < 0.95 * best;
   const int stall = (m && !gain) ? a.stall[i] + 1 : 0;
   const bool ok_tol = (m == 0) || (rel <= a.tol) || (rel <= 100.0 * a.tol && stall >= 3);
-  const bool conv = ok_tol || final_sweep;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a.sweeps[i] += 1;
-    a.msel[i] = m;
-    a.rres[i] = rel;
-    if (gain) a.rbest[i] = rel;
-    a.stall[i] = stall;
-    if (conv) a.done[i] = ok_tol ? 1 : 2;
-    // schedule: sweeps still needed at the observed per-sweep decay rate
-    int next = 2;
-    const double rl = a.rlast[i];
-    const int dsw = sw - a.swlast[i];
-    if (rl > 0.0 && rel > 0.0 && dsw > 0) {
-      const double rate = pow(rel / rl, 1.0 / dsw);
-      if (rate < 0.97) {
-        const double need = log(a.tol / rel) / log(rate);
-        next = need < 1.0 ? 1 : (need > 8.0 ? 8 : (int)ceil(need));
-      }
-    }
-    a.next_rr[i] = sw + next;
-    a.rlast[i] = rel;
-    a.swlast[i] = sw;
+  a.rres[i] = rel;
+  if (gain) a.rbest[i] = rel;
+  a.stall[i] = stall;
+  if (ok_tol || final_sweep) {
+    a.done[i] = ok_tol ? 1 : 2;
+    a.sweeps[i] = sw + 1;
   }
-  if (conv) {
-    double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
-    for (int e = threadIdx.x; e < p * m; e += blockDim.x) Vs[e] = S.se.V[e];
-    double* lam = a.lam + (int64_t)i * 2 * PMAX;
-    for (int c = threadIdx.x; c < m; c += blockDim.x) {
-      lam[c] = S.lam_re[c];
-      lam[PMAX + c] = S.lam_im[c];
+  int next = 2;
+  const double rl = a.rlast[i];
+  const int dsw = sw - a.swlast[i];
+  if (rl > 0.0 && rel > 0.0 && dsw > 0) {
+    const double rate = pow(rel / rl, 1.0 / dsw);
+    if (rate < 0.97) {
+      const double need = log(a.tol / rel) / log(rate);
+      next = need < 1.0 ? 1 : (need > 8.0 ? 8 : (int)ceil(need));
     }
-    return;
   }
-  __syncthreads();
-  int ok = cholqr2_g(Y, X, ld, n, npad, p, S, S.Gy);
-  if (!ok && threadIdx.x == 0) atomicOr(a.err, 2);
+  a.next_rr[i] = sw + next;
+  a.rlast[i] = rel;
+  a.swlast[i] = sw;
 }
 
 // W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
@@ -1075,15 +1319,24 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   double* scratch = c.mem.alloc<double>((size_t)nsub * 2 * 1024);
   size_t init_lds = (2 * smax <= 4096) ? 2 * smax * sizeof(double) : 0;
   if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
+  const int pq = (a.p + 3) & ~3;
+  const size_t rb_lds = (size_t)2 * (1 << a.lrb) * pq * sizeof(double);
+  const unsigned nblk = (unsigned)c.h_eig_nblk;
+  auto orth = [&]() {
+    ADS_LAUNCH(k_eig_gram, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 0);
+    ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 0);
+    ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
+  };
   ADS_LAUNCH((k_eig_init<FT>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
-  ADS_LAUNCH(k_eig_orth0, dim3(nsub), dim3(EIG_T), 0, st, a);
+  orth();
   constexpr int PC = EIG_PC;
   const bool fast = c.solve_fast;
   size_t op_lds = fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
                        : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
   const unsigned op_t = fast ? adsd::SOLVE_T : EIG_T;
   const int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
-  std::vector<int32_t> hdone;
+  std::vector<int32_t> hdone, hnext;
+  int next = 3;  // first Rayleigh-Ritz step after 4 sweeps
   for (int sw = 0; sw < maxsw; ++sw) {
     if (fast)
       ADS_LAUNCH((k_eig_op<FT, PC, true>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
@@ -1091,13 +1344,29 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     else
       ADS_LAUNCH((k_eig_op<FT, PC, false>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
                  fac, a);
-    ADS_LAUNCH(k_eig_step, dim3(nsub), dim3(EIG_T), 0, st, a, sw, (int)(sw == maxsw - 1));
-    if (sw % 4 == 3 || sw == maxsw - 1) {
-      download(hdone, a.done, nsub, st);
-      bool all = true;
-      for (int v : hdone) all &= (v != 0);
-      if (all) break;
+    const bool last = sw == maxsw - 1;
+    if (sw < next && !last) {
+      orth();
+      continue;
     }
+    ADS_LAUNCH(k_eig_gram, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
+    ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a);
+    ADS_LAUNCH(k_eig_resid, dim3(nblk), dim3(EIG_T), rb_lds, st, a);
+    ADS_LAUNCH(k_eig_decide, dim3((nsub + 63) / 64), dim3(64), 0, st, a, nsub, sw, (int)last);
+    download(hdone, a.done, nsub, st);
+    download(hnext, a.next_rr, nsub, st);
+    // next check when the slowest unconverged subdomain is predicted to
+    // converge (the others keep iterating meanwhile)
+    bool all = true;
+    next = sw + 1;
+    for (int i = 0; i < nsub; ++i)
+      if (hdone[i] == 0) {
+        all = false;
+        next = std::max(next, hnext[i]);
+      }
+    if (all) break;
+    ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 0);
+    ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
   }
   ADS_HIP(hipStreamSynchronize(st));
   c.mem.release(scratch);
@@ -1148,8 +1417,28 @@ void eigensolve(Ctx& c) {
   a.swlast = c.mem.alloc<int32_t>(nsub);
   ADS_HIP(hipMemsetAsync(a.rlast, 0, nsub * 8, st));
   ADS_HIP(hipMemsetAsync(a.swlast, 0, nsub * 4, st));
-  const std::vector<int32_t> first_rr(nsub, 3);  // first Rayleigh-Ritz step after 4 sweeps
-  a.next_rr = upload(c.mem, first_rr.data(), nsub, st);
+  a.next_rr = c.mem.alloc<int32_t>(nsub);
+  a.HVs = c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
+  // row blocks
+  a.lrb = rb_log2(p);
+  std::vector<int32_t> blk_sub, blk_r0, sub_blk0(nsub + 1, 0);
+  for (int i = 0; i < nsub; ++i) {
+    sub_blk0[i] = (int32_t)blk_sub.size();
+    for (int r0 = 0; r0 < c.h_ni[i]; r0 += 1 << a.lrb) {
+      blk_sub.push_back(i);
+      blk_r0.push_back(r0);
+    }
+  }
+  sub_blk0[nsub] = (int32_t)blk_sub.size();
+  c.h_eig_nblk = (int)blk_sub.size();
+  a.blk_sub = upload(c.mem, blk_sub.data(), blk_sub.size(), st);
+  a.blk_r0 = upload(c.mem, blk_r0.data(), blk_r0.size(), st);
+  a.sub_blk0 = upload(c.mem, sub_blk0.data(), nsub + 1, st);
+  a.partA = c.mem.alloc<double>((size_t)c.h_eig_nblk * PMAX * PMAX);
+  a.partB = c.mem.alloc<double>((size_t)c.h_eig_nblk * PMAX * PMAX);
+  a.partH = c.mem.alloc<double>((size_t)c.h_eig_nblk * PMAX * PMAX);
+  a.partR = c.mem.alloc<double>(c.h_eig_nblk);
+  ADS_HIP(hipMemsetAsync(a.X, 0, (size_t)c.npad_total * p * 8, st));
   ADS_HIP(hipMemsetAsync(a.stall, 0, nsub * 4, st));
   a.err = c.mem.alloc<int32_t>(1);
   a.p = p;
@@ -1219,8 +1508,10 @@ void eigensolve(Ctx& c) {
   ADS_LAUNCH(k_eig_finish, dim3(nsub), dim3(EIG_T), 0, st, a, c.W_off, c.W);
   download(herr, a.err, 1, st);
   if (herr[0] & 8) fail(ADS_ERR_EIG_NOCONV, "coarse basis of a subdomain is rank deficient");
-  c.mem.release(a.X);
-  c.mem.release(a.Y);
+  ADS_HIP(hipStreamSynchronize(st));
+  for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.partA, (void*)a.partB, (void*)a.partH,
+                  (void*)a.partR, (void*)a.HVs})
+    c.mem.release(q);
 
 }
 
