@@ -3,12 +3,67 @@
 // interface; errors become status codes plus a thread-local message.
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 
 #include "ads_internal.h"
 
 namespace ads {
+
+namespace pool {
+namespace {
+std::mutex g_mu;
+std::map<std::pair<int, size_t>, std::vector<void*>> g_free;
+}  // namespace
+
+size_t size_class(size_t bytes) {
+  // 256 B granularity up to 64 KiB, then an eighth of the power of two below
+  // (at most 12.5 % rounding)
+  if (bytes <= 65536) return (bytes + 255) & ~size_t(255);
+  size_t p2 = 1;
+  while (p2 * 2 <= bytes) p2 *= 2;
+  const size_t step = p2 / 8;
+  return (bytes + step - 1) / step * step;
+}
+
+void* get(size_t cls, int* devp) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  *devp = dev;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_free.find({dev, cls});
+    if (it != g_free.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, cls) == hipSuccess) return p;
+  (void)hipGetLastError();
+  // out of memory: hand every cached block of this device back and retry
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : g_free)
+      if (kv.first.first == dev) {
+        for (void* q : kv.second) (void)hipFree(q);
+        kv.second.clear();
+      }
+  }
+  if (hipMalloc(&p, cls) == hipSuccess) return p;
+  (void)hipGetLastError();
+  return nullptr;
+}
+
+void put(void* p, size_t cls, int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_free[{dev, cls}].push_back(p);
+}
+}  // namespace pool
 
 static thread_local std::string g_last_error;
 
@@ -119,7 +174,7 @@ static void import_csr(Ctx& c, const ads_csr& A, int64_t r0, int64_t k0, int32_t
   const int64_t* rp = A.row_ptr;
   const int32_t* ci = A.col;
   const double* v = A.val;
-  Arena tmp;
+  Arena tmp(st);
   if (!A.on_device) {
     rp = upload(tmp, A.row_ptr, A.n + 1, st);
     ci = upload(tmp, A.col, A.nnz, st);
@@ -145,6 +200,7 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
   auto c = new Ctx();
   try {
     c->stream = st;
+    c->mem.stream = st;
     c->opt = *opts;
     c->prec = opts->precision;
     c->nsys = nsys;
@@ -422,7 +478,7 @@ int ads_partition_bfs(const ads_csr* A, int32_t nparts, const int32_t* seeds, in
         if (k && chk[k] == chk[k - 1]) fail(ADS_ERR_ARG, "seeds must be distinct");
       }
     }
-    Arena mem;
+    Arena mem(st);
     std::vector<int32_t> rp(h.view.n + 1);
     for (int64_t r = 0; r <= h.view.n; ++r) rp[r] = (int32_t)h.view.row_ptr[r];
     int32_t* d_rp = upload(mem, rp.data(), rp.size(), st);

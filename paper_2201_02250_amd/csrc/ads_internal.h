@@ -43,34 +43,65 @@ inline void check_launch(dim3 g, dim3 b, size_t lds, const char* name) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// Device memory owned by a context
+// Device memory
 // ---------------------------------------------------------------------------
+// Process-wide cache of device blocks, by device and size class: blocks come
+// back here instead of to hipFree (which synchronises the whole device and
+// costs tens of microseconds per call), and a later request of the same class
+// on the same device reuses them.  Cached blocks are returned to the driver
+// only when a hipMalloc fails.  Thread safe.
+namespace pool {
+size_t size_class(size_t bytes);
+// a block of cls bytes on the current device (returned in *dev), nullptr if
+// out of memory
+void* get(size_t cls, int* dev);
+// p (from get on device dev) must no longer be in use by any stream
+void put(void* p, size_t cls, int dev);
+}  // namespace pool
+
+// Device memory owned by one context or call.  Every block is used on
+// `stream` only; release() and the destructor wait for that stream before the
+// block goes back to the cache.
 struct Arena {
-  std::vector<void*> ptrs;
+  struct Block {
+    void* p;
+    size_t cls;
+    int dev;
+  };
+  std::vector<Block> blocks;
   size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  Arena() = default;
+  explicit Arena(hipStream_t s) : stream(s) {}
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
   template <class T>
   T* alloc(size_t count) {
     if (count == 0) count = 1;
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(ADS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
-    ptrs.push_back(p);
-    bytes += count * sizeof(T);
+    const size_t cls = pool::size_class(count * sizeof(T));
+    int dev = 0;
+    void* p = pool::get(cls, &dev);
+    if (!p) fail(ADS_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    blocks.push_back({p, cls, dev});
+    bytes += cls;
     return static_cast<T*>(p);
   }
   void release(void* p) {
-    for (auto& q : ptrs)
-      if (q == p) {
-        (void)hipFree(q);
-        q = nullptr;
+    for (auto& b : blocks)
+      if (b.p == p) {
+        (void)hipStreamSynchronize(stream);
+        pool::put(b.p, b.cls, b.dev);
+        bytes -= b.cls;
+        b.p = nullptr;
       }
   }
   ~Arena() {
-    for (void* p : ptrs)
-      if (p) (void)hipFree(p);
+    bool any = false;
+    for (const auto& b : blocks) any |= b.p != nullptr;
+    if (!any) return;
+    (void)hipStreamSynchronize(stream);
+    for (const auto& b : blocks)
+      if (b.p) pool::put(b.p, b.cls, b.dev);
   }
 };
 

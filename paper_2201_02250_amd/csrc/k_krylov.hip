@@ -295,7 +295,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   const bool flex = ko.flexible != 0;
   const int fixed = ko.fixed_iters;
   auto t0 = std::chrono::steady_clock::now();
-  Arena mem;
+  Arena mem(st);
   // instance table
   std::vector<int64_t> hrow0(Q), hrows(Q);
   std::vector<int32_t> hcol(Q);

@@ -361,7 +361,7 @@ __global__ void k_bfs_level(const int32_t* rowptr, const int32_t* col, const int
 
 void bfs_partition(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
                    const std::vector<int32_t>& seeds, std::vector<int32_t>& part, hipStream_t s) {
-  Arena mem;
+  Arena mem(s);
   int32_t *tptr, *tcol;
   transpose_pattern(mem, rowptr, col, n, nnz, &tptr, &tcol, s);
   int32_t* dist = mem.alloc<int32_t>(n);
