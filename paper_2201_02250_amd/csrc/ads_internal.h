@@ -128,7 +128,13 @@ struct Ctx {
   int32_t* tptr = nullptr;  // transpose pattern (graph of A^T)
   int32_t* tcol = nullptr;
   int32_t* part = nullptr;  // global subdomain id of each unknown
-  int32_t* ipos = nullptr;  // position of each unknown inside its own Omega_Ii
+  int32_t* ipos = nullptr;
+  // per-subdomain window [wlo, whi) of the global index range containing
+  // Omega_i; wpos[woff + v - wlo] = position of v in ascending Omega_i, or -1
+  int64_t* wlo = nullptr;
+  int64_t* whi = nullptr;
+  int64_t* woff = nullptr;
+  int32_t* wpos = nullptr;  // position of each unknown inside its own Omega_Ii
 
   // maps: omega in ascending global order ("sorted") and in [I, Gamma] order ("export")
   int64_t omega_total = 0;

@@ -695,6 +695,8 @@ struct EigArgs {
   const int64_t* pad_off;
   const int32_t* cpl_col;
   const double* cpl_val;
+  const int32_t* ucpl_row;  // A_k,k+1 by column (fast coupling lists)
+  const double* ucpl_val;
   double* dummy;    // per-thread discard slots (subdomain x chunk x thread)
   double* X;        // per subdomain npad x p at p*pad_off
   double* Y;
@@ -791,7 +793,87 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
   }
 }
 
+// part[g * s + r] = sum over the g-th column chunk of G_k^T y (1024 threads,
+// Gn = T / s groups), then res[r] = sum_g part[g * s + r] in group order
 template <class FT>
+__device__ __forceinline__ void tile_tmatvec(const FT* G, int s, const double* y, double* part,
+                                             double* res, bool subtract) {
+  constexpr int V = adsd::TileV<FT>::V;
+  const int t = threadIdx.x, T = blockDim.x;
+  const int Gn = T / s, chunk = (s + Gn - 1) / Gn;
+  if (t < Gn * s) {
+    const int r = t % s, g = t / s;
+    const int c1 = min(s, (g + 1) * chunk);
+    double acc = 0.0;
+    for (int cc = g * chunk; cc < c1; ++cc) acc += adsd::ld_fac(G, adsd::tile_at(cc, r, s, V)) * y[cc];
+    part[g * s + r] = acc;
+  }
+  __syncthreads();
+  for (int r = t; r < s; r += T) {
+    double v = 0.0;
+    for (int g = 0; g < Gn; ++g) v += part[g * s + r];
+    res[r] = subtract ? res[r] - v : v;
+  }
+  __syncthreads();
+}
+
+// l solves Atilde_reg^T l = e_last with the splitting tiles and the fixed-
+// width coupling lists (A_k,k+1 by column for the forward sweep; the rows of
+// A_k+1,k staged in LDS and gathered by column for the backward sweep).
+// LDS: s (y) + T (partials) + s * NCPL (ints, as doubles) + s * NCPL + s doubles.
+template <class FT>
+__device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const int32_t* urow,
+                                     const double* uval, const int32_t* ccol, const double* cval,
+                                     double* x, double* lds) {
+  const int t = threadIdx.x, T = blockDim.x;
+  constexpr int V = adsd::TileV<FT>::V;
+  constexpr int NC = adsd::NCPL;
+  const int64_t TS = adsd::tile_size(s, V);
+  const int npad = K * s;
+  double* ybuf = lds;
+  double* part = ybuf + s;
+  int* cc_s = reinterpret_cast<int*>(part + T);
+  double* cv_s = part + T + (s * NC + 1) / 2;
+  double* lx = cv_s + s * NC;
+  for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
+  __syncthreads();
+  // forward with U^T: w_k = G_k^T (x_k - A_{k-1,k}^T w_{k-1})
+  for (int k = 0; k < K; ++k) {
+    const int r0 = k * s;
+    for (int c = t; c < s; c += T) {
+      double v = x[r0 + c];
+      if (k > 0)
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          const int rr = urow[(int64_t)(r0 + c) * NC + m];
+          if (rr >= 0) v -= uval[(int64_t)(r0 + c) * NC + m] * x[r0 - s + rr];
+        }
+      ybuf[c] = v;
+    }
+    __syncthreads();
+    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + r0, false);
+  }
+  // backward with L^T: l_k = w_k - G_k^T (A_{k+1,k}^T l_{k+1})
+  for (int k = K - 2; k >= 0; --k) {
+    const int r0 = k * s, r1 = r0 + s;
+    for (int e = t; e < s * NC; e += T) {
+      cc_s[e] = ccol[(int64_t)r1 * NC + e];
+      cv_s[e] = cval[(int64_t)r1 * NC + e];
+    }
+    for (int r = t; r < s; r += T) lx[r] = x[r1 + r];
+    __syncthreads();
+    for (int c = t; c < s; c += T) {
+      double v = 0.0;
+      for (int e = 0; e < s * NC; ++e)
+        if (cc_s[e] == c) v += cv_s[e] * lx[e / NC];
+      ybuf[c] = v;
+    }
+    __syncthreads();
+    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + r0, true);
+  }
+}
+
+template <class FT, bool CPL>
 __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, double* scratch) {
   __shared__ double red[16];
   const int i = blockIdx.x;
@@ -806,10 +888,14 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   __syncthreads();
   if (a.kdim[i]) {
     double* l = a.ell + a.pad_off[i];
-    double* tmp = scratch + (int64_t)blockIdx.x * 2 * 1024;  // unused if s <= 512
     extern __shared__ double dyn[];
-    double* tbuf = (2 * s <= 4096) ? dyn : tmp;
-    transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, l, tbuf);
+    if constexpr (CPL)
+      transposed_solve_cpl<FT>(fac + a.fac_off[i], s, K, n, a.ucpl_row + a.pad_off[i] * adsd::NCPL,
+                               a.ucpl_val + a.pad_off[i] * adsd::NCPL,
+                               a.cpl_col + a.pad_off[i] * adsd::NCPL,
+                               a.cpl_val + a.pad_off[i] * adsd::NCPL, l, dyn);
+    else
+      transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, l, dyn);
     double nn = 0.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) nn += l[r] * l[r];
     nn = adsd::block_sum(nn, red);
@@ -1316,9 +1402,12 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   hipStream_t st = c.stream;
   const int nsub = c.nsub;
   int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
-  double* scratch = c.mem.alloc<double>((size_t)nsub * 2 * 1024);
-  size_t init_lds = (2 * smax <= 4096) ? 2 * smax * sizeof(double) : 0;
+  double* scratch = nullptr;
   if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
+  const bool cpl = c.cpl_ok && c.ucpl_row != nullptr;
+  const size_t init_lds =
+      cpl ? (size_t)(2 * smax + EIG_T + (smax * adsd::NCPL + 1) / 2 + smax * adsd::NCPL + 8) * 8
+          : (size_t)2 * smax * sizeof(double);
   const int pq = (a.p + 3) & ~3;
   const size_t rb_lds = (size_t)2 * (1 << a.lrb) * pq * sizeof(double);
   const unsigned nblk = (unsigned)c.h_eig_nblk;
@@ -1327,7 +1416,10 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 0);
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
   };
-  ADS_LAUNCH((k_eig_init<FT>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
+  if (cpl)
+    ADS_LAUNCH((k_eig_init<FT, true>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
+  else
+    ADS_LAUNCH((k_eig_init<FT, false>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
   orth();
   constexpr int PC = EIG_PC;
   const bool fast = c.solve_fast;
@@ -1369,7 +1461,6 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
   }
   ADS_HIP(hipStreamSynchronize(st));
-  c.mem.release(scratch);
 }
 
 void eigensolve(Ctx& c) {
@@ -1399,6 +1490,8 @@ void eigensolve(Ctx& c) {
   a.pad_off = c.pad_off;
   a.cpl_col = c.cpl_col;
   a.cpl_val = c.cpl_val;
+  a.ucpl_row = c.ucpl_row;
+  a.ucpl_val = c.ucpl_val;
   a.dummy = c.mem.alloc<double>((size_t)nsub * ((p + EIG_PC - 1) / EIG_PC) * 1024);
   a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
   a.Y = c.mem.alloc<double>((size_t)c.npad_total * p);

@@ -17,65 +17,87 @@ namespace ads {
 
 static constexpr double KERNEL_ROWSUM_TOL = 1e-13;
 
+// position of global index c in ascending Omega_i, or -1 (window lookup)
+__device__ __forceinline__ int local_pos(const int32_t* wpos, int64_t wl, int64_t wh, int64_t wo,
+                                         int c) {
+  return (c >= wl && c < wh) ? wpos[wo + (c - wl)] : -1;
+}
+
 __global__ void k_extract_count(const int32_t* rowptr, const int32_t* col, const double* val,
                                 const int32_t* om_sorted, const int32_t* om_sub,
-                                const uint8_t* om_int, const int64_t* om_off, const int32_t* ni,
+                                const uint8_t* om_int, const int64_t* om_off, const int64_t* wlo,
+                                const int64_t* whi, const int64_t* woff, const int32_t* wpos,
                                 int64_t total, int32_t* cnt, double* lsum, int32_t* bw,
                                 int32_t* nfail) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= total) return;
-  const int i = om_sub[f];
-  const int64_t base = om_off[i];
-  const int n = ni[i];
-  const int32_t* om = om_sorted + base;
-  const int r = (int)(f - base);
-  const int g = om[r];
-  const bool overlap_row = !om_int[f];
-  int count = 0, maxd = 0;
-  double s = 0.0, rs = 0.0, ars = 0.0;
-  double diag = 0.0;
-  for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
-    const int c = col[k];
-    const double a = val[k];
-    const int p = adsd::lower_bound_i32(om, n, c);
-    if (p < n && om[p] == c) {
-      ++count;
-      maxd = max(maxd, abs(p - r));
-      if (c == g)
-        diag = a;
-      else {
-        rs += a;
-        ars += fabs(a);
+  int maxd = 0, bad = 0, i = -1;
+  if (f < total) {
+    i = om_sub[f];
+    const int64_t base = om_off[i];
+    const int64_t wl = wlo[i], wh = whi[i], wo = woff[i];
+    const int r = (int)(f - base);
+    const int g = om_sorted[f];
+    const bool overlap_row = !om_int[f];
+    int count = 0;
+    double s = 0.0, rs = 0.0, ars = 0.0;
+    double diag = 0.0;
+    for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+      const int c = col[k];
+      const double a = val[k];
+      const int p = local_pos(wpos, wl, wh, wo, c);
+      if (p >= 0) {
+        ++count;
+        maxd = max(maxd, abs(p - r));
+        if (c == g)
+          diag = a;
+        else {
+          rs += a;
+          ars += fabs(a);
+        }
+      } else if (overlap_row) {
+        s += fabs(a);
       }
-    } else if (overlap_row) {
-      s += fabs(a);
+    }
+    const double dt = diag - s;  // diagonal of the splitting
+    rs += dt;
+    ars += fabs(dt);
+    cnt[f] = count;
+    lsum[f] = overlap_row ? s : 0.0;
+    bad = !(fabs(rs) <= KERNEL_ROWSUM_TOL * ars);
+  }
+  // one atomic per run of equal subdomains in the wavefront
+  const int lane = threadIdx.x & 63;
+  const int iprev = __shfl_up(i, 1, 64);
+  const bool head = lane == 0 || iprev != i;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int om = __shfl_down(maxd, o, 64), ob = __shfl_down(bad, o, 64);
+    const int oi = __shfl_down(i, o, 64);
+    if (lane + o < 64 && oi == i) {
+      maxd = max(maxd, om);
+      bad += ob;
     }
   }
-  const double dt = diag - s;  // diagonal of the splitting
-  rs += dt;
-  ars += fabs(dt);
-  cnt[f] = count;
-  lsum[f] = overlap_row ? s : 0.0;
-  atomicMax(&bw[i], maxd);
-  if (!(fabs(rs) <= KERNEL_ROWSUM_TOL * ars)) atomicAdd(&nfail[i], 1);
+  if (head && i >= 0) {
+    atomicMax(&bw[i], maxd);
+    if (bad) atomicAdd(&nfail[i], bad);
+  }
 }
 
 __global__ void k_extract_fill(const int32_t* rowptr, const int32_t* col, const double* val,
                                const int32_t* om_sorted, const int32_t* om_sub,
-                               const int64_t* om_off, const int32_t* ni, int64_t total,
-                               const int64_t* lrow, int32_t* lcol, double* lval) {
+                               const int64_t* wlo, const int64_t* whi, const int64_t* woff,
+                               const int32_t* wpos, int64_t total, const int64_t* lrow,
+                               int32_t* lcol, double* lval) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= total) return;
   const int i = om_sub[f];
-  const int64_t base = om_off[i];
-  const int n = ni[i];
-  const int32_t* om = om_sorted + base;
-  const int g = om[f - base];
+  const int64_t wl = wlo[i], wh = whi[i], wo = woff[i];
+  const int g = om_sorted[f];
   int64_t w = lrow[f];
   for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
     const int c = col[k];
-    const int p = adsd::lower_bound_i32(om, n, c);
-    if (p < n && om[p] == c) {
+    const int p = local_pos(wpos, wl, wh, wo, c);
+    if (p >= 0) {
       lcol[w] = p;
       lval[w] = val[k];
       ++w;
@@ -185,7 +207,8 @@ void extract_local(Ctx& c) {
   ADS_HIP(hipMemsetAsync(cnt + T, 0, 4, s));
   unsigned gb = (unsigned)((T + 255) / 256);
   ADS_LAUNCH(k_extract_count, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
-             c.om_sub, c.om_int, c.om_off, c.ni, T, cnt, c.lsum, bw, nfail);
+             c.om_sub, c.om_int, c.om_off, c.wlo, c.whi, c.woff, c.wpos, T, cnt, c.lsum, bw,
+             nfail);
   int64_t* lrow = c.mem.alloc<int64_t>(T + 1);
   exclusive_scan_i64(cnt, lrow, T + 1, c.mem, s);
   std::vector<int64_t> hl;
@@ -195,7 +218,7 @@ void extract_local(Ctx& c) {
   c.lcol = c.mem.alloc<int32_t>(c.lnnz);
   c.lval = c.mem.alloc<double>(c.lnnz);
   ADS_LAUNCH(k_extract_fill, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
-             c.om_sub, c.om_off, c.ni, T, lrow, c.lcol, c.lval);
+             c.om_sub, c.wlo, c.whi, c.woff, c.wpos, T, lrow, c.lcol, c.lval);
   c.kdim = c.mem.alloc<int32_t>(nsub);
   ADS_LAUNCH(k_kernel_dim, dim3((nsub + 255) / 256), dim3(256), 0, s, nfail, nsub, c.kdim);
   download(c.h_kdim, c.kdim, nsub, s);

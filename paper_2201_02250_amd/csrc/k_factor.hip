@@ -43,18 +43,18 @@ __device__ __forceinline__ void store_tile(FT* dst, const double* M, int s, int 
   }
 }
 
-template <class FT>
+template <class FT, bool USE_LDS>
 __global__ void __launch_bounds__(FAC_T)
 k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, const double* lsum,
                const uint8_t* om_int, const int64_t* om_off, const int32_t* ni,
                const int32_t* bsz, const int32_t* nblk, const int64_t* fac_off,
                const int32_t* kdim, int splitting, FT* fac, double* gscr, int64_t gscr_stride,
-               int use_lds, int32_t* bad_pivot) {
+               int32_t* bad_pivot) {
   extern __shared__ double lds[];
   const int i = blockIdx.x;
   const int s = bsz[i], K = nblk[i], n = ni[i];
   const int t = threadIdx.x, T = blockDim.x;
-  double* D = use_lds ? lds : gscr + (int64_t)i * gscr_stride;
+  double* D = USE_LDS ? lds : gscr + (int64_t)i * gscr_stride;
   double* Pp = D + (int64_t)s * s;
   double* colp = Pp + (int64_t)s * s;
   const int64_t rbase = om_off[i];
@@ -149,11 +149,22 @@ k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, con
   }
 }
 
-// Same factorization, element-parallel: 1024 threads, the Schur update and
-// P_k use the fixed-width coupling lists (A_k,k-1 by row, A_k,k+1 by column),
-// Gauss-Jordan takes two barriers per pivot.  blockIdx.y selects the matrix
-// (0: A_ii, 1: splitting), so both are factored in one launch.
-template <class FT>
+// Same factorization, register-resident: 1024 threads; thread t owns column
+// j = t % s of D_k for the rows g, g + G, g + 2G, ... (g = t / s, G = 1024 / s,
+// at most FMR rows).  The Schur update and P_k use the fixed-width coupling
+// lists (A_k,k-1 by row, A_k,k+1 by column).  Gauss-Jordan takes one barrier
+// per pivot: the owners of the next pivot row and column publish them into
+// the other half of a double buffer while they update.  blockIdx.y selects
+// the matrix (0: A_ii, 1: splitting), so both are factored in one launch.
+static constexpr int FMR = 9;
+
+__host__ __device__ inline bool factor_fast_ok(int s) {
+  if (s < 1 || s > 1024) return false;
+  const int G = 1024 / s;
+  return (s + G - 1) / G <= FMR;
+}
+
+template <class FT, bool USE_LDS>
 __global__ void __launch_bounds__(1024)
 k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval,
                     const double* lsum, const uint8_t* om_int, const int64_t* om_off,
@@ -161,33 +172,38 @@ k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval
                     const int64_t* fac_off, const int32_t* kdim, const int64_t* pad_off,
                     const int32_t* ccol, const double* cval, const int32_t* urow,
                     const double* uval, FT* facA, FT* facT, double* gscr, int64_t gscr_stride,
-                    int use_lds, int32_t* bad_pivot) {
+                    int32_t* bad_pivot) {
   extern __shared__ double lds[];
   const int i = blockIdx.x;
   const int splitting = blockIdx.y;
   FT* fac = splitting ? facT : facA;
   const int s = bsz[i], K = nblk[i], n = ni[i];
   const int t = threadIdx.x, T = blockDim.x;
-  double* D = use_lds ? lds : gscr + ((int64_t)splitting * gridDim.x + i) * gscr_stride;
+  // a pointer known to be LDS at compile time keeps ds_* instructions
+  double* D = USE_LDS ? lds : gscr + ((int64_t)splitting * gridDim.x + i) * gscr_stride;
   double* Pp = D + (int64_t)s * s;
-  double* rowp = Pp + (int64_t)s * s;
-  double* colp = rowp + s;
+  double* rowb = Pp + (int64_t)s * s;  // [2][s]
+  double* colb = rowb + 2 * s;         // [2][s]
   const int64_t rbase = om_off[i];
   const int64_t pbase = pad_off[i];
   const bool regularise = splitting && kdim[i];
   FT* F = fac + fac_off[i];
-  const int64_t ss = (int64_t)s * s;
+  const int ss = s * s;
   constexpr int V = adsd::TileV<FT>::V;
   const int64_t TS = adsd::tile_size(s, V);
+  const int G = T / s;
+  const int j = t % s, g = t / s;
+  const int nr = g < G ? (s - g + G - 1) / G : 0;
+  double v[FMR];
   for (int k = 0; k < K; ++k) {
     const int r0 = k * s;
     __syncthreads();
-    for (int64_t e = t; e < ss; e += T) D[e] = 0.0;
+    for (int e = t; e < ss; e += T) D[e] = 0.0;
     __syncthreads();
     for (int rr = t; rr < s; rr += T) {
       const int r = r0 + rr;
       if (r >= n) {
-        D[(int64_t)rr * s + rr] = 1.0;
+        D[rr * s + rr] = 1.0;
         continue;
       }
       const int64_t f = rbase + r;
@@ -199,66 +215,86 @@ k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval
           if (!om_int[f]) a -= lsum[f];
           if (regularise && r == n - 1) a *= 2.0;
         }
-        D[(int64_t)rr * s + cc] = a;
+        D[rr * s + cc] = a;
       }
     }
     __syncthreads();
-    if (k > 0) {  // D -= A_k,k-1 P_{k-1}
-      for (int64_t e = t; e < ss; e += T) {
-        const int rr = (int)(e / s), j = (int)(e - (int64_t)rr * s);
+    if (k > 0) {  // D -= A_k,k-1 P_{k-1}, on the owned elements
+      for (int m = 0; m < nr; ++m) {
+        const int rr = g + m * G;
         const int64_t cb = (pbase + r0 + rr) * adsd::NCPL;
-        double v = D[e];
+        double x = D[rr * s + j];
 #pragma unroll
-        for (int m = 0; m < adsd::NCPL; ++m) {
-          const int cc = ccol[cb + m];
-          if (cc >= 0) v -= cval[cb + m] * Pp[(int64_t)cc * s + j];
+        for (int q = 0; q < adsd::NCPL; ++q) {
+          const int cc = ccol[cb + q];
+          if (cc >= 0) x -= cval[cb + q] * Pp[cc * s + j];
         }
-        D[e] = v;
+        D[rr * s + j] = x;
       }
     }
-    // Gauss-Jordan inversion in place, no pivoting (2 barriers per pivot)
-    for (int p = 0; p < s; ++p) {
-      __syncthreads();
-      for (int e = t; e < s; e += T) {
-        rowp[e] = D[(int64_t)p * s + e];
-        colp[e] = D[(int64_t)e * s + p];
+    // own elements into registers; publish pivot row/column 0
+#pragma unroll
+    for (int m = 0; m < FMR; ++m) {
+      if (m < nr) {
+        const int rr = g + m * G;
+        const double x = D[rr * s + j];
+        v[m] = x;
+        if (rr == 0) rowb[j] = x;
+        if (j == 0) colb[rr] = x;
       }
-      __syncthreads();
-      double piv = rowp[p];
+    }
+    __syncthreads();
+    // Gauss-Jordan inversion, no pivoting, one barrier per pivot
+    for (int p = 0; p < s; ++p) {
+      const double* rw = rowb + (p & 1) * s;
+      const double* cl = colb + (p & 1) * s;
+      double* rwn = rowb + ((p + 1) & 1) * s;
+      double* cln = colb + ((p + 1) & 1) * s;
+      double piv = rw[p];
       if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
         if (t == 0) atomicMax(bad_pivot, i + 1);
         piv = 1.0;
       }
       const double inv = 1.0 / piv;
-      for (int64_t e = t; e < ss; e += T) {
-        const int rr = (int)(e / s), j = (int)(e - (int64_t)rr * s);
-        double v;
-        if (rr == p)
-          v = (j == p) ? inv : rowp[j] * inv;
-        else if (j == p)
-          v = -colp[rr] * inv;
-        else
-          v = D[e] - colp[rr] * rowp[j] * inv;
-        D[e] = v;
-      }
-    }
-    __syncthreads();
-    FT* G = F + (int64_t)k * 2 * TS;
-    store_tile(G, D, s, V);
-    if (k + 1 < K) {  // P_k = G_k A_k,k+1 (by columns of block k+1)
-      for (int64_t e = t; e < ss; e += T) {
-        const int cp = (int)(e / s), rho = (int)(e - (int64_t)cp * s);
-        const int64_t ub = (pbase + r0 + s + cp) * adsd::NCPL;
-        double v = 0.0;
+      const double rj = rw[j] * inv;
 #pragma unroll
-        for (int m = 0; m < adsd::NCPL; ++m) {
-          const int rr = urow[ub + m];
-          if (rr >= 0) v += D[(int64_t)rho * s + rr] * uval[ub + m];
+      for (int m = 0; m < FMR; ++m) {
+        if (m < nr) {
+          const int rr = g + m * G;
+          double x;
+          if (rr == p)
+            x = (j == p) ? inv : rj;
+          else if (j == p)
+            x = -cl[rr] * inv;
+          else
+            x = v[m] - cl[rr] * rj;
+          v[m] = x;
+          if (rr == p + 1) rwn[j] = x;
+          if (j == p + 1) cln[rr] = x;
         }
-        Pp[(int64_t)rho * s + cp] = v;
       }
       __syncthreads();
-      store_tile(G + TS, Pp, s, V);
+    }
+#pragma unroll
+    for (int m = 0; m < FMR; ++m)
+      if (m < nr) D[(g + m * G) * s + j] = v[m];
+    __syncthreads();
+    FT* Gt = F + (int64_t)k * 2 * TS;
+    store_tile(Gt, D, s, V);
+    if (k + 1 < K) {  // P_k = G_k A_k,k+1 (by columns of block k+1)
+      for (int e = t; e < ss; e += T) {
+        const int cp = e / s, rho = e - cp * s;
+        const int64_t ub = (pbase + r0 + s + cp) * adsd::NCPL;
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < adsd::NCPL; ++q) {
+          const int rr = urow[ub + q];
+          if (rr >= 0) x += D[rho * s + rr] * uval[ub + q];
+        }
+        Pp[rho * s + cp] = x;
+      }
+      __syncthreads();
+      store_tile(Gt + TS, Pp, s, V);
     }
   }
 }
@@ -272,16 +308,22 @@ static void factor_fast(Ctx& c, bool both) {
   c.facA = fa;
   c.facT = ft;
   int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
-  size_t need = ((size_t)2 * smax * smax + 2 * smax) * sizeof(double);
+  size_t need = ((size_t)2 * smax * smax + 4 * smax) * sizeof(double);
   int use_lds = need <= 150 * 1024;
-  int64_t stride = (int64_t)2 * smax * smax + 2 * smax;
+  int64_t stride = (int64_t)2 * smax * smax + 4 * smax;
   double* gscr = use_lds ? nullptr : c.mem.alloc<double>((size_t)stride * nsub * 2);
   int32_t* bad = c.mem.alloc<int32_t>(1);
   ADS_HIP(hipMemsetAsync(bad, 0, 4, st));
-  ADS_LAUNCH((k_block_factor_fast<FT>), dim3(nsub, both ? 2 : 1), dim3(1024), use_lds ? need : 0,
-             st, c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb,
-             c.fac_off, c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, fa, ft,
-             gscr, stride, use_lds, bad);
+  if (use_lds)
+    ADS_LAUNCH((k_block_factor_fast<FT, true>), dim3(nsub, both ? 2 : 1), dim3(1024), need, st,
+               c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
+               c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, fa, ft, gscr, stride,
+               bad);
+  else
+    ADS_LAUNCH((k_block_factor_fast<FT, false>), dim3(nsub, both ? 2 : 1), dim3(1024), 0, st,
+               c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
+               c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, fa, ft, gscr, stride,
+               bad);
   std::vector<int32_t> hb;
   download(hb, bad, 1, st);
   if (gscr) c.mem.release(gscr);
@@ -304,9 +346,14 @@ static void factor_one(Ctx& c, int splitting, void** out) {
   if (!use_lds) gscr = c.mem.alloc<double>((size_t)stride * nsub);
   int32_t* bad = c.mem.alloc<int32_t>(1);
   ADS_HIP(hipMemsetAsync(bad, 0, 4, s));
-  ADS_LAUNCH((k_block_factor<FT>), dim3(nsub), dim3(FAC_T), use_lds ? need : 0, s, c.lptr_off,
-             c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off, c.kdim,
-             splitting, fac, gscr, stride, use_lds, bad);
+  if (use_lds)
+    ADS_LAUNCH((k_block_factor<FT, true>), dim3(nsub), dim3(FAC_T), need, s, c.lptr_off, c.lcol,
+               c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off, c.kdim, splitting,
+               fac, gscr, stride, bad);
+  else
+    ADS_LAUNCH((k_block_factor<FT, false>), dim3(nsub), dim3(FAC_T), 0, s, c.lptr_off, c.lcol,
+               c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off, c.kdim, splitting,
+               fac, gscr, stride, bad);
   std::vector<int32_t> hb;
   download(hb, bad, 1, s);
   if (gscr) c.mem.release(gscr);
@@ -326,7 +373,9 @@ void factor_local(Ctx& c) {
   const bool need_split = c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0;
   size_t esz = c.prec == ADS_PREC_FP64 ? 8 : (c.prec == ADS_PREC_FP32 ? 4 : 2);
   c.factor_bytes = (int64_t)(c.fac_elems * esz);
-  if (c.cpl_ok) {
+  bool fast = c.cpl_ok;
+  for (int i = 0; i < nsub; ++i) fast = fast && factor_fast_ok(c.h_bs[i]);
+  if (fast) {
     switch (c.prec) {
       case ADS_PREC_FP64: factor_fast<double>(c, need_split); break;
       case ADS_PREC_FP32: factor_fast<float>(c, need_split); break;

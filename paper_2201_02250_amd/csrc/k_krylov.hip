@@ -15,13 +15,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "ads_internal.h"
 
 namespace ads {
 
 static constexpr int KR_T = 256;
-static constexpr int CH_ROWS = 8192;  // rows per reduction chunk
+static constexpr int CH_ROWS = 4 * KR_T;  // rows per reduction chunk (4 per thread)
 
 struct KInst {
   const int64_t* row0;   // [Q] first row of the instance's segment
@@ -46,7 +47,11 @@ __global__ void k_spmv(const int32_t* __restrict__ rowptr, const int32_t* __rest
   y[e] = mode ? b[e] - acc : acc;
 }
 
-// partial inner products <V_i, w> for i <= jq[q] over one row chunk
+typedef const double __attribute__((address_space(1)))* gcdptr;
+
+// partial inner products <V_i, w> for i <= jq[q] over one row chunk: every
+// thread keeps its 4 rows of w in registers and streams V_i; one wavefront
+// sum per vector, the 4 wavefront sums added in order
 __global__ void __launch_bounds__(KR_T)
 k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w, KInst I,
                const int32_t* __restrict__ jq, const int32_t* __restrict__ act, double* part,
@@ -56,13 +61,26 @@ k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w
   if (!act[q]) return;
   const int J = jq[q];
   const int64_t r0 = I.row0[q], len = I.rows[q];
-  const int64_t a = (int64_t)ch * CH_ROWS, b = min<int64_t>(len, a + CH_ROWS);
+  const int64_t a = (int64_t)ch * CH_ROWS;
+  if (a >= len) return;
   const int64_t off = (int64_t)I.colj[q] * I.n + r0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double wr[4];
+  int64_t rr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t r = a + threadIdx.x + k * KR_T;
+    const bool ok = r < len;
+    rr[k] = ok ? r : a;  // clamped (its w is zeroed)
+    const double x = w[off + rr[k]];
+    wr[k] = ok ? x : 0.0;
+  }
+#pragma unroll 2
   for (int i = 0; i <= J; ++i) {
-    const double* vi = V[i] + off;
+    const gcdptr vi = (gcdptr)(V[i] + off);
     double acc = 0.0;
-    for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) acc += vi[r] * w[off + r];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc += vi[rr[k]] * wr[k];
     acc = adsd::wave_sum(acc);
     if (lane == 0) wsum[wv][i] = acc;
   }
@@ -74,20 +92,25 @@ k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w
   }
 }
 
-// h[q][i] = sum over chunks (fixed order); mode 1 accumulates into h
+// h[q][i] = sum over chunks (lanes stride the chunks, then a wavefront sum:
+// fixed order); mode 1 accumulates into h.  One wavefront per i.
 __global__ void k_mdot_final(const double* part, KInst I, const int32_t* jq, const int32_t* act,
                              double* h, int stride, int accumulate) {
   const int q = blockIdx.x;
   if (!act[q]) return;
   const int64_t len = I.rows[q];
   const int nch = (int)((len + CH_ROWS - 1) / CH_ROWS);
-  for (int i = threadIdx.x; i <= jq[q]; i += blockDim.x) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wv; i <= jq[q]; i += nw) {
     double s = 0.0;
-    for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)q * I.nch + ch) * stride + i];
-    if (accumulate)
-      h[(int64_t)q * stride + i] += s;
-    else
-      h[(int64_t)q * stride + i] = s;
+    for (int ch = lane; ch < nch; ch += 64) s += part[((int64_t)q * I.nch + ch) * stride + i];
+    s = adsd::wave_sum(s);
+    if (lane == 0) {
+      if (accumulate)
+        h[(int64_t)q * stride + i] += s;
+      else
+        h[(int64_t)q * stride + i] = s;
+    }
   }
 }
 
@@ -123,13 +146,16 @@ k_norm_partial(const double* __restrict__ w, KInst I, const int32_t* __restrict_
   if (threadIdx.x == 0) part[(int64_t)q * I.nch + ch] = acc;
 }
 
+// one wavefront per instance: lanes stride the chunks, then a wavefront sum
 __global__ void k_norm_final(const double* part, KInst I, const int32_t* act, double* out) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= I.Q || !act[q]) return;
+  const int q = blockIdx.x;
+  if (!act[q]) return;
+  const int lane = threadIdx.x;
   const int nch = (int)((I.rows[q] + CH_ROWS - 1) / CH_ROWS);
   double s = 0.0;
-  for (int ch = 0; ch < nch; ++ch) s += part[(int64_t)q * I.nch + ch];
-  out[q] = sqrt(s);
+  for (int ch = lane; ch < nch; ch += 64) s += part[(int64_t)q * I.nch + ch];
+  s = adsd::wave_sum(s);
+  if (lane == 0) out[q] = sqrt(s);
 }
 
 // copy segments: dst(q) = src(q) * scale[q] (scale null -> 1); masked
@@ -334,10 +360,12 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   S.g = mem.alloc<double>((size_t)Q * (m + 1));
   S.h = mem.alloc<double>((size_t)Q * stride);
   S.h2 = mem.alloc<double>((size_t)Q * stride);
-  S.hn = mem.alloc<double>(Q);
-  S.est = mem.alloc<double>(Q);
+  // per-iteration status read by the host in one copy: est | hn | brk (int32)
+  double* stat = mem.alloc<double>((size_t)3 * Q);
+  S.est = stat;
+  S.hn = stat + Q;
+  S.brk = reinterpret_cast<int32_t*>(stat + 2 * Q);
   S.jq = mem.alloc<int32_t>(Q);
-  S.brk = mem.alloc<int32_t>(Q);
   double* part = mem.alloc<double>((size_t)Q * I.nch * stride);
   double* bnorm_d = mem.alloc<double>(Q);
   double* beta_d = mem.alloc<double>(Q);
@@ -352,7 +380,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   const unsigned gv = (unsigned)((vsz + 255) / 256);
   auto norms = [&](const double* v, const int32_t* mask, double* out) {
     ADS_LAUNCH(k_norm_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, v, I, mask, part);
-    ADS_LAUNCH(k_norm_final, dim3((Q + 63) / 64), dim3(64), 0, st, part, I, mask, out);
+    ADS_LAUNCH(k_norm_final, dim3(Q), dim3(64), 0, st, part, I, mask, out);
   };
   // x = 0, r = b
   ADS_HIP(hipMemsetAsync(x, 0, vsz * 8, st));
@@ -362,6 +390,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   std::vector<int32_t> state(Q, 0);  // 0 active, 1 done
   std::vector<int32_t> its(Q, 0), status(Q, ADS_OK), jcur(Q, 0);
   std::vector<int32_t> act(Q, 0), endm(Q, 0), jend(Q, 0);
+  std::vector<int32_t> act_up;  // contents of act_d as last uploaded
   std::vector<double> relres(Q, 0.0);
   for (int q = 0; q < Q; ++q)
     if (bnorm[q] == 0.0) state[q] = 1;
@@ -399,7 +428,10 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
       any |= act[q] != 0;
     }
     if (!any) break;
-    ADS_HIP(hipMemcpyAsync(act_d, act.data(), Q * 4, hipMemcpyHostToDevice, st));
+    if (act != act_up) {
+      ADS_HIP(hipMemcpyAsync(act_d, act.data(), Q * 4, hipMemcpyHostToDevice, st));
+      act_up = act;
+    }
     // z = M v_j ; w = A z
     ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dV, u, I, S.jq, act_d, 0);
     apply_prec(c, u, z, nrhs, st);
@@ -410,20 +442,24 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
     // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2
     ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
                S.jq, act_d, part, stride);
-    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(64), 0, st, part, I, S.jq, act_d, S.h, stride, 0);
+    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h, stride, 0);
     ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
                S.h, stride);
     ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
                S.jq, act_d, part, stride);
-    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(64), 0, st, part, I, S.jq, act_d, S.h2, stride, 0);
+    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h2, stride, 0);
     ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
                S.h2, stride);
     norms(w, act_d, S.hn);
     ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
-    download(est, S.est, Q, st);
-    std::vector<int32_t> brk;
-    download(brk, S.brk, Q, st);
-    download(hn, S.hn, Q, st);
+    std::vector<double> hstat;
+    download(hstat, stat, (size_t)3 * Q, st);
+    std::vector<int32_t> brk(Q);
+    for (int q = 0; q < Q; ++q) {
+      est[q] = hstat[q];
+      hn[q] = hstat[Q + q];
+    }
+    std::memcpy(brk.data(), hstat.data() + 2 * Q, (size_t)Q * 4);
     bool anyend = false;
     for (int q = 0; q < Q; ++q) {
       endm[q] = 0;
@@ -446,7 +482,10 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
     // next basis vector for continuing instances
     std::vector<int32_t> cont(Q, 0);
     for (int q = 0; q < Q; ++q) cont[q] = act[q] && !endm[q];
-    ADS_HIP(hipMemcpyAsync(act_d, cont.data(), Q * 4, hipMemcpyHostToDevice, st));
+    if (cont != act_up) {
+      ADS_HIP(hipMemcpyAsync(act_d, cont.data(), Q * 4, hipMemcpyHostToDevice, st));
+      act_up = cont;
+    }
     ADS_LAUNCH(k_advance, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
     ADS_LAUNCH(k_next_basis, gseg, dim3(256), 0, st, dV, w, I, S.jq, act_d, S.hn);
     if (!anyend) continue;

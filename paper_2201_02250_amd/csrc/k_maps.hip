@@ -112,22 +112,48 @@ void transpose_pattern(Arena& mem, const int32_t* rowptr, const int32_t* col, in
 // ---------------------------------------------------------------------------
 // subdomain windows
 // ---------------------------------------------------------------------------
-__global__ void k_part_range(const int32_t* part, int64_t n, int32_t* lo, int32_t* hi,
-                             int32_t* count) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  int p = part[v];
-  atomicMin(&lo[p], (int32_t)v);
-  atomicMax(&hi[p], (int32_t)v);
-  atomicAdd(&count[p], 1);
+// per-part first index, last index and size: each workgroup reduces its
+// slice in LDS (nparts <= PR_MAXP), then one global atomic per touched part
+static constexpr int PR_MAXP = 4096;
+static constexpr int PR_T = 1024;
+static constexpr int PR_PER = 16;  // elements per thread
+
+__global__ void __launch_bounds__(PR_T)
+k_part_range(const int32_t* part, int64_t n, int nparts, int32_t* lo, int32_t* hi,
+             int32_t* count) {
+  __shared__ int32_t slo[PR_MAXP], shi[PR_MAXP], scnt[PR_MAXP];
+  for (int p = threadIdx.x; p < nparts; p += PR_T) {
+    slo[p] = INT32_MAX;
+    shi[p] = -1;
+    scnt[p] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * PR_T * PR_PER;
+  for (int k = 0; k < PR_PER; ++k) {
+    const int64_t v = base + (int64_t)k * PR_T + threadIdx.x;
+    if (v >= n) break;
+    const int p = part[v];
+    atomicMin(&slo[p], (int32_t)v);
+    atomicMax(&shi[p], (int32_t)v);
+    atomicAdd(&scnt[p], 1);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < nparts; p += PR_T)
+    if (scnt[p]) {
+      atomicMin(&lo[p], slo[p]);
+      atomicMax(&hi[p], shi[p]);
+      atomicAdd(&count[p], scnt[p]);
+    }
 }
 
+// largest |column - row| over the stored entries (one atomic per wavefront)
 __global__ void k_bandwidth(const int32_t* rowptr, const int32_t* col, int64_t n, int32_t* bw) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int m = 0;
-  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) m = max(m, abs(col[k] - (int)r));
-  atomicMax(bw, m);
+  if (r < n)
+    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) m = max(m, abs(col[k] - (int)r));
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(bw, m);
 }
 
 __global__ void k_mark_interior(const int32_t* part, int64_t n, const int64_t* wlo,
@@ -211,7 +237,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* wtot, int* total) {
 __global__ void k_compact_window(const uint8_t* map, const int64_t* wlo, const int64_t* woff,
                                  const int64_t* om_off, const int32_t* nI, int32_t* om_sorted,
                                  int32_t* om_sub, uint8_t* om_int, int32_t* om_export,
-                                 int32_t* om_layer, int32_t* ipos) {
+                                 int32_t* om_layer, int32_t* ipos, int32_t* wpos) {
   __shared__ int wt[3][16];
   const int i = blockIdx.x;
   const int64_t a = woff[i], b = woff[i + 1];
@@ -226,6 +252,7 @@ __global__ void k_compact_window(const uint8_t* map, const int64_t* wlo, const i
     int pA = block_excl_scan(is_all, wt[0], &tA);
     int pI = block_excl_scan(is_I, wt[1], &tI);
     int pG = block_excl_scan(is_G, wt[2], &tG);
+    if (f < b) wpos[f] = is_all ? run_all + pA : -1;
     if (is_all) {
       int64_t v = wlo[i] + (f - a);
       int64_t s = base + run_all + pA;
@@ -266,8 +293,9 @@ void build_maps(Ctx& c, const std::vector<int32_t>& part_h) {
     ADS_HIP(hipMemsetAsync(hi, 0xFF, nsub * 4, s));  // -1
     ADS_HIP(hipMemsetAsync(cnt, 0, nsub * 4, s));
     ADS_HIP(hipMemsetAsync(bw, 0, 4, s));
-    ADS_LAUNCH(k_part_range, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.part, n, lo, hi,
-               cnt);
+    if (nsub > PR_MAXP) fail(ADS_ERR_UNSUPPORTED, "more than 4096 subdomains");
+    ADS_LAUNCH(k_part_range, dim3((unsigned)((n + PR_T * PR_PER - 1) / (PR_T * PR_PER))),
+               dim3(PR_T), 0, s, c.part, n, nsub, lo, hi, cnt);
     ADS_LAUNCH(k_bandwidth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.rowptr, c.col, n,
                bw);
     ADS_HIP(hipStreamSynchronize(s));
@@ -321,8 +349,12 @@ void build_maps(Ctx& c, const std::vector<int32_t>& part_h) {
   c.om_export = c.mem.alloc<int32_t>(c.omega_total);
   c.om_layer = c.mem.alloc<int32_t>(c.omega_total);
   c.ipos = c.mem.alloc<int32_t>(n);
+  c.wpos = c.mem.alloc<int32_t>(total);
+  c.wlo = d_wlo;
+  c.whi = d_whi;
+  c.woff = d_woff;
   ADS_LAUNCH(k_compact_window, dim3(nsub), dim3(256), 0, s, map, d_wlo, d_woff, c.om_off, c.nI,
-             c.om_sorted, c.om_sub, c.om_int, c.om_export, c.om_layer, c.ipos);
+             c.om_sorted, c.om_sub, c.om_int, c.om_export, c.om_layer, c.ipos, c.wpos);
   c.int_list = c.om_export;
   c.mem.release(map);
   ADS_HIP(hipStreamSynchronize(s));
