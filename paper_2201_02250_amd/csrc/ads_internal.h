@@ -171,11 +171,17 @@ struct Ctx {
   int64_t npad_total = 0;           // sum of nb*bs
   std::vector<int64_t> h_pad_off;
   int64_t* pad_off = nullptr;       // [nsub+1] offsets of padded local vectors
-  int32_t* cpl_col = nullptr;       // [npad_total * 4] couplings to the previous block
+  // coupling lists of the block-tridiagonal form, NCPL slots per padded row
+  // (column) with -1 / 0.0 in unused slots; indices are local to the block
+  int32_t* cpl_col = nullptr;       // A_k,k-1 by row: columns in block k-1
   double* cpl_val = nullptr;
-  int32_t* ucpl_row = nullptr;      // [npad_total * 4] A_k,k+1 by column: rows of the previous block
+  int32_t* rcpl_col = nullptr;      // A_k,k+1 by row: columns in block k+1
+  double* rcpl_val = nullptr;
+  int32_t* ucpl_row = nullptr;      // A_k-1,k by column of block k: rows in block k-1
   double* ucpl_val = nullptr;
-  bool cpl_ok = false;              // both coupling lists complete (<= 4 per row / column)
+  int32_t* lcpl_row = nullptr;      // A_k+1,k by column of block k: rows in block k+1
+  double* lcpl_val = nullptr;
+  bool cpl_ok = false;              // all four lists complete (<= NCPL per row / column)
   bool solve_fast = false;          // every subdomain fits the prefetching tile solve
   void* facA = nullptr;             // factors of A_ii (apply)
   void* facT = nullptr;             // factors of the regularised splitting (eigensolver)
@@ -201,6 +207,7 @@ struct Ctx {
 
   // workspace for apply / solve
   double* work = nullptr;   // padded local vectors, npad_total * work_cols
+  double* work2 = nullptr;  // backward results of the two-ended solve, same shape
   double* dummy = nullptr;  // per-thread discard slots of the tile solves
   int work_cols = 0;
   double* cvec = nullptr;   // coarse vectors, n0 * cols

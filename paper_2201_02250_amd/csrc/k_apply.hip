@@ -10,6 +10,8 @@
 //
 // Three launches per apply.  With the Boolean partition of unity every global
 // row is written by exactly one subdomain, so no atomics are needed.
+#include <type_traits>
+
 #include "ads_internal.h"
 #include "k_solve.h"
 
@@ -92,16 +94,18 @@ k_coarse_prolong(const double* __restrict__ c, int n0, const double* __restrict_
   }
 }
 
-// gather t = r - A q on Omega_i (zero on the padding) into X (column jj at X + jj*ld)
-__device__ __forceinline__ void gather_local(const int32_t* __restrict__ om, int ns, int npad,
+// gather t = r - A q on local rows [lo, hi) of Omega_i (zero on the padding)
+// into X (column jj at X + jj*ld)
+__device__ __forceinline__ void gather_local(const int32_t* __restrict__ om, int ns, int lo, int hi,
                                              const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ col,
                                              const double* __restrict__ val,
                                              const double* __restrict__ r,
                                              const double* __restrict__ q, int64_t n, int j0, int pc,
                                              double* X, int64_t ld) {
-  for (int e = threadIdx.x; e < npad * pc; e += blockDim.x) {
-    const int lr = e % npad, jj = e / npad;
+  const int len = hi - lo;
+  for (int e = threadIdx.x; e < len * pc; e += blockDim.x) {
+    const int lr = lo + e % len, jj = e / len;
     double v = 0.0;
     if (lr < ns) {
       const int g = om[lr];
@@ -117,14 +121,16 @@ __device__ __forceinline__ void gather_local(const int32_t* __restrict__ om, int
   }
 }
 
-// z = q + R_i^T D_i x_i on the interior rows (Boolean partition of unity)
+// z = q + R_i^T D_i x_i on the interior rows among local rows [lo, hi)
+// (Boolean partition of unity)
 __device__ __forceinline__ void scatter_local(const int32_t* __restrict__ om,
-                                              const uint8_t* __restrict__ om_int, int ns,
+                                              const uint8_t* __restrict__ om_int, int lo, int hi,
                                               const double* __restrict__ q, double* __restrict__ z,
                                               int64_t n, int j0, int pc, const double* X,
                                               int64_t ld) {
-  for (int e = threadIdx.x; e < ns * pc; e += blockDim.x) {
-    const int lr = e % ns, jj = e / ns;
+  const int len = hi - lo;
+  for (int e = threadIdx.x; e < len * pc; e += blockDim.x) {
+    const int lr = lo + e % len, jj = e / len;
     if (!om_int[lr]) continue;
     const int g = om[lr];
     const int64_t off = (int64_t)(j0 + jj) * n;
@@ -145,48 +151,79 @@ struct LocalArgs {
   const int64_t* lrow;
   const int32_t* lcol;
   const double* lval;
-  const int32_t* cpl_col;
+  const int32_t* cpl_col;   // A_k,k-1 by row
   const double* cpl_val;
+  const int32_t* rcpl_col;  // A_k,k+1 by row
+  const double* rcpl_val;
   const int32_t* rowptr;
   const int32_t* col;
   const double* val;
   const int64_t* pad_off;
   double* work;
+  double* work2;  // backward results of the two-ended solve
   int64_t ldw;
   int64_t n;
   int64_t vec_lds_off;  // doubles before the LDS-resident vector
   double* dummy;        // one slot per thread of the launch (stores of idle threads)
 };
 
-// fast path (prefetching tile solve, 1024 threads); LDSX keeps the local
-// vector of one column in LDS
-template <class FT, int P, int D, bool LDSX>
+// Fast path: the two-ended solve in two launches per apply.
+// k_local_fwd (grid: subdomain x column chunk x half): gathers t = r - A q on
+// its half of Omega_i (half 0: blocks 0..M, half 1: blocks M+1..K-1) and runs
+// its forward chain in place in work.  k_local_bwd: the middle block, the
+// backward chain into work2 (so no workgroup overwrites what the other half
+// still reads) and the owner scatter of its half.
+template <class FT, int P, int D>
 __global__ void __launch_bounds__(adsd::SOLVE_T)
-k_local_solve_fast(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
-                   const double* __restrict__ q, double* __restrict__ z, int nrhs) {
+k_local_fwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
+            const double* __restrict__ q, int nrhs) {
   extern __shared__ double lds[];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x, half = blockIdx.z;
   const int j0 = blockIdx.y * P;
   const int pc = min(P, nrhs - j0);
-  const int s = a.bs[i], K = a.nb[i], ns = a.ni[i];
-  const int npad = K * s;
+  const int s = a.bs[i], K = a.nb[i], ns = a.ni[i], M = K / 2;
   const int64_t base = a.om_off[i];
   const int32_t* om = a.om_sorted + base;
-  double* X;
-  int64_t ld;
-  if (LDSX) {
-    X = lds + a.vec_lds_off;
-    ld = npad;
-  } else {
-    X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
-    ld = a.ldw;
-  }
-  gather_local(om, ns, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, ld);
+  double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
+  const int lo = half ? (M + 1) * s : 0, hi = half ? K * s : (M + 1) * s;
+  gather_local(om, ns, lo, hi, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
   __syncthreads();
-  double* dummy = a.dummy + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
-  adsd::block_solve<FT, P, D, LDSX>(fac + a.fac_off[i], s, K, a.cpl_col + a.pad_off[i] * adsd::NCPL,
-                                    a.cpl_val + a.pad_off[i] * adsd::NCPL, X, ld, pc, lds, dummy);
-  scatter_local(om, a.om_int + base, ns, q, z, a.n, j0, pc, X, ld);
+  double* dummy =
+      a.dummy + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * blockDim.x +
+      threadIdx.x;
+  const int64_t cb = a.pad_off[i] * adsd::NCPL;
+  const int32_t* cc = (half ? a.rcpl_col : a.cpl_col) + cb;
+  const double* cv = (half ? a.rcpl_val : a.cpl_val) + cb;
+  adsd::block_chain<FT, P, D, true>(fac + a.fac_off[i], s, half ? K - 1 : 0, half ? -1 : 1,
+                                    half ? K - 1 - M : M, cc, cv, X, X, a.ldw, pc, lds, dummy);
+}
+
+template <class FT, int P, int D>
+__global__ void __launch_bounds__(adsd::SOLVE_T)
+k_local_bwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ q,
+            double* __restrict__ z, int nrhs) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x, half = blockIdx.z;
+  const int j0 = blockIdx.y * P;
+  const int pc = min(P, nrhs - j0);
+  const int s = a.bs[i], K = a.nb[i], ns = a.ni[i], M = K / 2;
+  const int64_t base = a.om_off[i];
+  const int32_t* om = a.om_sorted + base;
+  const double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
+  double* Xo = a.work2 + a.pad_off[i] + (int64_t)j0 * a.ldw;
+  const int64_t cb = a.pad_off[i] * adsd::NCPL;
+  const FT* F = fac + a.fac_off[i];
+  adsd::block_mid<FT, P>(F, s, M, K, a.cpl_col + cb, a.cpl_val + cb, a.rcpl_col + cb,
+                         a.rcpl_val + cb, X, half == 0 ? Xo : nullptr, a.ldw, pc, lds);
+  double* dummy =
+      a.dummy + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * blockDim.x +
+      threadIdx.x;
+  adsd::block_chain<FT, P, D, false>(F, s, half ? M + 1 : M - 1, half ? 1 : -1,
+                                     half ? K - 1 - M : M, nullptr, nullptr, X, Xo, a.ldw, pc, lds,
+                                     dummy);
+  __syncthreads();
+  const int lo = half ? (M + 1) * s : 0, hi = min(ns, half ? K * s : (M + 1) * s);
+  if (lo < hi) scatter_local(om, a.om_int + base, lo, hi, q, z, a.n, j0, pc, Xo, a.ldw);
 }
 
 // general path (any block size / coupling count)
@@ -203,11 +240,11 @@ k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict_
   const int64_t base = a.om_off[i];
   const int32_t* om = a.om_sorted + base;
   double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
-  gather_local(om, ns, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
+  gather_local(om, ns, 0, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
   __syncthreads();
   adsd::block_solve_general<FT, P>(fac + a.fac_off[i], s, K, ns, a.lrow + base, a.lcol, a.lval, X,
                                    a.ldw, pc, lds);
-  scatter_local(om, a.om_int + base, ns, q, z, a.n, j0, pc, X, a.ldw);
+  scatter_local(om, a.om_int + base, 0, ns, q, z, a.n, j0, pc, X, a.ldw);
 }
 
 void ensure_work(Ctx& c, int cols) {
@@ -215,8 +252,13 @@ void ensure_work(Ctx& c, int cols) {
   if (c.work) c.mem.release(c.work);
   if (c.cvec) c.mem.release(c.cvec);
   if (c.qvec) c.mem.release(c.qvec);
+  if (c.work2) c.mem.release(c.work2);
+  if (c.dummy) c.mem.release(c.dummy);
   c.work = c.mem.alloc<double>((size_t)c.npad_total * cols);
-  if (!c.dummy) c.dummy = c.mem.alloc<double>((size_t)c.nsub * 8 * adsd::SOLVE_T);
+  c.work2 = c.mem.alloc<double>((size_t)c.npad_total * cols);
+  // one discard slot per thread of a fast-path launch: subdomain x column
+  // chunk (at least one column per chunk) x half
+  c.dummy = c.mem.alloc<double>((size_t)c.nsub * cols * 2 * adsd::SOLVE_T);
   c.cvec = c.mem.alloc<double>((size_t)std::max(c.n0, 1) * cols);
   c.qvec = c.mem.alloc<double>((size_t)c.n * cols);
   c.work_cols = cols;
@@ -236,11 +278,14 @@ static LocalArgs local_args(Ctx& c) {
   a.lval = c.lval;
   a.cpl_col = c.cpl_col;
   a.cpl_val = c.cpl_val;
+  a.rcpl_col = c.rcpl_col;
+  a.rcpl_val = c.rcpl_val;
   a.rowptr = c.rowptr;
   a.col = c.col;
   a.val = c.val;
   a.pad_off = c.pad_off;
   a.work = c.work;
+  a.work2 = c.work2;
   a.ldw = c.npad_total;
   a.n = c.n;
   a.vec_lds_off = 0;
@@ -255,22 +300,22 @@ static void local_dispatch(Ctx& c, const double* r, const double* q, double* z, 
   constexpr int D = 2;
   constexpr int DM = 2;  // multi-column variants: shallower prefetch, fewer registers
   if (c.solve_fast) {
-    int64_t npad_max = 0;
-    for (int i = 0; i < c.nsub; ++i) npad_max = std::max<int64_t>(npad_max, (int64_t)c.h_nb[i] * c.h_bs[i]);
-    const int64_t sd1 = adsd::solve_lds_doubles<1>(c.h_bs, adsd::SOLVE_T);
-    if (nrhs == 1 && (sd1 + npad_max) * 8 <= 150 * 1024) {
-      a.vec_lds_off = sd1;
-      ADS_LAUNCH((k_local_solve_fast<FT, 1, D, true>), dim3(c.nsub, 1), dim3(adsd::SOLVE_T),
-                 (size_t)(sd1 + npad_max) * 8, s, (const FT*)c.facA, a, r, q, z, nrhs);
-    } else if (nrhs <= 4) {
-      const int64_t sd = adsd::solve_lds_doubles<4>(c.h_bs, adsd::SOLVE_T);
-      ADS_LAUNCH((k_local_solve_fast<FT, 4, DM, false>), dim3(c.nsub, 1), dim3(adsd::SOLVE_T),
-                 (size_t)sd * 8, s, (const FT*)c.facA, a, r, q, z, nrhs);
-    } else {
-      const int64_t sd = adsd::solve_lds_doubles<8>(c.h_bs, adsd::SOLVE_T);
-      ADS_LAUNCH((k_local_solve_fast<FT, 8, DM, false>), dim3(c.nsub, (nrhs + 7) / 8),
-                 dim3(adsd::SOLVE_T), (size_t)sd * 8, s, (const FT*)c.facA, a, r, q, z, nrhs);
-    }
+    auto run = [&](auto ptag, auto dtag) {
+      constexpr int P = decltype(ptag)::value;
+      constexpr int DD = decltype(dtag)::value;
+      const size_t lds = (size_t)adsd::solve_lds_doubles<P>(c.h_bs, adsd::SOLVE_T) * 8;
+      const dim3 grid(c.nsub, (nrhs + P - 1) / P, 2);
+      ADS_LAUNCH((k_local_fwd<FT, P, DD>), grid, dim3(adsd::SOLVE_T), lds, s, (const FT*)c.facA, a,
+                 r, q, nrhs);
+      ADS_LAUNCH((k_local_bwd<FT, P, DD>), grid, dim3(adsd::SOLVE_T), lds, s, (const FT*)c.facA, a,
+                 q, z, nrhs);
+    };
+    if (nrhs == 1)
+      run(std::integral_constant<int, 1>(), std::integral_constant<int, D>());
+    else if (nrhs <= 4)
+      run(std::integral_constant<int, 4>(), std::integral_constant<int, DM>());
+    else
+      run(std::integral_constant<int, 8>(), std::integral_constant<int, DM>());
     return;
   }
   if (nrhs == 1) {

@@ -695,13 +695,22 @@ struct EigArgs {
   const int64_t* pad_off;
   const int32_t* cpl_col;
   const double* cpl_val;
-  const int32_t* ucpl_row;  // A_k,k+1 by column (fast coupling lists)
+  const int32_t* rcpl_col;  // A_k,k+1 by row (fast coupling lists)
+  const double* rcpl_val;
+  const int32_t* ucpl_row;  // A_k-1,k by column
   const double* ucpl_val;
+  const int32_t* lcpl_row;  // A_k+1,k by column
+  const double* lcpl_val;
   double* dummy;    // per-thread discard slots (subdomain x chunk x thread)
   double* X;        // per subdomain npad x p at p*pad_off
   double* Y;
+  double* W;        // per subdomain npad x p: forward results of the two-ended solve
   double* ell;      // per subdomain npad (unit left null vector; floating only)
   double* bell;     // B * ell
+  double* btl;      // B^T * ell
+  double* gam;      // per subdomain ell^T B ell
+  double* colsum;   // per (subdomain, column chunk, half) PC partial column sums of Y
+  int defer;        // 1: the projection onto 1^perp is applied by k_eig_gram
   int32_t* done;    // converged flag
   int32_t* sweeps;
   int32_t* msel;    // selected count
@@ -817,60 +826,111 @@ __device__ __forceinline__ void tile_tmatvec(const FT* G, int s, const double* y
   __syncthreads();
 }
 
-// l solves Atilde_reg^T l = e_last with the splitting tiles and the fixed-
-// width coupling lists (A_k,k+1 by column for the forward sweep; the rows of
-// A_k+1,k staged in LDS and gathered by column for the backward sweep).
-// LDS: s (y) + T (partials) + s * NCPL (ints, as doubles) + s * NCPL + s doubles.
+// l solves Atilde_reg^T l = e_last with the two-ended splitting tiles: the
+// transposed system has the transposed two-ended factorization, so
+//   forward top    w_k = G_k^T (f_k - A_k-1,k^T w_{k-1})      k = 0 .. M-1
+//   forward bottom v_k = G_k^T (f_k - A_k+1,k^T v_{k+1})      k = K-1 .. M+1
+//   middle         l_M = G_M^T (f_M - A_M-1,M^T w - A_M+1,M^T v)
+//   backward top   l_k = w_k - G_k^T (A_k+1,k^T l_{k+1})      k = M-1 .. 0
+//   backward bottom l_k = v_k - G_k^T (A_k-1,k^T l_{k-1})     k = M+1 .. K-1
+// with A_k-1,k^T and A_k+1,k^T applied by column from the coupling lists.
+// One workgroup; LDS: s (y) + T (partials).
 template <class FT>
 __device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const int32_t* urow,
-                                     const double* uval, const int32_t* ccol, const double* cval,
+                                     const double* uval, const int32_t* lrw, const double* lvl,
                                      double* x, double* lds) {
   const int t = threadIdx.x, T = blockDim.x;
   constexpr int V = adsd::TileV<FT>::V;
   constexpr int NC = adsd::NCPL;
   const int64_t TS = adsd::tile_size(s, V);
-  const int npad = K * s;
+  const int npad = K * s, M = K / 2;
   double* ybuf = lds;
   double* part = ybuf + s;
-  int* cc_s = reinterpret_cast<int*>(part + T);
-  double* cv_s = part + T + (s * NC + 1) / 2;
-  double* lx = cv_s + s * NC;
   for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
   __syncthreads();
-  // forward with U^T: w_k = G_k^T (x_k - A_{k-1,k}^T w_{k-1})
-  for (int k = 0; k < K; ++k) {
+  // y_c = (keep ? x_k[c] : 0) - sum of the by-column lists (up: rows of
+  // block k-1, dn: rows of block k+1) applied to x
+  auto gather = [&](int k, bool keep, bool up, bool dn) {
     const int r0 = k * s;
     for (int c = t; c < s; c += T) {
-      double v = x[r0 + c];
-      if (k > 0)
+      double v = keep ? x[r0 + c] : 0.0;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) {
-          const int rr = urow[(int64_t)(r0 + c) * NC + m];
-          if (rr >= 0) v -= uval[(int64_t)(r0 + c) * NC + m] * x[r0 - s + rr];
+      for (int m = 0; m < NC; ++m) {
+        const int64_t e = (int64_t)(r0 + c) * NC + m;
+        if (up) {
+          const int rr = urow[e];
+          if (rr >= 0) v -= uval[e] * x[r0 - s + rr];
         }
+        if (dn) {
+          const int rr = lrw[e];
+          if (rr >= 0) v -= lvl[e] * x[r0 + s + rr];
+        }
+      }
       ybuf[c] = v;
     }
     __syncthreads();
-    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + r0, false);
+  };
+  for (int k = 0; k < M; ++k) {
+    gather(k, true, k > 0, false);
+    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, false);
   }
-  // backward with L^T: l_k = w_k - G_k^T (A_{k+1,k}^T l_{k+1})
-  for (int k = K - 2; k >= 0; --k) {
-    const int r0 = k * s, r1 = r0 + s;
-    for (int e = t; e < s * NC; e += T) {
-      cc_s[e] = ccol[(int64_t)r1 * NC + e];
-      cv_s[e] = cval[(int64_t)r1 * NC + e];
-    }
-    for (int r = t; r < s; r += T) lx[r] = x[r1 + r];
-    __syncthreads();
-    for (int c = t; c < s; c += T) {
-      double v = 0.0;
-      for (int e = 0; e < s * NC; ++e)
-        if (cc_s[e] == c) v += cv_s[e] * lx[e / NC];
-      ybuf[c] = v;
-    }
-    __syncthreads();
-    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + r0, true);
+  for (int k = K - 1; k > M; --k) {
+    gather(k, true, false, k < K - 1);
+    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, false);
   }
+  gather(M, true, M > 0, M < K - 1);
+  tile_tmatvec(fac + (int64_t)M * 2 * TS, s, ybuf, part, x + M * s, false);
+  // backward: x_k -= G_k^T (-y) with y = -(A^T l_neighbour)
+  for (int k = M - 1; k >= 0; --k) {
+    gather(k, false, false, true);
+    for (int c = t; c < s; c += T) ybuf[c] = -ybuf[c];
+    __syncthreads();
+    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, true);
+  }
+  for (int k = M + 1; k < K; ++k) {
+    gather(k, false, true, false);
+    for (int c = t; c < s; c += T) ybuf[c] = -ybuf[c];
+    __syncthreads();
+    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, true);
+  }
+}
+
+// btl = B^T l and gam = l^T B l for a floating subdomain, B = D A_ii D: for
+// every interior column c, the rows of A's column (transposed pattern, rows
+// ascending) that are interior rows of Omega_i, in that order
+__global__ void k_eig_btl(EigArgs a, const int32_t* om_sorted, const int32_t* rowptr,
+                          const int32_t* col, const double* val, const int32_t* tptr,
+                          const int32_t* tcol, const int64_t* wlo, const int64_t* whi,
+                          const int64_t* woff, const int32_t* wpos) {
+  __shared__ double red[16];
+  const int i = blockIdx.x;
+  if (!a.kdim[i]) return;
+  const int n = a.ni[i], npad = a.nb[i] * a.bs[i];
+  const int64_t base = a.om_off[i];
+  const int64_t wl = wlo[i], wh = whi[i], wo = woff[i];
+  const double* l = a.ell + a.pad_off[i];
+  double* bt = a.btl + a.pad_off[i];
+  for (int c = threadIdx.x; c < npad; c += blockDim.x) {
+    double v = 0.0;
+    if (c < n && a.om_int[base + c]) {
+      const int gc = om_sorted[base + c];
+      for (int q = tptr[gc]; q < tptr[gc + 1]; ++q) {
+        const int gr = tcol[q];
+        if (gr < wl || gr >= wh) continue;
+        const int r = wpos[wo + (gr - wl)];
+        if (r < 0 || !a.om_int[base + r]) continue;
+        double arc = 0.0;
+        for (int k = rowptr[gr]; k < rowptr[gr + 1]; ++k)
+          if (col[k] == gc) arc = val[k];
+        v += arc * l[r];
+      }
+    }
+    bt[c] = v;
+  }
+  double g = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) g += l[r] * a.bell[a.pad_off[i] + r];
+  g = adsd::block_sum(g, red);
+  if (threadIdx.x == 0) a.gam[i] = g;
 }
 
 template <class FT, bool CPL>
@@ -892,8 +952,8 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
     if constexpr (CPL)
       transposed_solve_cpl<FT>(fac + a.fac_off[i], s, K, n, a.ucpl_row + a.pad_off[i] * adsd::NCPL,
                                a.ucpl_val + a.pad_off[i] * adsd::NCPL,
-                               a.cpl_col + a.pad_off[i] * adsd::NCPL,
-                               a.cpl_val + a.pad_off[i] * adsd::NCPL, l, dyn);
+                               a.lcpl_row + a.pad_off[i] * adsd::NCPL,
+                               a.lcpl_val + a.pad_off[i] * adsd::NCPL, l, dyn);
     else
       transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, l, dyn);
     double nn = 0.0;
@@ -942,10 +1002,143 @@ __device__ __forceinline__ void block_sum_cols(double (&v)[PC], double (*red)[16
   __syncthreads();
 }
 
-// Y = T X for columns [j0, j0 + PC); FAST selects the prefetching tile solve.
-// T = Pi_1 Atilde^{-1} Pi B Pi on floating subdomains (Pi = I - l l^T, Pi_1 the
-// projection onto 1^perp), Atilde^{-1} B otherwise; B = D A_ii D.
-template <class FT, int PC, bool FAST>
+// Y = T X for columns [j0, j0 + PC), fast path: the two-ended solve in two
+// launches.  k_eig_op_fwd (grid: subdomain x column chunk x half) forms
+// F = B Pi X on its half of the rows (half 0: blocks 0..M, half 1: blocks
+// M+1..K-1) with alpha = l^T X and beta = l^T B Pi X = btl^T X - alpha gam
+// (both from X, so each half needs only its own rows of F), then runs its
+// forward chain in place in W.  k_eig_op_bwd: the middle block and the
+// backward chain from W into Y, and on floating subdomains the per-half
+// column sums of Y; the projection onto 1^perp is applied by k_eig_gram.
+template <class FT, int PC, int D>
+__global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[PC][16];
+  __shared__ double alpha[PC], beta[PC];
+  const int i = blockIdx.x, half = blockIdx.z;
+  if (a.done[i]) return;
+  const int j0 = blockIdx.y * PC;
+  const int p = a.p;
+  const int pc = min(PC, p - j0);
+  if (pc <= 0) return;
+  const int t = threadIdx.x, T = blockDim.x;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, M = K / 2;
+  const int64_t ld = npad;
+  const int64_t base = a.om_off[i];
+  const double* X = a.X + a.pad_off[i] * p + j0 * ld;
+  double* Wv = a.W + a.pad_off[i] * p + j0 * ld;
+  const bool floating = a.kdim[i] != 0;
+  const double* l = a.ell + a.pad_off[i];
+  const double* bl = a.bell + a.pad_off[i];
+  const uint8_t* oi = a.om_int + base;
+  const int64_t* lrow = a.lrow + base;
+  double acc[PC], acc2[PC];
+  if (floating) {  // alpha = l^T X, delta = btl^T X over all rows
+    const double* bt = a.btl + a.pad_off[i];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) acc[j] = acc2[j] = 0.0;
+    for (int r = t; r < n; r += T) {
+      const double lr = l[r], br = bt[r];
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) {
+          const double x = X[r + j * ld];
+          acc[j] += lr * x;
+          acc2[j] += br * x;
+        }
+    }
+    block_sum_cols<PC>(acc, red, alpha, pc);
+    block_sum_cols<PC>(acc2, red, beta, pc);
+    if (t < pc) beta[t] -= alpha[t] * a.gam[i];
+    __syncthreads();
+  }
+  const int lo = half ? (M + 1) * s : 0, hi = half ? npad : (M + 1) * s;
+  for (int r = lo + t; r < hi; r += T) {
+    double v[PC];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) v[j] = 0.0;
+    if (r < n && oi[r]) {
+      const int64_t q1 = lrow[r + 1];
+      for (int64_t q = lrow[r]; q < q1; ++q) {
+        const int c = a.lcol[q];
+        if (!oi[c]) continue;
+        const double av = a.lval[q];
+#pragma unroll
+        for (int j = 0; j < PC; ++j)
+          if (j < pc) v[j] += av * X[c + j * ld];
+      }
+    }
+    if (floating && r < n) {
+      const double br = bl[r], lr = l[r];
+#pragma unroll
+      for (int j = 0; j < PC; ++j) {
+        const int jj = j < pc ? j : 0;
+        v[j] -= alpha[jj] * br + beta[jj] * lr;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PC; ++j)
+      if (j < pc) Wv[r + j * ld] = v[j];
+  }
+  __syncthreads();
+  double* dummy =
+      a.dummy + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * blockDim.x +
+      threadIdx.x;
+  const int64_t cb = a.pad_off[i] * adsd::NCPL;
+  const int32_t* cc = (half ? a.rcpl_col : a.cpl_col) + cb;
+  const double* cv = (half ? a.rcpl_val : a.cpl_val) + cb;
+  adsd::block_chain<FT, PC, D, true>(fac + a.fac_off[i], s, half ? K - 1 : 0, half ? -1 : 1,
+                                     half ? K - 1 - M : M, cc, cv, Wv, Wv, ld, pc, lds, dummy);
+}
+
+template <class FT, int PC, int D>
+__global__ void __launch_bounds__(1024) k_eig_op_bwd(const FT* fac, EigArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[PC][16];
+  __shared__ double sums[PC];
+  const int i = blockIdx.x, half = blockIdx.z;
+  if (a.done[i]) return;
+  const int j0 = blockIdx.y * PC;
+  const int p = a.p;
+  const int pc = min(PC, p - j0);
+  if (pc <= 0) return;
+  const int t = threadIdx.x, T = blockDim.x;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, M = K / 2;
+  const int64_t ld = npad;
+  const double* Wv = a.W + a.pad_off[i] * p + j0 * ld;
+  double* Y = a.Y + a.pad_off[i] * p + j0 * ld;
+  const int64_t cb = a.pad_off[i] * adsd::NCPL;
+  const FT* F = fac + a.fac_off[i];
+  adsd::block_mid<FT, PC>(F, s, M, K, a.cpl_col + cb, a.cpl_val + cb, a.rcpl_col + cb,
+                          a.rcpl_val + cb, Wv, half == 0 ? Y : nullptr, ld, pc, lds);
+  double* dummy =
+      a.dummy + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * blockDim.x +
+      threadIdx.x;
+  adsd::block_chain<FT, PC, D, false>(F, s, half ? M + 1 : M - 1, half ? 1 : -1,
+                                      half ? K - 1 - M : M, nullptr, nullptr, Wv, Y, ld, pc, lds,
+                                      dummy);
+  if (a.kdim[i]) {  // partial column sums of this half's rows (padding rows are zero)
+    __syncthreads();
+    const int lo = half ? (M + 1) * s : 0, hi = min(n, half ? npad : (M + 1) * s);
+    double acc[PC];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+    for (int r = lo + t; r < hi; r += T) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) acc[j] += Y[r + j * ld];
+    }
+    block_sum_cols<PC>(acc, red, sums, pc);
+    if (t < pc)
+      a.colsum[(((int64_t)i * gridDim.y + blockIdx.y) * 2 + half) * PC + t] = sums[t];
+  }
+}
+
+// Y = T X for columns [j0, j0 + PC), general path (one-ended factorization,
+// any block size).  T = Pi_1 Atilde^{-1} Pi B Pi on floating subdomains
+// (Pi = I - l l^T, Pi_1 the projection onto 1^perp), Atilde^{-1} B otherwise;
+// B = D A_ii D.
+template <class FT, int PC>
 __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[PC][16];
@@ -1020,16 +1213,8 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
     }
   }
   __syncthreads();
-  if constexpr (FAST) {
-    constexpr int D = 2;
-    double* dummy = a.dummy + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
-    adsd::block_solve<FT, PC, D, false>(fac + a.fac_off[i], s, K,
-                                        a.cpl_col + a.pad_off[i] * adsd::NCPL,
-                                        a.cpl_val + a.pad_off[i] * adsd::NCPL, Y, ld, pc, lds, dummy);
-  } else {
-    adsd::block_solve_general<FT, PC>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval,
-                                      Y, ld, pc, lds);
-  }
+  adsd::block_solve_general<FT, PC>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, Y,
+                                    ld, pc, lds);
   if (floating) {  // projection onto 1^perp
     __syncthreads();
 #pragma unroll
@@ -1163,8 +1348,29 @@ __global__ void __launch_bounds__(EIG_T) k_eig_gram(EigArgs a, int rr) {
   const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
   double* Ys = rbuf;
   double* Xs = rbuf + RB * pq;
-  stage_rows(a.Y + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Ys);
+  double* Y = a.Y + a.pad_off[i] * p;
+  stage_rows(Y, ld, r0, rows, p, pq, lrb, Ys);
   if (rr) stage_rows(a.X + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Xs);
+  if (a.defer && a.kdim[i]) {
+    // projection onto 1^perp left by the two-ended operator: subtract the
+    // column means (from the per-half sums) from this block's rows
+    __shared__ double mu[PMAX];
+    const int nch = (p + EIG_PC - 1) / EIG_PC;
+    if (threadIdx.x < p) {
+      const int j = threadIdx.x, ch = j / EIG_PC, jj = j % EIG_PC;
+      const double* cs = a.colsum + (int64_t)i * nch * 2 * EIG_PC;
+      mu[j] = (cs[(ch * 2 + 0) * EIG_PC + jj] + cs[(ch * 2 + 1) * EIG_PC + jj]) / a.ni[i];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < RB * p; e += EIG_T) {
+      const int r = e & (RB - 1), c = e >> lrb;
+      if (r < rows) {
+        const double v = Ys[e] - mu[c];
+        Ys[e] = v;
+        Y[r0 + r + c * ld] = v;
+      }
+    }
+  }
   __syncthreads();
   block_gram(Ys, Ys, rows, p, pq, RB, a.partA + (int64_t)b * PMAX * PMAX);
   if (rr) block_gram(Xs, Ys, rows, p, pq, RB, a.partH + (int64_t)b * PMAX * PMAX);
@@ -1425,17 +1631,23 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   const bool fast = c.solve_fast;
   size_t op_lds = fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
                        : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
-  const unsigned op_t = fast ? adsd::SOLVE_T : EIG_T;
+  const unsigned nch = (unsigned)((a.p + PC - 1) / PC);
+  if (fast)
+    ADS_LAUNCH(k_eig_btl, dim3(nsub), dim3(256), 0, st, a, c.om_sorted, c.rowptr, c.col, c.val,
+               c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
   const int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
   std::vector<int32_t> hdone, hnext;
   int next = 3;  // first Rayleigh-Ritz step after 4 sweeps
   for (int sw = 0; sw < maxsw; ++sw) {
-    if (fast)
-      ADS_LAUNCH((k_eig_op<FT, PC, true>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
+    if (fast) {
+      constexpr int D = 2;
+      ADS_LAUNCH((k_eig_op_fwd<FT, PC, D>), dim3(nsub, nch, 2), dim3(adsd::SOLVE_T), op_lds, st,
                  fac, a);
-    else
-      ADS_LAUNCH((k_eig_op<FT, PC, false>), dim3(nsub, (a.p + PC - 1) / PC), dim3(op_t), op_lds, st,
+      ADS_LAUNCH((k_eig_op_bwd<FT, PC, D>), dim3(nsub, nch, 2), dim3(adsd::SOLVE_T), op_lds, st,
                  fac, a);
+    } else {
+      ADS_LAUNCH((k_eig_op<FT, PC>), dim3(nsub, nch), dim3(EIG_T), op_lds, st, fac, a);
+    }
     const bool last = sw == maxsw - 1;
     if (sw < next && !last) {
       orth();
@@ -1490,13 +1702,24 @@ void eigensolve(Ctx& c) {
   a.pad_off = c.pad_off;
   a.cpl_col = c.cpl_col;
   a.cpl_val = c.cpl_val;
+  a.rcpl_col = c.rcpl_col;
+  a.rcpl_val = c.rcpl_val;
   a.ucpl_row = c.ucpl_row;
   a.ucpl_val = c.ucpl_val;
-  a.dummy = c.mem.alloc<double>((size_t)nsub * ((p + EIG_PC - 1) / EIG_PC) * 1024);
+  a.lcpl_row = c.lcpl_row;
+  a.lcpl_val = c.lcpl_val;
+  const int nch = (p + EIG_PC - 1) / EIG_PC;
+  a.dummy = c.mem.alloc<double>((size_t)nsub * nch * 2 * 1024);
   a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
   a.Y = c.mem.alloc<double>((size_t)c.npad_total * p);
+  a.W = c.solve_fast ? c.mem.alloc<double>((size_t)c.npad_total * p) : nullptr;
   a.ell = c.mem.alloc<double>(c.npad_total);
   a.bell = c.mem.alloc<double>(c.npad_total);
+  a.btl = c.mem.alloc<double>(c.npad_total);
+  a.gam = c.mem.alloc<double>(nsub);
+  a.colsum = c.mem.alloc<double>((size_t)nsub * nch * 2 * EIG_PC);
+  a.defer = c.solve_fast ? 1 : 0;
+  ADS_HIP(hipMemsetAsync(a.colsum, 0, (size_t)nsub * nch * 2 * EIG_PC * 8, st));
   a.done = c.mem.alloc<int32_t>(nsub);
   a.sweeps = c.mem.alloc<int32_t>(nsub);
   a.msel = c.mem.alloc<int32_t>(nsub);
@@ -1602,9 +1825,10 @@ void eigensolve(Ctx& c) {
   download(herr, a.err, 1, st);
   if (herr[0] & 8) fail(ADS_ERR_EIG_NOCONV, "coarse basis of a subdomain is rank deficient");
   ADS_HIP(hipStreamSynchronize(st));
-  for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.partA, (void*)a.partB, (void*)a.partH,
-                  (void*)a.partR, (void*)a.HVs})
-    c.mem.release(q);
+  for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.W, (void*)a.partA, (void*)a.partB,
+                  (void*)a.partH, (void*)a.partR, (void*)a.HVs, (void*)a.btl, (void*)a.colsum,
+                  (void*)a.dummy})
+    if (q) c.mem.release(q);
 
 }
 

@@ -110,12 +110,13 @@ __global__ void k_kernel_dim(const int32_t* nfail, int nsub, int32_t* kdim) {
   if (i < nsub) kdim[i] = (nfail[i] == 0) ? 1 : 0;
 }
 
-// per padded local row: the (column in the previous block, value) couplings
-// A_k,k-1 of the block-tridiagonal form, at most NCPL of them
-__global__ void k_couplings(const int64_t* pad_off, int nsub, const int32_t* bs, const int32_t* ni,
-                            const int64_t* om_off, const int64_t* lrow, const int32_t* lcol,
-                            const double* lval, int64_t total, int32_t* ccol, double* cval,
-                            int32_t* overflow) {
+// per padded local row of block k: the (column in block k + dk, value)
+// couplings of the block-tridiagonal form, at most NCPL of them (dk = -1:
+// A_k,k-1 by row; dk = +1: A_k,k+1 by row)
+__global__ void k_row_couplings(const int64_t* pad_off, int nsub, const int32_t* bs,
+                                const int32_t* ni, const int64_t* om_off, const int64_t* lrow,
+                                const int32_t* lcol, const double* lval, int64_t total, int dk,
+                                int32_t* ccol, double* cval, int32_t* overflow) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= total) return;
   const int i = adsd::segment_of(pad_off, nsub, f);
@@ -123,10 +124,10 @@ __global__ void k_couplings(const int64_t* pad_off, int nsub, const int32_t* bs,
   const int s = bs[i];
   const int k = r / s;
   int cnt = 0;
-  if (r < ni[i] && k > 0) {
+  if (r < ni[i]) {
     const int64_t row = om_off[i] + r;
     for (int64_t q = lrow[row]; q < lrow[row + 1]; ++q) {
-      const int cc = lcol[q] - (k - 1) * s;
+      const int cc = lcol[q] - (k + dk) * s;
       if (cc < 0 || cc >= s) continue;
       if (cnt < adsd::NCPL) {
         ccol[f * adsd::NCPL + cnt] = cc;
@@ -142,12 +143,13 @@ __global__ void k_couplings(const int64_t* pad_off, int nsub, const int32_t* bs,
   }
 }
 
-// per padded local row c' (as a column of its block): the entries a_{r,c'} of
-// the rows r of the previous block, at most NCPL, sorted by r (deterministic)
-__global__ void k_upper_couplings(const int64_t* pad_off, int nsub, const int32_t* bs,
-                                  const int32_t* ni, const int64_t* om_off, const int64_t* lrow,
-                                  const int32_t* lcol, const double* lval, int64_t total,
-                                  int32_t* ucnt, int32_t* urow, double* uval) {
+// per padded local column c' of block kb: the entries a_{r,c'} of the rows r
+// of block kb + dr, at most NCPL, sorted by r afterwards (dr = -1: A_kb-1,kb
+// by column; dr = +1: A_kb+1,kb by column)
+__global__ void k_col_couplings(const int64_t* pad_off, int nsub, const int32_t* bs,
+                                const int32_t* ni, const int64_t* om_off, const int64_t* lrow,
+                                const int32_t* lcol, const double* lval, int64_t total, int dr,
+                                int32_t* ucnt, int32_t* urow, double* uval) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= total) return;
   const int i = adsd::segment_of(pad_off, nsub, f);
@@ -158,7 +160,7 @@ __global__ void k_upper_couplings(const int64_t* pad_off, int nsub, const int32_
   const int64_t row = om_off[i] + r;
   for (int64_t q = lrow[row]; q < lrow[row + 1]; ++q) {
     const int cp = lcol[q];
-    if (cp / s != k + 1) continue;
+    if (cp / s != k - dr) continue;
     const int64_t fc = pad_off[i] + cp;  // padded slot of column c'
     const int slot = atomicAdd(&ucnt[fc], 1);
     if (slot < adsd::NCPL) {
@@ -238,33 +240,42 @@ void extract_local(Ctx& c) {
   c.nb = upload(c.mem, c.h_nb.data(), nsub, s);
   c.pad_off = upload(c.mem, c.h_pad_off.data(), nsub + 1, s);
   c.mem.release(cnt);
-  // couplings for the prefetching tile solve
-  c.cpl_col = c.mem.alloc<int32_t>((size_t)c.npad_total * adsd::NCPL);
-  c.cpl_val = c.mem.alloc<double>((size_t)c.npad_total * adsd::NCPL);
+  // the four coupling lists of the block-tridiagonal form (tile solves and
+  // the two-ended factorization)
+  const int64_t NP = c.npad_total;
+  const unsigned gp = (unsigned)((NP + 255) / 256);
   int32_t* ovf = c.mem.alloc<int32_t>(1);
   ADS_HIP(hipMemsetAsync(ovf, 0, 4, s));
-  ADS_LAUNCH(k_couplings, dim3((unsigned)((c.npad_total + 255) / 256)), dim3(256), 0, s, c.pad_off,
-             nsub, c.bs, c.ni, c.om_off, c.lptr_off, c.lcol, c.lval, c.npad_total, c.cpl_col,
-             c.cpl_val, ovf);
-  int32_t* ucnt = c.mem.alloc<int32_t>(c.npad_total);
-  c.ucpl_row = c.mem.alloc<int32_t>((size_t)c.npad_total * adsd::NCPL);
-  c.ucpl_val = c.mem.alloc<double>((size_t)c.npad_total * adsd::NCPL);
-  int32_t* uovf = c.mem.alloc<int32_t>(1);
-  ADS_HIP(hipMemsetAsync(ucnt, 0, c.npad_total * 4, s));
-  ADS_HIP(hipMemsetAsync(uovf, 0, 4, s));
-  ADS_LAUNCH(k_upper_couplings, dim3((unsigned)((c.npad_total + 255) / 256)), dim3(256), 0, s,
-             c.pad_off, nsub, c.bs, c.ni, c.om_off, c.lptr_off, c.lcol, c.lval, c.npad_total, ucnt,
-             c.ucpl_row, c.ucpl_val);
-  ADS_LAUNCH(k_upper_sort, dim3((unsigned)((c.npad_total + 255) / 256)), dim3(256), 0, s,
-             c.npad_total, ucnt, c.ucpl_row, c.ucpl_val, uovf);
-  std::vector<int32_t> hov, huov;
+  auto row_list = [&](int dk, int32_t** cc, double** cv) {
+    *cc = c.mem.alloc<int32_t>((size_t)NP * adsd::NCPL);
+    *cv = c.mem.alloc<double>((size_t)NP * adsd::NCPL);
+    ADS_LAUNCH(k_row_couplings, dim3(gp), dim3(256), 0, s, c.pad_off, nsub, c.bs, c.ni, c.om_off,
+               c.lptr_off, c.lcol, c.lval, NP, dk, *cc, *cv, ovf);
+  };
+  int32_t* ucnt = c.mem.alloc<int32_t>(NP);
+  auto col_list = [&](int dr, int32_t** cr, double** cv) {
+    *cr = c.mem.alloc<int32_t>((size_t)NP * adsd::NCPL);
+    *cv = c.mem.alloc<double>((size_t)NP * adsd::NCPL);
+    ADS_HIP(hipMemsetAsync(ucnt, 0, NP * 4, s));
+    ADS_LAUNCH(k_col_couplings, dim3(gp), dim3(256), 0, s, c.pad_off, nsub, c.bs, c.ni, c.om_off,
+               c.lptr_off, c.lcol, c.lval, NP, dr, ucnt, *cr, *cv);
+    ADS_LAUNCH(k_upper_sort, dim3(gp), dim3(256), 0, s, NP, ucnt, *cr, *cv, ovf);
+  };
+  row_list(-1, &c.cpl_col, &c.cpl_val);    // A_k,k-1 by row
+  row_list(+1, &c.rcpl_col, &c.rcpl_val);  // A_k,k+1 by row
+  col_list(-1, &c.ucpl_row, &c.ucpl_val);  // A_k-1,k by column
+  col_list(+1, &c.lcpl_row, &c.lcpl_val);  // A_k+1,k by column
+  std::vector<int32_t> hov;
   download(hov, ovf, 1, s);
-  download(huov, uovf, 1, s);
   c.mem.release(ucnt);
-  c.cpl_ok = hov[0] == 0 && huov[0] == 0;
-  c.solve_fast = hov[0] == 0;
+  // fast path (two-ended factorization, prefetching tile solves): every list
+  // complete and every block size within the solve and factorization limits
+  c.cpl_ok = hov[0] == 0;
+  c.solve_fast = c.cpl_ok;
   const int V = c.prec == ADS_PREC_FP64 ? 2 : (c.prec == ADS_PREC_FP32 ? 4 : 8);
-  for (int b : c.h_bs) c.solve_fast = c.solve_fast && adsd::solve_fast_ok(b, adsd::SOLVE_T, 1, V);
+  for (int b : c.h_bs)
+    c.solve_fast = c.solve_fast && adsd::solve_fast_ok(b, adsd::SOLVE_T, 1, V) &&
+                   adsd::factor_fast_ok(b);
   ADS_HIP(hipStreamSynchronize(s));
 }
 

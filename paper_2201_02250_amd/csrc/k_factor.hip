@@ -23,6 +23,7 @@
 // Inversion is Gauss-Jordan without pivoting in FP64; tiles are stored in the
 // precision of the context.
 #include <algorithm>
+#include <type_traits>
 
 #include "ads_internal.h"
 #include "k_solve.h"
@@ -149,90 +150,130 @@ k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, con
   }
 }
 
-// Same factorization, register-resident: 1024 threads; thread t owns column
-// j = t % s of D_k for the rows g, g + G, g + 2G, ... (g = t / s, G = 1024 / s,
-// at most FMR rows).  The Schur update and P_k use the fixed-width coupling
-// lists (A_k,k-1 by row, A_k,k+1 by column).  Gauss-Jordan takes one barrier
+// ---------------------------------------------------------------------------
+// Fast path: two-ended block factorization, register-resident Gauss-Jordan.
+//
+// With M = K / 2 the chain is split in two (a "twisted" factorization):
+//   top    (k = 0 .. M-1):    D_k = A_kk - A_k,k-1 P_{k-1},  G_k = D_k^{-1},
+//                              P_k = G_k A_k,k+1
+//   bottom (k = K-1 .. M+1):  E_k = A_kk - A_k,k+1 Q_{k+1}, G_k = E_k^{-1},
+//                              Q_k = G_k A_k,k-1
+//   middle:                   C = A_MM - A_M,M-1 P_{M-1} - A_M,M+1 Q_{M+1},
+//                              G_M = C^{-1}
+// Per block the tiles are (G_k, P_k) above the middle, (G_k, Q_k) below it,
+// (G_M, unused) at it.  A solve is then two independent chains of about K/2
+// dependent steps each (forward from both ends, the middle block, backward
+// towards both ends) instead of one chain of 2K - 1 steps; the two halves of
+// the factorization run in parallel as well.
+//
+// Thread t owns column j = t % s of D_k for the rows g, g + G, g + 2G, ...
+// (g = t / s, G = 1024 / s, at most FMR rows).  Schur updates and the next
+// tile use the fixed-width coupling lists.  Gauss-Jordan takes one barrier
 // per pivot: the owners of the next pivot row and column publish them into
-// the other half of a double buffer while they update.  blockIdx.y selects
-// the matrix (0: A_ii, 1: splitting), so both are factored in one launch.
-static constexpr int FMR = 9;
+// the other half of a double buffer while they update.
+// ---------------------------------------------------------------------------
+struct FacArgs {
+  const int64_t* lrow;
+  const int32_t* lcol;
+  const double* lval;
+  const double* lsum;
+  const uint8_t* om_int;
+  const int64_t* om_off;
+  const int32_t* ni;
+  const int32_t* bs;
+  const int32_t* nb;
+  const int64_t* fac_off;
+  const int32_t* kdim;
+  const int64_t* pad_off;
+  const int32_t* cpl_col;   // A_k,k-1 by row
+  const double* cpl_val;
+  const int32_t* rcpl_col;  // A_k,k+1 by row
+  const double* rcpl_val;
+  const int32_t* ucpl_row;  // A_k-1,k by column
+  const double* ucpl_val;
+  const int32_t* lcpl_row;  // A_k+1,k by column
+  const double* lcpl_val;
+  double* gscr;             // per (subdomain, matrix) work when LDS is too small
+  int64_t gscr_stride;
+  double* mid;              // per (subdomain, matrix, half): the FP64 tile next to the middle
+  int64_t mid_stride;
+  int32_t* bad_pivot;
+};
 
-__host__ __device__ inline bool factor_fast_ok(int s) {
-  if (s < 1 || s > 1024) return false;
-  const int G = 1024 / s;
-  return (s + G - 1) / G <= FMR;
-}
-
-template <class FT, bool USE_LDS>
-__global__ void __launch_bounds__(1024)
-k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval,
-                    const double* lsum, const uint8_t* om_int, const int64_t* om_off,
-                    const int32_t* ni, const int32_t* bsz, const int32_t* nblk,
-                    const int64_t* fac_off, const int32_t* kdim, const int64_t* pad_off,
-                    const int32_t* ccol, const double* cval, const int32_t* urow,
-                    const double* uval, FT* facA, FT* facT, double* gscr, int64_t gscr_stride,
-                    int32_t* bad_pivot) {
-  extern __shared__ double lds[];
-  const int i = blockIdx.x;
-  const int splitting = blockIdx.y;
-  FT* fac = splitting ? facT : facA;
-  const int s = bsz[i], K = nblk[i], n = ni[i];
-  const int t = threadIdx.x, T = blockDim.x;
-  // a pointer known to be LDS at compile time keeps ds_* instructions
-  double* D = USE_LDS ? lds : gscr + ((int64_t)splitting * gridDim.x + i) * gscr_stride;
-  double* Pp = D + (int64_t)s * s;
-  double* rowb = Pp + (int64_t)s * s;  // [2][s]
-  double* colb = rowb + 2 * s;         // [2][s]
-  const int64_t rbase = om_off[i];
-  const int64_t pbase = pad_off[i];
-  const bool regularise = splitting && kdim[i];
-  FT* F = fac + fac_off[i];
-  const int ss = s * s;
-  constexpr int V = adsd::TileV<FT>::V;
-  const int64_t TS = adsd::tile_size(s, V);
-  const int G = T / s;
-  const int j = t % s, g = t / s;
-  const int nr = g < G ? (s - g + G - 1) / G : 0;
+// Per-workgroup state of the register-resident block factorization.
+template <class FT, int FMR>
+struct BlockFac {
+  const FacArgs& a;
+  int i, splitting, s, K, n, t, G, j, g, nr;
+  int64_t rbase, pbase, TS;
+  double *D, *Pp, *rowb, *colb;
   double v[FMR];
-  for (int k = 0; k < K; ++k) {
-    const int r0 = k * s;
+  __device__ BlockFac(const FacArgs& a_, int i_, int sp, double* base) : a(a_), i(i_), splitting(sp) {
+    s = a.bs[i];
+    K = a.nb[i];
+    n = a.ni[i];
+    t = threadIdx.x;
+    G = blockDim.x / s;
+    j = t % s;
+    g = t / s;
+    nr = g < G ? (s - g + G - 1) / G : 0;
+    rbase = a.om_off[i];
+    pbase = a.pad_off[i];
+    TS = adsd::tile_size(s, adsd::TileV<FT>::V);
+    D = base;
+    Pp = D + (int64_t)s * s;
+    rowb = Pp + (int64_t)s * s;  // [2][s]
+    colb = rowb + 2 * s;         // [2][s]
+  }
+
+  // D = A_kk (the splitting diagonal on Definition-1 rows, the regularised
+  // last entry on floating subdomains, identity on padding rows)
+  __device__ void assemble(int k) {
+    const int r0 = k * s, ss = s * s;
+    const bool regularise = splitting && a.kdim[i];
     __syncthreads();
-    for (int e = t; e < ss; e += T) D[e] = 0.0;
+    for (int e = t; e < ss; e += blockDim.x) D[e] = 0.0;
     __syncthreads();
-    for (int rr = t; rr < s; rr += T) {
+    for (int rr = t; rr < s; rr += blockDim.x) {
       const int r = r0 + rr;
       if (r >= n) {
         D[rr * s + rr] = 1.0;
         continue;
       }
       const int64_t f = rbase + r;
-      for (int64_t q = lrow[f]; q < lrow[f + 1]; ++q) {
-        const int cc = lcol[q] - r0;
+      for (int64_t q = a.lrow[f]; q < a.lrow[f + 1]; ++q) {
+        const int cc = a.lcol[q] - r0;
         if (cc < 0 || cc >= s) continue;
-        double a = lval[q];
+        double x = a.lval[q];
         if (cc == rr && splitting) {
-          if (!om_int[f]) a -= lsum[f];
-          if (regularise && r == n - 1) a *= 2.0;
+          if (!a.om_int[f]) x -= a.lsum[f];
+          if (regularise && r == n - 1) x *= 2.0;
         }
-        D[rr * s + cc] = a;
+        D[rr * s + cc] = x;
       }
     }
     __syncthreads();
-    if (k > 0) {  // D -= A_k,k-1 P_{k-1}, on the owned elements
-      for (int m = 0; m < nr; ++m) {
-        const int rr = g + m * G;
-        const int64_t cb = (pbase + r0 + rr) * adsd::NCPL;
-        double x = D[rr * s + j];
+  }
+
+  // D -= C Pp with C the row coupling list (ccol, cval) of block k
+  __device__ void schur(int k, const int32_t* ccol, const double* cval) {
+    const int r0 = k * s;
+    for (int m = 0; m < nr; ++m) {
+      const int rr = g + m * G;
+      const int64_t cb = (pbase + r0 + rr) * adsd::NCPL;
+      double x = D[rr * s + j];
 #pragma unroll
-        for (int q = 0; q < adsd::NCPL; ++q) {
-          const int cc = ccol[cb + q];
-          if (cc >= 0) x -= cval[cb + q] * Pp[cc * s + j];
-        }
-        D[rr * s + j] = x;
+      for (int q = 0; q < adsd::NCPL; ++q) {
+        const int cc = ccol[cb + q];
+        if (cc >= 0) x -= cval[cb + q] * Pp[cc * s + j];
       }
+      D[rr * s + j] = x;
     }
-    // own elements into registers; publish pivot row/column 0
+    __syncthreads();
+  }
+
+  // D <- D^{-1} (Gauss-Jordan without pivoting, registers, one barrier per pivot)
+  __device__ void invert() {
 #pragma unroll
     for (int m = 0; m < FMR; ++m) {
       if (m < nr) {
@@ -244,34 +285,57 @@ k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval
       }
     }
     __syncthreads();
-    // Gauss-Jordan inversion, no pivoting, one barrier per pivot
+    int gn = 0, mn = 0;  // owner of row p + 1: group gn, slot mn
     for (int p = 0; p < s; ++p) {
       const double* rw = rowb + (p & 1) * s;
       const double* cl = colb + (p & 1) * s;
       double* rwn = rowb + ((p + 1) & 1) * s;
       double* cln = colb + ((p + 1) & 1) * s;
+      // all LDS reads of the step first, then the arithmetic
       double piv = rw[p];
+      const double rwj = rw[j];
+      double cvs[FMR];
+#pragma unroll
+      for (int m = 0; m < FMR; ++m) cvs[m] = cl[m < nr ? g + m * G : 0];
       if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
-        if (t == 0) atomicMax(bad_pivot, i + 1);
+        if (t == 0) atomicMax(a.bad_pivot, i + 1);
         piv = 1.0;
       }
-      const double inv = 1.0 / piv;
-      const double rj = rw[j] * inv;
+      // 1 / pivot: hardware reciprocal refined by two Newton steps
+      double inv = __builtin_amdgcn_rcp(piv);
+      inv = inv * (2.0 - piv * inv);
+      inv = inv * (2.0 - piv * inv);
+      const double rj = rwj * inv;
+      const bool jc = j == p;
+      // v - c_r * (row p / pivot) everywhere; row p takes the scaled row (the
+      // pivot itself 1 / pivot); column p is fixed up below
+      const double rowv = jc ? inv : rj;
 #pragma unroll
       for (int m = 0; m < FMR; ++m) {
-        if (m < nr) {
-          const int rr = g + m * G;
-          double x;
-          if (rr == p)
-            x = (j == p) ? inv : rj;
-          else if (j == p)
-            x = -cl[rr] * inv;
-          else
-            x = v[m] - cl[rr] * rj;
-          v[m] = x;
-          if (rr == p + 1) rwn[j] = x;
-          if (j == p + 1) cln[rr] = x;
+        const double x = v[m] - cvs[m] * rj;
+        v[m] = (g + m * G == p) ? rowv : x;
+      }
+      if (jc) {
+#pragma unroll
+        for (int m = 0; m < FMR; ++m)
+          if (g + m * G != p) v[m] = -cvs[m] * inv;
+      }
+      const int pn = p + 1;
+      if (++gn == G) {
+        gn = 0;
+        ++mn;
+      }
+      if (pn < s) {
+        if (g == gn) {
+          double xr = v[0];
+#pragma unroll
+          for (int m = 1; m < FMR; ++m) xr = (m == mn) ? v[m] : xr;
+          rwn[j] = xr;
         }
+        if (j == pn)
+#pragma unroll
+          for (int m = 0; m < FMR; ++m)
+            if (m < nr) cln[g + m * G] = v[m];
       }
       __syncthreads();
     }
@@ -279,24 +343,78 @@ k_block_factor_fast(const int64_t* lrow, const int32_t* lcol, const double* lval
     for (int m = 0; m < FMR; ++m)
       if (m < nr) D[(g + m * G) * s + j] = v[m];
     __syncthreads();
-    FT* Gt = F + (int64_t)k * 2 * TS;
-    store_tile(Gt, D, s, V);
-    if (k + 1 < K) {  // P_k = G_k A_k,k+1 (by columns of block k+1)
-      for (int e = t; e < ss; e += T) {
-        const int cp = e / s, rho = e - cp * s;
-        const int64_t ub = (pbase + r0 + s + cp) * adsd::NCPL;
-        double x = 0.0;
-#pragma unroll
-        for (int q = 0; q < adsd::NCPL; ++q) {
-          const int rr = urow[ub + q];
-          if (rr >= 0) x += D[rho * s + rr] * uval[ub + q];
-        }
-        Pp[rho * s + cp] = x;
-      }
-      __syncthreads();
-      store_tile(Gt + TS, Pp, s, V);
-    }
   }
+
+  // Pp[rho][c'] = sum_m D[rho][row_m] val_m over the column list of block kc
+  // (D holds G_k; the list entries are rows of block k)
+  __device__ void next_tile(int kc, const int32_t* crow, const double* cval) {
+    const int ss = s * s;
+    for (int e = t; e < ss; e += blockDim.x) {
+      const int cp = e / s, rho = e - cp * s;
+      const int64_t ub = (pbase + (int64_t)kc * s + cp) * adsd::NCPL;
+      double x = 0.0;
+#pragma unroll
+      for (int q = 0; q < adsd::NCPL; ++q) {
+        const int rr = crow[ub + q];
+        if (rr >= 0) x += D[rho * s + rr] * cval[ub + q];
+      }
+      Pp[rho * s + cp] = x;
+    }
+    __syncthreads();
+  }
+};
+
+template <class FT, bool USE_LDS, int FMR>
+__global__ void __launch_bounds__(1024) k_factor_chain(FacArgs a, FT* facA, FT* facT) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x, splitting = blockIdx.y, half = blockIdx.z;
+  double* base = USE_LDS ? lds
+                         : a.gscr + (((int64_t)splitting * gridDim.x + i) * 2 + half) * a.gscr_stride;
+  BlockFac<FT, FMR> B(a, i, splitting, base);
+  const int s = B.s, K = B.K, M = K / 2;
+  const int k0 = half ? K - 1 : 0, dk = half ? -1 : 1, nsteps = half ? K - 1 - M : M;
+  const int32_t* schur_col = half ? a.rcpl_col : a.cpl_col;
+  const double* schur_val = half ? a.rcpl_val : a.cpl_val;
+  const int32_t* nxt_row = half ? a.lcpl_row : a.ucpl_row;
+  const double* nxt_val = half ? a.lcpl_val : a.ucpl_val;
+  FT* F = (splitting ? facT : facA) + a.fac_off[i];
+  constexpr int V = adsd::TileV<FT>::V;
+  for (int q = 0; q < nsteps; ++q) {
+    const int k = k0 + q * dk;
+    B.assemble(k);
+    if (q > 0) B.schur(k, schur_col, schur_val);
+    B.invert();
+    FT* Gt = F + (int64_t)k * 2 * B.TS;
+    store_tile(Gt, B.D, s, V);
+    B.next_tile(k + dk, nxt_row, nxt_val);
+    store_tile(Gt + B.TS, B.Pp, s, V);
+  }
+  if (nsteps > 0) {  // the tile next to the middle block, in FP64
+    double* mid = a.mid + (((int64_t)splitting * gridDim.x + i) * 2 + half) * a.mid_stride;
+    for (int e = threadIdx.x; e < s * s; e += blockDim.x) mid[e] = B.Pp[e];
+  }
+}
+
+template <class FT, bool USE_LDS, int FMR>
+__global__ void __launch_bounds__(1024) k_factor_mid(FacArgs a, FT* facA, FT* facT) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x, splitting = blockIdx.y;
+  double* base = USE_LDS ? lds : a.gscr + ((int64_t)splitting * gridDim.x + i) * 2 * a.gscr_stride;
+  BlockFac<FT, FMR> B(a, i, splitting, base);
+  const int s = B.s, K = B.K, M = K / 2;
+  B.assemble(M);
+  for (int half = 0; half < 2; ++half) {
+    if (half == 0 ? M == 0 : M + 1 > K - 1) continue;
+    const double* mid = a.mid + (((int64_t)splitting * gridDim.x + i) * 2 + half) * a.mid_stride;
+    for (int e = threadIdx.x; e < s * s; e += blockDim.x) B.Pp[e] = mid[e];
+    __syncthreads();
+    B.schur(M, half ? a.rcpl_col : a.cpl_col, half ? a.rcpl_val : a.cpl_val);
+  }
+  B.invert();
+  FT* F = (splitting ? facT : facA) + a.fac_off[i];
+  FT* Gt = F + (int64_t)M * 2 * B.TS;
+  store_tile(Gt, B.D, s, adsd::TileV<FT>::V);
+  for (int64_t e = threadIdx.x; e < B.TS; e += blockDim.x) adsd::st_fac(Gt + B.TS, e, 0.0);
 }
 
 template <class FT>
@@ -307,26 +425,61 @@ static void factor_fast(Ctx& c, bool both) {
   FT* ft = both ? c.mem.alloc<FT>(c.fac_elems) : nullptr;
   c.facA = fa;
   c.facT = ft;
+  const int nmat = both ? 2 : 1;
   int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
   size_t need = ((size_t)2 * smax * smax + 4 * smax) * sizeof(double);
-  int use_lds = need <= 150 * 1024;
-  int64_t stride = (int64_t)2 * smax * smax + 4 * smax;
-  double* gscr = use_lds ? nullptr : c.mem.alloc<double>((size_t)stride * nsub * 2);
-  int32_t* bad = c.mem.alloc<int32_t>(1);
-  ADS_HIP(hipMemsetAsync(bad, 0, 4, st));
+  const bool use_lds = need <= 150 * 1024;
+  FacArgs a{};
+  a.lrow = c.lptr_off;
+  a.lcol = c.lcol;
+  a.lval = c.lval;
+  a.lsum = c.lsum;
+  a.om_int = c.om_int;
+  a.om_off = c.om_off;
+  a.ni = c.ni;
+  a.bs = c.bs;
+  a.nb = c.nb;
+  a.fac_off = c.fac_off;
+  a.kdim = c.kdim;
+  a.pad_off = c.pad_off;
+  a.cpl_col = c.cpl_col;
+  a.cpl_val = c.cpl_val;
+  a.rcpl_col = c.rcpl_col;
+  a.rcpl_val = c.rcpl_val;
+  a.ucpl_row = c.ucpl_row;
+  a.ucpl_val = c.ucpl_val;
+  a.lcpl_row = c.lcpl_row;
+  a.lcpl_val = c.lcpl_val;
+  a.gscr_stride = (int64_t)2 * smax * smax + 4 * smax;
+  a.gscr = use_lds ? nullptr : c.mem.alloc<double>((size_t)a.gscr_stride * nsub * nmat * 2);
+  a.mid_stride = (int64_t)smax * smax;
+  a.mid = c.mem.alloc<double>((size_t)a.mid_stride * nsub * nmat * 2);
+  a.bad_pivot = c.mem.alloc<int32_t>(1);
+  ADS_HIP(hipMemsetAsync(a.bad_pivot, 0, 4, st));
+  int rmax = 1;
+  for (int b : c.h_bs) rmax = std::max(rmax, adsd::factor_rows(b));
+  auto launch = [&](auto lds_tag, auto fmr_tag) {
+    constexpr bool L = decltype(lds_tag)::value;
+    constexpr int R = decltype(fmr_tag)::value;
+    ADS_LAUNCH((k_factor_chain<FT, L, R>), dim3(nsub, nmat, 2), dim3(1024), L ? need : 0, st, a, fa,
+               ft);
+    ADS_LAUNCH((k_factor_mid<FT, L, R>), dim3(nsub, nmat), dim3(1024), L ? need : 0, st, a, fa, ft);
+  };
+  auto by_rows = [&](auto lds_tag) {
+    if (rmax <= 2) launch(lds_tag, std::integral_constant<int, 2>());
+    else if (rmax <= 3) launch(lds_tag, std::integral_constant<int, 3>());
+    else if (rmax <= 5) launch(lds_tag, std::integral_constant<int, 5>());
+    else if (rmax <= 7) launch(lds_tag, std::integral_constant<int, 7>());
+    else launch(lds_tag, std::integral_constant<int, 9>());
+  };
   if (use_lds)
-    ADS_LAUNCH((k_block_factor_fast<FT, true>), dim3(nsub, both ? 2 : 1), dim3(1024), need, st,
-               c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
-               c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, fa, ft, gscr, stride,
-               bad);
+    by_rows(std::true_type());
   else
-    ADS_LAUNCH((k_block_factor_fast<FT, false>), dim3(nsub, both ? 2 : 1), dim3(1024), 0, st,
-               c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
-               c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, fa, ft, gscr, stride,
-               bad);
+    by_rows(std::false_type());
   std::vector<int32_t> hb;
-  download(hb, bad, 1, st);
-  if (gscr) c.mem.release(gscr);
+  download(hb, a.bad_pivot, 1, st);
+  if (a.gscr) c.mem.release(a.gscr);
+  c.mem.release(a.mid);
   if (hb[0])
     fail(ADS_ERR_SINGULAR, "zero pivot in the local matrix or splitting of subdomain " +
                                std::to_string(hb[0] - 1));
@@ -373,9 +526,7 @@ void factor_local(Ctx& c) {
   const bool need_split = c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0;
   size_t esz = c.prec == ADS_PREC_FP64 ? 8 : (c.prec == ADS_PREC_FP32 ? 4 : 2);
   c.factor_bytes = (int64_t)(c.fac_elems * esz);
-  bool fast = c.cpl_ok;
-  for (int i = 0; i < nsub; ++i) fast = fast && factor_fast_ok(c.h_bs[i]);
-  if (fast) {
+  if (c.solve_fast) {  // two-ended layout, read by the fast solves
     switch (c.prec) {
       case ADS_PREC_FP64: factor_fast<double>(c, need_split); break;
       case ADS_PREC_FP32: factor_fast<float>(c, need_split); break;

@@ -77,7 +77,7 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, Arena& mem, 
 }
 
 // ---------------------------------------------------------------------------
-// transpose pattern: graph of A^T (neighbour order inside a row is irrelevant)
+// transpose pattern: graph of A^T, rows of each column ascending
 // ---------------------------------------------------------------------------
 __global__ void k_count_cols(const int32_t* col, int64_t nnz, int32_t* cnt) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,6 +95,20 @@ __global__ void k_fill_transpose(const int32_t* rowptr, const int32_t* col, int6
   }
 }
 
+// rows of every column in ascending order (the fill above is unordered)
+__global__ void k_sort_transpose(const int32_t* tptr, int64_t n, int32_t* tcol) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int32_t* v = tcol + tptr[c];
+  const int m = tptr[c + 1] - tptr[c];
+  for (int a = 1; a < m; ++a)
+    for (int b = a; b > 0 && v[b - 1] > v[b]; --b) {
+      const int32_t x = v[b];
+      v[b] = v[b - 1];
+      v[b - 1] = x;
+    }
+}
+
 void transpose_pattern(Arena& mem, const int32_t* rowptr, const int32_t* col, int64_t n,
                        int64_t nnz, int32_t** tptr, int32_t** tcol, hipStream_t s) {
   int32_t* cnt = mem.alloc<int32_t>(n + 1);
@@ -107,6 +121,7 @@ void transpose_pattern(Arena& mem, const int32_t* rowptr, const int32_t* col, in
   *tcol = mem.alloc<int32_t>(nnz);
   ADS_LAUNCH(k_fill_transpose, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rowptr, col, n,
              *tptr, cnt, *tcol);
+  ADS_LAUNCH(k_sort_transpose, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, *tptr, n, *tcol);
 }
 
 // ---------------------------------------------------------------------------

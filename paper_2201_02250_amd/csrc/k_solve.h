@@ -33,6 +33,16 @@ __host__ __device__ inline int solve_chunk(int s, int T, int V) {
   return V * ((chunk + V - 1) / V);
 }
 
+// rows per thread of the register-resident factorization for block size s
+static constexpr int FMR_MAX = 9;
+__host__ __device__ inline int factor_rows(int s) {
+  const int G = 1024 / s;
+  return (s + G - 1) / G;
+}
+__host__ __device__ inline bool factor_fast_ok(int s) {
+  return s >= 1 && s <= 1024 && factor_rows(s) <= FMR_MAX;
+}
+
 // fast path applies when every block size s satisfies this (and the couplings fit)
 __host__ __device__ inline bool solve_fast_ok(int s, int T = SOLVE_T, int P = 1, int V = 8) {
   if (s < 1 || s > T || (P == 1 ? 4 : 1) * s * P > T) return false;
@@ -95,17 +105,23 @@ __device__ __forceinline__ void tile_load_vec<__hip_bfloat16>(const __hip_bfloat
   }
 }
 
-// In-place solve.  ccol/cval: couplings of this subdomain's padded rows
-// (row-major, NCPL per row).  X: padded vectors (global or LDS, see LDSX).
-// The LDS work vectors are row-major [row * P + column] so that the column
-// index is an immediate offset of the LDS instruction.
-// dummy: a private scratch slot of this thread (global vector only): threads
+// One chain of the two-ended block solve (fast path).  Steps q = 0 ..
+// nsteps-1 visit blocks k = k0 + q dk:
+//   FWD:  h_k = T0_k (Xin_k - C_k h_prev)   (C: row coupling list of block k
+//                                            towards block k - dk)
+//   !FWD: x_k = Xin_k - T1_k x_prev          (x_prev in hbuf on entry)
+// and write the result to Xout (FWD may run in place).  T0_k / T1_k are the
+// two tiles of block k (see the factorization).  ccol/cval: couplings of this
+// subdomain's padded rows, NCPL per row.  The LDS work vectors are row-major
+// [row * P + column] so that the column index is an immediate offset of the
+// LDS instruction.  dummy: a private scratch slot of this thread: threads
 // that own no vector entry store there, so every store is unconditional.
 // Requires LPE * s * pc <= blockDim.x (LPE lanes per entry in phase C).
-template <class FT, int P, int D, bool LDSX>
-__device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int32_t* __restrict__ ccol,
-                            const double* __restrict__ cval, double* X, int64_t ldx, int pc,
-                            double* lds, double* dummy) {
+template <class FT, int P, int D, bool FWD>
+__device__ __forceinline__ void block_chain(const FT* __restrict__ fac, int s, int k0, int dk, int nsteps,
+                            const int32_t* __restrict__ ccol, const double* __restrict__ cval,
+                            const double* Xin, double* Xout, int64_t ldx, int pc, double* lds,
+                            double* dummy) {
   using RT = typename TileReg<FT>::T;
   constexpr int V = TileV<FT>::V;         // elements per 16-byte vector
   constexpr int NV = SOLVE_CH / V;        // vectors per thread per tile
@@ -117,12 +133,16 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
   const int c0 = g * chV;
   const int clen = (g < G) ? max(0, min(chV, s - c0)) : 0;
   const int64_t ss = tile_size(s, V);     // tile stride
-  const int NT = 2 * K - 1;
   const bool pa = t < s * pc;  // phase-A owner of (prr, pj)
   const int prr = t % s, pj = t / s;
   double* ybuf = lds;
   double* hbuf = ybuf + (int64_t)s * P;
   double* part = hbuf + (int64_t)s * P;
+  if (nsteps <= 0) return;
+  if (FWD) {  // no predecessor: the couplings of the first block are empty
+    for (int e = t; e < s * P; e += T) hbuf[e] = 0.0;
+    __syncthreads();
+  }
 
   static_assert(D % 2 == 0, "the tile ring depth must be even");
   RT treg[D][SOLVE_CH];
@@ -134,11 +154,9 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
   // All prefetch loads are unconditional with clamped, in-bounds addresses:
   // branch-free issue keeps the compiler's wait counts exact, so a step only
   // waits for its own tile, not for the tiles prefetched behind it.
-  auto blk = [&](int q) { return q < K ? q : 2 * K - 2 - q; };
+  auto blk = [&](int q) { return k0 + min(q, nsteps - 1) * dk; };
   auto issue_tile = [&](int q, int d) {
-    const int qq = min(q, NT - 1);
-    const int k = blk(qq);
-    const FT* M = fac + (int64_t)k * 2 * ss + (qq < K ? 0 : ss);
+    const FT* M = fac + (int64_t)blk(q) * 2 * ss + (FWD ? 0 : ss);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int qi = min(c0 / V + v, nq - 1);
@@ -146,10 +164,9 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
     }
   };
   auto issue_aux = [&](int q, int e) {
-    if (!pa) return;  // only the phase-A owners need couplings and inputs
-    const int qq = min(q, NT - 1);
-    const int row = blk(qq) * s + prr;
-    if (!LDSX) xreg[e] = X[row + pjc * ldx];
+    if (!FWD || !pa) return;  // only the forward phase-A owners need couplings and inputs
+    const int row = blk(q) * s + prr;
+    xreg[e] = Xin[row + pjc * ldx];
 #pragma unroll
     for (int m = 0; m < NCPL; ++m) {
       creg_c[e][m] = ccol[(int64_t)row * NCPL + m];
@@ -157,24 +174,22 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
     }
   };
 
-  // one step of the sequence with its tile in slot d
-  // phase-C mapping: LPE consecutive lanes per output entry (e = t / LPE), each
-  // summing a strided share of the G partials, combined by shuffles
+  // one step with its tile in slot d; phase-C mapping: LPE consecutive lanes
+  // per output entry (e = t / LPE), each summing a strided share of the G
+  // partials, combined by shuffles
   constexpr int LPE = (P == 1) ? 4 : 1;
   const int ce = t / LPE, cq = t % LPE;
   const bool cown = ce < s * pc;
   const int crr = ce % s, cj = min(ce / s, pc - 1);
   auto step = [&](int q, int d) {
     const int e = d & 1;  // aux slot (q and d have the same parity: q0 is a multiple of D)
-    const int k = blk(q);
-    const int r0 = k * s;
-    const bool fwd = q < K;
-    // h_k for the backward sweep, read by the phase-C owner (unconditional)
-    double hk = LDSX ? 0.0 : X[r0 + crr + (int64_t)cj * ldx];
+    const int r0 = blk(q) * s;
+    // backward: Xin_k for phase C, read by its owner (unconditional)
+    double hk = FWD ? 0.0 : Xin[r0 + crr + (int64_t)cj * ldx];
     // phase A: the vector the tile multiplies (branch-free coupling reads)
     if (pa) {
-      if (fwd) {
-        double y = LDSX ? X[r0 + prr + pj * ldx] : xreg[e];
+      if (FWD) {
+        double y = xreg[e];
 #pragma unroll
         for (int m = 0; m < NCPL; ++m) {
           const int cc = creg_c[e][m];
@@ -183,7 +198,7 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
         }
         ybuf[prr * P + pj] = y;
       } else {
-        ybuf[prr * P + pj] = hbuf[prr * P + pj];  // x_{k+1}
+        ybuf[prr * P + pj] = hbuf[prr * P + pj];  // x_prev
       }
     }
     __syncthreads();
@@ -218,15 +233,11 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
       v += part[((int64_t)gg * s + crr) * P + cj];
     if (LPE >= 2) v += __shfl_xor(v, 1, 64);
     if (LPE >= 4) v += __shfl_xor(v, 2, 64);
-    if (!fwd) v = (LDSX ? X[r0 + crr + (int64_t)cj * ldx] : hk) - v;
+    if (!FWD) v = hk - v;
     const bool wr = cown && cq == 0;
     if (wr) hbuf[crr * P + cj] = v;
-    if (LDSX) {
-      if (wr) X[r0 + crr + (int64_t)cj * ldx] = v;
-    } else {
-      double* dst = wr ? X + (r0 + crr + (int64_t)cj * ldx) : dummy;
-      *dst = v;
-    }
+    double* dst = wr ? Xout + (r0 + crr + (int64_t)cj * ldx) : dummy;
+    *dst = v;
     __syncthreads();
   };
 
@@ -235,7 +246,7 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
   issue_aux(0, 0);
   issue_aux(1, 1);
   // main part: whole groups of D steps, no per-step guard (exact wait counts)
-  const int NTmain = NT - NT % D;
+  const int NTmain = nsteps - nsteps % D;
   for (int q0 = 0; q0 < NTmain; q0 += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) step(q0 + d, d);
@@ -243,7 +254,62 @@ __device__ void block_solve(const FT* __restrict__ fac, int s, int K, const int3
   // tail
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    if (NTmain + d < NT) step(NTmain + d, d);
+    if (NTmain + d < nsteps) step(NTmain + d, d);
+}
+
+// The middle block of the two-ended solve: x_M = T0_M (Xin_M - L h_{M-1} -
+// U g_{M+1}) with L, U the row couplings of block M towards blocks M - 1 and
+// M + 1 (lcol/lval, ucol/uval), all read from Xin.  The result goes to hbuf
+// (the x_prev of both backward chains) and, if Xout is given, to Xout.
+template <class FT, int P>
+__device__ __forceinline__ void block_mid(const FT* __restrict__ fac, int s, int M, int K,
+                          const int32_t* __restrict__ lcol, const double* __restrict__ lval,
+                          const int32_t* __restrict__ ucol, const double* __restrict__ uval,
+                          const double* Xin, double* Xout, int64_t ldx, int pc, double* lds) {
+  constexpr int V = TileV<FT>::V;
+  const int t = threadIdx.x, T = blockDim.x;
+  double* ybuf = lds;
+  double* hbuf = ybuf + (int64_t)s * P;
+  double* part = hbuf + (int64_t)s * P;
+  const int r0 = M * s;
+  for (int e = t; e < s * pc; e += T) {
+    const int rr = e % s, j = e / s;
+    const int64_t row = r0 + rr;
+    double y = Xin[row + j * ldx];
+#pragma unroll
+    for (int m = 0; m < NCPL; ++m) {
+      const int cl = lcol[row * NCPL + m], cu = ucol[row * NCPL + m];
+      if (cl >= 0) y -= lval[row * NCPL + m] * Xin[r0 - s + cl + j * ldx];
+      if (cu >= 0) y -= uval[row * NCPL + m] * Xin[r0 + s + cu + j * ldx];
+    }
+    ybuf[rr * P + j] = y;
+  }
+  __syncthreads();
+  const FT* Mt = fac + (int64_t)M * 2 * tile_size(s, V);
+  const int G = T / s, chunk = (s + G - 1) / G;
+  const int r = t % s, g = t / s;
+  if (g < G) {
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
+    const int c1 = min(s, (g + 1) * chunk);
+    for (int c = g * chunk; c < c1; ++c) {
+      const double m = ld_fac(Mt, tile_at(r, c, s, V));
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] += m * ybuf[c * P + j];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) part[((int64_t)g * s + r) * P + j] = acc[j];
+  }
+  __syncthreads();
+  for (int e = t; e < s * pc; e += T) {
+    const int rr = e % s, j = e / s;
+    double v = 0.0;
+    for (int gg = 0; gg < G; ++gg) v += part[((int64_t)gg * s + rr) * P + j];
+    hbuf[rr * P + j] = v;
+    if (Xout) Xout[r0 + rr + j * ldx] = v;
+  }
+  __syncthreads();
 }
 
 }  // namespace adsd
