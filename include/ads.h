@@ -90,7 +90,9 @@ typedef struct {
   int32_t warm_start;     /* 0: none; 1: learned warm start (initial eigensolver block
                              from the graph network; exact eigensolve still decides) */
   double eig_tol;         /* relative residual of the selected invariant subspace
-                             (0 -> 1e-10 in FP64, 1e-6 otherwise)                    */
+                             (0 -> 1e-10 with FP64 factors; 1e-3 with FP32/BF16
+                             factors, where the coarse space only needs the
+                             accuracy of the factors it is built from)             */
   int32_t eig_max_sweeps; /* 0 -> 400                                                 */
   const char* gnn_weights_path; /* weights file for warm_start = 1 (NULL otherwise)  */
   int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream

@@ -250,6 +250,124 @@ k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int
   for (int i = t; i < n; i += T) so[i] = src[i];
 }
 
+// Register-resident panel (panel width 32, systems of order <= 32 * MR):
+// thread t owns column j = t % 32 for the rows g, g + 32, g + 64, ... of
+// row group g = t / 32.  Rows are never moved: the interchanges are kept as
+// a logical <-> physical row permutation in LDS, and the pivot column of a
+// row comes from the lanes of the same row group by a shuffle.  Two barriers
+// per pivot step; the result S is written in logical row order, so it is the
+// same as the LDS panel kernel's.
+template <int MR>
+__global__ void __launch_bounds__(GJ_T)
+k_gj_panel_reg(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+               double* Sbuf, int32_t* src_all, int32_t* piv_all, int32_t* singular) {
+  extern __shared__ int gj_perm[];  // [2 n]: logical -> physical, physical -> logical
+  __shared__ double rowq[2][32];
+  __shared__ double pval[GJ_T / 64];
+  __shared__ int pidx[GJ_T / 64];
+  constexpr int NB = 32;
+  const int sy = blockIdx.x;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  if (k0 >= n) return;
+  const int kb = min(NB, n - k0);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int j = t & (NB - 1), g = t >> 5, hb = lane & 32;
+  int* lperm = gj_perm;
+  int* lpos = gj_perm + n;
+  const double* A = Ain + E_off[sy];
+  double v[MR];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int i = g + NB * m;
+    v[m] = (i < n && j < kb) ? A[(int64_t)i * n + k0 + j] : 0.0;
+  }
+  for (int i = t; i < n; i += GJ_T) {
+    lperm[i] = i;
+    lpos[i] = i;
+  }
+  // candidates of the first pivot column
+  double bv = -1.0;
+  int bi = n;
+  if (j == 0)
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int i = g + NB * m;
+      if (i >= k0 && i < n) gj_better(bv, bi, fabs(v[m]), i);
+    }
+  for (int l = 0; l < kb; ++l) {
+    const int k = k0 + l;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      gj_better(bv, bi, ov, oi);
+    }
+    if (lane == 0) {
+      pval[wv] = bv;
+      pidx[wv] = bi;
+    }
+    __syncthreads();
+    bv = -1.0;
+    bi = n;
+    for (int w = 0; w < GJ_T / 64; ++w) gj_better(bv, bi, pval[w], pidx[w]);
+    int q = bi;  // physical pivot row
+    if (!(bv > 0.0) || q >= n) {
+      if (t == 0) atomicMax(singular, sy + 1);
+      q = lperm[k];
+    }
+    // publish the pivot row; record the interchange (logical k <-> lpos[q])
+    const int gq = q & (NB - 1), mq = q >> 5;
+    if (g == gq) {
+      double x = v[0];
+#pragma unroll
+      for (int m = 1; m < MR; ++m) x = (m == mq) ? v[m] : x;
+      rowq[l & 1][j] = x;
+    }
+    __syncthreads();
+    if (t == 0) {
+      const int p = lpos[q], a = lperm[k];
+      piv_all[sys_coff[sy] + k] = p;
+      lperm[k] = q;
+      lperm[p] = a;
+      lpos[q] = k;
+      lpos[a] = p;
+    }
+    const double piv = rowq[l & 1][l];
+    double inv = __builtin_amdgcn_rcp(piv);
+    inv = inv * (2.0 - piv * inv);
+    inv = inv * (2.0 - piv * inv);
+    if (piv == 0.0) inv = 1.0;
+    const double rj = rowq[l & 1][j] * inv;
+    const bool jc = j == l;
+    bv = -1.0;
+    bi = n;
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int i = g + NB * m;
+      const double f = __shfl(v[m], hb + l, 64);  // this row's pivot-column entry
+      const double x = (i == q) ? (jc ? inv : rj) : (jc ? -f * inv : v[m] - f * rj);
+      v[m] = x;
+    }
+    // candidates of the next pivot column: rows not yet used as pivots
+    // (their logical position after this step is > k)
+    __syncthreads();  // lpos updated by thread 0
+    if (j == l + 1)
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int i = g + NB * m;
+        if (i < n && lpos[i] > k) gj_better(bv, bi, fabs(v[m]), i);
+      }
+  }
+  __syncthreads();
+  double* S = Sbuf + (int64_t)NB * sys_coff[sy];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int i = g + NB * m;
+    if (i < n) S[(int64_t)lpos[i] * NB + j] = v[m];
+  }
+  int32_t* so = src_all + sys_coff[sy];
+  for (int i = t; i < n; i += GJ_T) so[i] = lperm[i];
+}
+
 // out = transform of in for the column block [k0, k0 + kb) (see above);
 // systems whose order is <= k0 are copied unchanged
 __global__ void __launch_bounds__(GJ_UT)
@@ -373,7 +491,9 @@ void assemble_coarse(Ctx& c) {
   std::vector<int32_t> hf;
   download(hf, flag, 1, st);
   if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
-  const int nb = gj_panel_width(maxs);
+  // register-resident panels (width 32) up to order 32 * 32, else LDS panels
+  const bool reg = maxs <= 32 * 32;
+  const int nb = reg ? 32 : gj_panel_width(maxs);
   if (nb == 0)
     fail(ADS_ERR_UNSUPPORTED, "coarse system of order " + std::to_string(maxs) +
                                   " exceeds the dense inverse limit");
@@ -387,8 +507,15 @@ void assemble_coarse(Ctx& c) {
   const unsigned tiles = (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
-    ADS_LAUNCH(k_gj_panel, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], c.E_off, c.sys_coff,
-               (int)k0, nb, S, src, piv, flag + 1);
+    if (!reg)
+      ADS_LAUNCH(k_gj_panel, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], c.E_off, c.sys_coff,
+                 (int)k0, nb, S, src, piv, flag + 1);
+    else if (maxs <= 32 * 17)
+      ADS_LAUNCH(k_gj_panel_reg<17>, dim3(nsys), dim3(GJ_T), (size_t)maxs * 8, st, bufs[cur],
+                 c.E_off, c.sys_coff, (int)k0, S, src, piv, flag + 1);
+    else
+      ADS_LAUNCH(k_gj_panel_reg<32>, dim3(nsys), dim3(GJ_T), (size_t)maxs * 8, st, bufs[cur],
+                 c.E_off, c.sys_coff, (int)k0, S, src, piv, flag + 1);
     ADS_LAUNCH(k_gj_update, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur], bufs[1 - cur],
                c.E_off, c.sys_coff, (int)k0, nb, S, src);
     cur = 1 - cur;

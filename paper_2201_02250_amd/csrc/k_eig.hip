@@ -1760,7 +1760,7 @@ void eigensolve(Ctx& c) {
   a.p = p;
   a.nev = nev;
   a.tau = c.opt.tau;
-  a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-6);
+  a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
   ADS_HIP(hipMemsetAsync(a.done, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.sweeps, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.msel, 0, nsub * 4, st));
