@@ -143,7 +143,8 @@ typedef struct {
  * graph of A + A^T and the partition `part` (host int32[n], values in
  * [0, nparts), every part non-empty), local block splittings (Definition 1),
  * local factorizations, local eigenproblems (eq. 5) and coarse space (eq. 6),
- * coarse operator E = Z^T A Z and its LU with partial pivoting.
+ * coarse operator E = Z^T A Z and its exact inverse (Gauss-Jordan elimination
+ * with partial pivoting).
  * *out receives a new context (NULL on error). */
 int ads_setup(const ads_csr* A, const int32_t* part, int32_t nparts, const ads_options* opts,
               void* hip_stream, ads_ctx** out);
@@ -196,6 +197,14 @@ int ads_export_coarse(const ads_ctx* ctx, double* W, int64_t* W_off, double* lam
  * [nparts], distinct vertices; part_out: host int32[n].  Runs on the GPU. */
 int ads_partition_bfs(const ads_csr* A, int32_t nparts, const int32_t* seeds, int32_t* part_out,
                       void* hip_stream);
+
+/* hipGraph replay (default on; off while ads_options.profile is set): the
+ * kernels of one apply, and of one Arnoldi step in ads_solve, are captured
+ * once and replayed while the buffers and nrhs stay the same.  Graphs run on
+ * a stream owned by the context, ordered after the work already queued on the
+ * caller's stream, which is ordered after them in turn.  enable = 0 launches
+ * every kernel directly on the caller's stream (same results, bit for bit). */
+int ads_set_graphs(ads_ctx* ctx, int32_t enable);
 
 /* Frees the context and its device memory (NULL is accepted). */
 int ads_destroy(ads_ctx* ctx);

@@ -27,7 +27,7 @@ ADS_PREC_FP64, ADS_PREC_FP32, ADS_PREC_BF16 = 0, 1, 2
 # every symbol declared in include/ads.h
 SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_solve", "ads_get_info",
            "ads_export_maps", "ads_export_splitting", "ads_export_coarse", "ads_partition_bfs",
-           "ads_destroy", "ads_status_string", "ads_last_error"]
+           "ads_set_graphs", "ads_destroy", "ads_status_string", "ads_last_error"]
 
 
 class ads_csr(C.Structure):
@@ -97,6 +97,7 @@ def lib():
         L.ads_export_splitting.argtypes = [P, P]
         L.ads_export_coarse.argtypes = [P, P, P, P, P]
         L.ads_partition_bfs.argtypes = [C.POINTER(ads_csr), I32, P, P, P]
+        L.ads_set_graphs.argtypes = [P, I32]
         L.ads_destroy.argtypes = [P]
         L.ads_status_string.argtypes = [C.c_int]
         L.ads_status_string.restype = C.c_char_p
@@ -250,6 +251,10 @@ def ads_partition_bfs(A, seeds, stream=None):
     return out
 
 
+def ads_set_graphs(ctx, enable):
+    _check(lib().ads_set_graphs(ctx, int(enable)))
+
+
 def ads_destroy(ctx):
     if ctx is not None and ctx.value:
         lib().ads_destroy(ctx)
@@ -297,6 +302,9 @@ class Context:
                    t_solve_ms=res.t_solve_ms)
         x = xx if b.dim() == 1 else xx.reshape(nrhs, self.n).t()
         return x, out
+
+    def set_graphs(self, enable):
+        ads_set_graphs(self.ctx, enable)
 
     def close(self):
         ads_destroy(self.ctx)

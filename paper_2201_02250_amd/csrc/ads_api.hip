@@ -328,7 +328,12 @@ int ads_apply(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, vo
     if (!ctx || !r_dev || !z_dev) fail(ADS_ERR_ARG, "null argument");
     if (nrhs < 1 || nrhs > 64) fail(ADS_ERR_ARG, "nrhs must be in [1, 64]");
     if (r_dev == z_dev) fail(ADS_ERR_ARG, "r and z must not alias");
-    apply_prec(*ctx->c, r_dev, z_dev, nrhs, (hipStream_t)hip_stream);
+    Ctx& c = *ctx->c;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (c.graphs_on())
+      on_own_stream(c, st, [&](hipStream_t ps) { apply_prec(c, r_dev, z_dev, nrhs, ps); });
+    else
+      apply_prec(c, r_dev, z_dev, nrhs, st);
     return ADS_OK;
   } catch (const Error& e) {
     return handle(e);
@@ -348,7 +353,14 @@ int ads_solve(ads_ctx* ctx, const double* b_dev, double* x_dev, int32_t nrhs,
     if (!(kopts->rtol >= 0.0)) fail(ADS_ERR_ARG, "rtol must be >= 0");
     if (b_dev == x_dev) fail(ADS_ERR_ARG, "b and x must not alias");
     if (res) std::memset(res, 0, sizeof(*res));
-    return gmres_solve(*ctx->c, b_dev, x_dev, nrhs, *kopts, res, (hipStream_t)hip_stream);
+    Ctx& c = *ctx->c;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (!c.graphs_on()) return gmres_solve(c, b_dev, x_dev, nrhs, *kopts, res, st);
+    int status = ADS_OK;
+    on_own_stream(c, st, [&](hipStream_t ps) {
+      status = gmres_solve(c, b_dev, x_dev, nrhs, *kopts, res, ps);
+    });
+    return status;
   } catch (const Error& e) {
     return handle(e);
   } catch (...) {
@@ -489,6 +501,22 @@ int ads_partition_bfs(const ads_csr* A, int32_t nparts, const int32_t* seeds, in
     return ADS_OK;
   } catch (const Error& e) {
     return handle(e);
+  }
+}
+
+int ads_set_graphs(ads_ctx* ctx, int32_t enable) {
+  try {
+    if (!ctx) fail(ADS_ERR_ARG, "null argument");
+    Ctx& c = *ctx->c;
+    if (c.priv) ADS_HIP(hipStreamSynchronize(c.priv));
+    c.drop_apply_graph();
+    c.use_graphs = enable != 0;
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  } catch (...) {
+    g_last_error = "unknown error";
+    return ADS_ERR_HIP;
   }
 }
 

@@ -128,13 +128,13 @@ struct Ctx {
   int32_t* tptr = nullptr;  // transpose pattern (graph of A^T)
   int32_t* tcol = nullptr;
   int32_t* part = nullptr;  // global subdomain id of each unknown
-  int32_t* ipos = nullptr;
+  int32_t* ipos = nullptr;  // position of each unknown inside its own Omega_Ii
   // per-subdomain window [wlo, whi) of the global index range containing
   // Omega_i; wpos[woff + v - wlo] = position of v in ascending Omega_i, or -1
   int64_t* wlo = nullptr;
   int64_t* whi = nullptr;
   int64_t* woff = nullptr;
-  int32_t* wpos = nullptr;  // position of each unknown inside its own Omega_Ii
+  int32_t* wpos = nullptr;
 
   // maps: omega in ascending global order ("sorted") and in [I, Gamma] order ("export")
   int64_t omega_total = 0;
@@ -219,6 +219,21 @@ struct Ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];
   double prof_ms[4] = {0};
   int64_t prof_n[4] = {0};
+  // hipGraph replay: the apply, and in ads_solve the Arnoldi step, are
+  // captured once and replayed while their arguments and stream are the same
+  bool use_graphs = true;
+  bool capturing = false;           // inside a capture: launch eagerly
+  hipStream_t priv = nullptr;       // the context's own stream (default priority)
+  hipEvent_t dep_ev = nullptr;      // orders priv against the caller's stream
+  hipGraphExec_t apply_exec = nullptr;
+  const double* ag_r = nullptr;
+  double* ag_z = nullptr;
+  int ag_nrhs = 0;
+  hipStream_t ag_st = nullptr;
+  hipStream_t own_stream();
+  void drop_apply_graph();
+  bool graphs_on() const { return use_graphs && !opt.profile; }
+
   void prof_resolve();
   ~Ctx();
   double t_setup_ms = 0;
@@ -234,6 +249,40 @@ void eigensolve(Ctx& c);
 void assemble_coarse(Ctx& c);
 void ensure_work(Ctx& c, int cols);
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);
+
+// Capture the launches of f on stream s (not the null stream) into an
+// executable graph.  The capture is ended on every exit path.
+template <class F>
+hipGraphExec_t capture_graph(hipStream_t s, F&& f) {
+  ADS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  try {
+    f();
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  ADS_HIP(hipStreamEndCapture(s, &g));
+  hipGraphExec_t e = nullptr;
+  const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  ADS_HIP(err);
+  return e;
+}
+
+// Runs f on the context's own stream ordered after the work already queued
+// on the caller's stream st, and orders st after it.
+template <class F>
+void on_own_stream(Ctx& c, hipStream_t st, F&& f) {
+  hipStream_t ps = c.own_stream();
+  ADS_HIP(hipEventRecord(c.dep_ev, st));
+  ADS_HIP(hipStreamWaitEvent(ps, c.dep_ev, 0));
+  f(ps);
+  ADS_HIP(hipEventRecord(c.dep_ev, ps));
+  ADS_HIP(hipStreamWaitEvent(st, c.dep_ev, 0));
+}
 int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_options& ko,
                 ads_ksp_result* res, hipStream_t s);
 void bfs_partition(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,

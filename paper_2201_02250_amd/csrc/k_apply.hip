@@ -249,6 +249,7 @@ k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict_
 
 void ensure_work(Ctx& c, int cols) {
   if (c.work_cols >= cols) return;
+  if (c.priv) ADS_HIP(hipStreamSynchronize(c.priv));  // the old workspace may be in use there
   if (c.work) c.mem.release(c.work);
   if (c.cvec) c.mem.release(c.cvec);
   if (c.qvec) c.mem.release(c.qvec);
@@ -364,6 +365,10 @@ void Ctx::prof_resolve() {
 }
 
 Ctx::~Ctx() {
+  if (priv) (void)hipStreamSynchronize(priv);
+  if (apply_exec) (void)hipGraphExecDestroy(apply_exec);
+  if (dep_ev) (void)hipEventDestroy(dep_ev);
+  if (priv) (void)hipStreamDestroy(priv);
   for (int k = 0; k < 4; ++k)
     for (auto& e : prof_ev[k]) {
       (void)hipEventDestroy(e.first);
@@ -371,8 +376,7 @@ Ctx::~Ctx() {
     }
 }
 
-void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
-  ensure_work(c, nrhs);
+static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
   ProfScope all(c, 3, s);
   const double* q = nullptr;
   if (c.n0 > 0) {
@@ -395,6 +399,50 @@ void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
     case ADS_PREC_FP32: local_dispatch<float>(c, r, q, z, nrhs, s); break;
     default: local_dispatch<__hip_bfloat16>(c, r, q, z, nrhs, s); break;
   }
+}
+
+hipStream_t Ctx::own_stream() {
+  if (!priv) {
+    ADS_HIP(hipStreamCreateWithFlags(&priv, hipStreamNonBlocking));
+    ADS_HIP(hipEventCreateWithFlags(&dep_ev, hipEventDisableTiming));
+  }
+  return priv;
+}
+
+void Ctx::drop_apply_graph() {
+  if (apply_exec) (void)hipGraphExecDestroy(apply_exec);
+  apply_exec = nullptr;
+  ag_r = nullptr;
+  ag_z = nullptr;
+  ag_nrhs = 0;
+  ag_st = nullptr;
+}
+
+// z = M^{-1} r on stream s: eager launches, or the replay of a captured graph
+// of them when graphs are on and s is not the null stream
+void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
+  if (c.work_cols < nrhs) c.drop_apply_graph();  // the workspace is reallocated
+  ensure_work(c, nrhs);
+  if (c.capturing || !c.graphs_on() || s == nullptr) {
+    apply_kernels(c, r, z, nrhs, s);
+    return;
+  }
+  if (!(c.apply_exec && c.ag_r == r && c.ag_z == z && c.ag_nrhs == nrhs && c.ag_st == s)) {
+    c.drop_apply_graph();
+    c.capturing = true;
+    try {
+      c.apply_exec = capture_graph(s, [&] { apply_kernels(c, r, z, nrhs, s); });
+    } catch (...) {
+      c.capturing = false;
+      throw;
+    }
+    c.capturing = false;
+    c.ag_r = r;
+    c.ag_z = z;
+    c.ag_nrhs = nrhs;
+    c.ag_st = s;
+  }
+  ADS_HIP(hipGraphLaunch(c.apply_exec, s));
 }
 
 }  // namespace ads

@@ -322,6 +322,18 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   const int fixed = ko.fixed_iters;
   auto t0 = std::chrono::steady_clock::now();
   Arena mem(st);
+  // graphs only on the context's own stream (nothing else is queued there);
+  // the apply workspace exists before any capture
+  const bool use_graph = c.graphs_on() && st == c.priv;
+  if (c.work_cols < nrhs) c.drop_apply_graph();
+  ensure_work(c, nrhs);
+  hipGraphExec_t step_exec = nullptr;
+  struct ExecGuard {
+    hipGraphExec_t& e;
+    ~ExecGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } exec_guard{step_exec};
   // instance table
   std::vector<int64_t> hrow0(Q), hrows(Q);
   std::vector<int32_t> hcol(Q);
@@ -432,26 +444,45 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
       ADS_HIP(hipMemcpyAsync(act_d, act.data(), Q * 4, hipMemcpyHostToDevice, st));
       act_up = act;
     }
-    // z = M v_j ; w = A z
-    ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dV, u, I, S.jq, act_d, 0);
-    apply_prec(c, u, z, nrhs, st);
-    if (flex)
-      ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dZ, z, I, S.jq, act_d, 1);
-    ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, z, (const double*)nullptr,
-               w, n, nrhs, 0);
-    // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2
-    ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
-               S.jq, act_d, part, stride);
-    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h, stride, 0);
-    ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
-               S.h, stride);
-    ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
-               S.jq, act_d, part, stride);
-    ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h2, stride, 0);
-    ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
-               S.h2, stride);
-    norms(w, act_d, S.hn);
-    ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
+    // one Arnoldi step: z = M v_j, w = A z, CGS2 against V, h_{j+1,j}, Givens;
+    // replayed from a captured graph after the first step when graphs are on
+    auto arnoldi_step = [&]() {
+      // z = M v_j ; w = A z
+      ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dV, u, I, S.jq, act_d, 0);
+      apply_prec(c, u, z, nrhs, st);
+      if (flex)
+        ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dZ, z, I, S.jq, act_d, 1);
+      ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, z, (const double*)nullptr,
+                 w, n, nrhs, 0);
+      // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2
+      ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
+                 S.jq, act_d, part, stride);
+      ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h, stride, 0);
+      ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
+                 S.h, stride);
+      ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
+                 S.jq, act_d, part, stride);
+      ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h2, stride, 0);
+      ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
+                 S.h2, stride);
+      norms(w, act_d, S.hn);
+      ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
+    };
+    if (use_graph) {
+      if (!step_exec) {
+        c.capturing = true;
+        try {
+          step_exec = capture_graph(st, arnoldi_step);
+        } catch (...) {
+          c.capturing = false;
+          throw;
+        }
+        c.capturing = false;
+      }
+      ADS_HIP(hipGraphLaunch(step_exec, st));
+    } else {
+      arnoldi_step();
+    }
     std::vector<double> hstat;
     download(hstat, stat, (size_t)3 * Q, st);
     std::vector<int32_t> brk(Q);

@@ -233,3 +233,47 @@ def test_errors_are_reported_not_raised():
     with pytest.raises(ads.AdsError) as e:
         ads.Context(A, part, 4, 1, 2)
     assert e.value.status == ads.ADS_ERR_ARG
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_graph_replays_match_direct_launches(nrhs):
+    """The captured apply graph, replayed with new contents in the same
+    buffers and with eager GPU work in between, gives the direct launches'
+    result bit for bit on every replay."""
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64", scale=64)
+    ctx = ads.Context(A, part, N, 2, 8, precision=ads.ADS_PREC_FP32)
+    n = A.n
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    r = torch.empty(nrhs * n, dtype=torch.float64, device=DEV)
+    z = torch.empty_like(r)
+    scratch = torch.zeros(1 << 20, dtype=torch.float64, device=DEV)
+    for rep in range(4):
+        r.copy_(torch.randn(nrhs * n, dtype=torch.float64, device=DEV, generator=gen))
+        ctx.set_graphs(False)
+        ads.ads_apply(ctx.ctx, r.data_ptr(), z.data_ptr(), nrhs, None)
+        torch.cuda.synchronize()
+        ref = z.clone()
+        ctx.set_graphs(True)
+        for k in range(3):
+            z.zero_()
+            scratch.add_(1.0)  # eager work between replays
+            ads.ads_apply(ctx.ctx, r.data_ptr(), z.data_ptr(), nrhs, None)
+            torch.cuda.synchronize()
+            assert torch.equal(z, ref), (rep, k)
+    ctx.close()
+
+
+def test_graph_solve_matches_direct_launches():
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64", scale=64)
+    b = torch.tensor(W.rhs(A.n, 3), dtype=torch.float64, device=DEV)
+    ctx = ads.Context(A, part, N, 2, 8, precision=ads.ADS_PREC_FP32)
+    out = []
+    for graphs in (False, True, True):
+        ctx.set_graphs(graphs)
+        x, info = ctx.solve(b, restart=50, flexible=True, rtol=1e-8)
+        torch.cuda.synchronize()
+        out.append((x.clone(), info["its"][0]))
+    ctx.close()
+    for x, its in out[1:]:
+        assert its == out[0][1]
+        assert torch.equal(x, out[0][0])
