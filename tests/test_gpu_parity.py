@@ -277,3 +277,51 @@ def test_graph_solve_matches_direct_launches():
     for x, its in out[1:]:
         assert its == out[0][1]
         assert torch.equal(x, out[0][0])
+
+
+@pytest.mark.skip(reason="the block subspace iteration stagnates when the eigenvalues of eq. 5 "
+                         "accumulate at 1 (small 2D subdomains, nev 10); enabled with the "
+                         "Krylov-Schur eigensolver")
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_bfs3d_and_2d_family(prec):
+    """The batched workload's shape at test size: a 3D upwind
+    convection-diffusion system with BFS-grown subdomains of uneven sizes
+    (partition from the GPU partitioner, bit-exact with the oracle's) and
+    2D systems of increasing size, all in one context (one launch per phase),
+    overlap 2, nev 10, FGMRES(30).  FP64: apply and solve match each system's
+    oracle; FP32 factors: every system reaches 1e-8 with iterations within +-1
+    and solutions within 1e-6."""
+    A3 = W.convdiff3d(16, nu=0.01)
+    seeds = W.bfs_seeds_3d(16, (8, 8, 4), seed=0)  # 16 parts of about 256 unknowns
+    N3 = len(seeds)
+    p_gpu = ads.ads_partition_bfs(A3, seeds)
+    p_cpu = OS.bfs_partition(A3.to_scipy(), seeds)
+    np.testing.assert_array_equal(p_gpu, p_cpu)
+    As, parts, Ns = [A3], [p_gpu], [N3]
+    for m in [16, 20, 26, 33]:
+        As.append(W.convdiff2d(m, 0.01))
+        pk = max(2, round(m / 16))
+        parts.append(W.block_partition_2d(m, pk))
+        Ns.append(pk * pk)
+    precision = ads.ADS_PREC_FP64 if prec == "fp64" else ads.ADS_PREC_FP32
+    ctx = ads.Context(As, parts, Ns, 2, 10, precision=precision,
+                      eig_tol=1e-12 if prec == "fp64" else 0.0)
+    offs = np.cumsum([0] + [A.n for A in As])
+    r = np.random.default_rng(13).standard_normal(offs[-1])
+    z = ctx.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    b = np.concatenate([W.rhs(A.n, 20 + k) for k, A in enumerate(As)])
+    x, info = ctx.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    x = x.cpu().numpy()
+    for k, (A, p, N) in enumerate(zip(As, parts, Ns)):
+        As_ = A.to_scipy()
+        P = OS.TwoLevelSchwarz(As_, p, N, 2, 10)
+        sl = slice(offs[k], offs[k + 1])
+        if prec == "fp64":
+            zo = P.apply(r[sl])
+            assert np.abs(z[sl] - zo).max() <= 1e-9 * np.abs(zo).max(), k
+        xo, io = OS.gmres(As_, b[sl], P.apply, restart=30, rtol=1e-8, flexible=True)
+        assert abs(info["its"][k] - io["its"]) <= 1, (k, info["its"][k], io["its"])
+        assert info["relres"][k] <= 1e-8
+        err = np.linalg.norm(x[sl] - xo) / np.linalg.norm(xo)
+        assert err <= (1e-7 if prec == "fp64" else 1e-6), (k, err)
+    ctx.close()
