@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define ADS_ABI_VERSION 1
+#define ADS_ABI_VERSION 2
 #define ADS_MAX_RESULTS 64 /* entries of ads_ksp_result: nsys * nrhs <= 64 */
 
 /* status codes */
@@ -66,6 +66,14 @@ enum {
   ADS_PREC_BF16 = 2          /* local factors stored BF16, products accumulated in FP64  */
 };
 
+/* eigensolver for the local eigenproblems of eq. 5 (largest |lambda|) */
+enum {
+  ADS_EIG_KRYLOV_SCHUR = 0,  /* block Krylov-Schur (block width 4, basis up to 32 vectors,
+                                restarts on the ordered Schur form); block subspace
+                                iteration where a subdomain is too small for the basis */
+  ADS_EIG_SUBSPACE = 1       /* block subspace iteration with Rayleigh-Ritz steps       */
+};
+
 typedef struct ads_ctx ads_ctx; /* opaque; owns all device memory it allocates */
 
 /* Sparse matrix in CSR form.  on_device = 0: host pointers; 1: device
@@ -93,10 +101,11 @@ typedef struct {
                              (0 -> 1e-10 with FP64 factors; 1e-3 with FP32/BF16
                              factors, where the coarse space only needs the
                              accuracy of the factors it is built from)             */
-  int32_t eig_max_sweeps; /* 0 -> 400                                                 */
+  int32_t eig_max_sweeps; /* 0 -> 400 (subspace sweeps, or Krylov-Schur block steps)   */
   const char* gnn_weights_path; /* weights file for warm_start = 1 (NULL otherwise)  */
   int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream
                              (reported in ads_info.t_kernel_ms / n_kernel)           */
+  int32_t eig_solver;     /* ADS_EIG_*: method for the eq. 5 eigenproblems            */
 } ads_options;
 
 typedef struct {
@@ -133,10 +142,11 @@ typedef struct {
   int32_t* kernel_dim;    /* dim ker(splitting) per subdomain (0 or 1)                */
   int32_t* n_i;           /* |Omega_i|                                                */
   int32_t* n_interior;    /* |Omega_Ii|                                               */
-  int32_t* sweeps;        /* eigensolver sweeps per subdomain                         */
+  int32_t* sweeps;        /* eigensolver sweeps (Krylov-Schur: block steps) per subdomain */
   int32_t* block;         /* block size of the local factorization                    */
   double* eig_resid;      /* final ||(T X - X H) V||_F / min |lambda| of the selected
                              invariant subspace per subdomain (eigensolver residual)  */
+  int32_t eig_solver;     /* ADS_EIG_* that ran                                      */
 } ads_info;
 
 /* Setup for one system (Sections 2 and 3): overlapping subdomains from the

@@ -16,13 +16,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libads.so")
 
-ADS_ABI_VERSION = 1
+ADS_ABI_VERSION = 2
 ADS_MAX_RESULTS = 64
 ADS_OK, ADS_KSP_MAXIT, ADS_KSP_BREAKDOWN = 0, 1, 2
 ADS_ERR_ARG, ADS_ERR_HIP, ADS_ERR_OOM, ADS_ERR_SINGULAR = -1, -2, -3, -4
 ADS_ERR_EIG_NOCONV, ADS_ERR_NAN, ADS_ERR_UNSUPPORTED = -5, -6, -7
 ADS_VARIANT_DEFLATED, ADS_VARIANT_RAS = 0, 1
 ADS_PREC_FP64, ADS_PREC_FP32, ADS_PREC_BF16 = 0, 1, 2
+ADS_EIG_KRYLOV_SCHUR, ADS_EIG_SUBSPACE = 0, 1
 
 # every symbol declared in include/ads.h
 SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_solve", "ads_get_info",
@@ -39,7 +40,8 @@ class ads_options(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("overlap", C.c_int32), ("nev", C.c_int32),
                 ("tau", C.c_double), ("variant", C.c_int32), ("precision", C.c_int32),
                 ("warm_start", C.c_int32), ("eig_tol", C.c_double), ("eig_max_sweeps", C.c_int32),
-                ("gnn_weights_path", C.c_char_p), ("profile", C.c_int32)]
+                ("gnn_weights_path", C.c_char_p), ("profile", C.c_int32),
+                ("eig_solver", C.c_int32)]
 
 
 class ads_ksp_options(C.Structure):
@@ -61,7 +63,7 @@ class ads_info(C.Structure):
                 ("t_kernel_ms", C.c_double * 4), ("n_kernel", C.c_int64 * 4),
                 ("nev_i", C.c_void_p), ("kernel_dim", C.c_void_p), ("n_i", C.c_void_p),
                 ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p),
-                ("eig_resid", C.c_void_p)]
+                ("eig_resid", C.c_void_p), ("eig_solver", C.c_int32)]
 
 
 class DeviceCSR:
@@ -156,9 +158,10 @@ def make_csr(A):
 
 
 def options(overlap, nev, variant=ADS_VARIANT_DEFLATED, precision=ADS_PREC_FP64, tau=0.0,
-            eig_tol=0.0, eig_max_sweeps=0, warm_start=0, gnn_weights_path=None, profile=0):
+            eig_tol=0.0, eig_max_sweeps=0, warm_start=0, gnn_weights_path=None, profile=0,
+            eig_solver=0):
     return ads_options(ADS_ABI_VERSION, overlap, nev, tau, variant, precision, warm_start, eig_tol,
-                       eig_max_sweeps, gnn_weights_path, profile)
+                       eig_max_sweeps, gnn_weights_path, profile, eig_solver)
 
 
 def ads_setup(A, part, nparts, opts, stream=None):
@@ -269,11 +272,11 @@ class Context:
 
     def __init__(self, As, parts, nparts, overlap, nev, variant=ADS_VARIANT_DEFLATED,
                  precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None,
-                 profile=0):
+                 profile=0, eig_solver=0):
         if not isinstance(As, (list, tuple)):
             As, parts, nparts = [As], [parts], [nparts]
         self.opts = options(overlap, nev, variant, precision, tau, eig_tol, eig_max_sweeps,
-                            profile=profile)
+                            profile=profile, eig_solver=eig_solver)
         self.stream = stream
         self.ctx = ads_setup_batched(As, parts, nparts, self.opts, stream)
         self.info = ads_get_info(self.ctx)

@@ -197,6 +197,8 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
   if (opts->precision < ADS_PREC_FP64 || opts->precision > ADS_PREC_BF16)
     fail(ADS_ERR_ARG, "unknown precision");
   if (opts->warm_start != 0) fail(ADS_ERR_UNSUPPORTED, "warm_start requires the learned model");
+  if (opts->eig_solver != ADS_EIG_KRYLOV_SCHUR && opts->eig_solver != ADS_EIG_SUBSPACE)
+    fail(ADS_ERR_ARG, "unknown eig_solver");
   auto c = new Ctx();
   try {
     c->stream = st;
@@ -382,6 +384,7 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
     info->eig_sweeps_max = c.eig_sweeps_max;
     info->eig_unconverged = c.eig_unconverged;
     info->eig_fallbacks = c.eig_fallbacks;
+    info->eig_solver = c.eig_krylov_schur ? ADS_EIG_KRYLOV_SCHUR : ADS_EIG_SUBSPACE;
     for (int k = 0; k < 8; ++k) info->t_phase_ms[k] = c.t_phase_ms[k];
     ctx->c->prof_resolve();
     for (int k = 0; k < 4; ++k) {

@@ -203,7 +203,9 @@ struct Ctx {
   int32_t* sys_coff = nullptr; // [nsys+1] first coarse index of each system
   double* Einv = nullptr;
   int32_t eig_sweeps_max = 0, eig_unconverged = 0, eig_fallbacks = 0;
+  bool eig_krylov_schur = false;  // block Krylov-Schur ran (else block subspace iteration)
   int h_eig_nblk = 0;  // row blocks of the eigensolver sweep kernels
+  int h_eig_nqblk = 0;  // wide row blocks of the Krylov-Schur block QR kernels
 
   // workspace for apply / solve
   double* work = nullptr;   // padded local vectors, npad_total * work_cols

@@ -32,6 +32,12 @@ namespace ads {
 static constexpr int EIG_T = 1024;
 static constexpr int PMAX = 32;
 static constexpr int EIG_PC = 4;  // columns per workgroup of the operator kernel
+// block Krylov-Schur: block width EIG_PC, at most PMAX + EIG_PC basis vectors
+static constexpr int KS_W = PMAX + EIG_PC;
+static constexpr int KS_PK = KS_W * EIG_PC;  // partial V^T W per row block
+static constexpr int KS_BS = KS_W * PMAX;    // Bk per subdomain
+static constexpr int VSEL = KS_W * KS_W;     // Vsel per subdomain
+
 static constexpr double CLUSTER_RTOL = 1e-6;
 
 #define WAVE_SYNC()                                        \
@@ -84,12 +90,13 @@ __device__ __forceinline__ void cgivens(cd x, cd y, double& c, cd& s) {
 }
 
 struct SmallEigLds {
-  cd A[PMAX * PMAX];
-  cd Q[PMAX * PMAX];
+  cd A[PMAX * (PMAX + 1)];  // complex Schur form, row-major, leading dimension p | 1
+  cd Q[PMAX * (PMAX + 1)];  // Schur vectors, same layout
   cd v[PMAX];
-  double Pm[PMAX * PMAX];
-  double V[PMAX * PMAX];  // real basis, column-major p x m
+  double Pm[PMAX * (PMAX + 1)];
+  double V[PMAX * (PMAX + 1)];  // real basis, column-major p x m (leading dimension p)
   double mag[PMAX];
+  double rv[PMAX];
   int rank[PMAX];
   int selected[PMAX];
   double red[64];
@@ -100,138 +107,257 @@ struct SmallEigLds {
 // their eigenvalues in |lambda| order in lam_out[0..m), and V (p x m real
 // orthonormal basis of the selected invariant subspace).  ok = 0 on failure.
 __device__ int small_eig_select(int p, const double* H, int count, double tau, SmallEigLds& L,
-                                double* lam_re, double* lam_im, int* ok_out, double* cut_gap) {
+                                double* lam_re, double* lam_im, int* ok_out, double* cut_gap,
+                                int count2 = 0, int* m2_out = nullptr, double* V2 = nullptr) {
   const int lane = threadIdx.x;  // wave 0 only
+  // leading dimension of the work matrices: odd, so that a column access by
+  // the lanes of a wave spreads over the LDS banks
+  const int ld = p | 1;
   cd* A = L.A;
   cd* Q = L.Q;
+  // real arithmetic first: T (in L.Pm) and Z (in L.V), both row-major
+  double* T = L.Pm;
+  double* Z = L.V;
+  const double eps = 2.220446049250313e-16;
+  double anorm = 0.0;
   for (int e = lane; e < p * p; e += 64) {
-    A[e] = cd{H[e], 0.0};
-    Q[e] = cd{(e / p == e % p) ? 1.0 : 0.0, 0.0};
+    const int r = e / p, c = e % p;
+    T[r * ld + c] = H[e];
+    Z[r * ld + c] = (r == c) ? 1.0 : 0.0;
+    anorm = fmax(anorm, fabs(H[e]));
   }
+  for (int o = 32; o > 0; o >>= 1) anorm = fmax(anorm, __shfl_xor(anorm, o, 64));
+  if (!(anorm > 0.0)) anorm = 1.0;
   WAVE_SYNC();
-  // Householder reduction to upper Hessenberg form
+  // Householder reduction to upper Hessenberg form, T <- P T P, Z <- Z P
   for (int k = 0; k + 2 < p; ++k) {
     const int len = p - k - 1;
-    cd x = (lane < len) ? A[(k + 1 + lane) * p + k] : cd{0, 0};
-    double nx2 = adsd::wave_sum(cabs2(x));
-    double nx = sqrt(nx2);
-    cd x0 = A[(k + 1) * p + k];
-    double ax0 = cabs(x0);
+    const double x = (lane < len) ? T[(k + 1 + lane) * ld + k] : 0.0;
+    const double nx = sqrt(adsd::wave_sum(x * x));
     if (nx == 0.0) continue;
-    cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : cd{1.0, 0.0};
-    cd alpha = cscale(ph, -nx);
-    cd vl = (lane < len) ? x : cd{0, 0};
-    if (lane == 0) vl = csub(vl, alpha);
-    double nv = sqrt(adsd::wave_sum(cabs2(vl)));
-    if (nv == 0.0) continue;
-    vl = cscale(vl, 1.0 / nv);
-    if (lane < len) L.v[lane] = vl;
+    const double x0 = T[(k + 1) * ld + k];
+    const double beta = x0 > 0.0 ? -nx : nx;
+    const double vl = (lane == 0) ? x - beta : x;
+    const double vn2 = adsd::wave_sum(vl * vl);
+    if (vn2 == 0.0) continue;
+    const double tau = 2.0 / vn2;
+    if (lane < len) L.rv[lane] = vl;
     WAVE_SYNC();
-    // left: A <- (I - 2 v v^H) A on rows k+1.., all columns >= k
-    if (lane < p && lane >= k) {
+    if (lane < p && lane >= k) {  // rows k+1.., column lane
       const int j = lane;
-      cd w{0, 0};
-      for (int l = 0; l < len; ++l) w = cadd(w, cmul(cconj(L.v[l]), A[(k + 1 + l) * p + j]));
-      for (int l = 0; l < len; ++l)
-        A[(k + 1 + l) * p + j] = csub(A[(k + 1 + l) * p + j], cscale(cmul(L.v[l], w), 2.0));
+      double w = 0.0;
+      for (int l = 0; l < len; ++l) w += L.rv[l] * T[(k + 1 + l) * ld + j];
+      w *= tau;
+      for (int l = 0; l < len; ++l) T[(k + 1 + l) * ld + j] -= L.rv[l] * w;
     }
     WAVE_SYNC();
-    // right: A <- A (I - 2 v v^H), Q <- Q (I - 2 v v^H) on columns k+1..
-    if (lane < p) {
-      const int i = lane;
-      cd w{0, 0}, wq{0, 0};
-      for (int l = 0; l < len; ++l) {
-        w = cadd(w, cmul(A[i * p + k + 1 + l], L.v[l]));
-        wq = cadd(wq, cmul(Q[i * p + k + 1 + l], L.v[l]));
-      }
-      for (int l = 0; l < len; ++l) {
-        cd vc = cconj(L.v[l]);
-        A[i * p + k + 1 + l] = csub(A[i * p + k + 1 + l], cscale(cmul(w, vc), 2.0));
-        Q[i * p + k + 1 + l] = csub(Q[i * p + k + 1 + l], cscale(cmul(wq, vc), 2.0));
+    {  // columns k+1..: rows of T (lanes 0..31) and of Z (lanes 32..63)
+      double* M = lane < 32 ? T : Z;
+      const int i = lane & 31;
+      if (i < p) {
+        double w = 0.0;
+        for (int l = 0; l < len; ++l) w += M[i * ld + k + 1 + l] * L.rv[l];
+        w *= tau;
+        for (int l = 0; l < len; ++l) M[i * ld + k + 1 + l] -= w * L.rv[l];
       }
     }
     WAVE_SYNC();
-    if (lane < len && lane > 0) A[(k + 1 + lane) * p + k] = cd{0, 0};
+    if (lane < len) T[(k + 1 + lane) * ld + k] = (lane == 0) ? beta : 0.0;
     WAVE_SYNC();
   }
-  // shifted complex QR (single shift, Wilkinson / exceptional), full Schur form
-  const double eps = 2.220446049250313e-16;
+  // Francis double-shift QR to real Schur form (1x1 and 2x2 diagonal
+  // blocks), T <- Z^T H Z
   int hi = p - 1, its = 0, total = 0, ok = 1;
-  while (hi > 0) {
+  while (hi >= 1) {
     int l = hi;
-    while (l > 0) {
-      double sub = cnorm1(A[l * p + l - 1]);
-      double dd = cnorm1(A[(l - 1) * p + l - 1]) + cnorm1(A[l * p + l]);
-      if (sub <= eps * dd || sub < 1e-300) break;
+    while (l > 0) {  // normwise deflation test (only the largest |lambda| matter)
+      const double sub = fabs(T[l * ld + l - 1]);
+      const double dd = fmax(fabs(T[(l - 1) * ld + l - 1]) + fabs(T[l * ld + l]), anorm);
+      if (sub <= eps * dd) break;
       --l;
     }
     WAVE_SYNC();
-    if (l > 0 && lane == 0) A[l * p + l - 1] = cd{0, 0};
+    if (l > 0 && lane == 0) T[l * ld + l - 1] = 0.0;
     WAVE_SYNC();
-    if (l == hi) {
-      --hi;
+    if (l < hi - 1 && its >= 20) {
+      // stagnation on a tight cluster: split the window at its smallest
+      // subdiagonal entry if that is at the rounding level of the matrix
+      int kb = l + 1;
+      for (int k = l + 2; k <= hi; ++k)
+        if (fabs(T[k * ld + k - 1]) < fabs(T[kb * ld + kb - 1])) kb = k;
+      if (fabs(T[kb * ld + kb - 1]) <= 1e3 * eps * anorm) {
+        WAVE_SYNC();
+        if (lane == 0) T[kb * ld + kb - 1] = 0.0;
+        WAVE_SYNC();
+        its = 0;
+        continue;
+      }
+    }
+    if (l >= hi - 1) {  // a 1x1 or 2x2 block has split off
+      hi = l - 1;
       its = 0;
       continue;
     }
-    if (++total > 100 * p) {
+    if (++total > 60 * p) {
       ok = 0;
       break;
     }
     ++its;
-    cd a = A[(hi - 1) * p + hi - 1], b = A[(hi - 1) * p + hi], c = A[hi * p + hi - 1],
-       d = A[hi * p + hi];
-    cd mu;
-    if (its % 11 == 10) {
-      mu = cadd(d, cd{0.75 * cnorm1(c), 0.0});
+    // the two shifts r1, r2: the eigenvalues of the trailing 2 x 2 block if
+    // complex, else twice the one nearer to its last diagonal entry;
+    // exceptional shifts every tenth iteration
+    double r1r, r1i, r2r, r2i;
+    if (its % 10 == 0) {
+      const double w = fabs(T[hi * ld + hi - 1]) + fabs(T[(hi - 1) * ld + hi - 2]);
+      r1r = r2r = 0.75 * w + T[hi * ld + hi];
+      r1i = 0.6614378277661477 * w;  // sqrt(0.4375) w
+      r2i = -r1i;
     } else {
-      cd half = cscale(csub(a, d), 0.5);
-      cd disc = csqrt(cadd(cmul(half, half), cmul(b, c)));
-      cd m0 = cscale(cadd(a, d), 0.5);
-      cd mu1 = cadd(m0, disc), mu2 = csub(m0, disc);
-      mu = (cabs2(csub(mu1, d)) <= cabs2(csub(mu2, d))) ? mu1 : mu2;
-    }
-    for (int k = l; k < hi; ++k) {
-      cd x, y;
-      if (k == l) {
-        x = csub(A[l * p + l], mu);
-        y = A[(l + 1) * p + l];
+      const double a = T[(hi - 1) * ld + hi - 1], b = T[(hi - 1) * ld + hi];
+      const double c = T[hi * ld + hi - 1], d = T[hi * ld + hi];
+      const double pp = 0.5 * (a - d), q = pp * pp + b * c;
+      if (q >= 0.0) {
+        const double e1 = d + pp + copysign(sqrt(q), pp);
+        const double e2 = e1 != 0.0 ? (a * d - b * c) / e1 : d + pp - copysign(sqrt(q), pp);
+        r1r = r2r = fabs(e1 - d) <= fabs(e2 - d) ? e1 : e2;
+        r1i = r2i = 0.0;
       } else {
-        x = A[k * p + k - 1];
-        y = A[(k + 1) * p + k - 1];
+        r1r = r2r = d + pp;
+        r1i = sqrt(-q);
+        r2i = -r1i;
       }
-      double cg;
-      cd sg;
-      cgivens(x, y, cg, sg);
+    }
+    // first column of (T - s1)(T - s2) at the start row mm: the lowest row
+    // (>= l) where the bulge it creates is negligible against h(mm, mm-1), so
+    // two consecutive small subdiagonal entries do not stall the iteration
+    int mm = hi - 2;
+    double x, y, z;
+    for (;;) {
+      const double h00 = T[mm * ld + mm], h01 = T[mm * ld + mm + 1], h10 = T[(mm + 1) * ld + mm];
+      const double h11 = T[(mm + 1) * ld + mm + 1], h21 = T[(mm + 2) * ld + mm + 1];
+      // (h00 - r1)(h00 - r2) in factored form (no cancellation of h00^2
+      // against the shift terms), scaled
+      double s0 = fabs(h00 - r2r) + fabs(r2i) + fabs(h10);
+      if (s0 == 0.0) s0 = 1.0;
+      const double h10s = h10 / s0;
+      x = h10s * h01 + (h00 - r1r) * ((h00 - r2r) / s0) - r1i * (r2i / s0);
+      y = h10s * (h00 + h11 - r1r - r2r);
+      z = h10s * h21;
+      const double sc = fabs(x) + fabs(y) + fabs(z);
+      if (sc > 0.0) {
+        x /= sc;
+        y /= sc;
+        z /= sc;
+      }
+      if (mm == l) break;
+      const double e1 = fabs(T[mm * ld + mm - 1]) * (fabs(y) + fabs(z));
+      const double e2 = fabs(x) * (fabs(T[(mm - 1) * ld + mm - 1]) + fabs(h00) + fabs(h11));
+      if (e1 <= eps * e2) break;
+      --mm;
+    }
+    for (int k = mm; k < hi; ++k) {
+      const bool three = k < hi - 1;
+      if (k > mm) {
+        x = T[k * ld + k - 1];
+        y = T[(k + 1) * ld + k - 1];
+        z = three ? T[(k + 2) * ld + k - 1] : 0.0;
+      }
+      const double al = sqrt(x * x + y * y + z * z);
+      if (al == 0.0) continue;
+      const double beta = x > 0.0 ? -al : al;
+      const double v0 = x - beta, v1 = y, v2 = z;
+      const double tau = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
       WAVE_SYNC();
-      const int jlo = (k == l) ? l : k - 1;
-      if (lane < p && lane >= jlo) {
+      const int cmin = k > mm ? k - 1 : k;
+      if (lane >= cmin && lane < p) {  // rows k..k+2
         const int j = lane;
-        cd a1 = A[k * p + j], a2 = A[(k + 1) * p + j];
-        A[k * p + j] = cadd(cscale(a1, cg), cmul(sg, a2));
-        A[(k + 1) * p + j] = csub(cscale(a2, cg), cmul(cconj(sg), a1));
+        double w = v0 * T[k * ld + j] + v1 * T[(k + 1) * ld + j];
+        if (three) w += v2 * T[(k + 2) * ld + j];
+        w *= tau;
+        T[k * ld + j] -= v0 * w;
+        T[(k + 1) * ld + j] -= v1 * w;
+        if (three) T[(k + 2) * ld + j] -= v2 * w;
       }
       WAVE_SYNC();
-      const int ihi = min(k + 2, hi);
-      if (lane < p) {
-        const int i = lane;
-        if (i <= ihi) {
-          cd b1 = A[i * p + k], b2 = A[i * p + k + 1];
-          A[i * p + k] = cadd(cscale(b1, cg), cmul(cconj(sg), b2));
-          A[i * p + k + 1] = csub(cscale(b2, cg), cmul(sg, b1));
+      {  // columns k..k+2: rows of T up to min(k+3, hi) and all rows of Z
+        double* M = lane < 32 ? T : Z;
+        const int i = lane & 31;
+        const int imax = lane < 32 ? min(k + 3, hi) : p - 1;
+        if (i <= imax) {
+          double w = M[i * ld + k] * v0 + M[i * ld + k + 1] * v1;
+          if (three) w += M[i * ld + k + 2] * v2;
+          w *= tau;
+          M[i * ld + k] -= w * v0;
+          M[i * ld + k + 1] -= w * v1;
+          if (three) M[i * ld + k + 2] -= w * v2;
         }
-        cd q1 = Q[i * p + k], q2 = Q[i * p + k + 1];
-        Q[i * p + k] = cadd(cscale(q1, cg), cmul(cconj(sg), q2));
-        Q[i * p + k + 1] = csub(cscale(q2, cg), cmul(sg, q1));
       }
       WAVE_SYNC();
-      if (k > l && lane == 0) A[(k + 1) * p + k - 1] = cd{0, 0};
+      if (lane == 0) {
+        if (k > mm) {
+          T[k * ld + k - 1] = beta;
+          T[(k + 1) * ld + k - 1] = 0.0;
+          if (three) T[(k + 2) * ld + k - 1] = 0.0;
+        } else if (mm > l) {
+          // the reflector's effect on the small h(mm, mm-1); its fill below
+          // is negligible by the choice of mm
+          T[k * ld + k - 1] *= 1.0 - tau * v0 * v0;
+        }
+      }
       WAVE_SYNC();
     }
+  }
+  // complex Schur form: each remaining 2x2 block [a b; c d] is triangularised
+  // by the unitary G = [u, (-u2, conj(u1))] with u the unit eigenvector
+  // (lambda - d, c) of one of its eigenvalues
+  for (int e = lane; e < p * ld; e += 64) {
+    A[e] = cd{T[e], 0.0};
+    Q[e] = cd{Z[e], 0.0};
+  }
+  WAVE_SYNC();
+  for (int k = 0; k + 1 < p;) {
+    const double c = T[(k + 1) * ld + k];
+    if (c == 0.0) {
+      ++k;
+      continue;
+    }
+    const double a = T[k * ld + k], b = T[k * ld + k + 1], d = T[(k + 1) * ld + k + 1];
+    const double pp = 0.5 * (a - d), q = pp * pp + b * c;
+    cd x1;
+    if (q >= 0.0)
+      x1 = cd{pp + copysign(sqrt(q), pp), 0.0};
+    else
+      x1 = cd{pp, sqrt(-q)};
+    const double nrm = sqrt(cabs2(x1) + c * c);
+    const cd u1 = cscale(x1, 1.0 / nrm);
+    const double u2 = c / nrm;
+    WAVE_SYNC();
+    if (lane < p && lane >= k) {  // rows k, k+1 <- G^H rows
+      const int j = lane;
+      const cd r0 = A[k * ld + j], r1 = A[(k + 1) * ld + j];
+      A[k * ld + j] = cadd(cmul(cconj(u1), r0), cscale(r1, u2));
+      A[(k + 1) * ld + j] = csub(cmul(u1, r1), cscale(r0, u2));
+    }
+    WAVE_SYNC();
+    {  // columns k, k+1 <- columns G: A rows up to k+1 (lanes 0..31), Q (lanes 32..63)
+      cd* M = lane < 32 ? A : Q;
+      const int i = lane & 31;
+      const int imax = lane < 32 ? k + 1 : p - 1;
+      if (i <= imax) {
+        const cd c0 = M[i * ld + k], c1 = M[i * ld + k + 1];
+        M[i * ld + k] = cadd(cmul(c0, u1), cscale(c1, u2));
+        M[i * ld + k + 1] = csub(cmul(c1, cconj(u1)), cscale(c0, u2));
+      }
+    }
+    WAVE_SYNC();
+    if (lane == 0) A[(k + 1) * ld + k] = cd{0.0, 0.0};
+    WAVE_SYNC();
+    k += 2;
   }
   *ok_out = ok;
   WAVE_SYNC();
   // ranks by |lambda| descending (ties by index)
-  if (lane < p) L.mag[lane] = cabs(A[lane * p + lane]);
+  if (lane < p) L.mag[lane] = cabs(A[lane * ld + lane]);
   WAVE_SYNC();
   if (lane < p) {
     int rk = 0;
@@ -243,27 +369,32 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
     L.rank[lane] = rk;
   }
   WAVE_SYNC();
-  // selection: the count largest, extended by the cluster rule, optional tau
-  int m = 0;
-  double cut = 0.0, next = 0.0;
-  if (count > 0) {
+  // selection: the count largest, extended by the cluster rule, optional tau.
+  // A second, larger cut (count2, cluster rule only) marks the set kept for a
+  // restart; the wanted set is a prefix of it in |lambda| order.
+  int m = 0, mk = 0;
+  double cut = 0.0, next = 0.0, cut2 = 0.0;
+  const int ck = count2 > count ? count2 : count;
+  if (count > 0)
     for (int j = 0; j < p; ++j)
       if (L.rank[j] == count - 1) cut = L.mag[j];
-    for (int j = 0; j < p; ++j) {
-      bool sel = L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut;
-      if (tau > 0 && !(L.mag[j] > 1.0 / tau)) sel = false;
-      if (lane == 0) L.selected[j] = sel;
-      m += sel;
-      if (!(L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut)) next = fmax(next, L.mag[j]);
-    }
-  } else {
+  if (ck > 0)
     for (int j = 0; j < p; ++j)
-      if (lane == 0) L.selected[j] = 0;
+      if (L.rank[j] == ck - 1) cut2 = L.mag[j];
+  for (int j = 0; j < p; ++j) {
+    bool sel = count > 0 && L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut;
+    if (tau > 0 && !(L.mag[j] > 1.0 / tau)) sel = false;
+    const bool keep = sel || (ck > 0 && L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut2);
+    if (lane == 0) L.selected[j] = keep;
+    m += sel;
+    mk += keep;
+    if (count > 0 && !(L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut)) next = fmax(next, L.mag[j]);
   }
   *cut_gap = (cut > 0) ? (cut - next) / cut : 1.0;
+  if (m2_out) *m2_out = mk;
   WAVE_SYNC();
   // reorder: move selected eigenvalues (in rank order) to the leading positions
-  for (int tpos = 0; tpos < m; ++tpos) {
+  for (int tpos = 0; tpos < mk; ++tpos) {
     // find the selected entry with the smallest rank at positions >= tpos
     int idx = -1, best = 1 << 30;
     for (int j = tpos; j < p; ++j)
@@ -272,7 +403,7 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
         idx = j;
       }
     for (int k = idx - 1; k >= tpos; --k) {
-      cd t11 = A[k * p + k], t22 = A[(k + 1) * p + k + 1], t12 = A[k * p + k + 1];
+      cd t11 = A[k * ld + k], t22 = A[(k + 1) * ld + k + 1], t12 = A[k * ld + k + 1];
       cd x = t12, y = csub(t22, t11);
       double cg;
       cd sg;
@@ -280,27 +411,27 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
       WAVE_SYNC();
       if (lane < p && lane >= k) {
         const int j = lane;
-        cd a1 = A[k * p + j], a2 = A[(k + 1) * p + j];
-        A[k * p + j] = cadd(cscale(a1, cg), cmul(sg, a2));
-        A[(k + 1) * p + j] = csub(cscale(a2, cg), cmul(cconj(sg), a1));
+        cd a1 = A[k * ld + j], a2 = A[(k + 1) * ld + j];
+        A[k * ld + j] = cadd(cscale(a1, cg), cmul(sg, a2));
+        A[(k + 1) * ld + j] = csub(cscale(a2, cg), cmul(cconj(sg), a1));
       }
       WAVE_SYNC();
       if (lane < p) {
         const int i = lane;
         if (i <= k + 1) {
-          cd b1 = A[i * p + k], b2 = A[i * p + k + 1];
-          A[i * p + k] = cadd(cscale(b1, cg), cmul(cconj(sg), b2));
-          A[i * p + k + 1] = csub(cscale(b2, cg), cmul(sg, b1));
+          cd b1 = A[i * ld + k], b2 = A[i * ld + k + 1];
+          A[i * ld + k] = cadd(cscale(b1, cg), cmul(cconj(sg), b2));
+          A[i * ld + k + 1] = csub(cscale(b2, cg), cmul(sg, b1));
         }
-        cd q1 = Q[i * p + k], q2 = Q[i * p + k + 1];
-        Q[i * p + k] = cadd(cscale(q1, cg), cmul(cconj(sg), q2));
-        Q[i * p + k + 1] = csub(cscale(q2, cg), cmul(sg, q1));
+        cd q1 = Q[i * ld + k], q2 = Q[i * ld + k + 1];
+        Q[i * ld + k] = cadd(cscale(q1, cg), cmul(cconj(sg), q2));
+        Q[i * ld + k + 1] = csub(cscale(q2, cg), cmul(sg, q1));
       }
       WAVE_SYNC();
       if (lane == 0) {
-        A[k * p + k] = t22;
-        A[(k + 1) * p + k + 1] = t11;
-        A[(k + 1) * p + k] = cd{0, 0};
+        A[k * ld + k] = t22;
+        A[(k + 1) * ld + k + 1] = t11;
+        A[(k + 1) * ld + k] = cd{0, 0};
         int r0 = L.rank[k], s0 = L.selected[k];
         L.rank[k] = L.rank[k + 1];
         L.selected[k] = L.selected[k + 1];
@@ -311,60 +442,74 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
     }
   }
   if (lane < m) {
-    lam_re[lane] = A[lane * p + lane].x;
-    lam_im[lane] = A[lane * p + lane].y;
+    lam_re[lane] = A[lane * ld + lane].x;
+    lam_im[lane] = A[lane * ld + lane].y;
   }
-  // real basis of span(Q[:, 0:m]): the projector Q_m Q_m^H is real for a
-  // conjugation-closed selection; pivoted Gram-Schmidt on its columns
-  if (lane < p) {
-    const int j = lane;
-    for (int i = 0; i < p; ++i) {
-      double acc = 0.0;
-      for (int t = 0; t < m; ++t) acc += cmul(Q[i * p + t], cconj(Q[j * p + t])).x;
-      L.Pm[i * p + j] = acc;  // column j of P
-    }
-  }
-  WAVE_SYNC();
-  for (int t = 0; t < m; ++t) {
-    double nrm = 0.0;
-    if (lane < p)
-      for (int i = 0; i < p; ++i) nrm += L.Pm[i * p + lane] * L.Pm[i * p + lane];
-    // argmax over lanes (ties -> smallest index)
-    double bn = nrm;
-    int bj = lane < p ? lane : 1 << 30;
-    if (lane >= p) bn = -1.0;
-    for (int o = 32; o > 0; o >>= 1) {
-      double on = __shfl_xor(bn, o, 64);
-      int oj = __shfl_xor(bj, o, 64);
-      if (on > bn || (on == bn && oj < bj)) {
-        bn = on;
-        bj = oj;
+  // real bases of span(Q[:, 0:m]) (into L.V) and of span(Q[:, 0:mk]) (into
+  // V2): the projector Q_b Q_b^H is real for a conjugation-closed selection;
+  // pivoted Gram-Schmidt on its columns, then classical Gram-Schmidt twice of
+  // each new column against the earlier ones (numerical safety)
+  for (int which = 0; which < (V2 ? 2 : 1); ++which) {
+    const int mb = which ? mk : m;
+    double* VV = which ? V2 : L.V;
+    double* P = L.Pm;
+    if (lane < p) {
+      const int j = lane;
+      for (int i = 0; i < p; ++i) {
+        double acc = 0.0;
+        for (int t = 0; t < mb; ++t) acc += cmul(Q[i * ld + t], cconj(Q[j * ld + t])).x;
+        P[i * ld + j] = acc;  // column j of the projector
       }
     }
-    double inv = bn > 0 ? 1.0 / sqrt(bn) : 0.0;
-    if (lane < p) L.V[t * p + lane] = L.Pm[lane * p + bj] * inv;
     WAVE_SYNC();
-    for (int pass = 0; pass < 2; ++pass) {
-      if (lane < p) {
-        const int j = lane;
-        double d = 0.0;
-        for (int i = 0; i < p; ++i) d += L.V[t * p + i] * L.Pm[i * p + j];
-        for (int i = 0; i < p; ++i) L.Pm[i * p + j] -= d * L.V[t * p + i];
-      }
-      WAVE_SYNC();
-    }
-    // re-orthogonalise V[:, t] against earlier columns (numerical safety)
-    if (t > 0) {
-      double vt = lane < p ? L.V[t * p + lane] : 0.0;
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int u = 0; u < t; ++u) {
-          double d = adsd::wave_sum(lane < p ? L.V[u * p + lane] * vt : 0.0);
-          if (lane < p) vt -= d * L.V[u * p + lane];
+    for (int t = 0; t < mb; ++t) {
+      double nrm = 0.0;
+      if (lane < p)
+        for (int i = 0; i < p; ++i) nrm += P[i * ld + lane] * P[i * ld + lane];
+      // argmax over lanes (ties -> smallest index)
+      double bn = nrm;
+      int bj = lane < p ? lane : 1 << 30;
+      if (lane >= p) bn = -1.0;
+      for (int o = 32; o > 0; o >>= 1) {
+        double on = __shfl_xor(bn, o, 64);
+        int oj = __shfl_xor(bj, o, 64);
+        if (on > bn || (on == bn && oj < bj)) {
+          bn = on;
+          bj = oj;
         }
       }
-      double nn = sqrt(adsd::wave_sum(vt * vt));
-      if (lane < p) L.V[t * p + lane] = nn > 0 ? vt / nn : 0.0;
+      double inv = bn > 0 ? 1.0 / sqrt(bn) : 0.0;
+      if (lane < p) VV[t * p + lane] = P[lane * ld + bj] * inv;
       WAVE_SYNC();
+      for (int pass = 0; pass < 2; ++pass) {
+        if (lane < p) {
+          const int j = lane;
+          double d = 0.0;
+          for (int i = 0; i < p; ++i) d += VV[t * p + i] * P[i * ld + j];
+          for (int i = 0; i < p; ++i) P[i * ld + j] -= d * VV[t * p + i];
+        }
+        WAVE_SYNC();
+      }
+      if (t > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          if (lane < t) {  // coefficients against the earlier columns, lane u
+            double d = 0.0;
+            for (int i = 0; i < p; ++i) d += VV[lane * p + i] * VV[t * p + i];
+            L.rv[lane] = d;
+          }
+          WAVE_SYNC();
+          if (lane < p) {
+            double v = VV[t * p + lane];
+            for (int u = 0; u < t; ++u) v -= L.rv[u] * VV[u * p + lane];
+            VV[t * p + lane] = v;
+          }
+          WAVE_SYNC();
+        }
+        const double vt = lane < p ? VV[t * p + lane] : 0.0;
+        const double nn = sqrt(adsd::wave_sum(vt * vt));
+        if (lane < p) VV[t * p + lane] = nn > 0 ? vt / nn : 0.0;
+        WAVE_SYNC();
+      }
     }
   }
   return m;
@@ -726,14 +871,29 @@ struct EigArgs {
   const int32_t* blk_sub;   // row block -> subdomain
   const int32_t* blk_r0;    // row block -> first row
   const int32_t* sub_blk0;  // subdomain -> first row block (nsub + 1)
+  const int32_t* qblk_sub;  // wide row blocks of k_ks_qr (KS_QRB rows): same maps
+  const int32_t* qblk_r0;
+  const int32_t* qsub_blk0;
   double* partA;    // per row block p x p partial products (PMAX^2 stride)
   double* partB;
   double* partH;
   double* partR;    // per row block partial squared residual
   int lrb;          // log2 of the row-block height
+  // block Krylov-Schur state (block width p)
+  int ks;           // 1: the operator kernels map columns jcur .. jcur + p - 1 of V
+  int km;           // largest Rayleigh quotient order
+  double* V;        // per subdomain npad x (km + p) basis, at (km + p) * pad_off
+  double* Bk;       // per subdomain (km + p) x km row-major: T V_k = V_{k+p} Bk
+  int32_t* jcur;    // per subdomain: first column of the block expanded next
+  int32_t* kprev;   // per subdomain: Rayleigh quotient order of the last restart
+  double* partK;    // per row block KS_PK partial products V^T W
+  double* partK2;
+  double* Ures;     // per subdomain kept Schur basis (order x kept, column-major)
+  double* Racc;     // per subdomain two accumulated EIG_PC x EIG_PC triangular factors
   int32_t* err;
   int p;
   int nev;
+  int kkeep;        // basis vectors kept by a restart (before the cluster rule)
   double tau;
   double tol;
 };
@@ -1016,7 +1176,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
   __shared__ double red[PC][16];
   __shared__ double alpha[PC], beta[PC];
   const int i = blockIdx.x, half = blockIdx.z;
-  if (a.done[i]) return;
+  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.km)) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
@@ -1025,7 +1185,8 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
   const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, M = K / 2;
   const int64_t ld = npad;
   const int64_t base = a.om_off[i];
-  const double* X = a.X + a.pad_off[i] * p + j0 * ld;
+  const double* X = a.ks ? a.V + a.pad_off[i] * (a.km + p) + a.jcur[i] * ld
+                         : a.X + a.pad_off[i] * p + j0 * ld;
   double* Wv = a.W + a.pad_off[i] * p + j0 * ld;
   const bool floating = a.kdim[i] != 0;
   const double* l = a.ell + a.pad_off[i];
@@ -1097,7 +1258,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_bwd(const FT* fac, EigArgs a) {
   __shared__ double red[PC][16];
   __shared__ double sums[PC];
   const int i = blockIdx.x, half = blockIdx.z;
-  if (a.done[i]) return;
+  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.km)) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
@@ -1144,7 +1305,7 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   __shared__ double red[PC][16];
   __shared__ double alpha[PC], beta[PC];
   const int i = blockIdx.x;
-  if (a.done[i]) return;
+  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.km)) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
@@ -1153,7 +1314,8 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s;
   const int64_t ld = npad;
   const int64_t base = a.om_off[i];
-  const double* X = a.X + a.pad_off[i] * p + j0 * ld;
+  const double* X = a.ks ? a.V + a.pad_off[i] * (a.km + p) + a.jcur[i] * ld
+                         : a.X + a.pad_off[i] * p + j0 * ld;
   double* Y = a.Y + a.pad_off[i] * p + j0 * ld;
   const bool floating = a.kdim[i] != 0;
   const double* l = a.ell + a.pad_off[i];
@@ -1338,6 +1500,70 @@ __device__ __forceinline__ void sum_parts(const double* part, int b0, int b1, in
   __syncthreads();
 }
 
+// sum of the per-block partial vectors of cnt entries (stride ld) of blocks
+// b0..b1-1, in a fixed grouping; tmp holds EIG_T doubles of LDS
+__device__ __forceinline__ void sum_parts_n(const double* part, int64_t ld, int b0, int b1,
+                                            int cnt, double* out, double* tmp) {
+  const int t = threadIdx.x;
+  const int G = EIG_T / cnt;
+  const int e = t % cnt, g = t / cnt;
+  if (g < G) {
+    double sacc = 0.0;
+#pragma unroll 4
+    for (int bb = b0 + g; bb < b1; bb += G) sacc += part[(int64_t)bb * ld + e];
+    tmp[g * cnt + e] = sacc;
+  }
+  __syncthreads();
+  if (t < cnt) {
+    double sacc = 0.0;
+    for (int k = 0; k < G; ++k) sacc += tmp[k * cnt + t];
+    out[t] = sacc;
+  }
+  __syncthreads();
+}
+
+// out[x * ldo + y] = sum_{r < rows} U[r + x RB] V[r + y RB] for x < nu, y < nv
+// (U and V staged with zero columns up to a multiple of 4); 4 x 4 tiles per
+// wave as in block_gram
+__device__ __forceinline__ void block_gram_rect(const double* U, int nu, const double* V, int nv,
+                                                int rows, int RB, double* out, int ldo) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int qa = (nu + 3) >> 2, qb = (nv + 3) >> 2;
+  for (int tile = wv; tile < qa * qb; tile += EIG_T / 64) {
+    const int ta = tile / qb, tb = tile % qb;
+    const double* Ua = U + 4 * ta * RB;
+    const double* Vb = V + 4 * tb * RB;
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int r = lane; r < rows; r += 64) {
+      double u[4], v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        u[x] = Ua[r + x * RB];
+        v[x] = Vb[r + x * RB];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x * 4 + y] += u[x] * v[y];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[k] += __shfl_xor(acc[k], o, 64);
+    if (lane < 16) {
+      const int x = lane >> 2, y = lane & 3;
+      const int ra = 4 * ta + x, cb = 4 * tb + y;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k == lane) v = acc[k];
+      if (ra < nu && cb < nv) out[ra * ldo + cb] = v;
+    }
+  }
+}
+
 // partial Gram matrices of one row block: Y^T Y (and X^T Y for Rayleigh-Ritz)
 __global__ void __launch_bounds__(EIG_T) k_eig_gram(EigArgs a, int rr) {
   extern __shared__ double rbuf[];
@@ -1376,9 +1602,54 @@ __global__ void __launch_bounds__(EIG_T) k_eig_gram(EigArgs a, int rr) {
   if (rr) block_gram(Xs, Ys, rows, p, pq, RB, a.partH + (int64_t)b * PMAX * PMAX);
 }
 
-// one Cholesky QR pass on a row block: R^T R = sum of the partial Gram
-// matrices, then Y <- Y R^{-1} with the new block's partial Gram (pass 0), or
-// X <- Y R^{-1} (pass 1)
+// Cholesky factor R (upper, row-major) of G + shift I and its inverse for a
+// block of p <= EIG_PC columns, by one thread; returns 0 on a non-positive
+// pivot
+__device__ inline int chol_small(const double* G, double shift, double* R, double* Rinv, int p) {
+  int ok = 1;
+  for (int k = 0; k < p; ++k) {
+    double d = G[k * p + k] + shift;
+    for (int q = 0; q < k; ++q) d -= R[q * p + k] * R[q * p + k];
+    if (!(d > 0.0)) {
+      ok = 0;
+      d = 1e-300;
+    }
+    const double rkk = sqrt(d);
+    for (int j = 0; j < p; ++j) {
+      double v = 0.0;
+      if (j == k)
+        v = rkk;
+      else if (j > k) {
+        v = G[k * p + j];
+        for (int q = 0; q < k; ++q) v -= R[q * p + k] * R[q * p + j];
+        v /= rkk;
+      }
+      R[k * p + j] = v;
+    }
+  }
+  for (int j = 0; j < p; ++j)
+    for (int ii = p - 1; ii >= 0; --ii) {
+      double v = 0.0;
+      if (ii == j)
+        v = 1.0 / R[ii * p + ii];
+      else if (ii < j) {
+        for (int k = ii + 1; k <= j; ++k) v -= R[ii * p + k] * Rinv[k * p + j];
+        v /= R[ii * p + ii];
+      }
+      Rinv[ii * p + j] = v;
+    }
+  return ok;
+}
+
+__device__ __forceinline__ double ks_shift(const double* G, int p, int n) {
+  double tr = 0.0;
+  for (int k = 0; k < p; ++k) tr += G[k * p + k];
+  return 11.0 * ((double)n * p + p * (p + 1)) * 1.1102230246251565e-16 * tr;
+}
+
+// one Cholesky QR pass on a row block (block subspace iteration): R^T R = sum
+// of the partial Gram matrices, then Y <- Y R^{-1} with the new block's
+// partial Gram (pass 0), or X <- Y R^{-1} (pass 1)
 __global__ void __launch_bounds__(EIG_T) k_eig_orth(EigArgs a, int pass) {
   extern __shared__ double rbuf[];
   __shared__ double Gs[PMAX * PMAX];
@@ -1449,7 +1720,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a) {
     if (m + a.kdim[i] >= p) atomicOr(a.err, 16);
     a.msel[i] = m;
   }
-  double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
+  double* Vs = a.Vsel + (int64_t)i * VSEL;
   double* HV = a.HVs + (int64_t)i * PMAX * PMAX;
   for (int e = threadIdx.x; e < p * m; e += blockDim.x) {
     const int r = e % p, c = e / p;
@@ -1477,7 +1748,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_resid(EigArgs a) {
   const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
   const int m = a.msel[i];
   for (int e = threadIdx.x; e < p * m; e += blockDim.x) {
-    Vs[e] = a.Vsel[(int64_t)i * PMAX * PMAX + e];
+    Vs[e] = a.Vsel[(int64_t)i * VSEL + e];
     HV[e] = a.HVs[(int64_t)i * PMAX * PMAX + e];
   }
   double* Ys = rbuf;
@@ -1541,6 +1812,389 @@ __global__ void k_eig_decide(EigArgs a, int nsub, int sw, int final_sweep) {
   a.swlast[i] = sw;
 }
 
+// ---------------------------------------------------------------------------
+// Block Krylov-Schur.  Per subdomain a block Krylov decomposition
+//   T V_k = V_{k+p} Bk,   V_{k+p} = [V_k | V_res] orthonormal, Bk (k+p) x k,
+// is expanded block by block (columns jcur .. jcur+p-1 of V through the
+// operator, block classical Gram-Schmidt twice against V_{jcur+p}, Cholesky QR
+// twice for the new block), then the Rayleigh quotient H = Bk(0:k, 0:k) is
+// brought to ordered Schur form (wanted set, then the kept set), convergence
+// is judged from the residual block R = Bk(k:k+p, 0:k) on the wanted Schur
+// vectors, and otherwise the decomposition is restarted on the kept ones:
+//   V <- [V_k U | V_res],  Bk <- [U^T H U ; R U].
+// Row-block kernels per expansion step (W = the operator's output block),
+// block Gram-Schmidt twice with the QR of the block after each pass:
+//   k_ks_dots(0): deferred 1^perp projection of W, partial V^T W
+//   k_ks_upd(0): W -= V h1, Bk(:, jcur..) = h1, partial W^T W
+//   k_ks_qr(0 .. 2): W = Q1 R_A (shifted Cholesky QR three times)
+//   k_ks_dots(1): partial V^T Q1
+//   k_ks_upd(1): Q1 -= V h2, Bk(:, jcur..) += h2 R_A, partial Q1^T Q1
+//   k_ks_qr(3, 4): Q1 = V_new R_B (Cholesky QR twice), Bk subdiagonal R_B R_A
+//   k_ks_advance: jcur += p
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool ks_active(const EigArgs& a, int i) {
+  return !a.done[i] && a.jcur[i] + a.p <= a.km;
+}
+
+// partial V^T Y of one row block (pass 0: the operator's output, after the
+// deferred projection onto 1^perp; pass 1: the block Q1 of the first pass)
+__global__ void __launch_bounds__(EIG_T) k_ks_dots(EigArgs a, int pass) {
+  extern __shared__ double rbuf[];
+  __shared__ double mu[EIG_PC];
+  const int b = blockIdx.x, i = a.blk_sub[b];
+  if (!ks_active(a, i)) return;
+  const int p = a.p, J = a.jcur[i] + p, lrb = a.lrb, RB = 1 << lrb;
+  if (J == 0) return;
+  const int r0 = a.blk_r0[b], rows = min(RB, a.ni[i] - r0);
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  double* Wg = a.Y + a.pad_off[i] * p;
+  const double* Vg = a.V + a.pad_off[i] * (a.km + p);
+  double* Ws = rbuf;
+  double* Vs = rbuf + RB * EIG_PC;
+  stage_rows(Wg, ld, r0, rows, p, EIG_PC, lrb, Ws);
+  stage_rows(Vg, ld, r0, rows, J, (J + 3) & ~3, lrb, Vs);
+  if (pass == 0 && a.defer && a.kdim[i]) {
+    // projection onto 1^perp left by the two-ended operator (one column chunk)
+    if ((int)threadIdx.x < p)
+      mu[threadIdx.x] = (a.colsum[(int64_t)i * 2 * EIG_PC + threadIdx.x] +
+                         a.colsum[(int64_t)i * 2 * EIG_PC + EIG_PC + threadIdx.x]) /
+                        a.ni[i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < RB * p; e += EIG_T) {
+      const int r = e & (RB - 1), c = e >> lrb;
+      if (r < rows) {
+        const double v = Ws[e] - mu[c];
+        Ws[e] = v;
+        Wg[r0 + r + c * ld] = v;
+      }
+    }
+  }
+  __syncthreads();
+  block_gram_rect(Vs, J, Ws, p, rows, RB, (pass ? a.partK2 : a.partK) + (int64_t)b * KS_PK, p);
+}
+
+// Y <- Y - V h with h the summed partial products, and the partial Gram
+// matrix of the result.  Coefficients (first block of the subdomain):
+// pass 0: Bk(0:J, jcur ..) = h; pass 1: Bk(0:J, jcur ..) += h R_A, where R_A
+// is the triangular factor of the first pass's QR.  With no basis yet (the
+// start block) only the Gram matrix is formed.
+__global__ void __launch_bounds__(EIG_T) k_ks_upd(EigArgs a, int pass) {
+  extern __shared__ double rbuf[];
+  __shared__ double h[KS_PK];
+  __shared__ double tmp[EIG_T];
+  const int b = blockIdx.x, i = a.blk_sub[b];
+  if (!ks_active(a, i)) return;
+  const int p = a.p, jc = a.jcur[i], J = jc + p, lrb = a.lrb, RB = 1 << lrb;
+  const int r0 = a.blk_r0[b], rows = min(RB, a.ni[i] - r0);
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  double* Wg = a.Y + a.pad_off[i] * p;
+  const double* Vg = a.V + a.pad_off[i] * (a.km + p);
+  double* Ws = rbuf;
+  double* Vs = rbuf + RB * EIG_PC;
+  stage_rows(Wg, ld, r0, rows, p, EIG_PC, lrb, Ws);
+  if (J > 0) {
+    stage_rows(Vg, ld, r0, rows, J, (J + 3) & ~3, lrb, Vs);
+    sum_parts_n(pass ? a.partK2 : a.partK, KS_PK, a.sub_blk0[i], a.sub_blk0[i + 1], J * p, h, tmp);
+    if (b == a.sub_blk0[i] && jc >= 0) {
+      const double* RA = a.Racc + (int64_t)i * 2 * EIG_PC * EIG_PC;
+      for (int e = threadIdx.x; e < J * p; e += EIG_T) {
+        const int r = e / p, cc = e % p;
+        double* dst = a.Bk + (int64_t)i * KS_BS + (int64_t)r * a.km + jc + cc;
+        if (pass == 0) {
+          *dst = h[e];
+        } else {
+          double v = 0.0;
+          for (int q = 0; q <= cc; ++q) v += h[r * p + q] * RA[q * p + cc];
+          *dst += v;
+        }
+      }
+    }
+    for (int e = threadIdx.x; e < RB * EIG_PC; e += EIG_T) {
+      const int r = e & (RB - 1), c = e >> lrb;
+      if (c < p && r < rows) {
+        double v = Ws[e];
+        for (int q = 0; q < J; ++q) v -= Vs[r + q * RB] * h[q * p + c];
+        Ws[e] = v;
+        Wg[r0 + r + c * ld] = v;
+      }
+    }
+  }
+  __syncthreads();
+  block_gram_rect(Ws, p, Ws, p, rows, RB, a.partA + (int64_t)b * PMAX * PMAX, p);
+}
+
+// one Cholesky QR pass of the new block W (p <= EIG_PC columns, in Y) on a
+// wide row block (KS_QT threads, KS_QR rows each; W rows held in registers).
+// Steps 0..2: shifted Cholesky QR three times of the first Gram-Schmidt
+// pass's block (the first Cholesky of G + s I, s = 11 (n p + p (p + 1)) u
+// tr(G), as in the shifted CholeskyQR3 of Fukaya, Kannan, Nakatsukasa,
+// Yamamoto and Yanagisawa, which stays backward stable when the block is
+// numerically rank deficient, e.g. an exhausted Krylov direction); steps 3..4:
+// Cholesky QR twice of the second pass's block, the last one into
+// V(:, J .. J+p-1).  Steps 0 and 3 read the Gram partials of k_ks_upd (its
+// row blocks); the others those of the previous step (these row blocks).  The
+// first block of each subdomain accumulates the triangular factors (R_A of
+// steps 0..2, R_B of steps 3..4) and finally writes R_B R_A into Bk.
+static constexpr int KS_QT = 256;
+static constexpr int KS_QR = 4;
+static constexpr int KS_QRB = KS_QT * KS_QR;  // rows per block
+
+__global__ void __launch_bounds__(KS_QT) k_ks_qr(EigArgs a, int step) {
+  constexpr int PC = EIG_PC;
+  __shared__ double Gs[PC * PC];
+  __shared__ double Rs[PC * PC];
+  __shared__ double Ri[PC * PC];
+  __shared__ double tmp[KS_QT];
+  __shared__ double wred[KS_QT / 64][10];
+  const int b = blockIdx.x, i = a.qblk_sub[b];
+  if (!ks_active(a, i)) return;
+  const int t = threadIdx.x;
+  const int p = a.p, n = a.ni[i];
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  const int jc = a.jcur[i], J = jc + p;
+  const int r0 = a.qblk_r0[b];
+  double* Y = a.Y + a.pad_off[i] * p;
+  double y[KS_QR][PC];
+#pragma unroll
+  for (int k = 0; k < KS_QR; ++k) {
+    const int r = r0 + t + k * KS_QT;
+#pragma unroll
+    for (int c = 0; c < PC; ++c) y[k][c] = (r < n && c < p) ? Y[r + c * ld] : 0.0;
+  }
+  const bool from_upd = step == 0 || step == 3;
+  const double* gin = from_upd ? a.partA : ((step == 1 || step == 4) ? a.partB : a.partH);
+  const int g0 = from_upd ? a.sub_blk0[i] : a.qsub_blk0[i];
+  const int g1 = from_upd ? a.sub_blk0[i + 1] : a.qsub_blk0[i + 1];
+  {  // Gram matrix: KS_QT / 16 groups of 16 threads over the partials
+    const int e = t & 15, g = t >> 4, G = KS_QT / 16;
+    double sacc = 0.0;
+    for (int bb = g0 + g; bb < g1; bb += G) sacc += gin[(int64_t)bb * PMAX * PMAX + e];
+    tmp[t] = sacc;
+    __syncthreads();
+    if (t < 16) {
+      double v = 0.0;
+      for (int k = 0; k < G; ++k) v += tmp[k * 16 + t];
+      if (t < p * p) Gs[t] = v;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double sh = step == 0 ? ks_shift(Gs, p, n) : 0.0;
+    if (!chol_small(Gs, sh, Rs, Ri, p)) atomicOr(a.err, 2);
+  }
+  __syncthreads();
+  if (b == a.qsub_blk0[i] && t < 64) {
+    // accumulate R <- R_step R (first step of a chain: R <- R_step)
+    double* acc = a.Racc + (int64_t)i * 2 * PC * PC + (step >= 3 ? PC * PC : 0);
+    const bool first = step == 0 || step == 3;
+    double v = 0.0;
+    if (t < p * p) {
+      const int r = t / p, cc = t % p;
+      if (first)
+        v = Rs[t];
+      else
+        for (int q = r; q <= cc; ++q) v += Rs[r * p + q] * acc[q * p + cc];
+    }
+    WAVE_SYNC();
+    if (t < p * p) acc[t] = v;
+    if (step == 4 && jc >= 0 && t < p * p) {
+      // subdiagonal block R_B R_A (R_B = v just formed, R_A the other slot)
+      __shared__ double RB_[PC * PC];
+      RB_[t] = v;
+      WAVE_SYNC();
+      const double* RA = a.Racc + (int64_t)i * 2 * PC * PC;
+      const int r = t / p, cc = t % p;
+      double w = 0.0;
+      for (int q = r; q <= cc; ++q) w += RB_[r * p + q] * RA[q * p + cc];
+      a.Bk[(int64_t)i * KS_BS + (int64_t)(J + r) * a.km + jc + cc] = w;
+    }
+  }
+  double* out = step == 4 ? a.V + a.pad_off[i] * (a.km + p) + (int64_t)J * ld : Y;
+  double gl[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) gl[q] = 0.0;
+#pragma unroll
+  for (int k = 0; k < KS_QR; ++k) {
+    const int r = r0 + t + k * KS_QT;
+    double z[PC];
+#pragma unroll
+    for (int c = 0; c < PC; ++c) {
+      double v = 0.0;
+      if (c < p)
+#pragma unroll
+        for (int q = 0; q <= c; ++q) v += y[k][q] * Ri[q * p + c];
+      z[c] = v;
+    }
+    if (r < n)
+#pragma unroll
+      for (int c = 0; c < PC; ++c)
+        if (c < p) out[r + c * ld] = z[c];
+    int q = 0;
+#pragma unroll
+    for (int c1 = 0; c1 < PC; ++c1)
+#pragma unroll
+      for (int c2 = c1; c2 < PC; ++c2) gl[q++] += z[c1] * z[c2];
+  }
+  if (step == 2 || step == 4) return;
+  // partial Gram of this block: wave butterflies, then the waves in order
+#pragma unroll
+  for (int q = 0; q < 10; ++q)
+    for (int o = 32; o > 0; o >>= 1) gl[q] += __shfl_xor(gl[q], o, 64);
+  if ((t & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) wred[t >> 6][q] = gl[q];
+  __syncthreads();
+  if (t < PC * PC) {
+    const int c1 = t / PC, c2 = t % PC;
+    const int lo = min(c1, c2), hi = max(c1, c2);
+    const int q = lo * PC - lo * (lo - 1) / 2 + (hi - lo);
+    double v = 0.0;
+    for (int w = 0; w < KS_QT / 64; ++w) v += wred[w][q];
+    if (c1 < p && c2 < p)
+      (step == 0 || step == 3 ? a.partB : a.partH)[(int64_t)b * PMAX * PMAX + c1 * p + c2] = v;
+  }
+}
+
+__global__ void k_ks_advance(EigArgs a, int nsub) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsub || !ks_active(a, i)) return;
+  if (a.jcur[i] >= 0) a.sweeps[i] += 1;
+  a.jcur[i] += a.p;
+}
+
+// Schur form of the Rayleigh quotient, convergence test and restart data (one
+// workgroup per subdomain).  Converged: ||R V1||_F / min |lambda| below the
+// tolerance (V1 the wanted Schur basis), or stagnated within 100x of it (three
+// restarts without a 5% gain on the best residual).
+__global__ void __launch_bounds__(EIG_T) k_ks_rr(EigArgs a, int final_cycle) {
+  __shared__ SmallEigLds se;
+  __shared__ double H[PMAX * PMAX];
+  __shared__ double Rb[EIG_PC * PMAX];
+  __shared__ double V2[PMAX * PMAX];
+  __shared__ double lam_re[PMAX], lam_im[PMAX];
+  __shared__ double red[16];
+  __shared__ int flag[4];
+  const int i = blockIdx.x;
+  if (a.done[i]) return;
+  const int t = threadIdx.x;
+  const int p = a.p, km = a.km, m = a.jcur[i];
+  double* B = a.Bk + (int64_t)i * KS_BS;
+  for (int e = t; e < m * m; e += EIG_T) H[e] = B[(e / m) * km + e % m];
+  for (int e = t; e < p * m; e += EIG_T) Rb[e] = B[(m + e / m) * km + e % m];
+  __syncthreads();
+  if (t < 64) {
+    int ok = 1, mk = 0;
+    double gap = 1.0;
+    const int m1 = small_eig_select(m, H, a.nev - a.kdim[i], a.tau, se, lam_re, lam_im, &ok, &gap,
+                                    a.kkeep - a.kdim[i], &mk, V2);
+    if (t == 0) {
+      flag[0] = m1;
+      flag[1] = ok;
+      flag[2] = mk;
+    }
+  }
+  __syncthreads();
+  const int m1 = flag[0], mk = flag[2];
+  double r2 = 0.0;
+  for (int e = t; e < p * m1; e += EIG_T) {
+    const int r = e % p, cc = e / p;
+    double v = 0.0;
+    for (int k = 0; k < m; ++k) v += Rb[r * m + k] * se.V[cc * m + k];
+    r2 += v * v;
+  }
+  r2 = adsd::block_sum(r2, red);
+  if (t == 0) {
+    if (!flag[1]) atomicOr(a.err, 4);
+    double lmin = 1e300;
+    for (int cc = 0; cc < m1; ++cc) lmin = fmin(lmin, hypot(lam_re[cc], lam_im[cc]));
+    const double rel = m1 ? sqrt(r2) / lmin : 0.0;
+    const double best = a.rbest[i];
+    const bool gain = !(best > 0.0) || rel < 0.95 * best;
+    const int stall = (m1 && !gain) ? a.stall[i] + 1 : 0;
+    const bool ok_tol = (m1 == 0) || (rel <= a.tol) || (rel <= 100.0 * a.tol && stall >= 3);
+    a.rres[i] = rel;
+    if (gain) a.rbest[i] = rel;
+    a.stall[i] = stall;
+    int fin = 0;
+    if (ok_tol || final_cycle) fin = ok_tol ? 1 : 2;
+    // the wanted cluster must leave a Ritz value outside it, and a restart
+    // must leave room for at least one more block
+    if (m1 >= m || (!fin && (mk > km - p || mk < m1))) {
+      atomicOr(a.err, 16);
+      fin = 2;
+    }
+    if (fin) a.done[i] = fin;
+    a.msel[i] = m1;
+    flag[3] = fin;
+  }
+  __syncthreads();
+  if (flag[3]) {
+    // Ritz basis in V coordinates, zero below row m (stride km + p)
+    const int ldv = km + p;
+    double* Vs = a.Vsel + (int64_t)i * VSEL;
+    for (int e = t; e < ldv * m1; e += EIG_T) {
+      const int r = e % ldv, cc = e / ldv;
+      Vs[e] = r < m ? se.V[cc * m + r] : 0.0;
+    }
+    double* lam = a.lam + (int64_t)i * 2 * PMAX;
+    for (int cc = t; cc < m1; cc += EIG_T) {
+      lam[cc] = lam_re[cc];
+      lam[PMAX + cc] = lam_im[cc];
+    }
+    return;
+  }
+  // restart on the kept Schur basis U = V2 (m x mk): HU in se.Pm
+  for (int e = t; e < m * mk; e += EIG_T) {
+    const int r = e % m, cc = e / m;
+    double v = 0.0;
+    for (int k = 0; k < m; ++k) v += H[r * m + k] * V2[cc * m + k];
+    se.Pm[e] = v;
+    a.Ures[(int64_t)i * PMAX * PMAX + e] = V2[e];
+  }
+  __syncthreads();
+  for (int e = t; e < (km + p) * km; e += EIG_T) {
+    const int r = e / km, cc = e % km;
+    double v = 0.0;
+    if (cc < mk && r < mk)
+      for (int k = 0; k < m; ++k) v += V2[r * m + k] * se.Pm[cc * m + k];
+    else if (cc < mk && r < mk + p)
+      for (int k = 0; k < m; ++k) v += Rb[(r - mk) * m + k] * V2[cc * m + k];
+    B[e] = v;
+  }
+  if (t == 0) {
+    a.kprev[i] = m;
+    a.jcur[i] = mk;
+  }
+}
+
+// V <- [V_m U | V(:, m .. m+p-1)] on one row block (restarted subdomains)
+__global__ void __launch_bounds__(EIG_T) k_ks_restart(EigArgs a) {
+  extern __shared__ double rbuf[];
+  __shared__ double U[PMAX * PMAX];
+  const int b = blockIdx.x, i = a.blk_sub[b];
+  if (a.done[i]) return;
+  const int p = a.p, m = a.kprev[i], mk = a.jcur[i], lrb = a.lrb, RB = 1 << lrb;
+  const int r0 = a.blk_r0[b], rows = min(RB, a.ni[i] - r0);
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  double* Vg = a.V + a.pad_off[i] * (a.km + p);
+  double* Vs = rbuf;
+  stage_rows(Vg, ld, r0, rows, m + p, (m + p + 3) & ~3, lrb, Vs);
+  for (int e = threadIdx.x; e < m * mk; e += EIG_T) U[e] = a.Ures[(int64_t)i * PMAX * PMAX + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < RB * (mk + p); e += EIG_T) {
+    const int r = e & (RB - 1), cc = e >> lrb;
+    if (r >= rows) continue;
+    double v;
+    if (cc < mk) {
+      v = 0.0;
+      for (int k = 0; k < m; ++k) v += Vs[r + k * RB] * U[cc * m + k];
+    } else {
+      v = Vs[r + (m + cc - mk) * RB];
+    }
+    Vg[r0 + r + cc * ld] = v;
+  }
+}
+
 // W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
 __global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* W_off, double* W) {
   __shared__ EigShared S;
@@ -1556,7 +2210,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* 
   if (cols == 0) return;
   // Z (interior rows, column-major nint x cols) in the Y buffer (npad x p >= nint x cols)
   double* Z = a.Y + a.pad_off[i] * p;
-  const double* Vs = a.Vsel + (int64_t)i * PMAX * PMAX;
+  const double* Vs = a.Vsel + (int64_t)i * VSEL;
   // interior rows in ascending local order: chunked block scan of the flags
   __shared__ int wtot[EIG_T / 64];
   int run = 0;
@@ -1675,18 +2329,104 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   ADS_HIP(hipStreamSynchronize(st));
 }
 
+// block Krylov-Schur driver (block width a.p = EIG_PC)
+template <class FT>
+static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub;
+  int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
+  double* scratch = nullptr;
+  if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
+  const bool cpl = c.cpl_ok && c.ucpl_row != nullptr;
+  const size_t init_lds =
+      cpl ? (size_t)(2 * smax + EIG_T + (smax * adsd::NCPL + 1) / 2 + smax * adsd::NCPL + 8) * 8
+          : (size_t)2 * smax * sizeof(double);
+  const int RB = 1 << a.lrb;
+  const unsigned nqblk = (unsigned)c.h_eig_nqblk;
+  const size_t ks_lds = (size_t)RB * (EIG_PC + KS_W) * sizeof(double);
+  const unsigned nblk = (unsigned)c.h_eig_nblk;
+  const unsigned g64 = (unsigned)((nsub + 63) / 64);
+  constexpr int PC = EIG_PC;
+  const bool fast = c.solve_fast;
+  const size_t op_lds =
+      fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
+           : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
+  if (cpl)
+    ADS_LAUNCH((k_eig_init<FT, true>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
+  else
+    ADS_LAUNCH((k_eig_init<FT, false>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
+  if (fast)
+    ADS_LAUNCH(k_eig_btl, dim3(nsub), dim3(256), 0, st, a, c.om_sorted, c.rowptr, c.col, c.val,
+               c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
+  // block classical Gram-Schmidt twice of the operator's output against V,
+  // each pass followed by the QR of the block (Barlow-Smoktunowicz BCGS2)
+  auto orth_block = [&]() {
+    ADS_LAUNCH(k_ks_dots, dim3(nblk), dim3(EIG_T), ks_lds, st, a, 0);
+    ADS_LAUNCH(k_ks_upd, dim3(nblk), dim3(EIG_T), ks_lds, st, a, 0);
+    for (int q = 0; q < 3; ++q) ADS_LAUNCH(k_ks_qr, dim3(nqblk), dim3(KS_QT), 0, st, a, q);
+    ADS_LAUNCH(k_ks_dots, dim3(nblk), dim3(EIG_T), ks_lds, st, a, 1);
+    ADS_LAUNCH(k_ks_upd, dim3(nblk), dim3(EIG_T), ks_lds, st, a, 1);
+    for (int q = 3; q < 5; ++q) ADS_LAUNCH(k_ks_qr, dim3(nqblk), dim3(KS_QT), 0, st, a, q);
+    ADS_LAUNCH(k_ks_advance, dim3(g64), dim3(64), 0, st, a, nsub);
+  };
+  auto step = [&]() {
+    if (fast) {
+      constexpr int D = 2;
+      ADS_LAUNCH((k_eig_op_fwd<FT, PC, D>), dim3(nsub, 1, 2), dim3(adsd::SOLVE_T), op_lds, st, fac,
+                 a);
+      ADS_LAUNCH((k_eig_op_bwd<FT, PC, D>), dim3(nsub, 1, 2), dim3(adsd::SOLVE_T), op_lds, st, fac,
+                 a);
+    } else {
+      ADS_LAUNCH((k_eig_op<FT, PC>), dim3(nsub, 1), dim3(EIG_T), op_lds, st, fac, a);
+    }
+    orth_block();
+  };
+  orth_block();  // start block into V(:, 0 .. p-1)
+  const int maxsteps = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
+  std::vector<int32_t> hdone(nsub, 0), hj(nsub, 0);
+  int total = 0;
+  for (int cyc = 0;; ++cyc) {
+    int nst = 0;
+    for (int i = 0; i < nsub; ++i)
+      if (!hdone[i] && hj[i] + a.p <= a.km) nst = std::max(nst, (a.km - a.p - hj[i]) / a.p + 1);
+    for (int k = 0; k < nst; ++k) step();
+    total += nst;
+    ADS_LAUNCH(k_ks_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)(total >= maxsteps));
+    download(hdone, a.done, nsub, st);
+    bool all = true;
+    for (int i = 0; i < nsub; ++i) all &= hdone[i] != 0;
+    if (all) break;
+    download(hj, a.jcur, nsub, st);
+    ADS_LAUNCH(k_ks_restart, dim3(nblk), dim3(EIG_T), ks_lds, st, a);
+  }
+  ADS_HIP(hipStreamSynchronize(st));
+}
+
 void eigensolve(Ctx& c) {
   hipStream_t st = c.stream;
   const int nsub = c.nsub;
   const int nev = c.opt.nev;
+  // block subspace iteration: block of p columns
   int p = std::min(PMAX, std::max(2 * nev, nev + 8));
   p = (p + 3) / 4 * 4;
   p = std::min(p, PMAX);
   int minfree = 1 << 30;
   for (int i = 0; i < nsub; ++i) minfree = std::min(minfree, c.h_ni[i] - c.h_kdim[i] - 1);
   p = std::min(p, minfree);
-  if (p < nev + 1)
+  // block Krylov-Schur: Rayleigh quotients up to km, restarts keep kkeep
+  // (before the cluster rule); the basis must fit in the range of the
+  // operator (interior rows) of every subdomain
+  int km = std::min(PMAX, std::max(3 * nev, nev + 16));
+  for (int i = 0; i < nsub; ++i)
+    km = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
+  const int kkeep = (km + nev) / 2;
+  const bool ks = c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && km >= nev + 2 * EIG_PC &&
+                  kkeep + EIG_PC <= km;
+  if (!ks && p < nev + 1)
     fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
+  c.eig_krylov_schur = ks;
+  const int pw = ks ? EIG_PC : p;  // columns per operator application
+  const int ncol = ks ? km + EIG_PC : p;  // columns of the basis / output blocks
   EigArgs a{};
   a.fac_off = c.fac_off;
   a.bs = c.bs;
@@ -1708,11 +2448,18 @@ void eigensolve(Ctx& c) {
   a.ucpl_val = c.ucpl_val;
   a.lcpl_row = c.lcpl_row;
   a.lcpl_val = c.lcpl_val;
-  const int nch = (p + EIG_PC - 1) / EIG_PC;
+  const int nch = (pw + EIG_PC - 1) / EIG_PC;
   a.dummy = c.mem.alloc<double>((size_t)nsub * nch * 2 * 1024);
-  a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
-  a.Y = c.mem.alloc<double>((size_t)c.npad_total * p);
-  a.W = c.solve_fast ? c.mem.alloc<double>((size_t)c.npad_total * p) : nullptr;
+  if (ks) {
+    a.V = c.mem.alloc<double>((size_t)c.npad_total * ncol);
+    a.X = a.V;
+    ADS_HIP(hipMemsetAsync(a.V, 0, (size_t)c.npad_total * ncol * 8, st));
+  } else {
+    a.X = c.mem.alloc<double>((size_t)c.npad_total * p);
+    ADS_HIP(hipMemsetAsync(a.X, 0, (size_t)c.npad_total * p * 8, st));
+  }
+  a.Y = c.mem.alloc<double>((size_t)c.npad_total * ncol);
+  a.W = c.solve_fast ? c.mem.alloc<double>((size_t)c.npad_total * pw) : nullptr;
   a.ell = c.mem.alloc<double>(c.npad_total);
   a.bell = c.mem.alloc<double>(c.npad_total);
   a.btl = c.mem.alloc<double>(c.npad_total);
@@ -1723,7 +2470,7 @@ void eigensolve(Ctx& c) {
   a.done = c.mem.alloc<int32_t>(nsub);
   a.sweeps = c.mem.alloc<int32_t>(nsub);
   a.msel = c.mem.alloc<int32_t>(nsub);
-  a.Vsel = c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
+  a.Vsel = c.mem.alloc<double>((size_t)nsub * VSEL);
   a.lam = c.mem.alloc<double>((size_t)nsub * 2 * PMAX);
   a.rres = c.mem.alloc<double>(nsub);
   a.rbest = c.mem.alloc<double>(nsub);
@@ -1734,9 +2481,9 @@ void eigensolve(Ctx& c) {
   ADS_HIP(hipMemsetAsync(a.rlast, 0, nsub * 8, st));
   ADS_HIP(hipMemsetAsync(a.swlast, 0, nsub * 4, st));
   a.next_rr = c.mem.alloc<int32_t>(nsub);
-  a.HVs = c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
+  a.HVs = ks ? nullptr : c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
   // row blocks
-  a.lrb = rb_log2(p);
+  a.lrb = ks ? rb_log2(KS_W + EIG_PC) : rb_log2(p);
   std::vector<int32_t> blk_sub, blk_r0, sub_blk0(nsub + 1, 0);
   for (int i = 0; i < nsub; ++i) {
     sub_blk0[i] = (int32_t)blk_sub.size();
@@ -1750,14 +2497,42 @@ void eigensolve(Ctx& c) {
   a.blk_sub = upload(c.mem, blk_sub.data(), blk_sub.size(), st);
   a.blk_r0 = upload(c.mem, blk_r0.data(), blk_r0.size(), st);
   a.sub_blk0 = upload(c.mem, sub_blk0.data(), nsub + 1, st);
+  if (ks) {  // wide row blocks of the block QR passes
+    std::vector<int32_t> qb_sub, qb_r0, qsub0(nsub + 1, 0);
+    for (int i = 0; i < nsub; ++i) {
+      qsub0[i] = (int32_t)qb_sub.size();
+      for (int r0 = 0; r0 < c.h_ni[i]; r0 += KS_QRB) {
+        qb_sub.push_back(i);
+        qb_r0.push_back(r0);
+      }
+    }
+    qsub0[nsub] = (int32_t)qb_sub.size();
+    c.h_eig_nqblk = (int)qb_sub.size();
+    a.qblk_sub = upload(c.mem, qb_sub.data(), qb_sub.size(), st);
+    a.qblk_r0 = upload(c.mem, qb_r0.data(), qb_r0.size(), st);
+    a.qsub_blk0 = upload(c.mem, qsub0.data(), nsub + 1, st);
+  }
   a.partA = c.mem.alloc<double>((size_t)c.h_eig_nblk * PMAX * PMAX);
   a.partB = c.mem.alloc<double>((size_t)c.h_eig_nblk * PMAX * PMAX);
   a.partH = c.mem.alloc<double>((size_t)c.h_eig_nblk * PMAX * PMAX);
   a.partR = c.mem.alloc<double>(c.h_eig_nblk);
-  ADS_HIP(hipMemsetAsync(a.X, 0, (size_t)c.npad_total * p * 8, st));
+  if (ks) {
+    a.ks = 1;
+    a.km = km;
+    a.kkeep = kkeep;
+    a.Bk = c.mem.alloc<double>((size_t)nsub * KS_BS);
+    ADS_HIP(hipMemsetAsync(a.Bk, 0, (size_t)nsub * KS_BS * 8, st));
+    std::vector<int32_t> j0(nsub, -EIG_PC);
+    a.jcur = upload(c.mem, j0.data(), nsub, st);
+    a.kprev = c.mem.alloc<int32_t>(nsub);
+    a.partK = c.mem.alloc<double>((size_t)c.h_eig_nblk * KS_PK);
+    a.partK2 = c.mem.alloc<double>((size_t)c.h_eig_nblk * KS_PK);
+    a.Ures = c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
+    a.Racc = c.mem.alloc<double>((size_t)nsub * 2 * EIG_PC * EIG_PC);
+  }
   ADS_HIP(hipMemsetAsync(a.stall, 0, nsub * 4, st));
   a.err = c.mem.alloc<int32_t>(1);
-  a.p = p;
+  a.p = pw;
   a.nev = nev;
   a.tau = c.opt.tau;
   a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
@@ -1767,10 +2542,21 @@ void eigensolve(Ctx& c) {
   ADS_HIP(hipMemsetAsync(a.err, 0, 4, st));
   ADS_HIP(hipMemsetAsync(a.ell, 0, c.npad_total * 8, st));
   ADS_HIP(hipMemsetAsync(a.bell, 0, c.npad_total * 8, st));
-  switch (c.prec) {
-    case ADS_PREC_FP64: eig_run<double>(c, a, (const double*)c.facT); break;
-    case ADS_PREC_FP32: eig_run<float>(c, a, (const float*)c.facT); break;
-    default: eig_run<__hip_bfloat16>(c, a, (const __hip_bfloat16*)c.facT); break;
+  if (ks) {
+    switch (c.prec) {
+      case ADS_PREC_FP64: eig_run_ks<double>(c, a, (const double*)c.facT); break;
+      case ADS_PREC_FP32: eig_run_ks<float>(c, a, (const float*)c.facT); break;
+      default: eig_run_ks<__hip_bfloat16>(c, a, (const __hip_bfloat16*)c.facT); break;
+    }
+    // the Ritz bases are in V coordinates
+    a.X = a.V;
+    a.p = ncol;
+  } else {
+    switch (c.prec) {
+      case ADS_PREC_FP64: eig_run<double>(c, a, (const double*)c.facT); break;
+      case ADS_PREC_FP32: eig_run<float>(c, a, (const float*)c.facT); break;
+      default: eig_run<__hip_bfloat16>(c, a, (const __hip_bfloat16*)c.facT); break;
+    }
   }
   std::vector<int32_t> herr, hm, hsw, hdone;
   download(herr, a.err, 1, st);
@@ -1794,7 +2580,7 @@ void eigensolve(Ctx& c) {
   c.h_coff.assign(nsub + 1, 0);
   c.h_W_off.assign(nsub + 1, 0);
   for (int i = 0; i < nsub; ++i) {
-    if (hm[i] + c.h_kdim[i] > p)
+    if (hm[i] + c.h_kdim[i] > (ks ? km : p))
       fail(ADS_ERR_UNSUPPORTED, "eigenvalue cluster at the cut exceeds the subspace size in subdomain " +
                                     std::to_string(i));
     c.h_nev[i] = hm[i] + c.h_kdim[i];
@@ -1827,7 +2613,8 @@ void eigensolve(Ctx& c) {
   ADS_HIP(hipStreamSynchronize(st));
   for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.W, (void*)a.partA, (void*)a.partB,
                   (void*)a.partH, (void*)a.partR, (void*)a.HVs, (void*)a.btl, (void*)a.colsum,
-                  (void*)a.dummy})
+                  (void*)a.dummy, (void*)a.Bk, (void*)a.partK, (void*)a.partK2, (void*)a.Ures,
+                  (void*)a.Racc})
     if (q) c.mem.release(q);
 
 }

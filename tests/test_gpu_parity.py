@@ -79,12 +79,16 @@ def test_maps_and_splitting_bit_exact(case):
     ctx.close()
 
 
+@pytest.mark.parametrize("solver", [ads.ADS_EIG_KRYLOV_SCHUR, ads.ADS_EIG_SUBSPACE],
+                         ids=["krylov-schur", "subspace"])
 @pytest.mark.parametrize("case", CASES, ids=IDS)
-def test_coarse_space_matches_oracle(case):
+def test_coarse_space_matches_oracle(case, solver):
     name, A, part, N, ov, nev, restart, flex = case
-    ctx = ads.Context(A, part, N, ov, nev)
+    ctx = ads.Context(A, part, N, ov, nev, eig_solver=solver)
     P = oracle_for(case)
     Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+    if nev:
+        assert info["eig_solver"] == solver
     np.testing.assert_array_equal(info["nev_i"], P.nev_i)
     assert info["n0"] == P.n0
     assert info["eig_unconverged"] == 0
@@ -279,9 +283,6 @@ def test_graph_solve_matches_direct_launches():
         assert torch.equal(x, out[0][0])
 
 
-@pytest.mark.skip(reason="the block subspace iteration stagnates when the eigenvalues of eq. 5 "
-                         "accumulate at 1 (small 2D subdomains, nev 10); enabled with the "
-                         "Krylov-Schur eigensolver")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batched_bfs3d_and_2d_family(prec):
     """The batched workload's shape at test size: a 3D upwind
