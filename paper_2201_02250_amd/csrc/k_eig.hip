@@ -167,14 +167,16 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
   }
   // Francis double-shift QR to real Schur form (1x1 and 2x2 diagonal
   // blocks), T <- Z^T H Z
-  int hi = p - 1, its = 0, total = 0, ok = 1;
+  int hi = p - 1, its = 0, total = 0, ok = 1, l = 0;
   while (hi >= 1) {
-    int l = hi;
-    while (l > 0) {  // normwise deflation test (only the largest |lambda| matter)
-      const double sub = fabs(T[l * ld + l - 1]);
-      const double dd = fmax(fabs(T[(l - 1) * ld + l - 1]) + fabs(T[l * ld + l]), anorm);
-      if (sub <= eps * dd) break;
-      --l;
+    // window start l: the last negligible subdiagonal entry at or above hi
+    // (normwise test: only the largest |lambda| matter); one lane per row
+    const double subl = (lane >= 1 && lane <= hi) ? fabs(T[lane * ld + lane - 1]) : 0.0;
+    {
+      const bool neg = lane >= 1 && lane <= hi &&
+                       subl <= eps * fmax(fabs(T[(lane - 1) * ld + lane - 1]) + fabs(T[lane * ld + lane]), anorm);
+      const unsigned long long bm = __ballot(neg);
+      l = bm ? 63 - __clzll(bm) : 0;
     }
     WAVE_SYNC();
     if (l > 0 && lane == 0) T[l * ld + l - 1] = 0.0;
@@ -182,10 +184,17 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
     if (l < hi - 1 && its >= 20) {
       // stagnation on a tight cluster: split the window at its smallest
       // subdiagonal entry if that is at the rounding level of the matrix
-      int kb = l + 1;
-      for (int k = l + 2; k <= hi; ++k)
-        if (fabs(T[k * ld + k - 1]) < fabs(T[kb * ld + kb - 1])) kb = k;
-      if (fabs(T[kb * ld + kb - 1]) <= 1e3 * eps * anorm) {
+      double bv = (lane > l && lane <= hi) ? subl : 1e300;
+      int kb = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int ok2 = __shfl_xor(kb, o, 64);
+        if (ov < bv || (ov == bv && ok2 < kb)) {
+          bv = ov;
+          kb = ok2;
+        }
+      }
+      if (bv <= 1e3 * eps * anorm) {
         WAVE_SYNC();
         if (lane == 0) T[kb * ld + kb - 1] = 0.0;
         WAVE_SYNC();
@@ -230,30 +239,44 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
     // first column of (T - s1)(T - s2) at the start row mm: the lowest row
     // (>= l) where the bulge it creates is negligible against h(mm, mm-1), so
     // two consecutive small subdiagonal entries do not stall the iteration
-    int mm = hi - 2;
+    // (one lane per candidate row, the highest acceptable one is taken)
+    int mm;
     double x, y, z;
-    for (;;) {
-      const double h00 = T[mm * ld + mm], h01 = T[mm * ld + mm + 1], h10 = T[(mm + 1) * ld + mm];
-      const double h11 = T[(mm + 1) * ld + mm + 1], h21 = T[(mm + 2) * ld + mm + 1];
-      // (h00 - r1)(h00 - r2) in factored form (no cancellation of h00^2
-      // against the shift terms), scaled
-      double s0 = fabs(h00 - r2r) + fabs(r2i) + fabs(h10);
-      if (s0 == 0.0) s0 = 1.0;
-      const double h10s = h10 / s0;
-      x = h10s * h01 + (h00 - r1r) * ((h00 - r2r) / s0) - r1i * (r2i / s0);
-      y = h10s * (h00 + h11 - r1r - r2r);
-      z = h10s * h21;
-      const double sc = fabs(x) + fabs(y) + fabs(z);
-      if (sc > 0.0) {
-        x /= sc;
-        y /= sc;
-        z /= sc;
+    {
+      const int c = lane;  // candidate start row
+      const bool cand = c >= l && c <= hi - 2;
+      double cx = 0.0, cy = 0.0, cz = 0.0;
+      bool good = false;
+      if (cand) {
+        const double h00 = T[c * ld + c], h01 = T[c * ld + c + 1], h10 = T[(c + 1) * ld + c];
+        const double h11 = T[(c + 1) * ld + c + 1], h21 = T[(c + 2) * ld + c + 1];
+        // (h00 - r1)(h00 - r2) in factored form (no cancellation of h00^2
+        // against the shift terms), scaled
+        double s0 = fabs(h00 - r2r) + fabs(r2i) + fabs(h10);
+        if (s0 == 0.0) s0 = 1.0;
+        const double h10s = h10 / s0;
+        cx = h10s * h01 + (h00 - r1r) * ((h00 - r2r) / s0) - r1i * (r2i / s0);
+        cy = h10s * (h00 + h11 - r1r - r2r);
+        cz = h10s * h21;
+        const double sc = fabs(cx) + fabs(cy) + fabs(cz);
+        if (sc > 0.0) {
+          cx /= sc;
+          cy /= sc;
+          cz /= sc;
+        }
+        if (c == l) {
+          good = true;
+        } else {
+          const double e1 = fabs(T[c * ld + c - 1]) * (fabs(cy) + fabs(cz));
+          const double e2 = fabs(cx) * (fabs(T[(c - 1) * ld + c - 1]) + fabs(h00) + fabs(h11));
+          good = e1 <= eps * e2;
+        }
       }
-      if (mm == l) break;
-      const double e1 = fabs(T[mm * ld + mm - 1]) * (fabs(y) + fabs(z));
-      const double e2 = fabs(x) * (fabs(T[(mm - 1) * ld + mm - 1]) + fabs(h00) + fabs(h11));
-      if (e1 <= eps * e2) break;
-      --mm;
+      const unsigned long long bm = __ballot(good);
+      mm = 63 - __clzll(bm);  // lane l is always good
+      x = __shfl(cx, mm, 64);
+      y = __shfl(cy, mm, 64);
+      z = __shfl(cz, mm, 64);
     }
     for (int k = mm; k < hi; ++k) {
       const bool three = k < hi - 1;
@@ -448,28 +471,32 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
   // real bases of span(Q[:, 0:m]) (into L.V) and of span(Q[:, 0:mk]) (into
   // V2): the projector Q_b Q_b^H is real for a conjugation-closed selection;
   // pivoted Gram-Schmidt on its columns, then classical Gram-Schmidt twice of
-  // each new column against the earlier ones (numerical safety)
+  // each new column against the earlier ones (numerical safety).  Two lanes
+  // per column (j = lane & 31): each takes half of the rows, joined by one
+  // butterfly step.
+  const int jl = lane & 31, hf = lane >> 5;
+  const int ih = (p + 1) >> 1;
+  const int i0 = hf ? ih : 0, i1 = hf ? p : ih;
   for (int which = 0; which < (V2 ? 2 : 1); ++which) {
     const int mb = which ? mk : m;
     double* VV = which ? V2 : L.V;
     double* P = L.Pm;
-    if (lane < p) {
-      const int j = lane;
-      for (int i = 0; i < p; ++i) {
+    if (jl < p) {
+      for (int i = i0; i < i1; ++i) {
         double acc = 0.0;
-        for (int t = 0; t < mb; ++t) acc += cmul(Q[i * ld + t], cconj(Q[j * ld + t])).x;
-        P[i * ld + j] = acc;  // column j of the projector
+        for (int t = 0; t < mb; ++t) acc += cmul(Q[i * ld + t], cconj(Q[jl * ld + t])).x;
+        P[i * ld + jl] = acc;  // column jl of the projector
       }
     }
     WAVE_SYNC();
     for (int t = 0; t < mb; ++t) {
       double nrm = 0.0;
-      if (lane < p)
-        for (int i = 0; i < p; ++i) nrm += P[i * ld + lane] * P[i * ld + lane];
-      // argmax over lanes (ties -> smallest index)
-      double bn = nrm;
-      int bj = lane < p ? lane : 1 << 30;
-      if (lane >= p) bn = -1.0;
+      if (jl < p)
+        for (int i = i0; i < i1; ++i) nrm += P[i * ld + jl] * P[i * ld + jl];
+      nrm += __shfl_xor(nrm, 32, 64);
+      // argmax over the columns (ties -> smallest index)
+      double bn = (jl < p && hf == 0) ? nrm : -1.0;
+      int bj = (jl < p && hf == 0) ? jl : 1 << 30;
       for (int o = 32; o > 0; o >>= 1) {
         double on = __shfl_xor(bn, o, 64);
         int oj = __shfl_xor(bj, o, 64);
@@ -482,21 +509,22 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
       if (lane < p) VV[t * p + lane] = P[lane * ld + bj] * inv;
       WAVE_SYNC();
       for (int pass = 0; pass < 2; ++pass) {
-        if (lane < p) {
-          const int j = lane;
-          double d = 0.0;
-          for (int i = 0; i < p; ++i) d += VV[t * p + i] * P[i * ld + j];
-          for (int i = 0; i < p; ++i) P[i * ld + j] -= d * VV[t * p + i];
-        }
+        double d = 0.0;
+        if (jl < p)
+          for (int i = i0; i < i1; ++i) d += VV[t * p + i] * P[i * ld + jl];
+        d += __shfl_xor(d, 32, 64);
+        if (jl < p)
+          for (int i = i0; i < i1; ++i) P[i * ld + jl] -= d * VV[t * p + i];
         WAVE_SYNC();
       }
       if (t > 0) {
         for (int pass = 0; pass < 2; ++pass) {
-          if (lane < t) {  // coefficients against the earlier columns, lane u
-            double d = 0.0;
-            for (int i = 0; i < p; ++i) d += VV[lane * p + i] * VV[t * p + i];
-            L.rv[lane] = d;
-          }
+          // coefficients against the earlier columns, column u = jl
+          double d = 0.0;
+          if (jl < t)
+            for (int i = i0; i < i1; ++i) d += VV[jl * p + i] * VV[t * p + i];
+          d += __shfl_xor(d, 32, 64);
+          if (lane < t) L.rv[lane] = d;
           WAVE_SYNC();
           if (lane < p) {
             double v = VV[t * p + lane];
@@ -2416,12 +2444,15 @@ void eigensolve(Ctx& c) {
   // block Krylov-Schur: Rayleigh quotients up to km, restarts keep kkeep
   // (before the cluster rule); the basis must fit in the range of the
   // operator (interior rows) of every subdomain
-  int km = std::min(PMAX, std::max(3 * nev, nev + 16));
+  // (a larger basis means fewer restarts, each with one dense Schur
+  // decomposition per subdomain: on 2D convection-diffusion subdomains with
+  // nev 8, order 32 keeping 16 converges in the fewest block steps)
+  int km = std::min(PMAX, std::max(4 * nev, nev + 24));
   for (int i = 0; i < nsub; ++i)
     km = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
-  const int kkeep = (km + nev) / 2;
+  const int kkeep = std::min(std::max(2 * nev, km / 2), km - 2 * EIG_PC);
   const bool ks = c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && km >= nev + 2 * EIG_PC &&
-                  kkeep + EIG_PC <= km;
+                  kkeep >= nev && kkeep + EIG_PC <= km;
   if (!ks && p < nev + 1)
     fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
   c.eig_krylov_schur = ks;
