@@ -30,6 +30,65 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 WORKLOAD = "c2_convdiff2d_512_blocks64"
+# measured HBM traffic of the local-solve launches (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by a plain copy); valid only for the kernel sources it
+# was taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_local_solve_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_2201_02250_amd/csrc/k_apply.hip", "paper_2201_02250_amd/csrc/k_solve.h"]
+COPY_BYTES = 1 << 28  # plain device copy of known size for the counter scaling
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per local-solve launch from the committed counter summary, or
+    None if it is absent or was taken with other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.split(":", 1) for l in fh.read().splitlines() if l.startswith("- ") and ":" in l)
+    except OSError:
+        return None
+    kv = {k[2:].strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel source hash") != kernel_source_hash():
+        return None
+    try:
+        return int(kv["traffic bytes per local-solve launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pmc_apply(reps):
+    """Counter run: FP32 context on the workload, `reps` applies (direct
+    launches), then three plain copies of COPY_BYTES for the scaling."""
+    import torch
+    import workloads as W
+    from paper_2201_02250_amd import ads
+    dev = torch.device("cuda:0")
+    A, part, N, o = W.config(WORKLOAD)
+    Ad = ads.DeviceCSR(A, dev)
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=ads.ADS_PREC_FP32, stream=sp)
+    ctx.set_graphs(False)
+    r = torch.randn(A.n, dtype=torch.float64, device=dev)
+    z = torch.empty_like(r)
+    for _ in range(reps):
+        ads.ads_apply(ctx.ctx, r.data_ptr(), z.data_ptr(), 1, sp)
+    torch.cuda.synchronize()
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ctx.close()
+    print("pmc_apply: %d applies, 3 copies of %d bytes, kernel source hash %s"
+          % (reps, COPY_BYTES, kernel_source_hash()), flush=True)
 
 
 def apply_bytes(A, part, info, om, off, elem):
@@ -85,11 +144,16 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-apply", action="store_true",
+                    help="only run applies and a plain copy (for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_apply:
+        pmc_apply(args.apply_reps)
+        return
 
     import numpy as np
     import torch
@@ -173,10 +237,10 @@ def main():
         "speedup_vs_plain_fp64": round(t_fp64 / t_prod, 3),
         "production": m_prod,
         "plain_fp64": m_fp64,
-        "roofline": {"kernel": "k_local_solve", "bound": "hbm", "achieved": round(ach_local, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_local / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": int(b_local),
-                     "avg_launch_us": round(t_local * 1e3, 2)},
+        "roofline": {"kernel": "k_local_fwd+k_local_bwd", "bound": "hbm",
+                     "achieved": round(ach_local, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach_local / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "bytes_per_launch": int(b_local), "avg_launch_us": round(t_local * 1e3, 2)},
         "apply": {"achieved_GBs": round(ach_apply, 1), "frac": round(ach_apply / HBM_PEAK_GBS, 4),
                   "bytes_per_apply": int(b_apply), "avg_us": round(t_apply * 1e3, 2),
                   "factor_tile_bytes": int(b_tiles)},

@@ -9,18 +9,23 @@
 //     diagonal entry, Pi = I - l l^T with l the unit left null vector.
 // The nonzero eigenpairs of T are the eigenpairs of eq. 5 on K^perp.
 //
-// Block subspace iteration with Rayleigh-Ritz, all subdomains batched:
-//   k_eig_op   (grid: subdomain x column chunk)  Y = T X   (tile solves)
-//   X <- orth(Y) by Cholesky QR twice over row blocks (k_eig_gram, k_eig_orth)
-//   on the sweeps the schedule selects, first the Rayleigh-Ritz step:
-//     k_eig_rr (grid: subdomain) H = X^T Y, complex Schur form of H in LDS
-//              (Householder Hessenberg + shifted QR), eigenvalues ordered by
-//              |lambda|, the cut of eq. 6 with the cluster rule, reordering of
-//              the Schur form so the selected eigenvalues lead, a real
-//              orthonormal basis V of the selected invariant subspace;
-//     k_eig_resid / k_eig_decide: ||(Y - X H) V||_F and the convergence test
+// Two methods, all subdomains batched in the same launches:
+//  * block Krylov-Schur (default; block width 4): expansion steps through the
+//    two-ended operator kernels k_eig_op_fwd / k_eig_op_bwd (or k_eig_op on
+//    the general path), block Gram-Schmidt twice with a QR of the block after
+//    each pass (k_ks_dots, k_ks_upd, k_ks_qr), restarts from the ordered Schur
+//    form of the Rayleigh quotient (k_ks_rr, k_ks_restart);
+//  * block subspace iteration (k_eig_op, k_eig_gram, k_eig_orth) with
+//    Rayleigh-Ritz steps on a predicted schedule (k_eig_rr, k_eig_resid,
+//    k_eig_decide).
+// Both use small_eig_select: the Schur form of a real matrix of order <= 32
+// in LDS by one wave (Householder Hessenberg reduction, Francis double-shift
+// QR, complex triangularisation of the 2 x 2 blocks), eigenvalues ordered by
+// |lambda|, the cut of eq. 6 with the cluster rule, Givens reordering so that
+// the selected (and the kept) eigenvalues lead, real orthonormal bases of the
+// selected (and kept) invariant subspaces.
 //   k_eig_finish  W_i = orth([1 | (X V) restricted to Omega_Ii])
-// Converged subdomains skip further sweeps.
+// Converged subdomains skip further work.
 #include <algorithm>
 #include <cmath>
 
