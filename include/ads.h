@@ -216,6 +216,101 @@ int ads_partition_bfs(const ads_csr* A, int32_t nparts, const int32_t* seeds, in
  * every kernel directly on the caller's stream (same results, bit for bit). */
 int ads_set_graphs(ads_ctx* ctx, int32_t enable);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not in the paper): a message-passing graph network on
+ * the graph of every subdomain matrix A_ii predicts a block whose span
+ * approximates the coarse space of eq. 6 (Section 3.2), used to start the
+ * eq. 5 eigensolves (ads_options.warm_start).  Definition, per graph:
+ *   h_0 = F W_in^T + b_in;  a_l = A_w h_l;
+ *   u_l = h_l W_s,l^T + a_l W_n,l^T + b_l;  h_{l+1} = h_l + relu(u_l);
+ *   X = h_L W_out^T
+ * Parameters: one flat vector, W_in (width x n_in, row-major), b_in, then per
+ * layer W_s (width x width), W_n (width x width), b (width), then W_out
+ * (n_out x width).  The network reads BF16 parameters (uint16 bit patterns);
+ * the trainer keeps an FP32 master copy.  Activations and every accumulation
+ * are FP32.  All pointers below are device pointers unless stated; calls are
+ * ordered on the given HIP stream.  Errors as everywhere: ADS_ERR_ARG for bad
+ * shapes or null pointers.
+ * ------------------------------------------------------------------------- */
+#define ADS_GNN_FEATURES 16 /* node features written by ads_gnn_graph_build */
+
+typedef struct {
+  int32_t n_in;   /* input features per node, 1..64 */
+  int32_t width;  /* hidden width, 1..64 */
+  int32_t layers; /* message-passing layers, 0..16 */
+  int32_t n_out;  /* output columns, 1..16 */
+} ads_gnn_shape;
+
+/* A batch of graphs with consecutively numbered nodes (device pointers, owned
+ * by the caller).  The graph must be symmetric: (j, k) is an edge with weight
+ * w iff (k, j) is one with the same weight; no self loops. */
+typedef struct {
+  int32_t ngraph;
+  int64_t nnode;
+  const int64_t* node_off; /* [ngraph + 1] first node of each graph */
+  const int64_t* row_ptr;  /* [nnode + 1] edge list of every node */
+  const int32_t* col;      /* [nedge] neighbour node */
+  const float* w;          /* [nedge] edge weight */
+  const float* feat;       /* [nnode][n_in] node features, row-major */
+  const uint8_t* mask;     /* [nnode] 1 on the rows that enter the loss */
+} ads_gnn_graph;
+
+/* Number of parameters of the shape (-1 on a bad shape). */
+int64_t ads_gnn_nparams(const ads_gnn_shape* shape);
+
+/* Floats of workspace needed by ads_gnn_forward / ads_gnn_backward for a
+ * batch of nnode nodes (the activations of every layer are kept there by the
+ * forward pass for the backward pass). */
+int64_t ads_gnn_workspace_floats(const ads_gnn_shape* shape, int64_t nnode);
+
+/* Sizes of the graph batch of a context's subdomains: one graph per
+ * subdomain (node = slot of Omega_i in ascending global order, edges = the
+ * off-diagonal entries of A_ii), nnode = sum |Omega_i| (host outputs). */
+int ads_gnn_graph_size(const ads_ctx* ctx, int64_t* nnode, int64_t* nedge, int32_t* ngraph);
+
+/* Builds that batch into caller buffers of the sizes above: node_off
+ * [ngraph + 1], row_ptr [nnode + 1], col/w [nedge] with symmetric weights
+ * (|a_jk| + |a_kj|) / (2 sqrt(|a_jj a_kk|)), feat [nnode][ADS_GNN_FEATURES]
+ * (relative diagonal, its log, lumped s_j / a_jj of Definition 1, interior
+ * flag, off-diagonal row sum / a_jj, position t = j / (n_i - 1) in the local
+ * order and q = (j mod s) / s with s the local block size, sin and cos of
+ * pi t, 2 pi t, pi q, 2 pi q, and 1), mask [nnode] = interior flag.
+ * ADS_ERR_SINGULAR if a row of A_ii has no diagonal entry. */
+int ads_gnn_graph_build(const ads_ctx* ctx, int64_t* node_off, int64_t* row_ptr, int32_t* col,
+                        float* w, float* feat, uint8_t* mask, void* hip_stream);
+
+/* Training targets from a context's coarse space: Z [nnode][nz], interior
+ * row j of subdomain i = row j of W_i (ads_export_coarse) in its first
+ * min(nev_i, nz) columns; all other entries 0.  nz in 1..16. */
+int ads_gnn_targets(const ads_ctx* ctx, float* Z, int32_t nz, void* hip_stream);
+
+/* X [nnode][n_out] = network(params) on the batch; ws of
+ * ads_gnn_workspace_floats floats keeps the activations. */
+int ads_gnn_forward(const ads_gnn_shape* shape, const uint16_t* params, const ads_gnn_graph* g,
+                    float* ws, float* X, void* hip_stream);
+
+/* Projection loss of X against targets Z [nnode][nz] on the masked rows:
+ * loss = mean over graphs of ||Z_g - X_g C_g||_F^2 / ||Z_g||_F^2 with
+ * C_g = (X_g^T X_g)^{-1} X_g^T Z_g; dX [nnode][n_out] = dloss/dX (0 on
+ * unmasked rows); *loss (device double).  A graph whose X_g^T X_g is not
+ * positive definite contributes 1 and no gradient. */
+int ads_gnn_loss(const ads_gnn_shape* shape, const ads_gnn_graph* g, const float* X,
+                 const float* Z, int32_t nz, float* dX, double* loss, void* hip_stream);
+
+/* grad [nparams] += d(sum(dX * X))/d(params), using the activations left in
+ * ws by the last ads_gnn_forward on the same batch (ws is also scratch). */
+int ads_gnn_backward(const ads_gnn_shape* shape, const uint16_t* params, const ads_gnn_graph* g,
+                     float* ws, const float* dX, float* grad, void* hip_stream);
+
+/* One Adam step (bias-corrected, step >= 1) on the FP32 master copy, which is
+ * then rounded to nearest-even BF16 into params. */
+int ads_gnn_adam(int64_t nparams, float* master, uint16_t* params, const float* grad, float* m,
+                 float* v, int32_t step, float lr, float beta1, float beta2, float eps,
+                 void* hip_stream);
+
+/* params = BF16 (round to nearest even) of the FP32 master copy. */
+int ads_gnn_round_bf16(int64_t nparams, const float* master, uint16_t* params, void* hip_stream);
+
 /* Frees the context and its device memory (NULL is accepted). */
 int ads_destroy(ads_ctx* ctx);
 

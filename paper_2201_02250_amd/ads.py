@@ -28,7 +28,10 @@ ADS_EIG_KRYLOV_SCHUR, ADS_EIG_SUBSPACE = 0, 1
 # every symbol declared in include/ads.h
 SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_solve", "ads_get_info",
            "ads_export_maps", "ads_export_splitting", "ads_export_coarse", "ads_partition_bfs",
-           "ads_set_graphs", "ads_destroy", "ads_status_string", "ads_last_error"]
+           "ads_set_graphs", "ads_destroy", "ads_status_string", "ads_last_error",
+           "ads_gnn_nparams", "ads_gnn_workspace_floats", "ads_gnn_graph_size",
+           "ads_gnn_graph_build", "ads_gnn_targets", "ads_gnn_forward", "ads_gnn_loss",
+           "ads_gnn_backward", "ads_gnn_adam", "ads_gnn_round_bf16"]
 
 
 class ads_csr(C.Structure):
@@ -42,6 +45,20 @@ class ads_options(C.Structure):
                 ("warm_start", C.c_int32), ("eig_tol", C.c_double), ("eig_max_sweeps", C.c_int32),
                 ("gnn_weights_path", C.c_char_p), ("profile", C.c_int32),
                 ("eig_solver", C.c_int32)]
+
+
+class ads_gnn_shape(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("layers", C.c_int32),
+                ("n_out", C.c_int32)]
+
+
+class ads_gnn_graph(C.Structure):
+    _fields_ = [("ngraph", C.c_int32), ("nnode", C.c_int64), ("node_off", C.c_void_p),
+                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("w", C.c_void_p),
+                ("feat", C.c_void_p), ("mask", C.c_void_p)]
+
+
+ADS_GNN_FEATURES = 16
 
 
 class ads_ksp_options(C.Structure):
@@ -105,9 +122,22 @@ def lib():
         L.ads_status_string.restype = C.c_char_p
         L.ads_last_error.argtypes = []
         L.ads_last_error.restype = C.c_char_p
+        SH, GR, F = C.POINTER(ads_gnn_shape), C.POINTER(ads_gnn_graph), C.c_float
+        L.ads_gnn_nparams.argtypes = [SH]
+        L.ads_gnn_workspace_floats.argtypes = [SH, I64]
+        L.ads_gnn_graph_size.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)]
+        L.ads_gnn_graph_build.argtypes = [P, P, P, P, P, P, P, P]
+        L.ads_gnn_targets.argtypes = [P, P, I32, P]
+        L.ads_gnn_forward.argtypes = [SH, P, GR, P, P, P]
+        L.ads_gnn_loss.argtypes = [SH, GR, P, P, I32, P, P, P]
+        L.ads_gnn_backward.argtypes = [SH, P, GR, P, P, P, P]
+        L.ads_gnn_adam.argtypes = [I64, P, P, P, P, P, I32, F, F, F, F, P]
+        L.ads_gnn_round_bf16.argtypes = [I64, P, P, P]
         for name in SYMBOLS:
             if name not in ("ads_status_string", "ads_last_error"):
                 getattr(L, name).restype = C.c_int
+        L.ads_gnn_nparams.restype = I64
+        L.ads_gnn_workspace_floats.restype = I64
         _lib = L
     return _lib
 

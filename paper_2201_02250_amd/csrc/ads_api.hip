@@ -74,6 +74,8 @@ static int handle(const Error& e) {
   return e.code;
 }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 struct Timer {
   hipStream_t s;
   std::chrono::steady_clock::time_point t;
@@ -291,9 +293,6 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
 
 using namespace ads;
 
-struct ads_ctx {
-  Ctx* c;
-};
 
 extern "C" {
 

@@ -19,6 +19,8 @@ struct Error {
 };
 
 [[noreturn]] void fail(int code, const std::string& msg);
+// message returned by ads_last_error() on this thread
+void set_last_error(const std::string& msg);
 
 #define ADS_HIP(call)                                                                  \
   do {                                                                                 \
@@ -240,6 +242,25 @@ struct Ctx {
   ~Ctx();
   double t_setup_ms = 0;
 };
+
+}  // namespace ads
+
+// the opaque handle of the C interface
+struct ads_ctx {
+  ads::Ctx* c;
+};
+
+namespace ads {
+
+inline const Ctx* ctx_of(const ads_ctx* h) { return h->c; }
+inline Ctx* ctx_of(ads_ctx* h) { return h->c; }
+
+// graph network (learned warm start), implemented in k_gnn.hip
+void gnn_forward_impl(const ads_gnn_shape& s, const uint16_t* params, const ads_gnn_graph& g,
+                      float* ws, float* X, hipStream_t st);
+void gnn_graph_impl(const Ctx& c, int64_t* node_off, int64_t* row_ptr, int32_t* col, float* w,
+                    float* feat, uint8_t* mask, hipStream_t st);
+int64_t gnn_edges(const Ctx& c);
 
 // ---------------------------------------------------------------------------
 // launchers (host functions implemented in the kernel translation units)

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2201_02250_amd", "libads.so")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:int|const char\*)\s+(ads_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(?:int|int64_t|const char\*)\s+(ads_\w+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
