@@ -95,14 +95,25 @@ typedef struct {
   double tau;             /* <= 0: off; > 0: keep only |lambda| > 1/tau (eq. 6)       */
   int32_t variant;        /* ADS_VARIANT_*                                            */
   int32_t precision;      /* ADS_PREC_*                                               */
-  int32_t warm_start;     /* 0: none; 1: learned warm start (initial eigensolver block
-                             from the graph network; exact eigensolve still decides) */
+  int32_t warm_start;     /* 0: none; 1: learned warm start: the graph network's block
+                             (ads_gnn_*) starts a block subspace iteration that is run
+                             to eig_tol, with the cold exact eigensolve as fallback
+                             (ads_info.eig_fallbacks) if it misses the tolerance
+                             within 150 sweeps; 2: learned coarse space: the
+                             network's block, with the kernel part (the constant)
+                             in front on floating subdomains, orthonormalised on the
+                             interior rows, is the coarse space itself (nev_i =
+                             n_out + dim K_i, no eigensolve; falls back to the
+                             exact one if a block is rank deficient)                */
   double eig_tol;         /* relative residual of the selected invariant subspace
                              (0 -> 1e-10 with FP64 factors; 1e-3 with FP32/BF16
                              factors, where the coarse space only needs the
                              accuracy of the factors it is built from)             */
   int32_t eig_max_sweeps; /* 0 -> 400 (subspace sweeps, or Krylov-Schur block steps)   */
-  const char* gnn_weights_path; /* weights file for warm_start = 1 (NULL otherwise)  */
+  const char* gnn_weights_path; /* weights file for warm_start != 0: 8 bytes
+                             "ADSGNN01", int32 n_in (= ADS_GNN_FEATURES), width,
+                             layers, n_out, int64 nparams, nparams FP32 master
+                             parameters (little endian, order of ads_gnn_*)         */
   int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream
                              (reported in ads_info.t_kernel_ms / n_kernel)           */
   int32_t eig_solver;     /* ADS_EIG_*: method for the eq. 5 eigenproblems            */
@@ -133,7 +144,7 @@ typedef struct {
   int32_t eig_sweeps_max; /* largest eigensolver sweep count over subdomains          */
   int32_t eig_unconverged;/* subdomains that hit eig_max_sweeps                       */
   int32_t eig_fallbacks;  /* warm starts rejected in favour of the cold start         */
-  double t_phase_ms[8];   /* maps, extract, factor, eig, coarse, other, -, -          */
+  double t_phase_ms[8];   /* maps, extract, factor, eig, coarse, other, learned start, - */
   double t_kernel_ms[4];  /* profile = 1: summed device time of the apply kernels:
                              local solve, coarse restrict, coarse prolong, total apply */
   int64_t n_kernel[4];    /* number of timed launches of each                         */

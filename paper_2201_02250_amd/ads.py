@@ -302,11 +302,14 @@ class Context:
 
     def __init__(self, As, parts, nparts, overlap, nev, variant=ADS_VARIANT_DEFLATED,
                  precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None,
-                 profile=0, eig_solver=0):
+                 profile=0, eig_solver=0, warm_start=0, gnn_weights_path=None):
         if not isinstance(As, (list, tuple)):
             As, parts, nparts = [As], [parts], [nparts]
+        self._path = (gnn_weights_path.encode() if isinstance(gnn_weights_path, str)
+                      else gnn_weights_path)  # kept alive for the call
         self.opts = options(overlap, nev, variant, precision, tau, eig_tol, eig_max_sweeps,
-                            profile=profile, eig_solver=eig_solver)
+                            warm_start=warm_start, gnn_weights_path=self._path, profile=profile,
+                            eig_solver=eig_solver)
         self.stream = stream
         self.ctx = ads_setup_batched(As, parts, nparts, self.opts, stream)
         self.info = ads_get_info(self.ctx)

@@ -198,7 +198,9 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     fail(ADS_ERR_ARG, "unknown variant");
   if (opts->precision < ADS_PREC_FP64 || opts->precision > ADS_PREC_BF16)
     fail(ADS_ERR_ARG, "unknown precision");
-  if (opts->warm_start != 0) fail(ADS_ERR_UNSUPPORTED, "warm_start requires the learned model");
+  if (opts->warm_start < 0 || opts->warm_start > 2) fail(ADS_ERR_ARG, "unknown warm_start");
+  if (opts->warm_start != 0 && !opts->gnn_weights_path)
+    fail(ADS_ERR_ARG, "warm_start needs gnn_weights_path");
   if (opts->eig_solver != ADS_EIG_KRYLOV_SCHUR && opts->eig_solver != ADS_EIG_SUBSPACE)
     fail(ADS_ERR_ARG, "unknown eig_solver");
   auto c = new Ctx();
@@ -264,6 +266,10 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->t_phase_ms[2] = tm.lap();
     const bool coarse = opts->variant == ADS_VARIANT_DEFLATED && opts->nev > 0;
     if (coarse) {
+      if (opts->warm_start) {
+        learned_start(*c);
+        c->t_phase_ms[6] = tm.lap();
+      }
       eigensolve(*c);
       c->t_phase_ms[3] = tm.lap();
       if (c->n0 > 0) {

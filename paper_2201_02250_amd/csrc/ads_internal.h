@@ -206,6 +206,10 @@ struct Ctx {
   double* Einv = nullptr;
   int32_t eig_sweeps_max = 0, eig_unconverged = 0, eig_fallbacks = 0;
   bool eig_krylov_schur = false;  // block Krylov-Schur ran (else block subspace iteration)
+  // learned warm start: the network's block (node rows of Omega_i in sorted
+  // order x gnn_cols, FP32), set by learned_start for the eigensolve
+  float* gnn_x = nullptr;
+  int gnn_cols = 0;
   int h_eig_nblk = 0;  // row blocks of the eigensolver sweep kernels
   int h_eig_nqblk = 0;  // wide row blocks of the Krylov-Schur block QR kernels
 
@@ -261,6 +265,9 @@ void gnn_forward_impl(const ads_gnn_shape& s, const uint16_t* params, const ads_
 void gnn_graph_impl(const Ctx& c, int64_t* node_off, int64_t* row_ptr, int32_t* col, float* w,
                     float* feat, uint8_t* mask, hipStream_t st);
 int64_t gnn_edges(const Ctx& c);
+// loads ads_options.gnn_weights_path and runs the network on the context's
+// subdomain graphs into c.gnn_x
+void learned_start(Ctx& c);
 
 // ---------------------------------------------------------------------------
 // launchers (host functions implemented in the kernel translation units)

@@ -44,6 +44,8 @@ static constexpr int KS_BS = KS_W * PMAX;    // Bk per subdomain
 static constexpr int VSEL = KS_W * KS_W;     // Vsel per subdomain
 
 static constexpr double CLUSTER_RTOL = 1e-6;
+// sweep budget of a warm-started subspace iteration before the cold fallback
+static constexpr int WARM_SWEEPS = 150;
 
 #define WAVE_SYNC()                                        \
   do {                                                     \
@@ -923,6 +925,8 @@ struct EigArgs {
   double* partK2;
   double* Ures;     // per subdomain kept Schur basis (order x kept, column-major)
   double* Racc;     // per subdomain two accumulated EIG_PC x EIG_PC triangular factors
+  const float* x0;  // learned start block (node rows x x0_cols), interior rows used
+  int x0_cols;
   int32_t* err;
   int p;
   int nev;
@@ -1136,7 +1140,14 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   const int64_t base = a.om_off[i];
   for (int64_t e = threadIdx.x; e < (int64_t)npad * p; e += blockDim.x) {
     const int r = (int)(e % npad), j = (int)(e / npad);
-    X[r + j * ld] = (r < n) ? adsd::hash_unit(((uint64_t)i << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)r) : 0.0;
+    double v = 0.0;
+    if (r < n) {
+      if (a.x0 && j < a.x0_cols)  // learned start: interior rows of the network's block
+        v = a.om_int[base + r] ? (double)a.x0[(base + r) * a.x0_cols + j] : 0.0;
+      else
+        v = adsd::hash_unit(((uint64_t)i << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)r);
+    }
+    X[r + j * ld] = v;
   }
   __syncthreads();
   if (a.kdim[i]) {
@@ -2322,7 +2333,8 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   if (fast)
     ADS_LAUNCH(k_eig_btl, dim3(nsub), dim3(256), 0, st, a, c.om_sorted, c.rowptr, c.col, c.val,
                c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
-  const int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
+  int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
+  if (a.x0) maxsw = std::min(maxsw, WARM_SWEEPS);  // then the cold fallback
   std::vector<int32_t> hdone, hnext;
   int next = 3;  // first Rayleigh-Ritz step after 4 sweeps
   for (int sw = 0; sw < maxsw; ++sw) {
@@ -2360,6 +2372,99 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
   }
   ADS_HIP(hipStreamSynchronize(st));
+}
+
+// Learned coarse space: per subdomain the interior rows of [1 (floating
+// subdomains: the kernel part) | the network's block] orthonormalised by
+// Cholesky QR twice (one block each)
+__global__ void __launch_bounds__(EIG_T) k_learned_coarse(const int64_t* om_off,
+                                                          const uint8_t* om_int,
+                                                          const int32_t* nI, const int32_t* kdim,
+                                                          const float* X, int kx,
+                                                          const int64_t* W_off, double* W,
+                                                          double* Zbuf, int32_t* err) {
+  __shared__ EigShared S;
+  __shared__ int wtot[EIG_T / 64];
+  const int i = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t b = om_off[i];
+  const int n = (int)(om_off[i + 1] - b), nint = nI[i];
+  const int kd = kdim[i], k = kx + kd;  // the kernel part (constant) leads, as in eq. 6
+  double* Z = Zbuf + W_off[i];  // nint x k, column-major
+  int run = 0;
+  for (int r0 = 0; r0 < n; r0 += EIG_T) {
+    const int r = r0 + t;
+    const int f = r < n ? (int)om_int[b + r] : 0;
+    int incl = f;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int q = 0; q < EIG_T / 64; ++q) {
+      if (q < wv) off += wtot[q];
+      tot += wtot[q];
+    }
+    if (f) {
+      const int q = run + off + incl - 1;
+      if (kd) Z[q] = 1.0;
+      for (int c = 0; c < kx; ++c) Z[q + (int64_t)(c + kd) * nint] = X[(b + r) * kx + c];
+    }
+    run += tot;
+  }
+  __syncthreads();
+  const int ok = cholqr2(Z, Z, nint, nint, nint, k, S);
+  if (!ok && t == 0) atomicOr(err, 1);
+  double* Wi = W + W_off[i];
+  for (int64_t e = t; e < (int64_t)nint * k; e += EIG_T) {
+    const int r = (int)(e / k), c = (int)(e % k);
+    Wi[e] = Z[r + (int64_t)c * nint];
+  }
+}
+
+// the coarse layout and W from the learned block (c.gnn_x, c.gnn_cols
+// columns); false if a subdomain's block is not of full rank
+static bool learned_coarse(Ctx& c) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub, k = c.gnn_cols;
+  c.h_nev.resize(nsub);
+  c.h_coff.assign(nsub + 1, 0);
+  c.h_W_off.assign(nsub + 1, 0);
+  for (int i = 0; i < nsub; ++i) {
+    c.h_nev[i] = k + c.h_kdim[i];
+    if (c.h_nI[i] < c.h_nev[i] || c.h_nev[i] > PMAX) return false;
+    c.h_coff[i + 1] = c.h_coff[i] + c.h_nev[i];
+    c.h_W_off[i + 1] = c.h_W_off[i] + (int64_t)c.h_nI[i] * c.h_nev[i];
+  }
+  double* W = c.mem.alloc<double>(std::max<int64_t>(c.h_W_off[nsub], 1));
+  double* Zb = c.mem.alloc<double>(std::max<int64_t>(c.h_W_off[nsub], 1));
+  int64_t* Woff = upload(c.mem, c.h_W_off.data(), nsub + 1, st);
+  int32_t* err = c.mem.alloc<int32_t>(1);
+  ADS_HIP(hipMemsetAsync(err, 0, 4, st));
+  ADS_LAUNCH(k_learned_coarse, dim3(nsub), dim3(EIG_T), 0, st, c.om_off, c.om_int, c.nI, c.kdim,
+             c.gnn_x, k, Woff, W, Zb, err);
+  std::vector<int32_t> he;
+  download(he, err, 1, st);
+  c.mem.release(Zb);
+  if (he[0]) {
+    c.mem.release(W);
+    return false;
+  }
+  c.W = W;
+  c.W_off = Woff;
+  c.n0 = c.h_coff[nsub];
+  c.nev = upload(c.mem, c.h_nev.data(), nsub, st);
+  c.coff = upload(c.mem, c.h_coff.data(), nsub + 1, st);
+  c.h_lam_re.assign(c.n0, 0.0);  // no eigenvalues: the space is predicted
+  c.h_lam_im.assign(c.n0, 0.0);
+  c.h_sweeps.assign(nsub, 0);
+  c.h_eig_res.assign(nsub, 0.0);
+  c.eig_sweeps_max = 0;
+  c.eig_unconverged = 0;
+  c.eig_krylov_schur = false;
+  return true;
 }
 
 // block Krylov-Schur driver (block width a.p = EIG_PC)
@@ -2439,6 +2544,15 @@ void eigensolve(Ctx& c) {
   hipStream_t st = c.stream;
   const int nsub = c.nsub;
   const int nev = c.opt.nev;
+  if (c.gnn_x && c.opt.warm_start == 2) {
+    // learned coarse space: the network's block itself, orthonormalised
+    if (learned_coarse(c)) return;
+    c.eig_fallbacks = nsub;  // a rank-deficient prediction: exact eigensolve
+    c.gnn_x = nullptr;
+  }
+  // learned warm start: block subspace iteration started from the
+  // network's block, with the exact cold eigensolve as the fallback
+  const bool warm = c.gnn_x && c.opt.warm_start == 1;
   // block subspace iteration: block of p columns
   int p = std::min(PMAX, std::max(2 * nev, nev + 8));
   p = (p + 3) / 4 * 4;
@@ -2456,7 +2570,7 @@ void eigensolve(Ctx& c) {
   for (int i = 0; i < nsub; ++i)
     km = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
   const int kkeep = std::min(std::max(2 * nev, km / 2), km - 2 * EIG_PC);
-  const bool ks = c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && km >= nev + 2 * EIG_PC &&
+  const bool ks = !warm && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && km >= nev + 2 * EIG_PC &&
                   kkeep >= nev && kkeep + EIG_PC <= km;
   if (!ks && p < nev + 1)
     fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
@@ -2569,6 +2683,8 @@ void eigensolve(Ctx& c) {
   ADS_HIP(hipMemsetAsync(a.stall, 0, nsub * 4, st));
   a.err = c.mem.alloc<int32_t>(1);
   a.p = pw;
+  a.x0 = warm ? c.gnn_x : nullptr;
+  a.x0_cols = warm ? std::min(c.gnn_cols, pw) : 0;
   a.nev = nev;
   a.tau = c.opt.tau;
   a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
@@ -2596,6 +2712,26 @@ void eigensolve(Ctx& c) {
   }
   std::vector<int32_t> herr, hm, hsw, hdone;
   download(herr, a.err, 1, st);
+  auto release_all = [&]() {
+    ADS_HIP(hipStreamSynchronize(st));
+    for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.W, (void*)a.partA, (void*)a.partB,
+                    (void*)a.partH, (void*)a.partR, (void*)a.HVs, (void*)a.btl, (void*)a.colsum,
+                    (void*)a.dummy, (void*)a.Bk, (void*)a.partK, (void*)a.partK2, (void*)a.Ures,
+                    (void*)a.Racc})
+      if (q) c.mem.release(q);
+  };
+  if (warm) {
+    download(hdone, a.done, nsub, st);
+    int missed = 0;
+    for (int i = 0; i < nsub; ++i) missed += hdone[i] != 1;
+    if (missed || herr[0]) {  // fallback: the exact eigensolve from a cold start
+      release_all();
+      c.eig_fallbacks = std::max(missed, 1);
+      c.gnn_x = nullptr;
+      eigensolve(c);
+      return;
+    }
+  }
   if (herr[0] & 4) fail(ADS_ERR_EIG_NOCONV, "small dense eigensolver did not converge");
   if (herr[0] & 16)
     fail(ADS_ERR_UNSUPPORTED,
@@ -2646,12 +2782,7 @@ void eigensolve(Ctx& c) {
   ADS_LAUNCH(k_eig_finish, dim3(nsub), dim3(EIG_T), 0, st, a, c.W_off, c.W);
   download(herr, a.err, 1, st);
   if (herr[0] & 8) fail(ADS_ERR_EIG_NOCONV, "coarse basis of a subdomain is rank deficient");
-  ADS_HIP(hipStreamSynchronize(st));
-  for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.W, (void*)a.partA, (void*)a.partB,
-                  (void*)a.partH, (void*)a.partR, (void*)a.HVs, (void*)a.btl, (void*)a.colsum,
-                  (void*)a.dummy, (void*)a.Bk, (void*)a.partK, (void*)a.partK2, (void*)a.Ures,
-                  (void*)a.Racc})
-    if (q) c.mem.release(q);
+  release_all();
 
 }
 

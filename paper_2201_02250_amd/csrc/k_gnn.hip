@@ -564,6 +564,58 @@ void gnn_graph_impl(const Ctx& c, int64_t* node_off, int64_t* row_ptr, int32_t* 
 
 int64_t gnn_edges(const Ctx& c) { return c.lnnz - c.omega_total; }
 
+void learned_start(Ctx& c) {
+  hipStream_t st = c.stream;
+  const char* path = c.opt.gnn_weights_path;
+  if (!path) fail(ADS_ERR_ARG, "warm_start needs gnn_weights_path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) fail(ADS_ERR_ARG, std::string("cannot open the weights file ") + path);
+  char magic[8];
+  int32_t sh[4];
+  int64_t np = 0;
+  const bool head = std::fread(magic, 1, 8, f) == 8 && std::fread(sh, 4, 4, f) == 4 &&
+                    std::fread(&np, 8, 1, f) == 1;
+  ads_gnn_shape s{sh[0], sh[1], sh[2], sh[3]};
+  if (!head || std::string(magic, 8) != "ADSGNN01") {
+    std::fclose(f);
+    fail(ADS_ERR_ARG, "not a weights file (magic ADSGNN01)");
+  }
+  try {
+    check_shape(&s);
+  } catch (...) {
+    std::fclose(f);
+    throw;
+  }
+  if (s.n_in != ADS_GNN_FEATURES || np != offsets(s).total) {
+    std::fclose(f);
+    fail(ADS_ERR_ARG, "weights file: shape does not match the node features");
+  }
+  std::vector<float> master(np);
+  const bool body = std::fread(master.data(), 4, np, f) == (size_t)np;
+  std::fclose(f);
+  if (!body) fail(ADS_ERR_ARG, "weights file truncated");
+  Arena mem(st);
+  float* dm = upload(mem, master.data(), np, st);
+  uint16_t* pb = mem.alloc<uint16_t>(np);
+  ADS_LAUNCH(k_gnn_round, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np, dm, pb);
+  const int64_t nn = c.omega_total, ne = std::max<int64_t>(gnn_edges(c), 1);
+  int64_t* node_off = mem.alloc<int64_t>(c.nsub + 1);
+  int64_t* row_ptr = mem.alloc<int64_t>(nn + 1);
+  int32_t* col = mem.alloc<int32_t>(ne);
+  float* w = mem.alloc<float>(ne);
+  float* feat = mem.alloc<float>(nn * ADS_GNN_FEATURES);
+  uint8_t* mask = mem.alloc<uint8_t>(nn);
+  gnn_graph_impl(c, node_off, row_ptr, col, w, feat, mask, st);
+  ads_gnn_graph g{c.nsub, nn, node_off, row_ptr, col, w, feat, mask};
+  const int64_t nblk = (nn + RB - 1) / RB;
+  float* ws = mem.alloc<float>((int64_t)(3 * s.layers + 4) * nn * s.width + nblk * ((int64_t)GW * GW + GW));
+  float* X = c.mem.alloc<float>(nn * s.n_out);
+  gnn_forward_impl(s, pb, g, ws, X, st);
+  ADS_HIP(hipStreamSynchronize(st));
+  c.gnn_x = X;
+  c.gnn_cols = s.n_out;
+}
+
 }  // namespace ads
 
 using namespace ads;

@@ -3,8 +3,11 @@ forward, loss and backward against the FP64 CPU oracle (oracle/gnn.py) with
 the same BF16-rounded parameters (the remaining difference is FP32
 arithmetic: <= 1e-5 relative), the graph and targets built from a context
 against their definition, and Adam."""
+import os
+
 import numpy as np
 import pytest
+import scipy.linalg as sla
 
 import workloads as W
 from oracle import gnn as OG
@@ -138,3 +141,99 @@ def test_graph_and_targets_from_a_context():
         np.testing.assert_allclose(Zh[b:b + n][interior][:, :m], Wi, rtol=1e-6, atol=1e-7)
         assert np.all(Zh[b:b + n][~interior] == 0)
     ctx.close()
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2201_02250_amd", "gnn", "c4_lognormal_nev8.adsgnn")
+
+
+def c4_field(seed):
+    A, part, N, o = W.config("c4_lognormal2d_256_blocks64", seed=seed)
+    return ads.DeviceCSR(A, DEV), part, N, o, A
+
+
+def solve_its(Ad, part, N, o, b, **kw):
+    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], gnn_weights_path=WEIGHTS, **kw)
+    x, info = ctx.solve(b, restart=o["restart"], rtol=1e-8)
+    out = dict(its=info["its"][0], relres=info["relres"][0], info=ctx.info)
+    Wg, woff, lam, cinfo = ads.ads_export_coarse(ctx.ctx)
+    out["W"] = (Wg, woff, cinfo["nev_i"].copy(), cinfo["n_interior"].copy())
+    ctx.close()
+    return out
+
+
+def max_angle(Wa, Wb):
+    (Ga, oa, na, nIa), (Gb, ob, nb, nIb) = Wa, Wb
+    np.testing.assert_array_equal(na, nb)
+    worst = 0.0
+    for i in range(len(na)):
+        m = int(na[i])
+        A_ = Ga[oa[i]:oa[i + 1]].reshape(int(nIa[i]), m)
+        B_ = Gb[ob[i]:ob[i + 1]].reshape(int(nIb[i]), m)
+        worst = max(worst, float(sla.subspace_angles(A_, B_).max()))
+    return worst
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_learned_coarse_space_gain_on_held_out_fields():
+    """The trained network on log-normal fields it has not seen (numpy
+    generator, seeds outside the training sample): GMRES(30) to 1e-8 with
+    the learned coarse space (no eigensolve) against the exact coarse space
+    and against no coarse space.  Measured on 10 such fields: 31.8 iterations
+    against 14.9 (exact) and 458 (none); asserted with margins."""
+    for seed in (100000, 100003):
+        Ad, part, N, o, A = c4_field(seed)
+        b = torch.tensor(W.rhs(A.n, seed), device=DEV)
+        ex = solve_its(Ad, part, N, o, b)
+        ln = solve_its(Ad, part, N, o, b, warm_start=2)
+        ras = solve_its(Ad, part, N, o, b, variant=ads.ADS_VARIANT_RAS)
+        assert ln["relres"] <= 1e-8 and ln["info"]["eig_fallbacks"] == 0
+        assert ln["its"] <= 3 * ex["its"], (ln["its"], ex["its"])
+        assert ln["its"] <= ras["its"] / 5, (ln["its"], ras["its"])
+        # the eigensolve is replaced by one network inference
+        assert ln["info"]["t_phase_ms"][3] < 0.1 * ex["info"]["t_phase_ms"][3]
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_warm_started_eigensolve_gives_the_exact_coarse_space():
+    Ad, part, N, o, A = c4_field(100001)
+    b = torch.tensor(W.rhs(A.n, 1), device=DEV)
+    ex = solve_its(Ad, part, N, o, b, eig_tol=1e-12)
+    wm = solve_its(Ad, part, N, o, b, warm_start=1, eig_tol=1e-12)
+    assert wm["info"]["eig_fallbacks"] == 0
+    assert max_angle(ex["W"], wm["W"]) <= 1e-7
+    assert wm["its"] == ex["its"]
+
+
+def test_zero_weights_fall_back_to_the_exact_eigensolve(tmp_path):
+    """A network that predicts nothing (all weights zero): both learned modes
+    fall back to the exact eigensolve and give its coarse space."""
+    path = str(tmp_path / "zero.adsgnn")
+    shape = G.DEFAULT_SHAPE
+    G.save_weights(path, shape, np.zeros(G.nparams(shape), np.float32))
+    A, part, N, o = W.config("c4_lognormal2d_256_blocks64", scale=64)
+    Ad = ads.DeviceCSR(A, DEV)
+    b = torch.tensor(W.rhs(A.n, 0), device=DEV)
+    res = {}
+    for ws in (0, 1, 2):
+        ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], warm_start=ws, gnn_weights_path=path,
+                          eig_tol=1e-12)
+        x, info = ctx.solve(b, restart=o["restart"], rtol=1e-8)
+        Wg, woff, lam, cinfo = ads.ads_export_coarse(ctx.ctx)
+        res[ws] = (info["its"][0], ctx.info["eig_fallbacks"],
+                   (Wg, woff, cinfo["nev_i"].copy(), cinfo["n_interior"].copy()))
+        ctx.close()
+    assert res[0][1] == 0 and res[1][1] > 0 and res[2][1] > 0
+    for ws in (1, 2):
+        assert res[ws][0] == res[0][0]
+        assert max_angle(res[0][2], res[ws][2]) <= 1e-7
+
+
+def test_bad_weights_files_are_rejected(tmp_path):
+    A, part, N, o = W.config("c4_lognormal2d_256_blocks64", scale=64)
+    bad = tmp_path / "bad.adsgnn"
+    bad.write_bytes(b"NOTAFILE" + bytes(32))
+    for path in (str(bad), str(tmp_path / "missing.adsgnn")):
+        with pytest.raises(ads.AdsError) as e:
+            ads.Context(A, part, N, o["overlap"], o["nev"], warm_start=1, gnn_weights_path=path)
+        assert e.value.status == ads.ADS_ERR_ARG

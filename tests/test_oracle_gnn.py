@@ -104,3 +104,26 @@ def test_forward_by_hand():
     p2[4] = -10.0
     X2, _ = OG.forward(p2, shape, graph)
     assert np.allclose(X2[:, 0], [3.0, 9.0], rtol=0, atol=1e-14)
+
+
+def test_torch_field_values_follow_the_recipe():
+    """The device field generator (training data) keeps the structure of the
+    numpy one: same pattern, symmetric, diagonal = sum of the face
+    coefficients (zero row sums away from the boundary)."""
+    import torch
+    import workloads as W
+    m = 24
+    A = W.diffusion2d_lognormal(m, seed=0, npad=64)
+    ip = torch.tensor(A.indptr)
+    ix = torch.tensor(A.indices)
+    v = W.lognormal2d_values_torch(m, 3, ip, ix, npad=64).numpy()
+    import scipy.sparse as sp
+    M = sp.csr_matrix((v, A.indices, A.indptr), shape=(A.n, A.n))
+    assert abs(M - M.T).max() <= 1e-12 * abs(M).max()
+    d = M.diagonal()
+    assert np.all(d > 0)
+    rs = np.asarray(M.sum(axis=1)).ravel()
+    i, j = np.arange(A.n) % m, np.arange(A.n) // m
+    inner = (i > 0) & (i < m - 1) & (j > 0) & (j < m - 1)
+    assert np.abs(rs[inner]).max() <= 1e-12 * d.max()
+    assert np.all(rs[~inner] > 0)

@@ -23,6 +23,7 @@ from .problems import (  # noqa: F401
     convdiff2d,
     convdiff3d,
     diffusion2d_lognormal,
+    lognormal2d_values_torch,
     diffusion3d_blocks,
     gaussian_field_2d,
     strip_partition,

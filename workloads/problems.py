@@ -317,3 +317,41 @@ def config(name: str, scale: int | None = None, seed: int = 0):
         raise KeyError(name)
     nparts = int(part.max()) + 1 if part is not None else len(opts["seeds"])
     return A, part, nparts, opts
+
+
+def lognormal2d_values_torch(m: int, seed: int, indptr, indices, sigma: float = 2.0,
+                             corr_len: float = 0.05, npad: int = 512):
+    """Values of diffusion2d_lognormal(m, sigma, corr_len) for the same CSR
+    pattern (indptr, indices: device tensors), drawn on the device with
+    torch's generator (seed) instead of numpy's: the same recipe (white noise
+    filtered by the square root of the periodised squared-exponential
+    covariance, k = exp(sigma g) at the nodes, harmonic face means), a
+    different sample.  Used to make many training fields quickly."""
+    import torch
+    dev = indptr.device
+    h = 1.0 / (m + 1)
+    gen = torch.Generator(device=dev).manual_seed(int(seed))
+    w = torch.randn((npad, npad), generator=gen, device=dev, dtype=torch.float64)
+    ar = torch.arange(npad, device=dev, dtype=torch.float64)
+    d = torch.minimum(ar, npad - ar) * h
+    r2 = d[:, None] ** 2 + d[None, :] ** 2
+    c = torch.exp(-r2 / (2.0 * corr_len ** 2))
+    S = torch.clamp(torch.fft.fft2(c).real, min=0.0)
+    g = torch.fft.ifft2(torch.sqrt(S) * torch.fft.fft2(w)).real[: m + 2, : m + 2]
+    kk = torch.exp(sigma * g)
+    n = m * m
+    deg = indptr[1:] - indptr[:-1]
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), deg)
+    cols = indices.to(torch.int64)
+    i, j = rows % m, rows // m
+    harm = lambda a, b: 2.0 * a * b / (a + b)
+    kc = kk[j + 1, i + 1]
+    kw = harm(kc, kk[j + 1, i])
+    ke = harm(kc, kk[j + 1, i + 2])
+    ks = harm(kc, kk[j, i + 1])
+    kn = harm(kc, kk[j + 2, i + 1])
+    dlt = cols - rows
+    val = torch.where(dlt == 0, kw + ke + ks + kn,
+          torch.where(dlt == -1, -kw, torch.where(dlt == 1, -ke,
+          torch.where(dlt == -m, -ks, -kn))))
+    return val
