@@ -47,9 +47,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(tile_factor):
     """Bytes per local-solve launch from the committed counter summary, or
-    None if it is absent or was taken with other kernel sources."""
+    None if it is absent or was taken with other kernel sources or tiles."""
     try:
         with open(TRAFFIC_FILE) as fh:
             kv = dict(l.split(":", 1) for l in fh.read().splitlines() if l.startswith("- ") and ":" in l)
@@ -57,6 +57,11 @@ def measured_traffic():
         return None
     kv = {k[2:].strip(): v.strip() for k, v in kv.items()}
     if kv.get("kernel source hash") != kernel_source_hash():
+        return None
+    try:
+        if abs(float(kv.get("tile factor", "nan")) - tile_factor) > 1e-12:
+            return None
+    except ValueError:
         return None
     try:
         return int(kv["traffic bytes per local-solve launch"])
@@ -74,7 +79,8 @@ def pmc_apply(reps):
     A, part, N, o = W.config(WORKLOAD)
     Ad = ads.DeviceCSR(A, dev)
     sp = torch.cuda.current_stream(dev).cuda_stream
-    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=ads.ADS_PREC_FP32, stream=sp)
+    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=ads.ADS_PREC_FP32, stream=sp,
+                      autotune=1)
     ctx.set_graphs(False)
     r = torch.randn(A.n, dtype=torch.float64, device=dev)
     z = torch.empty_like(r)
@@ -87,8 +93,8 @@ def pmc_apply(reps):
         y.copy_(x)
     torch.cuda.synchronize()
     ctx.close()
-    print("pmc_apply: %d applies, 3 copies of %d bytes, kernel source hash %s"
-          % (reps, COPY_BYTES, kernel_source_hash()), flush=True)
+    print("pmc_apply: %d applies, 3 copies of %d bytes, kernel source hash %s, tile factor %r"
+          % (reps, COPY_BYTES, kernel_source_hash(), ctx.info["tile_factor"]), flush=True)
 
 
 def apply_bytes(A, part, info, om, off, elem):
@@ -170,7 +176,11 @@ def main():
     prec = precs[args.precision]
 
     def step(p):
-        ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=p, stream=sp)
+        # the production form tunes its tile shapes (the first, warm-up, setup
+        # times the candidates; later setups of the same shape hit the cache);
+        # the plain FP64 form keeps the bandwidth tiles
+        ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=p, stream=sp,
+                          autotune=int(p != ads.ADS_PREC_FP64))
         x, info = ctx.solve(b, restart=o["restart"], flexible=True, rtol=1e-8)
         return ctx, x, info
 
@@ -189,8 +199,9 @@ def main():
         xh, bh = x.cpu().numpy(), b.cpu().numpy()
         relres = float(np.linalg.norm(bh - A.to_scipy() @ xh) / np.linalg.norm(bh))
         meta = dict(its=info["its"][0], relres=relres, setup_ms=info["t_setup_ms"],
-                    solve_ms=info["t_solve_ms"], phases=c.info["t_phase_ms"][:6],
-                    n0=c.info["n0"], eig_sweeps_max=c.info["eig_sweeps_max"])
+                    solve_ms=info["t_solve_ms"], phases=c.info["t_phase_ms"][:8],
+                    n0=c.info["n0"], eig_sweeps_max=c.info["eig_sweeps_max"],
+                    tile_factor=c.info["tile_factor"], tile_tuned=c.info["tile_tuned"])
         for c, x, info in runs:
             c.close()
         print("[bench] %s: %.2f ms/step its %d relres %.2e" % (label, dt * 1e3, meta["its"], relres),
@@ -201,7 +212,8 @@ def main():
     t_fp64, m_fp64 = timed(ads.ADS_PREC_FP64, args.steps, 1, "fp64")
 
     # apply: live hipEvent timing of the local-solve kernel and of the whole apply
-    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=prec, stream=sp, profile=1)
+    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=prec, stream=sp, profile=1,
+                      autotune=1)
     om, off, nI, lay = ads.ads_export_maps(ctx.ctx)
     r = torch.randn(A.n, dtype=torch.float64, device=dev)
     z = torch.empty_like(r)
@@ -209,6 +221,7 @@ def main():
         ads.ads_apply(ctx.ctx, r.data_ptr(), z.data_ptr(), 1, sp)
     torch.cuda.synchronize()
     info = ads.ads_get_info(ctx.ctx)
+    tile_factor = info["tile_factor"]
     t_local = info["t_kernel_ms"][0] / max(info["n_kernel"][0], 1)
     t_apply = info["t_kernel_ms"][3] / max(info["n_kernel"][3], 1)
     elem = {ads.ADS_PREC_FP64: 8, ads.ADS_PREC_FP32: 4, ads.ADS_PREC_BF16: 2}[prec]
@@ -239,8 +252,9 @@ def main():
         "plain_fp64": m_fp64,
         "roofline": {"kernel": "k_local_fwd+k_local_bwd", "bound": "hbm",
                      "achieved": round(ach_local, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach_local / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "bytes_per_launch": int(b_local), "avg_launch_us": round(t_local * 1e3, 2)},
+                     "frac": round(ach_local / HBM_PEAK_GBS, 4), "traffic": measured_traffic(tile_factor),
+                     "bytes_per_launch": int(b_local), "avg_launch_us": round(t_local * 1e3, 2),
+                     "tile_factor": tile_factor},
         "apply": {"achieved_GBs": round(ach_apply, 1), "frac": round(ach_apply / HBM_PEAK_GBS, 4),
                   "bytes_per_apply": int(b_apply), "avg_us": round(t_apply * 1e3, 2),
                   "factor_tile_bytes": int(b_tiles)},

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define ADS_ABI_VERSION 2
+#define ADS_ABI_VERSION 3
 #define ADS_MAX_RESULTS 64 /* entries of ads_ksp_result: nsys * nrhs <= 64 */
 
 /* status codes */
@@ -117,6 +117,12 @@ typedef struct {
   int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream
                              (reported in ads_info.t_kernel_ms / n_kernel)           */
   int32_t eig_solver;     /* ADS_EIG_*: method for the eq. 5 eigenproblems            */
+  int32_t autotune;       /* 0: block size of every subdomain's block-tridiagonal
+                             form = its local bandwidth; 1: pick the block sizes by
+                             timing candidates (ceil(f * bandwidth), f in
+                             {1, 1.25, 1.5, 2, 2.5}, within the fast-path limits) on
+                             this context's matrices, cached per workload shape for
+                             the process (ads_tune_cache_*)                         */
 } ads_options;
 
 typedef struct {
@@ -144,7 +150,8 @@ typedef struct {
   int32_t eig_sweeps_max; /* largest eigensolver sweep count over subdomains          */
   int32_t eig_unconverged;/* subdomains that hit eig_max_sweeps                       */
   int32_t eig_fallbacks;  /* warm starts rejected in favour of the cold start         */
-  double t_phase_ms[8];   /* maps, extract, factor, eig, coarse, other, learned start, - */
+  double t_phase_ms[8];   /* maps, extract, factor, eig, coarse, other, learned start,
+                             tile tuning                                            */
   double t_kernel_ms[4];  /* profile = 1: summed device time of the apply kernels:
                              local solve, coarse restrict, coarse prolong, total apply */
   int64_t n_kernel[4];    /* number of timed launches of each                         */
@@ -158,6 +165,8 @@ typedef struct {
   double* eig_resid;      /* final ||(T X - X H) V||_F / min |lambda| of the selected
                              invariant subspace per subdomain (eigensolver residual)  */
   int32_t eig_solver;     /* ADS_EIG_* that ran                                      */
+  double tile_factor;     /* block size / bandwidth factor in use (1 without tuning) */
+  int32_t tile_tuned;     /* 0: not tuned; 1: timed in this setup; 2: from the cache */
 } ads_info;
 
 /* Setup for one system (Sections 2 and 3): overlapping subdomains from the
@@ -321,6 +330,14 @@ int ads_gnn_adam(int64_t nparams, float* master, uint16_t* params, const float* 
 
 /* params = BF16 (round to nearest even) of the FP32 master copy. */
 int ads_gnn_round_bf16(int64_t nparams, const float* master, uint16_t* params, void* hip_stream);
+
+/* The tile tuner's process-wide cache (ads_options.autotune): save it to a
+ * text file, merge a saved file into it, or empty it.  Entries are keyed by
+ * the workload's shape (precision, sizes, per-subdomain sizes and bandwidths);
+ * ADS_ERR_ARG on unreadable or malformed files. */
+int ads_tune_cache_save(const char* path);
+int ads_tune_cache_load(const char* path);
+int ads_tune_cache_clear(void);
 
 /* Frees the context and its device memory (NULL is accepted). */
 int ads_destroy(ads_ctx* ctx);

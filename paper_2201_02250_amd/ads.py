@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libads.so")
 
-ADS_ABI_VERSION = 2
+ADS_ABI_VERSION = 3
 ADS_MAX_RESULTS = 64
 ADS_OK, ADS_KSP_MAXIT, ADS_KSP_BREAKDOWN = 0, 1, 2
 ADS_ERR_ARG, ADS_ERR_HIP, ADS_ERR_OOM, ADS_ERR_SINGULAR = -1, -2, -3, -4
@@ -31,7 +31,8 @@ SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_solve", "ads_get_
            "ads_set_graphs", "ads_destroy", "ads_status_string", "ads_last_error",
            "ads_gnn_nparams", "ads_gnn_workspace_floats", "ads_gnn_graph_size",
            "ads_gnn_graph_build", "ads_gnn_targets", "ads_gnn_forward", "ads_gnn_loss",
-           "ads_gnn_backward", "ads_gnn_adam", "ads_gnn_round_bf16"]
+           "ads_gnn_backward", "ads_gnn_adam", "ads_gnn_round_bf16", "ads_tune_cache_save",
+           "ads_tune_cache_load", "ads_tune_cache_clear"]
 
 
 class ads_csr(C.Structure):
@@ -44,7 +45,7 @@ class ads_options(C.Structure):
                 ("tau", C.c_double), ("variant", C.c_int32), ("precision", C.c_int32),
                 ("warm_start", C.c_int32), ("eig_tol", C.c_double), ("eig_max_sweeps", C.c_int32),
                 ("gnn_weights_path", C.c_char_p), ("profile", C.c_int32),
-                ("eig_solver", C.c_int32)]
+                ("eig_solver", C.c_int32), ("autotune", C.c_int32)]
 
 
 class ads_gnn_shape(C.Structure):
@@ -80,7 +81,8 @@ class ads_info(C.Structure):
                 ("t_kernel_ms", C.c_double * 4), ("n_kernel", C.c_int64 * 4),
                 ("nev_i", C.c_void_p), ("kernel_dim", C.c_void_p), ("n_i", C.c_void_p),
                 ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p),
-                ("eig_resid", C.c_void_p), ("eig_solver", C.c_int32)]
+                ("eig_resid", C.c_void_p), ("eig_solver", C.c_int32),
+                ("tile_factor", C.c_double), ("tile_tuned", C.c_int32)]
 
 
 class DeviceCSR:
@@ -133,6 +135,9 @@ def lib():
         L.ads_gnn_backward.argtypes = [SH, P, GR, P, P, P, P]
         L.ads_gnn_adam.argtypes = [I64, P, P, P, P, P, I32, F, F, F, F, P]
         L.ads_gnn_round_bf16.argtypes = [I64, P, P, P]
+        L.ads_tune_cache_save.argtypes = [C.c_char_p]
+        L.ads_tune_cache_load.argtypes = [C.c_char_p]
+        L.ads_tune_cache_clear.argtypes = []
         for name in SYMBOLS:
             if name not in ("ads_status_string", "ads_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -189,9 +194,9 @@ def make_csr(A):
 
 def options(overlap, nev, variant=ADS_VARIANT_DEFLATED, precision=ADS_PREC_FP64, tau=0.0,
             eig_tol=0.0, eig_max_sweeps=0, warm_start=0, gnn_weights_path=None, profile=0,
-            eig_solver=0):
+            eig_solver=0, autotune=0):
     return ads_options(ADS_ABI_VERSION, overlap, nev, tau, variant, precision, warm_start, eig_tol,
-                       eig_max_sweeps, gnn_weights_path, profile, eig_solver)
+                       eig_max_sweeps, gnn_weights_path, profile, eig_solver, autotune)
 
 
 def ads_setup(A, part, nparts, opts, stream=None):
@@ -302,14 +307,14 @@ class Context:
 
     def __init__(self, As, parts, nparts, overlap, nev, variant=ADS_VARIANT_DEFLATED,
                  precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None,
-                 profile=0, eig_solver=0, warm_start=0, gnn_weights_path=None):
+                 profile=0, eig_solver=0, warm_start=0, gnn_weights_path=None, autotune=0):
         if not isinstance(As, (list, tuple)):
             As, parts, nparts = [As], [parts], [nparts]
         self._path = (gnn_weights_path.encode() if isinstance(gnn_weights_path, str)
                       else gnn_weights_path)  # kept alive for the call
         self.opts = options(overlap, nev, variant, precision, tau, eig_tol, eig_max_sweeps,
                             warm_start=warm_start, gnn_weights_path=self._path, profile=profile,
-                            eig_solver=eig_solver)
+                            eig_solver=eig_solver, autotune=autotune)
         self.stream = stream
         self.ctx = ads_setup_batched(As, parts, nparts, self.opts, stream)
         self.info = ads_get_info(self.ctx)

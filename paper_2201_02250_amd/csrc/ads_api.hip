@@ -262,6 +262,8 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->t_phase_ms[0] = tm.lap();
     extract_local(*c);
     c->t_phase_ms[1] = tm.lap();
+    tune_tiles(*c);
+    c->t_phase_ms[7] = tm.lap();
     factor_local(*c);
     c->t_phase_ms[2] = tm.lap();
     const bool coarse = opts->variant == ADS_VARIANT_DEFLATED && opts->nev > 0;
@@ -390,6 +392,8 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
     info->eig_unconverged = c.eig_unconverged;
     info->eig_fallbacks = c.eig_fallbacks;
     info->eig_solver = c.eig_krylov_schur ? ADS_EIG_KRYLOV_SCHUR : ADS_EIG_SUBSPACE;
+    info->tile_factor = c.tile_factor;
+    info->tile_tuned = c.tile_tuned;
     for (int k = 0; k < 8; ++k) info->t_phase_ms[k] = c.t_phase_ms[k];
     ctx->c->prof_resolve();
     for (int k = 0; k < 4; ++k) {

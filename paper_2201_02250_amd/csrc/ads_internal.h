@@ -165,6 +165,10 @@ struct Ctx {
 
   // block-tridiagonal factors
   std::vector<int32_t> h_bs, h_nb;  // block size and block count per subdomain
+  std::vector<int32_t> h_bw;        // local bandwidth (smallest valid block size)
+  int32_t* bw_d = nullptr;          // its device copy
+  double tile_factor = 1.0;         // block size / bandwidth target chosen by the tuner
+  int tile_tuned = 0;               // 0 default tiles, 1 timed now, 2 from the tuning cache
   std::vector<int64_t> h_fac_off;   // per subdomain, in elements, per matrix
   int32_t* bs = nullptr;
   int32_t* nb = nullptr;
@@ -274,7 +278,11 @@ void learned_start(Ctx& c);
 // ---------------------------------------------------------------------------
 void build_maps(Ctx& c, const std::vector<int32_t>& part_host_concat);
 void extract_local(Ctx& c);
-void factor_local(Ctx& c);
+void set_tiles(Ctx& c, const std::vector<int32_t>& sizes);
+void tune_tiles(Ctx& c);
+double time_local_solve(Ctx& c, int reps);
+void release_factors(Ctx& c);
+void factor_local(Ctx& c, bool only_a = false);
 void eigensolve(Ctx& c);
 void assemble_coarse(Ctx& c);
 void ensure_work(Ctx& c, int cols);

@@ -330,6 +330,47 @@ static void local_dispatch(Ctx& c, const double* r, const double* q, double* z, 
   }
 }
 
+// average time (ms) of one local solve (both chain launches, nrhs = 1) on
+// the current tiles, from hipEvents around reps launches after a warm-up
+// launch; the apply workspace is released afterwards (its size depends on
+// the tiles and on the coarse dimension)
+double time_local_solve(Ctx& c, int reps) {
+  hipStream_t st = c.stream;
+  ensure_work(c, 1);
+  double* r = c.mem.alloc<double>(c.n);
+  double* q = c.mem.alloc<double>(c.n);
+  double* z = c.mem.alloc<double>(c.n);
+  ADS_HIP(hipMemsetAsync(r, 0, c.n * 8, st));
+  ADS_HIP(hipMemsetAsync(q, 0, c.n * 8, st));
+  auto run = [&]() {
+    switch (c.prec) {
+      case ADS_PREC_FP64: local_dispatch<double>(c, r, q, z, 1, st); break;
+      case ADS_PREC_FP32: local_dispatch<float>(c, r, q, z, 1, st); break;
+      default: local_dispatch<__hip_bfloat16>(c, r, q, z, 1, st); break;
+    }
+  };
+  run();
+  hipEvent_t e0, e1;
+  ADS_HIP(hipEventCreate(&e0));
+  ADS_HIP(hipEventCreate(&e1));
+  ADS_HIP(hipEventRecord(e0, st));
+  for (int k = 0; k < reps; ++k) run();
+  ADS_HIP(hipEventRecord(e1, st));
+  ADS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  ADS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (double* p : {r, q, z}) c.mem.release(p);
+  for (double** p : {&c.work, &c.work2, &c.dummy, &c.cvec, &c.qvec})
+    if (*p) {
+      c.mem.release(*p);
+      *p = nullptr;
+    }
+  c.work_cols = 0;
+  return (double)ms / reps;
+}
+
 // records a hipEvent pair around a launch when profiling is on
 struct ProfScope {
   Ctx& c;

@@ -226,11 +226,28 @@ void extract_local(Ctx& c) {
   download(c.h_kdim, c.kdim, nsub, s);
   std::vector<int32_t> hbw;
   download(hbw, bw, nsub, s);
+  c.h_bw.resize(nsub);
+  for (int i = 0; i < nsub; ++i) c.h_bw[i] = std::max(1, hbw[i]);
+  c.bw_d = upload(c.mem, c.h_bw.data(), nsub, s);
+  c.mem.release(cnt);
+  set_tiles(c, c.h_bw);
+}
+
+// Block sizes of the block-tridiagonal form (any size >= the local bandwidth
+// is valid): the padded layout, the four coupling lists and the fast-path
+// flags.  Replaces a previous layout.
+void set_tiles(Ctx& c, const std::vector<int32_t>& sizes) {
+  hipStream_t s = c.stream;
+  const int nsub = c.nsub;
+  for (void* q : {(void*)c.bs, (void*)c.nb, (void*)c.pad_off, (void*)c.cpl_col, (void*)c.cpl_val,
+                  (void*)c.rcpl_col, (void*)c.rcpl_val, (void*)c.ucpl_row, (void*)c.ucpl_val,
+                  (void*)c.lcpl_row, (void*)c.lcpl_val})
+    if (q) c.mem.release(q);
   c.h_bs.resize(nsub);
   c.h_nb.resize(nsub);
   c.h_pad_off.assign(nsub + 1, 0);
   for (int i = 0; i < nsub; ++i) {
-    int b = std::max(1, hbw[i]);
+    const int b = std::max(sizes[i], c.h_bw[i]);
     c.h_bs[i] = b;
     c.h_nb[i] = (c.h_ni[i] + b - 1) / b;
     c.h_pad_off[i + 1] = c.h_pad_off[i] + (int64_t)c.h_nb[i] * b;
@@ -239,7 +256,6 @@ void extract_local(Ctx& c) {
   c.bs = upload(c.mem, c.h_bs.data(), nsub, s);
   c.nb = upload(c.mem, c.h_nb.data(), nsub, s);
   c.pad_off = upload(c.mem, c.h_pad_off.data(), nsub + 1, s);
-  c.mem.release(cnt);
   // the four coupling lists of the block-tridiagonal form (tile solves and
   // the two-ended factorization)
   const int64_t NP = c.npad_total;
@@ -268,6 +284,7 @@ void extract_local(Ctx& c) {
   std::vector<int32_t> hov;
   download(hov, ovf, 1, s);
   c.mem.release(ucnt);
+  c.mem.release(ovf);
   // fast path (two-ended factorization, prefetching tile solves): every list
   // complete and every block size within the solve and factorization limits
   c.cpl_ok = hov[0] == 0;

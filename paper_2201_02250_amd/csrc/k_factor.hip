@@ -515,7 +515,15 @@ static void factor_one(Ctx& c, int splitting, void** out) {
                                " of subdomain " + std::to_string(hb[0] - 1));
 }
 
-void factor_local(Ctx& c) {
+void release_factors(Ctx& c) {
+  for (void** p : {&c.facA, &c.facT, (void**)&c.fac_off})
+    if (*p) {
+      c.mem.release(*p);
+      *p = nullptr;
+    }
+}
+
+void factor_local(Ctx& c, bool only_a) {
   const int nsub = c.nsub;
   c.h_fac_off.assign(nsub + 1, 0);
   const int V = c.prec == ADS_PREC_FP64 ? 2 : (c.prec == ADS_PREC_FP32 ? 4 : 8);
@@ -523,7 +531,7 @@ void factor_local(Ctx& c) {
     c.h_fac_off[i + 1] = c.h_fac_off[i] + (int64_t)2 * c.h_nb[i] * adsd::tile_size(c.h_bs[i], V);
   c.fac_elems = c.h_fac_off[nsub];
   c.fac_off = upload(c.mem, c.h_fac_off.data(), nsub + 1, c.stream);
-  const bool need_split = c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0;
+  const bool need_split = !only_a && c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0;
   size_t esz = c.prec == ADS_PREC_FP64 ? 8 : (c.prec == ADS_PREC_FP32 ? 4 : 2);
   c.factor_bytes = (int64_t)(c.fac_elems * esz);
   if (c.solve_fast) {  // two-ended layout, read by the fast solves

@@ -554,7 +554,7 @@ void gnn_graph_impl(const Ctx& c, int64_t* node_off, int64_t* row_ptr, int32_t* 
              dmean, err);
   const int64_t T = c.omega_total;
   ADS_LAUNCH(k_gnn_graph, dim3((unsigned)((T + 256) / 256)), dim3(256), 0, st, T, c.om_sub,
-             c.om_off, c.om_int, c.lptr_off, c.lcol, c.lval, c.lsum, c.bs, dmean, row_ptr, col, w,
+             c.om_off, c.om_int, c.lptr_off, c.lcol, c.lval, c.lsum, c.bw_d, dmean, row_ptr, col, w,
              feat, mask);
   ADS_HIP(hipMemcpyAsync(node_off, c.om_off, (c.nsub + 1) * 8, hipMemcpyDeviceToDevice, st));
   std::vector<int32_t> he;

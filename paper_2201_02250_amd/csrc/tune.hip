@@ -1,0 +1,188 @@
+// Autotuner of the tile shape: the block size s_i of every subdomain's
+// block-tridiagonal form.  Any s_i at or above the local bandwidth b_i is a
+// valid block size; a larger one shortens the dependent chain of the
+// factorization, of every local solve and of every eigensolver operator
+// application (K_i = ceil(n_i / s_i) steps) at the price of larger tiles
+// ((2 K_i - 1) s_i^2 entries).  Candidates s_i = ceil(f b_i) for a few
+// factors f, clamped to the largest size the register-resident fast path
+// accepts, are timed on the context's own matrices (factorization of A_ii
+// plus a weighted local solve) and the best factor is kept in a
+// process-wide cache keyed by the shape of the workload, so that later
+// setups of the same shape reuse it without timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "ads_internal.h"
+#include "k_solve.h"
+
+namespace ads {
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, double> g_tune_cache;
+
+constexpr double TUNE_FACTORS[] = {1.0, 1.25, 1.5, 2.0, 2.5};
+// score of a candidate: (matrices factored) x t_factor(A_ii) + APPLY_WEIGHT x
+// t_solve, APPLY_WEIGHT being about the number of chain traversals of one
+// setup and solve (GMRES iterations plus eigensolver operator applications)
+constexpr double APPLY_WEIGHT = 40.0;
+
+std::string shape_key(const Ctx& c) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the per-subdomain sizes
+  auto mix = [&](int64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (int i = 0; i < c.nsub; ++i) {
+    mix(c.h_ni[i]);
+    mix(c.h_bw[i]);
+  }
+  std::ostringstream o;
+  o << "p" << c.prec << "-s" << c.nsys << "-d" << c.nsub << "-n" << c.n << "-z" << c.nnz << "-l"
+    << c.lnnz << "-o" << c.opt.overlap << "-h" << std::hex << h;
+  return o.str();
+}
+
+// block sizes for the factor f: ceil(f b_i), lowered to the largest size the
+// fast path takes (when the bandwidth itself is taken)
+std::vector<int32_t> sizes_for(const Ctx& c, double f) {
+  const int V = c.prec == ADS_PREC_FP64 ? 2 : (c.prec == ADS_PREC_FP32 ? 4 : 8);
+  auto ok = [&](int s) {
+    return adsd::solve_fast_ok(s, adsd::SOLVE_T, 1, V) && adsd::factor_fast_ok(s);
+  };
+  std::vector<int32_t> out(c.nsub);
+  for (int i = 0; i < c.nsub; ++i) {
+    const int b = c.h_bw[i];
+    int s = std::max(b, (int)std::ceil(f * b));
+    s = std::min(s, std::max(b, c.h_ni[i]));
+    if (ok(b))
+      while (s > b && !ok(s)) --s;
+    else
+      s = b;
+    out[i] = s;
+  }
+  return out;
+}
+
+}  // namespace
+
+void tune_tiles(Ctx& c) {
+  c.tile_factor = 1.0;
+  c.tile_tuned = 0;
+  if (!c.opt.autotune) return;  // extract_local set the bandwidth tiles
+  const std::string key = shape_key(c);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c.tile_factor = it->second;
+      c.tile_tuned = 2;
+      if (c.tile_factor != 1.0) set_tiles(c, sizes_for(c, c.tile_factor));
+      return;
+    }
+  }
+  hipStream_t st = c.stream;
+  const bool base_fast = c.solve_fast;
+  const double nmat = (c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0) ? 2.0 : 1.0;
+  double best = 1.0, best_score = 1e300;
+  std::vector<int32_t> last;
+  hipEvent_t e0, e1;
+  ADS_HIP(hipEventCreate(&e0));
+  ADS_HIP(hipEventCreate(&e1));
+  for (double f : TUNE_FACTORS) {
+    std::vector<int32_t> sz = sizes_for(c, f);
+    if (sz == last) continue;
+    last = sz;
+    set_tiles(c, sz);
+    if (base_fast && !c.solve_fast) continue;  // the couplings no longer fit the fast path
+    ADS_HIP(hipEventRecord(e0, st));
+    factor_local(c, true);
+    ADS_HIP(hipEventRecord(e1, st));
+    ADS_HIP(hipEventSynchronize(e1));
+    float tf = 0.0f;
+    ADS_HIP(hipEventElapsedTime(&tf, e0, e1));
+    const double ts = time_local_solve(c, 5);
+    release_factors(c);
+    const double score = nmat * tf + APPLY_WEIGHT * ts;
+    if (score < best_score) {
+      best_score = score;
+      best = f;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_tiles(c, sizes_for(c, best));
+  c.tile_factor = best;
+  c.tile_tuned = 1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best;
+}
+
+}  // namespace ads
+
+using namespace ads;
+
+extern "C" {
+
+int ads_tune_cache_save(const char* path) {
+  try {
+    if (!path) fail(ADS_ERR_ARG, "null path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) fail(ADS_ERR_ARG, std::string("cannot write ") + path);
+    std::fprintf(f, "ads-tune 1\n");
+    for (const auto& kv : g_tune_cache) std::fprintf(f, "%s %.17g\n", kv.first.c_str(), kv.second);
+    std::fclose(f);
+    return ADS_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+}
+
+int ads_tune_cache_load(const char* path) {
+  try {
+    if (!path) fail(ADS_ERR_ARG, "null path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) fail(ADS_ERR_ARG, std::string("cannot read ") + path);
+    char head[32] = {0};
+    int ver = 0;
+    if (std::fscanf(f, "%31s %d", head, &ver) != 2 || std::string(head) != "ads-tune" || ver != 1) {
+      std::fclose(f);
+      fail(ADS_ERR_ARG, "not a tuning cache file");
+    }
+    std::map<std::string, double> add;
+    char key[256];
+    double v = 0.0;
+    while (std::fscanf(f, "%255s %lf", key, &v) == 2) {
+      if (!(v >= 1.0 && v <= 8.0)) {
+        std::fclose(f);
+        fail(ADS_ERR_ARG, "tuning cache entry out of range");
+      }
+      add[key] = v;
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : add) g_tune_cache[kv.first] = kv.second;
+    return ADS_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+}
+
+int ads_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
+  return ADS_OK;
+}
+
+}  // extern "C"

@@ -326,3 +326,38 @@ def test_batched_bfs3d_and_2d_family(prec):
         err = np.linalg.norm(x[sl] - xo) / np.linalg.norm(xo)
         assert err <= (1e-7 if prec == "fp64" else 1e-6), (k, err)
     ctx.close()
+
+
+def test_autotuned_tiles_keep_parity_and_are_cached(tmp_path):
+    """ads_options.autotune: the tile tuner times candidate block sizes on the
+    context's matrices; the preconditioner stays the oracle's (apply within
+    1e-9, same iterations), the choice is cached per workload shape and the
+    cache survives a save / clear / load round trip."""
+    ads.lib().ads_tune_cache_clear()
+    case = CASES[1]
+    name, A, part, N, ov, nev, restart, flex = case
+    P = oracle_for(case)
+    r = np.random.default_rng(3).standard_normal(A.n)
+    b = W.rhs(A.n, 5)
+    xo, io = OS.gmres(A.to_scipy(), b, P.apply, restart=restart, rtol=1e-8, flexible=flex)
+    zo = P.apply(r)
+    factors = []
+    for k in range(3):
+        if k == 2:
+            path = str(tmp_path / "tune.txt")
+            assert ads.lib().ads_tune_cache_save(path.encode()) == 0
+            ads.lib().ads_tune_cache_clear()
+            assert ads.lib().ads_tune_cache_load(path.encode()) == 0
+        ctx = ads.Context(A, part, N, ov, nev, eig_tol=1e-12, autotune=1)
+        assert ctx.info["tile_tuned"] == (1 if k == 0 else 2)
+        factors.append(ctx.info["tile_factor"])
+        assert all(ctx.info["block"] >= 1)
+        z = ctx.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+        assert np.abs(z - zo).max() <= 1e-9 * np.abs(zo).max()
+        x, info = ctx.solve(torch.tensor(b, device=DEV), restart=restart, flexible=flex, rtol=1e-8)
+        assert abs(info["its"][0] - io["its"]) <= 1 and info["relres"][0] <= 1e-8
+        ctx.close()
+    assert factors[0] == factors[1] == factors[2] >= 1.0
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a cache\n")
+    assert ads.lib().ads_tune_cache_load(str(bad).encode()) == ads.ADS_ERR_ARG
