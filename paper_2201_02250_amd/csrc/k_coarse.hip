@@ -157,7 +157,7 @@ __device__ __forceinline__ void gj_better(double& bv, int& bi, double v, int i) 
 
 __global__ void __launch_bounds__(GJ_T)
 k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int nb,
-           double* Sbuf, int32_t* src_all, int32_t* piv_all, int32_t* singular) {
+           double* Sbuf, int32_t* src_all, int32_t* tot_all, int32_t* singular) {
   extern __shared__ double gj_lds[];
   __shared__ double rowk[32], rowkold[32];
   __shared__ double pval[GJ_T / 64];
@@ -205,10 +205,7 @@ k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int
       if (t == 0) atomicMax(singular, sy + 1);
       p = k;
     }
-    if (t == 0) {
-      swp[l] = p;
-      piv_all[sys_coff[sy] + k] = p;
-    }
+    if (t == 0) swp[l] = p;
     // save the pivot column (rows k and p interchanged) and both rows
     for (int i = t; i < n; i += T) {
       const int si = i == k ? p : (i == p ? k : i);
@@ -248,124 +245,132 @@ k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int
   for (int e = t; e < ne; e += T) S[e] = P[e];
   int32_t* so = src_all + sys_coff[sy];
   for (int i = t; i < n; i += T) so[i] = src[i];
+  // cumulative row map: tot(x) <- tot(src(x)), through LDS (fcol is free)
+  int32_t* tot = tot_all + sys_coff[sy];
+  int* tmp = reinterpret_cast<int*>(fcol);
+  for (int i = t; i < n; i += T) tmp[i] = k0 == 0 ? src[i] : tot[src[i]];
+  __syncthreads();
+  for (int i = t; i < n; i += T) tot[i] = tmp[i];
 }
 
-// Register-resident panel (panel width 32, systems of order <= 32 * MR):
-// thread t owns column j = t % 32 for the rows g, g + 32, g + 64, ... of
-// row group g = t / 32.  Rows are never moved: the interchanges are kept as
-// a logical <-> physical row permutation in LDS, and the pivot column of a
-// row comes from the lanes of the same row group by a shuffle.  Two barriers
-// per pivot step; the result S is written in logical row order, so it is the
-// same as the LDS panel kernel's.
-template <int MR>
+// one DPP step of a wave maximum: x = max(x, x of the lane given by CTRL)
+template <int CTRL>
+__device__ __forceinline__ double gj_dpp_max(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return fmax(x, __longlong_as_double(((long long)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double gj_lane(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// maximum over the 64 lanes (every lane active): pairs, quads, half rows and
+// rows of 16 by DPP (quad_perm 1032, quad_perm 2301, row_half_mirror,
+// row_mirror), then the four rows by readlane
+__device__ __forceinline__ double gj_wave_max(double x) {
+  x = gj_dpp_max<0xB1>(x);
+  x = gj_dpp_max<0x4E>(x);
+  x = gj_dpp_max<0x141>(x);
+  x = gj_dpp_max<0x140>(x);
+  return fmax(fmax(gj_lane(x, 0), gj_lane(x, 16)), fmax(gj_lane(x, 32), gj_lane(x, 48)));
+}
+
+// Register-resident panel for systems of order <= GJ_T (panel width 32):
+// thread i owns row i of the n x 32 column panel (rows in the logical order
+// that the previous panels left) and tracks the logical position of that
+// row; rows never move.  One barrier per pivot step: every wave publishes its
+// best pivot candidate (largest |entry| in the pivot column among the rows
+// not yet used, ties to the smaller row) together with that row's values in
+// a double-buffered LDS slot, and every thread then takes the first slot of
+// largest magnitude.  The result S is written in logical row order.
 __global__ void __launch_bounds__(GJ_T)
-k_gj_panel_reg(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
-               double* Sbuf, int32_t* src_all, int32_t* piv_all, int32_t* singular) {
-  extern __shared__ int gj_perm[];  // [2 n]: logical -> physical, physical -> logical
-  __shared__ double rowq[2][32];
-  __shared__ double pval[GJ_T / 64];
-  __shared__ int pidx[GJ_T / 64];
+k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+               double* Sbuf, int32_t* src_all, int32_t* tot_all, int32_t* singular) {
   constexpr int NB = 32;
+  __shared__ double slot_r[2][GJ_T / 64][NB + 1];  // row values, then the key
+  __shared__ int slot_q[2][GJ_T / 64][2];          // physical row, logical position
   const int sy = blockIdx.x;
-  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int base = sys_coff[sy];
+  const int n = sys_coff[sy + 1] - base;
   if (k0 >= n) return;
   const int kb = min(NB, n - k0);
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int j = t & (NB - 1), g = t >> 5, hb = lane & 32;
-  int* lperm = gj_perm;
-  int* lpos = gj_perm + n;
-  const double* A = Ain + E_off[sy];
-  double v[MR];
+  const int i = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(i >> 6);  // wave-uniform
+  const int nw = (int)(blockDim.x + 63) >> 6;
+  const bool live = i < n;
+  const double* A = Ain + E_off[sy] + (int64_t)(live ? i : 0) * n + k0;
+  double v[NB];
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    const int i = g + NB * m;
-    v[m] = (i < n && j < kb) ? A[(int64_t)i * n + k0 + j] : 0.0;
+  for (int j = 0; j < NB; ++j) {
+    const double a = A[min(j, kb - 1)];  // in bounds for every lane
+    v[j] = (live && j < kb) ? a : 0.0;
   }
-  for (int i = t; i < n; i += GJ_T) {
-    lperm[i] = i;
-    lpos[i] = i;
-  }
-  // candidates of the first pivot column
-  double bv = -1.0;
-  int bi = n;
-  if (j == 0)
-#pragma unroll
-    for (int m = 0; m < MR; ++m) {
-      const int i = g + NB * m;
-      if (i >= k0 && i < n) gj_better(bv, bi, fabs(v[m]), i);
-    }
+  int pos = i;
+  bool sing = false;
   for (int l = 0; l < kb; ++l) {
-    const int k = k0 + l;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      gj_better(bv, bi, ov, oi);
-    }
-    if (lane == 0) {
-      pval[wv] = bv;
-      pidx[wv] = bi;
+    const int k = k0 + l, b = l & 1;
+    double f = v[0];  // this row's entry in the pivot column
+#pragma unroll
+    for (int j = 1; j < NB; ++j) f = j == l ? v[j] : f;
+    double cand = (live && pos >= k) ? fabs(f) : -1.0;
+    if (!(cand >= 0.0)) cand = -1.0;  // NaN never wins
+    const double m = gj_wave_max(cand);
+    const bool top = cand == m;
+    const unsigned long long hit = __ballot(top);
+    // the lowest lane holding the maximum: no lane of the ballot below it
+    const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(hit >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)hit, 0u));
+    if (top && below == 0) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) slot_r[b][wv][j] = v[j];
+      slot_r[b][wv][NB] = m;
+      slot_q[b][wv][0] = i;
+      slot_q[b][wv][1] = pos;
     }
     __syncthreads();
-    bv = -1.0;
-    bi = n;
-    for (int w = 0; w < GJ_T / 64; ++w) gj_better(bv, bi, pval[w], pidx[w]);
-    int q = bi;  // physical pivot row
-    if (!(bv > 0.0) || q >= n) {
-      if (t == 0) atomicMax(singular, sy + 1);
-      q = lperm[k];
-    }
-    // publish the pivot row; record the interchange (logical k <-> lpos[q])
-    const int gq = q & (NB - 1), mq = q >> 5;
-    if (g == gq) {
-      double x = v[0];
-#pragma unroll
-      for (int m = 1; m < MR; ++m) x = (m == mq) ? v[m] : x;
-      rowq[l & 1][j] = x;
-    }
-    __syncthreads();
-    if (t == 0) {
-      const int p = lpos[q], a = lperm[k];
-      piv_all[sys_coff[sy] + k] = p;
-      lperm[k] = q;
-      lperm[p] = a;
-      lpos[q] = k;
-      lpos[a] = p;
-    }
-    const double piv = rowq[l & 1][l];
-    double inv = __builtin_amdgcn_rcp(piv);
-    inv = inv * (2.0 - piv * inv);
-    inv = inv * (2.0 - piv * inv);
-    if (piv == 0.0) inv = 1.0;
-    const double rj = rowq[l & 1][j] * inv;
-    const bool jc = j == l;
-    bv = -1.0;
-    bi = n;
-#pragma unroll
-    for (int m = 0; m < MR; ++m) {
-      const int i = g + NB * m;
-      const double f = __shfl(v[m], hb + l, 64);  // this row's pivot-column entry
-      const double x = (i == q) ? (jc ? inv : rj) : (jc ? -f * inv : v[m] - f * rj);
-      v[m] = x;
-    }
-    // candidates of the next pivot column: rows not yet used as pivots
-    // (their logical position after this step is > k)
-    __syncthreads();  // lpos updated by thread 0
-    if (j == l + 1)
-#pragma unroll
-      for (int m = 0; m < MR; ++m) {
-        const int i = g + NB * m;
-        if (i < n && lpos[i] > k) gj_better(bv, bi, fabs(v[m]), i);
+    int w = 0;
+    double best = slot_r[b][0][NB];
+    for (int u = 1; u < nw; ++u) {
+      const double kv = slot_r[b][u][NB];
+      if (kv > best) {
+        best = kv;
+        w = u;
       }
-  }
-  __syncthreads();
-  double* S = Sbuf + (int64_t)NB * sys_coff[sy];
+    }
+    w = __builtin_amdgcn_readfirstlane(w);
+    const double* r = slot_r[b][w];
+    const int q = slot_q[b][w][0], pq = slot_q[b][w][1];
+    sing |= !(best > 0.0);
+    const double piv = r[l];
+    const double inv = piv != 0.0 ? 1.0 / piv : 1.0;
+    const bool me = i == q;
+    const double fi = me ? 0.0 : f * inv;  // row i minus fi times the pivot row
+    const double sc = me ? inv : 1.0;
+    const double vl = me ? inv : -fi;       // the new pivot-column entry
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    const int i = g + NB * m;
-    if (i < n) S[(int64_t)lpos[i] * NB + j] = v[m];
+    for (int j = 0; j < NB; ++j) {
+      const double x = (v[j] - fi * r[j]) * sc;
+      v[j] = j == l ? vl : x;
+    }
+    pos = me ? k : (pos == k ? pq : pos);
   }
-  int32_t* so = src_all + sys_coff[sy];
-  for (int i = t; i < n; i += GJ_T) so[i] = lperm[i];
+  if (i == 0 && sing) atomicMax(singular, sy + 1);
+  int32_t* tot = tot_all + base;
+  int tv = 0;
+  if (live) {
+    double* S = Sbuf + (int64_t)NB * base + (int64_t)pos * NB;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) S[j] = v[j];
+    src_all[base + pos] = i;
+    tv = k0 == 0 ? i : tot[i];
+  }
+  __syncthreads();  // every read of the old cumulative map precedes the writes
+  if (live) tot[pos] = tv;
 }
 
 // out = transform of in for the column block [k0, k0 + kb) (see above);
@@ -422,25 +427,17 @@ k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t
     }
 }
 
-// Einv(:, j) = W(:, c_j), c = the identity with the recorded interchanges
-// applied to positions in reverse order
+// Einv(:, j) = W(:, c_j) with c the inverse of the cumulative row map of
+// the interchanges (c(tot(x)) = x)
 __global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_off,
-                               const int32_t* sys_coff, const int32_t* piv_all, int rows_per_block) {
+                               const int32_t* sys_coff, const int32_t* tot_all, int rows_per_block) {
   extern __shared__ int cmap[];
   const int sy = blockIdx.y;
   const int n = sys_coff[sy + 1] - sys_coff[sy];
   const int r0 = blockIdx.x * rows_per_block;
   if (r0 >= n) return;
-  const int32_t* piv = piv_all + sys_coff[sy];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) cmap[j] = j;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int k = n - 1; k >= 0; --k) {
-      const int p = piv[k];
-      const int tmp = cmap[k];
-      cmap[k] = cmap[p];
-      cmap[p] = tmp;
-    }
+  const int32_t* tot = tot_all + sys_coff[sy];
+  for (int x = threadIdx.x; x < n; x += blockDim.x) cmap[tot[x]] = x;
   __syncthreads();
   const double* W = Win + E_off[sy];
   double* X = Out + E_off[sy];
@@ -491,45 +488,44 @@ void assemble_coarse(Ctx& c) {
   std::vector<int32_t> hf;
   download(hf, flag, 1, st);
   if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
-  // register-resident panels (width 32) up to order 32 * 32, else LDS panels
-  const bool reg = maxs <= 32 * 32;
+  // register-resident panels (width 32, one row per thread) up to order GJ_T,
+  // else LDS panels
+  const bool reg = maxs <= GJ_T;
   const int nb = reg ? 32 : gj_panel_width(maxs);
   if (nb == 0)
     fail(ADS_ERR_UNSUPPORTED, "coarse system of order " + std::to_string(maxs) +
                                   " exceeds the dense inverse limit");
   const int n0t = std::max(c.n0, 1);
-  int32_t* piv = c.mem.alloc<int32_t>(n0t);
+  int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
   double* S = c.mem.alloc<double>((int64_t)n0t * nb);
   double* F = c.mem.alloc<double>(etot);
   double* bufs[2] = {E, F};
   const size_t plds = (size_t)maxs * (nb * 8 + 8 + 4);
   const unsigned tiles = (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
+  const unsigned rows = (unsigned)((maxs + 63) / 64 * 64);  // one thread per row
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
     if (!reg)
       ADS_LAUNCH(k_gj_panel, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], c.E_off, c.sys_coff,
-                 (int)k0, nb, S, src, piv, flag + 1);
-    else if (maxs <= 32 * 17)
-      ADS_LAUNCH(k_gj_panel_reg<17>, dim3(nsys), dim3(GJ_T), (size_t)maxs * 8, st, bufs[cur],
-                 c.E_off, c.sys_coff, (int)k0, S, src, piv, flag + 1);
+                 (int)k0, nb, S, src, tot, flag + 1);
     else
-      ADS_LAUNCH(k_gj_panel_reg<32>, dim3(nsys), dim3(GJ_T), (size_t)maxs * 8, st, bufs[cur],
-                 c.E_off, c.sys_coff, (int)k0, S, src, piv, flag + 1);
+      ADS_LAUNCH(k_gj_panel_row, dim3(nsys), dim3(rows), 0, st, bufs[cur], c.E_off, c.sys_coff,
+                 (int)k0, S, src, tot, flag + 1);
     ADS_LAUNCH(k_gj_update, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur], bufs[1 - cur],
                c.E_off, c.sys_coff, (int)k0, nb, S, src);
     cur = 1 - cur;
   }
   const int rpb = 16;
   ADS_LAUNCH(k_gj_unpermute, dim3((unsigned)((maxs + rpb - 1) / rpb), nsys), dim3(256),
-             (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], c.E_off, c.sys_coff, piv, rpb);
+             (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], c.E_off, c.sys_coff, tot, rpb);
   download(hf, flag, 2, st);
   if (hf[1]) fail(ADS_ERR_SINGULAR, "singular coarse operator in system " + std::to_string(hf[1] - 1));
   c.Einv = bufs[1 - cur];
   c.mem.release(bufs[cur]);
   c.mem.release(S);
   c.mem.release(src);
-  c.mem.release(piv);
+  c.mem.release(tot);
 }
 
 }  // namespace ads

@@ -103,6 +103,9 @@ void tune_tiles(Ctx& c) {
     last = sz;
     set_tiles(c, sz);
     if (base_fast && !c.solve_fast) continue;  // the couplings no longer fit the fast path
+    // untimed first run: the first launch of each kernel instance also loads it
+    factor_local(c, true);
+    release_factors(c);
     ADS_HIP(hipEventRecord(e0, st));
     factor_local(c, true);
     ADS_HIP(hipEventRecord(e1, st));

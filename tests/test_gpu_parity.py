@@ -127,6 +127,26 @@ def test_apply_matches_oracle(case, variant):
     ctx.close()
 
 
+@pytest.mark.parametrize("m,nb,nev,n0", [(96, 12, 7, 1008), (128, 16, 5, 1280)],
+                         ids=["n0-1008-register-panels", "n0-1280-lds-panels"])
+def test_apply_with_large_coarse_systems(m, nb, nev, n0):
+    """Coarse systems of order 1008 (16 waves of one-row-per-thread panels)
+    and 1280 (beyond the register panels: LDS panels of width 8) on
+    nonsymmetric convection-diffusion, where E needs row interchanges."""
+    A = W.convdiff2d(m, 0.02)
+    part = W.block_partition_2d(m, nb)
+    N = nb * nb
+    ctx = ads.Context(A, part, N, 1, nev, eig_tol=1e-12)
+    P = OS.TwoLevelSchwarz(A.to_scipy(), part, N, 1, nev)
+    assert P.n0 == n0 and ctx.info["n0"] == n0
+    R = np.random.default_rng(11).standard_normal((A.n, 2))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    assert err <= 1e-9, err
+    ctx.close()
+
+
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_solve_matches_oracle(case):
     name, A, part, N, ov, nev, restart, flex = case
