@@ -222,7 +222,7 @@ struct Ctx {
   double* work2 = nullptr;  // backward results of the two-ended solve, same shape
   double* dummy = nullptr;  // per-thread discard slots of the tile solves
   int work_cols = 0;
-  double* cvec = nullptr;   // coarse vectors, n0 * cols
+  double* cvec = nullptr;   // partial sums of the coarse restriction, n0 * cols * chunks
   double* qvec = nullptr;   // coarse correction, n * cols
   int cvec_cols = 0;
 

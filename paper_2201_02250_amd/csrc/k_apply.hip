@@ -1,15 +1,18 @@
 // Preconditioner apply, eq. 4 of Section 2 (restricted two-level Schwarz with
 // deflated coarse correction), or eq. 3 (RAS) without a coarse space:
 //
-//   c = R_0 r             k_coarse_restrict   (W_i^T r|Omega_Ii, per subdomain)
-//   y = A_00^{-1} c       k_coarse_prolong    (rows of the explicit inverse of E,
-//   q = R_0^T y                                then W_i y_i on Omega_Ii)
+//   c = R_0 r             k_coarse_restrict   (W_i^T r|Omega_Ii, partial sums per
+//                                              chunk of 512 rows of Omega_Ii)
+//   y = A_00^{-1} c       k_coarse_prolong    (c summed from the partials, rows
+//   q = R_0^T y                                of the explicit inverse of E,
+//                                              then W_i y_i per chunk of rows)
 //   t = r - A q           k_local_solve       (gathered on Omega_i from the CSR)
 //   x_i = A_ii^{-1} t|Omega_i                  (block-tridiagonal tiles)
 //   z = q + sum_i R_i^T D_i x_i               (Boolean D: owner rows only)
 //
 // Three launches per apply.  With the Boolean partition of unity every global
 // row is written by exactly one subdomain, so no atomics are needed.
+#include <algorithm>
 #include <type_traits>
 
 #include "ads_internal.h"
@@ -20,73 +23,134 @@ namespace ads {
 static constexpr int APPLY_T = 256;
 static constexpr int MAXNEV = 32;
 
+// rows of Omega_Ii per block of the coarse restriction and prolongation
+static constexpr int CO_CH = 2 * APPLY_T;
+
+int coarse_chunks(const Ctx& c) {
+  int mx = 1;
+  for (int i = 0; i < c.nsub; ++i) mx = std::max(mx, (c.h_nI[i] + CO_CH - 1) / CO_CH);
+  return mx;
+}
+
+// one DPP step of a wave sum: x + x of the lane given by CTRL (the pairs are
+// symmetric, so both lanes of a pair hold the same value afterwards)
+template <int CTRL>
+__device__ __forceinline__ double co_dpp_add(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return x + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double co_lane(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// deterministic sum over the 64 lanes (every lane active): pairs, quads, half
+// rows and rows of 16 by DPP, then the four rows by readlane; uniform result
+__device__ __forceinline__ double co_wave_sum(double x) {
+  x = co_dpp_add<0xB1>(x);
+  x = co_dpp_add<0x4E>(x);
+  x = co_dpp_add<0x141>(x);
+  x = co_dpp_add<0x140>(x);
+  return (co_lane(x, 0) + co_lane(x, 16)) + (co_lane(x, 32) + co_lane(x, 48));
+}
+
+// out[a stride] = sum over the block of acc[a], a < m (fixed order; threads
+// t < m write)
+template <int N>
+__device__ __forceinline__ void co_block_sums(const double (&acc)[N], int m,
+                                              double (*red)[APPLY_T / 64], double* out,
+                                              int64_t stride) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+    if (a < m) {
+      const double sw = co_wave_sum(acc[a]);
+      if (lane == 0) red[a][wv] = sw;
+    }
+  __syncthreads();
+  if (t < m) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < APPLY_T / 64; ++w) v += red[t][w];
+    out[(int64_t)t * stride] = v;
+  }
+}
+
+// partial sums of c = W_i^T r|Omega_Ii over the rows of chunk ch:
+// part[(j n0 + coff_i + a) nch + ch]
 __global__ void __launch_bounds__(APPLY_T)
 k_coarse_restrict(const double* __restrict__ r, int64_t n, const int32_t* __restrict__ int_list,
                   const int64_t* __restrict__ om_off, const int32_t* __restrict__ nI,
                   const double* __restrict__ W, const int64_t* __restrict__ W_off,
                   const int32_t* __restrict__ nev, const int32_t* __restrict__ coff,
-                  double* __restrict__ c, int n0) {
-  __shared__ double red[16];
-  const int i = blockIdx.x, j = blockIdx.y;
+                  double* __restrict__ part, int n0, int nch) {
+  __shared__ double red[MAXNEV][APPLY_T / 64];
+  const int i = blockIdx.x, ch = blockIdx.y, j = blockIdx.z;
   const int m = nev[i];
   if (m == 0) return;
-  const int nint = nI[i];
+  const int k0 = ch * CO_CH, k1 = min(nI[i], k0 + CO_CH);
   const int32_t* rows = int_list + om_off[i];
   const double* Wi = W + W_off[i];
   const double* rj = r + (int64_t)j * n;
   double acc[MAXNEV];
 #pragma unroll
   for (int a = 0; a < MAXNEV; ++a) acc[a] = 0.0;
-  for (int k = threadIdx.x; k < nint; k += blockDim.x) {
+  for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) {
     const double rv = rj[rows[k]];
     const double* w = Wi + (int64_t)k * m;
 #pragma unroll
     for (int a = 0; a < MAXNEV; ++a)
       if (a < m) acc[a] += w[a] * rv;
   }
-#pragma unroll
-  for (int a = 0; a < MAXNEV; ++a) {
-    if (a < m) {
-      double v = adsd::block_sum(acc[a], red);
-      if (threadIdx.x == 0) c[(int64_t)j * n0 + coff[i] + a] = v;
-    }
-  }
+  co_block_sums(acc, m, red, part + ((int64_t)j * n0 + coff[i]) * nch + ch, nch);
 }
 
+// y_i = rows coff_i .. coff_i + m of E^{-1} times c (c summed from the
+// restriction's partials in a fixed order), then q = W_i y_i on the rows of
+// chunk ch
 __global__ void __launch_bounds__(APPLY_T)
-k_coarse_prolong(const double* __restrict__ c, int n0, const double* __restrict__ Einv,
+k_coarse_prolong(const double* __restrict__ part, int n0, int nch, const double* __restrict__ Einv,
                  const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
                  const int32_t* __restrict__ sub_sys, const int32_t* __restrict__ int_list,
                  const int64_t* __restrict__ om_off, const int32_t* __restrict__ nI,
                  const double* __restrict__ W, const int64_t* __restrict__ W_off,
                  const int32_t* __restrict__ nev, const int32_t* __restrict__ coff,
                  double* __restrict__ q, int64_t n) {
-  __shared__ double red[16];
+  __shared__ double red[MAXNEV][APPLY_T / 64];
   __shared__ double y[MAXNEV];
-  const int i = blockIdx.x, j = blockIdx.y;
+  const int i = blockIdx.x, ch = blockIdx.y, j = blockIdx.z;
   const int m = nev[i];
-  const int nint = nI[i];
+  const int k0 = ch * CO_CH, k1 = min(nI[i], k0 + CO_CH);
+  if (k0 >= k1) return;
   const int32_t* rows = int_list + om_off[i];
   double* qj = q + (int64_t)j * n;
   if (m == 0) {
-    for (int k = threadIdx.x; k < nint; k += blockDim.x) qj[rows[k]] = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) qj[rows[k]] = 0.0;
     return;
   }
   const int sy = sub_sys[i];
   const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
-  const double* cj = c + (int64_t)j * n0 + c0;
-  const double* E = Einv + E_off[sy];
-  const int row0 = coff[i] - c0;
-  for (int a = 0; a < m; ++a) {
-    const double* er = E + (int64_t)(row0 + a) * ns;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < ns; b += blockDim.x) acc += er[b] * cj[b];
-    acc = adsd::block_sum(acc, red);
-    if (threadIdx.x == 0) y[a] = acc;
+  const double* pj = part + ((int64_t)j * n0 + c0) * nch;
+  const double* E = Einv + E_off[sy] + (int64_t)(coff[i] - c0) * ns;
+  double acc[MAXNEV];
+#pragma unroll
+  for (int a = 0; a < MAXNEV; ++a) acc[a] = 0.0;
+  for (int b = threadIdx.x; b < ns; b += APPLY_T) {
+    double cb = 0.0;
+    for (int h = 0; h < nch; ++h) cb += pj[(int64_t)b * nch + h];
+#pragma unroll
+    for (int a = 0; a < MAXNEV; ++a)
+      if (a < m) acc[a] += E[(int64_t)a * ns + b] * cb;
   }
+  co_block_sums(acc, m, red, y, 1);
   __syncthreads();
   const double* Wi = W + W_off[i];
-  for (int k = threadIdx.x; k < nint; k += blockDim.x) {
+  for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) {
     const double* w = Wi + (int64_t)k * m;
     double v = 0.0;
     for (int a = 0; a < m; ++a) v += w[a] * y[a];
@@ -260,7 +324,8 @@ void ensure_work(Ctx& c, int cols) {
   // one discard slot per thread of a fast-path launch: subdomain x column
   // chunk (at least one column per chunk) x half
   c.dummy = c.mem.alloc<double>((size_t)c.nsub * cols * 2 * adsd::SOLVE_T);
-  c.cvec = c.mem.alloc<double>((size_t)std::max(c.n0, 1) * cols);
+  // partial sums of the coarse restriction: one per (coarse entry, row chunk)
+  c.cvec = c.mem.alloc<double>((size_t)std::max(c.n0, 1) * cols * coarse_chunks(c));
   c.qvec = c.mem.alloc<double>((size_t)c.n * cols);
   c.work_cols = cols;
 }
@@ -421,16 +486,17 @@ static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStrea
   ProfScope all(c, 3, s);
   const double* q = nullptr;
   if (c.n0 > 0) {
+    const int nch = coarse_chunks(c);
     {
       ProfScope p1(c, 1, s);
-      ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nrhs), dim3(APPLY_T), 0, s, r, c.n, c.int_list,
-                 c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, c.cvec, c.n0);
+      ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, r, c.n,
+                 c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, c.cvec, c.n0, nch);
     }
     {
       ProfScope p2(c, 2, s);
-      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nrhs), dim3(APPLY_T), 0, s, c.cvec, c.n0, c.Einv,
-                 c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W, c.W_off,
-                 c.nev, c.coff, c.qvec, c.n);
+      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, c.cvec, c.n0, nch,
+                 c.Einv, c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W,
+                 c.W_off, c.nev, c.coff, c.qvec, c.n);
     }
     q = c.qvec;
   }
