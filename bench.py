@@ -179,31 +179,33 @@ def main():
         # the production form tunes its tile shapes (the first, warm-up, setup
         # times the candidates; later setups of the same shape hit the cache);
         # the plain FP64 form keeps the bandwidth tiles
+        # one whole job: setup, solve and release of the context (its device
+        # memory goes back to the library's block cache for the next job)
         ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=p, stream=sp,
                           autotune=int(p != ads.ADS_PREC_FP64))
         x, info = ctx.solve(b, restart=o["restart"], flexible=True, rtol=1e-8)
-        return ctx, x, info
+        info["ctx_info"] = ctx.info
+        ctx.close()
+        return x, info
 
     def timed(p, steps, warmup, label):
         for _ in range(warmup):
-            c, x, info = step(p)
-            c.close()
+            step(p)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         runs = [step(p) for _ in range(steps)]
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        for c, x, info in runs:
+        for x, info in runs:
             assert info["status"] == 0, (label, info)
-        c, x, info = runs[-1]
+        x, info = runs[-1]
         xh, bh = x.cpu().numpy(), b.cpu().numpy()
         relres = float(np.linalg.norm(bh - A.to_scipy() @ xh) / np.linalg.norm(bh))
+        ci = info["ctx_info"]
         meta = dict(its=info["its"][0], relres=relres, setup_ms=info["t_setup_ms"],
-                    solve_ms=info["t_solve_ms"], phases=c.info["t_phase_ms"][:8],
-                    n0=c.info["n0"], eig_sweeps_max=c.info["eig_sweeps_max"],
-                    tile_factor=c.info["tile_factor"], tile_tuned=c.info["tile_tuned"])
-        for c, x, info in runs:
-            c.close()
+                    solve_ms=info["t_solve_ms"], phases=ci["t_phase_ms"][:8],
+                    n0=ci["n0"], eig_sweeps_max=ci["eig_sweeps_max"],
+                    tile_factor=ci["tile_factor"], tile_tuned=ci["tile_tuned"])
         print("[bench] %s: %.2f ms/step its %d relres %.2e" % (label, dt * 1e3, meta["its"], relres),
               file=sys.stderr, flush=True)
         return dt, meta

@@ -116,7 +116,11 @@ typedef struct {
                              parameters (little endian, order of ads_gnn_*)         */
   int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream
                              (reported in ads_info.t_kernel_ms / n_kernel)           */
-  int32_t eig_solver;     /* ADS_EIG_*: method for the eq. 5 eigenproblems            */
+  int32_t eig_solver;     /* ADS_EIG_*: method for the eq. 5 eigenproblems; a block
+                             Krylov-Schur run whose basis loses rank (a Krylov space
+                             exhausted on very small subdomains) is redone with the
+                             block subspace iteration (counted in eig_fallbacks,
+                             reported in ads_info.eig_solver)                        */
   int32_t autotune;       /* 0: block size of every subdomain's block-tridiagonal
                              form = its local bandwidth; 1: pick the block sizes by
                              timing candidates (ceil(f * bandwidth), f in
@@ -149,7 +153,8 @@ typedef struct {
   int32_t n0;             /* coarse dimension, all systems                            */
   int32_t eig_sweeps_max; /* largest eigensolver sweep count over subdomains          */
   int32_t eig_unconverged;/* subdomains that hit eig_max_sweeps                       */
-  int32_t eig_fallbacks;  /* warm starts rejected in favour of the cold start         */
+  int32_t eig_fallbacks;  /* warm starts rejected in favour of the cold start, or 1
+                             when Krylov-Schur fell back to the subspace iteration  */
   double t_phase_ms[8];   /* maps, extract, factor, eig, coarse, other, learned start,
                              tile tuning                                            */
   double t_kernel_ms[4];  /* profile = 1: summed device time of the apply kernels:

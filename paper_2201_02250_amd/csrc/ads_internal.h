@@ -210,6 +210,7 @@ struct Ctx {
   double* Einv = nullptr;
   int32_t eig_sweeps_max = 0, eig_unconverged = 0, eig_fallbacks = 0;
   bool eig_krylov_schur = false;  // block Krylov-Schur ran (else block subspace iteration)
+  bool eig_ks_lost_rank = false;  // Krylov-Schur lost rank: the setup uses subspace iteration
   // learned warm start: the network's block (node rows of Omega_i in sorted
   // order x gnn_cols, FP32), set by learned_start for the eigensolve
   float* gnn_x = nullptr;

@@ -2570,8 +2570,8 @@ void eigensolve(Ctx& c) {
   for (int i = 0; i < nsub; ++i)
     km = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
   const int kkeep = std::min(std::max(2 * nev, km / 2), km - 2 * EIG_PC);
-  const bool ks = !warm && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && km >= nev + 2 * EIG_PC &&
-                  kkeep >= nev && kkeep + EIG_PC <= km;
+  const bool ks = !warm && !c.eig_ks_lost_rank && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR &&
+                  km >= nev + 2 * EIG_PC && kkeep >= nev && kkeep + EIG_PC <= km;
   if (!ks && p < nev + 1)
     fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
   c.eig_krylov_schur = ks;
@@ -2731,6 +2731,15 @@ void eigensolve(Ctx& c) {
       eigensolve(c);
       return;
     }
+  }
+  if (ks && (herr[0] & 2)) {
+    // a new block numerically inside the basis (the Krylov space of a very
+    // small subdomain exhausted): the block subspace iteration instead
+    release_all();
+    c.eig_ks_lost_rank = true;
+    c.eig_fallbacks = std::max(c.eig_fallbacks, 1);
+    eigensolve(c);
+    return;
   }
   if (herr[0] & 4) fail(ADS_ERR_EIG_NOCONV, "small dense eigensolver did not converge");
   if (herr[0] & 16)
