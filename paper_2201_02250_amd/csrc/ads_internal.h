@@ -237,6 +237,27 @@ struct Ctx {
   bool use_graphs = true;
   bool capturing = false;           // inside a capture: launch eagerly
   hipStream_t priv = nullptr;       // the context's own stream (default priority)
+  // pinned host staging of the solver's per-step status
+  struct Pinned {
+    double* p = nullptr;
+    size_t n = 0;
+    double* get(size_t need) {
+      if (n < need) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        if (hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+          p = nullptr;
+          return nullptr;
+        }
+        n = need;
+      }
+      return p;
+    }
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+    }
+  } pin;
   hipEvent_t dep_ev = nullptr;      // orders priv against the caller's stream
   hipGraphExec_t apply_exec = nullptr;
   const double* ag_r = nullptr;

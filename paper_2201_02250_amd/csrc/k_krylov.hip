@@ -327,13 +327,16 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   const bool use_graph = c.graphs_on() && st == c.priv;
   if (c.work_cols < nrhs) c.drop_apply_graph();
   ensure_work(c, nrhs);
-  hipGraphExec_t step_exec = nullptr;
+  // two captured forms of one Arnoldi step: alone, and preceded by the
+  // previous step's basis update (k_advance, k_next_basis) when no instance
+  // ended its cycle there
+  hipGraphExec_t step_exec = nullptr, step_exec2 = nullptr;
   struct ExecGuard {
     hipGraphExec_t& e;
     ~ExecGuard() {
       if (e) (void)hipGraphExecDestroy(e);
     }
-  } exec_guard{step_exec};
+  } exec_guard{step_exec}, exec_guard2{step_exec2};
   // instance table
   std::vector<int64_t> hrow0(Q), hrows(Q);
   std::vector<int32_t> hcol(Q);
@@ -382,6 +385,9 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   double* bnorm_d = mem.alloc<double>(Q);
   double* beta_d = mem.alloc<double>(Q);
   int32_t* act_d = mem.alloc<int32_t>(Q);
+  int32_t* cont_d = mem.alloc<int32_t>(Q);  // instances continuing their cycle
+  double* stat_h = c.pin.get((size_t)3 * Q);
+  if (!stat_h) fail(ADS_ERR_OOM, "pinned host memory for the solver status");
   int32_t* endm_d = mem.alloc<int32_t>(Q);
   int32_t* jend_d = mem.alloc<int32_t>(Q);
   int32_t* all_d = mem.alloc<int32_t>(Q);
@@ -433,6 +439,12 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
     for (int q = 0; q < Q; ++q) mk[q] = state[q] == 0;
     start_cycles(mk);
   }
+  bool pending = false;  // k_advance / k_next_basis of the last step not yet launched
+  std::vector<int32_t> cont_up;
+  auto basis_update = [&]() {
+    ADS_LAUNCH(k_advance, dim3((Q + 63) / 64), dim3(64), 0, st, S, cont_d, Q);
+    ADS_LAUNCH(k_next_basis, gseg, dim3(256), 0, st, dV, w, I, S.jq, cont_d, S.hn);
+  };
   for (;;) {
     bool any = false;
     for (int q = 0; q < Q; ++q) {
@@ -468,29 +480,38 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
       norms(w, act_d, S.hn);
       ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
     };
+    auto update_and_step = [&]() {
+      basis_update();
+      arnoldi_step();
+    };
     if (use_graph) {
-      if (!step_exec) {
+      hipGraphExec_t& ex = pending ? step_exec2 : step_exec;
+      if (!ex) {
         c.capturing = true;
         try {
-          step_exec = capture_graph(st, arnoldi_step);
+          ex = pending ? capture_graph(st, update_and_step) : capture_graph(st, arnoldi_step);
         } catch (...) {
           c.capturing = false;
           throw;
         }
         c.capturing = false;
       }
-      ADS_HIP(hipGraphLaunch(step_exec, st));
+      ADS_HIP(hipGraphLaunch(ex, st));
+    } else if (pending) {
+      update_and_step();
     } else {
       arnoldi_step();
     }
-    std::vector<double> hstat;
-    download(hstat, stat, (size_t)3 * Q, st);
+    pending = false;
+    // status of the step (est | hn | brk) through pinned memory
+    ADS_HIP(hipMemcpyAsync(stat_h, stat, (size_t)3 * Q * sizeof(double), hipMemcpyDeviceToHost, st));
+    ADS_HIP(hipStreamSynchronize(st));
     std::vector<int32_t> brk(Q);
     for (int q = 0; q < Q; ++q) {
-      est[q] = hstat[q];
-      hn[q] = hstat[Q + q];
+      est[q] = stat_h[q];
+      hn[q] = stat_h[Q + q];
     }
-    std::memcpy(brk.data(), hstat.data() + 2 * Q, (size_t)Q * 4);
+    std::memcpy(brk.data(), stat_h + 2 * Q, (size_t)Q * 4);
     bool anyend = false;
     for (int q = 0; q < Q; ++q) {
       endm[q] = 0;
@@ -510,15 +531,19 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
         jcur[q] += 1;
       }
     }
-    // next basis vector for continuing instances
+    // next basis vector for continuing instances: launched now when a cycle
+    // ends (the end-of-cycle residual reuses w), else at the head of the
+    // next step's graph
     std::vector<int32_t> cont(Q, 0);
     for (int q = 0; q < Q; ++q) cont[q] = act[q] && !endm[q];
-    if (cont != act_up) {
-      ADS_HIP(hipMemcpyAsync(act_d, cont.data(), Q * 4, hipMemcpyHostToDevice, st));
-      act_up = cont;
+    if (cont != cont_up) {
+      ADS_HIP(hipMemcpyAsync(cont_d, cont.data(), Q * 4, hipMemcpyHostToDevice, st));
+      cont_up = cont;
     }
-    ADS_LAUNCH(k_advance, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
-    ADS_LAUNCH(k_next_basis, gseg, dim3(256), 0, st, dV, w, I, S.jq, act_d, S.hn);
+    if (anyend)
+      basis_update();
+    else
+      pending = true;
     if (!anyend) continue;
     // end of cycle: x += Z y  (flexible)  or  x += M (V y)
     ADS_HIP(hipMemcpyAsync(endm_d, endm.data(), Q * 4, hipMemcpyHostToDevice, st));
