@@ -485,9 +485,7 @@ void assemble_coarse(Ctx& c) {
   ADS_LAUNCH(k_coarse_block, dim3(nsub, NB_MAX), dim3(CO_T), 0, st, nbcnt, nblist, c.rowptr, c.col,
              c.val, c.part, c.ipos, c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff,
              c.sub_sys_d, c.sys_coff, c.E_off, E);
-  std::vector<int32_t> hf;
-  download(hf, flag, 1, st);
-  if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
+  std::vector<int32_t> hf;  // both flags are read once, after the inverse
   // register-resident panels (width 32, one row per thread) up to order GJ_T,
   // else LDS panels
   const bool reg = maxs <= GJ_T;
@@ -520,6 +518,7 @@ void assemble_coarse(Ctx& c) {
   ADS_LAUNCH(k_gj_unpermute, dim3((unsigned)((maxs + rpb - 1) / rpb), nsys), dim3(256),
              (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], c.E_off, c.sys_coff, tot, rpb);
   download(hf, flag, 2, st);
+  if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
   if (hf[1]) fail(ADS_ERR_SINGULAR, "singular coarse operator in system " + std::to_string(hf[1] - 1));
   c.Einv = bufs[1 - cur];
   c.mem.release(bufs[cur]);

@@ -2335,7 +2335,7 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
                c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
   int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
   if (a.x0) maxsw = std::min(maxsw, WARM_SWEEPS);  // then the cold fallback
-  std::vector<int32_t> hdone, hnext;
+  std::vector<int32_t> hdone(nsub, 0), hnext(nsub, 0), hint;
   int next = 3;  // first Rayleigh-Ritz step after 4 sweeps
   for (int sw = 0; sw < maxsw; ++sw) {
     if (fast) {
@@ -2356,8 +2356,12 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     ADS_LAUNCH(k_eig_rr, dim3(nsub), dim3(EIG_T), 0, st, a);
     ADS_LAUNCH(k_eig_resid, dim3(nblk), dim3(EIG_T), rb_lds, st, a);
     ADS_LAUNCH(k_eig_decide, dim3((nsub + 63) / 64), dim3(64), 0, st, a, nsub, sw, (int)last);
-    download(hdone, a.done, nsub, st);
-    download(hnext, a.next_rr, nsub, st);
+    // err | done | sweeps | msel | jcur | next_rr in one copy
+    download(hint, a.err, 1 + 5 * (size_t)nsub, st);
+    for (int i = 0; i < nsub; ++i) {
+      hdone[i] = hint[1 + i];
+      hnext[i] = hint[1 + 4 * nsub + i];
+    }
     // next check when the slowest unconverged subdomain is predicted to
     // converge (the others keep iterating meanwhile)
     bool all = true;
@@ -2521,7 +2525,7 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   };
   orth_block();  // start block into V(:, 0 .. p-1)
   const int maxsteps = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
-  std::vector<int32_t> hdone(nsub, 0), hj(nsub, 0);
+  std::vector<int32_t> hdone(nsub, 0), hj(nsub, 0), hint;
   int total = 0;
   for (int cyc = 0;; ++cyc) {
     int nst = 0;
@@ -2530,11 +2534,15 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
     for (int k = 0; k < nst; ++k) step();
     total += nst;
     ADS_LAUNCH(k_ks_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)(total >= maxsteps));
-    download(hdone, a.done, nsub, st);
+    // err | done | sweeps | msel | jcur in one copy
+    download(hint, a.err, 1 + 4 * (size_t)nsub, st);
     bool all = true;
-    for (int i = 0; i < nsub; ++i) all &= hdone[i] != 0;
+    for (int i = 0; i < nsub; ++i) {
+      hdone[i] = hint[1 + i];
+      hj[i] = hint[1 + 3 * nsub + i];
+      all &= hdone[i] != 0;
+    }
     if (all) break;
-    download(hj, a.jcur, nsub, st);
     ADS_LAUNCH(k_ks_restart, dim3(nblk), dim3(EIG_T), ks_lds, st, a);
   }
   ADS_HIP(hipStreamSynchronize(st));
@@ -2617,12 +2625,20 @@ void eigensolve(Ctx& c) {
   a.colsum = c.mem.alloc<double>((size_t)nsub * nch * 2 * EIG_PC);
   a.defer = c.solve_fast ? 1 : 0;
   ADS_HIP(hipMemsetAsync(a.colsum, 0, (size_t)nsub * nch * 2 * EIG_PC * 8, st));
-  a.done = c.mem.alloc<int32_t>(nsub);
-  a.sweeps = c.mem.alloc<int32_t>(nsub);
-  a.msel = c.mem.alloc<int32_t>(nsub);
+  // what the host reads back, in one block (one copy per read):
+  // doubles rres | lam, then int32 err | done | sweeps | msel | jcur | next_rr
+  const size_t rep_d = (size_t)nsub * (1 + 2 * PMAX), rep_i = 1 + 5 * (size_t)nsub;
+  double* rep = c.mem.alloc<double>(rep_d + (rep_i + 1) / 2);
+  int32_t* rep_int = reinterpret_cast<int32_t*>(rep + rep_d);
+  a.rres = rep;
+  a.lam = rep + nsub;
+  a.err = rep_int;
+  a.done = rep_int + 1;
+  a.sweeps = rep_int + 1 + nsub;
+  a.msel = rep_int + 1 + 2 * nsub;
+  a.jcur = rep_int + 1 + 3 * nsub;
+  a.next_rr = rep_int + 1 + 4 * nsub;
   a.Vsel = c.mem.alloc<double>((size_t)nsub * VSEL);
-  a.lam = c.mem.alloc<double>((size_t)nsub * 2 * PMAX);
-  a.rres = c.mem.alloc<double>(nsub);
   a.rbest = c.mem.alloc<double>(nsub);
   a.stall = c.mem.alloc<int32_t>(nsub);
   ADS_HIP(hipMemsetAsync(a.rbest, 0, nsub * 8, st));
@@ -2630,7 +2646,6 @@ void eigensolve(Ctx& c) {
   a.swlast = c.mem.alloc<int32_t>(nsub);
   ADS_HIP(hipMemsetAsync(a.rlast, 0, nsub * 8, st));
   ADS_HIP(hipMemsetAsync(a.swlast, 0, nsub * 4, st));
-  a.next_rr = c.mem.alloc<int32_t>(nsub);
   a.HVs = ks ? nullptr : c.mem.alloc<double>((size_t)nsub * PMAX * PMAX);
   // row blocks
   a.lrb = ks ? rb_log2(KS_W + EIG_PC) : rb_log2(p);
@@ -2673,7 +2688,7 @@ void eigensolve(Ctx& c) {
     a.Bk = c.mem.alloc<double>((size_t)nsub * KS_BS);
     ADS_HIP(hipMemsetAsync(a.Bk, 0, (size_t)nsub * KS_BS * 8, st));
     std::vector<int32_t> j0(nsub, -EIG_PC);
-    a.jcur = upload(c.mem, j0.data(), nsub, st);
+    ADS_HIP(hipMemcpyAsync(a.jcur, j0.data(), nsub * 4, hipMemcpyHostToDevice, st));
     a.kprev = c.mem.alloc<int32_t>(nsub);
     a.partK = c.mem.alloc<double>((size_t)c.h_eig_nblk * KS_PK);
     a.partK2 = c.mem.alloc<double>((size_t)c.h_eig_nblk * KS_PK);
@@ -2681,7 +2696,6 @@ void eigensolve(Ctx& c) {
     a.Racc = c.mem.alloc<double>((size_t)nsub * 2 * EIG_PC * EIG_PC);
   }
   ADS_HIP(hipMemsetAsync(a.stall, 0, nsub * 4, st));
-  a.err = c.mem.alloc<int32_t>(1);
   a.p = pw;
   a.x0 = warm ? c.gnn_x : nullptr;
   a.x0_cols = warm ? std::min(c.gnn_cols, pw) : 0;
@@ -2711,7 +2725,7 @@ void eigensolve(Ctx& c) {
     }
   }
   std::vector<int32_t> herr, hm, hsw, hdone;
-  download(herr, a.err, 1, st);
+  download(herr, a.err, 1, st);  // (warm fallback and errors first: small)
   auto release_all = [&]() {
     ADS_HIP(hipStreamSynchronize(st));
     for (void* q : {(void*)a.X, (void*)a.Y, (void*)a.W, (void*)a.partA, (void*)a.partB,
@@ -2746,10 +2760,14 @@ void eigensolve(Ctx& c) {
     fail(ADS_ERR_UNSUPPORTED,
          "an eigenvalue cluster at the cut fills the eigensolver subspace (e.g. overlap 0)");
   if (herr[0] & 2) fail(ADS_ERR_EIG_NOCONV, "loss of orthogonality in the eigensolver block");
-  download(hm, a.msel, nsub, st);
-  download(c.h_sweeps, a.sweeps, nsub, st);
-  download(c.h_eig_res, a.rres, nsub, st);
-  download(hdone, a.done, nsub, st);
+  // the whole report block in one copy
+  std::vector<double> hrep;
+  download(hrep, rep, rep_d + (rep_i + 1) / 2, st);
+  const int32_t* hi = reinterpret_cast<const int32_t*>(hrep.data() + rep_d);
+  hm.assign(hi + 1 + 2 * nsub, hi + 1 + 3 * nsub);
+  c.h_sweeps.assign(hi + 1 + nsub, hi + 1 + 2 * nsub);
+  c.h_eig_res.assign(hrep.begin(), hrep.begin() + nsub);
+  hdone.assign(hi + 1, hi + 1 + nsub);
   c.eig_sweeps_max = 0;
   c.eig_unconverged = 0;
   for (int i = 0; i < nsub; ++i) {
@@ -2770,8 +2788,7 @@ void eigensolve(Ctx& c) {
     c.h_W_off[i + 1] = c.h_W_off[i] + (int64_t)c.h_nI[i] * c.h_nev[i];
   }
   c.n0 = c.h_coff[nsub];
-  std::vector<double> hlam;
-  download(hlam, a.lam, (size_t)nsub * 2 * PMAX, st);
+  const double* hlam = hrep.data() + nsub;
   c.h_lam_re.clear();
   c.h_lam_im.clear();
   for (int i = 0; i < nsub; ++i) {

@@ -202,7 +202,9 @@ void extract_local(Ctx& c) {
   const int nsub = c.nsub;
   int32_t* cnt = c.mem.alloc<int32_t>(T + 1);
   c.lsum = c.mem.alloc<double>(T);
-  int32_t* bw = c.mem.alloc<int32_t>(nsub);
+  // kernel dimension | bandwidth in one block (one copy back)
+  int32_t* kb = c.mem.alloc<int32_t>(2 * (size_t)nsub);
+  int32_t* bw = kb + nsub;
   int32_t* nfail = c.mem.alloc<int32_t>(nsub);
   ADS_HIP(hipMemsetAsync(bw, 0, nsub * 4, s));
   ADS_HIP(hipMemsetAsync(nfail, 0, nsub * 4, s));
@@ -221,13 +223,13 @@ void extract_local(Ctx& c) {
   c.lval = c.mem.alloc<double>(c.lnnz);
   ADS_LAUNCH(k_extract_fill, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
              c.om_sub, c.wlo, c.whi, c.woff, c.wpos, T, lrow, c.lcol, c.lval);
-  c.kdim = c.mem.alloc<int32_t>(nsub);
+  c.kdim = kb;
   ADS_LAUNCH(k_kernel_dim, dim3((nsub + 255) / 256), dim3(256), 0, s, nfail, nsub, c.kdim);
-  download(c.h_kdim, c.kdim, nsub, s);
-  std::vector<int32_t> hbw;
-  download(hbw, bw, nsub, s);
+  std::vector<int32_t> hkb;
+  download(hkb, kb, 2 * (size_t)nsub, s);
+  c.h_kdim.assign(hkb.begin(), hkb.begin() + nsub);
   c.h_bw.resize(nsub);
-  for (int i = 0; i < nsub; ++i) c.h_bw[i] = std::max(1, hbw[i]);
+  for (int i = 0; i < nsub; ++i) c.h_bw[i] = std::max(1, hkb[nsub + i]);
   c.bw_d = upload(c.mem, c.h_bw.data(), nsub, s);
   c.mem.release(cnt);
   set_tiles(c, c.h_bw);

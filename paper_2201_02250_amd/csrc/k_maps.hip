@@ -298,10 +298,12 @@ void build_maps(Ctx& c, const std::vector<int32_t>& part_h) {
   c.part = upload(c.mem, part_h.data(), n, s);
   transpose_pattern(c.mem, c.rowptr, c.col, n, c.nnz, &c.tptr, &c.tcol, s);
 
-  int32_t* lo = c.mem.alloc<int32_t>(nsub);
-  int32_t* hi = c.mem.alloc<int32_t>(nsub);
-  int32_t* cnt = c.mem.alloc<int32_t>(nsub);
-  int32_t* bw = c.mem.alloc<int32_t>(1);
+  // lo | hi | cnt | bw in one block (one copy back)
+  int32_t* rng = c.mem.alloc<int32_t>(3 * (size_t)nsub + 1);
+  int32_t* lo = rng;
+  int32_t* hi = rng + nsub;
+  int32_t* cnt = rng + 2 * nsub;
+  int32_t* bw = rng + 3 * nsub;
   {
     std::vector<int32_t> init(nsub, INT_MAX);
     ADS_HIP(hipMemcpyAsync(lo, init.data(), nsub * 4, hipMemcpyHostToDevice, s));
@@ -313,13 +315,13 @@ void build_maps(Ctx& c, const std::vector<int32_t>& part_h) {
                dim3(PR_T), 0, s, c.part, n, nsub, lo, hi, cnt);
     ADS_LAUNCH(k_bandwidth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.rowptr, c.col, n,
                bw);
-    ADS_HIP(hipStreamSynchronize(s));
   }
-  std::vector<int32_t> hlo, hhi, hcnt, hbw;
-  download(hlo, lo, nsub, s);
-  download(hhi, hi, nsub, s);
-  download(hcnt, cnt, nsub, s);
-  download(hbw, bw, 1, s);
+  std::vector<int32_t> hrng;
+  download(hrng, rng, 3 * (size_t)nsub + 1, s);
+  const int32_t* hlo = hrng.data();
+  const int32_t* hhi = hlo + nsub;
+  const int32_t* hcnt = hlo + 2 * nsub;
+  const int32_t* hbw = hlo + 3 * nsub;
   std::vector<int64_t> wlo(nsub), whi(nsub), woff(nsub + 1, 0);
   for (int i = 0; i < nsub; ++i) {
     if (hcnt[i] == 0) fail(ADS_ERR_ARG, "part " + std::to_string(i) + " is empty");
@@ -337,20 +339,21 @@ void build_maps(Ctx& c, const std::vector<int32_t>& part_h) {
   ADS_HIP(hipMemsetAsync(map, 0xFF, total, s));
   ADS_LAUNCH(k_mark_interior, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.part, n, d_wlo,
              d_woff, map);
-  int32_t* err = c.mem.alloc<int32_t>(1);
+  // err | nI | ni in one block (one copy back)
+  int32_t* cblk = c.mem.alloc<int32_t>(1 + 2 * (size_t)nsub);
+  int32_t* err = cblk;
   ADS_HIP(hipMemsetAsync(err, 0, 4, s));
   for (int d = 1; d <= delta; ++d)
     ADS_LAUNCH(k_bfs_layer, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, c.rowptr, c.col,
                c.tptr, c.tcol, d_wlo, d_whi, d_woff, nsub, total, map, d, err);
-  std::vector<int32_t> herr;
-  download(herr, err, 1, s);
-  if (herr[0]) fail(ADS_ERR_ARG, "overlap growth left its window (matrix bandwidth inconsistent)");
-
-  c.nI = c.mem.alloc<int32_t>(nsub);
-  c.ni = c.mem.alloc<int32_t>(nsub);
+  c.nI = cblk + 1;
+  c.ni = cblk + 1 + nsub;
   ADS_LAUNCH(k_count_window, dim3(nsub), dim3(256), 0, s, map, d_woff, c.nI, c.ni);
-  download(c.h_nI, c.nI, nsub, s);
-  download(c.h_ni, c.ni, nsub, s);
+  std::vector<int32_t> hcb;
+  download(hcb, cblk, 1 + 2 * (size_t)nsub, s);
+  if (hcb[0]) fail(ADS_ERR_ARG, "overlap growth left its window (matrix bandwidth inconsistent)");
+  c.h_nI.assign(hcb.begin() + 1, hcb.begin() + 1 + nsub);
+  c.h_ni.assign(hcb.begin() + 1 + nsub, hcb.end());
   c.h_om_off.assign(nsub + 1, 0);
   for (int i = 0; i < nsub; ++i) {
     if (c.h_nI[i] != hcnt[i]) fail(ADS_ERR_ARG, "internal: interior count mismatch");
