@@ -2240,57 +2240,56 @@ __global__ void __launch_bounds__(EIG_T) k_ks_restart(EigArgs a) {
 }
 
 // W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
+// Z = [1 | X V] on the interior rows of every subdomain, column-major nint x
+// cols in the Y buffer (leading dimension npad): one thread per interior row
+// (its local row from the window map), the row of X in registers, the Ritz
+// coefficients V in LDS
+static constexpr int EZ_T = 256;
+__global__ void __launch_bounds__(EZ_T)
+k_eig_z(EigArgs a, const int32_t* __restrict__ int_list, const int64_t* __restrict__ wlo,
+        const int64_t* __restrict__ woff, const int32_t* __restrict__ wpos) {
+  __shared__ double Vsh[VSEL];
+  const int i = blockIdx.x;
+  const int nint = a.nI[i];
+  const int k = blockIdx.y * EZ_T + threadIdx.x;
+  if (blockIdx.y * EZ_T >= nint) return;
+  const int p = a.p, m = a.msel[i], kd = a.kdim[i], cols = m + kd;
+  if (cols == 0) return;
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  const double* Vs = a.Vsel + (int64_t)i * VSEL;
+  for (int e = threadIdx.x; e < m * p; e += EZ_T) Vsh[e] = Vs[e];
+  __syncthreads();
+  if (k >= nint) return;
+  const int g = int_list[a.om_off[i] + k];
+  const int r = wpos[woff[i] + (g - wlo[i])];
+  const double* X = a.X + a.pad_off[i] * p;
+  double xr[KS_W];
+#pragma unroll
+  for (int j = 0; j < KS_W; ++j) xr[j] = j < p ? X[r + j * ld] : 0.0;
+  double* Z = a.Y + a.pad_off[i] * p;
+  if (kd) Z[k] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    const double* vc = Vsh + c * p;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < KS_W; ++j)
+      if (j < p) v += xr[j] * vc[j];
+    Z[k + (c + kd) * ld] = v;
+  }
+}
+
 __global__ void __launch_bounds__(EIG_T) k_eig_finish(EigArgs a, const int64_t* W_off, double* W) {
   __shared__ EigShared S;
   const int i = blockIdx.x;
-  const int s = a.bs[i], K = a.nb[i], n = a.ni[i], npad = K * s, p = a.p;
+  const int p = a.p;
   const int nint = a.nI[i];
-  const int64_t ld = npad;
-  const int64_t base = a.om_off[i];
-  const double* X = a.X + a.pad_off[i] * p;
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
   const int m = a.msel[i];
   const int kd = a.kdim[i];
   const int cols = m + kd;
   if (cols == 0) return;
-  // Z (interior rows, column-major nint x cols) in the Y buffer (npad x p >= nint x cols)
+  // Z (interior rows, column-major nint x cols) in the Y buffer, formed by k_eig_z
   double* Z = a.Y + a.pad_off[i] * p;
-  const double* Vs = a.Vsel + (int64_t)i * VSEL;
-  // interior rows in ascending local order: chunked block scan of the flags
-  __shared__ int wtot[EIG_T / 64];
-  int run = 0;
-  for (int r0 = 0; r0 < n; r0 += blockDim.x) {
-    const int r = r0 + threadIdx.x;
-    const int f = (r < n) ? (int)a.om_int[base + r] : 0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int incl = f;
-    for (int o = 1; o < 64; o <<= 1) {
-      int tv = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += tv;
-    }
-    __syncthreads();
-    if (lane == 63) wtot[w] = incl;
-    __syncthreads();
-    int off = 0, tot = 0;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
-      if (q < w) off += wtot[q];
-      tot += wtot[q];
-    }
-    if (f) {
-      const int k = run + off + incl - 1;
-      for (int c = 0; c < cols; ++c) {
-        double v;
-        if (kd && c == 0)
-          v = 1.0;
-        else {
-          v = 0.0;
-          for (int j = 0; j < p; ++j) v += X[r + j * ld] * Vs[(c - kd) * p + j];
-        }
-        Z[k + c * ld] = v;
-      }
-    }
-    run += tot;
-  }
-  __syncthreads();
   // orthonormalise the nint x cols block (Cholesky QR twice, in place)
   const int okz = cholqr2(Z, Z, ld, nint, nint, cols, S);
   if (!okz && threadIdx.x == 0) atomicOr(a.err, 8);
@@ -2805,6 +2804,12 @@ void eigensolve(Ctx& c) {
   c.coff = upload(c.mem, c.h_coff.data(), nsub + 1, st);
   c.W_off = upload(c.mem, c.h_W_off.data(), nsub + 1, st);
   c.W = c.mem.alloc<double>(std::max<int64_t>(c.h_W_off[nsub], 1));
+  {
+    int maxint = 1;
+    for (int i = 0; i < nsub; ++i) maxint = std::max(maxint, c.h_nI[i]);
+    ADS_LAUNCH(k_eig_z, dim3(nsub, (maxint + EZ_T - 1) / EZ_T), dim3(EZ_T), 0, st, a, c.int_list,
+               c.wlo, c.woff, c.wpos);
+  }
   ADS_LAUNCH(k_eig_finish, dim3(nsub), dim3(EIG_T), 0, st, a, c.W_off, c.W);
   download(herr, a.err, 1, st);
   if (herr[0] & 8) fail(ADS_ERR_EIG_NOCONV, "coarse basis of a subdomain is rank deficient");
