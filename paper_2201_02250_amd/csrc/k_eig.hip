@@ -1095,6 +1095,13 @@ __device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const i
 // btl = B^T l and gam = l^T B l for a floating subdomain, B = D A_ii D: for
 // every interior column c, the rows of A's column (transposed pattern, rows
 // ascending) that are interior rows of Omega_i, in that order
+// largest padded local size nb * bs over the subdomains
+static int64_t npad_max(const Ctx& c) {
+  int64_t m = 1;
+  for (int i = 0; i < c.nsub; ++i) m = std::max(m, (int64_t)c.h_nb[i] * c.h_bs[i]);
+  return m;
+}
+
 __global__ void k_eig_btl(EigArgs a, const int32_t* om_sorted, const int32_t* rowptr,
                           const int32_t* col, const double* val, const int32_t* tptr,
                           const int32_t* tcol, const int64_t* wlo, const int64_t* whi,
@@ -1107,7 +1114,9 @@ __global__ void k_eig_btl(EigArgs a, const int32_t* om_sorted, const int32_t* ro
   const int64_t wl = wlo[i], wh = whi[i], wo = woff[i];
   const double* l = a.ell + a.pad_off[i];
   double* bt = a.btl + a.pad_off[i];
-  for (int c = threadIdx.x; c < npad; c += blockDim.x) {
+  // one column per thread, the columns spread over blockIdx.y
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c < npad) {
     double v = 0.0;
     if (c < n && a.om_int[base + c]) {
       const int gc = om_sorted[base + c];
@@ -1124,6 +1133,7 @@ __global__ void k_eig_btl(EigArgs a, const int32_t* om_sorted, const int32_t* ro
     }
     bt[c] = v;
   }
+  if (blockIdx.y != 0) return;
   double g = 0.0;
   for (int r = threadIdx.x; r < n; r += blockDim.x) g += l[r] * a.bell[a.pad_off[i] + r];
   g = adsd::block_sum(g, red);
@@ -1175,12 +1185,13 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
           if (a.om_int[base + a.lcol[q]]) v += a.lval[q] * l[a.lcol[q]];
       bl[r] = v;
     }
-    // X <- projection onto 1^perp
-    for (int j = 0; j < p; ++j) {
+    // X <- projection onto 1^perp, column j by wave j mod (number of waves)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wv; j < p; j += nw) {
       double sm = 0.0;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) sm += X[r + j * ld];
-      sm = adsd::block_sum(sm, red) / n;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) X[r + j * ld] -= sm;
+      for (int r = lane; r < n; r += 64) sm += X[r + j * ld];
+      sm = adsd::wave_sum(sm) / n;
+      for (int r = lane; r < n; r += 64) X[r + j * ld] -= sm;
     }
   }
 }
@@ -2330,8 +2341,8 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
                        : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
   const unsigned nch = (unsigned)((a.p + PC - 1) / PC);
   if (fast)
-    ADS_LAUNCH(k_eig_btl, dim3(nsub), dim3(256), 0, st, a, c.om_sorted, c.rowptr, c.col, c.val,
-               c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
+    ADS_LAUNCH(k_eig_btl, dim3(nsub, (unsigned)((npad_max(c) + 255) / 256)), dim3(256), 0, st, a,
+               c.om_sorted, c.rowptr, c.col, c.val, c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
   int maxsw = c.opt.eig_max_sweeps > 0 ? c.opt.eig_max_sweeps : 400;
   if (a.x0) maxsw = std::min(maxsw, WARM_SWEEPS);  // then the cold fallback
   std::vector<int32_t> hdone(nsub, 0), hnext(nsub, 0), hint;
@@ -2497,8 +2508,8 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   else
     ADS_LAUNCH((k_eig_init<FT, false>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
   if (fast)
-    ADS_LAUNCH(k_eig_btl, dim3(nsub), dim3(256), 0, st, a, c.om_sorted, c.rowptr, c.col, c.val,
-               c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
+    ADS_LAUNCH(k_eig_btl, dim3(nsub, (unsigned)((npad_max(c) + 255) / 256)), dim3(256), 0, st, a,
+               c.om_sorted, c.rowptr, c.col, c.val, c.tptr, c.tcol, c.wlo, c.whi, c.woff, c.wpos);
   // block classical Gram-Schmidt twice of the operator's output against V,
   // each pass followed by the QR of the block (Barlow-Smoktunowicz BCGS2)
   auto orth_block = [&]() {

@@ -253,7 +253,7 @@ __global__ void k_compact_window(const uint8_t* map, const int64_t* wlo, const i
                                  const int64_t* om_off, const int32_t* nI, int32_t* om_sorted,
                                  int32_t* om_sub, uint8_t* om_int, int32_t* om_export,
                                  int32_t* om_layer, int32_t* ipos, int32_t* wpos) {
-  __shared__ int wt[3][16];
+  __shared__ int wt[1][16];
   const int i = blockIdx.x;
   const int64_t a = woff[i], b = woff[i + 1];
   const int64_t base = om_off[i];
@@ -263,10 +263,12 @@ __global__ void k_compact_window(const uint8_t* map, const int64_t* wlo, const i
     int64_t f = c0 + threadIdx.x;
     uint8_t m = (f < b) ? map[f] : (uint8_t)0xFF;
     int is_all = (m != 0xFF), is_I = (m == 0), is_G = is_all && !is_I;
-    int tA, tI, tG;
-    int pA = block_excl_scan(is_all, wt[0], &tA);
-    int pI = block_excl_scan(is_I, wt[1], &tI);
-    int pG = block_excl_scan(is_G, wt[2], &tG);
+    // interior and overlap flags packed in 16-bit fields (at most 1024 per
+    // chunk): one scan; "all" is their sum
+    int tp;
+    const int pp = block_excl_scan(is_I | (is_G << 16), wt[0], &tp);
+    const int pI = pp & 0xFFFF, pG = pp >> 16, pA = pI + pG;
+    const int tI = tp & 0xFFFF, tG = tp >> 16, tA = tI + tG;
     if (f < b) wpos[f] = is_all ? run_all + pA : -1;
     if (is_all) {
       int64_t v = wlo[i] + (f - a);
@@ -371,7 +373,7 @@ void build_maps(Ctx& c, const std::vector<int32_t>& part_h) {
   c.wlo = d_wlo;
   c.whi = d_whi;
   c.woff = d_woff;
-  ADS_LAUNCH(k_compact_window, dim3(nsub), dim3(256), 0, s, map, d_wlo, d_woff, c.om_off, c.nI,
+  ADS_LAUNCH(k_compact_window, dim3(nsub), dim3(1024), 0, s, map, d_wlo, d_woff, c.om_off, c.nI,
              c.om_sorted, c.om_sub, c.om_int, c.om_export, c.om_layer, c.ipos, c.wpos);
   c.int_list = c.om_export;
   c.mem.release(map);
