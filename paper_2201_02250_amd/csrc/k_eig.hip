@@ -1031,11 +1031,13 @@ __device__ __forceinline__ void tile_tmatvec(const FT* G, int s, const double* y
 //   backward top   l_k = w_k - G_k^T (A_k+1,k^T l_{k+1})      k = M-1 .. 0
 //   backward bottom l_k = v_k - G_k^T (A_k-1,k^T l_{k-1})     k = M+1 .. K-1
 // with A_k-1,k^T and A_k+1,k^T applied by column from the coupling lists.
-// One workgroup; LDS: s (y) + T (partials).
+// In three phases (separate launches, so that the two halves run on two
+// workgroups): 0 the forward half `half` (with its rows of e_last), 1 the
+// middle block, 2 the backward half `half`.  LDS: s (y) + T (partials).
 template <class FT>
 __device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const int32_t* urow,
                                      const double* uval, const int32_t* lrw, const double* lvl,
-                                     double* x, double* lds) {
+                                     double* x, double* lds, int phase, int half) {
   const int t = threadIdx.x, T = blockDim.x;
   constexpr int V = adsd::TileV<FT>::V;
   constexpr int NC = adsd::NCPL;
@@ -1043,8 +1045,6 @@ __device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const i
   const int npad = K * s, M = K / 2;
   double* ybuf = lds;
   double* part = ybuf + s;
-  for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
-  __syncthreads();
   // y_c = (keep ? x_k[c] : 0) - sum of the by-column lists (up: rows of
   // block k-1, dn: rows of block k+1) applied to x
   auto gather = [&](int k, bool keep, bool up, bool dn) {
@@ -1067,29 +1067,53 @@ __device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const i
     }
     __syncthreads();
   };
-  for (int k = 0; k < M; ++k) {
-    gather(k, true, k > 0, false);
-    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, false);
-  }
-  for (int k = K - 1; k > M; --k) {
-    gather(k, true, false, k < K - 1);
-    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, false);
-  }
-  gather(M, true, M > 0, M < K - 1);
-  tile_tmatvec(fac + (int64_t)M * 2 * TS, s, ybuf, part, x + M * s, false);
-  // backward: x_k -= G_k^T (-y) with y = -(A^T l_neighbour)
-  for (int k = M - 1; k >= 0; --k) {
-    gather(k, false, false, true);
-    for (int c = t; c < s; c += T) ybuf[c] = -ybuf[c];
+  if (phase == 0) {
+    const int lo = half ? M * s : 0, hi = half ? npad : M * s;
+    for (int r = lo + t; r < hi; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
     __syncthreads();
-    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, true);
+    if (!half) {
+      for (int k = 0; k < M; ++k) {
+        gather(k, true, k > 0, false);
+        tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, false);
+      }
+    } else {
+      for (int k = K - 1; k > M; --k) {
+        gather(k, true, false, k < K - 1);
+        tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, false);
+      }
+    }
+  } else if (phase == 1) {
+    gather(M, true, M > 0, M < K - 1);
+    tile_tmatvec(fac + (int64_t)M * 2 * TS, s, ybuf, part, x + M * s, false);
+  } else if (!half) {
+    // backward: x_k -= G_k^T (-y) with y = -(A^T l_neighbour)
+    for (int k = M - 1; k >= 0; --k) {
+      gather(k, false, false, true);
+      for (int c = t; c < s; c += T) ybuf[c] = -ybuf[c];
+      __syncthreads();
+      tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, true);
+    }
+  } else {
+    for (int k = M + 1; k < K; ++k) {
+      gather(k, false, true, false);
+      for (int c = t; c < s; c += T) ybuf[c] = -ybuf[c];
+      __syncthreads();
+      tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, true);
+    }
   }
-  for (int k = M + 1; k < K; ++k) {
-    gather(k, false, true, false);
-    for (int c = t; c < s; c += T) ybuf[c] = -ybuf[c];
-    __syncthreads();
-    tile_tmatvec(fac + (int64_t)k * 2 * TS, s, ybuf, part, x + k * s, true);
-  }
+}
+
+// the unnormalised left null vector of the splitting on floating subdomains
+// (fast coupling lists), one phase of transposed_solve_cpl per launch
+template <class FT>
+__global__ void __launch_bounds__(EIG_T) k_eig_ell(const FT* fac, EigArgs a, int phase) {
+  extern __shared__ double dyn[];
+  const int i = blockIdx.x;
+  if (!a.kdim[i]) return;
+  const int64_t po = a.pad_off[i] * adsd::NCPL;
+  transposed_solve_cpl<FT>(fac + a.fac_off[i], a.bs[i], a.nb[i], a.ni[i], a.ucpl_row + po,
+                           a.ucpl_val + po, a.lcpl_row + po, a.lcpl_val + po,
+                           a.ell + a.pad_off[i], dyn, phase, blockIdx.y);
 }
 
 // btl = B^T l and gam = l^T B l for a floating subdomain, B = D A_ii D: for
@@ -1163,12 +1187,7 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   if (a.kdim[i]) {
     double* l = a.ell + a.pad_off[i];
     extern __shared__ double dyn[];
-    if constexpr (CPL)
-      transposed_solve_cpl<FT>(fac + a.fac_off[i], s, K, n, a.ucpl_row + a.pad_off[i] * adsd::NCPL,
-                               a.ucpl_val + a.pad_off[i] * adsd::NCPL,
-                               a.lcpl_row + a.pad_off[i] * adsd::NCPL,
-                               a.lcpl_val + a.pad_off[i] * adsd::NCPL, l, dyn);
-    else
+    if constexpr (!CPL)  // (with the coupling lists, k_eig_ell has formed l)
       transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, l, dyn);
     double nn = 0.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) nn += l[r] * l[r];
@@ -2330,9 +2349,13 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 0);
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
   };
-  if (cpl)
+  if (cpl) {
+    const size_t ell_lds = (size_t)(smax + EIG_T) * sizeof(double);
+    ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 2), dim3(EIG_T), ell_lds, st, fac, a, 0);
+    ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 1), dim3(EIG_T), ell_lds, st, fac, a, 1);
+    ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 2), dim3(EIG_T), ell_lds, st, fac, a, 2);
     ADS_LAUNCH((k_eig_init<FT, true>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
-  else
+  } else
     ADS_LAUNCH((k_eig_init<FT, false>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
   orth();
   constexpr int PC = EIG_PC;
@@ -2503,9 +2526,13 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   const size_t op_lds =
       fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
            : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
-  if (cpl)
+  if (cpl) {
+    const size_t ell_lds = (size_t)(smax + EIG_T) * sizeof(double);
+    ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 2), dim3(EIG_T), ell_lds, st, fac, a, 0);
+    ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 1), dim3(EIG_T), ell_lds, st, fac, a, 1);
+    ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 2), dim3(EIG_T), ell_lds, st, fac, a, 2);
     ADS_LAUNCH((k_eig_init<FT, true>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
-  else
+  } else
     ADS_LAUNCH((k_eig_init<FT, false>), dim3(nsub), dim3(EIG_T), init_lds, st, fac, a, scratch);
   if (fast)
     ADS_LAUNCH(k_eig_btl, dim3(nsub, (unsigned)((npad_max(c) + 255) / 256)), dim3(256), 0, st, a,
