@@ -416,3 +416,57 @@ def test_autotuned_tiles_keep_parity_and_are_cached(tmp_path):
     bad = tmp_path / "bad.txt"
     bad.write_text("not a cache\n")
     assert ads.lib().ads_tune_cache_load(str(bad).encode()) == ads.ADS_ERR_ARG
+
+
+def test_full_size_benchmark_workload_matches_oracle():
+    """The benchmark workload at full size (2D convection-diffusion 512^2,
+    8 x 8 blocks, overlap 2, nev 8) against the oracle, which finishes it in
+    seconds: index maps, layers and lumped sums bit-exact for every
+    subdomain; nev_i and n0 exact; coarse spans of a sample of subdomains
+    (corners, edges, interior) within 1e-7 rad and the apply within 1e-9
+    (FP64, eigensolver to 1e-12); FP64 FGMRES(50) iterations within +-1 and
+    solution within 1e-7; the production form as the benchmark times it (FP32
+    factors, tuned tiles) reaching 1e-8 with a solution within 1e-6 of the
+    oracle's."""
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64")
+    As = A.to_scipy()
+    ov, nev, m = o["overlap"], o["nev"], o["restart"]
+    P = OS.TwoLevelSchwarz(As, part, N, ov, nev)
+    Ad = ads.DeviceCSR(A, DEV)
+    ctx = ads.Context(Ad, part, N, ov, nev, eig_tol=1e-12)
+    om, off, nI, lay = ads.ads_export_maps(ctx.ctx)
+    s_gpu = ads.ads_export_splitting(ctx.ctx)
+    for i, sub in enumerate(OS.subdomains(As, part, N, ov)):
+        np.testing.assert_array_equal(om[off[i]:off[i + 1]], sub.omega)
+        assert nI[i] == sub.n_interior
+        np.testing.assert_array_equal(lay[off[i]:off[i + 1]],
+                                      np.r_[np.zeros(sub.n_interior, int), sub.layer])
+        _, sv, _ = OS.block_splitting(As, sub)
+        np.testing.assert_array_equal(s_gpu[off[i] + sub.n_interior:off[i + 1]], sv)
+    Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+    np.testing.assert_array_equal(info["nev_i"], P.nev_i)
+    assert info["n0"] == P.n0
+    for i in (0, 7, 9, 27, 36, 56, 63):
+        mi = int(info["nev_i"][i])
+        Wi = Wg[woff[i]:woff[i + 1]].reshape(int(info["n_interior"][i]), mi)
+        assert sla.subspace_angles(Wi, P.W[i]).max() < 1e-7, i
+    R = np.random.default_rng(3).standard_normal((A.n, 1))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    assert np.abs(Z - Zo).max() / np.abs(Zo).max() <= 1e-9
+    b = W.rhs(A.n, 0)
+    bd = torch.tensor(b, device=DEV)
+    xo, io = OS.gmres(As, b, P.apply, restart=m, rtol=1e-8, flexible=True)
+    x, inf = ctx.solve(bd, restart=m, flexible=True, rtol=1e-8)
+    x = x.cpu().numpy()
+    assert inf["status"] == 0 and abs(inf["its"][0] - io["its"]) <= 1, (inf["its"], io["its"])
+    assert np.linalg.norm(b - As @ x) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-7
+    ctx.close()
+    prod = ads.Context(Ad, part, N, ov, nev, precision=ads.ADS_PREC_FP32, autotune=1)
+    x32, inf32 = prod.solve(bd, restart=m, flexible=True, rtol=1e-8)
+    x32 = x32.cpu().numpy()
+    assert inf32["status"] == 0 and inf32["its"][0] <= io["its"] + 2, (inf32["its"], io["its"])
+    assert np.linalg.norm(b - As @ x32) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(x32 - xo) / np.linalg.norm(xo) <= 1e-6
+    prod.close()
