@@ -2337,7 +2337,9 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
   int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
   double* scratch = nullptr;
   if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
-  const bool cpl = c.cpl_ok && c.ucpl_row != nullptr;
+  // the coupling-list transposed solve reads the two-ended tiles of the fast
+  // path; the general path's one-ended tiles take the CSR form
+  const bool cpl = c.solve_fast && c.cpl_ok && c.ucpl_row != nullptr;
   const size_t init_lds =
       cpl ? (size_t)(2 * smax + EIG_T + (smax * adsd::NCPL + 1) / 2 + smax * adsd::NCPL + 8) * 8
           : (size_t)2 * smax * sizeof(double);
@@ -2512,7 +2514,9 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   int smax = *std::max_element(c.h_bs.begin(), c.h_bs.end());
   double* scratch = nullptr;
   if (2 * smax > 4096) fail(ADS_ERR_UNSUPPORTED, "block size too large for the eigensolver");
-  const bool cpl = c.cpl_ok && c.ucpl_row != nullptr;
+  // the coupling-list transposed solve reads the two-ended tiles of the fast
+  // path; the general path's one-ended tiles take the CSR form
+  const bool cpl = c.solve_fast && c.cpl_ok && c.ucpl_row != nullptr;
   const size_t init_lds =
       cpl ? (size_t)(2 * smax + EIG_T + (smax * adsd::NCPL + 1) / 2 + smax * adsd::NCPL + 8) * 8
           : (size_t)2 * smax * sizeof(double);

@@ -35,6 +35,8 @@ def small_cases():
     out = []
     A, part, N, o = W.config("c1_laplace2d_64_strips8", scale=32)
     out.append(("lap32-strips", A, part, N, 1, 4, 30, False))
+    A, part, N, o = W.config("c1_laplace2d_64_strips8")  # the full-size plain-method workload
+    out.append(("c1-lap64-strips8", A, part, N, o["overlap"], o["nev"], o["restart"], o["flexible"]))
     A = W.convdiff2d(40, 0.01)
     out.append(("cd40-blocks3-d2", A, W.block_partition_2d(40, 3), 9, 2, 6, 50, True))
     A = W.convdiff2d(37, 0.02)
@@ -45,6 +47,10 @@ def small_cases():
     out.append(("cd3d14-2x2x2-d2", A, W.block_partition_3d(14, 2, 2, 2), 8, 2, 6, 30, True))
     A = W.laplace2d(20)
     out.append(("lap20-d0-nev0", A, W.block_partition_2d(20, 2), 4, 0, 0, 30, False))
+    # block size 109 (beyond the register-resident fast path: one-ended
+    # factors and general solves) with a floating centre subdomain
+    A = W.convdiff3d(21, nu=0.02)
+    out.append(("cd3d21-3x3x3-d2-general", A, W.block_partition_3d(21, 3, 3, 3), 27, 2, 6, 30, True))
     return out
 
 
@@ -470,3 +476,49 @@ def test_full_size_benchmark_workload_matches_oracle():
     assert np.linalg.norm(b - As @ x32) / np.linalg.norm(b) <= 1e-8
     assert np.linalg.norm(x32 - xo) / np.linalg.norm(xo) <= 1e-6
     prod.close()
+
+
+def test_full_size_bfs3d_workload_matches_oracle():
+    """The batched-family 3D workload at full size (convection-diffusion 64^3,
+    256 BFS-grown subdomains of uneven size, overlap 2, nev 10): the GPU BFS
+    partition bit-exact; index maps and layers bit-exact for every subdomain;
+    nev_i and n0 (2587: LDS Gauss-Jordan panels) exact; the apply within 1e-9
+    (FP64, eigensolver to 1e-12); FGMRES(30) to 1e-8 with FP64 factors
+    (iterations within +-1, solution within 1e-7) and with FP32 factors
+    (solution within 1e-6)."""
+    A, _, _, o = W.config("c3a_convdiff3d_64_bfs256")
+    As = A.to_scipy()
+    seeds = o["seeds"]
+    part = ads.ads_partition_bfs(A, seeds)
+    np.testing.assert_array_equal(part, OS.bfs_partition(As, seeds))
+    N = len(seeds)
+    P = OS.TwoLevelSchwarz(As, part, N, o["overlap"], o["nev"])
+    Ad = ads.DeviceCSR(A, DEV)
+    ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], eig_tol=1e-12)
+    om, off, nI, lay = ads.ads_export_maps(ctx.ctx)
+    for i, sub in enumerate(OS.subdomains(As, part, N, o["overlap"])):
+        np.testing.assert_array_equal(om[off[i]:off[i + 1]], sub.omega)
+        assert nI[i] == sub.n_interior
+        np.testing.assert_array_equal(lay[off[i] + sub.n_interior:off[i + 1]], sub.layer)
+    Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+    np.testing.assert_array_equal(info["nev_i"], P.nev_i)
+    assert info["n0"] == P.n0
+    R = np.random.default_rng(5).standard_normal((A.n, 1))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    assert np.abs(Z - Zo).max() / np.abs(Zo).max() <= 1e-9
+    b = W.rhs(A.n, 0)
+    bd = torch.tensor(b, device=DEV)
+    xo, io = OS.gmres(As, b, P.apply, restart=o["restart"], rtol=1e-8, flexible=True)
+    x, inf = ctx.solve(bd, restart=o["restart"], flexible=True, rtol=1e-8)
+    x = x.cpu().numpy()
+    assert inf["status"] == 0 and abs(inf["its"][0] - io["its"]) <= 1, (inf["its"], io["its"])
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-7
+    ctx.close()
+    c32 = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=ads.ADS_PREC_FP32)
+    x32, inf32 = c32.solve(bd, restart=o["restart"], flexible=True, rtol=1e-8)
+    x32 = x32.cpu().numpy()
+    assert inf32["status"] == 0
+    assert np.linalg.norm(b - As @ x32) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(x32 - xo) / np.linalg.norm(xo) <= 1e-6
+    c32.close()
