@@ -224,6 +224,7 @@ struct Ctx {
   double* dummy = nullptr;  // per-thread discard slots of the tile solves
   int work_cols = 0;
   double* cvec = nullptr;   // partial sums of the coarse restriction, n0 * cols * chunks
+  double* yvec = nullptr;   // c and y = E^{-1} c of large coarse systems, 2 n0 cols
   double* qvec = nullptr;   // coarse correction, n * cols
   int cvec_cols = 0;
 

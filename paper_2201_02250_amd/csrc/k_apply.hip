@@ -26,6 +26,11 @@ static constexpr int MAXNEV = 32;
 // rows of Omega_Ii per block of the coarse restriction and prolongation
 static constexpr int CO_CH = 2 * APPLY_T;
 
+// E^{-1} larger than 16 MB: y = E^{-1} c in a pass of its own (k_coarse_emul)
+bool coarse_big(const Ctx& c) {
+  return c.n0 > 0 && !c.h_E_off.empty() && c.h_E_off.back() * 8 > ((int64_t)16 << 20);
+}
+
 int coarse_chunks(const Ctx& c) {
   int mx = 1;
   for (int i = 0; i < c.nsub; ++i) mx = std::max(mx, (c.h_nI[i] + CO_CH - 1) / CO_CH);
@@ -110,11 +115,69 @@ k_coarse_restrict(const double* __restrict__ r, int64_t n, const int32_t* __rest
   co_block_sums(acc, m, red, part + ((int64_t)j * n0 + coff[i]) * nch + ch, nch);
 }
 
+// Large coarse systems (E^{-1} beyond the caches): y = E^{-1} c is formed once
+// per apply instead of once per (subdomain chunk, right-hand side), so that
+// E^{-1} streams from HBM once.  First c = the sum of the restriction's
+// partials (fixed order), cy[j n0 + b] ...
+__global__ void k_coarse_csum(const double* __restrict__ part, int n0, int nch, int nrhs,
+                              double* __restrict__ cy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n0 * nrhs) return;
+  double v = 0.0;
+  for (int h = 0; h < nch; ++h) v += part[e * nch + h];
+  cy[e] = v;
+}
+
+// ... then y[j n0 + c0 + r] = sum_b E_s^{-1}(r, b) c[j n0 + c0 + b] for 32 rows
+// (blockIdx.x) of system s (blockIdx.y) and 16 right-hand sides (blockIdx.z)
+// per workgroup, over LDS tiles of 64 columns (fixed summation order)
+static constexpr int EM_R = 32, EM_B = 64, EM_J = 16;
+__global__ void __launch_bounds__(256)
+k_coarse_emul(const double* __restrict__ cy, int n0, int nrhs, const double* __restrict__ Einv,
+              const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
+              double* __restrict__ y) {
+  __shared__ double Es[EM_R][EM_B + 1];
+  __shared__ double Cs[EM_J][EM_B + 1];
+  const int sy = blockIdx.y;
+  const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
+  const int r0 = blockIdx.x * EM_R, j0 = blockIdx.z * EM_J;
+  if (r0 >= ns) return;
+  const double* E = Einv + E_off[sy];
+  const int t = threadIdx.x, r = t >> 3, jj = t & 7;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int b0 = 0; b0 < ns; b0 += EM_B) {
+    for (int e = t; e < EM_R * EM_B; e += 256) {
+      const int rr = e / EM_B, bb = e % EM_B;
+      const int gr = r0 + rr, gb = b0 + bb;
+      Es[rr][bb] = (gr < ns && gb < ns) ? E[(int64_t)gr * ns + gb] : 0.0;
+    }
+    for (int e = t; e < EM_J * EM_B; e += 256) {
+      const int j = e / EM_B, bb = e % EM_B;
+      const int gj = j0 + j, gb = b0 + bb;
+      Cs[j][bb] = (gj < nrhs && gb < ns) ? cy[(int64_t)gj * n0 + c0 + gb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int bb = 0; bb < EM_B; ++bb) {
+      const double ev = Es[r][bb];
+      acc0 += ev * Cs[jj][bb];
+      acc1 += ev * Cs[jj + 8][bb];
+    }
+    __syncthreads();
+  }
+  const int gr = r0 + r;
+  if (gr < ns) {
+    if (j0 + jj < nrhs) y[(int64_t)(j0 + jj) * n0 + c0 + gr] = acc0;
+    if (j0 + jj + 8 < nrhs) y[(int64_t)(j0 + jj + 8) * n0 + c0 + gr] = acc1;
+  }
+}
+
 // y_i = rows coff_i .. coff_i + m of E^{-1} times c (c summed from the
-// restriction's partials in a fixed order), then q = W_i y_i on the rows of
-// chunk ch
+// restriction's partials in a fixed order; or, when yfull is given, the rows
+// of y that k_coarse_emul formed), then q = W_i y_i on the rows of chunk ch
 __global__ void __launch_bounds__(APPLY_T)
-k_coarse_prolong(const double* __restrict__ part, int n0, int nch, const double* __restrict__ Einv,
+k_coarse_prolong(const double* __restrict__ part, const double* __restrict__ yfull, int n0,
+                 int nch, const double* __restrict__ Einv,
                  const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
                  const int32_t* __restrict__ sub_sys, const int32_t* __restrict__ int_list,
                  const int64_t* __restrict__ om_off, const int32_t* __restrict__ nI,
@@ -133,21 +196,25 @@ k_coarse_prolong(const double* __restrict__ part, int n0, int nch, const double*
     for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) qj[rows[k]] = 0.0;
     return;
   }
-  const int sy = sub_sys[i];
-  const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
-  const double* pj = part + ((int64_t)j * n0 + c0) * nch;
-  const double* E = Einv + E_off[sy] + (int64_t)(coff[i] - c0) * ns;
-  double acc[MAXNEV];
+  if (yfull) {
+    if (threadIdx.x < m) y[threadIdx.x] = yfull[(int64_t)j * n0 + coff[i] + threadIdx.x];
+  } else {
+    const int sy = sub_sys[i];
+    const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
+    const double* pj = part + ((int64_t)j * n0 + c0) * nch;
+    const double* E = Einv + E_off[sy] + (int64_t)(coff[i] - c0) * ns;
+    double acc[MAXNEV];
 #pragma unroll
-  for (int a = 0; a < MAXNEV; ++a) acc[a] = 0.0;
-  for (int b = threadIdx.x; b < ns; b += APPLY_T) {
-    double cb = 0.0;
-    for (int h = 0; h < nch; ++h) cb += pj[(int64_t)b * nch + h];
+    for (int a = 0; a < MAXNEV; ++a) acc[a] = 0.0;
+    for (int b = threadIdx.x; b < ns; b += APPLY_T) {
+      double cb = 0.0;
+      for (int h = 0; h < nch; ++h) cb += pj[(int64_t)b * nch + h];
 #pragma unroll
-    for (int a = 0; a < MAXNEV; ++a)
-      if (a < m) acc[a] += E[(int64_t)a * ns + b] * cb;
+      for (int a = 0; a < MAXNEV; ++a)
+        if (a < m) acc[a] += E[(int64_t)a * ns + b] * cb;
+    }
+    co_block_sums(acc, m, red, y, 1);
   }
-  co_block_sums(acc, m, red, y, 1);
   __syncthreads();
   const double* Wi = W + W_off[i];
   for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) {
@@ -312,10 +379,12 @@ k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict_
 }
 
 void ensure_work(Ctx& c, int cols) {
-  if (c.work_cols >= cols) return;
+  if (c.work_cols >= cols && (c.yvec || !coarse_big(c))) return;
   if (c.priv) ADS_HIP(hipStreamSynchronize(c.priv));  // the old workspace may be in use there
   if (c.work) c.mem.release(c.work);
   if (c.cvec) c.mem.release(c.cvec);
+  if (c.yvec) c.mem.release(c.yvec);
+  c.yvec = nullptr;
   if (c.qvec) c.mem.release(c.qvec);
   if (c.work2) c.mem.release(c.work2);
   if (c.dummy) c.mem.release(c.dummy);
@@ -326,6 +395,8 @@ void ensure_work(Ctx& c, int cols) {
   c.dummy = c.mem.alloc<double>((size_t)c.nsub * cols * 2 * adsd::SOLVE_T);
   // partial sums of the coarse restriction: one per (coarse entry, row chunk)
   c.cvec = c.mem.alloc<double>((size_t)std::max(c.n0, 1) * cols * coarse_chunks(c));
+  // c and y of the large-system form: 2 n0 cols
+  if (coarse_big(c)) c.yvec = c.mem.alloc<double>((size_t)2 * c.n0 * cols);
   c.qvec = c.mem.alloc<double>((size_t)c.n * cols);
   c.work_cols = cols;
 }
@@ -427,7 +498,7 @@ double time_local_solve(Ctx& c, int reps) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (double* p : {r, q, z}) c.mem.release(p);
-  for (double** p : {&c.work, &c.work2, &c.dummy, &c.cvec, &c.qvec})
+  for (double** p : {&c.work, &c.work2, &c.dummy, &c.cvec, &c.yvec, &c.qvec})
     if (*p) {
       c.mem.release(*p);
       *p = nullptr;
@@ -492,10 +563,24 @@ static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStrea
       ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, r, c.n,
                  c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, c.cvec, c.n0, nch);
     }
+    double* yfull = nullptr;
     {
       ProfScope p2(c, 2, s);
-      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, c.cvec, c.n0, nch,
-                 c.Einv, c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W,
+      if (c.yvec) {
+        double* cy = c.yvec;
+        yfull = c.yvec + (size_t)c.n0 * nrhs;
+        const int64_t ne = (int64_t)c.n0 * nrhs;
+        ADS_LAUNCH(k_coarse_csum, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, c.cvec,
+                   c.n0, nch, nrhs, cy);
+        int maxs = 0;
+        for (int v : c.h_n0s) maxs = std::max(maxs, v);
+        ADS_LAUNCH(k_coarse_emul,
+                   dim3((unsigned)((maxs + EM_R - 1) / EM_R), (unsigned)c.nsys,
+                        (unsigned)((nrhs + EM_J - 1) / EM_J)),
+                   dim3(256), 0, s, cy, c.n0, nrhs, c.Einv, c.E_off, c.sys_coff, yfull);
+      }
+      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, c.cvec, yfull,
+                 c.n0, nch, c.Einv, c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W,
                  c.W_off, c.nev, c.coff, c.qvec, c.n);
     }
     q = c.qvec;

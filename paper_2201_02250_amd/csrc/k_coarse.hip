@@ -155,22 +155,29 @@ __device__ __forceinline__ void gj_better(double& bv, int& bi, double v, int i) 
   }
 }
 
+// HBM = false: the panel, the saved pivot column and the row sources live in
+// LDS (n (8 nb + 12) bytes); HBM = true (systems too large for LDS): the panel
+// is worked on in place in its output S, the row sources in src_all and the
+// pivot column in fcol_all (n0 doubles), all through the cache hierarchy.
+template <bool HBM>
 __global__ void __launch_bounds__(GJ_T)
 k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int nb,
-           double* Sbuf, int32_t* src_all, int32_t* tot_all, int32_t* singular) {
+           double* Sbuf, int32_t* src_all, int32_t* tot_all, double* fcol_all, int32_t* singular) {
   extern __shared__ double gj_lds[];
   __shared__ double rowk[32], rowkold[32];
   __shared__ double pval[GJ_T / 64];
   __shared__ int pidx[GJ_T / 64];
   __shared__ int swp[32];
   const int sy = blockIdx.x;
-  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int base = sys_coff[sy];
+  const int n = sys_coff[sy + 1] - base;
   if (k0 >= n) return;
   const int kb = min(nb, n - k0);
   const int t = threadIdx.x, T = blockDim.x, lane = t & 63, wv = t >> 6;
-  double* P = gj_lds;                 // n x nb panel, row-major
-  double* fcol = P + (size_t)n * nb;  // saved pivot column
-  int* src = reinterpret_cast<int*>(fcol + n);
+  // n x nb panel, row-major; saved pivot column; row sources
+  double* P = HBM ? Sbuf + (int64_t)nb * base : gj_lds;
+  double* fcol = HBM ? fcol_all + base : P + (size_t)n * nb;
+  int* src = HBM ? src_all + base : reinterpret_cast<int*>(fcol + n);
   const double* A = Ain + E_off[sy];
   const int lnb = __ffs(nb) - 1;  // nb is a power of two
   const int ne = n * nb;
@@ -241,12 +248,15 @@ k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int
       src[p] = tmp;
     }
   __syncthreads();
-  double* S = Sbuf + (int64_t)nb * sys_coff[sy];
-  for (int e = t; e < ne; e += T) S[e] = P[e];
-  int32_t* so = src_all + sys_coff[sy];
-  for (int i = t; i < n; i += T) so[i] = src[i];
-  // cumulative row map: tot(x) <- tot(src(x)), through LDS (fcol is free)
-  int32_t* tot = tot_all + sys_coff[sy];
+  if (!HBM) {
+    double* S = Sbuf + (int64_t)nb * base;
+    for (int e = t; e < ne; e += T) S[e] = P[e];
+    int32_t* so = src_all + base;
+    for (int i = t; i < n; i += T) so[i] = src[i];
+  }
+  // cumulative row map: tot(x) <- tot(src(x)), through the pivot column's
+  // storage (free by now)
+  int32_t* tot = tot_all + base;
   int* tmp = reinterpret_cast<int*>(fcol);
   for (int i = t; i < n; i += T) tmp[i] = k0 == 0 ? src[i] : tot[src[i]];
   __syncthreads();
@@ -488,25 +498,29 @@ void assemble_coarse(Ctx& c) {
   std::vector<int32_t> hf;  // both flags are read once, after the inverse
   // register-resident panels (width 32, one row per thread) up to order GJ_T,
   // else LDS panels
+  // else LDS panels, else (orders above about 7400) panels in HBM
   const bool reg = maxs <= GJ_T;
-  const int nb = reg ? 32 : gj_panel_width(maxs);
-  if (nb == 0)
-    fail(ADS_ERR_UNSUPPORTED, "coarse system of order " + std::to_string(maxs) +
-                                  " exceeds the dense inverse limit");
+  const int nbl = reg ? 32 : gj_panel_width(maxs);
+  const bool hbm = nbl == 0;
+  const int nb = hbm ? 32 : nbl;
   const int n0t = std::max(c.n0, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
   double* S = c.mem.alloc<double>((int64_t)n0t * nb);
+  double* fcol = hbm ? c.mem.alloc<double>(n0t) : nullptr;
   double* F = c.mem.alloc<double>(etot);
   double* bufs[2] = {E, F};
-  const size_t plds = (size_t)maxs * (nb * 8 + 8 + 4);
+  const size_t plds = hbm ? 0 : (size_t)maxs * (nb * 8 + 8 + 4);
   const unsigned tiles = (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
   const unsigned rows = (unsigned)((maxs + 63) / 64 * 64);  // one thread per row
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
-    if (!reg)
-      ADS_LAUNCH(k_gj_panel, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], c.E_off, c.sys_coff,
-                 (int)k0, nb, S, src, tot, flag + 1);
+    if (hbm)
+      ADS_LAUNCH(k_gj_panel<true>, dim3(nsys), dim3(GJ_T), 0, st, bufs[cur], c.E_off, c.sys_coff,
+                 (int)k0, nb, S, src, tot, fcol, flag + 1);
+    else if (!reg)
+      ADS_LAUNCH(k_gj_panel<false>, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], c.E_off,
+                 c.sys_coff, (int)k0, nb, S, src, tot, fcol, flag + 1);
     else
       ADS_LAUNCH(k_gj_panel_row, dim3(nsys), dim3(rows), 0, st, bufs[cur], c.E_off, c.sys_coff,
                  (int)k0, S, src, tot, flag + 1);
@@ -523,6 +537,7 @@ void assemble_coarse(Ctx& c) {
   c.Einv = bufs[1 - cur];
   c.mem.release(bufs[cur]);
   c.mem.release(S);
+  if (fcol) c.mem.release(fcol);
   c.mem.release(src);
   c.mem.release(tot);
 }
