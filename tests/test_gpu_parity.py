@@ -16,6 +16,7 @@ results are compared to the tolerances derived in the design notes:
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import schwarz as OS
@@ -589,3 +590,91 @@ def test_full_size_batched_2d_family_matches_oracle():
         assert info["statuses"][k] == 0 and info["its"][k] <= io["its"] + 2, (k, info["its"][k], io["its"])
         assert np.linalg.norm(b[sl] - As_ @ x[sl]) / np.linalg.norm(b[sl]) <= 1e-8, k
         assert np.linalg.norm(x[sl] - xo) / np.linalg.norm(xo) <= 1e-6, k
+
+
+def _oracle_subdomain(As, G, part, i, overlap):
+    """The oracle's Omega_i for one subdomain of a large partition (the
+    partition relabelled as {i, rest}, so that only two BFS runs are made)."""
+    return OS.subdomains(As, np.where(part == i, 0, 1), 2, overlap, G=G)[0]
+
+
+def test_full_size_jump3d_workload_sampled():
+    """The full-scale 3D family at full size (-div(k grad u) on 128^3 with log10
+    k uniform in [-3, 3] on 8^3 blocks, 1024 boxes of 2048 unknowns, overlap 2,
+    nev 12, 16 right-hand sides; n0 12290 > the LDS panel limit).  The oracle
+    cannot build all 1024 coarse spaces in seconds, so five subdomains (two
+    corners, an edge, a face and an interior one) are compared one by one:
+    index maps and layers bit-exact, nev_i exact, coarse spans within 1e-7
+    rad (FP64, eigensolver to 1e-12), and the one-level RAS apply on their
+    interior rows within 1e-10 of the oracle's sparse LU solves.  Properties
+    that hold at any size check the whole coarse space: the deflation
+    identity M^{-1} A z = z for 16 coarse basis vectors z (eq. 4: the coarse
+    correction reproduces z and the local solves see a zero residual), and
+    every right-hand side of the FP64 and FP32-factor FGMRES(30) solves
+    reaches a true relative residual of 1e-8."""
+    A, part, N, o = W.config("c5_jump3d_128_boxes1024")
+    ov, nev = o["overlap"], o["nev"]
+    assert N == 1024 and A.n == 128 ** 3
+    As = A.to_scipy()
+    G = OS.adjacency(As)
+    sample = [0, 1023, 7 + 8 * (0 + 8 * 5), 4 + 8 * (4 + 8 * 0), 3 + 8 * (4 + 8 * 8)]
+    Ad = ads.DeviceCSR(A, DEV)
+    ctx = ads.Context(Ad, part, N, ov, nev, eig_tol=1e-12)
+    assert ctx.info["n0"] > 7475
+    om, off, nI, lay = ads.ads_export_maps(ctx.ctx)
+    Wg, woff, _, info = ads.ads_export_coarse(ctx.ctx)
+    nev_i = np.asarray(info["nev_i"])
+    assert nev_i.min() >= nev and info["n0"] == nev_i.sum()
+    subs = {}
+    for i in sample:
+        sub = _oracle_subdomain(As, G, part, i, ov)
+        subs[i] = sub
+        np.testing.assert_array_equal(om[off[i]:off[i + 1]], sub.omega)
+        assert nI[i] == sub.n_interior
+        np.testing.assert_array_equal(lay[off[i] + sub.n_interior:off[i + 1]], sub.layer)
+        A_ii, _, At = OS.block_splitting(As, sub)
+        res = OS.local_eigenproblem(A_ii, At, sub.n_interior, nev, kdim=OS.kernel_dimension(At))
+        Wo, _ = np.linalg.qr(res["Z"][: sub.n_interior])
+        assert nev_i[i] == Wo.shape[1], (i, nev_i[i], Wo.shape[1])
+        Wi = Wg[woff[i]:woff[i + 1]].reshape(int(nI[i]), int(nev_i[i]))
+        ang = sla.subspace_angles(Wi, Wo).max()
+        print(f"subdomain {i}: nev_i {nev_i[i]} span angle {ang:.2e}", flush=True)
+        assert ang < 1e-7, (i, ang)
+    # deflation identity on one coarse basis vector of each of 16 subdomains
+    coff = np.concatenate([[0], np.cumsum(nev_i)])
+    pick = np.linspace(0, N - 1, 16).astype(int)
+    Zc = np.zeros((A.n, 16))
+    for c, i in enumerate(pick):
+        a = c % int(nev_i[i])
+        rows = om[off[i]:off[i] + nI[i]]
+        Zc[rows, c] = Wg[woff[i]:woff[i + 1]].reshape(int(nI[i]), int(nev_i[i]))[:, a]
+    MZ = ctx.apply(torch.tensor(As @ Zc, device=DEV)).cpu().numpy()
+    dz = np.abs(MZ - Zc).max()
+    print(f"deflation identity: max |M^-1 A z - z| = {dz:.2e}", flush=True)
+    assert dz <= 1e-8, dz
+    B = np.stack([W.rhs(A.n, s) for s in range(16)], axis=1)
+    Bd = torch.tensor(B, device=DEV)
+    X, inf = ctx.solve(Bd, restart=o["restart"], flexible=True, rtol=1e-8)
+    X = X.cpu().numpy()
+    rel = np.linalg.norm(B - As @ X, axis=0) / np.linalg.norm(B, axis=0)
+    print(f"fp64 its {inf['its'][:16]} max relres {rel.max():.2e}", flush=True)
+    assert inf["status"] == 0 and rel.max() <= 1e-8
+    ctx.close()
+    c32 = ads.Context(Ad, part, N, ov, nev, precision=ads.ADS_PREC_FP32)
+    X32, inf32 = c32.solve(Bd, restart=o["restart"], flexible=True, rtol=1e-8)
+    X32 = X32.cpu().numpy()
+    rel32 = np.linalg.norm(B - As @ X32, axis=0) / np.linalg.norm(B, axis=0)
+    print(f"fp32 its {inf32['its'][:16]} max relres {rel32.max():.2e}", flush=True)
+    assert inf32["status"] == 0 and rel32.max() <= 1e-8
+    assert max(inf32["its"][:16]) <= max(inf["its"][:16]) + 2
+    c32.close()
+    ras = ads.Context(Ad, part, N, ov, 0, variant=ads.ADS_VARIANT_RAS)
+    r = np.random.default_rng(23).standard_normal(A.n)
+    z = ras.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    ras.close()
+    for i, sub in subs.items():
+        A_ii, _, _ = OS.block_splitting(As, sub)
+        xi = spla.splu(A_ii.tocsc()).solve(r[sub.omega])[: sub.n_interior]
+        err = np.abs(z[sub.interior] - xi).max() / np.abs(xi).max()
+        print(f"RAS subdomain {i}: {err:.2e}", flush=True)
+        assert err <= 1e-10, (i, err)
