@@ -26,6 +26,7 @@
 #include <type_traits>
 
 #include "ads_internal.h"
+#include "k_gj.h"
 #include "k_solve.h"
 
 namespace ads {
@@ -515,6 +516,163 @@ static void factor_one(Ctx& c, int splitting, void** out) {
                                " of subdomain " + std::to_string(hb[0] - 1));
 }
 
+// ---------------------------------------------------------------------------
+// Batched general factorization (block sizes beyond the register-resident
+// fast path, coupling lists complete): block step k of every subdomain at
+// once, in three passes over the whole GPU instead of one workgroup per
+// subdomain:
+//   build : D_k = A_kk - A_k,k-1 P_{k-1} in FP64, row-major (the Schur update
+//           through the coupling list of A_k,k-1 by row, P_{k-1} kept in FP64);
+//   invert: G_k = D_k^{-1} by the batched Gauss-Jordan elimination with
+//           partial pivoting (one row per thread up to s = 1024);
+//   store : the packed tiles G_k and P_k = G_k A_k,k+1 (the coupling list of
+//           A_k,k+1 by column, rows ascending), and P_k in FP64 for step k + 1.
+// Subdomains with fewer than k + 1 blocks invert an identity at step k.
+// ---------------------------------------------------------------------------
+struct BfArgs {
+  const int64_t* lrow;
+  const int32_t* lcol;
+  const double* lval;
+  const double* lsum;
+  const uint8_t* om_int;
+  const int64_t* om_off;
+  const int32_t* ni;
+  const int32_t* bs;
+  const int32_t* nb;
+  const int64_t* fac_off;
+  const int32_t* kdim;
+  const int64_t* pad_off;
+  const int32_t* cpl_col;   // A_k,k-1 by row
+  const double* cpl_val;
+  const int32_t* ucpl_row;  // A_k-1,k by column
+  const double* ucpl_val;
+  const int64_t* d_off;     // per subdomain: start of its s_i x s_i FP64 work matrices
+};
+
+static constexpr int BF_RB = 8;  // rows of D_k per workgroup of the build pass
+
+__global__ void __launch_bounds__(256)
+k_bf_build(BfArgs a, int k, int splitting, double* D, const double* Pp) {
+  const int i = blockIdx.x;
+  const int s = a.bs[i], K = a.nb[i], n = a.ni[i];
+  const int rr0 = blockIdx.y * BF_RB;
+  if (rr0 >= s) return;
+  double* Di = D + a.d_off[i];
+  const double* Pi = Pp + a.d_off[i];
+  const int r0 = k * s;
+  const bool regularise = splitting && a.kdim[i];
+  for (int rr = rr0; rr < min(s, rr0 + BF_RB); ++rr) {
+    const int r = r0 + rr;
+    double* Drow = Di + (int64_t)rr * s;
+    if (k >= K || r >= n) {  // identity rows: past the last block, or padding
+      for (int j = threadIdx.x; j < s; j += blockDim.x) Drow[j] = j == rr ? 1.0 : 0.0;
+      continue;
+    }
+    const int64_t f = a.om_off[i] + r;
+    const int64_t q0 = a.lrow[f], q1 = a.lrow[f + 1];
+    const int64_t fp = (a.pad_off[i] + r) * adsd::NCPL;  // coupling slots of this row
+    for (int j = threadIdx.x; j < s; j += blockDim.x) {
+      double v = 0.0;
+      for (int64_t q = q0; q < q1; ++q) {
+        if (a.lcol[q] - r0 != j) continue;
+        double x = a.lval[q];
+        if (j == rr && splitting) {
+          if (!a.om_int[f]) x -= a.lsum[f];
+          if (regularise && r == n - 1) x *= 2.0;
+        }
+        v = x;
+      }
+      if (k > 0)
+#pragma unroll
+        for (int m = 0; m < adsd::NCPL; ++m) {
+          const int cc = a.cpl_col[fp + m];
+          if (cc >= 0) v -= a.cpl_val[fp + m] * Pi[(int64_t)cc * s + j];
+        }
+      Drow[j] = v;
+    }
+  }
+}
+
+template <class FT>
+__global__ void __launch_bounds__(256)
+k_bf_store(BfArgs a, int k, const double* Ginv, double* Pp, FT* fac) {
+  const int i = blockIdx.x;
+  const int s = a.bs[i], K = a.nb[i];
+  if (k >= K) return;
+  constexpr int V = adsd::TileV<FT>::V;
+  const int64_t TS = adsd::tile_size(s, V);
+  const double* G = Ginv + a.d_off[i];
+  double* P = Pp + a.d_off[i];
+  FT* Gt = fac + a.fac_off[i] + (int64_t)k * 2 * TS;
+  const bool more = k + 1 < K;
+  const int64_t cbase = a.pad_off[i] + (int64_t)(k + 1) * s;  // padded columns of block k + 1
+  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < TS;
+       e += (int64_t)gridDim.y * blockDim.x) {
+    const int v = (int)(e % V);
+    const int64_t rest = e / V;
+    const int r = (int)(rest % s), cidx = (int)(rest / s) * V + v;
+    const bool in = cidx < s;
+    adsd::st_fac(Gt, e, in ? G[(int64_t)r * s + cidx] : 0.0);
+    if (more) {
+      double pv = 0.0;
+      if (in) {
+        const int64_t fc = (cbase + cidx) * adsd::NCPL;
+#pragma unroll
+        for (int m = 0; m < adsd::NCPL; ++m) {
+          const int rw = a.ucpl_row[fc + m];
+          if (rw >= 0) pv += G[(int64_t)r * s + rw] * a.ucpl_val[fc + m];
+        }
+        P[(int64_t)r * s + cidx] = pv;
+      }
+      adsd::st_fac(Gt + TS, e, pv);
+    }
+  }
+}
+
+template <class FT>
+static void factor_batched(Ctx& c, int splitting, void** out) {
+  hipStream_t st = c.stream;
+  const int nsub = c.nsub;
+  FT* fac = c.mem.alloc<FT>(c.fac_elems);
+  *out = fac;
+  constexpr int V = adsd::TileV<FT>::V;
+  std::vector<int64_t> hd(nsub + 1, 0);
+  std::vector<int32_t> hs(nsub + 1, 0);
+  int smax = 0, kmax = 0;
+  int64_t tsmax = 0;
+  for (int i = 0; i < nsub; ++i) {
+    const int b = c.h_bs[i];
+    hd[i + 1] = hd[i] + (int64_t)b * b;
+    hs[i + 1] = hs[i] + b;
+    smax = std::max(smax, b);
+    kmax = std::max(kmax, (int)c.h_nb[i]);
+    tsmax = std::max(tsmax, adsd::tile_size(b, V));
+  }
+  int64_t* d_off = upload(c.mem, hd.data(), nsub + 1, st);
+  int32_t* s_off = upload(c.mem, hs.data(), nsub + 1, st);
+  double* D = c.mem.alloc<double>(hd[nsub]);
+  double* F = c.mem.alloc<double>(hd[nsub]);
+  double* Pp = c.mem.alloc<double>(hd[nsub]);
+  int32_t* bad = c.mem.alloc<int32_t>(1);
+  ADS_HIP(hipMemsetAsync(bad, 0, 4, st));
+  BfArgs a{c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
+           c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, d_off};
+  const dim3 gb(nsub, (unsigned)((smax + BF_RB - 1) / BF_RB));
+  const dim3 gs(nsub, (unsigned)std::max<int64_t>(1, (tsmax + 1023) / 1024));
+  for (int k = 0; k < kmax; ++k) {
+    ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
+    double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], D, F, d_off, s_off, bad);
+    ADS_LAUNCH((k_bf_store<FT>), gs, dim3(256), 0, st, a, k, inv, Pp, fac);
+  }
+  std::vector<int32_t> hb;
+  download(hb, bad, 1, st);
+  for (void* q : {(void*)D, (void*)F, (void*)Pp, (void*)bad, (void*)d_off, (void*)s_off})
+    c.mem.release(q);
+  if (hb[0])
+    fail(ADS_ERR_SINGULAR, std::string("zero pivot in the ") + (splitting ? "splitting" : "local matrix") +
+                               " of subdomain " + std::to_string(hb[0] - 1));
+}
+
 void release_factors(Ctx& c) {
   for (void** p : {&c.facA, &c.facT, (void**)&c.fac_off})
     if (*p) {
@@ -539,6 +697,23 @@ void factor_local(Ctx& c, bool only_a) {
       case ADS_PREC_FP64: factor_fast<double>(c, need_split); break;
       case ADS_PREC_FP32: factor_fast<float>(c, need_split); break;
       default: factor_fast<__hip_bfloat16>(c, need_split); break;
+    }
+    return;
+  }
+  if (c.cpl_ok) {  // block sizes beyond the fast path: batched block steps
+    switch (c.prec) {
+      case ADS_PREC_FP64:
+        factor_batched<double>(c, 0, &c.facA);
+        if (need_split) factor_batched<double>(c, 1, &c.facT);
+        break;
+      case ADS_PREC_FP32:
+        factor_batched<float>(c, 0, &c.facA);
+        if (need_split) factor_batched<float>(c, 1, &c.facT);
+        break;
+      default:
+        factor_batched<__hip_bfloat16>(c, 0, &c.facA);
+        if (need_split) factor_batched<__hip_bfloat16>(c, 1, &c.facT);
+        break;
     }
     return;
   }
