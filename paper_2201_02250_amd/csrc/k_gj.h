@@ -15,11 +15,12 @@ namespace {  // one copy of the kernels per translation unit
 // Explicit inverse of each dense E_s by blocked Gauss-Jordan elimination with
 // partial pivoting (row interchanges, the usual column un-permutation at the
 // end).  Column blocks of width nb are processed in turn:
-//   panel kernel : one workgroup per system runs the unblocked in-place
-//                  Gauss-Jordan steps on the n x nb column panel held in LDS,
-//                  records the pivots, writes the panel result S (the panel
-//                  columns of the accumulated transform) and the composed row
-//                  source map src of the block's interchanges;
+//   panel        : the unblocked Gauss-Jordan steps on the n x nb column
+//                  panel (one workgroup per system with one row per thread up
+//                  to GJ_T rows, else one launch per pivot over chunks of
+//                  rows), recording the pivots; the result S is the panel
+//                  columns of the accumulated transform, src the composed row
+//                  source map of the block's interchanges;
 //   update kernel: every other column receives the same transform as a rank-nb
 //                  product, out(i, j) = in(src i, j) + sum_l (S(i,l) - [i = k0+l]) in(src(k0+l), j),
 //                  written to the other buffer of a ping-pong pair (no in-place
@@ -29,14 +30,7 @@ namespace {  // one copy of the kernels per translation unit
 static constexpr int GJ_T = 1024;
 static constexpr int GJ_UT = 256;
 static constexpr int GJ_TILE = 32;
-static constexpr size_t GJ_LDS_MAX = 150 * 1024;
-
-// largest power-of-two panel width <= 32 whose panel fits the LDS budget
-static int gj_panel_width(int64_t n) {
-  int nb = 32;
-  while (nb > 1 && (size_t)n * (nb * 8 + 8 + 4) + 4096 > GJ_LDS_MAX) nb >>= 1;
-  return ((size_t)n * (nb * 8 + 8 + 4) + 4096 > GJ_LDS_MAX) ? 0 : nb;
-}
+static constexpr int GJ_CH = 256;  // rows per workgroup of the chunked panel
 
 // (value, index) max with ties to the smaller index; NaN never wins
 __device__ __forceinline__ void gj_better(double& bv, int& bi, double v, int i) {
@@ -46,112 +40,174 @@ __device__ __forceinline__ void gj_better(double& bv, int& bi, double v, int i) 
   }
 }
 
-// HBM = false: the panel, the saved pivot column and the row sources live in
-// LDS (n (8 nb + 12) bytes); HBM = true (systems too large for LDS): the panel
-// is worked on in place in its output S, the row sources in src_all and the
-// pivot column in fcol_all (n0 doubles), all through the cache hierarchy.
-template <bool HBM>
-__global__ void __launch_bounds__(GJ_T)
-k_gj_panel(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int nb,
-           double* Sbuf, int32_t* src_all, int32_t* tot_all, double* fcol_all, int32_t* singular) {
-  extern __shared__ double gj_lds[];
-  __shared__ double rowk[32], rowkold[32];
-  __shared__ double pval[GJ_T / 64];
-  __shared__ int pidx[GJ_T / 64];
-  __shared__ int swp[32];
-  const int sy = blockIdx.x;
-  const int base = sys_coff[sy];
-  const int n = sys_coff[sy + 1] - base;
-  if (k0 >= n) return;
-  const int kb = min(nb, n - k0);
-  const int t = threadIdx.x, T = blockDim.x, lane = t & 63, wv = t >> 6;
-  // n x nb panel, row-major; saved pivot column; row sources
-  double* P = HBM ? Sbuf + (int64_t)nb * base : gj_lds;
-  double* fcol = HBM ? fcol_all + base : P + (size_t)n * nb;
-  int* src = HBM ? src_all + base : reinterpret_cast<int*>(fcol + n);
-  const double* A = Ain + E_off[sy];
-  const int lnb = __ffs(nb) - 1;  // nb is a power of two
-  const int ne = n * nb;
-  for (int e = t; e < ne; e += T) {
-    const int i = e >> lnb, l = e & (nb - 1);
-    P[e] = l < kb ? A[(int64_t)i * n + k0 + l] : 0.0;
+// Panels of systems above GJ_T rows: one launch per pivot step over chunks
+// of GJ_CH rows (grid: chunks x systems).  The panel alternates between two
+// buffers (step l reads P[l & 1] and writes P[(l + 1) & 1], rows in the
+// logical order of the block: the pivot row and row k trade places), so no
+// workgroup reads a row that another one writes.  Every workgroup reduces
+// the previous step's per-chunk (|entry|, row) maxima in the same order, and
+// so takes the same pivot, then publishes the maxima of its own rows for the
+// next column.  Steps past a system's last column copy its panel, so that
+// every system's panel ends in the same buffer.
+
+// block-wide (value, index) maximum, ties to the smaller index; the result
+// is valid in thread 0
+__device__ __forceinline__ void gj_block_best(double& bv, int& bi, double* sv, int* si) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    gj_better(bv, bi, ov, oi);
   }
-  for (int i = t; i < n; i += T) src[i] = i;
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) {
+    sv[t >> 6] = bv;
+    si[t >> 6] = bi;
+  }
   __syncthreads();
-  // pivot candidates of the first panel column
+  if (t == 0)
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) gj_better(bv, bi, sv[w], si[w]);
+}
+
+// panel columns [k0, k0 + nb) of the input into P0; maxima of column k0
+__global__ void __launch_bounds__(GJ_CH)
+k_gjc_init(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int nb,
+           double* P0, double* part_v, int* part_i, int nchm, int nsys) {
+  __shared__ double sv[GJ_CH / 64];
+  __shared__ int si[GJ_CH / 64];
+  const int sy = blockIdx.y, ch = blockIdx.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  if (k0 >= n || ch * GJ_CH >= n) return;
+  const int kb = min(nb, n - k0);
+  const int i = ch * GJ_CH + threadIdx.x;
   double bv = -1.0;
   int bi = n;
-  for (int i = k0 + t; i < n; i += T) gj_better(bv, bi, fabs(P[(int64_t)i * nb]), i);
-  for (int l = 0; l < kb; ++l) {
-    // block-wide argmax of the candidates (wave shuffles, then the partials)
+  if (i < n) {
+    const double* a = Ain + E_off[sy] + (int64_t)i * n + k0;
+    double* p = P0 + ((int64_t)base + i) * nb;
+    for (int l = 0; l < nb; ++l) p[l] = l < kb ? a[l] : 0.0;
+    if (i >= k0) gj_better(bv, bi, fabs(a[0]), i);
+  }
+  gj_block_best(bv, bi, sv, si);
+  if (threadIdx.x == 0) {
+    part_v[(int64_t)sy * nchm + ch] = bv;
+    part_i[(int64_t)sy * nchm + ch] = bi;
+  }
+}
+
+// pivot step l (column k0 + l) of every system's panel
+__global__ void __launch_bounds__(GJ_CH)
+k_gjc_step(const int32_t* sys_coff, int k0, int nb, int l, double* P0, double* P1,
+           double* part_v, int* part_i, int nchm, int nsys, int32_t* swp, int32_t* singular) {
+  constexpr int NB = 32;
+  __shared__ double rowk[NB], rowkold[NB];
+  __shared__ double sv[GJ_CH / 64];
+  __shared__ int si[GJ_CH / 64];
+  __shared__ int sp;
+  const int sy = blockIdx.y, ch = blockIdx.x, t = threadIdx.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  if (k0 >= n || ch * GJ_CH >= n) return;
+  const int kb = min(nb, n - k0);
+  const int nch = (n + GJ_CH - 1) / GJ_CH;
+  const double* Pin = (l & 1) ? P1 : P0;
+  double* Pout = (l & 1) ? P0 : P1;
+  const int i = ch * GJ_CH + t;
+  if (l >= kb) {  // past this system's last column: carry the panel over
+    if (i < n)
+      for (int j = 0; j < nb; ++j) Pout[((int64_t)base + i) * nb + j] = Pin[((int64_t)base + i) * nb + j];
+    return;
+  }
+  const int k = k0 + l;
+  const int64_t pin = (int64_t)(l & 1) * nsys * nchm, pout = (int64_t)((l + 1) & 1) * nsys * nchm;
+  if (t < 64) {  // the pivot: maximum of the previous step's chunk maxima
+    double bv = -1.0;
+    int bi = n;
+    for (int c = t; c < nch; c += 64)
+      gj_better(bv, bi, part_v[pin + (int64_t)sy * nchm + c], part_i[pin + (int64_t)sy * nchm + c]);
     for (int o = 32; o > 0; o >>= 1) {
       const double ov = __shfl_xor(bv, o, 64);
       const int oi = __shfl_xor(bi, o, 64);
       gj_better(bv, bi, ov, oi);
     }
-    if (lane == 0) {
-      pval[wv] = bv;
-      pidx[wv] = bi;
-    }
-    __syncthreads();
-    bv = -1.0;
-    bi = n;
-    for (int w = 0; w < T / 64; ++w) gj_better(bv, bi, pval[w], pidx[w]);
-    const int k = k0 + l;
-    int p = bi;
-    if (!(bv > 0.0) || p >= n) {
-      if (t == 0) atomicMax(singular, sy + 1);
-      p = k;
-    }
-    if (t == 0) swp[l] = p;
-    // save the pivot column (rows k and p interchanged) and both rows
-    for (int i = t; i < n; i += T) {
-      const int si = i == k ? p : (i == p ? k : i);
-      fcol[i] = P[(int64_t)si * nb + l];
-    }
-    if (t < nb) {
-      rowk[t] = P[(int64_t)p * nb + t];
-      rowkold[t] = P[(int64_t)k * nb + t];
-    }
-    __syncthreads();
-    const double v = fcol[k];
-    const double d = (v != 0.0) ? 1.0 / v : 1.0;
-    bv = -1.0;
-    bi = n;
-    for (int e = t; e < ne; e += T) {
-      const int i = e >> lnb, j = e & (nb - 1);
-      const double old = i == k ? rowk[j] : (i == p ? rowkold[j] : P[e]);
-      double nw;
-      if (i == k)
-        nw = j == l ? d : old * d;
-      else
-        nw = j == l ? -fcol[i] * d : old - fcol[i] * (rowk[j] * d);
-      P[e] = nw;
-      if (j == l + 1 && i > k) gj_better(bv, bi, fabs(nw), i);
+    if (t == 0) {
+      int p = bi;
+      if (!(bv > 0.0) || p >= n) {
+        if (ch == 0) atomicMax(singular, sy + 1);
+        p = k;
+      }
+      sp = p;
+      if (ch == 0) swp[sy * NB + l] = p;
     }
   }
+  __syncthreads();
+  const int p = sp;
+  if (t < nb) {
+    rowk[t] = Pin[((int64_t)base + p) * nb + t];
+    rowkold[t] = Pin[((int64_t)base + k) * nb + t];
+  }
+  __syncthreads();
+  double bv = -1.0;
+  int bi = n;
+  if (i < n) {
+    const double* src = Pin + ((int64_t)base + i) * nb;
+    double v[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double x = i == k ? rowk[j] : (i == p ? rowkold[j] : src[min(j, nb - 1)]);
+      v[j] = j < nb ? x : 0.0;
+    }
+    double f = v[0];  // this row's entry in the pivot column
+#pragma unroll
+    for (int j = 1; j < NB; ++j) f = j == l ? v[j] : f;
+    const double piv = rowk[l];
+    const double d = piv != 0.0 ? 1.0 / piv : 1.0;
+    double* dst = Pout + ((int64_t)base + i) * nb;
+    double nxt = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      double w;
+      if (i == k)
+        w = j == l ? d : v[j] * d;
+      else
+        w = j == l ? -f * d : v[j] - f * (rowk[j] * d);
+      if (j < nb) dst[j] = w;
+      nxt = j == l + 1 ? w : nxt;
+    }
+    if (i > k && l + 1 < kb) gj_better(bv, bi, fabs(nxt), i);
+  }
+  if (l + 1 < kb) {
+    gj_block_best(bv, bi, sv, si);
+    if (t == 0) {
+      part_v[pout + (int64_t)sy * nchm + ch] = bv;
+      part_i[pout + (int64_t)sy * nchm + ch] = bi;
+    }
+  }
+}
+
+// the block's composed row sources and the cumulative row map
+// tot(x) <- tot(src(x)) (tmp: n0 ints of scratch)
+__global__ void __launch_bounds__(GJ_T)
+k_gjc_fini(const int32_t* sys_coff, int k0, int nb, const int32_t* swp, int32_t* src_all,
+           int32_t* tot_all, int32_t* tmp_all) {
+  const int sy = blockIdx.x, t = threadIdx.x, T = blockDim.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  if (k0 >= n) return;
+  const int kb = min(nb, n - k0);
+  int32_t* src = src_all + base;
+  int32_t* tot = tot_all + base;
+  int32_t* tmp = tmp_all + base;
+  for (int x = t; x < n; x += T) src[x] = x;
   __syncthreads();
   if (t == 0)
     for (int l = 0; l < kb; ++l) {
-      const int k = k0 + l, p = swp[l];
-      const int tmp = src[k];
+      const int k = k0 + l, p = swp[sy * 32 + l];
+      const int a = src[k];
       src[k] = src[p];
-      src[p] = tmp;
+      src[p] = a;
     }
   __syncthreads();
-  if (!HBM) {
-    double* S = Sbuf + (int64_t)nb * base;
-    for (int e = t; e < ne; e += T) S[e] = P[e];
-    int32_t* so = src_all + base;
-    for (int i = t; i < n; i += T) so[i] = src[i];
-  }
-  // cumulative row map: tot(x) <- tot(src(x)), through the pivot column's
-  // storage (free by now)
-  int32_t* tot = tot_all + base;
-  int* tmp = reinterpret_cast<int*>(fcol);
-  for (int i = t; i < n; i += T) tmp[i] = k0 == 0 ? src[i] : tot[src[i]];
+  for (int x = t; x < n; x += T) tmp[x] = k0 == 0 ? src[x] : tot[src[x]];
   __syncthreads();
-  for (int i = t; i < n; i += T) tot[i] = tmp[i];
+  for (int x = t; x < n; x += T) tot[x] = tmp[x];
 }
 
 // one DPP step of a wave maximum: x = max(x, x of the lane given by CTRL)
@@ -274,24 +330,29 @@ k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff,
   if (live) tot[pos] = tv;
 }
 
-// out = transform of in for the column block [k0, k0 + kb) (see above);
-// systems whose order is <= k0 are copied unchanged
+// out = transform of in for the column block [k0, k0 + kb) (see above), on
+// TL x TL output tiles; each thread accumulates (TL/16)^2 outputs in
+// registers, so every LDS read feeds TL/16 products.  Systems whose order is
+// <= k0 are copied unchanged.  The sum over l runs in the same order for
+// every tile shape.
+template <int TL>
 __global__ void __launch_bounds__(GJ_UT)
 k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff, int k0,
             int nb, const double* Sbuf, const int32_t* src_all) {
-  __shared__ double Ssh[GJ_TILE][33];
-  __shared__ double Rsh[32][GJ_TILE];
-  __shared__ int srow[GJ_TILE];
+  constexpr int R = TL / 16;
+  __shared__ double Ssh[TL][33];
+  __shared__ double Rsh[32][TL];
+  __shared__ int srow[TL];
   const int sy = blockIdx.z;
   const int n = sys_coff[sy + 1] - sys_coff[sy];
-  const int i0 = blockIdx.y * GJ_TILE, j0 = blockIdx.x * GJ_TILE;
+  const int i0 = blockIdx.y * TL, j0 = blockIdx.x * TL;
   if (i0 >= n || j0 >= n) return;
   const double* A = Ain + E_off[sy];
   double* B = Aout + E_off[sy];
   const int t = threadIdx.x, tr = t / 16, tc = t % 16;
   if (k0 >= n) {
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
+    for (int a = 0; a < R; ++a)
+      for (int b = 0; b < R; ++b) {
         const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
         if (i < n && j < n) B[(int64_t)i * n + j] = A[(int64_t)i * n + j];
       }
@@ -300,31 +361,44 @@ k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t
   const int kb = min(nb, n - k0);
   const double* S = Sbuf + (int64_t)nb * sys_coff[sy];
   const int32_t* src = src_all + sys_coff[sy];
-  for (int e = t; e < GJ_TILE * 32; e += GJ_UT) {
+  for (int e = t; e < TL * 32; e += GJ_UT) {
     const int r = e / 32, l = e % 32;
     const int i = i0 + r;
     double v = 0.0;
     if (i < n && l < kb) v = S[(int64_t)i * nb + l] - (i == k0 + l ? 1.0 : 0.0);
     Ssh[r][l] = v;
-    const int rl = e / GJ_TILE, cc = e % GJ_TILE;
+    const int rl = e / TL, cc = e % TL;
     const int j = j0 + cc;
     Rsh[rl][cc] = (rl < kb && j < n) ? A[(int64_t)src[k0 + rl] * n + j] : 0.0;
   }
-  if (t < GJ_TILE) srow[t] = (i0 + t < n) ? src[i0 + t] : 0;
+  if (t < TL) srow[t] = (i0 + t < n) ? src[i0 + t] : 0;
   __syncthreads();
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int r = tr + 16 * a, cc = tc + 16 * b;
-      const int i = i0 + r, j = j0 + cc;
+  double acc[R][R];
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+      acc[a][b] = (i < n && j < n) ? A[(int64_t)srow[tr + 16 * a] * n + j] : 0.0;
+    }
+  for (int l = 0; l < kb; ++l) {
+    double sa[R], rb[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) sa[a] = Ssh[tr + 16 * a][l];
+#pragma unroll
+    for (int b = 0; b < R; ++b) rb[b] = Rsh[l][tc + 16 * b];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < R; ++b) acc[a][b] += sa[a] * rb[b];
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
       if (i >= n || j >= n) continue;
-      double v;
-      if (j >= k0 && j < k0 + kb) {
-        v = S[(int64_t)i * nb + (j - k0)];
-      } else {
-        v = A[(int64_t)srow[r] * n + j];
-        for (int l = 0; l < kb; ++l) v += Ssh[r][l] * Rsh[l][cc];
-      }
-      B[(int64_t)i * n + j] = v;
+      B[(int64_t)i * n + j] = (j >= k0 && j < k0 + kb) ? S[(int64_t)i * nb + (j - k0)] : acc[a][b];
     }
 }
 
@@ -358,41 +432,65 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
                                  double* A, double* B, const int64_t* E_off,
                                  const int32_t* sys_coff, int32_t* flag) {
   if (maxs <= 0) return A;
-  // register-resident panels (width 32, one row per thread) up to order GJ_T,
-  // else LDS panels, else (orders above about 7400) panels in HBM
+  // register-resident panels (one row per thread) up to order GJ_T, else
+  // panels stepped over chunks of rows; width 32
   const bool reg = maxs <= GJ_T;
-  const int nbl = reg ? 32 : gj_panel_width(maxs);
-  const bool hbm = nbl == 0;
-  const int nb = hbm ? 32 : nbl;
+  const int nb = 32;
   const int64_t n0t = std::max<int64_t>(nrow, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
   double* S = c.mem.alloc<double>(n0t * nb);
-  double* fcol = hbm ? c.mem.alloc<double>(n0t) : nullptr;
+  double* S1 = nullptr;
+  double* part_v = nullptr;
+  int32_t* part_i = nullptr;
+  int32_t* swp = nullptr;
+  int32_t* tmp = nullptr;
+  const int nchm = (int)((maxs + GJ_CH - 1) / GJ_CH);
+  if (!reg) {
+    S1 = c.mem.alloc<double>(n0t * nb);
+    part_v = c.mem.alloc<double>((size_t)2 * nsys * nchm);
+    part_i = c.mem.alloc<int32_t>((size_t)2 * nsys * nchm);
+    swp = c.mem.alloc<int32_t>((size_t)nsys * nb);
+    tmp = c.mem.alloc<int32_t>(n0t);
+  }
   double* bufs[2] = {A, B};
-  const size_t plds = hbm ? 0 : (size_t)maxs * (nb * 8 + 8 + 4);
-  const unsigned tiles = (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
+  // 64 x 64 output tiles when they still give the GPU a few thousand
+  // workgroups, else 32 x 32
+  const unsigned t64 = (unsigned)((maxs + 63) / 64);
+  const bool wide = (int64_t)t64 * t64 * nsys >= 2048;
+  const unsigned tiles = wide ? t64 : (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
   const unsigned rows = (unsigned)((maxs + 63) / 64 * 64);  // one thread per row
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
-    if (hbm)
-      ADS_LAUNCH(k_gj_panel<true>, dim3(nsys), dim3(GJ_T), 0, st, bufs[cur], E_off, sys_coff,
-                 (int)k0, nb, S, src, tot, fcol, flag);
-    else if (!reg)
-      ADS_LAUNCH(k_gj_panel<false>, dim3(nsys), dim3(GJ_T), plds, st, bufs[cur], E_off, sys_coff,
-                 (int)k0, nb, S, src, tot, fcol, flag);
-    else
+    double* Sk = S;
+    if (reg) {
       ADS_LAUNCH(k_gj_panel_row, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
                  (int)k0, S, src, tot, flag);
-    ADS_LAUNCH(k_gj_update, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur], bufs[1 - cur],
-               E_off, sys_coff, (int)k0, nb, S, src);
+    } else {
+      const dim3 g((unsigned)nchm, (unsigned)nsys);
+      ADS_LAUNCH(k_gjc_init, g, dim3(GJ_CH), 0, st, bufs[cur], E_off, sys_coff, (int)k0, nb, S,
+                 part_v, part_i, nchm, nsys);
+      const int L = (int)std::min<int64_t>(nb, maxs - k0);
+      for (int l = 0; l < L; ++l)
+        ADS_LAUNCH(k_gjc_step, g, dim3(GJ_CH), 0, st, sys_coff, (int)k0, nb, l, S, S1, part_v,
+                   part_i, nchm, nsys, swp, flag);
+      Sk = (L & 1) ? S1 : S;
+      ADS_LAUNCH(k_gjc_fini, dim3(nsys), dim3(GJ_T), 0, st, sys_coff, (int)k0, nb, swp, src, tot,
+                 tmp);
+    }
+    if (wide)
+      ADS_LAUNCH(k_gj_update<64>, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur],
+                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, Sk, src);
+    else
+      ADS_LAUNCH(k_gj_update<GJ_TILE>, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur],
+                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, Sk, src);
     cur = 1 - cur;
   }
   const int rpb = 16;
   ADS_LAUNCH(k_gj_unpermute, dim3((unsigned)((maxs + rpb - 1) / rpb), nsys), dim3(256),
              (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], E_off, sys_coff, tot, rpb);
-  c.mem.release(S);
-  if (fcol) c.mem.release(fcol);
+  for (void* q : {(void*)S, (void*)S1, (void*)part_v, (void*)part_i, (void*)swp, (void*)tmp})
+    if (q) c.mem.release(q);
   c.mem.release(src);
   c.mem.release(tot);
   return bufs[1 - cur];
