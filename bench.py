@@ -142,6 +142,38 @@ def cpu_baseline():
                 host_cpus=os.cpu_count())
 
 
+def profile_workload(name, steps, precision):
+    """Profiling driver for the other named workloads (their own right-hand
+    side count and Krylov settings): `steps` setup+solve runs, one timing line
+    each on stderr, no bench line."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_02250_amd import ads
+
+    dev = torch.device("cuda:0")
+    A, part, N, o = W.config(name)
+    if part is None:
+        part = ads.ads_partition_bfs(A, o["seeds"])
+    Ad = ads.DeviceCSR(A, dev)
+    nrhs = o.get("nrhs", 1)
+    B = torch.tensor(np.stack([W.rhs(A.n, s) for s in range(nrhs)], axis=1), device=dev)
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=precision)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = ctx.solve(B, restart=o["restart"], flexible=o["flexible"], rtol=1e-8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ci = ctx.info
+        ctx.close()
+        print("[profile] %s step %d: setup %.1f ms solve %.1f ms its max %d status %d n0 %d phases %s"
+              % (name, k, 1e3 * (t1 - t0), 1e3 * (t2 - t1), max(info["its"][:nrhs]), info["status"],
+                 ci["n0"], [round(v, 2) for v in ci["t_phase_ms"][:6]]), file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-apply", action="store_true",
                     help="only run applies and a plain copy (for rocprofv3 --pmc runs)")
+    ap.add_argument("--profile-workload", default=None,
+                    help="only run setup+solve of another named workload (profiling driver)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -159,6 +193,11 @@ def main():
         sys.exit(2)
     if args.pmc_apply:
         pmc_apply(args.apply_reps)
+        return
+    if args.profile_workload:
+        from paper_2201_02250_amd import ads
+        precs = {"fp64": ads.ADS_PREC_FP64, "fp32": ads.ADS_PREC_FP32, "bf16": ads.ADS_PREC_BF16}
+        profile_workload(args.profile_workload, args.steps, precs[args.precision])
         return
 
     import numpy as np
