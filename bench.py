@@ -169,9 +169,11 @@ def profile_workload(name, steps, precision):
         t2 = time.perf_counter()
         ci = ctx.info
         ctx.close()
-        print("[profile] %s step %d: setup %.1f ms solve %.1f ms its max %d status %d n0 %d phases %s"
+        print("[profile] %s step %d: setup %.1f ms solve %.1f ms its max %d status %d n0 %d "
+              "tile factor %g phases %s"
               % (name, k, 1e3 * (t1 - t0), 1e3 * (t2 - t1), max(info["its"][:nrhs]), info["status"],
-                 ci["n0"], [round(v, 2) for v in ci["t_phase_ms"][:6]]), file=sys.stderr, flush=True)
+                 ci["n0"], ci["tile_factor"], [round(v, 2) for v in ci["t_phase_ms"][:6]]),
+              file=sys.stderr, flush=True)
 
 
 def main():

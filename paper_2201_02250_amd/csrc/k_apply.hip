@@ -227,6 +227,7 @@ k_coarse_prolong(const double* __restrict__ part, const double* __restrict__ yfu
 
 // gather t = r - A q on local rows [lo, hi) of Omega_i (zero on the padding)
 // into X (column jj at X + jj*ld)
+template <int P>
 __device__ __forceinline__ void gather_local(const int32_t* __restrict__ om, int ns, int lo, int hi,
                                              const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ col,
@@ -235,20 +236,54 @@ __device__ __forceinline__ void gather_local(const int32_t* __restrict__ om, int
                                              const double* __restrict__ q, int64_t n, int j0, int pc,
                                              double* X, int64_t ld) {
   const int len = hi - lo;
-  for (int e = threadIdx.x; e < len * pc; e += blockDim.x) {
-    const int lr = lo + e % len, jj = e / len;
-    double v = 0.0;
+  if (P == 1 || pc == 1) {
+    for (int e = threadIdx.x; e < len * pc; e += blockDim.x) {
+      const int lr = lo + e % len, jj = e / len;
+      double v = 0.0;
+      if (lr < ns) {
+        const int g = om[lr];
+        const int64_t off = (int64_t)(j0 + jj) * n;
+        v = r[off + g];
+        if (q) {
+          double aq = 0.0;
+          for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) aq += val[k] * q[off + col[k]];
+          v -= aq;
+        }
+      }
+      X[lr + (int64_t)jj * ld] = v;
+    }
+    return;
+  }
+  // several columns: one row per thread, the row's pattern read once and the
+  // q entries of all columns fetched together (same summation order)
+  for (int e = threadIdx.x; e < len; e += blockDim.x) {
+    const int lr = lo + e;
+    double v[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j] = 0.0;
     if (lr < ns) {
       const int g = om[lr];
-      const int64_t off = (int64_t)(j0 + jj) * n;
-      v = r[off + g];
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (j < pc) v[j] = r[(int64_t)(j0 + j) * n + g];
       if (q) {
-        double aq = 0.0;
-        for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) aq += val[k] * q[off + col[k]];
-        v -= aq;
+        double aq[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) aq[j] = 0.0;
+        for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+          const int c = col[k];
+          const double a = val[k];
+#pragma unroll
+          for (int j = 0; j < P; ++j)
+            if (j < pc) aq[j] += a * q[(int64_t)(j0 + j) * n + c];
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] -= aq[j];
       }
     }
-    X[lr + (int64_t)jj * ld] = v;
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (j < pc) X[lr + (int64_t)j * ld] = v[j];
   }
 }
 
@@ -290,6 +325,7 @@ struct LocalArgs {
   const int32_t* col;
   const double* val;
   const int64_t* pad_off;
+  int cpl_ok;     // the coupling lists are complete
   double* work;
   double* work2;  // backward results of the two-ended solve
   int64_t ldw;
@@ -317,7 +353,7 @@ k_local_fwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ 
   const int32_t* om = a.om_sorted + base;
   double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
   const int lo = half ? (M + 1) * s : 0, hi = half ? K * s : (M + 1) * s;
-  gather_local(om, ns, lo, hi, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
+  gather_local<P>(om, ns, lo, hi, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
   __syncthreads();
   double* dummy =
       a.dummy + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * blockDim.x +
@@ -371,9 +407,12 @@ k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict_
   const int64_t base = a.om_off[i];
   const int32_t* om = a.om_sorted + base;
   double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
-  gather_local(om, ns, 0, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
+  gather_local<P>(om, ns, 0, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
   __syncthreads();
-  adsd::block_solve_general<FT, P>(fac + a.fac_off[i], s, K, ns, a.lrow + base, a.lcol, a.lval, X,
+  const int64_t cb = a.pad_off[i] * adsd::NCPL;
+  adsd::block_solve_general<FT, P>(fac + a.fac_off[i], s, K, ns, a.lrow + base, a.lcol, a.lval,
+                                   a.cpl_ok ? a.cpl_col + cb : nullptr,
+                                   a.cpl_ok ? a.cpl_val + cb : nullptr, X,
                                    a.ldw, pc, lds);
   scatter_local(om, a.om_int + base, 0, ns, q, z, a.n, j0, pc, X, a.ldw);
 }
@@ -414,6 +453,7 @@ static LocalArgs local_args(Ctx& c) {
   a.lcol = c.lcol;
   a.lval = c.lval;
   a.cpl_col = c.cpl_col;
+  a.cpl_ok = c.cpl_ok ? 1 : 0;
   a.cpl_val = c.cpl_val;
   a.rcpl_col = c.rcpl_col;
   a.rcpl_val = c.rcpl_val;

@@ -875,6 +875,7 @@ struct EigArgs {
   const int64_t* pad_off;
   const int32_t* cpl_col;
   const double* cpl_val;
+  int cpl_ok;               // the coupling lists are complete
   const int32_t* rcpl_col;  // A_k,k+1 by row (fast coupling lists)
   const double* rcpl_val;
   const int32_t* ucpl_row;  // A_k-1,k by column
@@ -1449,7 +1450,10 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
     }
   }
   __syncthreads();
-  adsd::block_solve_general<FT, PC>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, Y,
+  const int64_t cb = a.pad_off[i] * adsd::NCPL;
+  adsd::block_solve_general<FT, PC, false>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol,
+                                           a.lval, a.cpl_ok ? a.cpl_col + cb : nullptr,
+                                           a.cpl_ok ? a.cpl_val + cb : nullptr, Y,
                                     ld, pc, lds);
   if (floating) {  // projection onto 1^perp
     __syncthreads();
@@ -2641,6 +2645,7 @@ void eigensolve(Ctx& c) {
   a.pad_off = c.pad_off;
   a.cpl_col = c.cpl_col;
   a.cpl_val = c.cpl_val;
+  a.cpl_ok = c.cpl_ok ? 1 : 0;
   a.rcpl_col = c.rcpl_col;
   a.rcpl_val = c.rcpl_val;
   a.ucpl_row = c.ucpl_row;

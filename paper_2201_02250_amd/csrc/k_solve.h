@@ -318,26 +318,57 @@ namespace adsd {
 
 // General path (any block size, any number of couplings): the tile entries
 // are read directly (no prefetch) and the couplings come from the local CSR.
-template <class FT, int P>
+// acc[j] += sum over the 16-byte column groups [qa, qb) of row r of a tile
+// (mr = the row's first vector) times vin[c + j s], columns ascending; U
+// loads are issued before any is consumed (addresses clamped in bounds)
+template <class FT, int P, int U>
+__device__ __forceinline__ void tile_row_dot(const FT* __restrict__ mr, int s, int qa, int qb,
+                                             const double* vin, double (&acc)[P]) {
+  constexpr int V = TileV<FT>::V;
+  using RT = typename TileReg<FT>::T;
+  for (int q0 = qa; q0 < qb; q0 += U) {
+    RT m[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) tile_load_vec<FT>(mr + (int64_t)min(q0 + u, qb - 1) * s * V, m[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c0 = (q0 + u) * V;
+      if (q0 + u < qb) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (c0 + v < s)
+#pragma unroll
+            for (int j = 0; j < P; ++j) acc[j] += (double)m[u][v] * vin[c0 + v + j * s];
+      }
+    }
+  }
+}
+
+// out = M vin (mode 0) or base - M vin (mode 1) for one s x s tile and pc
+// columns of vin (s x P, column-major in LDS).  G = T / s threads share a
+// row when 2 s <= T (column chunks of whole 16-byte groups, partial sums
+// in part, summed in chunk order), else each thread owns rows.  WIDE: 8
+// loads in flight per thread, else 2 (at most 64 registers in 1024-thread
+// kernels).
+template <class FT, int P, bool WIDE = true>
 __device__ __forceinline__ void tile_product_general(const FT* __restrict__ M, int s,
                                                      const double* vin, double* part, double* out,
                                                      int mode, const double* base, int64_t ldb,
                                                      int pc) {
+  constexpr int V = TileV<FT>::V;
+  constexpr int U = WIDE ? 8 : 2;
   const int t = threadIdx.x, T = blockDim.x;
+  const int nq = (s + V - 1) / V;
   const int G = (2 * s <= T) ? (T / s) : 1;
   if (G > 1) {
-    const int chunk = (s + G - 1) / G;
+    const int qch = (nq + G - 1) / G;
     const int r = t % s, g = t / s;
     if (g < G) {
       double acc[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) acc[j] = 0.0;
-      const int c0 = g * chunk, c1 = min(s, c0 + chunk);
-      for (int cidx = c0; cidx < c1; ++cidx) {
-        const double m = ld_fac(M, tile_at(r, cidx, s, TileV<FT>::V));
-#pragma unroll
-        for (int j = 0; j < P; ++j) acc[j] += m * vin[cidx + j * s];
-      }
+      const int qa = g * qch, qb = min(nq, qa + qch);
+      if (qa < qb) tile_row_dot<FT, P, U>(M + (int64_t)r * V, s, qa, qb, vin, acc);
 #pragma unroll
       for (int j = 0; j < P; ++j) part[((int64_t)g * s + r) * P + j] = acc[j];
     }
@@ -353,11 +384,7 @@ __device__ __forceinline__ void tile_product_general(const FT* __restrict__ M, i
       double acc[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) acc[j] = 0.0;
-      for (int cidx = 0; cidx < s; ++cidx) {
-        const double m = ld_fac(M, tile_at(r, cidx, s, TileV<FT>::V));
-#pragma unroll
-        for (int j = 0; j < P; ++j) acc[j] += m * vin[cidx + j * s];
-      }
+      tile_row_dot<FT, P, U>(M + (int64_t)r * V, s, 0, nq, vin, acc);
       for (int j = 0; j < pc; ++j) out[r + j * s] = mode ? base[r + j * ldb] - acc[j] : acc[j];
     }
   }
@@ -374,11 +401,16 @@ inline int64_t solve_lds_doubles_general(const std::vector<int32_t>& sizes, int 
   return m;
 }
 
-template <class FT, int P>
+// ccol / cval: the subdomain's row coupling list of A_k,k-1 (NCPL slots per
+// padded row, CSR order), or null when the lists are incomplete; the Schur
+// step then walks the local CSR rows
+template <class FT, int P, bool WIDE = true>
 __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, int n,
                                     const int64_t* __restrict__ lrow,
                                     const int32_t* __restrict__ lcol,
-                                    const double* __restrict__ lval, double* X, int64_t ldx, int pc,
+                                    const double* __restrict__ lval,
+                                    const int32_t* __restrict__ ccol,
+                                    const double* __restrict__ cval, double* X, int64_t ldx, int pc,
                                     double* lds) {
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t ss = tile_size(s, TileV<FT>::V);  // tile stride
@@ -388,20 +420,38 @@ __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, in
   for (int k = 0; k < K; ++k) {
     const int r0 = k * s;
     __syncthreads();
-    for (int e = t; e < s * pc; e += T) {
-      const int rr = e % s, j = e / s;
-      const int r = r0 + rr;
-      double y = X[r + j * ldx];
-      if (k > 0 && r < n) {
-        for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
-          const int cc = lcol[q] - (r0 - s);
-          if (cc >= 0 && cc < s) y -= lval[q] * hbuf[cc + j * s];
+    if (ccol) {
+      for (int e = t; e < s * pc; e += T) {
+        const int rr = e % s, j = e / s;
+        const int r = r0 + rr;
+        double y = X[r + j * ldx];
+        if (k > 0) {
+          const int32_t* cr = ccol + (int64_t)r * NCPL;
+          const double* vr = cval + (int64_t)r * NCPL;
+#pragma unroll
+          for (int m = 0; m < NCPL; ++m) {
+            const int cc = cr[m];
+            if (cc >= 0) y -= vr[m] * hbuf[cc + j * s];
+          }
         }
+        ybuf[rr + j * s] = y;
       }
-      ybuf[rr + j * s] = y;
+    } else {
+      for (int e = t; e < s * pc; e += T) {
+        const int rr = e % s, j = e / s;
+        const int r = r0 + rr;
+        double y = X[r + j * ldx];
+        if (k > 0 && r < n) {
+          for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
+            const int cc = lcol[q] - (r0 - s);
+            if (cc >= 0 && cc < s) y -= lval[q] * hbuf[cc + j * s];
+          }
+        }
+        ybuf[rr + j * s] = y;
+      }
     }
     __syncthreads();
-    tile_product_general<FT, P>(fac + (int64_t)k * 2 * ss, s, ybuf, part, hbuf, 0, nullptr, 0, pc);
+    tile_product_general<FT, P, WIDE>(fac + (int64_t)k * 2 * ss, s, ybuf, part, hbuf, 0, nullptr, 0, pc);
     __syncthreads();
     for (int e = t; e < s * pc; e += T) {
       const int rr = e % s, j = e / s;
@@ -413,7 +463,7 @@ __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, in
     __syncthreads();
     for (int e = t; e < s * pc; e += T) ybuf[e] = hbuf[e];
     __syncthreads();
-    tile_product_general<FT, P>(fac + (int64_t)k * 2 * ss + ss, s, ybuf, part, hbuf, 1, X + r0,
+    tile_product_general<FT, P, WIDE>(fac + (int64_t)k * 2 * ss + ss, s, ybuf, part, hbuf, 1, X + r0,
                                 ldx, pc);
     __syncthreads();
     for (int e = t; e < s * pc; e += T) {
