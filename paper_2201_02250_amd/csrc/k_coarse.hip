@@ -160,7 +160,8 @@ void assemble_coarse(Ctx& c) {
              c.sub_sys_d, c.sys_coff, c.E_off, E);
   std::vector<int32_t> hf;  // both flags are read once, after the inverse
   double* F = c.mem.alloc<double>(etot);
-  double* inv = gj_invert_batched(c, st, nsys, maxs, sc[nsys], E, F, c.E_off, c.sys_coff, flag + 1);
+  double* inv = gj_invert_batched(c, st, nsys, maxs, sc[nsys], c.h_E_off[nsys], E, F, c.E_off,
+                                  c.sys_coff, flag + 1);
   download(hf, flag, 2, st);
   if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");
   if (hf[1]) fail(ADS_ERR_SINGULAR, "singular coarse operator in system " + std::to_string(hf[1] - 1));

@@ -661,7 +661,7 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   const dim3 gs(nsub, (unsigned)std::max<int64_t>(1, (tsmax + 1023) / 1024));
   for (int k = 0; k < kmax; ++k) {
     ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
-    double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], D, F, d_off, s_off, bad);
+    double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad);
     ADS_LAUNCH((k_bf_store<FT>), gs, dim3(256), 0, st, a, k, inv, Pp, fac);
   }
   std::vector<int32_t> hb;

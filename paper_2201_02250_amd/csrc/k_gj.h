@@ -245,10 +245,10 @@ __device__ __forceinline__ double gj_wave_max(double x) {
 // not yet used, ties to the smaller row) together with that row's values in
 // a double-buffered LDS slot, and every thread then takes the first slot of
 // largest magnitude.  The result S is written in logical row order.
+template <int NB>
 __global__ void __launch_bounds__(GJ_T)
 k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
                double* Sbuf, int32_t* src_all, int32_t* tot_all, int32_t* singular) {
-  constexpr int NB = 32;
   __shared__ double slot_r[2][GJ_T / 64][NB + 1];  // row values, then the key
   __shared__ int slot_q[2][GJ_T / 64][2];          // physical row, logical position
   const int sy = blockIdx.x;
@@ -427,15 +427,19 @@ __global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_
 // sy has order sys_coff[sy + 1] - sys_coff[sy] (device arrays) and starts at
 // E_off[sy]; B has the size of A.  Returns A or B, whichever holds the
 // inverses (the other is free).  A singular system sets *flag to sy + 1 (the
-// largest such index); nrow = sys_coff[nsys] (host).
+// largest such index); nrow = sys_coff[nsys] and total = the sum of the
+// orders squared (host).
 double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_t nrow,
-                                 double* A, double* B, const int64_t* E_off,
-                                 const int32_t* sys_coff, int32_t* flag) {
+                          int64_t total, double* A, double* B, const int64_t* E_off,
+                          const int32_t* sys_coff, int32_t* flag) {
+  const bool small_batch = total * 8 <= ((int64_t)32 << 20);  // all matrices within 32 MB
   if (maxs <= 0) return A;
   // register-resident panels (one row per thread) up to order GJ_T, else
-  // panels stepped over chunks of rows; width 32
+  // panels stepped over chunks of rows.  Width 32; register panels of
+  // batches small enough for the caches take width 16 (half the
+  // instructions per pivot step, twice the update passes).
   const bool reg = maxs <= GJ_T;
-  const int nb = 32;
+  const int nb = (reg && small_batch) ? 16 : 32;
   const int64_t n0t = std::max<int64_t>(nrow, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
@@ -464,8 +468,12 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
     double* Sk = S;
     if (reg) {
-      ADS_LAUNCH(k_gj_panel_row, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
-                 (int)k0, S, src, tot, flag);
+      if (nb == 16)
+        ADS_LAUNCH(k_gj_panel_row<16>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
+                   (int)k0, S, src, tot, flag);
+      else
+        ADS_LAUNCH(k_gj_panel_row<32>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
+                   (int)k0, S, src, tot, flag);
     } else {
       const dim3 g((unsigned)nchm, (unsigned)nsys);
       ADS_LAUNCH(k_gjc_init, g, dim3(GJ_CH), 0, st, bufs[cur], E_off, sys_coff, (int)k0, nb, S,
