@@ -436,10 +436,10 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   if (maxs <= 0) return A;
   // register-resident panels (one row per thread) up to order GJ_T, else
   // panels stepped over chunks of rows.  Width 32; register panels of
-  // batches small enough for the caches take width 16 (half the
-  // instructions per pivot step, twice the update passes).
+  // batches small enough for the caches take width 8 (a quarter of the
+  // instructions per dependent pivot step, four times the update passes).
   const bool reg = maxs <= GJ_T;
-  const int nb = (reg && small_batch) ? 16 : 32;
+  const int nb = (reg && small_batch) ? 8 : 32;
   const int64_t n0t = std::max<int64_t>(nrow, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
@@ -468,8 +468,8 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
     double* Sk = S;
     if (reg) {
-      if (nb == 16)
-        ADS_LAUNCH(k_gj_panel_row<16>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
+      if (nb == 8)
+        ADS_LAUNCH(k_gj_panel_row<8>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
                    (int)k0, S, src, tot, flag);
       else
         ADS_LAUNCH(k_gj_panel_row<32>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
