@@ -386,8 +386,19 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   double* beta_d = mem.alloc<double>(Q);
   int32_t* act_d = mem.alloc<int32_t>(Q);
   int32_t* cont_d = mem.alloc<int32_t>(Q);  // instances continuing their cycle
-  double* stat_h = c.pin.get((size_t)3 * Q);
-  if (!stat_h) fail(ADS_ERR_OOM, "pinned host memory for the solver status");
+  // two status slots (est | hn | brk each): a speculative step copies into
+  // the other slot while the host reads this one
+  double* stat_pin = c.pin.get((size_t)6 * Q);
+  if (!stat_pin) fail(ADS_ERR_OOM, "pinned host memory for the solver status");
+  hipEvent_t stat_ev[2] = {nullptr, nullptr};
+  struct EventGuard {
+    hipEvent_t* e;
+    ~EventGuard() {
+      for (int k = 0; k < 2; ++k)
+        if (e[k]) (void)hipEventDestroy(e[k]);
+    }
+  } ev_guard{stat_ev};
+  for (int k = 0; k < 2; ++k) ADS_HIP(hipEventCreateWithFlags(&stat_ev[k], hipEventDisableTiming));
   int32_t* endm_d = mem.alloc<int32_t>(Q);
   int32_t* jend_d = mem.alloc<int32_t>(Q);
   int32_t* all_d = mem.alloc<int32_t>(Q);
@@ -441,6 +452,19 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   }
   bool pending = false;  // k_advance / k_next_basis of the last step not yet launched
   std::vector<int32_t> cont_up;
+  // Speculation (one system, one right-hand side): the next step is queued
+  // before the host reads this step's status, so the GPU does not idle
+  // during the round trip.  It is not queued when this step must end the
+  // cycle (restart length, iteration limit) or when the trend of the
+  // residual estimates predicts convergence at this step.  If this step
+  // ends the cycle anyway, the extra step has only written column j + 1 of
+  // V, Z and H, the rotations and g below row j + 1 and w, none of which the
+  // end of the cycle reads (it solves with the first jend columns, from the
+  // host's jend, and recomputes w); the next cycle starts from k_cycle_start.
+  const bool spec_on = Q == 1;
+  int slot = 0;
+  bool inflight = false;  // this step was queued speculatively (status in slot)
+  double est1 = -1.0, est2 = -1.0;  // the last two processed estimates
   auto basis_update = [&]() {
     ADS_LAUNCH(k_advance, dim3((Q + 63) / 64), dim3(64), 0, st, S, cont_d, Q);
     ADS_LAUNCH(k_next_basis, gseg, dim3(256), 0, st, dV, w, I, S.jq, cont_d, S.hn);
@@ -484,34 +508,66 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
       basis_update();
       arnoldi_step();
     };
-    if (use_graph) {
-      hipGraphExec_t& ex = pending ? step_exec2 : step_exec;
-      if (!ex) {
-        c.capturing = true;
-        try {
-          ex = pending ? capture_graph(st, update_and_step) : capture_graph(st, arnoldi_step);
-        } catch (...) {
+    auto launch_step = [&](bool with_update) {
+      if (use_graph) {
+        hipGraphExec_t& ex = with_update ? step_exec2 : step_exec;
+        if (!ex) {
+          c.capturing = true;
+          try {
+            ex = with_update ? capture_graph(st, update_and_step) : capture_graph(st, arnoldi_step);
+          } catch (...) {
+            c.capturing = false;
+            throw;
+          }
           c.capturing = false;
-          throw;
         }
-        c.capturing = false;
+        ADS_HIP(hipGraphLaunch(ex, st));
+      } else if (with_update) {
+        update_and_step();
+      } else {
+        arnoldi_step();
       }
-      ADS_HIP(hipGraphLaunch(ex, st));
-    } else if (pending) {
-      update_and_step();
-    } else {
-      arnoldi_step();
+    };
+    // status of a step (est | hn | brk) through pinned memory
+    auto queue_status = [&](int k) {
+      ADS_HIP(hipMemcpyAsync(stat_pin + (size_t)3 * Q * k, stat, (size_t)3 * Q * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+      ADS_HIP(hipEventRecord(stat_ev[k], st));
+    };
+    if (!inflight) {
+      launch_step(pending);
+      queue_status(slot);
     }
+    inflight = false;
     pending = false;
-    // status of the step (est | hn | brk) through pinned memory
-    ADS_HIP(hipMemcpyAsync(stat_h, stat, (size_t)3 * Q * sizeof(double), hipMemcpyDeviceToHost, st));
-    ADS_HIP(hipStreamSynchronize(st));
+    bool spec = false;
+    if (spec_on && act[0]) {
+      const bool last = jcur[0] + 1 >= m || its[0] + 1 >= (fixed ? fixed : maxit);
+      bool near = false;
+      if (!fixed && est1 >= 0.0 && est2 > 0.0)
+        near = est1 * (est1 / est2) <= 3.0 * ko.rtol * bnorm[0];
+      spec = !last && !near;
+    }
+    if (spec) {
+      if (cont_up.size() != 1 || cont_up[0] != 1) {
+        cont_up.assign(1, 1);
+        ADS_HIP(hipMemcpyAsync(cont_d, cont_up.data(), 4, hipMemcpyHostToDevice, st));
+      }
+      launch_step(true);
+      queue_status(1 - slot);
+    }
+    ADS_HIP(hipEventSynchronize(stat_ev[slot]));
+    const double* stat_h = stat_pin + (size_t)3 * Q * slot;
     std::vector<int32_t> brk(Q);
     for (int q = 0; q < Q; ++q) {
       est[q] = stat_h[q];
       hn[q] = stat_h[Q + q];
     }
     std::memcpy(brk.data(), stat_h + 2 * Q, (size_t)Q * 4);
+    if (spec_on && act[0]) {
+      est2 = est1;
+      est1 = est[0];
+    }
     bool anyend = false;
     for (int q = 0; q < Q; ++q) {
       endm[q] = 0;
@@ -534,6 +590,11 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
     // next basis vector for continuing instances: launched now when a cycle
     // ends (the end-of-cycle residual reuses w), else at the head of the
     // next step's graph
+    if (!anyend && spec) {  // the next step is already queued, with its basis update
+      inflight = true;
+      slot = 1 - slot;
+      continue;
+    }
     std::vector<int32_t> cont(Q, 0);
     for (int q = 0; q < Q; ++q) cont[q] = act[q] && !endm[q];
     if (cont != cont_up) {
