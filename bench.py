@@ -176,6 +176,116 @@ def profile_workload(name, steps, precision):
               file=sys.stderr, flush=True)
 
 
+def config_table(with_oracle):
+    """Setup and solve times of every named workload: GPU plain FP64, GPU
+    mixed precision (FP32 factors; BF16 too for the 3D jumping-coefficient
+    workload), GPU mixed with the learned coarse space (log-normal workload),
+    and the FP64 CPU oracle on one host thread (not for the 3D
+    jumping-coefficient workload, which it needs minutes for).  One JSON line per (workload, form) on stdout; GPU figures are
+    medians of 3 runs after a warm-up run, each creating, solving with and
+    releasing its context."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_02250_amd import ads
+    from workloads.problems import c3b_sizes
+
+    dev = torch.device("cuda:0")
+    here = os.path.dirname(os.path.abspath(__file__))
+    weights = os.path.join(here, "paper_2201_02250_amd", "gnn", "c4_lognormal_nev8.adsgnn")
+    P = {"fp64": ads.ADS_PREC_FP64, "fp32": ads.ADS_PREC_FP32, "bf16": ads.ADS_PREC_BF16}
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    def gpu_rows(name, mk, Bd, restart, flex, forms):
+        for form, kw in forms:
+            t_set, t_sol, its, rel, n0 = [], [], 0, 0.0, 0
+            for rep in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx = mk(**kw)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, info = ctx.solve(Bd, restart=restart, flexible=flex, rtol=1e-8)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                n0 = ctx.info["n0"]
+                ctx.close()
+                if rep == 0:
+                    continue
+                t_set.append(1e3 * (t1 - t0))
+                t_sol.append(1e3 * (t2 - t1))
+                its = max(info["its"])
+                rel = max(info["relres"])
+            emit({"workload": name, "form": form, "setup_ms": round(float(np.median(t_set)), 2),
+                  "solve_ms": round(float(np.median(t_sol)), 2), "its": int(its),
+                  "relres": float(rel), "n0": int(n0)})
+
+    def oracle_row(name, systems, restart, flex):
+        from threadpoolctl import threadpool_limits
+        from oracle import schwarz as OS  # the oracle, timed as it stands
+        t_set = t_sol = 0.0
+        its = 0
+        with threadpool_limits(1):
+            for As, part, N, ov, nev, B in systems:
+                t0 = time.perf_counter()
+                Pc = OS.TwoLevelSchwarz(As, part, N, ov, nev)
+                t1 = time.perf_counter()
+                for j in range(B.shape[1]):
+                    _, io = OS.gmres(As, B[:, j], Pc.apply, restart=restart, rtol=1e-8,
+                                     flexible=flex)
+                    its = max(its, io["its"])
+                t_set += t1 - t0
+                t_sol += time.perf_counter() - t1
+        emit({"workload": name, "form": "oracle", "setup_ms": round(1e3 * t_set, 1),
+              "solve_ms": round(1e3 * t_sol, 1), "its": int(its), "cores": 1})
+
+    for name in ["c1_laplace2d_64_strips8", "c2_convdiff2d_512_blocks64", "c3a_convdiff3d_64_bfs256",
+                 "c3b_convdiff2d_batch32", "c4_lognormal2d_256_blocks64", "c5_jump3d_128_boxes1024"]:
+        if name.startswith("c3b"):
+            sizes = c3b_sizes()
+            As = [W.convdiff2d(m, 0.01) for m in sizes]
+            parts = [W.block_partition_2d(m, max(2, round(m / 32))) for m in sizes]
+            Ns = [max(2, round(m / 32)) ** 2 for m in sizes]
+            b = np.concatenate([W.rhs(A.n, k) for k, A in enumerate(As)])
+            Bd = torch.tensor(b, device=dev)
+            ov, nev, restart, flex = 2, 10, 30, True
+
+            def mk(**kw):
+                return ads.Context(As, parts, Ns, ov, nev, **kw)
+
+            gpu_rows(name, mk, Bd, restart, flex,
+                     [("fp64", dict(precision=P["fp64"])), ("fp32", dict(precision=P["fp32"]))])
+            if with_oracle:
+                offs = np.cumsum([0] + [A.n for A in As])
+                oracle_row(name, [(A.to_scipy(), parts[k], Ns[k], ov, nev,
+                                   b[offs[k]:offs[k + 1], None]) for k, A in enumerate(As)],
+                           restart, flex)
+            continue
+        A, part, N, o = W.config(name)
+        if part is None:
+            part = ads.ads_partition_bfs(A, o["seeds"])
+        Ad = ads.DeviceCSR(A, dev)
+        nrhs = o.get("nrhs", 1)
+        B = np.stack([W.rhs(A.n, s) for s in range(nrhs)], axis=1)
+        Bd = torch.tensor(B if nrhs > 1 else B[:, 0], device=dev)
+
+        def mk(**kw):
+            return ads.Context(Ad, part, N, o["overlap"], o["nev"], **kw)
+
+        forms = [("fp64", dict(precision=P["fp64"])), ("fp32", dict(precision=P["fp32"]))]
+        if name.startswith("c5"):
+            forms.append(("bf16", dict(precision=P["bf16"])))
+        if name.startswith("c4"):
+            forms.append(("fp32+learned", dict(precision=P["fp32"], warm_start=2,
+                                               gnn_weights_path=weights)))
+        gpu_rows(name, mk, Bd, o["restart"], o["flexible"], forms)
+        if with_oracle and not name.startswith("c5"):
+            oracle_row(name, [(A.to_scipy(), part, N, o["overlap"], o["nev"], B)], o["restart"],
+                       o["flexible"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +296,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-apply", action="store_true",
                     help="only run applies and a plain copy (for rocprofv3 --pmc runs)")
+    ap.add_argument("--config-table", action="store_true",
+                    help="only time every named workload (GPU forms and the oracle); JSON lines")
+    ap.add_argument("--no-oracle", action="store_true", help="with --config-table: GPU forms only")
     ap.add_argument("--profile-workload", default=None,
                     help="only run setup+solve of another named workload (profiling driver)")
     args = ap.parse_args()
@@ -195,6 +308,9 @@ def main():
         sys.exit(2)
     if args.pmc_apply:
         pmc_apply(args.apply_reps)
+        return
+    if args.config_table:
+        config_table(not args.no_oracle)
         return
     if args.profile_workload:
         from paper_2201_02250_amd import ads
