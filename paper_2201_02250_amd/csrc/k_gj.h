@@ -17,8 +17,9 @@ namespace {  // one copy of the kernels per translation unit
 // end).  Column blocks of width nb are processed in turn:
 //   panel        : the unblocked Gauss-Jordan steps on the n x nb column
 //                  panel (one workgroup per system with one row per thread up
-//                  to GJ_T rows, else one launch per pivot over chunks of
-//                  rows), recording the pivots; the result S is the panel
+//                  to GJ_T rows, two to four rows per thread up to 4 GJ_T,
+//                  else one launch per pivot over chunks of rows), recording
+//                  the pivots; the result S is the panel
 //                  columns of the accumulated transform, src the composed row
 //                  source map of the block's interchanges;
 //   update kernel: every other column receives the same transform as a rank-nb
@@ -330,6 +331,131 @@ k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff,
   if (live) tot[pos] = tv;
 }
 
+// Register-resident panel for systems of order <= R * GJ_T: as
+// k_gj_panel_row, with R consecutive rows per thread (thread t owns rows
+// t R .. t R + R - 1, so lane order is row order and a tie still goes to the
+// smallest row).  The thread's best candidate is its first row of largest
+// magnitude; the published row is picked from the thread's rows by selects
+// (no dynamic register indexing).
+template <int NB, int R>
+__global__ void __launch_bounds__(GJ_T)
+k_gj_panel_rows(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+                double* Sbuf, int32_t* src_all, int32_t* tot_all, int32_t* singular) {
+  __shared__ double slot_r[2][GJ_T / 64][NB + 1];  // row values, then the key
+  __shared__ int slot_q[2][GJ_T / 64][2];          // physical row, logical position
+  const int sy = blockIdx.x;
+  const int base = sys_coff[sy];
+  const int n = sys_coff[sy + 1] - base;
+  if (k0 >= n) return;
+  const int kb = min(NB, n - k0);
+  const int t = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
+  const int nw = (int)(blockDim.x + 63) >> 6;
+  double v[R][NB];
+  int pos[R];
+  bool live[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = t * R + q;
+    live[q] = i < n;
+    pos[q] = i;
+    const double* A = Ain + E_off[sy] + (int64_t)(live[q] ? i : 0) * n + k0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double a = A[min(j, kb - 1)];  // in bounds for every lane
+      v[q][j] = (live[q] && j < kb) ? a : 0.0;
+    }
+  }
+  bool sing = false;
+  for (int l = 0; l < kb; ++l) {
+    const int k = k0 + l, b = l & 1;
+    double f[R];  // each row's entry in the pivot column
+    double cb = -1.0;
+    int qb = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double x = v[q][0];
+#pragma unroll
+      for (int j = 1; j < NB; ++j) x = j == l ? v[q][j] : x;
+      f[q] = x;
+      double cand = (live[q] && pos[q] >= k) ? fabs(x) : -1.0;
+      if (!(cand >= 0.0)) cand = -1.0;  // NaN never wins
+      if (cand > cb) {
+        cb = cand;
+        qb = q;
+      }
+    }
+    const double m = gj_wave_max(cb);
+    const bool top = cb == m;
+    const unsigned long long hit = __ballot(top);
+    const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(hit >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)hit, 0u));
+    if (top && below == 0) {
+      int pb = pos[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) pb = q == qb ? pos[q] : pb;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double x = v[0][j];
+#pragma unroll
+        for (int q = 1; q < R; ++q) x = q == qb ? v[q][j] : x;
+        slot_r[b][wv][j] = x;
+      }
+      slot_r[b][wv][NB] = m;
+      slot_q[b][wv][0] = t * R + qb;
+      slot_q[b][wv][1] = pb;
+    }
+    __syncthreads();
+    int w = 0;
+    double best = slot_r[b][0][NB];
+    for (int u = 1; u < nw; ++u) {
+      const double kv = slot_r[b][u][NB];
+      if (kv > best) {
+        best = kv;
+        w = u;
+      }
+    }
+    w = __builtin_amdgcn_readfirstlane(w);
+    const double* r = slot_r[b][w];
+    const int prow = slot_q[b][w][0], pq = slot_q[b][w][1];
+    sing |= !(best > 0.0);
+    const double piv = r[l];
+    const double inv = piv != 0.0 ? 1.0 / piv : 1.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const bool me = t * R + q == prow;
+      const double fi = me ? 0.0 : f[q] * inv;  // row minus fi times the pivot row
+      const double sc = me ? inv : 1.0;
+      const double vl = me ? inv : -fi;         // the new pivot-column entry
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const double x = (v[q][j] - fi * r[j]) * sc;
+        v[q][j] = j == l ? vl : x;
+      }
+      pos[q] = me ? k : (pos[q] == k ? pq : pos[q]);
+    }
+  }
+  if (t == 0 && sing) atomicMax(singular, sy + 1);
+  int32_t* tot = tot_all + base;
+  int tv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    tv[q] = 0;
+    if (live[q]) {
+      const int i = t * R + q;
+      double* S = Sbuf + (int64_t)NB * base + (int64_t)pos[q] * NB;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) S[j] = v[q][j];
+      src_all[base + pos[q]] = i;
+      tv[q] = k0 == 0 ? i : tot[i];
+    }
+  }
+  __syncthreads();  // every read of the old cumulative map precedes the writes
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (live[q]) tot[pos[q]] = tv[q];
+}
+
 // out = transform of in for the column block [k0, k0 + kb) (see above), on
 // TL x TL output tiles; each thread accumulates (TL/16)^2 outputs in
 // registers, so every LDS read feeds TL/16 products.  Systems whose order is
@@ -439,7 +565,10 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   // batches small enough for the caches take width 8 (a quarter of the
   // instructions per dependent pivot step, four times the update passes).
   const bool reg = maxs <= GJ_T;
-  const int nb = (reg && small_batch) ? 8 : 32;
+  // orders up to 4 GJ_T: register panels of width 8 with 2-4 rows per thread
+  const int R = reg ? 1 : (int)((maxs + GJ_T - 1) / GJ_T);
+  const bool multi = !reg && R <= 4;
+  const int nb = ((reg && small_batch) || multi) ? 8 : 32;
   const int64_t n0t = std::max<int64_t>(nrow, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
@@ -450,7 +579,7 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   int32_t* swp = nullptr;
   int32_t* tmp = nullptr;
   const int nchm = (int)((maxs + GJ_CH - 1) / GJ_CH);
-  if (!reg) {
+  if (!reg && !multi) {
     S1 = c.mem.alloc<double>(n0t * nb);
     part_v = c.mem.alloc<double>((size_t)2 * nsys * nchm);
     part_i = c.mem.alloc<int32_t>((size_t)2 * nsys * nchm);
@@ -467,7 +596,18 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
     double* Sk = S;
-    if (reg) {
+    if (multi) {
+      const unsigned mrows = (unsigned)(((maxs + R - 1) / R + 63) / 64 * 64);
+      if (R == 2)
+        ADS_LAUNCH((k_gj_panel_rows<8, 2>), dim3(nsys), dim3(mrows), 0, st, bufs[cur], E_off,
+                   sys_coff, (int)k0, S, src, tot, flag);
+      else if (R == 3)
+        ADS_LAUNCH((k_gj_panel_rows<8, 3>), dim3(nsys), dim3(mrows), 0, st, bufs[cur], E_off,
+                   sys_coff, (int)k0, S, src, tot, flag);
+      else
+        ADS_LAUNCH((k_gj_panel_rows<8, 4>), dim3(nsys), dim3(mrows), 0, st, bufs[cur], E_off,
+                   sys_coff, (int)k0, S, src, tot, flag);
+    } else if (reg) {
       if (nb == 8)
         ADS_LAUNCH(k_gj_panel_row<8>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
                    (int)k0, S, src, tot, flag);

@@ -138,15 +138,17 @@ def test_apply_matches_oracle(case, variant):
 
 
 @pytest.mark.parametrize("m,nb,nev,n0", [(96, 12, 7, 1008), (128, 16, 5, 1280), (128, 16, 7, 1792),
-                                          (256, 32, 8, 8192)],
-                         ids=["n0-1008-register-panels", "n0-1280-chunked-panels",
-                              "n0-1792-separate-coarse-product", "n0-8192-wide-update-tiles"])
+                                          (192, 24, 6, 3480), (256, 32, 8, 8192)],
+                         ids=["n0-1008-register-panels", "n0-1280-two-rows-per-thread",
+                              "n0-1792-separate-coarse-product", "n0-3480-four-rows-per-thread",
+                              "n0-8192-chunked-panels"])
 def test_apply_with_large_coarse_systems(m, nb, nev, n0):
     """Coarse systems of order 1008 (16 waves of one-row-per-thread panels),
-    1280 (beyond the register panels: one launch per pivot over chunks of
-    rows), 1792 (E^{-1} beyond 16 MB: y = E^{-1} c formed in a pass of its
-    own) and 8192 (64 x 64 update tiles) on nonsymmetric convection-diffusion,
-    where E needs row interchanges."""
+    1280 (register panels with two rows per thread), 1792 (E^{-1} beyond
+    16 MB: y = E^{-1} c formed in a pass of its own), 3480 (four rows per
+    thread) and 8192 (one launch per pivot over chunks of rows, 64 x 64
+    update tiles) on nonsymmetric convection-diffusion, where E needs row
+    interchanges."""
     A = W.convdiff2d(m, 0.02)
     part = W.block_partition_2d(m, nb)
     N = nb * nb
