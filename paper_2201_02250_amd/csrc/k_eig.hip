@@ -940,18 +940,51 @@ struct EigArgs {
 // Atilde_reg^T l = e_last.  One-off per floating subdomain, single column.
 template <class FT>
 __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const int64_t* lrow,
-                                      const int32_t* lcol, const double* lval, double* x,
+                                      const int32_t* lcol, const double* lval,
+                                      const int32_t* urow, const double* uval,
+                                      const int32_t* drow, const double* dval, double* x,
                                       double* tmp) {
+  // urow / uval: A_k-1,k by column, drow / dval: A_k+1,k by column (NCPL
+  // slots per padded column, rows ascending), or null: one thread then walks
+  // the CSR rows (the same order of the sums)
   const int t = threadIdx.x, T = blockDim.x;
   constexpr int V = adsd::TileV<FT>::V;
+  constexpr int U = 8;  // tile loads in flight per thread
+  constexpr int NC = adsd::NCPL;
   const int64_t TS = adsd::tile_size(s, V);
   const int npad = K * s;
   for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
   __syncthreads();
+  // tmp[r] = sum_cc G(cc, r) v[cc] over cc ascending (G^T v)
+  auto gt_product = [&](const FT* G, const double* v) {
+    for (int r = t; r < s; r += T) {
+      double acc = 0.0;
+      for (int c0 = 0; c0 < s; c0 += U) {
+        double m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = adsd::ld_fac(G, adsd::tile_at(min(c0 + u, s - 1), r, s, V));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (c0 + u < s) acc += m[u] * v[c0 + u];
+      }
+      tmp[r] = acc;
+    }
+  };
   // forward with U^T: w_k = G_k^T (f_k - A_{k-1,k}^T w_{k-1})
   for (int k = 0; k < K; ++k) {
     const int r0 = k * s;
-    if (k > 0 && t == 0) {
+    if (k > 0 && urow) {
+      for (int cc = t; cc < s; cc += T) {
+        const int64_t f = (int64_t)(r0 + cc) * NC;
+        double v = x[r0 + cc];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          const int rw = urow[f + m];
+          if (rw >= 0) v -= uval[f + m] * x[r0 - s + rw];
+        }
+        x[r0 + cc] = v;
+      }
+    } else if (k > 0 && t == 0) {
       for (int rr = 0; rr < s; ++rr) {
         const int r = r0 - s + rr;
         if (r >= n) break;
@@ -962,12 +995,7 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
       }
     }
     __syncthreads();
-    const FT* G = fac + (int64_t)k * 2 * TS;
-    for (int r = t; r < s; r += T) {
-      double acc = 0.0;
-      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, adsd::tile_at(cc, r, s, V)) * x[r0 + cc];
-      tmp[r] = acc;
-    }
+    gt_product(fac + (int64_t)k * 2 * TS, x + r0);
     __syncthreads();
     for (int r = t; r < s; r += T) x[r0 + r] = tmp[r];
     __syncthreads();
@@ -975,25 +1003,33 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
   // backward with L^T: l_k = w_k - G_k^T (A_{k+1,k}^T l_{k+1})
   for (int k = K - 2; k >= 0; --k) {
     const int r0 = k * s;
-    for (int r = t; r < s; r += T) tmp[s + r] = 0.0;
-    __syncthreads();
-    if (t == 0) {
-      for (int rr = 0; rr < s; ++rr) {
-        const int r = r0 + s + rr;
-        if (r >= n) break;
-        for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
-          const int cidx = lcol[q];
-          if (cidx >= r0 && cidx < r0 + s) tmp[s + cidx - r0] += lval[q] * x[r];
+    if (drow) {
+      for (int cc = t; cc < s; cc += T) {
+        const int64_t f = (int64_t)(r0 + cc) * NC;
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          const int rw = drow[f + m];
+          if (rw >= 0) v += dval[f + m] * x[r0 + s + rw];
+        }
+        tmp[s + cc] = v;
+      }
+    } else {
+      for (int r = t; r < s; r += T) tmp[s + r] = 0.0;
+      __syncthreads();
+      if (t == 0) {
+        for (int rr = 0; rr < s; ++rr) {
+          const int r = r0 + s + rr;
+          if (r >= n) break;
+          for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
+            const int cidx = lcol[q];
+            if (cidx >= r0 && cidx < r0 + s) tmp[s + cidx - r0] += lval[q] * x[r];
+          }
         }
       }
     }
     __syncthreads();
-    const FT* G = fac + (int64_t)k * 2 * TS;
-    for (int r = t; r < s; r += T) {
-      double acc = 0.0;
-      for (int cc = 0; cc < s; ++cc) acc += adsd::ld_fac(G, adsd::tile_at(cc, r, s, V)) * tmp[s + cc];
-      tmp[r] = acc;
-    }
+    gt_product(fac + (int64_t)k * 2 * TS, tmp + s);
     __syncthreads();
     for (int r = t; r < s; r += T) x[r0 + r] -= tmp[r];
     __syncthreads();
@@ -1189,7 +1225,12 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
     double* l = a.ell + a.pad_off[i];
     extern __shared__ double dyn[];
     if constexpr (!CPL)  // (with the coupling lists, k_eig_ell has formed l)
-      transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval, l, dyn);
+      transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval,
+                                a.cpl_ok ? a.ucpl_row + a.pad_off[i] * adsd::NCPL : nullptr,
+                                a.cpl_ok ? a.ucpl_val + a.pad_off[i] * adsd::NCPL : nullptr,
+                                a.cpl_ok ? a.lcpl_row + a.pad_off[i] * adsd::NCPL : nullptr,
+                                a.cpl_ok ? a.lcpl_val + a.pad_off[i] * adsd::NCPL : nullptr, l,
+                                dyn);
     double nn = 0.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) nn += l[r] * l[r];
     nn = adsd::block_sum(nn, red);
