@@ -408,8 +408,9 @@ def test_flexible_equals_standard_for_fixed_preconditioner():
 
 
 def test_c1_full_size_converges():
-    """Config C1 end to end: converges to 1e-8, coarse size 8 x 4, solution
-    within kappa * rtol of a sparse direct solve."""
+    """The 64 x 64 Laplacian in 8 strips (overlap 1, nev 4) end to end:
+    converges to 1e-8, coarse size 8 x 4, solution within kappa * rtol of a
+    sparse direct solve."""
     A, part, N, opts = W.config("c1_laplace2d_64_strips8")
     As = A.to_scipy()
     b = W.rhs(A.n, 0)
