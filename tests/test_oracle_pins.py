@@ -423,3 +423,124 @@ def test_c1_full_size_converges():
     # the coarse space helps: one-level RAS needs more iterations
     x1, info1, _ = OS.solve(As, b, part, N, opts["overlap"], 0, restart=30, rtol=1e-8, variant="ras")
     assert info1["its"] > info["its"]
+
+
+# ---------------------------------------------------------------------------
+# eq. 1 - eq. 4 as explicit matrices, and the tau rule of eq. 6
+# ---------------------------------------------------------------------------
+
+VARIANTS = [("asm", "asm"), ("ras", "ras"), ("additive-asm", "additive"),
+            ("additive-ras", "additive_ras"), ("deflated", "deflated")]
+
+
+def _golden_matrix(g, key):
+    n = int(g["n"][0])
+    return np.array(g[key]).reshape(n, n) / g[key + "_den"][0]
+
+
+def _dense_variant(D, variant):
+    return {"asm": D.M_asm, "ras": D.M_ras, "additive-asm": D.M_additive,
+            "additive-ras": lambda: D.coarse() + D.M_ras(), "deflated": D.M_deflated}[variant]()
+
+
+@pytest.mark.parametrize("variant,key", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_golden_1d_variants(golden, variant, key):
+    """Both tiers reproduce the hand-derived matrices of eq. 1 (ASM), eq. 3
+    (RAS), eq. 2 (additive two-level), the additive restricted form and eq. 4
+    (deflated) on the 1D two-part example, and the coarse correction
+    R_0^H A_00^{-1} R_0 (nev = 1)."""
+    g = golden("oned_two_parts_variants.txt")
+    n = int(g["n"][0])
+    A = sp.csr_matrix(lap1d(n))
+    part = np.array(g["part"], dtype=np.int32)
+    ref = _golden_matrix(g, key)
+    P = OS.TwoLevelSchwarz(A, part, 2, 1, 1, variant=variant)
+    np.testing.assert_allclose(P.apply(np.eye(n)), ref, rtol=0, atol=1e-14)
+    D = OD.DenseSchwarz(A, part, 2, 1, 1)
+    np.testing.assert_allclose(_dense_variant(D, variant), ref, rtol=0, atol=1e-14)
+    Q = _golden_matrix(g, "coarse")
+    np.testing.assert_allclose(D.coarse(), Q, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(P.coarse_correction(np.eye(n)) if P.n0 else Q, Q, rtol=0, atol=1e-14)
+
+
+def test_golden_1d_tau_selection(golden):
+    """eq. 6: nev caps the count (with the cluster rule), tau keeps only
+    |lambda| > 1/tau.  Both tiers, all hand-derived cases; the tau = 0.3 space
+    gives the nev = 1 preconditioner and an empty selection gives eq. 3."""
+    g = golden("oned_two_parts_variants.txt")
+    n = int(g["n"][0])
+    A = sp.csr_matrix(lap1d(n))
+    part = np.array(g["part"], dtype=np.int32)
+    lam_all = np.array(g["lambda_all"])
+    for key in ["select_a", "select_b", "select_c", "select_d", "select_e", "select_f"]:
+        nev, tau, want = int(g[key][0]), g[key][1], int(g[key][2])
+        P = OS.TwoLevelSchwarz(A, part, 2, 1, nev, tau=tau)
+        assert list(P.nev_i) == [want, want], key
+        D = OD.DenseSchwarz(A, part, 2, 1, nev, tau=tau)
+        assert [e["Z"].shape[1] for e in D.eig] == [want, want], key
+        assert len(OS.select_eigenvalues(lam_all, nev, tau)) == want, key
+        for e in D.eig:
+            assert np.abs(e["lam_all"].imag).max() < 1e-12
+            np.testing.assert_allclose(np.sort(e["lam_all"].real)[::-1], lam_all, rtol=0, atol=1e-12)
+            assert np.all(np.abs(e["lam_sel"]) > 1.0 / tau) if tau > 0 else True
+    nev, tau, want = int(g["select_g"][0]), g["select_g"][1], int(g["select_g"][2])
+    assert len(OS.select_eigenvalues(lam_all, nev, tau)) == want
+    r = np.eye(n)
+    P = OS.TwoLevelSchwarz(A, part, 2, 1, 3, tau=0.3)
+    np.testing.assert_allclose(P.apply(r), _golden_matrix(g, "deflated"), rtol=0, atol=1e-14)
+    P = OS.TwoLevelSchwarz(A, part, 2, 1, 3, tau=0.2)
+    assert P.n0 == 0
+    np.testing.assert_allclose(P.apply(r), _golden_matrix(g, "ras"), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", PROBLEMS, ids=[p[0] for p in PROBLEMS])
+def test_variants_tiers_agree(case):
+    """The scalable tier's eq. 1, eq. 2 and additive restricted applies equal
+    the dense tier's explicit matrices (sums of R_i^T A_ii^{-1} R_i formed with
+    dense inverses) on every small problem."""
+    name, A, part, N, delta, nev = case
+    D = OD.DenseSchwarz(A, part, N, delta, nev)
+    r = np.random.default_rng(4).standard_normal((A.shape[0], 2))
+    for variant in ("asm", "additive-asm", "additive-ras"):
+        P = OS.TwoLevelSchwarz(A, part, N, delta, nev, variant=variant)
+        Md = _dense_variant(D, variant)
+        ref = Md @ r
+        np.testing.assert_allclose(P.apply(r), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def _tau_between(lam_sel, nev):
+    """A threshold 1/tau halfway (in |lambda|) between two well separated
+    consecutive selected eigenvalues, or None."""
+    mags = np.sort(np.abs(lam_sel))[::-1]
+    for k in range(1, len(mags)):
+        if mags[k] < 0.9 * mags[k - 1]:
+            return 2.0 / (mags[k] + mags[k - 1])
+    return None
+
+
+@pytest.mark.parametrize("case", PROBLEMS, ids=[p[0] for p in PROBLEMS])
+def test_tau_selection_tiers_agree(case):
+    """tau cut inside the selected spectrum: QZ on the restricted pencil (dense
+    tier) and ARPACK on T (scalable tier) keep the same eigenvalues and span,
+    all of them with |lambda| > 1/tau, and the applies of eq. 4 agree."""
+    name, A, part, N, delta, nev = case
+    D0 = OD.DenseSchwarz(A, part, N, delta, nev)
+    taus = [t for t in (_tau_between(e["lam_sel"], nev) for e in D0.eig) if t]
+    if not taus:
+        pytest.skip("no well separated pair in the selected spectra")
+    tau = float(np.median(taus))
+    D = OD.DenseSchwarz(A, part, N, delta, nev, tau=tau)
+    P = OS.TwoLevelSchwarz(A, part, N, delta, nev, tau=tau)
+    assert P.n0 == D.n0 < D0.n0
+    for i in range(N):
+        e_d, e_s = D.eig[i], P.eig[i]
+        assert e_d["Z"].shape[1] == e_s["Z"].shape[1]
+        assert np.all(np.abs(e_s["lam_sel"]) > 1.0 / tau)
+        lam_full = np.abs(D0.eig[i]["lam_sel"])
+        assert len(e_d["lam_sel"]) == int(np.sum(lam_full > 1.0 / tau))
+        assert_same_eigs(e_d["lam_sel"], e_s["lam_sel"], 1e-9)
+        if e_d["Z"].shape[1]:
+            assert sla.subspace_angles(e_d["Z"], e_s["Z"]).max() < 1e-8
+    r = np.random.default_rng(5).standard_normal(A.shape[0])
+    ref = D.M_deflated() @ r
+    np.testing.assert_allclose(P.apply(r), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
