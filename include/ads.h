@@ -53,10 +53,19 @@ enum {
   ADS_ERR_UNSUPPORTED = -7   /* valid input outside what this build implements    */
 };
 
-/* preconditioner variants (Section 2) */
+/* preconditioner variants (Section 2).  R0^T A00^{-1} R0 is the coarse
+ * correction with the coarse space of eq. 6; M_RAS^{-1} = sum_i R_i^T D_i
+ * A_ii^{-1} R_i (eq. 3) and M_ASM^{-1} = sum_i R_i^T A_ii^{-1} R_i (eq. 1).
+ * The non-restricted forms sum the overlapping local solutions of every
+ * subdomain that contains a row, in ascending subdomain order. */
 enum {
-  ADS_VARIANT_DEFLATED = 0,  /* eq. 4: R0^T A00^{-1} R0 + M_RAS^{-1}(I - A R0^T A00^{-1} R0) */
-  ADS_VARIANT_RAS = 1        /* eq. 3: one-level restricted additive Schwarz (no coarse space) */
+  ADS_VARIANT_DEFLATED = 0,     /* eq. 4: R0^T A00^{-1} R0 + M_RAS^{-1}(I - A R0^T A00^{-1} R0) */
+  ADS_VARIANT_RAS = 1,          /* eq. 3: one-level restricted additive Schwarz (no coarse space) */
+  ADS_VARIANT_ASM = 2,          /* eq. 1: one-level additive Schwarz (no coarse space)          */
+  ADS_VARIANT_ADDITIVE = 3,     /* eq. 2: R0^T A00^{-1} R0 + M_ASM^{-1}, the additive two-level
+                                   preconditioner of the condition bound of Section 3.2        */
+  ADS_VARIANT_ADDITIVE_RAS = 4  /* R0^T A00^{-1} R0 + M_RAS^{-1}: eq. 2 with the restricted
+                                   one-level part                                              */
 };
 
 /* storage precision of the local factors and of the eigensolver operator */

@@ -21,7 +21,7 @@ ADS_MAX_RESULTS = 64
 ADS_OK, ADS_KSP_MAXIT, ADS_KSP_BREAKDOWN = 0, 1, 2
 ADS_ERR_ARG, ADS_ERR_HIP, ADS_ERR_OOM, ADS_ERR_SINGULAR = -1, -2, -3, -4
 ADS_ERR_EIG_NOCONV, ADS_ERR_NAN, ADS_ERR_UNSUPPORTED = -5, -6, -7
-ADS_VARIANT_DEFLATED, ADS_VARIANT_RAS = 0, 1
+ADS_VARIANT_DEFLATED, ADS_VARIANT_RAS, ADS_VARIANT_ASM, ADS_VARIANT_ADDITIVE, ADS_VARIANT_ADDITIVE_RAS = 0, 1, 2, 3, 4
 ADS_PREC_FP64, ADS_PREC_FP32, ADS_PREC_BF16 = 0, 1, 2
 ADS_EIG_KRYLOV_SCHUR, ADS_EIG_SUBSPACE = 0, 1
 

@@ -1,33 +1,48 @@
 """Build the ads HIP library (libads.so) for gfx950 with hipcc.
 
 Usage: python -m paper_2201_02250_amd.build   (or build() from Python)
-The shared library is written next to this file, in-tree."""
+Every translation unit is compiled to an object in parallel (objects in a
+scratch folder), then linked; the shared library is written next to this
+file, in-tree."""
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libads.so")
 SOURCES = ["ads_api.hip", "k_maps.hip", "k_extract.hip", "k_factor.hip", "k_eig.hip",
            "k_coarse.hip", "k_apply.hip", "k_krylov.hip", "k_gnn.hip", "tune.hip"]
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 
 
-def build(verbose=False):
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(HERE, "..", "include"),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libads.so")
-    os.replace(tmp, OUT)
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose=False, jobs=None):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
+    with tempfile.TemporaryDirectory(prefix="ads_build_") as tmpd:
+        objs = [os.path.join(tmpd, s.replace(".hip", ".o")) for s in SOURCES]
+        cmds = [[hipcc, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o]
+                for s, o in zip(SOURCES, objs)]
+        with cf.ThreadPoolExecutor(jobs) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = OUT + ".tmp"
+        _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+        os.replace(tmp, OUT)
     return OUT
 
 

@@ -171,6 +171,26 @@ __global__ void k_import_csr(const int64_t* rp, const int32_t* ci, const double*
   }
 }
 
+// *asym = 1 unless every stored a_rc has a stored a_cr of the same value
+// (columns sorted within rows: binary search in row c)
+__global__ void k_check_symmetric(const int32_t* rowptr, const int32_t* col, const double* val,
+                                  int64_t n, int32_t* asym) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+    const int c = col[k];
+    int lo = rowptr[c], hi = rowptr[c + 1];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (col[mid] < r) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= rowptr[c + 1] || col[lo] != r || val[lo] != val[k]) {
+      atomicOr(asym, 1);
+      return;
+    }
+  }
+}
+
 static void import_csr(Ctx& c, const ads_csr& A, int64_t r0, int64_t k0, int32_t* bad,
                        hipStream_t st) {
   const int64_t* rp = A.row_ptr;
@@ -194,7 +214,7 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
   if (opts->abi_version != ADS_ABI_VERSION) fail(ADS_ERR_ARG, "abi_version mismatch");
   if (opts->overlap < 0 || opts->overlap > 16) fail(ADS_ERR_ARG, "overlap must be in [0, 16]");
   if (opts->nev < 0 || opts->nev > 30) fail(ADS_ERR_ARG, "nev must be in [0, 30]");
-  if (opts->variant != ADS_VARIANT_DEFLATED && opts->variant != ADS_VARIANT_RAS)
+  if (opts->variant < ADS_VARIANT_DEFLATED || opts->variant > ADS_VARIANT_ADDITIVE_RAS)
     fail(ADS_ERR_ARG, "unknown variant");
   if (opts->precision < ADS_PREC_FP64 || opts->precision > ADS_PREC_BF16)
     fail(ADS_ERR_ARG, "unknown precision");
@@ -255,6 +275,11 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
       ADS_HIP(hipStreamSynchronize(st));
       if (h & 8) fail(ADS_ERR_NAN, "non-finite matrix entry");
       if (h) fail(ADS_ERR_ARG, "invalid CSR (row pointers, column range or column order)");
+      ADS_LAUNCH(k_check_symmetric, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, st,
+                 c->rowptr, c->col, c->val, c->n, bad);
+      ADS_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
+      ADS_HIP(hipStreamSynchronize(st));
+      c->sym = h == 0;
     }
     c->sub_sys_d = upload(c->mem, c->sub_sys.data(), c->nsub, st);
     c->t_phase_ms[5] += tm.lap();
@@ -266,7 +291,7 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->t_phase_ms[7] = tm.lap();
     factor_local(*c);
     c->t_phase_ms[2] = tm.lap();
-    const bool coarse = opts->variant == ADS_VARIANT_DEFLATED && opts->nev > 0;
+    const bool coarse = variant_has_coarse(opts->variant) && opts->nev > 0;
     if (coarse) {
       if (opts->warm_start) {
         learned_start(*c);
@@ -286,6 +311,7 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
       c->n0 = 0;
       c->h_nev.assign(c->nsub, 0);
     }
+    if (!variant_restricted(opts->variant)) build_cover(*c);
     ensure_work(*c, 1);
     ADS_HIP(hipStreamSynchronize(st));
     c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

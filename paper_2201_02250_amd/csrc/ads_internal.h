@@ -13,6 +13,15 @@
 
 namespace ads {
 
+// the variants of Section 2 that carry the coarse space of eq. 6, and those
+// whose local part keeps only the owner rows (Boolean partition of unity)
+inline bool variant_has_coarse(int v) {
+  return v == ADS_VARIANT_DEFLATED || v == ADS_VARIANT_ADDITIVE || v == ADS_VARIANT_ADDITIVE_RAS;
+}
+inline bool variant_restricted(int v) {
+  return v == ADS_VARIANT_DEFLATED || v == ADS_VARIANT_RAS || v == ADS_VARIANT_ADDITIVE_RAS;
+}
+
 struct Error {
   int code;
   std::string msg;
@@ -189,6 +198,7 @@ struct Ctx {
   double* lcpl_val = nullptr;
   bool cpl_ok = false;              // all four lists complete (<= NCPL per row / column)
   bool solve_fast = false;          // every subdomain fits the prefetching tile solve
+  bool sym = false;                 // A equals A^T entry for entry (pattern and values)
   void* facA = nullptr;             // factors of A_ii (apply)
   void* facT = nullptr;             // factors of the regularised splitting (eigensolver)
   int prec = ADS_PREC_FP64;
@@ -219,6 +229,8 @@ struct Ctx {
   int h_eig_nqblk = 0;  // wide row blocks of the Krylov-Schur block QR kernels
 
   // workspace for apply / solve
+  int32_t* cover_ptr = nullptr;  // [n + 1] non-restricted variants: per global row, the
+  int32_t* cover_idx = nullptr;  //   padded local slots (pad_off[i] + local row), ascending i
   double* work = nullptr;   // padded local vectors, npad_total * work_cols
   double* work2 = nullptr;  // backward results of the two-ended solve, same shape
   double* dummy = nullptr;  // per-thread discard slots of the tile solves
@@ -309,6 +321,9 @@ void factor_local(Ctx& c, bool only_a = false);
 void eigensolve(Ctx& c);
 void assemble_coarse(Ctx& c);
 void ensure_work(Ctx& c, int cols);
+// row -> local-solution slots of every subdomain containing the row (eq. 1
+// and eq. 2 prolongation), built once per context
+void build_cover(Ctx& c);
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);
 
 // Capture the launches of f on stream s (not the null stream) into an

@@ -12,6 +12,13 @@
 //
 // Three launches per apply.  With the Boolean partition of unity every global
 // row is written by exactly one subdomain, so no atomics are needed.
+//
+// The other variants of Section 2 reuse the same kernels: eq. 3 (RAS) skips
+// the coarse part; the additive forms (eq. 2 and its restricted version) form
+// q = R_0^T A_00^{-1} R_0 r but solve the local problems on r itself; eq. 1
+// and eq. 2 prolong every local solution on all of Omega_i, summed per global
+// row over the subdomains that contain it in ascending order (k_prolong_sum,
+// from a row -> slots map built once).
 #include <algorithm>
 #include <type_traits>
 
@@ -368,7 +375,7 @@ k_local_fwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ 
 template <class FT, int P, int D>
 __global__ void __launch_bounds__(adsd::SOLVE_T)
 k_local_bwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ q,
-            double* __restrict__ z, int nrhs) {
+            double* __restrict__ z, int nrhs) {  // z = nullptr: no owner scatter
   extern __shared__ double lds[];
   const int i = blockIdx.x, half = blockIdx.z;
   const int j0 = blockIdx.y * P;
@@ -390,14 +397,16 @@ k_local_bwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ 
                                      dummy);
   __syncthreads();
   const int lo = half ? (M + 1) * s : 0, hi = min(ns, half ? K * s : (M + 1) * s);
-  if (lo < hi) scatter_local(om, a.om_int + base, lo, hi, q, z, a.n, j0, pc, Xo, a.ldw);
+  if (z && lo < hi) scatter_local(om, a.om_int + base, lo, hi, q, z, a.n, j0, pc, Xo, a.ldw);
 }
 
-// general path (any block size / coupling count)
+// general path (any block size / coupling count); qg enters the residual
+// gather t = r - A qg, qs the owner scatter z = qs + x (z = nullptr: none)
 template <class FT, int P>
 __global__ void __launch_bounds__(APPLY_T)
 k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
-              const double* __restrict__ q, double* __restrict__ z, int nrhs) {
+              const double* __restrict__ qg, const double* __restrict__ qs,
+              double* __restrict__ z, int nrhs) {
   extern __shared__ double lds[];
   const int i = blockIdx.x;
   const int j0 = blockIdx.y * P;
@@ -407,14 +416,91 @@ k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict_
   const int64_t base = a.om_off[i];
   const int32_t* om = a.om_sorted + base;
   double* X = a.work + a.pad_off[i] + (int64_t)j0 * a.ldw;
-  gather_local<P>(om, ns, 0, npad, a.rowptr, a.col, a.val, r, q, a.n, j0, pc, X, a.ldw);
+  gather_local<P>(om, ns, 0, npad, a.rowptr, a.col, a.val, r, qg, a.n, j0, pc, X, a.ldw);
   __syncthreads();
   const int64_t cb = a.pad_off[i] * adsd::NCPL;
   adsd::block_solve_general<FT, P>(fac + a.fac_off[i], s, K, ns, a.lrow + base, a.lcol, a.lval,
                                    a.cpl_ok ? a.cpl_col + cb : nullptr,
                                    a.cpl_ok ? a.cpl_val + cb : nullptr, X,
                                    a.ldw, pc, lds);
-  scatter_local(om, a.om_int + base, 0, ns, q, z, a.n, j0, pc, X, a.ldw);
+  if (z) scatter_local(om, a.om_int + base, 0, ns, qs, z, a.n, j0, pc, X, a.ldw);
+}
+
+// eq. 1 / eq. 2 prolongation: z(g) = qs(g) + sum over the subdomains i that
+// contain g (ascending i) of x_i at g's local slot
+__global__ void __launch_bounds__(256)
+k_prolong_sum(int64_t n, const int32_t* __restrict__ cptr, const int32_t* __restrict__ cidx,
+              const double* __restrict__ X, int64_t ldw, const double* __restrict__ qs,
+              double* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (g >= n) return;
+  double v = qs ? qs[(int64_t)j * n + g] : 0.0;
+  const double* Xj = X + (int64_t)j * ldw;
+  for (int p = cptr[g]; p < cptr[g + 1]; ++p) v += Xj[cidx[p]];
+  z[(int64_t)j * n + g] = v;
+}
+
+// the row -> slots map: counts, offsets by scan, fill, then each row's short
+// list sorted (slots grow with the subdomain index)
+__global__ void k_cover_count(const int64_t* __restrict__ om_off, const int32_t* __restrict__ ni,
+                              const int32_t* __restrict__ om_sorted, int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x;
+  const int32_t* om = om_sorted + om_off[i];
+  for (int lr = blockIdx.y * blockDim.x + threadIdx.x; lr < ni[i]; lr += gridDim.y * blockDim.x)
+    atomicAdd(&cnt[om[lr]], 1);
+}
+
+__global__ void k_cover_fill(const int64_t* __restrict__ om_off, const int32_t* __restrict__ ni,
+                             const int32_t* __restrict__ om_sorted, const int64_t* __restrict__ pad_off,
+                             const int32_t* __restrict__ cptr, int32_t* __restrict__ fill,
+                             int32_t* __restrict__ cidx) {
+  const int i = blockIdx.x;
+  const int32_t* om = om_sorted + om_off[i];
+  for (int lr = blockIdx.y * blockDim.x + threadIdx.x; lr < ni[i]; lr += gridDim.y * blockDim.x) {
+    const int g = om[lr];
+    const int k = atomicAdd(&fill[g], 1);
+    cidx[cptr[g] + k] = (int32_t)(pad_off[i] + lr);
+  }
+}
+
+__global__ void k_cover_sort(int64_t n, const int32_t* __restrict__ cptr, int32_t* __restrict__ cidx) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  int32_t* a = cidx + cptr[g];
+  const int m = cptr[g + 1] - cptr[g];
+  for (int k = 1; k < m; ++k) {
+    const int32_t v = a[k];
+    int q = k - 1;
+    while (q >= 0 && a[q] > v) {
+      a[q + 1] = a[q];
+      --q;
+    }
+    a[q + 1] = v;
+  }
+}
+
+void build_cover(Ctx& c) {
+  hipStream_t st = c.stream;
+  if (c.npad_total >= ((int64_t)1 << 31)) fail(ADS_ERR_UNSUPPORTED, "local vectors too long");
+  int maxn = 1;
+  for (int i = 0; i < c.nsub; ++i) maxn = std::max(maxn, c.h_ni[i]);
+  const dim3 g(c.nsub, (unsigned)((maxn + 255) / 256));
+  int32_t* cnt = c.mem.alloc<int32_t>(c.n + 1);
+  ADS_HIP(hipMemsetAsync(cnt, 0, (c.n + 1) * 4, st));
+  ADS_LAUNCH(k_cover_count, g, dim3(256), 0, st, c.om_off, c.ni, c.om_sorted, cnt);
+  c.cover_ptr = c.mem.alloc<int32_t>(c.n + 1);
+  exclusive_scan_i32(cnt, c.cover_ptr, c.n + 1, c.mem, st);
+  int32_t total = 0;
+  ADS_HIP(hipMemcpyAsync(&total, c.cover_ptr + c.n, 4, hipMemcpyDeviceToHost, st));
+  ADS_HIP(hipStreamSynchronize(st));
+  c.cover_idx = c.mem.alloc<int32_t>(std::max<int32_t>(total, 1));
+  ADS_HIP(hipMemsetAsync(cnt, 0, (c.n + 1) * 4, st));
+  ADS_LAUNCH(k_cover_fill, g, dim3(256), 0, st, c.om_off, c.ni, c.om_sorted, c.pad_off, c.cover_ptr,
+             cnt, c.cover_idx);
+  ADS_LAUNCH(k_cover_sort, dim3((unsigned)((c.n + 255) / 256)), dim3(256), 0, st, c.n, c.cover_ptr,
+             c.cover_idx);
+  c.mem.release(cnt);
 }
 
 void ensure_work(Ctx& c, int cols) {
@@ -470,9 +556,12 @@ static LocalArgs local_args(Ctx& c) {
   return a;
 }
 
+// the local solves of one apply: gather t = r - A qg (qg may be null), solve,
+// and scatter z = qs + x on the owner rows (z = nullptr: the solutions stay
+// in the work buffers for k_prolong_sum)
 template <class FT>
-static void local_dispatch(Ctx& c, const double* r, const double* q, double* z, int nrhs,
-                           hipStream_t s) {
+static void local_dispatch(Ctx& c, const double* r, const double* qg, const double* qs, double* z,
+                           int nrhs, hipStream_t s) {
   LocalArgs a = local_args(c);
   constexpr int D = 2;
   constexpr int DM = 2;  // multi-column variants: shallower prefetch, fewer registers
@@ -483,9 +572,9 @@ static void local_dispatch(Ctx& c, const double* r, const double* q, double* z, 
       const size_t lds = (size_t)adsd::solve_lds_doubles<P>(c.h_bs, adsd::SOLVE_T) * 8;
       const dim3 grid(c.nsub, (nrhs + P - 1) / P, 2);
       ADS_LAUNCH((k_local_fwd<FT, P, DD>), grid, dim3(adsd::SOLVE_T), lds, s, (const FT*)c.facA, a,
-                 r, q, nrhs);
+                 r, qg, nrhs);
       ADS_LAUNCH((k_local_bwd<FT, P, DD>), grid, dim3(adsd::SOLVE_T), lds, s, (const FT*)c.facA, a,
-                 q, z, nrhs);
+                 qs, z, nrhs);
     };
     if (nrhs == 1)
       run(std::integral_constant<int, 1>(), std::integral_constant<int, D>());
@@ -498,11 +587,11 @@ static void local_dispatch(Ctx& c, const double* r, const double* q, double* z, 
   if (nrhs == 1) {
     size_t lds = (size_t)adsd::solve_lds_doubles_general<1>(c.h_bs, APPLY_T) * 8;
     ADS_LAUNCH((k_local_solve<FT, 1>), dim3(c.nsub, 1), dim3(APPLY_T), lds, s, (const FT*)c.facA, a,
-               r, q, z, nrhs);
+               r, qg, qs, z, nrhs);
   } else {
     size_t lds = (size_t)adsd::solve_lds_doubles_general<8>(c.h_bs, APPLY_T) * 8;
     ADS_LAUNCH((k_local_solve<FT, 8>), dim3(c.nsub, (nrhs + 7) / 8), dim3(APPLY_T), lds, s,
-               (const FT*)c.facA, a, r, q, z, nrhs);
+               (const FT*)c.facA, a, r, qg, qs, z, nrhs);
   }
 }
 
@@ -520,9 +609,9 @@ double time_local_solve(Ctx& c, int reps) {
   ADS_HIP(hipMemsetAsync(q, 0, c.n * 8, st));
   auto run = [&]() {
     switch (c.prec) {
-      case ADS_PREC_FP64: local_dispatch<double>(c, r, q, z, 1, st); break;
-      case ADS_PREC_FP32: local_dispatch<float>(c, r, q, z, 1, st); break;
-      default: local_dispatch<__hip_bfloat16>(c, r, q, z, 1, st); break;
+      case ADS_PREC_FP64: local_dispatch<double>(c, r, q, q, z, 1, st); break;
+      case ADS_PREC_FP32: local_dispatch<float>(c, r, q, q, z, 1, st); break;
+      default: local_dispatch<__hip_bfloat16>(c, r, q, q, z, 1, st); break;
     }
   };
   run();
@@ -625,12 +714,21 @@ static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStrea
     }
     q = c.qvec;
   }
-  ProfScope p0(c, 0, s);
-  switch (c.prec) {
-    case ADS_PREC_FP64: local_dispatch<double>(c, r, q, z, nrhs, s); break;
-    case ADS_PREC_FP32: local_dispatch<float>(c, r, q, z, nrhs, s); break;
-    default: local_dispatch<__hip_bfloat16>(c, r, q, z, nrhs, s); break;
+  // eq. 4 solves the local problems on r - A q; the additive forms on r
+  const double* qg = c.opt.variant == ADS_VARIANT_DEFLATED ? q : nullptr;
+  const bool restricted = variant_restricted(c.opt.variant);
+  double* zs = restricted ? z : nullptr;
+  {
+    ProfScope p0(c, 0, s);
+    switch (c.prec) {
+      case ADS_PREC_FP64: local_dispatch<double>(c, r, qg, q, zs, nrhs, s); break;
+      case ADS_PREC_FP32: local_dispatch<float>(c, r, qg, q, zs, nrhs, s); break;
+      default: local_dispatch<__hip_bfloat16>(c, r, qg, q, zs, nrhs, s); break;
+    }
   }
+  if (!restricted)
+    ADS_LAUNCH(k_prolong_sum, dim3((unsigned)((c.n + 255) / 256), nrhs), dim3(256), 0, s, c.n,
+               c.cover_ptr, c.cover_idx, c.solve_fast ? c.work2 : c.work, c.npad_total, q, z);
 }
 
 hipStream_t Ctx::own_stream() {

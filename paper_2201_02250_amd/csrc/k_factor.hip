@@ -593,39 +593,57 @@ k_bf_build(BfArgs a, int k, int splitting, double* D, const double* Pp) {
   }
 }
 
+// G_k = D_k^{-1} (row-major, from the batched inversion) and P_k = G_k
+// A_k,k+1 into the packed tiles, and P_k (FP64, row-major) for the next block
+// step.  One workgroup per (subdomain, rb rows): the rows of G_k are read
+// into LDS with coalesced loads, P_k's rows are formed there from the column
+// coupling list (at most NCPL entries per column of A_k,k+1), and both tiles
+// are written in their packed order, where the rb rows of one 16-byte column
+// group are contiguous.
 template <class FT>
 __global__ void __launch_bounds__(256)
-k_bf_store(BfArgs a, int k, const double* Ginv, double* Pp, FT* fac) {
+k_bf_store(BfArgs a, int k, const double* Ginv, double* Pp, FT* fac, int rb) {
+  extern __shared__ double sh[];
   const int i = blockIdx.x;
   const int s = a.bs[i], K = a.nb[i];
-  if (k >= K) return;
+  const int r0 = blockIdx.y * rb;
+  if (k >= K || r0 >= s) return;
+  const int nr = min(rb, s - r0);
   constexpr int V = adsd::TileV<FT>::V;
   const int64_t TS = adsd::tile_size(s, V);
-  const double* G = Ginv + a.d_off[i];
-  double* P = Pp + a.d_off[i];
-  FT* Gt = fac + a.fac_off[i] + (int64_t)k * 2 * TS;
+  const int nq = (s + V - 1) / V;
+  double* Gs = sh;
+  double* Ps = sh + (int64_t)rb * s;
+  const double* G = Ginv + a.d_off[i] + (int64_t)r0 * s;
+  for (int e = threadIdx.x; e < nr * s; e += blockDim.x) Gs[e] = G[e];
+  __syncthreads();
   const bool more = k + 1 < K;
-  const int64_t cbase = a.pad_off[i] + (int64_t)(k + 1) * s;  // padded columns of block k + 1
-  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < TS;
-       e += (int64_t)gridDim.y * blockDim.x) {
-    const int v = (int)(e % V);
-    const int64_t rest = e / V;
-    const int r = (int)(rest % s), cidx = (int)(rest / s) * V + v;
-    const bool in = cidx < s;
-    adsd::st_fac(Gt, e, in ? G[(int64_t)r * s + cidx] : 0.0);
-    if (more) {
+  if (more) {
+    const int64_t cbase = a.pad_off[i] + (int64_t)(k + 1) * s;  // padded columns of block k + 1
+    double* P = Pp + a.d_off[i] + (int64_t)r0 * s;
+    for (int e = threadIdx.x; e < nr * s; e += blockDim.x) {
+      const int rr = e / s, cidx = e % s;
+      const int64_t fc = (cbase + cidx) * adsd::NCPL;
       double pv = 0.0;
-      if (in) {
-        const int64_t fc = (cbase + cidx) * adsd::NCPL;
 #pragma unroll
-        for (int m = 0; m < adsd::NCPL; ++m) {
-          const int rw = a.ucpl_row[fc + m];
-          if (rw >= 0) pv += G[(int64_t)r * s + rw] * a.ucpl_val[fc + m];
-        }
-        P[(int64_t)r * s + cidx] = pv;
+      for (int m = 0; m < adsd::NCPL; ++m) {
+        const int rw = a.ucpl_row[fc + m];
+        if (rw >= 0) pv += Gs[rr * s + rw] * a.ucpl_val[fc + m];
       }
-      adsd::st_fac(Gt + TS, e, pv);
+      Ps[e] = pv;
+      P[e] = pv;
     }
+    __syncthreads();
+  }
+  FT* Gt = fac + a.fac_off[i] + (int64_t)k * 2 * TS;
+  const int run = nr * V;  // contiguous entries per column group
+  for (int e = threadIdx.x; e < nq * run; e += blockDim.x) {
+    const int q = e / run, rem = e % run, rr = rem / V, v = rem % V;
+    const int cidx = q * V + v;
+    const int64_t dst = ((int64_t)q * s + r0 + rr) * V + v;
+    const bool in = cidx < s;
+    adsd::st_fac(Gt, dst, in ? Gs[rr * s + cidx] : 0.0);
+    if (more) adsd::st_fac(Gt + TS, dst, in ? Ps[rr * s + cidx] : 0.0);
   }
 }
 
@@ -639,14 +657,12 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   std::vector<int64_t> hd(nsub + 1, 0);
   std::vector<int32_t> hs(nsub + 1, 0);
   int smax = 0, kmax = 0;
-  int64_t tsmax = 0;
   for (int i = 0; i < nsub; ++i) {
     const int b = c.h_bs[i];
     hd[i + 1] = hd[i] + (int64_t)b * b;
     hs[i + 1] = hs[i] + b;
     smax = std::max(smax, b);
     kmax = std::max(kmax, (int)c.h_nb[i]);
-    tsmax = std::max(tsmax, adsd::tile_size(b, V));
   }
   int64_t* d_off = upload(c.mem, hd.data(), nsub + 1, st);
   int32_t* s_off = upload(c.mem, hs.data(), nsub + 1, st);
@@ -658,11 +674,22 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   BfArgs a{c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
            c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, d_off};
   const dim3 gb(nsub, (unsigned)((smax + BF_RB - 1) / BF_RB));
-  const dim3 gs(nsub, (unsigned)std::max<int64_t>(1, (tsmax + 1023) / 1024));
+  // rows of G_k per workgroup of the store pass: G and P rows in LDS
+  const int rb = std::max(1, std::min(8, 10240 / std::max(smax, 1)));
+  const dim3 gs(nsub, (unsigned)((smax + rb - 1) / rb));
+  const size_t st_lds = (size_t)2 * rb * smax * 8;
   for (int k = 0; k < kmax; ++k) {
     ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
-    double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad);
-    ADS_LAUNCH((k_bf_store<FT>), gs, dim3(256), 0, st, a, k, inv, Pp, fac);
+    // symmetric A: the D_k are symmetric positive definite (Schur complements
+    // of the SPD local matrices), inverted without interchanges; a pivot that
+    // is not positive sends this block step back to partial pivoting
+    double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad,
+                                    c.sym);
+    if (!inv) {
+      ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
+      inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad);
+    }
+    ADS_LAUNCH((k_bf_store<FT>), gs, dim3(256), st_lds, st, a, k, inv, Pp, fac, rb);
   }
   std::vector<int32_t> hb;
   download(hb, bad, 1, st);
@@ -689,7 +716,7 @@ void factor_local(Ctx& c, bool only_a) {
     c.h_fac_off[i + 1] = c.h_fac_off[i] + (int64_t)2 * c.h_nb[i] * adsd::tile_size(c.h_bs[i], V);
   c.fac_elems = c.h_fac_off[nsub];
   c.fac_off = upload(c.mem, c.h_fac_off.data(), nsub + 1, c.stream);
-  const bool need_split = !only_a && c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0;
+  const bool need_split = !only_a && variant_has_coarse(c.opt.variant) && c.opt.nev > 0;
   size_t esz = c.prec == ADS_PREC_FP64 ? 8 : (c.prec == ADS_PREC_FP32 ? 4 : 2);
   c.factor_bytes = (int64_t)(c.fac_elems * esz);
   if (c.solve_fast) {  // two-ended layout, read by the fast solves

@@ -17,171 +17,37 @@ namespace {  // one copy of the kernels per translation unit
 // end).  Column blocks of width nb are processed in turn:
 //   panel        : the unblocked Gauss-Jordan steps on the n x nb column
 //                  panel (one workgroup per system with one row per thread up
-//                  to GJ_T rows, two to four rows per thread up to 4 GJ_T,
-//                  else one launch per pivot over chunks of rows), recording
-//                  the pivots; the result S is the panel
+//                  to GJ_T rows, two to four rows per thread up to 4 GJ_T),
+//                  or, for larger systems, the panel's pivot rows chosen by
+//                  tournament pivoting and its transform formed in parallel
+//                  (see k_tslu); the result S is the panel
 //                  columns of the accumulated transform, src the composed row
 //                  source map of the block's interchanges;
 //   update kernel: every other column receives the same transform as a rank-nb
 //                  product, out(i, j) = in(src i, j) + sum_l (S(i,l) - [i = k0+l]) in(src(k0+l), j),
 //                  written to the other buffer of a ping-pong pair (no in-place
-//                  races between tiles); the panel columns receive S.
+//                  races between tiles); the panel columns receive S.  Large
+//                  batches run it on the matrix cores (k_gj_update_mfma).
 // Every reduction has a fixed order, so the result is deterministic.
 // ---------------------------------------------------------------------------
 static constexpr int GJ_T = 1024;
 static constexpr int GJ_UT = 256;
 static constexpr int GJ_TILE = 32;
-static constexpr int GJ_CH = 256;  // rows per workgroup of the chunked panel
 
-// (value, index) max with ties to the smaller index; NaN never wins
-__device__ __forceinline__ void gj_better(double& bv, int& bi, double v, int i) {
-  if (v > bv || (v == bv && i < bi)) {
-    bv = v;
-    bi = i;
-  }
-}
+// x if keep, else 0, as arithmetic on a value that was loaded from an
+// always-valid (clamped) address: the load stays unconditional, so the
+// compiler issues all the loads of a tile back to back instead of one
+// branch (and one wait) per masked load
+__device__ __forceinline__ double gj_keep(double x, bool keep) { return x * (keep ? 1.0 : 0.0); }
 
-// Panels of systems above GJ_T rows: one launch per pivot step over chunks
-// of GJ_CH rows (grid: chunks x systems).  The panel alternates between two
-// buffers (step l reads P[l & 1] and writes P[(l + 1) & 1], rows in the
-// logical order of the block: the pivot row and row k trade places), so no
-// workgroup reads a row that another one writes.  Every workgroup reduces
-// the previous step's per-chunk (|entry|, row) maxima in the same order, and
-// so takes the same pivot, then publishes the maxima of its own rows for the
-// next column.  Steps past a system's last column copy its panel, so that
-// every system's panel ends in the same buffer.
-
-// block-wide (value, index) maximum, ties to the smaller index; the result
-// is valid in thread 0
-__device__ __forceinline__ void gj_block_best(double& bv, int& bi, double* sv, int* si) {
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(bv, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    gj_better(bv, bi, ov, oi);
-  }
-  const int t = threadIdx.x;
-  if ((t & 63) == 0) {
-    sv[t >> 6] = bv;
-    si[t >> 6] = bi;
-  }
-  __syncthreads();
-  if (t == 0)
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) gj_better(bv, bi, sv[w], si[w]);
-}
-
-// panel columns [k0, k0 + nb) of the input into P0; maxima of column k0
-__global__ void __launch_bounds__(GJ_CH)
-k_gjc_init(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int nb,
-           double* P0, double* part_v, int* part_i, int nchm, int nsys) {
-  __shared__ double sv[GJ_CH / 64];
-  __shared__ int si[GJ_CH / 64];
-  const int sy = blockIdx.y, ch = blockIdx.x;
-  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
-  if (k0 >= n || ch * GJ_CH >= n) return;
-  const int kb = min(nb, n - k0);
-  const int i = ch * GJ_CH + threadIdx.x;
-  double bv = -1.0;
-  int bi = n;
-  if (i < n) {
-    const double* a = Ain + E_off[sy] + (int64_t)i * n + k0;
-    double* p = P0 + ((int64_t)base + i) * nb;
-    for (int l = 0; l < nb; ++l) p[l] = l < kb ? a[l] : 0.0;
-    if (i >= k0) gj_better(bv, bi, fabs(a[0]), i);
-  }
-  gj_block_best(bv, bi, sv, si);
-  if (threadIdx.x == 0) {
-    part_v[(int64_t)sy * nchm + ch] = bv;
-    part_i[(int64_t)sy * nchm + ch] = bi;
-  }
-}
-
-// pivot step l (column k0 + l) of every system's panel
-__global__ void __launch_bounds__(GJ_CH)
-k_gjc_step(const int32_t* sys_coff, int k0, int nb, int l, double* P0, double* P1,
-           double* part_v, int* part_i, int nchm, int nsys, int32_t* swp, int32_t* singular) {
-  constexpr int NB = 32;
-  __shared__ double rowk[NB], rowkold[NB];
-  __shared__ double sv[GJ_CH / 64];
-  __shared__ int si[GJ_CH / 64];
-  __shared__ int sp;
-  const int sy = blockIdx.y, ch = blockIdx.x, t = threadIdx.x;
-  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
-  if (k0 >= n || ch * GJ_CH >= n) return;
-  const int kb = min(nb, n - k0);
-  const int nch = (n + GJ_CH - 1) / GJ_CH;
-  const double* Pin = (l & 1) ? P1 : P0;
-  double* Pout = (l & 1) ? P0 : P1;
-  const int i = ch * GJ_CH + t;
-  if (l >= kb) {  // past this system's last column: carry the panel over
-    if (i < n)
-      for (int j = 0; j < nb; ++j) Pout[((int64_t)base + i) * nb + j] = Pin[((int64_t)base + i) * nb + j];
-    return;
-  }
-  const int k = k0 + l;
-  const int64_t pin = (int64_t)(l & 1) * nsys * nchm, pout = (int64_t)((l + 1) & 1) * nsys * nchm;
-  if (t < 64) {  // the pivot: maximum of the previous step's chunk maxima
-    double bv = -1.0;
-    int bi = n;
-    for (int c = t; c < nch; c += 64)
-      gj_better(bv, bi, part_v[pin + (int64_t)sy * nchm + c], part_i[pin + (int64_t)sy * nchm + c]);
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      gj_better(bv, bi, ov, oi);
-    }
-    if (t == 0) {
-      int p = bi;
-      if (!(bv > 0.0) || p >= n) {
-        if (ch == 0) atomicMax(singular, sy + 1);
-        p = k;
-      }
-      sp = p;
-      if (ch == 0) swp[sy * NB + l] = p;
-    }
-  }
-  __syncthreads();
-  const int p = sp;
-  if (t < nb) {
-    rowk[t] = Pin[((int64_t)base + p) * nb + t];
-    rowkold[t] = Pin[((int64_t)base + k) * nb + t];
-  }
-  __syncthreads();
-  double bv = -1.0;
-  int bi = n;
-  if (i < n) {
-    const double* src = Pin + ((int64_t)base + i) * nb;
-    double v[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double x = i == k ? rowk[j] : (i == p ? rowkold[j] : src[min(j, nb - 1)]);
-      v[j] = j < nb ? x : 0.0;
-    }
-    double f = v[0];  // this row's entry in the pivot column
-#pragma unroll
-    for (int j = 1; j < NB; ++j) f = j == l ? v[j] : f;
-    const double piv = rowk[l];
-    const double d = piv != 0.0 ? 1.0 / piv : 1.0;
-    double* dst = Pout + ((int64_t)base + i) * nb;
-    double nxt = 0.0;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double w;
-      if (i == k)
-        w = j == l ? d : v[j] * d;
-      else
-        w = j == l ? -f * d : v[j] - f * (rowk[j] * d);
-      if (j < nb) dst[j] = w;
-      nxt = j == l + 1 ? w : nxt;
-    }
-    if (i > k && l + 1 < kb) gj_better(bv, bi, fabs(nxt), i);
-  }
-  if (l + 1 < kb) {
-    gj_block_best(bv, bi, sv, si);
-    if (t == 0) {
-      part_v[pout + (int64_t)sy * nchm + ch] = bv;
-      part_i[pout + (int64_t)sy * nchm + ch] = bi;
-    }
-  }
+// a per-lane (vector register) copy of a workgroup-uniform loop index: the
+// column selects "j == l" of the unrolled row updates then compile to lane
+// selects instead of one uniform branch per column, and the pivot row's LDS
+// reads are no longer split by those branches (one wait each)
+__device__ __forceinline__ int gj_lane_copy(int x) {
+  int y;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
+  return y;
 }
 
 // the block's composed row sources and the cumulative row map
@@ -200,7 +66,7 @@ k_gjc_fini(const int32_t* sys_coff, int k0, int nb, const int32_t* swp, int32_t*
   __syncthreads();
   if (t == 0)
     for (int l = 0; l < kb; ++l) {
-      const int k = k0 + l, p = swp[sy * 32 + l];
+      const int k = k0 + l, p = swp[sy * nb + l];
       const int a = src[k];
       src[k] = src[p];
       src[p] = a;
@@ -238,20 +104,21 @@ __device__ __forceinline__ double gj_wave_max(double x) {
   return fmax(fmax(gj_lane(x, 0), gj_lane(x, 16)), fmax(gj_lane(x, 32), gj_lane(x, 48)));
 }
 
-// Register-resident panel for systems of order <= GJ_T (panel width 32):
-// thread i owns row i of the n x 32 column panel (rows in the logical order
+// Register-resident panel for systems of order <= T threads (panel width NB:
+// 8 or 32 with 1024 threads, 64 with 512 threads so that the 64 entries of a
+// row stay in registers): thread i owns row i of the n x NB column panel (rows in the logical order
 // that the previous panels left) and tracks the logical position of that
 // row; rows never move.  One barrier per pivot step: every wave publishes its
 // best pivot candidate (largest |entry| in the pivot column among the rows
 // not yet used, ties to the smaller row) together with that row's values in
 // a double-buffered LDS slot, and every thread then takes the first slot of
 // largest magnitude.  The result S is written in logical row order.
-template <int NB>
-__global__ void __launch_bounds__(GJ_T)
+template <int NB, int T = GJ_T>
+__global__ void __launch_bounds__(T)
 k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
                double* Sbuf, int32_t* src_all, int32_t* tot_all, int32_t* singular) {
-  __shared__ double slot_r[2][GJ_T / 64][NB + 1];  // row values, then the key
-  __shared__ int slot_q[2][GJ_T / 64][2];          // physical row, logical position
+  __shared__ double slot_r[2][T / 64][NB + 1];  // row values, then the key
+  __shared__ int slot_q[2][T / 64][2];          // physical row, logical position
   const int sy = blockIdx.x;
   const int base = sys_coff[sy];
   const int n = sys_coff[sy + 1] - base;
@@ -264,17 +131,15 @@ k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff,
   const double* A = Ain + E_off[sy] + (int64_t)(live ? i : 0) * n + k0;
   double v[NB];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const double a = A[min(j, kb - 1)];  // in bounds for every lane
-    v[j] = (live && j < kb) ? a : 0.0;
-  }
+  for (int j = 0; j < NB; ++j) v[j] = gj_keep(A[min(j, kb - 1)], live && j < kb);
   int pos = i;
   bool sing = false;
   for (int l = 0; l < kb; ++l) {
     const int k = k0 + l, b = l & 1;
+    const int lv = gj_lane_copy(l);
     double f = v[0];  // this row's entry in the pivot column
 #pragma unroll
-    for (int j = 1; j < NB; ++j) f = j == l ? v[j] : f;
+    for (int j = 1; j < NB; ++j) f = j == lv ? v[j] : f;
     double cand = (live && pos >= k) ? fabs(f) : -1.0;
     if (!(cand >= 0.0)) cand = -1.0;  // NaN never wins
     const double m = gj_wave_max(cand);
@@ -313,7 +178,7 @@ k_gj_panel_row(const double* Ain, const int64_t* E_off, const int32_t* sys_coff,
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const double x = (v[j] - fi * r[j]) * sc;
-      v[j] = j == l ? vl : x;
+      v[j] = j == lv ? vl : x;
     }
     pos = me ? k : (pos == k ? pq : pos);
   }
@@ -361,14 +226,12 @@ k_gj_panel_rows(const double* Ain, const int64_t* E_off, const int32_t* sys_coff
     pos[q] = i;
     const double* A = Ain + E_off[sy] + (int64_t)(live[q] ? i : 0) * n + k0;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double a = A[min(j, kb - 1)];  // in bounds for every lane
-      v[q][j] = (live[q] && j < kb) ? a : 0.0;
-    }
+    for (int j = 0; j < NB; ++j) v[q][j] = gj_keep(A[min(j, kb - 1)], live[q] && j < kb);
   }
   bool sing = false;
   for (int l = 0; l < kb; ++l) {
     const int k = k0 + l, b = l & 1;
+    const int lv = gj_lane_copy(l);
     double f[R];  // each row's entry in the pivot column
     double cb = -1.0;
     int qb = 0;
@@ -376,7 +239,7 @@ k_gj_panel_rows(const double* Ain, const int64_t* E_off, const int32_t* sys_coff
     for (int q = 0; q < R; ++q) {
       double x = v[q][0];
 #pragma unroll
-      for (int j = 1; j < NB; ++j) x = j == l ? v[q][j] : x;
+      for (int j = 1; j < NB; ++j) x = j == lv ? v[q][j] : x;
       f[q] = x;
       double cand = (live[q] && pos[q] >= k) ? fabs(x) : -1.0;
       if (!(cand >= 0.0)) cand = -1.0;  // NaN never wins
@@ -430,7 +293,7 @@ k_gj_panel_rows(const double* Ain, const int64_t* E_off, const int32_t* sys_coff
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const double x = (v[q][j] - fi * r[j]) * sc;
-        v[q][j] = j == l ? vl : x;
+        v[q][j] = j == lv ? vl : x;
       }
       pos[q] = me ? k : (pos[q] == k ? pq : pos[q]);
     }
@@ -528,6 +391,405 @@ k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form of the update (large batches and large systems): the
+// same transform as k_gj_update on 64 x 64 output tiles, computed with
+// v_mfma_f64_16x16x4f64.  The workgroup stages S' = S - [i = k0 + l] (its 64
+// rows, kb <= 64 columns) and the kb source rows R = in(src(k0 + l), :) of
+// its 64 columns in LDS once; wave w owns the 32 x 32 quarter (w / 2, w % 2)
+// as 2 x 2 blocks of 16 x 16, whose accumulators start from in(src(i), j).
+// Operand layouts of the instruction (16 x 4 by 4 x 16): lane l holds
+// A(l % 16, l / 16) and B(l / 16, l % 16); accumulator register r of lane l
+// holds D(l / 16 + 4 r, l % 16).  The sum over l runs in steps of four in a
+// fixed order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+static constexpr int GM_T = 256;
+static constexpr int GM_K = 64;   // panel columns staged per pass (panels up to 2 GM_K wide)
+static constexpr int GM_SLD = GM_K + 1;
+static constexpr int GM_RLD = 64 + 4;
+
+// 64 x 64 tile (i0, j0) of the update, K = kb <= 2 GM_K columns of the panel
+// taken in passes of GM_K through LDS; the loads of a pass are all issued
+// before its first LDS store
+__global__ void __launch_bounds__(GM_T)
+k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff,
+                 int k0, int nb, const double* Sbuf, const int32_t* src_all) {
+  __shared__ double Ssh[64 * GM_SLD];
+  __shared__ double Rsh[GM_K * GM_RLD];
+  __shared__ int srow[64];
+  __shared__ int rsrc[2 * GM_K];
+  const int sy = blockIdx.z;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  if (i0 >= n || j0 >= n) return;
+  const double* A = Ain + E_off[sy];
+  double* B = Aout + E_off[sy];
+  const int t = threadIdx.x;
+  if (k0 >= n) {
+    for (int e = t; e < 64 * 64; e += GM_T) {
+      const int i = i0 + e / 64, j = j0 + e % 64;
+      if (i < n && j < n) B[(int64_t)i * n + j] = A[(int64_t)i * n + j];
+    }
+    return;
+  }
+  const int kb = min(nb, n - k0);
+  const double* S = Sbuf + (int64_t)nb * sys_coff[sy];
+  const int32_t* src = src_all + sys_coff[sy];
+  if (t < 2 * GM_K) rsrc[t] = t < kb ? src[k0 + t] : 0;
+  if (t < 64) srow[t] = (i0 + t < n) ? src[i0 + t] : 0;
+  __syncthreads();
+  const int w = t >> 6, lane = t & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int NQ = 64 * GM_K / GM_T;
+  double sv[NQ], rv[NQ];
+  // pass 0 of the panel, issued together with the accumulators' loads
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int r = (t >> 6) + (GM_T / 64) * q, l = t & 63;
+    const int i = i0 + r, j = j0 + l;
+    sv[q] = gj_keep(S[(int64_t)min(i, n - 1) * nb + min(l, kb - 1)], i < n && l < kb);
+    rv[q] = gj_keep(A[(int64_t)rsrc[min(r, kb - 1)] * n + min(j, n - 1)], r < kb && j < n);
+  }
+  gj_d4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ri = wr + bi * 16 + lk + 4 * r;
+        const int i = i0 + ri, j = j0 + wc + bj * 16 + li;
+        acc[bi][bj][r] = gj_keep(A[(int64_t)srow[ri] * n + min(j, n - 1)], i < n && j < n);
+      }
+  for (int kc = 0; kc < kb; kc += GM_K) {
+    if (kc > 0) {
+      __syncthreads();  // the previous pass's LDS reads are done
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int r = (t >> 6) + (GM_T / 64) * q, l = t & 63;
+        const int i = i0 + r, j = j0 + l;
+        sv[q] = gj_keep(S[(int64_t)min(i, n - 1) * nb + min(kc + l, kb - 1)], i < n && kc + l < kb);
+        rv[q] = gj_keep(A[(int64_t)rsrc[min(kc + r, kb - 1)] * n + min(j, n - 1)],
+                        kc + r < kb && j < n);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = (t >> 6) + (GM_T / 64) * q, l = t & 63;
+      Ssh[r * GM_SLD + l] = sv[q] - ((kc + l < kb && i0 + r == k0 + kc + l) ? 1.0 : 0.0);
+      Rsh[r * GM_RLD + l] = rv[q];
+    }
+    __syncthreads();
+    const int kp = min(GM_K, (kb - kc + 3) & ~3);
+    for (int kk = 0; kk < kp; kk += 4) {
+      const double a0 = Ssh[(wr + li) * GM_SLD + kk + lk];
+      const double a1 = Ssh[(wr + 16 + li) * GM_SLD + kk + lk];
+      const double b0 = Rsh[(kk + lk) * GM_RLD + wc + li];
+      const double b1 = Rsh[(kk + lk) * GM_RLD + wc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  // the panel columns receive S: only the tiles that hold them (a uniform
+  // test) load it, so the other tiles store without waiting on loads
+  // (no load between the stores: every store would otherwise wait for the
+  // one before it)
+  const bool touch = j0 < k0 + kb && j0 + 64 > k0;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + bi * 16 + lk + 4 * r, j = j0 + wc + bj * 16 + li;
+        if (i < n && j < n && !(j >= k0 && j < k0 + kb)) B[(int64_t)i * n + j] = acc[bi][bj][r];
+      }
+  if (touch)
+    for (int e = t; e < 64 * 64; e += GM_T) {
+      const int i = i0 + e / 64, j = j0 + e % 64;
+      if (i < n && j < n && j >= k0 && j < k0 + kb) B[(int64_t)i * n + j] = S[(int64_t)i * nb + (j - k0)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Panels of large systems (order above 4 GJ_T): the kb pivot rows of the
+// panel are chosen by tournament pivoting (communication-avoiding LU of the
+// tall n x kb panel: Grigori, Demmel and Xiang, 2011) instead of one launch
+// per pivot, then the panel's transform is formed in parallel:
+//   k_tslu          partial-pivoting LU on groups of up to TS_T candidate
+//                   rows (one row per thread, the panel entries in registers)
+//                   keeps each group's kb pivot rows; level 0 takes the rows
+//                   not yet used as pivots in chunks of TS_T, later levels
+//                   merge TS_G groups' winners, until one group is left;
+//   k_gj_block_inv  the kb x kb block of the winners (in pick order) is
+//                   inverted by Gauss-Jordan without further interchanges
+//                   (the pick order is a partial-pivoting order for it, so
+//                   every multiplier is at most 1 in magnitude), and
+//   k_gj_pick_swaps turns the picks into the sequential interchanges of
+//                   the block (row k0 + l with the l-th pick's current row);
+//   k_gj_panel_form the panel columns of the block transform: the inverse on
+//                   the pivot rows, -a_i P^{-1} on every other row.
+// The update and the row maps are the ones of the other panel forms.
+// ---------------------------------------------------------------------------
+static constexpr int TS_T = 256;
+static constexpr int TS_NB = 64;
+static constexpr int TS_G = TS_T / TS_NB;  // groups merged per workgroup
+
+// groups of system sy's candidates at tournament level lev (0: leaves)
+__device__ __host__ inline int ts_groups(int n, int k0, int lev) {
+  int g = (n - k0 + TS_T - 1) / TS_T;
+  for (int v = 0; v < lev; ++v) g = (g + TS_G - 1) / TS_G;
+  return g;
+}
+
+__global__ void __launch_bounds__(TS_T)
+k_tslu(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0, int lev,
+       const int32_t* cin, int32_t* cout, int gstride) {
+  __shared__ double slot_r[2][TS_T / 64][TS_NB + 1];
+  __shared__ int slot_q[2][TS_T / 64];
+  const int sy = blockIdx.y, g = blockIdx.x, t = threadIdx.x;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  if (k0 >= n) return;
+  const int ng = ts_groups(n, k0, lev);
+  if (g >= ng) return;
+  const int kb = min(TS_NB, n - k0);
+  int32_t* out = cout + ((int64_t)sy * gstride + g) * TS_NB;
+  int id = -1;
+  if (lev == 0) {
+    const int i = k0 + g * TS_T + t;
+    id = i < n ? i : -1;
+  } else {
+    const int ngin = ts_groups(n, k0, lev - 1);
+    if (ngin == 1) {  // already one group: carry it over
+      if (t < TS_NB) out[t] = cin[(int64_t)sy * gstride * TS_NB + t];
+      return;
+    }
+    const int gi = g * TS_G + t / TS_NB;
+    if (gi < ngin) id = cin[((int64_t)sy * gstride + gi) * TS_NB + t % TS_NB];
+  }
+  const double* row = Ain + E_off[sy] + (int64_t)(id >= 0 ? id : 0) * n + k0;
+  double v[TS_NB];
+#pragma unroll
+  for (int j = 0; j < TS_NB; ++j) v[j] = gj_keep(row[min(j, kb - 1)], id >= 0 && j < kb);
+  bool alive = id >= 0;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  int picked = 0;
+  bool done = false;  // uniform: no nonzero candidate left
+#pragma unroll
+  for (int l = 0; l < TS_NB; ++l) {
+    if (l >= kb || done) continue;  // uniform; the loop stays fully unrolled
+    const int b = l & 1;
+    double cand = alive ? fabs(v[l]) : -1.0;
+    if (!(cand >= 0.0)) cand = -1.0;  // NaN never wins
+    const double m = gj_wave_max(cand);
+    const bool top = cand == m;
+    const unsigned long long hit = __ballot(top);
+    const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(hit >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)hit, 0u));
+    if (top && below == 0) {
+#pragma unroll
+      for (int j = l; j < TS_NB; ++j) slot_r[b][wv][j] = v[j];
+      slot_r[b][wv][TS_NB] = m;
+      slot_q[b][wv] = t;
+    }
+    __syncthreads();
+    int w = 0;
+    double best = slot_r[b][0][TS_NB];
+#pragma unroll
+    for (int u = 1; u < TS_T / 64; ++u) {
+      const double kv = slot_r[b][u][TS_NB];
+      if (kv > best) {
+        best = kv;
+        w = u;
+      }
+    }
+    w = __builtin_amdgcn_readfirstlane(w);
+    if (!(best > 0.0)) {  // no nonzero candidate left in this column
+      done = true;
+      continue;
+    }
+    const double* r = slot_r[b][w];
+    const int q = slot_q[b][w];
+    if (t == q) {
+      out[l] = id;
+      alive = false;
+    }
+    picked = l + 1;
+    const double f = v[l] / r[l];
+#pragma unroll
+    for (int j = l + 1; j < TS_NB; ++j) v[j] -= f * r[j];
+  }
+  for (int l = picked + t; l < TS_NB; l += TS_T) out[l] = -1;
+}
+
+// Inverse of the kb x kb pivot block P(l, j) = in(row_l, k0 + j), kb <= NBK,
+// by Gauss-Jordan elimination without interchanges: row_l = picks[l] (the
+// tournament's pick order, in which every multiplier is at most 1 in
+// magnitude) or, with picks = nullptr, row k0 + l (symmetric positive
+// definite systems, whose pivots stay positive without interchanges).  256
+// threads; thread t owns the NBK/16 x NBK/16 block (t / 16, t % 16) in
+// registers; per step the pivot row and column go through a double-buffered
+// LDS slot (one barrier per step).  Rows and columns past kb are the
+// identity.  A pivot that is not finite, zero, or (spd = 1) not positive sets
+// *bad to sy + 1.  Pinv[sy] is NBK x NBK, row-major.
+template <int NBK>
+__global__ void __launch_bounds__(256)
+k_gj_block_inv(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+               const int32_t* picks, int pstride, int spd, double* Pinv, int32_t* bad) {
+  constexpr int Q = NBK / 16;
+  __shared__ double prow[2][NBK], pcol[2][NBK];
+  const int sy = blockIdx.x, t = threadIdx.x;
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  if (k0 >= n) return;
+  const int kb = min(NBK, n - k0);
+  const int br = t >> 4, bc = t & 15;
+  const double* A = Ain + E_off[sy];
+  double a[Q][Q];
+#pragma unroll
+  for (int ii = 0; ii < Q; ++ii) {
+    const int l = Q * br + ii;
+    int row = -1;
+    if (l < kb) row = picks ? picks[(int64_t)sy * pstride + l] : k0 + l;
+#pragma unroll
+    for (int jj = 0; jj < Q; ++jj) {
+      const int j = Q * bc + jj;
+      const bool in = l < kb && j < kb;
+      const double x = gj_keep(A[(int64_t)max(row, 0) * n + k0 + min(j, kb - 1)], in && row >= 0);
+      a[ii][jj] = in ? x : (l == j ? 1.0 : 0.0);
+    }
+  }
+  bool sing = false;
+  for (int m = 0; m < kb; ++m) {
+    const int b = m & 1;
+    if (br == m / Q)
+#pragma unroll
+      for (int ii = 0; ii < Q; ++ii)
+        if (Q * br + ii == m)
+#pragma unroll
+          for (int jj = 0; jj < Q; ++jj) prow[b][Q * bc + jj] = a[ii][jj];
+    if (bc == m / Q)
+#pragma unroll
+      for (int jj = 0; jj < Q; ++jj)
+        if (Q * bc + jj == m)
+#pragma unroll
+          for (int ii = 0; ii < Q; ++ii) pcol[b][Q * br + ii] = a[ii][jj];
+    __syncthreads();
+    const double piv = prow[b][m];
+    sing |= !(fabs(piv) < INFINITY) || (spd ? !(piv > 0.0) : !(piv != 0.0));
+    const double inv = piv != 0.0 ? 1.0 / piv : 1.0;
+    double pr[Q];
+#pragma unroll
+    for (int jj = 0; jj < Q; ++jj) pr[jj] = prow[b][Q * bc + jj];
+#pragma unroll
+    for (int ii = 0; ii < Q; ++ii) {
+      const int i = Q * br + ii;
+      const double f = pcol[b][i] * inv;
+#pragma unroll
+      for (int jj = 0; jj < Q; ++jj) {
+        const int j = Q * bc + jj;
+        const double x = a[ii][jj];
+        double y;
+        if (i == m)
+          y = j == m ? inv : x * inv;
+        else
+          y = j == m ? -f : x - f * pr[jj];
+        a[ii][jj] = y;
+      }
+    }
+  }
+  double* out = Pinv + (int64_t)sy * NBK * NBK;
+#pragma unroll
+  for (int ii = 0; ii < Q; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < Q; ++jj) out[(Q * br + ii) * NBK + Q * bc + jj] = a[ii][jj];
+  if (t == 0 && sing) atomicMax(bad, sy + 1);
+}
+
+// the tournament's picks as sequential interchanges: swp[sy nb + l] = the
+// row that trades places with row k0 + l (the l-th pick, moved by the
+// earlier trades of the block); one thread per system
+__global__ void k_gj_pick_swaps(const int32_t* sys_coff, int k0, const int32_t* picks, int pstride,
+                                int32_t* swp, int32_t* singular) {
+  const int sy = blockIdx.x;
+  if (threadIdx.x != 0 || sys_coff[sy + 1] - sys_coff[sy] <= k0) return;
+  const int kb = min(TS_NB, sys_coff[sy + 1] - sys_coff[sy] - k0);
+  const int32_t* P = picks + (int64_t)sy * pstride;
+  bool sing = false;
+  for (int a = 0; a < kb; ++a) {
+    sing |= P[a] < 0;
+    int cur = P[a] >= 0 ? P[a] : k0 + a;
+    for (int b = 0; b < a; ++b) {
+      const int pb = swp[sy * TS_NB + b];
+      if (cur == k0 + b)
+        cur = pb;
+      else if (cur == pb)
+        cur = k0 + b;
+    }
+    swp[sy * TS_NB + a] = cur;
+  }
+  if (sing) atomicMax(singular, sy + 1);
+}
+
+// S(i, :) of the block transform in the block's row order (src from the row
+// maps): P^{-1} on the pivot rows k0 .. k0 + kb, -in(src(i), panel) P^{-1} on
+// the others, as a matrix-core product: 64 rows (one 16-row slab per wave)
+// by 64 columns of S per workgroup (blockIdx.z picks the column half when
+// NBK = 128); the slab of P^{-1} sits in LDS.  S has row stride NBK.
+template <int NBK>
+__global__ void __launch_bounds__(256)
+k_gj_panel_form(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+                const double* Pinv, const int32_t* src_all, double* Sbuf) {
+  constexpr int LD = 64 + 4;
+  __shared__ double Ps[NBK * LD];
+  const int sy = blockIdx.y, t = threadIdx.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  const int i0 = blockIdx.x * 64, c0 = blockIdx.z * 64;
+  if (k0 >= n || i0 >= n) return;
+  const int kb = min(NBK, n - k0);
+  const double* Pi = Pinv + (int64_t)sy * NBK * NBK;
+  for (int e = t; e < NBK * 64; e += 256) Ps[(e >> 6) * LD + (e & 63)] = Pi[(e >> 6) * NBK + c0 + (e & 63)];
+  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int ia = i0 + 16 * w + li;  // this lane's row of the A operand
+  const double* arow = Ain + E_off[sy] + (int64_t)(ia < n ? src_all[base + ia] : 0) * n + k0;
+  double av[NBK / 4];
+#pragma unroll
+  for (int q = 0; q < NBK / 4; ++q) {
+    const int l = 4 * q + lk;
+    av[q] = gj_keep(arow[min(l, kb - 1)], ia < n && l < kb);
+  }
+  __syncthreads();
+  gj_d4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = gj_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NBK / 4; ++q) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], Ps[(4 * q + lk) * LD + 16 * c + li],
+                                                    acc[c], 0, 0, 0);
+  }
+  double* S = Sbuf + (int64_t)NBK * base;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 16 * w + lk + 4 * r, j = c0 + 16 * c + li;
+      if (i >= n) continue;
+      double v;
+      if (j >= kb)
+        v = 0.0;
+      else if (i >= k0 && i < k0 + kb)
+        v = Ps[(i - k0) * LD + 16 * c + li];
+      else
+        v = -acc[c][r];
+      S[(int64_t)i * NBK + j] = v;
+    }
+}
+
 // Einv(:, j) = W(:, c_j) with c the inverse of the cumulative row map of
 // the interchanges (c(tot(x)) = x)
 __global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_off,
@@ -549,54 +811,149 @@ __global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_
   }
 }
 
+// Panel of an elimination without interchanges (symmetric positive definite
+// systems): S = the panel columns [k0, k0 + kb) of the block transform, P^{-1}
+// on the pivot rows k0 .. k0 + kb and -in(i, panel) P^{-1} on the others, by
+// kb Gauss-Jordan steps on the rows themselves.  Every workgroup (TP threads,
+// one row each, the row's NB panel entries in registers) carries the kb pivot
+// rows (threads 0 .. kb-1, loaded redundantly) and its own chunk of TP - NB
+// other rows, so the chunks of a large system need no communication.  Per
+// step one barrier: the pivot thread publishes its row in a double-buffered
+// LDS slot.  A pivot that is not finite or not positive sets *bad.
+template <int NB, int TP>
+__global__ void __launch_bounds__(TP)
+k_gj_panel_np(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+              double* Sbuf, int32_t* bad) {
+  __shared__ double prow[2][NB];
+  const int sy = blockIdx.y, t = threadIdx.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  if (k0 >= n) return;
+  const int kb = min(NB, n - k0);
+  constexpr int CH = TP - NB;  // other rows per workgroup
+  const int nother = n - kb;
+  if (blockIdx.x > 0 && (int)blockIdx.x * CH >= nother) return;
+  int row = -1;
+  if (t < NB) {
+    if (t < kb) row = k0 + t;
+  } else {
+    const int o = blockIdx.x * CH + (t - NB);  // o-th row outside the pivot block
+    if (o < nother) row = o < k0 ? o : o + kb;
+  }
+  const double* A = Ain + E_off[sy] + (int64_t)(row >= 0 ? row : 0) * n + k0;
+  double v[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) v[j] = gj_keep(A[min(j, kb - 1)], row >= 0 && j < kb);
+  bool sing = false;
+  for (int l = 0; l < kb; ++l) {
+    const int b = l & 1;
+    if (t == l)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) prow[b][j] = v[j];
+    __syncthreads();
+    const double piv = prow[b][l];
+    sing |= !(piv > 0.0) || !(piv < INFINITY);
+    const double inv = piv > 0.0 ? 1.0 / piv : 1.0;
+    const bool me = t == l;
+    const int lv = gj_lane_copy(l);
+    double vl = v[0];  // this row's entry in the pivot column (selects: no dynamic indexing)
+#pragma unroll
+    for (int j = 1; j < NB; ++j) vl = j == lv ? v[j] : vl;
+    const double f = me ? 0.0 : vl * inv;
+    const double sc = me ? inv : 1.0;
+    const double pc = me ? inv : -f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double x = (v[j] - f * prow[b][j]) * sc;
+      v[j] = j == lv ? pc : x;
+    }
+  }
+  if (row >= 0 && (t >= NB || blockIdx.x == 0)) {
+    double* S = Sbuf + (int64_t)NB * base + (int64_t)row * NB;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) S[j] = v[j];
+  }
+  if (t == 0 && blockIdx.x == 0 && sing) atomicMax(bad, sy + 1);
+}
+
+// src(x) = x within every system (row maps of an elimination without
+// interchanges)
+__global__ void k_iota(int32_t* src, const int32_t* sys_coff, int nsys, int64_t nrow) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nrow) return;
+  int lo = 0, hi = nsys;  // system of row x: sys_coff[lo] <= x < sys_coff[lo + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (sys_coff[mid] <= x) lo = mid; else hi = mid;
+  }
+  src[x] = (int32_t)(x - sys_coff[lo]);
+}
+
 // Inverts the nsys row-major matrices of A in place of a ping-pong pair: system
 // sy has order sys_coff[sy + 1] - sys_coff[sy] (device arrays) and starts at
 // E_off[sy]; B has the size of A.  Returns A or B, whichever holds the
 // inverses (the other is free).  A singular system sets *flag to sy + 1 (the
 // largest such index); nrow = sys_coff[nsys] and total = the sum of the
 // orders squared (host).
+//
+// spd = true (the matrices are symmetric up to rounding and expected to be
+// positive definite): large systems and large batches are inverted without
+// interchanges, panels of width 64 eliminated on the rows themselves
+// (no pivot search, no row maps, no final un-permutation); if a pivot is not
+// positive, nothing usable is returned (nullptr, after a synchronisation)
+// and the caller repeats the inversion with partial pivoting on a fresh copy.
 double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_t nrow,
                           int64_t total, double* A, double* B, const int64_t* E_off,
-                          const int32_t* sys_coff, int32_t* flag) {
+                          const int32_t* sys_coff, int32_t* flag, bool spd = false) {
   const bool small_batch = total * 8 <= ((int64_t)32 << 20);  // all matrices within 32 MB
   if (maxs <= 0) return A;
-  // register-resident panels (one row per thread) up to order GJ_T, else
-  // panels stepped over chunks of rows.  Width 32; register panels of
-  // batches small enough for the caches take width 8 (a quarter of the
-  // instructions per dependent pivot step, four times the update passes).
+  // register-resident panels (one row per thread) up to order GJ_T; orders
+  // up to 4 GJ_T: register panels of width 8 with 2-4 rows per thread; above:
+  // tournament-pivoted panels of width 64.  Register panels of batches small
+  // enough for the caches take width 8 (a quarter of the instructions per
+  // dependent pivot step, more update passes).
   const bool reg = maxs <= GJ_T;
-  // orders up to 4 GJ_T: register panels of width 8 with 2-4 rows per thread
   const int R = reg ? 1 : (int)((maxs + GJ_T - 1) / GJ_T);
   const bool multi = !reg && R <= 4;
-  const int nb = ((reg && small_batch) || multi) ? 8 : 32;
+  const bool direct = spd && (maxs > 4 * GJ_T || (reg && !small_batch));
+  const bool tslu = !reg && !multi && !direct;
+  constexpr int DNB = 64;   // panel width without interchanges
+  constexpr int DTP = 256;  // threads of its panel kernel (DTP - DNB own rows)
+  const int nb = direct ? DNB : (tslu ? TS_NB : (((reg && small_batch) || multi) ? 8 : 32));
   const int64_t n0t = std::max<int64_t>(nrow, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
   double* S = c.mem.alloc<double>(n0t * nb);
-  double* S1 = nullptr;
-  double* part_v = nullptr;
-  int32_t* part_i = nullptr;
+  double* Pinv = nullptr;
+  int32_t* cand[2] = {nullptr, nullptr};
   int32_t* swp = nullptr;
   int32_t* tmp = nullptr;
-  const int nchm = (int)((maxs + GJ_CH - 1) / GJ_CH);
-  if (!reg && !multi) {
-    S1 = c.mem.alloc<double>(n0t * nb);
-    part_v = c.mem.alloc<double>((size_t)2 * nsys * nchm);
-    part_i = c.mem.alloc<int32_t>((size_t)2 * nsys * nchm);
+  int32_t* dflag = nullptr;
+  const int gstride = (int)((maxs + TS_T - 1) / TS_T);
+  if (tslu) Pinv = c.mem.alloc<double>((size_t)nsys * nb * nb);
+  if (tslu) {
+    for (auto& q : cand) q = c.mem.alloc<int32_t>((size_t)nsys * gstride * TS_NB);
     swp = c.mem.alloc<int32_t>((size_t)nsys * nb);
     tmp = c.mem.alloc<int32_t>(n0t);
   }
+  if (direct) {  // no interchanges: the row maps stay the identity
+    dflag = c.mem.alloc<int32_t>(1);
+    ADS_HIP(hipMemsetAsync(dflag, 0, 4, st));
+    ADS_LAUNCH(k_iota, dim3((unsigned)((n0t + 255) / 256)), dim3(256), 0, st, src, sys_coff, nsys,
+               n0t);
+  }
   double* bufs[2] = {A, B};
-  // 64 x 64 output tiles when they still give the GPU a few thousand
-  // workgroups, else 32 x 32
+  // 64 x 64 matrix-core output tiles when they still give the GPU a few
+  // thousand workgroups, else 32 x 32 vector tiles
   const unsigned t64 = (unsigned)((maxs + 63) / 64);
   const bool wide = (int64_t)t64 * t64 * nsys >= 2048;
   const unsigned tiles = wide ? t64 : (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
   const unsigned rows = (unsigned)((maxs + 63) / 64 * 64);  // one thread per row
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
-    double* Sk = S;
-    if (multi) {
+    if (direct) {
+      ADS_LAUNCH((k_gj_panel_np<DNB, DTP>), dim3((unsigned)((maxs + DTP - DNB - 1) / (DTP - DNB)),
+                 (unsigned)nsys), dim3(DTP), 0, st, bufs[cur], E_off, sys_coff, (int)k0, S, dflag);
+    } else if (multi) {
       const unsigned mrows = (unsigned)(((maxs + R - 1) / R + 63) / 64 * 64);
       if (R == 2)
         ADS_LAUNCH((k_gj_panel_rows<8, 2>), dim3(nsys), dim3(mrows), 0, st, bufs[cur], E_off,
@@ -615,33 +972,55 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         ADS_LAUNCH(k_gj_panel_row<32>, dim3(nsys), dim3(rows), 0, st, bufs[cur], E_off, sys_coff,
                    (int)k0, S, src, tot, flag);
     } else {
-      const dim3 g((unsigned)nchm, (unsigned)nsys);
-      ADS_LAUNCH(k_gjc_init, g, dim3(GJ_CH), 0, st, bufs[cur], E_off, sys_coff, (int)k0, nb, S,
-                 part_v, part_i, nchm, nsys);
-      const int L = (int)std::min<int64_t>(nb, maxs - k0);
-      for (int l = 0; l < L; ++l)
-        ADS_LAUNCH(k_gjc_step, g, dim3(GJ_CH), 0, st, sys_coff, (int)k0, nb, l, S, S1, part_v,
-                   part_i, nchm, nsys, swp, flag);
-      Sk = (L & 1) ? S1 : S;
+      // tournament: leaves, then merges until one group per system is left
+      int lev = 0, io = 0;
+      ADS_LAUNCH(k_tslu, dim3((unsigned)ts_groups((int)maxs, (int)k0, 0), (unsigned)nsys),
+                 dim3(TS_T), 0, st, bufs[cur], E_off, sys_coff, (int)k0, 0, (const int32_t*)nullptr,
+                 cand[0], gstride);
+      while (ts_groups((int)maxs, (int)k0, lev) > 1) {
+        ++lev;
+        ADS_LAUNCH(k_tslu, dim3((unsigned)ts_groups((int)maxs, (int)k0, lev), (unsigned)nsys),
+                   dim3(TS_T), 0, st, bufs[cur], E_off, sys_coff, (int)k0, lev,
+                   (const int32_t*)cand[io], cand[1 - io], gstride);
+        io = 1 - io;
+      }
+      const int pstride = gstride * TS_NB;
+      ADS_LAUNCH(k_gj_block_inv<TS_NB>, dim3(nsys), dim3(256), 0, st, bufs[cur], E_off, sys_coff,
+                 (int)k0, (const int32_t*)cand[io], pstride, 0, Pinv, flag);
+      ADS_LAUNCH(k_gj_pick_swaps, dim3(nsys), dim3(64), 0, st, sys_coff, (int)k0,
+                 (const int32_t*)cand[io], pstride, swp, flag);
       ADS_LAUNCH(k_gjc_fini, dim3(nsys), dim3(GJ_T), 0, st, sys_coff, (int)k0, nb, swp, src, tot,
                  tmp);
+      ADS_LAUNCH(k_gj_panel_form<TS_NB>, dim3((unsigned)((maxs + 63) / 64), (unsigned)nsys, 1),
+                 dim3(256), 0, st, bufs[cur], E_off, sys_coff, (int)k0, Pinv, src, S);
     }
     if (wide)
-      ADS_LAUNCH(k_gj_update<64>, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur],
-                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, Sk, src);
+      ADS_LAUNCH(k_gj_update_mfma, dim3(tiles, tiles, nsys), dim3(GM_T), 0, st, bufs[cur],
+                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S, src);
     else
       ADS_LAUNCH(k_gj_update<GJ_TILE>, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur],
-                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, Sk, src);
+                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S, src);
     cur = 1 - cur;
   }
-  const int rpb = 16;
-  ADS_LAUNCH(k_gj_unpermute, dim3((unsigned)((maxs + rpb - 1) / rpb), nsys), dim3(256),
-             (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], E_off, sys_coff, tot, rpb);
-  for (void* q : {(void*)S, (void*)S1, (void*)part_v, (void*)part_i, (void*)swp, (void*)tmp})
+  double* result = nullptr;
+  if (direct) {
+    result = bufs[cur];  // identity row maps: nothing to un-permute
+    int32_t h = 0;
+    ADS_HIP(hipMemcpyAsync(&h, dflag, 4, hipMemcpyDeviceToHost, st));
+    ADS_HIP(hipStreamSynchronize(st));
+    if (h) result = nullptr;
+  } else {
+    const int rpb = 16;
+    ADS_LAUNCH(k_gj_unpermute, dim3((unsigned)((maxs + rpb - 1) / rpb), nsys), dim3(256),
+               (size_t)maxs * 4, st, bufs[cur], bufs[1 - cur], E_off, sys_coff, tot, rpb);
+    result = bufs[1 - cur];
+  }
+  for (void* q : {(void*)S, (void*)Pinv, (void*)cand[0], (void*)cand[1], (void*)swp, (void*)tmp,
+                  (void*)dflag})
     if (q) c.mem.release(q);
   c.mem.release(src);
   c.mem.release(tot);
-  return bufs[1 - cur];
+  return result;
 }
 
 }  // namespace

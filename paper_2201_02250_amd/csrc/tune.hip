@@ -91,7 +91,7 @@ void tune_tiles(Ctx& c) {
   }
   hipStream_t st = c.stream;
   const bool base_fast = c.solve_fast;
-  const double nmat = (c.opt.variant == ADS_VARIANT_DEFLATED && c.opt.nev > 0) ? 2.0 : 1.0;
+  const double nmat = (variant_has_coarse(c.opt.variant) && c.opt.nev > 0) ? 2.0 : 1.0;
   double best = 1.0, best_score = 1e300;
   std::vector<int32_t> last;
   hipEvent_t e0, e1;
