@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define ADS_ABI_VERSION 3
+#define ADS_ABI_VERSION 4
 #define ADS_MAX_RESULTS 64 /* entries of ads_ksp_result: nsys * nrhs <= 64 */
 
 /* status codes */
@@ -123,8 +123,13 @@ typedef struct {
                              "ADSGNN01", int32 n_in (= ADS_GNN_FEATURES), width,
                              layers, n_out, int64 nparams, nparams FP32 master
                              parameters (little endian, order of ads_gnn_*)         */
-  int32_t profile;        /* 1: time every apply kernel with hipEvents on its stream
-                             (reported in ads_info.t_kernel_ms / n_kernel)           */
+  int32_t profile;        /* bit 0 (1): time every apply kernel with hipEvents on its
+                             stream (ads_info.t_kernel_ms / n_kernel; hipGraph replay
+                             off); bit 1 (2): time every matrix-core update of the
+                             setup's dense inversions (coarse operator, diagonal
+                             blocks) and count its algorithmic flops
+                             (ads_info.t_mfma_update_ms / n_mfma_update /
+                             mfma_update_flops); graphs unaffected                */
   int32_t eig_solver;     /* ADS_EIG_*: method for the eq. 5 eigenproblems; a block
                              Krylov-Schur run whose basis loses rank (a Krylov space
                              exhausted on very small subdomains) is redone with the
@@ -181,6 +186,10 @@ typedef struct {
   int32_t eig_solver;     /* ADS_EIG_* that ran                                      */
   double tile_factor;     /* block size / bandwidth factor in use (1 without tuning) */
   int32_t tile_tuned;     /* 0: not tuned; 1: timed in this setup; 2: from the cache */
+  double t_mfma_update_ms;   /* profile bit 1: summed device time of the matrix-core
+                                Gauss-Jordan updates of the setup                    */
+  int64_t n_mfma_update;     /* their launches                                        */
+  double mfma_update_flops;  /* their algorithmic flops, sum of 2 n (n - kb) kb       */
 } ads_info;
 
 /* Setup for one system (Sections 2 and 3): overlapping subdomains from the

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libads.so")
 
-ADS_ABI_VERSION = 3
+ADS_ABI_VERSION = 4
 ADS_MAX_RESULTS = 64
 ADS_OK, ADS_KSP_MAXIT, ADS_KSP_BREAKDOWN = 0, 1, 2
 ADS_ERR_ARG, ADS_ERR_HIP, ADS_ERR_OOM, ADS_ERR_SINGULAR = -1, -2, -3, -4
@@ -82,7 +82,9 @@ class ads_info(C.Structure):
                 ("nev_i", C.c_void_p), ("kernel_dim", C.c_void_p), ("n_i", C.c_void_p),
                 ("n_interior", C.c_void_p), ("sweeps", C.c_void_p), ("block", C.c_void_p),
                 ("eig_resid", C.c_void_p), ("eig_solver", C.c_int32),
-                ("tile_factor", C.c_double), ("tile_tuned", C.c_int32)]
+                ("tile_factor", C.c_double), ("tile_tuned", C.c_int32),
+                ("t_mfma_update_ms", C.c_double), ("n_mfma_update", C.c_int64),
+                ("mfma_update_flops", C.c_double)]
 
 
 class DeviceCSR:

@@ -426,6 +426,9 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
       info->t_kernel_ms[k] = c.prof_ms[k];
       info->n_kernel[k] = c.prof_n[k];
     }
+    info->t_mfma_update_ms = c.prof_gj_ms;
+    info->n_mfma_update = c.prof_gj_n;
+    info->mfma_update_flops = c.prof_gj_flops;
     for (int i = 0; i < c.nsub; ++i) {
       if (info->nev_i) info->nev_i[i] = c.h_nev.empty() ? 0 : c.h_nev[i];
       if (info->kernel_dim) info->kernel_dim[i] = c.h_kdim[i];

@@ -241,10 +241,14 @@ struct Ctx {
   int cvec_cols = 0;
 
   double t_phase_ms[8] = {0};
-  // apply profiling (opt.profile): event pairs per kernel, resolved lazily
+  // apply profiling (opt.profile bit 0): event pairs per kernel, resolved lazily
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];
   double prof_ms[4] = {0};
   int64_t prof_n[4] = {0};
+  // setup profiling (opt.profile bit 1): the matrix-core Gauss-Jordan updates
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_gj_ev;
+  double prof_gj_ms = 0.0, prof_gj_flops = 0.0;
+  int64_t prof_gj_n = 0;
   // hipGraph replay: the apply, and in ads_solve the Arnoldi step, are
   // captured once and replayed while their arguments and stream are the same
   bool use_graphs = true;
@@ -279,7 +283,7 @@ struct Ctx {
   hipStream_t ag_st = nullptr;
   hipStream_t own_stream();
   void drop_apply_graph();
-  bool graphs_on() const { return use_graphs && !opt.profile; }
+  bool graphs_on() const { return use_graphs && !(opt.profile & 1); }
 
   void prof_resolve();
   ~Ctx();

@@ -643,19 +643,29 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(Ctx& cc, int kk, hipStream_t ss) : c(cc), k(kk), s(ss) {
-    if (!c.opt.profile) return;
+    if (!(c.opt.profile & 1)) return;
     ADS_HIP(hipEventCreate(&a));
     ADS_HIP(hipEventCreate(&b));
     ADS_HIP(hipEventRecord(a, s));
   }
   ~ProfScope() {
-    if (!c.opt.profile) return;
+    if (!(c.opt.profile & 1)) return;
     (void)hipEventRecord(b, s);
     c.prof_ev[k].push_back({a, b});
   }
 };
 
 void Ctx::prof_resolve() {
+  for (auto& e : prof_gj_ev) {
+    float ms = 0.f;
+    ADS_HIP(hipEventSynchronize(e.second));
+    ADS_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    prof_gj_ms += ms;
+    prof_gj_n += 1;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  prof_gj_ev.clear();
   for (int k = 0; k < 4; ++k) {
     for (auto& e : prof_ev[k]) {
       float ms = 0.f;
@@ -672,6 +682,10 @@ void Ctx::prof_resolve() {
 
 Ctx::~Ctx() {
   if (priv) (void)hipStreamSynchronize(priv);
+  for (auto& e : prof_gj_ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (apply_exec) (void)hipGraphExecDestroy(apply_exec);
   if (dep_ev) (void)hipEventDestroy(dep_ev);
   if (priv) (void)hipStreamDestroy(priv);

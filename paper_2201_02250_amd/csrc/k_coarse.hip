@@ -164,14 +164,14 @@ void assemble_coarse(Ctx& c) {
   // inverted without interchanges, or, if a pivot is not positive, assembled
   // again and inverted with partial pivoting
   double* inv = gj_invert_batched(c, st, nsys, maxs, sc[nsys], c.h_E_off[nsys], E, F, c.E_off,
-                                  c.sys_coff, flag + 1, c.sym);
+                                  c.sys_coff, flag + 1, c.sym, c.h_n0s.data());
   if (!inv) {
     ADS_HIP(hipMemsetAsync(E, 0, etot * 8, st));
     ADS_LAUNCH(k_coarse_block, dim3(nsub, NB_MAX), dim3(CO_T), 0, st, nbcnt, nblist, c.rowptr,
                c.col, c.val, c.part, c.ipos, c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev,
                c.coff, c.sub_sys_d, c.sys_coff, c.E_off, E);
     inv = gj_invert_batched(c, st, nsys, maxs, sc[nsys], c.h_E_off[nsys], E, F, c.E_off,
-                            c.sys_coff, flag + 1);
+                            c.sys_coff, flag + 1, false, c.h_n0s.data());
   }
   download(hf, flag, 2, st);
   if (hf[0]) fail(ADS_ERR_UNSUPPORTED, "a subdomain has more than 127 neighbours");

@@ -678,16 +678,19 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   const int rb = std::max(1, std::min(8, 10240 / std::max(smax, 1)));
   const dim3 gs(nsub, (unsigned)((smax + rb - 1) / rb));
   const size_t st_lds = (size_t)2 * rb * smax * 8;
+  std::vector<int32_t> orders(nsub);
   for (int k = 0; k < kmax; ++k) {
+    for (int i = 0; i < nsub; ++i) orders[i] = k < c.h_nb[i] ? c.h_bs[i] : 0;
     ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
     // symmetric A: the D_k are symmetric positive definite (Schur complements
     // of the SPD local matrices), inverted without interchanges; a pivot that
     // is not positive sends this block step back to partial pivoting
     double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad,
-                                    c.sym);
+                                    c.sym, orders.data());
     if (!inv) {
       ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
-      inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad);
+      inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad, false,
+                              orders.data());
     }
     ADS_LAUNCH((k_bf_store<FT>), gs, dim3(256), st_lds, st, a, k, inv, Pp, fac, rb);
   }

@@ -901,9 +901,15 @@ __global__ void k_iota(int32_t* src, const int32_t* sys_coff, int nsys, int64_t 
 // (no pivot search, no row maps, no final un-permutation); if a pivot is not
 // positive, nothing usable is returned (nullptr, after a synchronisation)
 // and the caller repeats the inversion with partial pivoting on a fresh copy.
+//
+// h_orders (host, nsys entries, may be null): the orders of the systems whose
+// inversion the method needs (0 for padding systems); with opt.profile bit 1
+// every matrix-core update is timed with hipEvents on st and its algorithmic
+// flops, 2 n (n - kb) kb per system, are added to the context's counters.
 double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_t nrow,
                           int64_t total, double* A, double* B, const int64_t* E_off,
-                          const int32_t* sys_coff, int32_t* flag, bool spd = false) {
+                          const int32_t* sys_coff, int32_t* flag, bool spd = false,
+                          const int32_t* h_orders = nullptr) {
   const bool small_batch = total * 8 <= ((int64_t)32 << 20);  // all matrices within 32 MB
   if (maxs <= 0) return A;
   // register-resident panels (one row per thread) up to order GJ_T; orders
@@ -994,10 +1000,27 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
       ADS_LAUNCH(k_gj_panel_form<TS_NB>, dim3((unsigned)((maxs + 63) / 64), (unsigned)nsys, 1),
                  dim3(256), 0, st, bufs[cur], E_off, sys_coff, (int)k0, Pinv, src, S);
     }
-    if (wide)
+    if (wide) {
+      const bool prof = (c.opt.profile & 2) && h_orders;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof) {
+        ADS_HIP(hipEventCreate(&e0));
+        ADS_HIP(hipEventCreate(&e1));
+        ADS_HIP(hipEventRecord(e0, st));
+      }
       ADS_LAUNCH(k_gj_update_mfma, dim3(tiles, tiles, nsys), dim3(GM_T), 0, st, bufs[cur],
                  bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S, src);
-    else
+      if (prof) {
+        ADS_HIP(hipEventRecord(e1, st));
+        c.prof_gj_ev.push_back({e0, e1});
+        for (int q = 0; q < nsys; ++q) {
+          const int64_t ns = h_orders[q];
+          if (ns <= k0) continue;
+          const int64_t kbq = std::min<int64_t>(nb, ns - k0);
+          c.prof_gj_flops += 2.0 * (double)ns * (double)(ns - kbq) * (double)kbq;
+        }
+      }
+    } else
       ADS_LAUNCH(k_gj_update<GJ_TILE>, dim3(tiles, tiles, nsys), dim3(GJ_UT), 0, st, bufs[cur],
                  bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S, src);
     cur = 1 - cur;
