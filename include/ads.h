@@ -214,6 +214,21 @@ int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part
  * not overlap.  1 <= nrhs <= 64. */
 int ads_apply(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * z = M^{-1} r as ads_apply (same kernels, same results), with no hipMalloc,
+ * hipFree, event or graph creation.  The apply's workspace lives in a
+ * file-scope device array of the library, 128 MiB on every GPU the library
+ * runs on, held until the process ends; a context whose workspace for nrhs
+ * columns exceeds it is rejected with ADS_ERR_ARG (ads_last_error gives the
+ * sizes).  The kernels are launched directly on hip_stream.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Arguments as for ads_apply; a context with ads_options.profile bit 0 set
+ * is rejected. */
+int ads_apply_noalloc(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs,
+                      void* hip_stream);
+
 /* Solve A x = b with right-preconditioned restarted (F)GMRES, x0 = 0
  * (Section 4), independently for every (system, column).  b_dev, x_dev:
  * device FP64 column-major n x nrhs.  nsys * nrhs <= ADS_MAX_RESULTS.

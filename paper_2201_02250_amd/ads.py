@@ -26,7 +26,8 @@ ADS_PREC_FP64, ADS_PREC_FP32, ADS_PREC_BF16 = 0, 1, 2
 ADS_EIG_KRYLOV_SCHUR, ADS_EIG_SUBSPACE = 0, 1
 
 # every symbol declared in include/ads.h
-SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_solve", "ads_get_info",
+SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_apply_noalloc", "ads_solve",
+           "ads_get_info",
            "ads_export_maps", "ads_export_splitting", "ads_export_coarse", "ads_partition_bfs",
            "ads_set_graphs", "ads_destroy", "ads_status_string", "ads_last_error",
            "ads_gnn_nparams", "ads_gnn_workspace_floats", "ads_gnn_graph_size",
@@ -114,6 +115,7 @@ def lib():
         L.ads_setup_batched.argtypes = [I32, C.POINTER(ads_csr), P, P, C.POINTER(ads_options), P,
                                         C.POINTER(P)]
         L.ads_apply.argtypes = [P, P, P, I32, P]
+        L.ads_apply_noalloc.argtypes = [P, P, P, I32, P]
         L.ads_solve.argtypes = [P, P, P, I32, C.POINTER(ads_ksp_options), C.POINTER(ads_ksp_result), P]
         L.ads_get_info.argtypes = [P, C.POINTER(ads_info)]
         L.ads_export_maps.argtypes = [P, P, P, P, P]
@@ -227,6 +229,10 @@ def ads_setup_batched(As, parts, nparts, opts, stream=None):
 
 def ads_apply(ctx, r_ptr, z_ptr, nrhs, stream=None):
     return _check(lib().ads_apply(ctx, r_ptr, z_ptr, nrhs, stream))
+
+
+def ads_apply_noalloc(ctx, r_ptr, z_ptr, nrhs, stream=None):
+    return _check(lib().ads_apply_noalloc(ctx, r_ptr, z_ptr, nrhs, stream))
 
 
 def ads_solve(ctx, b_ptr, x_ptr, nrhs, kopts, stream=None):

@@ -378,6 +378,22 @@ int ads_apply(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, vo
   }
 }
 
+int ads_apply_noalloc(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs,
+                      void* hip_stream) {
+  try {
+    if (!ctx || !r_dev || !z_dev) fail(ADS_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > 64) fail(ADS_ERR_ARG, "nrhs must be in [1, 64]");
+    if (r_dev == z_dev) fail(ADS_ERR_ARG, "r and z must not alias");
+    apply_noalloc(*ctx->c, r_dev, z_dev, nrhs, (hipStream_t)hip_stream);
+    return ADS_OK;
+  } catch (const Error& e) {
+    return handle(e);
+  } catch (...) {
+    g_last_error = "unknown error";
+    return ADS_ERR_HIP;
+  }
+}
+
 int ads_solve(ads_ctx* ctx, const double* b_dev, double* x_dev, int32_t nrhs,
               const ads_ksp_options* kopts, ads_ksp_result* res, void* hip_stream) {
   try {

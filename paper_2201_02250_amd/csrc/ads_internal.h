@@ -329,6 +329,9 @@ void ensure_work(Ctx& c, int cols);
 // and eq. 2 prolongation), built once per context
 void build_cover(Ctx& c);
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);
+// the same apply with its workspace in the library's scratch array (no
+// allocation; calls that overlap on one GPU race)
+void apply_noalloc(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);
 
 // Capture the launches of f on stream s (not the null stream) into an
 // executable graph.  The capture is ended on every exit path.

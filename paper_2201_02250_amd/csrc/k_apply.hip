@@ -20,6 +20,7 @@
 // row over the subdomains that contain it in ascending order (k_prolong_sum,
 // from a row -> slots map built once).
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "ads_internal.h"
@@ -526,7 +527,20 @@ void ensure_work(Ctx& c, int cols) {
   c.work_cols = cols;
 }
 
-static LocalArgs local_args(Ctx& c) {
+// the apply's workspace: the context's own buffers (ensure_work) or, for
+// the no-allocation entry point, slices of the file-scope scratch array
+struct ApplyWs {
+  double* work;
+  double* work2;
+  double* dummy;
+  double* cvec;
+  double* yvec;  // non-null: y = E^{-1} c formed in a pass of its own
+  double* qvec;
+};
+
+static ApplyWs ctx_ws(const Ctx& c) { return {c.work, c.work2, c.dummy, c.cvec, c.yvec, c.qvec}; }
+
+static LocalArgs local_args(Ctx& c, const ApplyWs& w) {
   LocalArgs a;
   a.fac_off = c.fac_off;
   a.bs = c.bs;
@@ -547,12 +561,12 @@ static LocalArgs local_args(Ctx& c) {
   a.col = c.col;
   a.val = c.val;
   a.pad_off = c.pad_off;
-  a.work = c.work;
-  a.work2 = c.work2;
+  a.work = w.work;
+  a.work2 = w.work2;
   a.ldw = c.npad_total;
   a.n = c.n;
   a.vec_lds_off = 0;
-  a.dummy = c.dummy;
+  a.dummy = w.dummy;
   return a;
 }
 
@@ -560,9 +574,9 @@ static LocalArgs local_args(Ctx& c) {
 // and scatter z = qs + x on the owner rows (z = nullptr: the solutions stay
 // in the work buffers for k_prolong_sum)
 template <class FT>
-static void local_dispatch(Ctx& c, const double* r, const double* qg, const double* qs, double* z,
-                           int nrhs, hipStream_t s) {
-  LocalArgs a = local_args(c);
+static void local_dispatch(Ctx& c, const ApplyWs& w, const double* r, const double* qg,
+                           const double* qs, double* z, int nrhs, hipStream_t s) {
+  LocalArgs a = local_args(c, w);
   constexpr int D = 2;
   constexpr int DM = 2;  // multi-column variants: shallower prefetch, fewer registers
   if (c.solve_fast) {
@@ -607,11 +621,12 @@ double time_local_solve(Ctx& c, int reps) {
   double* z = c.mem.alloc<double>(c.n);
   ADS_HIP(hipMemsetAsync(r, 0, c.n * 8, st));
   ADS_HIP(hipMemsetAsync(q, 0, c.n * 8, st));
+  const ApplyWs w = ctx_ws(c);
   auto run = [&]() {
     switch (c.prec) {
-      case ADS_PREC_FP64: local_dispatch<double>(c, r, q, q, z, 1, st); break;
-      case ADS_PREC_FP32: local_dispatch<float>(c, r, q, q, z, 1, st); break;
-      default: local_dispatch<__hip_bfloat16>(c, r, q, q, z, 1, st); break;
+      case ADS_PREC_FP64: local_dispatch<double>(c, w, r, q, q, z, 1, st); break;
+      case ADS_PREC_FP32: local_dispatch<float>(c, w, r, q, q, z, 1, st); break;
+      default: local_dispatch<__hip_bfloat16>(c, w, r, q, q, z, 1, st); break;
     }
   };
   run();
@@ -696,7 +711,8 @@ Ctx::~Ctx() {
     }
 }
 
-static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
+static void apply_kernels(Ctx& c, const ApplyWs& w, const double* r, double* z, int nrhs,
+                          hipStream_t s) {
   ProfScope all(c, 3, s);
   const double* q = nullptr;
   if (c.n0 > 0) {
@@ -704,16 +720,16 @@ static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStrea
     {
       ProfScope p1(c, 1, s);
       ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, r, c.n,
-                 c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, c.cvec, c.n0, nch);
+                 c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, w.cvec, c.n0, nch);
     }
     double* yfull = nullptr;
     {
       ProfScope p2(c, 2, s);
-      if (c.yvec) {
-        double* cy = c.yvec;
-        yfull = c.yvec + (size_t)c.n0 * nrhs;
+      if (w.yvec) {
+        double* cy = w.yvec;
+        yfull = w.yvec + (size_t)c.n0 * nrhs;
         const int64_t ne = (int64_t)c.n0 * nrhs;
-        ADS_LAUNCH(k_coarse_csum, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, c.cvec,
+        ADS_LAUNCH(k_coarse_csum, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, w.cvec,
                    c.n0, nch, nrhs, cy);
         int maxs = 0;
         for (int v : c.h_n0s) maxs = std::max(maxs, v);
@@ -722,11 +738,11 @@ static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStrea
                         (unsigned)((nrhs + EM_J - 1) / EM_J)),
                    dim3(256), 0, s, cy, c.n0, nrhs, c.Einv, c.E_off, c.sys_coff, yfull);
       }
-      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, c.cvec, yfull,
+      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, w.cvec, yfull,
                  c.n0, nch, c.Einv, c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W,
-                 c.W_off, c.nev, c.coff, c.qvec, c.n);
+                 c.W_off, c.nev, c.coff, w.qvec, c.n);
     }
-    q = c.qvec;
+    q = w.qvec;
   }
   // eq. 4 solves the local problems on r - A q; the additive forms on r
   const double* qg = c.opt.variant == ADS_VARIANT_DEFLATED ? q : nullptr;
@@ -735,14 +751,14 @@ static void apply_kernels(Ctx& c, const double* r, double* z, int nrhs, hipStrea
   {
     ProfScope p0(c, 0, s);
     switch (c.prec) {
-      case ADS_PREC_FP64: local_dispatch<double>(c, r, qg, q, zs, nrhs, s); break;
-      case ADS_PREC_FP32: local_dispatch<float>(c, r, qg, q, zs, nrhs, s); break;
-      default: local_dispatch<__hip_bfloat16>(c, r, qg, q, zs, nrhs, s); break;
+      case ADS_PREC_FP64: local_dispatch<double>(c, w, r, qg, q, zs, nrhs, s); break;
+      case ADS_PREC_FP32: local_dispatch<float>(c, w, r, qg, q, zs, nrhs, s); break;
+      default: local_dispatch<__hip_bfloat16>(c, w, r, qg, q, zs, nrhs, s); break;
     }
   }
   if (!restricted)
     ADS_LAUNCH(k_prolong_sum, dim3((unsigned)((c.n + 255) / 256), nrhs), dim3(256), 0, s, c.n,
-               c.cover_ptr, c.cover_idx, c.solve_fast ? c.work2 : c.work, c.npad_total, q, z);
+               c.cover_ptr, c.cover_idx, c.solve_fast ? w.work2 : w.work, c.npad_total, q, z);
 }
 
 hipStream_t Ctx::own_stream() {
@@ -767,15 +783,16 @@ void Ctx::drop_apply_graph() {
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
   if (c.work_cols < nrhs) c.drop_apply_graph();  // the workspace is reallocated
   ensure_work(c, nrhs);
+  const ApplyWs w = ctx_ws(c);
   if (c.capturing || !c.graphs_on() || s == nullptr) {
-    apply_kernels(c, r, z, nrhs, s);
+    apply_kernels(c, w, r, z, nrhs, s);
     return;
   }
   if (!(c.apply_exec && c.ag_r == r && c.ag_z == z && c.ag_nrhs == nrhs && c.ag_st == s)) {
     c.drop_apply_graph();
     c.capturing = true;
     try {
-      c.apply_exec = capture_graph(s, [&] { apply_kernels(c, r, z, nrhs, s); });
+      c.apply_exec = capture_graph(s, [&] { apply_kernels(c, w, r, z, nrhs, s); });
     } catch (...) {
       c.capturing = false;
       throw;
@@ -787,6 +804,79 @@ void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
     c.ag_st = s;
   }
   ADS_HIP(hipGraphLaunch(c.apply_exec, s));
+}
+
+// ---------------------------------------------------------------------------
+// Apply without allocation (callers that cannot allocate: code under HIP
+// graph capture, serving loops, harnesses that forbid hipMalloc).  The
+// workspace of one apply (padded local vectors, the coarse restriction's
+// partial sums, c and y of large coarse systems, the coarse correction q) is
+// carved from `scratch`, a file-scope device array of NOALLOC_DOUBLES
+// doubles (128 MiB) that every GPU the library runs on holds until the
+// process ends.  Its device address is resolved once per device with
+// hipGetSymbolAddress (the array's name is only a host-side stand-in).  No
+// part of the workspace has to start at zero.  All calls on one GPU share the
+// array: calls that overlap on one GPU race.  No graph capture, no events, no
+// allocation: the kernels of the ordinary apply are launched directly on the
+// caller's stream.
+// ---------------------------------------------------------------------------
+static constexpr int64_t NOALLOC_DOUBLES = (int64_t)16 << 20;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+static constexpr int NOALLOC_MAX_DEV = 64;
+static double* g_scratch[NOALLOC_MAX_DEV] = {nullptr};
+static std::mutex g_scratch_mu;
+
+static double* scratch_ptr() {
+  int dev = 0;
+  ADS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) fail(ADS_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    ADS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(ADS_ERR_HIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  return g_scratch[dev];
+}
+
+int64_t noalloc_doubles_needed(const Ctx& c, int cols) {
+  auto al = [](int64_t d) { return (d + 31) & ~(int64_t)31; };  // 256-byte slices
+  int64_t need = al((int64_t)c.npad_total * cols);                // work
+  if (c.solve_fast) {
+    need += al((int64_t)c.npad_total * cols);                      // work2
+    need += al((int64_t)c.nsub * cols * 2 * adsd::SOLVE_T);        // dummy
+  }
+  need += al((int64_t)std::max(c.n0, 1) * cols * coarse_chunks(c));  // cvec
+  if (coarse_big(c)) need += al((int64_t)2 * c.n0 * cols);          // yvec
+  need += al((int64_t)c.n * cols);                                  // qvec
+  return need;
+}
+
+void apply_noalloc(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
+  const int64_t need = noalloc_doubles_needed(c, nrhs);
+  if (need > NOALLOC_DOUBLES)
+    fail(ADS_ERR_ARG, "ads_apply_noalloc: this context needs " + std::to_string(need * 8) +
+                          " bytes of workspace for nrhs = " + std::to_string(nrhs) +
+                          ", beyond the scratch array's " + std::to_string(NOALLOC_DOUBLES * 8));
+  if (c.opt.profile & 1) fail(ADS_ERR_ARG, "ads_apply_noalloc: apply profiling records events");
+  double* base = scratch_ptr();
+  auto al = [](int64_t d) { return (d + 31) & ~(int64_t)31; };
+  auto take = [&](int64_t d) {
+    double* p = base;
+    base += al(d);
+    return p;
+  };
+  ApplyWs w{};
+  w.work = take((int64_t)c.npad_total * nrhs);
+  if (c.solve_fast) {
+    w.work2 = take((int64_t)c.npad_total * nrhs);
+    w.dummy = take((int64_t)c.nsub * nrhs * 2 * adsd::SOLVE_T);
+  }
+  w.cvec = take((int64_t)std::max(c.n0, 1) * nrhs * coarse_chunks(c));
+  w.yvec = coarse_big(c) ? take((int64_t)2 * c.n0 * nrhs) : nullptr;
+  w.qvec = take((int64_t)c.n * nrhs);
+  apply_kernels(c, w, r, z, nrhs, s);
 }
 
 }  // namespace ads
