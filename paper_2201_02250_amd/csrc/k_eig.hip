@@ -934,6 +934,7 @@ struct EigArgs {
   int kkeep;        // basis vectors kept by a restart (before the cluster rule)
   double tau;
   double tol;
+  int sym;          // A symmetric: the splitting is too, its left null vector is the constant
 };
 
 // transposed solve with the splitting tiles for the left null vector:
@@ -1224,13 +1225,19 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   if (a.kdim[i]) {
     double* l = a.ell + a.pad_off[i];
     extern __shared__ double dyn[];
-    if constexpr (!CPL)  // (with the coupling lists, k_eig_ell has formed l)
+    if (a.sym) {
+      // symmetric splitting: its left null vector is its right one, the
+      // constant (exact, no solve with the ill-conditioned regularised matrix)
+      for (int r = threadIdx.x; r < npad; r += blockDim.x) l[r] = r < n ? 1.0 : 0.0;
+      __syncthreads();
+    } else if constexpr (!CPL) {  // (with the coupling lists, k_eig_ell has formed l)
       transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval,
                                 a.cpl_ok ? a.ucpl_row + a.pad_off[i] * adsd::NCPL : nullptr,
                                 a.cpl_ok ? a.ucpl_val + a.pad_off[i] * adsd::NCPL : nullptr,
                                 a.cpl_ok ? a.lcpl_row + a.pad_off[i] * adsd::NCPL : nullptr,
                                 a.cpl_ok ? a.lcpl_val + a.pad_off[i] * adsd::NCPL : nullptr, l,
                                 dyn);
+    }
     double nn = 0.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) nn += l[r] * l[r];
     nn = adsd::block_sum(nn, red);
@@ -2314,6 +2321,157 @@ __global__ void __launch_bounds__(EIG_T) k_ks_restart(EigArgs a) {
   }
 }
 
+// Eigenvalues of eq. 5 on the selected invariant subspace, from the pencil
+// itself: with U = X V_sel the Ritz vectors of the subdomain on all n_i local
+// rows, H_B = (Pi U)^T B (Pi U) (Pi symmetric, so this is U^T Pi B Pi U) and
+// H_A = U^T Atilde U are formed with sparse products only (A_ii's local CSR,
+// the lumped sums of Definition 1, the unit left null vector ell of a
+// floating subdomain: Pi u = u - ell (ell^T u)), and the reported eigenvalues
+// are those of H_A^{-1} H_B (the Galerkin projection of the pencil onto
+// span U; exact when span U is invariant).  The operator's own Rayleigh
+// quotient carries the forward error of the solves with the regularised
+// splitting, which grows with its conditioning; span U, hence the coarse
+// space, is unchanged.  One workgroup per subdomain; U is written to ubuf
+// (column stride npad), thread (a, b) accumulates entry (a, b) of both
+// matrices over row blocks of RR_B rows staged in LDS.
+static constexpr int RR_B = EIG_T / PMAX;
+__global__ void __launch_bounds__(EIG_T)
+k_eig_rayleigh(EigArgs a, const double* __restrict__ lsum, double* __restrict__ ubuf) {
+  __shared__ SmallEigLds se;
+  __shared__ double Ub[RR_B][PMAX + 1], Vb[RR_B][PMAX + 1], YA[RR_B][PMAX + 1], YB[RR_B][PMAX + 1];
+  __shared__ double G[PMAX][2 * PMAX + 1];
+  __shared__ double M[PMAX * PMAX];
+  __shared__ double pu[PMAX], red[PMAX][EIG_T / 64];
+  __shared__ double lam_re[PMAX], lam_im[PMAX];
+  __shared__ int flag[2];
+  const int i = blockIdx.x, t = threadIdx.x;
+  const int m = a.msel[i];
+  if (m <= 0) return;
+  const int p = a.p, ni = a.ni[i], kd = a.kdim[i];
+  const int64_t ld = (int64_t)a.nb[i] * a.bs[i];
+  const double* X = a.X + a.pad_off[i] * p;
+  const double* Vs = a.Vsel + (int64_t)i * VSEL;
+  double* U = ubuf + a.pad_off[i] * p;
+  const double* ell = a.ell + a.pad_off[i];
+  const int64_t f0 = a.om_off[i];
+  const uint8_t* isint = a.om_int + f0;
+  // U = X V_sel on every local row
+  for (int e = t; e < ni * m; e += EIG_T) {
+    const int r = e % ni, c = e / ni;
+    double v = 0.0;
+    for (int j = 0; j < p; ++j) v += X[r + j * ld] * Vs[c * p + j];
+    U[r + c * ld] = v;
+  }
+  __syncthreads();
+  // pu = ell^T U (floating subdomains)
+  if (t < PMAX) pu[t] = 0.0;
+  if (kd) {
+    double acc[PMAX];
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c) acc[c] = 0.0;
+    for (int r = t; r < ni; r += EIG_T) {
+      const double l = ell[r];
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c)
+        if (c < m) acc[c] += l * U[r + c * ld];
+    }
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c) {
+      double v = acc[c];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if ((t & 63) == 0) red[c][t >> 6] = v;
+    }
+    __syncthreads();
+    if (t < m) {
+      double v = 0.0;
+      for (int w = 0; w < EIG_T / 64; ++w) v += red[t][w];
+      pu[t] = v;
+    }
+  }
+  __syncthreads();
+  const int aa = t / PMAX, bb = t % PMAX;
+  double ha = 0.0, hb = 0.0;
+  for (int r0 = 0; r0 < ni; r0 += RR_B) {
+    {
+      const int rr = t / PMAX, c = t % PMAX, r = r0 + rr;  // one (row, column) per thread
+      double u = 0.0, v = 0.0, ya = 0.0, yb = 0.0;
+      if (r < ni && c < m) {
+        const double pc = kd ? pu[c] : 0.0;
+        u = U[r + c * ld];
+        v = u - (kd ? ell[r] * pc : 0.0);
+        const bool ri = isint[r];
+        for (int64_t q = a.lrow[f0 + r]; q < a.lrow[f0 + r + 1]; ++q) {
+          const int cc = a.lcol[q];
+          const double av = a.lval[q], uc = U[cc + c * ld];
+          ya += av * uc;
+          if (ri && isint[cc]) yb += av * (uc - (kd ? ell[cc] * pc : 0.0));
+        }
+        if (!ri) ya -= lsum[f0 + r] * u;
+      }
+      Ub[rr][c] = u;
+      Vb[rr][c] = v;
+      YA[rr][c] = ya;
+      YB[rr][c] = yb;
+    }
+    __syncthreads();
+    if (aa < m && bb < m)
+      for (int rr = 0; rr < RR_B; ++rr) {
+        ha += Ub[rr][aa] * YA[rr][bb];
+        hb += Vb[rr][aa] * YB[rr][bb];
+      }
+    __syncthreads();
+  }
+  if (aa < m && bb < m) {
+    G[aa][bb] = ha;
+    G[aa][m + bb] = hb;
+  }
+  __syncthreads();
+  if (t < 64) {  // wave 0: [H_A | H_B] -> [I | H_A^{-1} H_B], partial pivoting
+    const int lane = t;
+    int ok = 1;
+    for (int k = 0; k < m; ++k) {
+      double cand = (lane < m && lane >= k) ? fabs(G[lane][k]) : -1.0;
+      if (!(cand >= 0.0)) cand = -1.0;
+      double mx = cand;
+      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+      const unsigned long long hit = __ballot(cand == mx);
+      const int pr = __ffsll((long long)hit) - 1;
+      if (!(mx > 0.0)) ok = 0;
+      if (pr != k)
+        for (int j = lane; j < 2 * m; j += 64) {
+          const double x = G[k][j];
+          G[k][j] = G[pr][j];
+          G[pr][j] = x;
+        }
+      WAVE_SYNC();
+      const double piv = G[k][k];
+      const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+      WAVE_SYNC();
+      for (int j = lane; j < 2 * m; j += 64) G[k][j] *= inv;
+      WAVE_SYNC();
+      for (int r = 0; r < m; ++r) {
+        if (r == k) continue;
+        const double f = G[r][k];
+        WAVE_SYNC();
+        for (int j = lane; j < 2 * m; j += 64) G[r][j] -= f * G[k][j];
+        WAVE_SYNC();
+      }
+    }
+    for (int e = lane; e < m * m; e += 64) M[e] = G[e / m][m + e % m];
+    WAVE_SYNC();
+    int ok2 = 1;
+    double gap = 1.0;
+    const int got = small_eig_select(m, M, m, 0.0, se, lam_re, lam_im, &ok2, &gap);
+    if (lane == 0) flag[0] = ok && ok2 && got == m;
+  }
+  __syncthreads();
+  if (flag[0] && t < m) {
+    double* lam = a.lam + (int64_t)i * 2 * PMAX;
+    lam[t] = lam_re[t];
+    lam[PMAX + t] = lam_im[t];
+  }
+}
+
 // W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
 // Z = [1 | X V] on the interior rows of every subdomain, column-major nint x
 // cols in the Y buffer (leading dimension npad): one thread per interior row
@@ -2396,7 +2554,7 @@ static void eig_run(Ctx& c, EigArgs& a, const FT* fac) {
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 0);
     ADS_LAUNCH(k_eig_orth, dim3(nblk), dim3(EIG_T), rb_lds, st, a, 1);
   };
-  if (cpl) {
+  if (cpl && !a.sym) {
     const size_t ell_lds = (size_t)(smax + EIG_T) * sizeof(double);
     ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 2), dim3(EIG_T), ell_lds, st, fac, a, 0);
     ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 1), dim3(EIG_T), ell_lds, st, fac, a, 1);
@@ -2575,7 +2733,7 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   const size_t op_lds =
       fast ? (size_t)adsd::solve_lds_doubles<PC>(c.h_bs, adsd::SOLVE_T) * sizeof(double)
            : (size_t)adsd::solve_lds_doubles_general<PC>(c.h_bs, EIG_T) * sizeof(double);
-  if (cpl) {
+  if (cpl && !a.sym) {
     const size_t ell_lds = (size_t)(smax + EIG_T) * sizeof(double);
     ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 2), dim3(EIG_T), ell_lds, st, fac, a, 0);
     ADS_LAUNCH((k_eig_ell<FT>), dim3(nsub, 1), dim3(EIG_T), ell_lds, st, fac, a, 1);
@@ -2789,6 +2947,7 @@ void eigensolve(Ctx& c) {
   a.nev = nev;
   a.tau = c.opt.tau;
   a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
+  a.sym = c.sym ? 1 : 0;
   ADS_HIP(hipMemsetAsync(a.done, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.sweeps, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.msel, 0, nsub * 4, st));
@@ -2847,6 +3006,8 @@ void eigensolve(Ctx& c) {
     fail(ADS_ERR_UNSUPPORTED,
          "an eigenvalue cluster at the cut fills the eigensolver subspace (e.g. overlap 0)");
   if (herr[0] & 2) fail(ADS_ERR_EIG_NOCONV, "loss of orthogonality in the eigensolver block");
+  // the reported eigenvalues from the pencil on the selected subspaces
+  ADS_LAUNCH(k_eig_rayleigh, dim3(nsub), dim3(EIG_T), 0, st, a, c.lsum, a.Y);
   // the whole report block in one copy
   std::vector<double> hrep;
   download(hrep, rep, rep_d + (rep_i + 1) / 2, st);

@@ -767,10 +767,6 @@ def _int_checksum(v):
     return (int(v.sum()), int((k * v).sum()), int((k * k * v).sum()))
 
 
-@pytest.mark.xfail(reason="4 of 11784 eigenvalues (floating subdomains) are 1e-8..5e-8 off: the "
-                          "reported values come from the operator's Rayleigh quotient, whose "
-                          "forward error follows the conditioning of the regularised splitting",
-                   strict=False)
 def test_full_size_jump3d_every_subdomain_matches_oracle():
     """All 1024 subdomains of the full-scale 3D family (128^3, log10 k uniform
     in [-3, 3] on 8^3 blocks, overlap 2, nev 12) against the FP64 oracle's
