@@ -72,7 +72,10 @@ enum {
 enum {
   ADS_PREC_FP64 = 0,         /* everything FP64                                          */
   ADS_PREC_FP32 = 1,         /* local factors stored FP32, products accumulated in FP64  */
-  ADS_PREC_BF16 = 2          /* local factors stored BF16, products accumulated in FP64  */
+  ADS_PREC_BF16 = 2          /* local factors stored BF16, products accumulated in FP64;
+                                refused (ADS_ERR_UNSUPPORTED) when a local solve with them
+                                leaves a relative residual above 0.25 (ads_info.local_resid)
+                                on the given matrix, e.g. strongly jumping coefficients */
 };
 
 /* eigensolver for the local eigenproblems of eq. 5 (largest |lambda|) */
@@ -190,6 +193,9 @@ typedef struct {
                                 Gauss-Jordan updates of the setup                    */
   int64_t n_mfma_update;     /* their launches                                        */
   double mfma_update_flops;  /* their algorithmic flops, sum of 2 n (n - kb) kb       */
+  double local_resid;        /* largest relative residual ||t - A_ii x|| / ||t|| of one
+                                local solve with the stored factors (pseudo-random t):
+                                what the factor precision costs each local solve     */
 } ads_info;
 
 /* Setup for one system (Sections 2 and 3): overlapping subdomains from the

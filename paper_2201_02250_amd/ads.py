@@ -85,7 +85,7 @@ class ads_info(C.Structure):
                 ("eig_resid", C.c_void_p), ("eig_solver", C.c_int32),
                 ("tile_factor", C.c_double), ("tile_tuned", C.c_int32),
                 ("t_mfma_update_ms", C.c_double), ("n_mfma_update", C.c_int64),
-                ("mfma_update_flops", C.c_double)]
+                ("mfma_update_flops", C.c_double), ("local_resid", C.c_double)]
 
 
 class DeviceCSR:

@@ -207,6 +207,9 @@ static void import_csr(Ctx& c, const ads_csr& A, int64_t r0, int64_t k0, int32_t
   ADS_HIP(hipStreamSynchronize(st));
 }
 
+// largest local-solve relative residual accepted with BF16 factors
+static constexpr double BF16_MAX_LOCAL_RESID = 0.25;
+
 static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, const int32_t* nparts,
                        const ads_options* opts, hipStream_t st) {
   if (nsys <= 0) fail(ADS_ERR_ARG, "nsys must be positive");
@@ -290,6 +293,17 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     tune_tiles(*c);
     c->t_phase_ms[7] = tm.lap();
     factor_local(*c);
+    c->local_resid = local_solve_accuracy(*c);
+    // BF16 factors (8-bit significands) on strongly varying coefficients: a
+    // local solve that leaves more than a quarter of its right-hand side
+    // unresolved made FGMRES stall in every measured case (3D jumping
+    // coefficients 64^3: 0.33, 128^3: 4.7), while the cases up to 0.12
+    // converged
+    if (c->prec == ADS_PREC_BF16 && !(c->local_resid <= BF16_MAX_LOCAL_RESID))
+      fail(ADS_ERR_UNSUPPORTED,
+           "BF16 local factors leave a local-solve relative residual of " +
+               std::to_string(c->local_resid) + " (above " + std::to_string(BF16_MAX_LOCAL_RESID) +
+               ") on this matrix; use ADS_PREC_FP32");
     c->t_phase_ms[2] = tm.lap();
     const bool coarse = variant_has_coarse(opts->variant) && opts->nev > 0;
     if (coarse) {
@@ -442,6 +456,7 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
       info->t_kernel_ms[k] = c.prof_ms[k];
       info->n_kernel[k] = c.prof_n[k];
     }
+    info->local_resid = c.local_resid;
     info->t_mfma_update_ms = c.prof_gj_ms;
     info->n_mfma_update = c.prof_gj_n;
     info->mfma_update_flops = c.prof_gj_flops;

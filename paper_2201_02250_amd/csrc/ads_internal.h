@@ -163,9 +163,7 @@ struct Ctx {
 
   // local matrices: CSR of A_ii in the sorted local order
   int64_t lnnz = 0;
-  int64_t* lptr_off = nullptr;  // [nsub+1] offsets into lptr (sum of (ni+1))
-  int32_t* lptr = nullptr;      // per subdomain ni+1 row pointers (relative to lnz_off[i])
-  int64_t* lnz_off = nullptr;   // [nsub+1]
+  int64_t* lptr_off = nullptr;  // [omega_total+1] row starts into lcol / lval, sorted order
   int32_t* lcol = nullptr;
   double* lval = nullptr;
   double* lsum = nullptr;       // [omega_total] lumped s (0 on interior rows), sorted order
@@ -199,6 +197,7 @@ struct Ctx {
   bool cpl_ok = false;              // all four lists complete (<= NCPL per row / column)
   bool solve_fast = false;          // every subdomain fits the prefetching tile solve
   bool sym = false;                 // A equals A^T entry for entry (pattern and values)
+  double local_resid = 0.0;         // local_solve_accuracy() after the factorization
   void* facA = nullptr;             // factors of A_ii (apply)
   void* facT = nullptr;             // factors of the regularised splitting (eigensolver)
   int prec = ADS_PREC_FP64;
@@ -235,6 +234,7 @@ struct Ctx {
   double* work2 = nullptr;  // backward results of the two-ended solve, same shape
   double* dummy = nullptr;  // per-thread discard slots of the tile solves
   int work_cols = 0;
+  int work_n0 = -1;         // coarse dimension the workspace was sized for
   double* cvec = nullptr;   // partial sums of the coarse restriction, n0 * cols * chunks
   double* yvec = nullptr;   // c and y = E^{-1} c of large coarse systems, 2 n0 cols
   double* qvec = nullptr;   // coarse correction, n * cols
@@ -324,11 +324,15 @@ void release_factors(Ctx& c);
 void factor_local(Ctx& c, bool only_a = false);
 void eigensolve(Ctx& c);
 void assemble_coarse(Ctx& c);
+bool work_fits(const Ctx& c, int cols);
 void ensure_work(Ctx& c, int cols);
 // row -> local-solution slots of every subdomain containing the row (eq. 1
 // and eq. 2 prolongation), built once per context
 void build_cover(Ctx& c);
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);
+// largest relative residual ||t_i - A_ii x_i|| / ||t_i|| of one local solve
+// with the stored factors (fixed pseudo-random right-hand side)
+double local_solve_accuracy(Ctx& c);
 // the same apply with its workspace in the library's scratch array (no
 // allocation; calls that overlap on one GPU race)
 void apply_noalloc(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s);

@@ -504,8 +504,14 @@ void build_cover(Ctx& c) {
   c.mem.release(cnt);
 }
 
+// the apply workspace holds cols columns for the current coarse dimension
+// (cvec and yvec are sized by n0)
+bool work_fits(const Ctx& c, int cols) {
+  return c.work_cols >= cols && c.work_n0 == c.n0 && (c.yvec || !coarse_big(c));
+}
+
 void ensure_work(Ctx& c, int cols) {
-  if (c.work_cols >= cols && (c.yvec || !coarse_big(c))) return;
+  if (work_fits(c, cols)) return;
   if (c.priv) ADS_HIP(hipStreamSynchronize(c.priv));  // the old workspace may be in use there
   if (c.work) c.mem.release(c.work);
   if (c.cvec) c.mem.release(c.cvec);
@@ -525,6 +531,7 @@ void ensure_work(Ctx& c, int cols) {
   if (coarse_big(c)) c.yvec = c.mem.alloc<double>((size_t)2 * c.n0 * cols);
   c.qvec = c.mem.alloc<double>((size_t)c.n * cols);
   c.work_cols = cols;
+  c.work_n0 = c.n0;
 }
 
 // the apply's workspace: the context's own buffers (ensure_work) or, for
@@ -607,6 +614,66 @@ static void local_dispatch(Ctx& c, const ApplyWs& w, const double* r, const doub
     ADS_LAUNCH((k_local_solve<FT, 8>), dim3(c.nsub, (nrhs + 7) / 8), dim3(APPLY_T), lds, s,
                (const FT*)c.facA, a, r, qg, qs, z, nrhs);
   }
+}
+
+// Accuracy of the stored local factors: for a fixed pseudo-random r, the
+// relative residual ||t_i - A_ii x_i|| / ||t_i|| of the local solves
+// x_i = (factors)^{-1} t_i, t_i = r restricted to Omega_i (one workgroup per
+// subdomain; the local CSR of A_ii, local row order).  With FP64 factors this
+// is rounding; with FP32 / BF16 factors it measures what the reduced storage
+// costs each subdomain solve of the apply.
+__global__ void k_fill_hash(double* r, int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) r[g] = adsd::hash_unit(0x5eedull ^ (uint64_t)g);
+}
+
+__global__ void __launch_bounds__(256)
+k_local_residual(const int64_t* __restrict__ om_off, const int32_t* __restrict__ ni,
+                 const int32_t* __restrict__ om_sorted, const int64_t* __restrict__ lrow,
+                 const int32_t* __restrict__ lcol, const double* __restrict__ lval,
+                 const int64_t* __restrict__ pad_off, const double* __restrict__ X,
+                 const double* __restrict__ r, double* __restrict__ ratio) {
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  const int64_t f0 = om_off[i];
+  const double* x = X + pad_off[i];
+  double rr = 0.0, tt = 0.0;
+  for (int k = threadIdx.x; k < ni[i]; k += blockDim.x) {
+    const double t = r[om_sorted[f0 + k]];
+    double v = t;
+    for (int64_t q = lrow[f0 + k]; q < lrow[f0 + k + 1]; ++q) v -= lval[q] * x[lcol[q]];
+    rr += v * v;
+    tt += t * t;
+  }
+  rr = adsd::block_sum(rr, red);
+  tt = adsd::block_sum(tt, red);
+  if (threadIdx.x == 0) ratio[i] = tt > 0.0 ? sqrt(rr / tt) : 0.0;
+}
+
+double local_solve_accuracy(Ctx& c) {
+  hipStream_t st = c.stream;
+  // buffers of its own: the apply's workspace is sized later, once the
+  // coarse dimension is known
+  ApplyWs w{};
+  w.work = c.mem.alloc<double>((size_t)c.npad_total);
+  w.work2 = c.mem.alloc<double>((size_t)c.npad_total);
+  w.dummy = c.mem.alloc<double>((size_t)c.nsub * 2 * adsd::SOLVE_T);
+  double* r = c.mem.alloc<double>(c.n);
+  double* ratio = c.mem.alloc<double>(c.nsub);
+  ADS_LAUNCH(k_fill_hash, dim3((unsigned)((c.n + 255) / 256)), dim3(256), 0, st, r, c.n);
+  switch (c.prec) {
+    case ADS_PREC_FP64: local_dispatch<double>(c, w, r, nullptr, nullptr, nullptr, 1, st); break;
+    case ADS_PREC_FP32: local_dispatch<float>(c, w, r, nullptr, nullptr, nullptr, 1, st); break;
+    default: local_dispatch<__hip_bfloat16>(c, w, r, nullptr, nullptr, nullptr, 1, st); break;
+  }
+  ADS_LAUNCH(k_local_residual, dim3(c.nsub), dim3(256), 0, st, c.om_off, c.ni, c.om_sorted,
+             c.lptr_off, c.lcol, c.lval, c.pad_off, c.solve_fast ? w.work2 : w.work, r, ratio);
+  std::vector<double> h;
+  download(h, ratio, c.nsub, st);
+  for (double* p : {r, ratio, w.work, w.work2, w.dummy}) c.mem.release(p);
+  double mx = 0.0;
+  for (double v : h) mx = std::max(mx, v);
+  return mx;
 }
 
 // average time (ms) of one local solve (both chain launches, nrhs = 1) on
@@ -781,7 +848,7 @@ void Ctx::drop_apply_graph() {
 // z = M^{-1} r on stream s: eager launches, or the replay of a captured graph
 // of them when graphs are on and s is not the null stream
 void apply_prec(Ctx& c, const double* r, double* z, int nrhs, hipStream_t s) {
-  if (c.work_cols < nrhs) c.drop_apply_graph();  // the workspace is reallocated
+  if (!work_fits(c, nrhs)) c.drop_apply_graph();  // the workspace is reallocated
   ensure_work(c, nrhs);
   const ApplyWs w = ctx_ws(c);
   if (c.capturing || !c.graphs_on() || s == nullptr) {

@@ -325,7 +325,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   // graphs only on the context's own stream (nothing else is queued there);
   // the apply workspace exists before any capture
   const bool use_graph = c.graphs_on() && st == c.priv;
-  if (c.work_cols < nrhs) c.drop_apply_graph();
+  if (!work_fits(c, nrhs)) c.drop_apply_graph();
   ensure_work(c, nrhs);
   // two captured forms of one Arnoldi step: alone, and preceded by the
   // previous step's basis update (k_advance, k_next_basis) when no instance
@@ -416,6 +416,10 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   norms(b, all_d, bnorm_d);
   std::vector<double> bnorm, beta(Q), est(Q), hn(Q);
   download(bnorm, bnorm_d, Q, st);
+  for (int q = 0; q < Q; ++q)
+    if (!std::isfinite(bnorm[q]))
+      fail(ADS_ERR_NAN, "non-finite right-hand side (system " + std::to_string(q / nrhs) +
+                            ", column " + std::to_string(q % nrhs) + ")");
   std::vector<int32_t> state(Q, 0);  // 0 active, 1 done
   std::vector<int32_t> its(Q, 0), status(Q, ADS_OK), jcur(Q, 0);
   std::vector<int32_t> act(Q, 0), endm(Q, 0), jend(Q, 0);
@@ -628,6 +632,8 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
       download(tr, beta_d, Q, st);
       for (int q = 0; q < Q; ++q) {
         if (!endm[q]) continue;
+        if (!std::isfinite(tr[q]))
+          fail(ADS_ERR_NAN, "non-finite residual in the iteration (column " + std::to_string(q) + ")");
         relres[q] = tr[q] / bnorm[q];
         if (fixed) {
           if (its[q] >= fixed || brk[q]) state[q] = 1;

@@ -427,6 +427,33 @@ def test_reduced_precision_factors_still_solve_to_tolerance(prec):
     ctx.close()
 
 
+def test_bf16_factors_refused_where_local_solves_fail():
+    """BF16 local factors on the full-scale 3D family (coefficient contrast
+    10^6, 128^3): a local solve with them leaves a relative residual above 1,
+    and FGMRES stalls, so the setup refuses them with ADS_ERR_UNSUPPORTED and
+    says why; FP32 factors on the same matrix leave about 1e-4 (reported in
+    ads_info.local_resid) and converge; BF16 on the 24^3 family of the same
+    contrast is accepted (its residual is about 0.1)."""
+    A, part, N, o = W.config("c5_jump3d_128_boxes1024")
+    Ad = ads.DeviceCSR(A, DEV)
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=ads.ADS_PREC_BF16)
+    assert e.value.status == ads.ADS_ERR_UNSUPPORTED and "local-solve relative residual" in str(e.value)
+    print(e.value, flush=True)
+    c32 = ads.Context(Ad, part, N, o["overlap"], o["nev"], precision=ads.ADS_PREC_FP32)
+    lr = ads.ads_get_info(c32.ctx)["local_resid"]
+    print(f"FP32 factors: local residual {lr:.2e}", flush=True)
+    assert lr < 1e-3
+    c32.close()
+    m = 24
+    small = ads.Context(W.diffusion3d_blocks(m, block=3, seed=5), W.block_partition_3d(m, 2, 2, 4), 16,
+                        2, 12, precision=ads.ADS_PREC_BF16)
+    lr = ads.ads_get_info(small.ctx)["local_resid"]
+    print(f"BF16 factors, 24^3: local residual {lr:.2e}", flush=True)
+    assert lr <= 0.25
+    small.close()
+
+
 def test_overlap0_coarse_space_is_unsupported():
     """Without overlap the splitting equals A_ii and every eigenvalue of eq. 5
     is 1: the cluster rule would take the whole subdomain.  The library
@@ -444,6 +471,59 @@ def test_errors_are_reported_not_raised():
     with pytest.raises(ads.AdsError) as e:
         ads.Context(A, part, 4, 1, 2)
     assert e.value.status == ads.ADS_ERR_ARG
+
+
+def test_singular_local_matrix_names_its_subdomain():
+    """Row r of A set to stored zeros (its diagonal entry included): the
+    local matrix of the subdomain holding r is singular, the factorization
+    stops with ADS_ERR_SINGULAR naming a subdomain, and a later setup in the
+    same process works."""
+    m = 16
+    A = W.laplace2d(m)
+    r = 5 * m + 5  # inside block (1, 1) of a 3 x 3 partition
+    data = A.data.copy()
+    data[A.indptr[r]:A.indptr[r + 1]] = 0.0
+    Ab = W.CSR(A.n, A.indptr, A.indices, data)
+    part = W.block_partition_2d(m, 3)
+    print(f"zero row {r} in part {int(part[r])}", flush=True)
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(Ab, part, 9, 1, 2)
+    print(e.value, flush=True)
+    assert e.value.status == ads.ADS_ERR_SINGULAR and "subdomain" in str(e.value)
+    ok = ads.Context(A, part, 9, 1, 2)
+    ok.close()
+
+
+def test_iteration_cap_nan_and_eigensolver_sweep_cap():
+    """maxit = 2: ADS_KSP_MAXIT after exactly 2 Arnoldi steps with the
+    residual of that iterate; a NaN in b: ADS_ERR_NAN naming the column;
+    eig_max_sweeps = 1: the setup completes with every unconverged subdomain
+    counted in eig_unconverged, and FGMRES still reaches 1e-8 with that
+    (less accurate) coarse space."""
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64", scale=256)
+    As = A.to_scipy()
+    ctx = ads.Context(A, part, N, 2, 8)
+    b = W.rhs(A.n, 0)
+    x, info = ctx.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8, maxit=2)
+    assert info["status"] == ads.ADS_KSP_MAXIT and info["its"][0] == 2, info
+    rel = np.linalg.norm(b - As @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert abs(rel - info["relres"][0]) <= 1e-10 * rel + 1e-15 and rel > 1e-8
+    bn = b.copy()
+    bn[17] = np.nan
+    B = torch.tensor(np.stack([b, bn], axis=1), device=DEV)
+    with pytest.raises(ads.AdsError) as e:
+        ctx.solve(B, restart=30, flexible=True, rtol=1e-8)
+    assert e.value.status == ads.ADS_ERR_NAN and "column 1" in str(e.value)
+    x, info = ctx.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    assert info["status"] == 0  # the context survives the error
+    ctx.close()
+    c1 = ads.Context(A, part, N, 2, 8, eig_max_sweeps=1)
+    inf1 = ads.ads_get_info(c1.ctx)
+    print(f"eig_max_sweeps 1: {inf1['eig_unconverged']} of {N} subdomains unconverged", flush=True)
+    assert inf1["eig_unconverged"] > 0
+    x, info = c1.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    assert info["status"] == 0 and info["relres"][0] <= 1e-8
+    c1.close()
 
 
 @pytest.mark.parametrize("nrhs", [1, 3])
