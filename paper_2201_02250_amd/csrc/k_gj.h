@@ -395,8 +395,8 @@ k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t
 // Matrix-core form of the update (large batches and large systems): the
 // same transform as k_gj_update on 64 x 64 output tiles, computed with
 // v_mfma_f64_16x16x4f64.  The workgroup stages S' = S - [i = k0 + l] (its 64
-// rows, kb <= 64 columns) and the kb source rows R = in(src(k0 + l), :) of
-// its 64 columns in LDS once; wave w owns the 32 x 32 quarter (w / 2, w % 2)
+// rows) and the source rows R = in(src(k0 + l), :) of its 64 columns in LDS,
+// GM_K panel columns at a time; wave w owns the 32 x 32 quarter (w / 2, w % 2)
 // as 2 x 2 blocks of 16 x 16, whose accumulators start from in(src(i), j).
 // Operand layouts of the instruction (16 x 4 by 4 x 16): lane l holds
 // A(l % 16, l / 16) and B(l / 16, l % 16); accumulator register r of lane l
@@ -405,23 +405,51 @@ k_gj_update(const double* Ain, double* Aout, const int64_t* E_off, const int32_t
 // ---------------------------------------------------------------------------
 typedef double gj_d4 __attribute__((ext_vector_type(4)));
 static constexpr int GM_T = 256;
-static constexpr int GM_K = 64;   // panel columns staged per pass (panels up to 2 GM_K wide)
+static constexpr int GM_K = 32;     // panel columns staged per pass
+static constexpr int GM_KMAX = 128; // widest panel
 static constexpr int GM_SLD = GM_K + 1;
 static constexpr int GM_RLD = 64 + 4;
 
-// 64 x 64 tile (i0, j0) of the update, K = kb <= 2 GM_K columns of the panel
-// taken in passes of GM_K through LDS; the loads of a pass are all issued
-// before its first LDS store
+static constexpr int GM_GROUP = 16;  // tile rows per column-major sweep
+
+// Tile of workgroup h in a one-dimensional grid of T x T tiles per system
+// times nsys.  Workgroups are dispatched to the eight XCDs (each with its
+// own L2) in turn, h to XCD h % 8; the logical order L gives every XCD one
+// contiguous range, so a system's tiles (which share the panel S and the
+// source rows R) are read through one L2.  Within a system, L runs over
+// groups of GM_GROUP tile rows, column-major inside a group: the tiles that
+// run together share their R block and the group's S rows stay cached.
+// Both maps are bijections, so the order only affects the caches.
+__device__ inline void gj_tile_of(int h, int T, int nsys, int& sy, int& ti, int& tj) {
+  const int N = T * T * nsys;
+  const int q = N >> 3, r = N & 7, x = h & 7, s = h >> 3;
+  const int L = x * q + min(x, r) + s;
+  const int TT = T * T;
+  sy = L / TT;
+  const int p = L - sy * TT;
+  const int G = min(T, GM_GROUP);
+  const int g = p / (G * T), ib = g * G, Gg = min(G, T - ib);
+  const int qq = p - g * G * T;
+  tj = qq / Gg;
+  ti = ib + (qq - tj * Gg);
+}
+
+// 64 x 64 tile (i0, j0) of the update, K = kb <= GM_KMAX columns of the
+// panel taken in passes of GM_K through LDS: the loads of the next pass are
+// issued before the matrix-core products of the current one, so they run
+// while it computes.  Grid: T * T * nsys workgroups (gj_tile_of).  At most
+// 128 registers per lane, so that four workgroups share a compute unit.
 __global__ void __launch_bounds__(GM_T)
 k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff,
-                 int k0, int nb, const double* Sbuf, const int32_t* src_all) {
+                 int k0, int nb, const double* Sbuf, const int32_t* src_all, int T, int nsys) {
   __shared__ double Ssh[64 * GM_SLD];
   __shared__ double Rsh[GM_K * GM_RLD];
   __shared__ int srow[64];
-  __shared__ int rsrc[2 * GM_K];
-  const int sy = blockIdx.z;
+  __shared__ int rsrc[GM_KMAX];
+  int sy, ti, tj;
+  gj_tile_of((int)blockIdx.x, T, nsys, sy, ti, tj);
   const int n = sys_coff[sy + 1] - sys_coff[sy];
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int i0 = ti * 64, j0 = tj * 64;
   if (i0 >= n || j0 >= n) return;
   const double* A = Ain + E_off[sy];
   double* B = Aout + E_off[sy];
@@ -435,23 +463,35 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
   }
   const int kb = min(nb, n - k0);
   const double* S = Sbuf + (int64_t)nb * sys_coff[sy];
-  const int32_t* src = src_all + sys_coff[sy];
-  if (t < 2 * GM_K) rsrc[t] = t < kb ? src[k0 + t] : 0;
-  if (t < 64) srow[t] = (i0 + t < n) ? src[i0 + t] : 0;
-  __syncthreads();
+  if (src_all) {
+    const int32_t* src = src_all + sys_coff[sy];
+    if (t < GM_KMAX) rsrc[t] = t < kb ? src[k0 + t] : 0;
+    if (t < 64) srow[t] = (i0 + t < n) ? src[i0 + t] : 0;
+    __syncthreads();
+  }
+  // src_all = nullptr: the row maps are the identity (no loads, no barrier)
+  const bool ident = src_all == nullptr;
   const int w = t >> 6, lane = t & 63;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
+  // a pass: S' rows i0 .. i0 + 63 by panel columns kc .. kc + GM_K - 1
+  // (element e = t + GM_T q: row e / GM_K, column e % GM_K) and the source
+  // rows of those columns by the tile's 64 columns (row e / 64, column e % 64)
   constexpr int NQ = 64 * GM_K / GM_T;
   double sv[NQ], rv[NQ];
-  // pass 0 of the panel, issued together with the accumulators' loads
+  auto load_pass = [&](int kc) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int r = (t >> 6) + (GM_T / 64) * q, l = t & 63;
-    const int i = i0 + r, j = j0 + l;
-    sv[q] = gj_keep(S[(int64_t)min(i, n - 1) * nb + min(l, kb - 1)], i < n && l < kb);
-    rv[q] = gj_keep(A[(int64_t)rsrc[min(r, kb - 1)] * n + min(j, n - 1)], r < kb && j < n);
-  }
+    for (int q = 0; q < NQ; ++q) {
+      const int e = t + GM_T * q;
+      const int sr = e / GM_K, sc = e % GM_K, rr = e / 64, rc = e % 64;
+      const int i = i0 + sr, j = j0 + rc;
+      sv[q] = gj_keep(S[(int64_t)min(i, n - 1) * nb + min(kc + sc, kb - 1)], i < n && kc + sc < kb);
+      const int kr = min(kc + rr, kb - 1);
+      rv[q] = gj_keep(A[(int64_t)(ident ? k0 + kr : rsrc[kr]) * n + min(j, n - 1)],
+                      kc + rr < kb && j < n);
+    }
+  };
+  load_pass(0);
   gj_d4 acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -461,27 +501,20 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
       for (int r = 0; r < 4; ++r) {
         const int ri = wr + bi * 16 + lk + 4 * r;
         const int i = i0 + ri, j = j0 + wc + bj * 16 + li;
-        acc[bi][bj][r] = gj_keep(A[(int64_t)srow[ri] * n + min(j, n - 1)], i < n && j < n);
+        acc[bi][bj][r] =
+            gj_keep(A[(int64_t)(ident ? min(i, n - 1) : srow[ri]) * n + min(j, n - 1)], i < n && j < n);
       }
   for (int kc = 0; kc < kb; kc += GM_K) {
-    if (kc > 0) {
-      __syncthreads();  // the previous pass's LDS reads are done
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int r = (t >> 6) + (GM_T / 64) * q, l = t & 63;
-        const int i = i0 + r, j = j0 + l;
-        sv[q] = gj_keep(S[(int64_t)min(i, n - 1) * nb + min(kc + l, kb - 1)], i < n && kc + l < kb);
-        rv[q] = gj_keep(A[(int64_t)rsrc[min(kc + r, kb - 1)] * n + min(j, n - 1)],
-                        kc + r < kb && j < n);
-      }
-    }
+    if (kc > 0) __syncthreads();  // the previous pass's LDS reads are done
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int r = (t >> 6) + (GM_T / 64) * q, l = t & 63;
-      Ssh[r * GM_SLD + l] = sv[q] - ((kc + l < kb && i0 + r == k0 + kc + l) ? 1.0 : 0.0);
-      Rsh[r * GM_RLD + l] = rv[q];
+      const int e = t + GM_T * q;
+      const int sr = e / GM_K, sc = e % GM_K;
+      Ssh[sr * GM_SLD + sc] = sv[q] - ((kc + sc < kb && i0 + sr == k0 + kc + sc) ? 1.0 : 0.0);
+      Rsh[(e / 64) * GM_RLD + e % 64] = rv[q];
     }
     __syncthreads();
+    if (kc + GM_K < kb) load_pass(kc + GM_K);  // in flight during the products below
     const int kp = min(GM_K, (kb - kc + 3) & ~3);
     for (int kk = 0; kk < kp; kk += 4) {
       const double a0 = Ssh[(wr + li) * GM_SLD + kk + lk];
@@ -626,11 +659,27 @@ k_tslu(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
   for (int l = picked + t; l < TS_NB; l += TS_T) out[l] = -1;
 }
 
-// Inverse of the kb x kb pivot block P(l, j) = in(row_l, k0 + j), kb <= NBK,
-// by Gauss-Jordan elimination without interchanges: row_l = picks[l] (the
-// tournament's pick order, in which every multiplier is at most 1 in
-// magnitude) or, with picks = nullptr, row k0 + l (symmetric positive
-// definite systems, whose pivots stay positive without interchanges).  256
+// A column panel of the systems' matrices: system sy's rows start at
+// base + E_off[sy] with row stride n (its order), or, with E_off = nullptr,
+// at base + ld sys_coff[sy] with row stride ld (an n x ld side buffer); the
+// panel's first column is c0.
+struct GjPanel {
+  const double* base;
+  const int64_t* E_off;
+  int ld;
+  int c0;
+  __device__ const double* rows(int sy, const int32_t* sys_coff) const {
+    return base + (E_off ? E_off[sy] : (int64_t)ld * sys_coff[sy]);
+  }
+  __device__ int stride(int n) const { return E_off ? n : ld; }
+};
+
+// Inverse of the kb x kb pivot block P(l, j) = in(row_l, c0 + j), kb =
+// min(NBK, n - kp), by Gauss-Jordan elimination without interchanges: row_l
+// = picks[l] (the tournament's pick order, in which every multiplier is at
+// most 1 in magnitude) or, with picks = nullptr, row kp + l (symmetric
+// positive definite systems, whose pivots stay positive without
+// interchanges).  256
 // threads; thread t owns the NBK/16 x NBK/16 block (t / 16, t % 16) in
 // registers; per step the pivot row and column go through a double-buffered
 // LDS slot (one barrier per step).  Rows and columns past kb are the
@@ -638,28 +687,29 @@ k_tslu(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
 // *bad to sy + 1.  Pinv[sy] is NBK x NBK, row-major.
 template <int NBK>
 __global__ void __launch_bounds__(256)
-k_gj_block_inv(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
-               const int32_t* picks, int pstride, int spd, double* Pinv, int32_t* bad) {
+k_gj_block_inv(GjPanel in, const int32_t* sys_coff, int kp, const int32_t* picks, int pstride,
+               int spd, double* Pinv, int32_t* bad) {
   constexpr int Q = NBK / 16;
   __shared__ double prow[2][NBK], pcol[2][NBK];
   const int sy = blockIdx.x, t = threadIdx.x;
   const int n = sys_coff[sy + 1] - sys_coff[sy];
-  if (k0 >= n) return;
-  const int kb = min(NBK, n - k0);
+  if (kp >= n) return;
+  const int kb = min(NBK, n - kp);
   const int br = t >> 4, bc = t & 15;
-  const double* A = Ain + E_off[sy];
+  const double* A = in.rows(sy, sys_coff);
+  const int ld = in.stride(n), c0 = in.c0;
   double a[Q][Q];
 #pragma unroll
   for (int ii = 0; ii < Q; ++ii) {
     const int l = Q * br + ii;
     int row = -1;
-    if (l < kb) row = picks ? picks[(int64_t)sy * pstride + l] : k0 + l;
+    if (l < kb) row = picks ? picks[(int64_t)sy * pstride + l] : kp + l;
 #pragma unroll
     for (int jj = 0; jj < Q; ++jj) {
       const int j = Q * bc + jj;
-      const bool in = l < kb && j < kb;
-      const double x = gj_keep(A[(int64_t)max(row, 0) * n + k0 + min(j, kb - 1)], in && row >= 0);
-      a[ii][jj] = in ? x : (l == j ? 1.0 : 0.0);
+      const bool inb = l < kb && j < kb;
+      const double x = gj_keep(A[(int64_t)max(row, 0) * ld + c0 + min(j, kb - 1)], inb && row >= 0);
+      a[ii][jj] = inb ? x : (l == j ? 1.0 : 0.0);
     }
   }
   bool sing = false;
@@ -735,26 +785,28 @@ __global__ void k_gj_pick_swaps(const int32_t* sys_coff, int k0, const int32_t* 
 }
 
 // S(i, :) of the block transform in the block's row order (src from the row
-// maps): P^{-1} on the pivot rows k0 .. k0 + kb, -in(src(i), panel) P^{-1} on
-// the others, as a matrix-core product: 64 rows (one 16-row slab per wave)
-// by 64 columns of S per workgroup (blockIdx.z picks the column half when
-// NBK = 128); the slab of P^{-1} sits in LDS.  S has row stride NBK.
+// maps, src_all = nullptr: the identity): P^{-1} on the pivot rows kp .. kp +
+// kb, -in(src(i), panel) P^{-1} on the others, as a matrix-core product: 64
+// rows (one 16-row slab per wave) by 64 columns of S per workgroup
+// (blockIdx.z picks the column half when NBK = 128); the slab of P^{-1}
+// sits in LDS.  S(i, j) is stored at Sbuf[ldS (sys_coff[sy] + i) + sc0 + j].
 template <int NBK>
 __global__ void __launch_bounds__(256)
-k_gj_panel_form(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
-                const double* Pinv, const int32_t* src_all, double* Sbuf) {
+k_gj_panel_form(GjPanel in, const int32_t* sys_coff, int kp, const double* Pinv,
+                const int32_t* src_all, double* Sbuf, int ldS, int sc0) {
   constexpr int LD = 64 + 4;
   __shared__ double Ps[NBK * LD];
   const int sy = blockIdx.y, t = threadIdx.x;
   const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
   const int i0 = blockIdx.x * 64, c0 = blockIdx.z * 64;
-  if (k0 >= n || i0 >= n) return;
-  const int kb = min(NBK, n - k0);
+  if (kp >= n || i0 >= n) return;
+  const int kb = min(NBK, n - kp);
   const double* Pi = Pinv + (int64_t)sy * NBK * NBK;
   for (int e = t; e < NBK * 64; e += 256) Ps[(e >> 6) * LD + (e & 63)] = Pi[(e >> 6) * NBK + c0 + (e & 63)];
   const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int ia = i0 + 16 * w + li;  // this lane's row of the A operand
-  const double* arow = Ain + E_off[sy] + (int64_t)(ia < n ? src_all[base + ia] : 0) * n + k0;
+  const int ra = ia < n ? (src_all ? src_all[base + ia] : ia) : 0;
+  const double* arow = in.rows(sy, sys_coff) + (int64_t)ra * in.stride(n) + in.c0;
   double av[NBK / 4];
 #pragma unroll
   for (int q = 0; q < NBK / 4; ++q) {
@@ -772,7 +824,7 @@ k_gj_panel_form(const double* Ain, const int64_t* E_off, const int32_t* sys_coff
       acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], Ps[(4 * q + lk) * LD + 16 * c + li],
                                                     acc[c], 0, 0, 0);
   }
-  double* S = Sbuf + (int64_t)NBK * base;
+  double* S = Sbuf + (int64_t)ldS * base + sc0;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -782,11 +834,146 @@ k_gj_panel_form(const double* Ain, const int64_t* E_off, const int32_t* sys_coff
       double v;
       if (j >= kb)
         v = 0.0;
-      else if (i >= k0 && i < k0 + kb)
-        v = Ps[(i - k0) * LD + 16 * c + li];
+      else if (i >= kp && i < kp + kb)
+        v = Ps[(i - kp) * LD + 16 * c + li];
       else
         v = -acc[c][r];
-      S[(int64_t)i * NBK + j] = v;
+      S[(int64_t)i * ldS + j] = v;
+    }
+}
+
+// Blocks of 128 columns without interchanges (symmetric positive definite
+// systems, large batches): the block's transform is built from two panels of
+// 64 so that one rank-128 update replaces two rank-64 ones (half the passes
+// over the matrices).  With W the first panel's S and P2 the rows k0 + 64 ..
+// k0 + 64 + kb2 - 1:
+//   k_gj_narrow   the block's last 64 columns after the first panel's steps,
+//                 C(i, c) = in(i, k0 + 64 + c) + sum_l (W(i, l) - [i = k0 + l]) in(k0 + l, k0 + 64 + c),
+//                 whose panel (pivot rows P2) gives the second S2;
+//   k_gj_combine  the block's first 64 columns, the product of the two
+//                 transforms on W: S(i, l) = [i not in P2] W(i, l) + sum_m S2(i, m) W(k0 + 64 + m, l).
+// The two transforms applied in turn equal I + (S - [i = k0 + l]) in(k0 + l, :)
+// over the 128 rows of the block, which the update applies.
+
+// C (row stride 64 per system, zero in the columns past the matrix); one 64
+// x 64 tile of rows per workgroup, grid (tile rows, nsys); W has row stride 64
+__global__ void __launch_bounds__(256)
+k_gj_narrow(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
+            const double* Wbuf, double* Cbuf) {
+  __shared__ double Ssh[64 * 65];
+  __shared__ double Rsh[64 * GM_RLD];
+  const int sy = blockIdx.y, t = threadIdx.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  const int i0 = blockIdx.x * 64;
+  if (n - k0 <= 64 || i0 >= n) return;  // no second panel
+  const int m = min(64, n - k0 - 64);   // columns of C inside the matrix
+  const int jc = k0 + 64;
+  const double* A = Ain + E_off[sy];
+  const double* W = Wbuf + (int64_t)64 * base;
+  double* Cm = Cbuf + (int64_t)64 * base;
+  const int w = t >> 6, lane = t & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  double sv[16], rv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = (t >> 6) + 4 * q, c = t & 63;  // row r, column c of both tiles
+    const int i = i0 + r;
+    sv[q] = gj_keep(W[(int64_t)min(i, n - 1) * 64 + c], i < n);
+    rv[q] = gj_keep(A[(int64_t)(k0 + r) * n + jc + min(c, m - 1)], c < m);
+  }
+  gj_d4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + bi * 16 + lk + 4 * r, c = wc + bj * 16 + li;
+        acc[bi][bj][r] = gj_keep(A[(int64_t)min(i, n - 1) * n + jc + min(c, m - 1)], i < n && c < m);
+      }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = (t >> 6) + 4 * q, c = t & 63;
+    Ssh[r * 65 + c] = sv[q] - (i0 + r == k0 + c ? 1.0 : 0.0);
+    Rsh[r * GM_RLD + c] = rv[q];
+  }
+  __syncthreads();
+  for (int kk = 0; kk < 64; kk += 4) {
+    const double a0 = Ssh[(wr + li) * 65 + kk + lk];
+    const double a1 = Ssh[(wr + 16 + li) * 65 + kk + lk];
+    const double b0 = Rsh[(kk + lk) * GM_RLD + wc + li];
+    const double b1 = Rsh[(kk + lk) * GM_RLD + wc + 16 + li];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + bi * 16 + lk + 4 * r, c = wc + bj * 16 + li;
+        if (i < n) Cm[(int64_t)i * 64 + c] = c < m ? acc[bi][bj][r] : 0.0;
+      }
+}
+
+// S(:, 0 .. 63) of the 128-column block (row stride 128), S(:, 64 ..) = S2
+// already in place; one 64-row slab per workgroup, grid (tile rows, nsys)
+__global__ void __launch_bounds__(256)
+k_gj_combine(const int32_t* sys_coff, int k0, const double* Wbuf, double* Sbuf) {
+  constexpr int LD = 64 + 4;
+  __shared__ double Xs[64 * LD];
+  const int sy = blockIdx.y, t = threadIdx.x;
+  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
+  const int i0 = blockIdx.x * 64;
+  if (k0 >= n || i0 >= n) return;
+  const double* W = Wbuf + (int64_t)64 * base;
+  double* S = Sbuf + (int64_t)128 * base;
+  const int kb2 = min(64, n - k0 - 64);
+  if (kb2 <= 0) {  // no second panel: the block's transform is the first one's
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int i = i0 + (e >> 6), l = e & 63;
+      if (i < n) S[(int64_t)i * 128 + l] = W[(int64_t)i * 64 + l];
+    }
+    return;
+  }
+  for (int e = t; e < 64 * 64; e += 256) {  // X = W(P2, :), zero past the matrix
+    const int mm = e >> 6, l = e & 63;
+    Xs[mm * LD + l] = gj_keep(W[(int64_t)min(k0 + 64 + mm, n - 1) * 64 + l], mm < kb2);
+  }
+  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int ia = i0 + 16 * w + li;  // this lane's row of the S2 operand
+  const double* s2 = S + (int64_t)min(ia, n - 1) * 128 + 64;
+  double av[16], wv[4][4];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) av[q] = gj_keep(s2[4 * q + lk], ia < n);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 16 * w + lk + 4 * r;
+      const bool p2 = i >= k0 + 64 && i < k0 + 64 + kb2;
+      wv[c][r] = gj_keep(W[(int64_t)min(i, n - 1) * 64 + 16 * c + li], i < n && !p2);
+    }
+  __syncthreads();
+  gj_d4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = gj_d4{wv[c][0], wv[c][1], wv[c][2], wv[c][3]};
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], Xs[(4 * q + lk) * LD + 16 * c + li], acc[c],
+                                                    0, 0, 0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 16 * w + lk + 4 * r;
+      if (i < n) S[(int64_t)i * 128 + 16 * c + li] = acc[c][r];
     }
 }
 
@@ -811,82 +998,6 @@ __global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_
   }
 }
 
-// Panel of an elimination without interchanges (symmetric positive definite
-// systems): S = the panel columns [k0, k0 + kb) of the block transform, P^{-1}
-// on the pivot rows k0 .. k0 + kb and -in(i, panel) P^{-1} on the others, by
-// kb Gauss-Jordan steps on the rows themselves.  Every workgroup (TP threads,
-// one row each, the row's NB panel entries in registers) carries the kb pivot
-// rows (threads 0 .. kb-1, loaded redundantly) and its own chunk of TP - NB
-// other rows, so the chunks of a large system need no communication.  Per
-// step one barrier: the pivot thread publishes its row in a double-buffered
-// LDS slot.  A pivot that is not finite or not positive sets *bad.
-template <int NB, int TP>
-__global__ void __launch_bounds__(TP)
-k_gj_panel_np(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
-              double* Sbuf, int32_t* bad) {
-  __shared__ double prow[2][NB];
-  const int sy = blockIdx.y, t = threadIdx.x;
-  const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
-  if (k0 >= n) return;
-  const int kb = min(NB, n - k0);
-  constexpr int CH = TP - NB;  // other rows per workgroup
-  const int nother = n - kb;
-  if (blockIdx.x > 0 && (int)blockIdx.x * CH >= nother) return;
-  int row = -1;
-  if (t < NB) {
-    if (t < kb) row = k0 + t;
-  } else {
-    const int o = blockIdx.x * CH + (t - NB);  // o-th row outside the pivot block
-    if (o < nother) row = o < k0 ? o : o + kb;
-  }
-  const double* A = Ain + E_off[sy] + (int64_t)(row >= 0 ? row : 0) * n + k0;
-  double v[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) v[j] = gj_keep(A[min(j, kb - 1)], row >= 0 && j < kb);
-  bool sing = false;
-  for (int l = 0; l < kb; ++l) {
-    const int b = l & 1;
-    if (t == l)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) prow[b][j] = v[j];
-    __syncthreads();
-    const double piv = prow[b][l];
-    sing |= !(piv > 0.0) || !(piv < INFINITY);
-    const double inv = piv > 0.0 ? 1.0 / piv : 1.0;
-    const bool me = t == l;
-    const int lv = gj_lane_copy(l);
-    double vl = v[0];  // this row's entry in the pivot column (selects: no dynamic indexing)
-#pragma unroll
-    for (int j = 1; j < NB; ++j) vl = j == lv ? v[j] : vl;
-    const double f = me ? 0.0 : vl * inv;
-    const double sc = me ? inv : 1.0;
-    const double pc = me ? inv : -f;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double x = (v[j] - f * prow[b][j]) * sc;
-      v[j] = j == lv ? pc : x;
-    }
-  }
-  if (row >= 0 && (t >= NB || blockIdx.x == 0)) {
-    double* S = Sbuf + (int64_t)NB * base + (int64_t)row * NB;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) S[j] = v[j];
-  }
-  if (t == 0 && blockIdx.x == 0 && sing) atomicMax(bad, sy + 1);
-}
-
-// src(x) = x within every system (row maps of an elimination without
-// interchanges)
-__global__ void k_iota(int32_t* src, const int32_t* sys_coff, int nsys, int64_t nrow) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nrow) return;
-  int lo = 0, hi = nsys;  // system of row x: sys_coff[lo] <= x < sys_coff[lo + 1]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (sys_coff[mid] <= x) lo = mid; else hi = mid;
-  }
-  src[x] = (int32_t)(x - sys_coff[lo]);
-}
 
 // Inverts the nsys row-major matrices of A in place of a ping-pong pair: system
 // sy has order sys_coff[sy + 1] - sys_coff[sy] (device arrays) and starts at
@@ -896,11 +1007,14 @@ __global__ void k_iota(int32_t* src, const int32_t* sys_coff, int nsys, int64_t 
 // orders squared (host).
 //
 // spd = true (the matrices are symmetric up to rounding and expected to be
-// positive definite): large systems and large batches are inverted without
-// interchanges, panels of width 64 eliminated on the rows themselves
-// (no pivot search, no row maps, no final un-permutation); if a pivot is not
-// positive, nothing usable is returned (nullptr, after a synchronisation)
-// and the caller repeats the inversion with partial pivoting on a fresh copy.
+// positive definite): large systems and large batches (when their update
+// runs on the matrix cores) are inverted without interchanges, in blocks of
+// 128 columns, each from two panels of 64 (k_gj_narrow, k_gj_combine): the
+// 64 x 64 pivot block inverted by Gauss-Jordan (k_gj_block_inv), the
+// panel's transform formed on the matrix cores (k_gj_panel_form); no pivot
+// search, no row maps, no final un-permutation.  If a pivot is not positive,
+// nothing usable is returned (nullptr, after a synchronisation) and the
+// caller repeats the inversion with partial pivoting on a fresh copy.
 //
 // h_orders (host, nsys entries, may be null): the orders of the systems whose
 // inversion the method needs (0 for padding systems); with opt.profile bit 1
@@ -920,16 +1034,23 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   const bool reg = maxs <= GJ_T;
   const int R = reg ? 1 : (int)((maxs + GJ_T - 1) / GJ_T);
   const bool multi = !reg && R <= 4;
-  const bool direct = spd && (maxs > 4 * GJ_T || (reg && !small_batch));
+  // 64 x 64 matrix-core output tiles when they still give the GPU a few
+  // thousand workgroups, else 32 x 32 vector tiles (panels of at most 32)
+  const unsigned t64 = (unsigned)((maxs + 63) / 64);
+  const bool wide = (int64_t)t64 * t64 * nsys >= 2048;
+  // without interchanges (matrix-core updates only): blocks of 128 columns
+  // from two panels of 64, rank-128 updates
+  const bool direct = spd && wide && (maxs > 4 * GJ_T || (reg && !small_batch));
   const bool tslu = !reg && !multi && !direct;
   constexpr int DNB = 64;   // panel width without interchanges
-  constexpr int DTP = 256;  // threads of its panel kernel (DTP - DNB own rows)
-  const int nb = direct ? DNB : (tslu ? TS_NB : (((reg && small_batch) || multi) ? 8 : 32));
+  const int nb = direct ? 2 * DNB : (tslu ? TS_NB : (((reg && small_batch) || multi) ? 8 : 32));
   const int64_t n0t = std::max<int64_t>(nrow, 1);
   int32_t* tot = c.mem.alloc<int32_t>(n0t);
   int32_t* src = c.mem.alloc<int32_t>(n0t);
   double* S = c.mem.alloc<double>(n0t * nb);
   double* Pinv = nullptr;
+  double* W1 = nullptr;  // first panel's S and the block's last 64 columns (128-column blocks)
+  double* Cn = nullptr;
   int32_t* cand[2] = {nullptr, nullptr};
   int32_t* swp = nullptr;
   int32_t* tmp = nullptr;
@@ -941,24 +1062,38 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
     swp = c.mem.alloc<int32_t>((size_t)nsys * nb);
     tmp = c.mem.alloc<int32_t>(n0t);
   }
-  if (direct) {  // no interchanges: the row maps stay the identity
+  if (direct) {  // no interchanges: no row maps, no pivot search
+    Pinv = c.mem.alloc<double>((size_t)nsys * DNB * DNB);
     dflag = c.mem.alloc<int32_t>(1);
     ADS_HIP(hipMemsetAsync(dflag, 0, 4, st));
-    ADS_LAUNCH(k_iota, dim3((unsigned)((n0t + 255) / 256)), dim3(256), 0, st, src, sys_coff, nsys,
-               n0t);
+    W1 = c.mem.alloc<double>(n0t * DNB);
+    Cn = c.mem.alloc<double>(n0t * DNB);
   }
   double* bufs[2] = {A, B};
-  // 64 x 64 matrix-core output tiles when they still give the GPU a few
-  // thousand workgroups, else 32 x 32 vector tiles
-  const unsigned t64 = (unsigned)((maxs + 63) / 64);
-  const bool wide = (int64_t)t64 * t64 * nsys >= 2048;
   const unsigned tiles = wide ? t64 : (unsigned)((maxs + GJ_TILE - 1) / GJ_TILE);
   const unsigned rows = (unsigned)((maxs + 63) / 64 * 64);  // one thread per row
+  if (wide && (int64_t)tiles * tiles * nsys > INT32_MAX)
+    fail(ADS_ERR_UNSUPPORTED, "dense inversion batch too large for one launch");
   int cur = 0;
   for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
     if (direct) {
-      ADS_LAUNCH((k_gj_panel_np<DNB, DTP>), dim3((unsigned)((maxs + DTP - DNB - 1) / (DTP - DNB)),
-                 (unsigned)nsys), dim3(DTP), 0, st, bufs[cur], E_off, sys_coff, (int)k0, S, dflag);
+      // P^{-1} of the pivot block without interchanges, then S = P^{-1} on
+      // the pivot rows and -in(i, panel) P^{-1} on the others on the matrix
+      // cores (the row maps are the identity)
+      const GjPanel p1{bufs[cur], E_off, 0, (int)k0};
+      const dim3 slabs((unsigned)((maxs + 63) / 64), (unsigned)nsys);
+      // the 128-column block from two panels of 64
+      ADS_LAUNCH(k_gj_block_inv<DNB>, dim3(nsys), dim3(256), 0, st, p1, sys_coff, (int)k0,
+                 (const int32_t*)nullptr, 0, 1, Pinv, dflag);
+      ADS_LAUNCH(k_gj_panel_form<DNB>, slabs, dim3(256), 0, st, p1, sys_coff, (int)k0, Pinv,
+                 (const int32_t*)nullptr, W1, DNB, 0);
+      ADS_LAUNCH(k_gj_narrow, slabs, dim3(256), 0, st, bufs[cur], E_off, sys_coff, (int)k0, W1, Cn);
+      const GjPanel p2{Cn, nullptr, DNB, 0};
+      ADS_LAUNCH(k_gj_block_inv<DNB>, dim3(nsys), dim3(256), 0, st, p2, sys_coff, (int)k0 + DNB,
+                 (const int32_t*)nullptr, 0, 1, Pinv, dflag);
+      ADS_LAUNCH(k_gj_panel_form<DNB>, slabs, dim3(256), 0, st, p2, sys_coff, (int)k0 + DNB, Pinv,
+                 (const int32_t*)nullptr, S, nb, DNB);
+      ADS_LAUNCH(k_gj_combine, slabs, dim3(256), 0, st, sys_coff, (int)k0, W1, S);
     } else if (multi) {
       const unsigned mrows = (unsigned)(((maxs + R - 1) / R + 63) / 64 * 64);
       if (R == 2)
@@ -991,14 +1126,16 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         io = 1 - io;
       }
       const int pstride = gstride * TS_NB;
-      ADS_LAUNCH(k_gj_block_inv<TS_NB>, dim3(nsys), dim3(256), 0, st, bufs[cur], E_off, sys_coff,
-                 (int)k0, (const int32_t*)cand[io], pstride, 0, Pinv, flag);
+      ADS_LAUNCH(k_gj_block_inv<TS_NB>, dim3(nsys), dim3(256), 0, st,
+                 (GjPanel{bufs[cur], E_off, 0, (int)k0}), sys_coff, (int)k0,
+                 (const int32_t*)cand[io], pstride, 0, Pinv, flag);
       ADS_LAUNCH(k_gj_pick_swaps, dim3(nsys), dim3(64), 0, st, sys_coff, (int)k0,
                  (const int32_t*)cand[io], pstride, swp, flag);
       ADS_LAUNCH(k_gjc_fini, dim3(nsys), dim3(GJ_T), 0, st, sys_coff, (int)k0, nb, swp, src, tot,
                  tmp);
       ADS_LAUNCH(k_gj_panel_form<TS_NB>, dim3((unsigned)((maxs + 63) / 64), (unsigned)nsys, 1),
-                 dim3(256), 0, st, bufs[cur], E_off, sys_coff, (int)k0, Pinv, src, S);
+                 dim3(256), 0, st, (GjPanel{bufs[cur], E_off, 0, (int)k0}), sys_coff, (int)k0,
+                 Pinv, (const int32_t*)src, S, nb, 0);
     }
     if (wide) {
       const bool prof = (c.opt.profile & 2) && h_orders;
@@ -1008,8 +1145,9 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         ADS_HIP(hipEventCreate(&e1));
         ADS_HIP(hipEventRecord(e0, st));
       }
-      ADS_LAUNCH(k_gj_update_mfma, dim3(tiles, tiles, nsys), dim3(GM_T), 0, st, bufs[cur],
-                 bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S, src);
+      ADS_LAUNCH(k_gj_update_mfma, dim3(tiles * tiles * (unsigned)nsys), dim3(GM_T), 0, st,
+                 bufs[cur], bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S,
+                 direct ? (const int32_t*)nullptr : (const int32_t*)src, (int)tiles, nsys);
       if (prof) {
         ADS_HIP(hipEventRecord(e1, st));
         c.prof_gj_ev.push_back({e0, e1});
@@ -1039,7 +1177,7 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
     result = bufs[1 - cur];
   }
   for (void* q : {(void*)S, (void*)Pinv, (void*)cand[0], (void*)cand[1], (void*)swp, (void*)tmp,
-                  (void*)dflag})
+                  (void*)dflag, (void*)W1, (void*)Cn})
     if (q) c.mem.release(q);
   c.mem.release(src);
   c.mem.release(tot);
