@@ -404,10 +404,11 @@ k_local_bwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ 
 // general path (any block size / coupling count); qg enters the residual
 // gather t = r - A qg, qs the owner scatter z = qs + x (z = nullptr: none)
 template <class FT, int P>
-__global__ void __launch_bounds__(APPLY_T)
-k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
-              const double* __restrict__ qg, const double* __restrict__ qs,
-              double* __restrict__ z, int nrhs) {
+__device__ __forceinline__ void local_solve_general(const FT* __restrict__ fac, const LocalArgs& a,
+                                                    const double* __restrict__ r,
+                                                    const double* __restrict__ qg,
+                                                    const double* __restrict__ qs,
+                                                    double* __restrict__ z, int nrhs) {
   extern __shared__ double lds[];
   const int i = blockIdx.x;
   const int j0 = blockIdx.y * P;
@@ -425,6 +426,25 @@ k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict_
                                    a.cpl_ok ? a.cpl_val + cb : nullptr, X,
                                    a.ldw, pc, lds);
   if (z) scatter_local(om, a.om_int + base, 0, ns, qs, z, a.n, j0, pc, X, a.ldw);
+}
+
+template <class FT, int P>
+__global__ void __launch_bounds__(APPLY_T)
+k_local_solve(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
+              const double* __restrict__ qg, const double* __restrict__ qs,
+              double* __restrict__ z, int nrhs) {
+  local_solve_general<FT, P>(fac, a, r, qg, qs, z, nrhs);
+}
+
+// 16 columns with the tile products on the matrix cores: one workgroup of
+// adsd::MF_T threads per compute unit, so the registers are budgeted for
+// four waves per SIMD (the loads of several column chunks stay in flight)
+template <class FT>
+__global__ void __launch_bounds__(adsd::MF_T) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_local_solve16(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
+                const double* __restrict__ qg, const double* __restrict__ qs,
+                double* __restrict__ z, int nrhs) {
+  local_solve_general<FT, 16>(fac, a, r, qg, qs, z, nrhs);
 }
 
 // eq. 1 / eq. 2 prolongation: z(g) = qs(g) + sum over the subdomains i that
@@ -577,6 +597,12 @@ static LocalArgs local_args(Ctx& c, const ApplyWs& w) {
   return a;
 }
 
+// the 16-column matrix-core form of the general path fits in LDS (two
+// workgroups per compute unit)
+static bool general_mfma_ok(const Ctx& c) {
+  return adsd::solve_lds_doubles_general<16>(c.h_bs, adsd::MF_T) * 8 <= 80 * 1024;
+}
+
 // the local solves of one apply: gather t = r - A qg (qg may be null), solve,
 // and scatter z = qs + x on the owner rows (z = nullptr: the solutions stay
 // in the work buffers for k_prolong_sum)
@@ -609,6 +635,12 @@ static void local_dispatch(Ctx& c, const ApplyWs& w, const double* r, const doub
     size_t lds = (size_t)adsd::solve_lds_doubles_general<1>(c.h_bs, APPLY_T) * 8;
     ADS_LAUNCH((k_local_solve<FT, 1>), dim3(c.nsub, 1), dim3(APPLY_T), lds, s, (const FT*)c.facA, a,
                r, qg, qs, z, nrhs);
+  } else if (nrhs > 8 && general_mfma_ok(c)) {
+    // more than 8 columns: chunks of 16 on the matrix cores (each tile read
+    // once per 16 columns)
+    size_t lds = (size_t)adsd::solve_lds_doubles_general<16>(c.h_bs, adsd::MF_T) * 8;
+    ADS_LAUNCH((k_local_solve16<FT>), dim3(c.nsub, (nrhs + 15) / 16), dim3(adsd::MF_T), lds, s,
+               (const FT*)c.facA, a, r, qg, qs, z, nrhs);
   } else {
     size_t lds = (size_t)adsd::solve_lds_doubles_general<8>(c.h_bs, APPLY_T) * 8;
     ADS_LAUNCH((k_local_solve<FT, 8>), dim3(c.nsub, (nrhs + 7) / 8), dim3(APPLY_T), lds, s,

@@ -390,12 +390,127 @@ __device__ __forceinline__ void tile_product_general(const FT* __restrict__ M, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core tile product for 16 right-hand sides (general path): out = M
+// vin on v_mfma_f64_16x16x4f64, the tile entries widened to FP64 as they
+// arrive.  Wave w of the workgroup owns 16-row blocks of the output, MF_RB of
+// them per pass over the tile's columns.  Per 16 tile columns, lane (i, kk)
+// (i = lane % 16, kk = lane / 16) loads the four entries c0 + 4 kk .. c0 + 4
+// kk + 3 of its row 16 rb + i (one 16-byte load for FP32 tiles), and step t
+// of the four products pairs column c0 + 4 kk + t of the tile with row c0 +
+// 4 kk + t of vin: the same permutation of the sum on both operands.  The
+// loads run MF_D chunks of 16 columns ahead of the products.  vin is
+// column-major, 16 columns with stride ls = s + 1 (which also keeps the 16
+// columns of a lane group on different LDS banks); its row s and the
+// columns past pc must hold zeros, so that its reads need no masks.  out
+// has stride ldo and may be base (each entry is read and written by the
+// same lane).
+// ---------------------------------------------------------------------------
+constexpr int MF_RB = 2;    // 16-row blocks per wave and pass
+constexpr int MF_T = 1024;  // threads of the workgroups that use it
+
+// four consecutive tile entries c .. c + 3 (c % 4 == 0) of row r, as loaded;
+// a column group past the tile's g groups is clamped to the last one (its
+// entries then only meet columns >= s, whose vector entries are zero)
+template <class FT>
+struct TileQuad;
+template <>
+struct TileQuad<float> {
+  float4 v;
+  __device__ void load(const float* M, int r, int c, int s, int g) {
+    v = *reinterpret_cast<const float4*>(M + ((int64_t)min(c >> 2, g - 1) * s + r) * 4);
+  }
+  __device__ double at(int t) const { return (double)(t == 0 ? v.x : t == 1 ? v.y : t == 2 ? v.z : v.w); }
+};
+template <>
+struct TileQuad<double> {
+  double2 a, b;
+  __device__ void load(const double* M, int r, int c, int s, int g) {  // groups c / 2, c / 2 + 1
+    a = *reinterpret_cast<const double2*>(M + ((int64_t)min(c >> 1, g - 1) * s + r) * 2);
+    b = *reinterpret_cast<const double2*>(M + ((int64_t)min((c >> 1) + 1, g - 1) * s + r) * 2);
+  }
+  __device__ double at(int t) const { return t == 0 ? a.x : t == 1 ? a.y : t == 2 ? b.x : b.y; }
+};
+template <>
+struct TileQuad<__hip_bfloat16> {
+  uint2 v;
+  __device__ void load(const __hip_bfloat16* M, int r, int c, int s, int g) {  // half of group c / 8
+    v = *reinterpret_cast<const uint2*>(M + ((int64_t)min(c >> 3, g - 1) * s + r) * 8 + (c & 4));
+  }
+  __device__ double at(int t) const {
+    const uint32_t w = t < 2 ? v.x : v.y;
+    return (double)__uint_as_float((t & 1) ? (w & 0xFFFF0000u) : (w << 16));
+  }
+};
+
+template <class FT>
+__device__ void tile_product_mfma(const FT* __restrict__ M, int s, const double* vin, int ls,
+                                  double* out, int64_t ldo, int mode, const double* base,
+                                  int64_t ldb, int pc) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int t = threadIdx.x, W = blockDim.x >> 6, w = t >> 6, lane = t & 63;
+  const int li = lane & 15, kk = lane >> 4;
+  const int nrb = (s + 15) >> 4;
+  const int ng = (s + TileV<FT>::V - 1) / TileV<FT>::V;  // stored column groups
+  for (int rb0 = w * MF_RB; rb0 < nrb; rb0 += W * MF_RB) {
+    int row[MF_RB];
+#pragma unroll
+    for (int u = 0; u < MF_RB; ++u) row[u] = min((rb0 + u) * 16 + li, s - 1);
+    d4 acc[MF_RB];
+#pragma unroll
+    for (int u = 0; u < MF_RB; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    // ring of MF_D chunks in flight: chunk c0 + 16 d sits in buf[d]
+    constexpr int MF_D = sizeof(FT) == 8 ? 2 : 3;
+    TileQuad<FT> buf[MF_D][MF_RB];
+#pragma unroll
+    for (int d = 0; d < MF_D; ++d) {
+#pragma unroll
+      for (int u = 0; u < MF_RB; ++u) buf[d][u].load(M, row[u], 16 * d + 4 * kk, s, ng);
+      __builtin_amdgcn_sched_barrier(0);  // slots issued in order
+    }
+    // branch-free: the chunks are rounded up to whole rings; a chunk past
+    // the tile multiplies zeros (row s of vin) and its loads are clamped
+    const int nit = ((s + 15) / 16 + MF_D - 1) / MF_D;
+    for (int it = 0; it < nit; ++it) {
+#pragma unroll
+      for (int d = 0; d < MF_D; ++d) {
+        const int cc = (it * MF_D + d) * 16;
+        double b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)  // vin(c, li); row s and the columns past pc hold zeros
+          b[q] = vin[min(cc + 4 * kk + q, s) + li * ls];
+#pragma unroll
+        for (int u = 0; u < MF_RB; ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[d][u].at(q), b[q], acc[u], 0, 0, 0);
+        // refill the slot MF_D chunks ahead, after its products; the
+        // scheduling barriers keep the loads here (not next to their use,
+        // and the slot's entries are not widened ahead of the products)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < MF_RB; ++u) buf[d][u].load(M, row[u], cc + 16 * MF_D + 4 * kk, s, ng);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // accumulator register r of lane l: row 16 rb + l / 16 + 4 r, column l % 16
+#pragma unroll
+    for (int u = 0; u < MF_RB; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (rb0 + u) * 16 + kk + 4 * r, j = li;
+        if (rr < s && j < pc) out[rr + j * ldo] = mode ? base[rr + j * ldb] - acc[u][r] : acc[u][r];
+      }
+  }
+}
+
 template <int P>
 inline int64_t solve_lds_doubles_general(const std::vector<int32_t>& sizes, int T) {
   int64_t m = 0;
   for (int s : sizes) {
     const int G = (2 * s <= T) ? (T / s) : 1;
-    const int64_t d = (int64_t)s * P * (2 + (G > 1 ? G : 0));
+    const int64_t d = P == 16 ? (int64_t)(s + 1) * P  // matrix-core products: the input block only
+                              : (int64_t)s * P * (2 + (G > 1 ? G : 0));
     m = m > d ? m : d;
   }
   return m;
@@ -403,7 +518,9 @@ inline int64_t solve_lds_doubles_general(const std::vector<int32_t>& sizes, int 
 
 // ccol / cval: the subdomain's row coupling list of A_k,k-1 (NCPL slots per
 // padded row, CSR order), or null when the lists are incomplete; the Schur
-// step then walks the local CSR rows
+// step then walks the local CSR rows.  P = 16: the tile products run on the
+// matrix cores (tile_product_mfma), with only their input block in LDS
+// (column stride s + 1).
 template <class FT, int P, bool WIDE = true>
 __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, int n,
                                     const int64_t* __restrict__ lrow,
@@ -412,11 +529,90 @@ __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, in
                                     const int32_t* __restrict__ ccol,
                                     const double* __restrict__ cval, double* X, int64_t ldx, int pc,
                                     double* lds) {
+  constexpr bool MF = P == 16;
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t ss = tile_size(s, TileV<FT>::V);  // tile stride
+  const int ls = MF ? s + 1 : s;                  // column stride of the LDS vectors
   double* ybuf = lds;
-  double* hbuf = ybuf + (int64_t)s * P;
-  double* part = hbuf + (int64_t)s * P;
+  double* hbuf = ybuf + (int64_t)ls * P;
+  double* part = hbuf + (int64_t)ls * P;
+  if constexpr (MF) {
+    // only the product's input block in LDS; h_k and x_k go straight to X
+    // (the next step reads them there after the barrier)
+    // the vector phases take GQ entries per thread at a time, their loads
+    // issued together (each entry is an independent chain of loads)
+    constexpr int GQ = 8;
+    const int ne = s * pc;
+    for (int e = t; e < ls * P; e += T) ybuf[e] = 0.0;  // row s, columns past pc
+    for (int k = 0; k < K; ++k) {
+      const int r0 = k * s;
+      __syncthreads();
+      for (int e0 = 0; e0 < ne; e0 += T * GQ) {
+        double y[GQ];
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+          const int e = min(e0 + t + T * q, ne - 1);
+          const int rr = e % s, j = e / s;
+          y[q] = X[r0 + rr + j * ldx];
+        }
+        if (k > 0) {
+#pragma unroll
+          for (int q = 0; q < GQ; ++q) {
+            const int e = min(e0 + t + T * q, ne - 1);
+            const int rr = e % s, j = e / s;
+            const int r = r0 + rr;
+            const double* hp = X + (r0 - s) + j * ldx;  // h_{k-1}
+            if (ccol) {
+              const int32_t* cr = ccol + (int64_t)r * NCPL;
+              const double* vr = cval + (int64_t)r * NCPL;
+#pragma unroll
+              for (int m = 0; m < NCPL; ++m) {
+                const int cc = cr[m];
+                if (cc >= 0) y[q] -= vr[m] * hp[cc];
+              }
+            } else if (r < n) {
+              for (int64_t qq = lrow[r]; qq < lrow[r + 1]; ++qq) {
+                const int cc = lcol[qq] - (r0 - s);
+                if (cc >= 0 && cc < s) y[q] -= lval[qq] * hp[cc];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+          const int e = e0 + t + T * q;
+          if (e < ne) ybuf[e % s + (e / s) * ls] = y[q];
+        }
+      }
+      __syncthreads();
+      tile_product_mfma<FT>(fac + (int64_t)k * 2 * ss, s, ybuf, ls, X + r0, ldx, 0, nullptr, 0, pc);
+    }
+    for (int k = K - 2; k >= 0; --k) {
+      const int r0 = k * s;
+      __syncthreads();
+      for (int e0 = 0; e0 < ne; e0 += T * GQ) {  // x_{k+1}
+        double y[GQ];
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+          const int e = min(e0 + t + T * q, ne - 1);
+          y[q] = X[r0 + s + e % s + (e / s) * ldx];
+        }
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+          const int e = e0 + t + T * q;
+          if (e < ne) ybuf[e % s + (e / s) * ls] = y[q];
+        }
+      }
+      __syncthreads();
+      tile_product_mfma<FT>(fac + (int64_t)k * 2 * ss + ss, s, ybuf, ls, X + r0, ldx, 1, X + r0,
+                            ldx, pc);
+    }
+    __syncthreads();
+    return;
+  }
+  auto product = [&](const FT* M, int mode, const double* base) {
+    tile_product_general<FT, P, WIDE>(M, s, ybuf, part, hbuf, mode, base, ldx, pc);
+  };
   for (int k = 0; k < K; ++k) {
     const int r0 = k * s;
     __syncthreads();
@@ -431,10 +627,10 @@ __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, in
 #pragma unroll
           for (int m = 0; m < NCPL; ++m) {
             const int cc = cr[m];
-            if (cc >= 0) y -= vr[m] * hbuf[cc + j * s];
+            if (cc >= 0) y -= vr[m] * hbuf[cc + j * ls];
           }
         }
-        ybuf[rr + j * s] = y;
+        ybuf[rr + j * ls] = y;
       }
     } else {
       for (int e = t; e < s * pc; e += T) {
@@ -444,31 +640,33 @@ __device__ void block_solve_general(const FT* __restrict__ fac, int s, int K, in
         if (k > 0 && r < n) {
           for (int64_t q = lrow[r]; q < lrow[r + 1]; ++q) {
             const int cc = lcol[q] - (r0 - s);
-            if (cc >= 0 && cc < s) y -= lval[q] * hbuf[cc + j * s];
+            if (cc >= 0 && cc < s) y -= lval[q] * hbuf[cc + j * ls];
           }
         }
-        ybuf[rr + j * s] = y;
+        ybuf[rr + j * ls] = y;
       }
     }
     __syncthreads();
-    tile_product_general<FT, P, WIDE>(fac + (int64_t)k * 2 * ss, s, ybuf, part, hbuf, 0, nullptr, 0, pc);
+    product(fac + (int64_t)k * 2 * ss, 0, nullptr);
     __syncthreads();
     for (int e = t; e < s * pc; e += T) {
       const int rr = e % s, j = e / s;
-      X[r0 + rr + j * ldx] = hbuf[rr + j * s];
+      X[r0 + rr + j * ldx] = hbuf[rr + j * ls];
     }
   }
   for (int k = K - 2; k >= 0; --k) {
     const int r0 = k * s;
     __syncthreads();
-    for (int e = t; e < s * pc; e += T) ybuf[e] = hbuf[e];
+    for (int e = t; e < s * pc; e += T) {
+      const int rr = e % s, j = e / s;
+      ybuf[rr + j * ls] = hbuf[rr + j * ls];
+    }
     __syncthreads();
-    tile_product_general<FT, P, WIDE>(fac + (int64_t)k * 2 * ss + ss, s, ybuf, part, hbuf, 1, X + r0,
-                                ldx, pc);
+    product(fac + (int64_t)k * 2 * ss + ss, 1, X + r0);
     __syncthreads();
     for (int e = t; e < s * pc; e += T) {
       const int rr = e % s, j = e / s;
-      X[r0 + rr + j * ldx] = hbuf[rr + j * s];
+      X[r0 + rr + j * ldx] = hbuf[rr + j * ls];
     }
   }
   __syncthreads();

@@ -190,6 +190,33 @@ def test_apply_matches_oracle(case, variant):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [ads.ADS_PREC_FP64, ads.ADS_PREC_FP32], ids=["fp64", "fp32"])
+def test_apply_sixteen_column_chunks_on_matrix_cores(prec):
+    """More than 8 right-hand sides on the general tile solves (block sizes
+    beyond the fast path) take chunks of 16 columns on the matrix cores: 19
+    columns (a full chunk and a ragged one of 3) against the oracle (FP64
+    factors) and against the one-column solves of the same factors."""
+    case = next(c for c in CASES if c[0] == "cd3d21-3x3x3-d2-general")
+    name, A, part, N, ov, nev, restart, flex = case
+    ctx = ads.Context(A, part, N, ov, nev, precision=prec, eig_tol=1e-12)
+    assert max(ctx.info["block"]) > 100  # general path (see the case list)
+    rng = np.random.default_rng(11)
+    R = rng.standard_normal((A.n, 19))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    scale = np.abs(Z).max()
+    for j in (0, 7, 8, 15, 16, 18):
+        zj = ctx.apply(torch.tensor(R[:, j].copy(), device=DEV)).cpu().numpy()
+        err = np.abs(zj - Z[:, j]).max() / scale
+        print(f"column {j}: one-column apply vs 16-column chunk {err:.1e}", flush=True)
+        assert err <= 1e-13, (j, err)
+    if prec == ads.ADS_PREC_FP64:
+        Zo = oracle_for(case).apply(R)
+        err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+        print(f"19 columns vs oracle {err:.1e}", flush=True)
+        assert err <= 1e-9, err
+    ctx.close()
+
+
 @pytest.mark.parametrize("m,nb,nev,n0", [(96, 12, 7, 1008), (128, 16, 5, 1280), (128, 16, 7, 1792),
                                           (192, 24, 6, 3480), (256, 32, 8, 8192)],
                          ids=["n0-1008-register-panels", "n0-1280-two-rows-per-thread",
