@@ -922,7 +922,8 @@ def test_full_size_jump3d_every_subdomain_matches_oracle():
 def test_full_size_jump3d_workload_sampled():
     """The full-scale 3D family at full size (-div(k grad u) on 128^3 with log10
     k uniform in [-3, 3] on 8^3 blocks, 1024 boxes of 2048 unknowns, overlap 2,
-    nev 12, 16 right-hand sides; n0 12290 > the LDS panel limit).  The oracle
+    nev 12, 16 right-hand sides; n0 about 12288, far above the register-panel
+    orders of the coarse inversion).  The oracle
     cannot build all 1024 coarse spaces in seconds, so five subdomains (two
     corners, an edge, a face and an interior one) are compared one by one:
     index maps and layers bit-exact, nev_i exact, coarse spans within 1e-7
