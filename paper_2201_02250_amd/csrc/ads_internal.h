@@ -226,6 +226,7 @@ struct Ctx {
   int gnn_cols = 0;
   int h_eig_nblk = 0;  // row blocks of the eigensolver sweep kernels
   int h_eig_nqblk = 0;  // wide row blocks of the Krylov-Schur block QR kernels
+  std::vector<int32_t> h_eig_km;  // per subdomain Krylov-Schur Rayleigh quotient order
 
   // workspace for apply / solve
   int32_t* cover_ptr = nullptr;  // [n + 1] non-restricted variants: per global row, the

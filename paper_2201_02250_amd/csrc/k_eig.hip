@@ -917,7 +917,9 @@ struct EigArgs {
   int lrb;          // log2 of the row-block height
   // block Krylov-Schur state (block width p)
   int ks;           // 1: the operator kernels map columns jcur .. jcur + p - 1 of V
-  int km;           // largest Rayleigh quotient order
+  int km;           // largest Rayleigh quotient order (the storage of V and Bk)
+  const int32_t* kmi;     // per subdomain: its Rayleigh quotient order (<= km)
+  const int32_t* kkeepi;  // per subdomain: basis vectors kept by a restart
   double* V;        // per subdomain npad x (km + p) basis, at (km + p) * pad_off
   double* Bk;       // per subdomain (km + p) x km row-major: T V_k = V_{k+p} Bk
   int32_t* jcur;    // per subdomain: first column of the block expanded next
@@ -931,7 +933,6 @@ struct EigArgs {
   int32_t* err;
   int p;
   int nev;
-  int kkeep;        // basis vectors kept by a restart (before the cluster rule)
   double tau;
   double tol;
   int sym;          // A symmetric: the splitting is too, its left null vector is the constant
@@ -1299,7 +1300,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
   __shared__ double red[PC][16];
   __shared__ double alpha[PC], beta[PC];
   const int i = blockIdx.x, half = blockIdx.z;
-  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.km)) return;
+  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
@@ -1381,7 +1382,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_bwd(const FT* fac, EigArgs a) {
   __shared__ double red[PC][16];
   __shared__ double sums[PC];
   const int i = blockIdx.x, half = blockIdx.z;
-  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.km)) return;
+  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
@@ -1428,7 +1429,7 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   __shared__ double red[PC][16];
   __shared__ double alpha[PC], beta[PC];
   const int i = blockIdx.x;
-  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.km)) return;
+  if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
   const int pc = min(PC, p - j0);
@@ -1959,7 +1960,7 @@ __global__ void k_eig_decide(EigArgs a, int nsub, int sw, int final_sweep) {
 //   k_ks_advance: jcur += p
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool ks_active(const EigArgs& a, int i) {
-  return !a.done[i] && a.jcur[i] + a.p <= a.km;
+  return !a.done[i] && a.jcur[i] + a.p <= a.kmi[i];
 }
 
 // partial V^T Y of one row block (pass 0: the operator's output, after the
@@ -2212,7 +2213,7 @@ __global__ void __launch_bounds__(EIG_T) k_ks_rr(EigArgs a, int final_cycle) {
     int ok = 1, mk = 0;
     double gap = 1.0;
     const int m1 = small_eig_select(m, H, a.nev - a.kdim[i], a.tau, se, lam_re, lam_im, &ok, &gap,
-                                    a.kkeep - a.kdim[i], &mk, V2);
+                                    a.kkeepi[i] - a.kdim[i], &mk, V2);
     if (t == 0) {
       flag[0] = m1;
       flag[1] = ok;
@@ -2245,7 +2246,7 @@ __global__ void __launch_bounds__(EIG_T) k_ks_rr(EigArgs a, int final_cycle) {
     if (ok_tol || final_cycle) fin = ok_tol ? 1 : 2;
     // the wanted cluster must leave a Ritz value outside it, and a restart
     // must leave room for at least one more block
-    if (m1 >= m || (!fin && (mk > km - p || mk < m1))) {
+    if (m1 >= m || (!fin && (mk > a.kmi[i] - p || mk < m1))) {
       atomicOr(a.err, 16);
       fin = 2;
     }
@@ -2774,7 +2775,8 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   for (int cyc = 0;; ++cyc) {
     int nst = 0;
     for (int i = 0; i < nsub; ++i)
-      if (!hdone[i] && hj[i] + a.p <= a.km) nst = std::max(nst, (a.km - a.p - hj[i]) / a.p + 1);
+      if (!hdone[i] && hj[i] + a.p <= c.h_eig_km[i])
+        nst = std::max(nst, (c.h_eig_km[i] - a.p - hj[i]) / a.p + 1);
     for (int k = 0; k < nst; ++k) step();
     total += nst;
     ADS_LAUNCH(k_ks_rr, dim3(nsub), dim3(EIG_T), 0, st, a, (int)(total >= maxsteps));
@@ -2818,12 +2820,19 @@ void eigensolve(Ctx& c) {
   // (a larger basis means fewer restarts, each with one dense Schur
   // decomposition per subdomain: on 2D convection-diffusion subdomains with
   // nev 8, order 32 keeping 16 converges in the fewest block steps)
-  int km = std::min(PMAX, std::max(4 * nev, nev + 24));
-  for (int i = 0; i < nsub; ++i)
-    km = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
-  const int kkeep = std::min(std::max(2 * nev, km / 2), km - 2 * EIG_PC);
-  const bool ks = !warm && !c.eig_ks_lost_rank && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR &&
-                  km >= nev + 2 * EIG_PC && kkeep >= nev && kkeep + EIG_PC <= km;
+  // per subdomain, so that a small subdomain does not shorten the basis of
+  // the others (the storage takes the largest order)
+  const int km = std::min(PMAX, std::max(4 * nev, nev + 24));
+  std::vector<int32_t> h_km(nsub), h_kkeep(nsub);
+  bool ks_fits = true;
+  for (int i = 0; i < nsub; ++i) {
+    const int ki = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
+    const int kk = std::min(std::max(2 * nev, ki / 2), ki - 2 * EIG_PC);
+    h_km[i] = ki;
+    h_kkeep[i] = kk;
+    ks_fits = ks_fits && ki >= nev + 2 * EIG_PC && kk >= nev && kk + EIG_PC <= ki;
+  }
+  const bool ks = !warm && !c.eig_ks_lost_rank && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && ks_fits;
   if (!ks && p < nev + 1)
     fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
   c.eig_krylov_schur = ks;
@@ -2929,7 +2938,9 @@ void eigensolve(Ctx& c) {
   if (ks) {
     a.ks = 1;
     a.km = km;
-    a.kkeep = kkeep;
+    a.kmi = upload(c.mem, h_km.data(), nsub, st);
+    c.h_eig_km = h_km;
+    a.kkeepi = upload(c.mem, h_kkeep.data(), nsub, st);
     a.Bk = c.mem.alloc<double>((size_t)nsub * KS_BS);
     ADS_HIP(hipMemsetAsync(a.Bk, 0, (size_t)nsub * KS_BS * 8, st));
     std::vector<int32_t> j0(nsub, -EIG_PC);

@@ -794,49 +794,133 @@ def test_full_size_batched_2d_family_matches_oracle():
     below 1e-12), and M^{-1} follows the span.  FP32 factors: FGMRES(30) of
     all 32 systems at once, each to 1e-8, iterations at most the oracle's + 2,
     solutions within 1e-8 or the residual bound (assert_solution_close)."""
+    As, parts, Ns = _c3b_systems()
+    assert sum(Ns) == 435 and sum(A.n for A in As) == 399086
+    _check_batch_against_oracles(As, parts, Ns, 2, 10, 30)
+
+
+def _c3b_systems():
     from workloads.problems import c3b_sizes
-    sizes = c3b_sizes()
     As, parts, Ns = [], [], []
-    for m in sizes:
+    for m in c3b_sizes():
         p = max(2, round(m / 32))
         As.append(W.convdiff2d(m, 0.01))
         parts.append(W.block_partition_2d(m, p))
         Ns.append(p * p)
-    assert sum(Ns) == 435 and sum(A.n for A in As) == 399086
+    return As, parts, Ns
+
+
+def _oracle_apply_with_basis(P, Ws, r):
+    """eq. 4 from the oracle's pieces (its local solves, sums and A) with a
+    given coarse basis Ws (interior rows of each subdomain, ascending)."""
+    rows, cols, vals, off = [], [], [], 0
+    for sub, Wi in zip(P.subs, Ws):
+        rows.append(np.repeat(sub.interior, Wi.shape[1]))
+        cols.append(np.tile(np.arange(off, off + Wi.shape[1]), len(sub.interior)))
+        vals.append(Wi.ravel())
+        off += Wi.shape[1]
+    Z = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(P.n, off))
+    q = Z @ np.linalg.solve((Z.T @ (P.A @ Z)).toarray(), Z.T @ r)
+    return q + P.one_level(r - P.A @ q, restricted=True)
+
+
+def _check_batch_against_oracles(As, parts, Ns, ov, nev, restart):
+    """One context over every system: FP64 (eigensolver to 1e-12) nev_i exact
+    per system, eigensolver residuals <= 1e-10, coarse spans within 1e-4 rad
+    of each system's own oracle, and the apply within 1e-9 of the oracle's
+    eq. 4 evaluated with the GPU's coarse basis (on some nonsymmetric
+    subdomains the selected invariant subspace is itself sensitive: the
+    oracle's own ARPACK runs from different start vectors differ by up to
+    7.4e-6 rad, and M^{-1} follows the span, so the span is judged by the
+    residual and the angle and the apply with the span fixed); FP32 factors:
+    FGMRES of all systems at once, each to 1e-8 with at most the oracle's
+    iterations + 2, solutions within 1e-8 or the residual bound."""
     offs = np.cumsum([0] + [A.n for A in As])
     r = np.random.default_rng(17).standard_normal(offs[-1])
     b = np.concatenate([W.rhs(A.n, k) for k, A in enumerate(As)])
-    c64 = ads.Context(As, parts, Ns, 2, 10, eig_tol=1e-12)
+    c64 = ads.Context(As, parts, Ns, ov, nev, eig_tol=1e-12)
     z = c64.apply(torch.tensor(r, device=DEV)).cpu().numpy()
     Wg, woff, _, cinfo = ads.ads_export_coarse(c64.ctx)
     nev_gpu = np.asarray(cinfo["nev_i"])
     nint = np.asarray(cinfo["n_interior"])
     assert np.asarray(c64.info["eig_resid"]).max() <= 1e-10
     c64.close()
-    c32 = ads.Context(As, parts, Ns, 2, 10, precision=ads.ADS_PREC_FP32)
-    x, info = c32.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    c32 = ads.Context(As, parts, Ns, ov, nev, precision=ads.ADS_PREC_FP32)
+    x, info = c32.solve(torch.tensor(b, device=DEV), restart=restart, flexible=True, rtol=1e-8)
     x = x.cpu().numpy()
     c32.close()
     k0 = 0
     for k, (A, p, N) in enumerate(zip(As, parts, Ns)):
         As_ = A.to_scipy()
-        P = OS.TwoLevelSchwarz(As_, p, N, 2, 10)
+        P = OS.TwoLevelSchwarz(As_, p, N, ov, nev)
         np.testing.assert_array_equal(nev_gpu[k0:k0 + N], P.nev_i)
-        ang = 0.0
+        ang, Ws = 0.0, []
         for i in range(N):
             g = k0 + i
             Wi = Wg[woff[g]:woff[g + 1]].reshape(int(nint[g]), int(nev_gpu[g]))
             ang = max(ang, float(sla.subspace_angles(Wi, P.W[i]).max()))
+            Ws.append(Wi)
         assert ang <= 1e-4, (k, ang)
-        tol = max(1e-9, 3e-2 * ang)
         k0 += N
         sl = slice(offs[k], offs[k + 1])
-        zo = P.apply(r[sl])
-        assert np.abs(z[sl] - zo).max() <= tol * np.abs(zo).max(), (k, tol)
-        xo, io = OS.gmres(As_, b[sl], P.apply, restart=30, rtol=1e-8, flexible=True)
+        zo = _oracle_apply_with_basis(P, Ws, r[sl])
+        assert np.abs(z[sl] - zo).max() <= 1e-9 * np.abs(zo).max(), k
+        xo, io = OS.gmres(As_, b[sl], P.apply, restart=restart, rtol=1e-8, flexible=True)
         assert info["statuses"][k] == 0 and info["its"][k] <= io["its"] + 2, (k, info["its"][k], io["its"])
         assert np.linalg.norm(b[sl] - As_ @ x[sl]) / np.linalg.norm(b[sl]) <= 1e-8, k
         assert_solution_close(As_, b[sl], x[sl], xo, f"system {k}")
+        print(f"system {k}: n {A.n}, {N} subdomains, n0 {P.n0}, span angle {ang:.1e}, "
+              f"its {info['its'][k]} (oracle {io['its']})", flush=True)
+
+
+def test_full_size_c3_combined_batch_matches_oracle():
+    """The batched workload as one launch per phase: the 3D convection-
+    diffusion system (64^3, 256 BFS-grown subdomains of uneven size) and the
+    32 independent 2D systems (sides 16 to 256, 435 subdomains) in one
+    context, overlap 2, nev 10, FGMRES(30): 33 systems, 691 subdomains,
+    661,230 unknowns, every one checked against its own oracle as above."""
+    A3, _, _, o = W.config("c3a_convdiff3d_64_bfs256")
+    part3 = ads.ads_partition_bfs(A3, o["seeds"])
+    As, parts, Ns = _c3b_systems()
+    As, parts, Ns = [A3] + As, [part3] + parts, [len(o["seeds"])] + Ns
+    assert sum(Ns) == 691 and sum(A.n for A in As) == 661230
+    _check_batch_against_oracles(As, parts, Ns, 2, 10, 30)
+
+
+@pytest.mark.parametrize("solver", [0, 1], ids=["krylov-schur", "subspace"])
+def test_subdomains_of_uneven_size_keep_their_own_basis(solver):
+    """A partition with one small subdomain (4 x 5 interior points in a corner
+    of a 24 x 24 Laplacian, the others up to 7 x 7): the Krylov-Schur basis is
+    sized per subdomain (19 vectors for the small one, 28 for the others), so
+    the small one neither shortens the others' nor switches the method off;
+    the coarse space matches the oracle's (spans within 1e-7 rad,
+    eigenvalues within 1e-8, nev_i and n0 exact)."""
+    m = 24
+    A = W.laplace2d(m)
+    xs, ys = [0, 4, 10, 17, 24], [0, 5, 12, 18, 24]
+    part = np.zeros(A.n, np.int32)
+    for y in range(m):
+        for x in range(m):
+            part[y * m + x] = (np.searchsorted(ys, y, side="right") - 1) * 4 + np.searchsorted(xs, x, side="right") - 1
+    N, ov, nev = 16, 1, 4
+    assert np.bincount(part).min() == 20
+    ctx = ads.Context(A, part, N, ov, nev, eig_solver=solver, eig_tol=1e-12)
+    P = OS.TwoLevelSchwarz(A.to_scipy(), part, N, ov, nev)
+    Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+    assert info["eig_solver"] == solver and info["eig_unconverged"] == 0
+    np.testing.assert_array_equal(info["nev_i"], P.nev_i)
+    assert info["n0"] == P.n0
+    k = 0
+    for i in range(N):
+        mi = int(info["nev_i"][i])
+        Wi = Wg[woff[i]:woff[i + 1]].reshape(int(info["n_interior"][i]), mi)
+        assert sla.subspace_angles(Wi, P.W[i]).max() < 1e-7, i
+        lam_g = lam[k + P.eig[i]["kernel"]: k + mi]
+        k += mi
+        for x in P.eig[i]["lam_sel"]:
+            assert np.min(np.abs(lam_g - x)) <= 1e-8 * abs(x), (i, x)
+    ctx.close()
 
 
 def _oracle_subdomain(As, G, part, i, overlap):
