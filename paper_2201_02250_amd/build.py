@@ -29,21 +29,45 @@ def _run(cmd, verbose):
         raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
 
 
-def build(verbose=False, jobs=None):
+# host-code sanitizers (AddressSanitizer and UndefinedBehaviorSanitizer on
+# the host pass only; the device code is built as usual)
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-O1"]
+
+
+def build(verbose=False, jobs=None, sanitize=False, out=None):
+    """Build libads.so in-tree; sanitize=True builds the host code with ASan
+    and UBSan into out (for the host-sanitizer test), linked against the
+    shared sanitizer runtimes."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = ["-I", os.path.join(HERE, "..", "include")]
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
+    out = out or OUT
+    extra = HOST_SANITIZE if sanitize else []
     with tempfile.TemporaryDirectory(prefix="ads_build_") as tmpd:
         objs = [os.path.join(tmpd, s.replace(".hip", ".o")) for s in SOURCES]
-        cmds = [[hipcc, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o]
+        cmds = [[hipcc, *FLAGS, *extra, *inc, "-c", os.path.join(CSRC, s), "-o", o]
                 for s, o in zip(SOURCES, objs)]
         with cf.ThreadPoolExecutor(jobs) as ex:
             for f in [ex.submit(_run, c, verbose) for c in cmds]:
                 f.result()
-        tmp = OUT + ".tmp"
-        _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
-        os.replace(tmp, OUT)
-    return OUT
+        tmp = out + ".tmp"
+        if sanitize:
+            # the objects carry their device code; the LLVM driver links them
+            # with the HIP runtime and the shared sanitizer runtimes
+            rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc)))
+            clangxx = os.path.join(rocm, "llvm", "bin", "clang++")
+            rt = os.path.dirname(subprocess.run(
+                [clangxx, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                text=True).stdout.strip())
+            _run([clangxx, "-shared", "-fPIC", "-fsanitize=address,undefined", "-shared-libsan",
+                  *objs, "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
+                  "-Wl,-rpath," + os.path.join(rocm, "lib"), "-Wl,-rpath," + rt, "-o", tmp], verbose)
+        else:
+            _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+        os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

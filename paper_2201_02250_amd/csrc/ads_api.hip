@@ -226,8 +226,21 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     fail(ADS_ERR_ARG, "warm_start needs gnn_weights_path");
   if (opts->eig_solver != ADS_EIG_KRYLOV_SCHUR && opts->eig_solver != ADS_EIG_SUBSPACE)
     fail(ADS_ERR_ARG, "unknown eig_solver");
+  // every system's arguments, before any device call
+  for (int s = 0; s < nsys; ++s) {
+    if (A[s].n <= 0 || A[s].n >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "n out of range");
+    if (A[s].nnz < 0 || A[s].nnz >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "nnz out of range");
+    if (!A[s].row_ptr || !A[s].col || !A[s].val) fail(ADS_ERR_ARG, "null CSR array");
+    if (!part[s]) fail(ADS_ERR_ARG, "null partition");
+    if (nparts[s] <= 0) fail(ADS_ERR_ARG, "nparts must be positive");
+  }
+  ads_gnn_shape gshape{};
+  std::vector<float> gmaster;
+  if (opts->warm_start) read_gnn_weights(opts->gnn_weights_path, &gshape, &gmaster);
   auto c = new Ctx();
   try {
+    c->gnn_shape = gshape;
+    c->gnn_master = std::move(gmaster);
     c->stream = st;
     c->mem.stream = st;
     c->opt = *opts;
@@ -241,11 +254,6 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->sys_sub.assign(nsys + 1, 0);
     std::vector<int64_t> sys_nnz(nsys + 1, 0);
     for (int s = 0; s < nsys; ++s) {
-      if (A[s].n <= 0 || A[s].n >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "n out of range");
-      if (A[s].nnz < 0 || A[s].nnz >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "nnz out of range");
-      if (!A[s].row_ptr || !A[s].col || !A[s].val) fail(ADS_ERR_ARG, "null CSR array");
-      if (!part[s]) fail(ADS_ERR_ARG, "null partition");
-      if (nparts[s] <= 0) fail(ADS_ERR_ARG, "nparts must be positive");
       c->sys_row[s + 1] = c->sys_row[s] + A[s].n;
       c->sys_sub[s + 1] = c->sys_sub[s] + nparts[s];
       sys_nnz[s + 1] = sys_nnz[s] + A[s].nnz;

@@ -224,6 +224,8 @@ struct Ctx {
   // order x gnn_cols, FP32), set by learned_start for the eigensolve
   float* gnn_x = nullptr;
   int gnn_cols = 0;
+  ads_gnn_shape gnn_shape{};        // the weights file, read while the arguments
+  std::vector<float> gnn_master;    // are checked (FP32 master parameters)
   int h_eig_nblk = 0;  // row blocks of the eigensolver sweep kernels
   int h_eig_nqblk = 0;  // wide row blocks of the Krylov-Schur block QR kernels
   std::vector<int32_t> h_eig_km;  // per subdomain Krylov-Schur Rayleigh quotient order
@@ -309,8 +311,11 @@ void gnn_forward_impl(const ads_gnn_shape& s, const uint16_t* params, const ads_
 void gnn_graph_impl(const Ctx& c, int64_t* node_off, int64_t* row_ptr, int32_t* col, float* w,
                     float* feat, uint8_t* mask, hipStream_t st);
 int64_t gnn_edges(const Ctx& c);
-// loads ads_options.gnn_weights_path and runs the network on the context's
-// subdomain graphs into c.gnn_x
+// reads and checks a weights file (host only; ADS_ERR_ARG on a missing,
+// malformed, mis-shaped or truncated file)
+void read_gnn_weights(const char* path, ads_gnn_shape* shape, std::vector<float>* master);
+// runs the network (parameters read by read_gnn_weights into c.gnn_shape /
+// c.gnn_master) on the context's subdomain graphs into c.gnn_x
 void learned_start(Ctx& c);
 
 // ---------------------------------------------------------------------------

@@ -564,22 +564,20 @@ void gnn_graph_impl(const Ctx& c, int64_t* node_off, int64_t* row_ptr, int32_t* 
 
 int64_t gnn_edges(const Ctx& c) { return c.lnnz - c.omega_total; }
 
-void learned_start(Ctx& c) {
-  hipStream_t st = c.stream;
-  const char* path = c.opt.gnn_weights_path;
+void read_gnn_weights(const char* path, ads_gnn_shape* shape, std::vector<float>* master) {
   if (!path) fail(ADS_ERR_ARG, "warm_start needs gnn_weights_path");
   FILE* f = std::fopen(path, "rb");
   if (!f) fail(ADS_ERR_ARG, std::string("cannot open the weights file ") + path);
-  char magic[8];
-  int32_t sh[4];
+  char magic[8] = {0};
+  int32_t sh[4] = {0, 0, 0, 0};
   int64_t np = 0;
   const bool head = std::fread(magic, 1, 8, f) == 8 && std::fread(sh, 4, 4, f) == 4 &&
                     std::fread(&np, 8, 1, f) == 1;
-  ads_gnn_shape s{sh[0], sh[1], sh[2], sh[3]};
   if (!head || std::string(magic, 8) != "ADSGNN01") {
     std::fclose(f);
     fail(ADS_ERR_ARG, "not a weights file (magic ADSGNN01)");
   }
+  const ads_gnn_shape s{sh[0], sh[1], sh[2], sh[3]};
   try {
     check_shape(&s);
   } catch (...) {
@@ -590,10 +588,18 @@ void learned_start(Ctx& c) {
     std::fclose(f);
     fail(ADS_ERR_ARG, "weights file: shape does not match the node features");
   }
-  std::vector<float> master(np);
-  const bool body = std::fread(master.data(), 4, np, f) == (size_t)np;
+  master->assign(np, 0.0f);
+  const bool body = std::fread(master->data(), 4, np, f) == (size_t)np;
   std::fclose(f);
   if (!body) fail(ADS_ERR_ARG, "weights file truncated");
+  *shape = s;
+}
+
+void learned_start(Ctx& c) {
+  hipStream_t st = c.stream;
+  const ads_gnn_shape s = c.gnn_shape;
+  const std::vector<float>& master = c.gnn_master;
+  const int64_t np = (int64_t)master.size();
   Arena mem(st);
   float* dm = upload(mem, master.data(), np, st);
   uint16_t* pb = mem.alloc<uint16_t>(np);
@@ -614,6 +620,8 @@ void learned_start(Ctx& c) {
   ADS_HIP(hipStreamSynchronize(st));
   c.gnn_x = X;
   c.gnn_cols = s.n_out;
+  c.gnn_master.clear();
+  c.gnn_master.shrink_to_fit();
 }
 
 }  // namespace ads
