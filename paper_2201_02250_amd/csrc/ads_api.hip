@@ -300,6 +300,18 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->t_phase_ms[1] = tm.lap();
     tune_tiles(*c);
     c->t_phase_ms[7] = tm.lap();
+    {
+      // per-subdomain launches take the longest chains first: decreasing
+      // (2K - 1) s^2 (tile entries walked by one factorization or solve)
+      std::vector<int32_t> ord(c->nsub);
+      std::vector<int64_t> cost(c->nsub);
+      for (int i = 0; i < c->nsub; ++i) {
+        ord[i] = i;
+        cost[i] = (int64_t)(2 * c->h_nb[i] - 1) * c->h_bs[i] * c->h_bs[i];
+      }
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+      c->sub_order = upload(c->mem, ord.data(), c->nsub, st);
+    }
     factor_local(*c);
     c->local_resid = local_solve_accuracy(*c);
     // BF16 factors (8-bit significands) on strongly varying coefficients: a

@@ -168,6 +168,7 @@ struct Ctx {
   double* lval = nullptr;
   double* lsum = nullptr;       // [omega_total] lumped s (0 on interior rows), sorted order
   int32_t* kdim = nullptr;      // [nsub] kernel dimension of the splitting (0/1)
+  int32_t* sub_order = nullptr; // [nsub] subdomains by decreasing (2K - 1) s^2 (longest first)
   std::vector<int32_t> h_kdim;
 
   // block-tridiagonal factors
@@ -459,6 +460,12 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // columns padded with zeros to a multiple of V.  A thread that owns row r and
 // a run of columns then fetches V entries with one 16-byte load, and lanes
 // with consecutive rows read consecutive 16-byte words (fully coalesced).
+// subdomain of block b of a per-subdomain launch: the blocks take the
+// subdomains in decreasing order of their chain cost (order, set at setup),
+// so that the dispatcher, which starts blocks in index order as compute
+// units free up, schedules the longest chains first
+__device__ __forceinline__ int sub_of(const int32_t* order, int b) { return order ? order[b] : b; }
+
 template <class FT>
 struct TileV {
   static constexpr int V = 16 / (int)sizeof(FT);

@@ -340,6 +340,7 @@ struct LocalArgs {
   int64_t n;
   int64_t vec_lds_off;  // doubles before the LDS-resident vector
   double* dummy;        // one slot per thread of the launch (stores of idle threads)
+  const int32_t* order; // subdomain of each block (longest chains first)
 };
 
 // Fast path: the two-ended solve in two launches per apply.
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(adsd::SOLVE_T)
 k_local_fwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ r,
             const double* __restrict__ q, int nrhs) {
   extern __shared__ double lds[];
-  const int i = blockIdx.x, half = blockIdx.z;
+  const int i = adsd::sub_of(a.order, blockIdx.x), half = blockIdx.z;
   const int j0 = blockIdx.y * P;
   const int pc = min(P, nrhs - j0);
   const int s = a.bs[i], K = a.nb[i], ns = a.ni[i], M = K / 2;
@@ -378,7 +379,7 @@ __global__ void __launch_bounds__(adsd::SOLVE_T)
 k_local_bwd(const FT* __restrict__ fac, LocalArgs a, const double* __restrict__ q,
             double* __restrict__ z, int nrhs) {  // z = nullptr: no owner scatter
   extern __shared__ double lds[];
-  const int i = blockIdx.x, half = blockIdx.z;
+  const int i = adsd::sub_of(a.order, blockIdx.x), half = blockIdx.z;
   const int j0 = blockIdx.y * P;
   const int pc = min(P, nrhs - j0);
   const int s = a.bs[i], K = a.nb[i], ns = a.ni[i], M = K / 2;
@@ -410,7 +411,7 @@ __device__ __forceinline__ void local_solve_general(const FT* __restrict__ fac, 
                                                     const double* __restrict__ qs,
                                                     double* __restrict__ z, int nrhs) {
   extern __shared__ double lds[];
-  const int i = blockIdx.x;
+  const int i = adsd::sub_of(a.order, blockIdx.x);
   const int j0 = blockIdx.y * P;
   const int pc = min(P, nrhs - j0);
   const int s = a.bs[i], K = a.nb[i], ns = a.ni[i];
@@ -594,6 +595,7 @@ static LocalArgs local_args(Ctx& c, const ApplyWs& w) {
   a.n = c.n;
   a.vec_lds_off = 0;
   a.dummy = w.dummy;
+  a.order = c.sub_order;
   return a;
 }
 

@@ -936,6 +936,7 @@ struct EigArgs {
   double tau;
   double tol;
   int sym;          // A symmetric: the splitting is too, its left null vector is the constant
+  const int32_t* order;  // subdomain of each block of the operator launches (longest first)
 };
 
 // transposed solve with the splitting tiles for the left null vector:
@@ -1299,7 +1300,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[PC][16];
   __shared__ double alpha[PC], beta[PC];
-  const int i = blockIdx.x, half = blockIdx.z;
+  const int i = adsd::sub_of(a.order, blockIdx.x), half = blockIdx.z;
   if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
@@ -1381,7 +1382,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_bwd(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[PC][16];
   __shared__ double sums[PC];
-  const int i = blockIdx.x, half = blockIdx.z;
+  const int i = adsd::sub_of(a.order, blockIdx.x), half = blockIdx.z;
   if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
@@ -1428,7 +1429,7 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[PC][16];
   __shared__ double alpha[PC], beta[PC];
-  const int i = blockIdx.x;
+  const int i = adsd::sub_of(a.order, blockIdx.x);
   if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
   const int p = a.p;
@@ -2959,6 +2960,7 @@ void eigensolve(Ctx& c) {
   a.tau = c.opt.tau;
   a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
   a.sym = c.sym ? 1 : 0;
+  a.order = c.sub_order;
   ADS_HIP(hipMemsetAsync(a.done, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.sweeps, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.msel, 0, nsub * 4, st));

@@ -199,6 +199,7 @@ struct FacArgs {
   double* mid;              // per (subdomain, matrix, half): the FP64 tile next to the middle
   int64_t mid_stride;
   int32_t* bad_pivot;
+  const int32_t* order;  // subdomain of each block (longest chains first)
 };
 
 // Per-workgroup state of the register-resident block factorization.
@@ -368,7 +369,7 @@ struct BlockFac {
 template <class FT, bool USE_LDS, int FMR>
 __global__ void __launch_bounds__(1024) k_factor_chain(FacArgs a, FT* facA, FT* facT) {
   extern __shared__ double lds[];
-  const int i = blockIdx.x, splitting = blockIdx.y, half = blockIdx.z;
+  const int i = adsd::sub_of(a.order, blockIdx.x), splitting = blockIdx.y, half = blockIdx.z;
   double* base = USE_LDS ? lds
                          : a.gscr + (((int64_t)splitting * gridDim.x + i) * 2 + half) * a.gscr_stride;
   BlockFac<FT, FMR> B(a, i, splitting, base);
@@ -399,7 +400,7 @@ __global__ void __launch_bounds__(1024) k_factor_chain(FacArgs a, FT* facA, FT* 
 template <class FT, bool USE_LDS, int FMR>
 __global__ void __launch_bounds__(1024) k_factor_mid(FacArgs a, FT* facA, FT* facT) {
   extern __shared__ double lds[];
-  const int i = blockIdx.x, splitting = blockIdx.y;
+  const int i = adsd::sub_of(a.order, blockIdx.x), splitting = blockIdx.y;
   double* base = USE_LDS ? lds : a.gscr + ((int64_t)splitting * gridDim.x + i) * 2 * a.gscr_stride;
   BlockFac<FT, FMR> B(a, i, splitting, base);
   const int s = B.s, K = B.K, M = K / 2;
@@ -431,6 +432,7 @@ static void factor_fast(Ctx& c, bool both) {
   size_t need = ((size_t)2 * smax * smax + 4 * smax) * sizeof(double);
   const bool use_lds = need <= 150 * 1024;
   FacArgs a{};
+  a.order = c.sub_order;
   a.lrow = c.lptr_off;
   a.lcol = c.lcol;
   a.lval = c.lval;
@@ -655,22 +657,17 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   *out = fac;
   constexpr int V = adsd::TileV<FT>::V;
   std::vector<int64_t> hd(nsub + 1, 0);
-  std::vector<int32_t> hs(nsub + 1, 0);
   int smax = 0, kmax = 0;
   for (int i = 0; i < nsub; ++i) {
     const int b = c.h_bs[i];
     hd[i + 1] = hd[i] + (int64_t)b * b;
-    hs[i + 1] = hs[i] + b;
     smax = std::max(smax, b);
     kmax = std::max(kmax, (int)c.h_nb[i]);
   }
   int64_t* d_off = upload(c.mem, hd.data(), nsub + 1, st);
-  int32_t* s_off = upload(c.mem, hs.data(), nsub + 1, st);
   double* D = c.mem.alloc<double>(hd[nsub]);
   double* F = c.mem.alloc<double>(hd[nsub]);
   double* Pp = c.mem.alloc<double>(hd[nsub]);
-  int32_t* bad = c.mem.alloc<int32_t>(1);
-  ADS_HIP(hipMemsetAsync(bad, 0, 4, st));
   BfArgs a{c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
            c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, d_off};
   const dim3 gb(nsub, (unsigned)((smax + BF_RB - 1) / BF_RB));
@@ -678,29 +675,68 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   const int rb = std::max(1, std::min(8, 10240 / std::max(smax, 1)));
   const dim3 gs(nsub, (unsigned)((smax + rb - 1) / rb));
   const size_t st_lds = (size_t)2 * rb * smax * 8;
-  std::vector<int32_t> orders(nsub);
+  // block step k inverts the D_k of the subdomains that still have a block
+  // k (a batch of the active ones, at offsets into the same buffers, with
+  // their own largest order), so subdomains of few large blocks are not
+  // inverted again while others with many small blocks continue
+  std::vector<std::vector<int32_t>> act(kmax);
+  std::vector<int64_t> h_eoff;
+  std::vector<int32_t> h_soff;
+  std::vector<size_t> at_e(kmax), at_s(kmax);
   for (int k = 0; k < kmax; ++k) {
-    for (int i = 0; i < nsub; ++i) orders[i] = k < c.h_nb[i] ? c.h_bs[i] : 0;
+    for (int i = 0; i < nsub; ++i)
+      if (k < c.h_nb[i]) act[k].push_back(i);
+    at_e[k] = h_eoff.size();
+    at_s[k] = h_soff.size();
+    int32_t so = 0;
+    h_soff.push_back(0);
+    for (int i : act[k]) {
+      h_eoff.push_back(hd[i]);
+      so += c.h_bs[i];
+      h_soff.push_back(so);
+    }
+  }
+  int64_t* eoff = upload(c.mem, h_eoff.data(), std::max<size_t>(h_eoff.size(), 1), st);
+  int32_t* soff = upload(c.mem, h_soff.data(), h_soff.size(), st);
+  int32_t* bads = c.mem.alloc<int32_t>(kmax);  // per step: active index + 1 of a zero pivot
+  ADS_HIP(hipMemsetAsync(bads, 0, (size_t)kmax * 4, st));
+  std::vector<int32_t> orders;
+  for (int k = 0; k < kmax; ++k) {
+    const int na = (int)act[k].size();
+    int smx = 0;
+    int64_t tot = 0;
+    orders.assign(na, 0);
+    for (int j = 0; j < na; ++j) {
+      const int b = c.h_bs[act[k][j]];
+      smx = std::max(smx, b);
+      tot += (int64_t)b * b;
+      orders[j] = b;
+    }
+    const int64_t* ek = eoff + at_e[k];
+    const int32_t* sk = soff + at_s[k];
+    const int64_t nrow = h_soff[at_s[k] + na];
     ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
     // symmetric A: the D_k are symmetric positive definite (Schur complements
     // of the SPD local matrices), inverted without interchanges; a pivot that
     // is not positive sends this block step back to partial pivoting
-    double* inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad,
-                                    c.sym, orders.data());
+    double* inv =
+        gj_invert_batched(c, st, na, smx, nrow, tot, D, F, ek, sk, bads + k, c.sym, orders.data());
     if (!inv) {
       ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
-      inv = gj_invert_batched(c, st, nsub, smax, hs[nsub], hd[nsub], D, F, d_off, s_off, bad, false,
+      inv = gj_invert_batched(c, st, na, smx, nrow, tot, D, F, ek, sk, bads + k, false,
                               orders.data());
     }
     ADS_LAUNCH((k_bf_store<FT>), gs, dim3(256), st_lds, st, a, k, inv, Pp, fac, rb);
   }
   std::vector<int32_t> hb;
-  download(hb, bad, 1, st);
-  for (void* q : {(void*)D, (void*)F, (void*)Pp, (void*)bad, (void*)d_off, (void*)s_off})
+  download(hb, bads, kmax, st);
+  for (void* q : {(void*)D, (void*)F, (void*)Pp, (void*)d_off, (void*)eoff, (void*)soff,
+                  (void*)bads})
     c.mem.release(q);
-  if (hb[0])
-    fail(ADS_ERR_SINGULAR, std::string("zero pivot in the ") + (splitting ? "splitting" : "local matrix") +
-                               " of subdomain " + std::to_string(hb[0] - 1));
+  for (int k = 0; k < kmax; ++k)
+    if (hb[k])
+      fail(ADS_ERR_SINGULAR, std::string("zero pivot in the ") + (splitting ? "splitting" : "local matrix") +
+                                 " of subdomain " + std::to_string(act[k][hb[k] - 1]));
 }
 
 void release_factors(Ctx& c) {
