@@ -103,7 +103,12 @@ typedef struct {
   int32_t overlap;        /* delta >= 0: graph layers added to each part (Section 2)  */
   int32_t nev;            /* >= 0: coarse vectors per subdomain, kernel part included
                              (eq. 6); a cut inside a cluster of equal |lambda| takes
-                             the whole cluster, so nev_i may exceed nev              */
+                             the whole cluster, so nev_i may exceed nev.  At most 30;
+                             with tau > 0 it is the cap of the tau rule, at most 60
+                             (the paper's setting: tau = 0.3, 60): the eigensolver
+                             resolves 24 per subdomain, and a subdomain where the
+                             rule keeps all 24 while the cap allows more is refused
+                             with ADS_ERR_UNSUPPORTED                               */
   double tau;             /* <= 0: off; > 0: keep only |lambda| > 1/tau (eq. 6)       */
   int32_t variant;        /* ADS_VARIANT_*                                            */
   int32_t precision;      /* ADS_PREC_*                                               */

@@ -216,7 +216,10 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
   if (!A || !part || !nparts || !opts) fail(ADS_ERR_ARG, "null argument");
   if (opts->abi_version != ADS_ABI_VERSION) fail(ADS_ERR_ARG, "abi_version mismatch");
   if (opts->overlap < 0 || opts->overlap > 16) fail(ADS_ERR_ARG, "overlap must be in [0, 16]");
-  if (opts->nev < 0 || opts->nev > 30) fail(ADS_ERR_ARG, "nev must be in [0, 30]");
+  // nev is the coarse vectors per subdomain, or with the tau rule of eq. 6
+  // their cap (the paper's setting: tau = 0.3, at most 60)
+  if (opts->nev < 0 || opts->nev > (opts->tau > 0 ? 60 : 30))
+    fail(ADS_ERR_ARG, "nev must be in [0, 30] (in [0, 60] as the cap of the tau rule)");
   if (opts->variant < ADS_VARIANT_DEFLATED || opts->variant > ADS_VARIANT_ADDITIVE_RAS)
     fail(ADS_ERR_ARG, "unknown variant");
   if (opts->precision < ADS_PREC_FP64 || opts->precision > ADS_PREC_BF16)

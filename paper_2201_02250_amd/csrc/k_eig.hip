@@ -2795,10 +2795,20 @@ static void eig_run_ks(Ctx& c, EigArgs& a, const FT* fac) {
   ADS_HIP(hipStreamSynchronize(st));
 }
 
+// eigenpairs the eigensolver resolves per subdomain (kernel part included):
+// a Rayleigh quotient of order PMAX with room for two expansion blocks
+static constexpr int NEV_SOLVE_MAX = PMAX - 2 * EIG_PC;
+
 void eigensolve(Ctx& c) {
   hipStream_t st = c.stream;
   const int nsub = c.nsub;
-  const int nev = c.opt.nev;
+  // with the tau rule of eq. 6, opt.nev is a cap (up to 60); the eigensolver
+  // resolves at most NEV_SOLVE_MAX of them and the rule keeps those above
+  // 1/tau; a subdomain where even the last resolved one is kept would need
+  // more, and is refused below instead of being truncated
+  const int nev_cap = c.opt.nev;
+  const bool tau_cap = c.opt.tau > 0 && nev_cap > NEV_SOLVE_MAX;
+  const int nev = tau_cap ? NEV_SOLVE_MAX : nev_cap;
   if (c.gnn_x && c.opt.warm_start == 2) {
     // learned coarse space: the network's block itself, orthonormalised
     if (learned_coarse(c)) return;
@@ -3044,6 +3054,11 @@ void eigensolve(Ctx& c) {
       fail(ADS_ERR_UNSUPPORTED, "eigenvalue cluster at the cut exceeds the subspace size in subdomain " +
                                     std::to_string(i));
     c.h_nev[i] = hm[i] + c.h_kdim[i];
+    if (tau_cap && c.h_nev[i] >= nev)
+      fail(ADS_ERR_UNSUPPORTED, "the tau rule keeps all " + std::to_string(nev) +
+                                    " eigenpairs the eigensolver resolves in subdomain " +
+                                    std::to_string(i) + " (cap " + std::to_string(nev_cap) +
+                                    "); use a smaller tau or nev <= " + std::to_string(nev));
     if (c.h_nev[i] > 32) fail(ADS_ERR_UNSUPPORTED, "more than 32 coarse vectors in one subdomain");
     c.h_coff[i + 1] = c.h_coff[i] + c.h_nev[i];
     c.h_W_off[i + 1] = c.h_W_off[i] + (int64_t)c.h_nI[i] * c.h_nev[i];

@@ -888,6 +888,77 @@ def test_full_size_c3_combined_batch_matches_oracle():
     _check_batch_against_oracles(As, parts, Ns, 2, 10, 30)
 
 
+@pytest.mark.parametrize("name", ["cd40-blocks3-d2", "ln48-4x4-d1"])
+def test_paper_tau_rule_with_sixty_eigenpair_cap(name):
+    """The paper's setting for eq. 6 (Section 4): tau = 0.3, at most 60
+    eigenpairs per subdomain, against the oracle run with the same rule:
+    nev_i and n0 exact, spans within 1e-7 rad, the apply within 1e-9 and
+    GMRES iterations within +-1 (the rule keeps at most 17 eigenpairs per
+    subdomain on the workloads here, below what the eigensolver resolves)."""
+    case = next(c for c in CASES if c[0] == name)
+    _, A, part, N, ov, _, restart, flex = case
+    ctx = ads.Context(A, part, N, ov, 60, tau=0.3, eig_tol=1e-12)
+    P = OS.TwoLevelSchwarz(A.to_scipy(), part, N, ov, 60, tau=0.3)
+    Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+    np.testing.assert_array_equal(info["nev_i"], P.nev_i)
+    assert info["n0"] == P.n0
+    print(f"{name}: tau 0.3, cap 60: nev_i {list(info['nev_i'])}, n0 {info['n0']}", flush=True)
+    for i in range(N):
+        mi = int(info["nev_i"][i])
+        if mi:
+            Wi = Wg[woff[i]:woff[i + 1]].reshape(int(info["n_interior"][i]), mi)
+            assert sla.subspace_angles(Wi, P.W[i]).max() < 1e-7, i
+    R = np.random.default_rng(3).standard_normal((A.n, 2))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    assert np.abs(Z - Zo).max() <= 1e-9 * np.abs(Zo).max()
+    b = W.rhs(A.n, 2)
+    x, inf = ctx.solve(torch.tensor(b, device=DEV), restart=restart, flexible=flex, rtol=1e-8)
+    xo, io = OS.gmres(A.to_scipy(), b, P.apply, restart=restart, rtol=1e-8, flexible=flex)
+    assert inf["status"] == 0 and abs(inf["its"][0] - io["its"]) <= 1, (inf["its"], io["its"])
+    ctx.close()
+
+
+def test_paper_tau_rule_full_size_convection_diffusion():
+    """tau = 0.3 with the cap of 60 on the full 2D convection-diffusion
+    workload (512^2, 64 blocks, overlap 2, FGMRES(50)), where the rule keeps
+    up to 17 eigenpairs per subdomain: nev_i and n0 exact against the
+    oracle's, the apply within 1e-9, iterations within +-1."""
+    A, part, N, o = W.config("c2_convdiff2d_512_blocks64")
+    As = A.to_scipy()
+    ctx = ads.Context(A, part, N, o["overlap"], 60, tau=0.3, eig_tol=1e-12)
+    P = OS.TwoLevelSchwarz(As, part, N, o["overlap"], 60, tau=0.3)
+    np.testing.assert_array_equal(ctx.info["nev_i"], P.nev_i)
+    assert ctx.info["n0"] == P.n0
+    print(f"c2 tau 0.3: nev_i from {min(P.nev_i)} to {max(P.nev_i)}, n0 {P.n0}", flush=True)
+    R = np.random.default_rng(4).standard_normal((A.n, 1))
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    assert np.abs(Z - Zo).max() <= 1e-9 * np.abs(Zo).max()
+    b = W.rhs(A.n, 0)
+    x, inf = ctx.solve(torch.tensor(b, device=DEV), restart=o["restart"], flexible=True, rtol=1e-8)
+    xo, io = OS.gmres(As, b, P.apply, restart=o["restart"], rtol=1e-8, flexible=True)
+    assert inf["status"] == 0 and abs(inf["its"][0] - io["its"]) <= 1, (inf["its"], io["its"])
+    print(f"c2 tau 0.3: {inf['its'][0]} iterations (oracle {io['its']})", flush=True)
+    ctx.close()
+
+
+def test_tau_rule_beyond_what_the_eigensolver_resolves_is_refused():
+    """tau so large that the rule keeps every eigenvalue (all are >= 1 on an
+    SPD problem) with a cap of 60: the eigensolver resolves 24 per subdomain
+    and the setup refuses rather than truncate; nev above 30 without the
+    tau rule is an argument error."""
+    A = W.laplace2d(24)
+    part = W.block_partition_2d(24, 2)
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(A, part, 4, 1, 60, tau=100.0)
+    assert e.value.status == ads.ADS_ERR_UNSUPPORTED and "tau rule keeps all" in str(e.value)
+    print(e.value, flush=True)
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(A, part, 4, 1, 40)
+    assert e.value.status == ads.ADS_ERR_ARG
+
+
 @pytest.mark.parametrize("solver", [0, 1], ids=["krylov-schur", "subspace"])
 def test_subdomains_of_uneven_size_keep_their_own_basis(solver):
     """A partition with one small subdomain (4 x 5 interior points in a corner
