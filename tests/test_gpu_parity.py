@@ -943,6 +943,65 @@ def test_paper_tau_rule_full_size_convection_diffusion():
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [ads.ADS_PREC_FP64, ads.ADS_PREC_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("m,nb", [(48, 3), (96, 2)], ids=["48-3x3-fast", "96-2x2-general"])
+def test_non_m_matrix_matches_oracle(m, nb, prec):
+    """A matrix that is not an M-matrix: convection-diffusion with central
+    differences at cell Peclet numbers up to 2.6 (over a third of the
+    off-diagonal entries are positive), nonsymmetric, so the diagonal blocks
+    are inverted with partial pivoting; 3 x 3 blocks (register-resident
+    factorization) and 2 x 2 blocks of 48 x 48 (block size beyond it: the
+    batched general path), overlap 2, nev 6.  FP64 (eigensolver to 1e-12):
+    where the cut of eq. 6 has a clear gap (|lambda| of the last kept and
+    the first left out more than 1 % apart) nev_i exact and the span within
+    1e-7 rad; where it falls inside a cluster of the non-normal operator
+    (one subdomain here: two complex pairs and two real eigenvalues within
+    0.3 %, which the oracle's two tiers order differently) nev_i within one;
+    the apply within 1e-9 of the oracle's eq. 4 with the GPU's coarse basis,
+    FGMRES iterations within +-1; FP32 factors: the solution within 1e-8 or
+    the residual bound, at most 2 more iterations."""
+    A = W.convdiff2d_central(m, 0.004 * 48 / m)
+    part = W.block_partition_2d(m, nb)
+    N = nb * nb
+    As = A.to_scipy()
+    P = OS.TwoLevelSchwarz(As, part, N, 2, 6)
+    ctx = ads.Context(A, part, N, 2, 6, precision=prec,
+                      eig_tol=1e-12 if prec == ads.ADS_PREC_FP64 else 0.0)
+    b = W.rhs(A.n, 0)
+    xo, io = OS.gmres(As, b, P.apply, restart=30, rtol=1e-8, flexible=True)
+    x, inf = ctx.solve(torch.tensor(b, device=DEV), restart=30, flexible=True, rtol=1e-8)
+    x = x.cpu().numpy()
+    assert inf["status"] == 0
+    if prec == ads.ADS_PREC_FP64:
+        Wg, woff, lam, info = ads.ads_export_coarse(ctx.ctx)
+        Ws, clear = [], 0
+        for i in range(N):
+            mi, mo = int(info["nev_i"][i]), int(P.nev_i[i])
+            Wi = Wg[woff[i]:woff[i + 1]].reshape(int(info["n_interior"][i]), mi)
+            Ws.append(Wi)
+            mags = np.sort(np.abs(P.eig[i]["lam_all"]))[::-1]
+            k = mo - P.eig[i]["kernel"]  # eigenvalues kept by the oracle
+            gap = (mags[k - 1] - mags[k]) / mags[k - 1] if 0 < k < len(mags) else 1.0
+            if gap > 1e-2:
+                assert mi == mo, (i, mi, mo)
+                assert sla.subspace_angles(Wi, P.W[i]).max() < 1e-7, i
+                clear += 1
+            else:
+                assert abs(mi - mo) <= 1, (i, mi, mo, gap)
+        print(f"non-M matrix {m}^2: {clear} of {N} cuts with a clear gap", flush=True)
+        R = np.random.default_rng(9).standard_normal(A.n)
+        z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+        zo = _oracle_apply_with_basis(P, Ws, R)
+        assert np.abs(z - zo).max() <= 1e-9 * np.abs(zo).max()
+        assert abs(inf["its"][0] - io["its"]) <= 1, (inf["its"], io["its"])
+    else:
+        assert inf["its"][0] <= io["its"] + 2, (inf["its"], io["its"])
+    assert_solution_close(As, b, x, xo, f"non-M {m} {prec}")
+    print(f"non-M matrix {m}^2, {N} blocks: max block {max(ctx.info['block'])}, "
+          f"its {inf['its'][0]} (oracle {io['its']})", flush=True)
+    ctx.close()
+
+
 def test_tau_rule_beyond_what_the_eigensolver_resolves_is_refused():
     """tau so large that the rule keeps every eigenvalue (all are >= 1 on an
     SPD problem) with a cap of 60: the eigensolver resolves 24 per subdomain

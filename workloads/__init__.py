@@ -21,6 +21,7 @@ from .problems import (  # noqa: F401
     CSR,
     laplace2d,
     convdiff2d,
+    convdiff2d_central,
     convdiff3d,
     diffusion2d_lognormal,
     lognormal2d_values_torch,

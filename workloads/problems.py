@@ -105,6 +105,37 @@ def convdiff2d(m: int, nu: float, velocity="cos-sin") -> CSR:
     return _assemble(n, ent)
 
 
+def convdiff2d_central(m: int, nu: float) -> CSR:
+    """-nu*Lap(u) + V.grad(u) with central differences for the convection,
+    V = (cos 2 pi y, sin 2 pi x), rows scaled by h^2: off-diagonals
+    -nu -+ (h/2) V.  Where the cell Peclet number h|V|/(2 nu) exceeds 1 some
+    off-diagonals are positive: a nonsymmetric matrix that is not an
+    M-matrix (interior rows still sum to zero)."""
+    n = m * m
+    h = 1.0 / (m + 1)
+    i, j = _grid2(m)
+    idx = i + m * j
+    x = (i + 1) * h
+    y = (j + 1) * h
+    vx = np.cos(2 * np.pi * y)
+    vy = np.sin(2 * np.pi * x)
+    diag = np.full(n, 4.0 * nu)
+    west = -nu - 0.5 * h * vx
+    east = -nu + 0.5 * h * vx
+    south = -nu - 0.5 * h * vy
+    north = -nu + 0.5 * h * vy
+    ent = [(idx, idx, diag)]
+    mk = i > 0
+    ent.append((idx[mk], idx[mk] - 1, west[mk]))
+    mk = i < m - 1
+    ent.append((idx[mk], idx[mk] + 1, east[mk]))
+    mk = j > 0
+    ent.append((idx[mk], idx[mk] - m, south[mk]))
+    mk = j < m - 1
+    ent.append((idx[mk], idx[mk] + m, north[mk]))
+    return _assemble(n, ent)
+
+
 def convdiff3d(m: int, nu: float) -> CSR:
     """-nu*Lap(u) + V.grad(u), upwind 7 points, with the 3D velocity of Section 4:
     V = (2x(1-x)(2y-1)z, -y(1-y)(2x-1), -z(1-z)(2x-1)(2y-1))."""
