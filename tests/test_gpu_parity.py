@@ -953,13 +953,18 @@ def test_non_m_matrix_matches_oracle(m, nb, prec):
     factorization) and 2 x 2 blocks of 48 x 48 (block size beyond it: the
     batched general path), overlap 2, nev 6.  FP64 (eigensolver to 1e-12):
     where the cut of eq. 6 has a clear gap (|lambda| of the last kept and
-    the first left out more than 1 % apart) nev_i exact and the span within
-    1e-7 rad; where it falls inside a cluster of the non-normal operator
-    (one subdomain here: two complex pairs and two real eigenvalues within
-    0.3 %, which the oracle's two tiers order differently) nev_i within one;
-    the apply within 1e-9 of the oracle's eq. 4 with the GPU's coarse basis,
-    FGMRES iterations within +-1; FP32 factors: the solution within 1e-8 or
-    the residual bound, at most 2 more iterations."""
+    the first left out more than 2e-3 apart, relatively) nev_i exact and the
+    span within 1e-7 rad.  Below that gap the order inside the cluster at
+    the cut is beyond what a Krylov method in FP64 resolves: on one
+    subdomain at m = 48 the cut falls in two complex pairs and two real
+    eigenvalues within 0.3 % of each other whose condition numbers reach
+    3.6e7 against an operator norm of 5.9e7, and the oracle's own Krylov
+    tier is 5.7e-5 off the exact values there; for such cuts nev_i within
+    one, and the eigenvector of the dominant eigenvalue (well separated,
+    well conditioned) inside the GPU's span within 1e-6 rad.  Then the apply
+    within 1e-9 of the oracle's eq. 4 with the GPU's coarse basis and FGMRES
+    iterations within +-1; FP32 factors: the solution within 1e-8 or the
+    residual bound, at most 2 more iterations."""
     A = W.convdiff2d_central(m, 0.004 * 48 / m)
     part = W.block_partition_2d(m, nb)
     N = nb * nb
@@ -982,12 +987,16 @@ def test_non_m_matrix_matches_oracle(m, nb, prec):
             mags = np.sort(np.abs(P.eig[i]["lam_all"]))[::-1]
             k = mo - P.eig[i]["kernel"]  # eigenvalues kept by the oracle
             gap = (mags[k - 1] - mags[k]) / mags[k - 1] if 0 < k < len(mags) else 1.0
-            if gap > 1e-2:
+            if gap > 2e-3:
                 assert mi == mo, (i, mi, mo)
                 assert sla.subspace_angles(Wi, P.W[i]).max() < 1e-7, i
                 clear += 1
             else:
                 assert abs(mi - mo) <= 1, (i, mi, mo, gap)
+                lam1 = P.eig[i]["lam_sel"][0]
+                assert lam1.imag == 0 and mags[1] < (1 - 2e-3) * mags[0], i
+                z1 = P.eig[i]["Z"][:Wi.shape[0], P.eig[i]["kernel"]]
+                assert sla.subspace_angles(Wi, z1[:, None]).max() < 1e-6, i
         print(f"non-M matrix {m}^2: {clear} of {N} cuts with a clear gap", flush=True)
         R = np.random.default_rng(9).standard_normal(A.n)
         z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
