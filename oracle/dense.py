@@ -9,8 +9,10 @@ and K_i = ker(Atilde_ii) from singular value decompositions, Pi_i the
 orthogonal projector onto range(Atilde_ii), and eq. 5 solved by the QZ
 algorithm on the pencil restricted to K_i^perp x range(Atilde_ii) (reading R7
 of the scalable tier; the unrestricted pencil is singular whenever K_i is not
-{0}).  The explicit preconditioner matrices of eq. 1 - eq. 4 are formed by
-products of these matrices.  This tier shares no code with ``oracle.schwarz``
+{0}).  Complex A is taken as it is (moduli in Definition 1, adjoints
+throughout, complex eigenvectors as the columns of Z_i).  The explicit
+preconditioner matrices of eq. 1 - eq. 4 are formed by products of these
+matrices.  This tier shares no code with ``oracle.schwarz``
 so that the two check each other.
 """
 from __future__ import annotations
@@ -88,7 +90,8 @@ def _orth(M):
 def local_eig(A_ii, At_ii, nI, nev, tau=0.0):
     """eq. 5 and eq. 6 on one subdomain.  Returns dict with all finite
     eigenvalues (|lambda| descending), the selected ones, the kernel part and
-    Z_i (real, nev_i columns, kernel part first)."""
+    Z_i (nev_i columns, kernel part first; real for real A)."""
+    cplx = np.iscomplexobj(A_ii)
     ni = A_ii.shape[0]
     D = np.diag(np.r_[np.ones(nI), np.zeros(ni - nI)])
     B = D @ A_ii @ D
@@ -119,12 +122,15 @@ def local_eig(A_ii, At_ii, nI, nev, tau=0.0):
     cols = []
     for t in sel:
         u = QU @ V[:, t]
-        if abs(w[t].imag) <= 1e-12 * abs(w[t]):
+        if cplx:
+            cols.append(u)
+        elif abs(w[t].imag) <= 1e-12 * abs(w[t]):
             cols.append(u.real if np.linalg.norm(u.real) >= np.linalg.norm(u.imag) else u.imag)
         elif w[t].imag > 0:
             cols += [u.real, u.imag]
     U = np.array(cols).T if cols else np.zeros((ni, 0))
-    Z = np.hstack([Y.real, U]) if count > 0 else Y.real[:, :max(nev, 0)]
+    Yk = Y if cplx else Y.real
+    Z = np.hstack([Yk, U]) if count > 0 else Yk[:, :max(nev, 0)]
     return dict(lam_all=w, lam_sel=w[sel], Z=Z, kernel=QK.shape[1], B=B, Pi=Pi,
                 K=QK, L=_null_and_range(B)["right_null"])
 
@@ -133,7 +139,8 @@ class DenseSchwarz:
     """All operators of Section 2 as explicit dense matrices."""
 
     def __init__(self, A, part, nparts, delta, nev, tau=0.0):
-        A = np.asarray(A.toarray() if hasattr(A, "toarray") else A, dtype=np.float64)
+        A = np.asarray(A.toarray() if hasattr(A, "toarray") else A)
+        A = A.astype(np.complex128 if np.iscomplexobj(A) else np.float64)
         part = np.asarray(part)
         self.A = A
         n = self.n = A.shape[0]

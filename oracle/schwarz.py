@@ -36,6 +36,14 @@ Readings taken where the paper is silent (shared with the dense tier):
   R10 GMRES converges when the Arnoldi estimate and the recomputed true
       residual are both <= rtol * ||b||; iterations are Arnoldi steps summed
       over restart cycles.
+
+Complex A (the Notation paragraph takes A complex and writes adjoints): the
+absolute values of Definition 1 are moduli, R_0^H and every inner product
+conjugate, the selected complex eigenvectors of eq. 5 form Z_i as they are
+(the real/imaginary split of R8 is for real A only), the projector of R7 uses
+the left null vector of the splitting under the adjoint, and GMRES runs in
+complex arithmetic with complex Givens rotations.  On real input every
+operation reduces to the real one.
 """
 from __future__ import annotations
 
@@ -205,7 +213,7 @@ def kernel_dimension(At: sp.csr_matrix) -> int:
     """Reading R6: 1 when every row of the splitting sums to zero relative to its
     absolute row sum (floating subdomain of a zero-row-sum M-matrix), else 0."""
     rows = np.repeat(np.arange(At.shape[0]), np.diff(At.indptr))
-    rs = np.zeros(At.shape[0])
+    rs = np.zeros(At.shape[0], dtype=At.dtype)
     ars = np.zeros(At.shape[0])
     np.add.at(rs, rows, At.data)
     np.add.at(ars, rows, np.abs(At.data))
@@ -268,6 +276,7 @@ def local_eigenproblem(A_ii: sp.csr_matrix, At: sp.csr_matrix, n_interior: int, 
     to K^perp.  Returns dict(lam_all, lam_sel, Z, kernel) with Z = [Y, U_sel]
     (nev_i real columns, the kernel part first)."""
     ni = A_ii.shape[0]
+    cplx = np.iscomplexobj(A_ii.data)
     if kdim is None:
         kdim = kernel_dimension(At)
     d = np.zeros(ni)
@@ -278,11 +287,12 @@ def local_eigenproblem(A_ii: sp.csr_matrix, At: sp.csr_matrix, n_interior: int, 
         Areg = At.tolil(copy=True)
         Areg[ni - 1, ni - 1] = 2.0 * At[ni - 1, ni - 1]
         lu = spla.splu(Areg.tocsc())
-        ell = lu.solve(np.eye(1, ni, ni - 1).ravel(), trans="T")
+        e_last = np.eye(1, ni, ni - 1).ravel().astype(A_ii.dtype)
+        ell = lu.solve(e_last, trans="H" if cplx else "T")  # null(Atilde^H)
         ell /= np.linalg.norm(ell)
 
         def Pi(x):
-            return x - ell * (ell @ x)
+            return x - ell * (ell.conj() @ x)
 
         def T(x):
             y = lu.solve(Pi(B @ Pi(x)))
@@ -300,8 +310,8 @@ def local_eigenproblem(A_ii: sp.csr_matrix, At: sp.csr_matrix, n_interior: int, 
     if count <= 0:
         lam = np.zeros(0, complex)
         return dict(lam_all=lam, lam_sel=lam, Z=Y[:, :max(nev, 0)], kernel=kdim)
-    op = spla.LinearOperator((ni, ni), matvec=T, dtype=np.float64)
-    v0 = np.ones(ni) + np.linspace(0.0, 1.0, ni)
+    op = spla.LinearOperator((ni, ni), matvec=T, dtype=A_ii.dtype)
+    v0 = (np.ones(ni) + np.linspace(0.0, 1.0, ni)).astype(A_ii.dtype)
     if kdim == 1:
         v0 -= k * (k @ v0)
     extra = 6
@@ -321,8 +331,8 @@ def local_eigenproblem(A_ii: sp.csr_matrix, At: sp.csr_matrix, n_interior: int, 
         except _NeedMore:
             extra *= 2
     order = np.argsort(-np.abs(lam), kind="stable")
-    U = real_basis(vec[:, sel], lam[sel])
-    Z = np.hstack([Y, U])
+    U = vec[:, sel] if cplx else real_basis(vec[:, sel], lam[sel])
+    Z = np.hstack([Y.astype(U.dtype), U])
     return dict(lam_all=lam[order], lam_sel=lam[sel], Z=Z, kernel=kdim)
 
 
@@ -389,7 +399,7 @@ class TwoLevelSchwarz:
                 off += Wi.shape[1]
             self.Z = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                                    shape=(self.n, self.n0))
-            self.E = (self.Z.T @ (A @ self.Z)).toarray()
+            self.E = (self.Z.conj().T @ (A @ self.Z)).toarray()
             self.E_lu = sla.lu_factor(self.E)
         else:
             self.Z = None
@@ -403,7 +413,7 @@ class TwoLevelSchwarz:
         """R_0^H A_00^{-1} R_0 r."""
         if not self.n0:
             return np.zeros_like(r)
-        c = self.Z.T @ r
+        c = self.Z.conj().T @ r
         return self.Z @ sla.lu_solve(self.E_lu, c)
 
     def one_level(self, t, restricted=True):
@@ -419,7 +429,7 @@ class TwoLevelSchwarz:
         return x
 
     def apply(self, r):
-        r = np.asarray(r, dtype=np.float64)
+        r = np.asarray(r, dtype=np.result_type(self.A.dtype, np.asarray(r).dtype, np.float64))
         if r.ndim == 2:
             return np.stack([self.apply(r[:, j]) for j in range(r.shape[1])], axis=1)
         if self.variant == "deflated":          # eq. 4
@@ -449,7 +459,10 @@ class TwoLevelSchwarz:
 
 def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed_iters=0):
     """Restarted right-preconditioned GMRES(m) / FGMRES(m), x0 = 0, modified
-    Gram-Schmidt, Givens rotations (reading R10).
+    Gram-Schmidt, Givens rotations (reading R10); complex A or b run in
+    complex arithmetic (conjugated inner products, rotations
+    [[conj c, conj s], [-s, c]] with c = h_jj / rho, s = h_j+1,j / rho, which
+    for real data are the usual [[c, s], [-s, c]]).
 
     fixed_iters > 0 runs exactly that many Arnoldi steps (no convergence test)
     and returns the iterate.  Returns (x, info) with info = dict(its, status,
@@ -458,8 +471,9 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
     A = sp.csr_matrix(A) if sp.issparse(A) else A
     n = len(b)
     Mv = (lambda v: v) if M is None else M
+    dt = np.result_type(A.dtype, np.asarray(b).dtype, np.float64)
     bnorm = np.linalg.norm(b)
-    x = np.zeros(n)
+    x = np.zeros(n, dtype=dt)
     its = 0
     hist = [1.0]
     if bnorm == 0.0:
@@ -472,12 +486,12 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
             status = OK
             break
         m = restart
-        V = np.zeros((m + 1, n))
-        Zs = np.zeros((m, n)) if flexible else None
-        H = np.zeros((m + 1, m))
-        cs = np.zeros(m)
-        sn = np.zeros(m)
-        g = np.zeros(m + 1)
+        V = np.zeros((m + 1, n), dtype=dt)
+        Zs = np.zeros((m, n), dtype=dt) if flexible else None
+        H = np.zeros((m + 1, m), dtype=dt)
+        cs = np.zeros(m, dtype=dt)
+        sn = np.zeros(m, dtype=dt)
+        g = np.zeros(m + 1, dtype=dt)
         g[0] = beta
         V[0] = r / beta
         j_end = 0
@@ -488,22 +502,22 @@ def gmres(A, b, M=None, restart=30, rtol=1e-8, maxit=1000, flexible=False, fixed
                 Zs[j] = z
             w = A @ z
             for i in range(j + 1):
-                H[i, j] = V[i] @ w
+                H[i, j] = np.conj(V[i]) @ w
                 w = w - H[i, j] * V[i]
             hnext = np.linalg.norm(w)
             H[j + 1, j] = hnext
             hcol = np.linalg.norm(H[: j + 2, j])
             for i in range(j):
-                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                t = np.conj(cs[i]) * H[i, j] + np.conj(sn[i]) * H[i + 1, j]
                 H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
                 H[i, j] = t
-            den = np.hypot(H[j, j], H[j + 1, j])
+            den = np.hypot(abs(H[j, j]), abs(H[j + 1, j]))
             cs[j] = H[j, j] / den
             sn[j] = H[j + 1, j] / den
             H[j, j] = den
             H[j + 1, j] = 0.0
             g[j + 1] = -sn[j] * g[j]
-            g[j] = cs[j] * g[j]
+            g[j] = np.conj(cs[j]) * g[j]
             its += 1
             j_end = j + 1
             hist.append(abs(g[j + 1]) / bnorm)

@@ -22,6 +22,8 @@ from .problems import (  # noqa: F401
     laplace2d,
     convdiff2d,
     convdiff2d_central,
+    convdiff2d_complex,
+    magnetic_laplace2d,
     convdiff3d,
     diffusion2d_lognormal,
     lognormal2d_values_torch,

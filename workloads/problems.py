@@ -14,12 +14,13 @@ import scipy.sparse as sp
 
 @dataclasses.dataclass
 class CSR:
-    """Compressed sparse rows with int64 row pointers, int32 sorted columns, FP64 values."""
+    """Compressed sparse rows with int64 row pointers, int32 sorted columns,
+    FP64 values (complex128 for the complex families)."""
 
     n: int
     indptr: np.ndarray   # int64[n+1]
     indices: np.ndarray  # int32[nnz]
-    data: np.ndarray     # float64[nnz]
+    data: np.ndarray     # float64[nnz] or complex128[nnz]
 
     @property
     def nnz(self) -> int:
@@ -33,8 +34,9 @@ class CSR:
         M = sp.csr_matrix(M)
         M.eliminate_zeros()
         M.sort_indices()
+        dt = np.complex128 if np.iscomplexobj(M.data) else np.float64
         return CSR(M.shape[0], M.indptr.astype(np.int64), M.indices.astype(np.int32),
-                   M.data.astype(np.float64))
+                   M.data.astype(dt))
 
 
 def _assemble(n: int, entries) -> CSR:
@@ -133,6 +135,78 @@ def convdiff2d_central(m: int, nu: float) -> CSR:
     ent.append((idx[mk], idx[mk] - m, south[mk]))
     mk = j < m - 1
     ent.append((idx[mk], idx[mk] + m, north[mk]))
+    return _assemble(n, ent)
+
+
+def convdiff2d_complex(m: int, nu: float, eta: float = 0.0, omega: float = 0.0,
+                       phase_seed=None, eta_y=None, neumann_x: bool = False) -> CSR:
+    """Frequency-domain convection-diffusion -nu ((1 + i eta) d_xx + (1 + i
+    eta_y) d_yy) u + V.grad(u) + i omega u (eta_y defaults to eta), first-order
+    upwind with V = (cos 2 pi y, sin 2 pi x), rows scaled by h^2: x-couplings
+    -nu (1 + i eta) - h max(+-Vx, 0), y-couplings likewise with eta_y, the
+    diagonal minus their sum plus i omega h^2.  Interior rows sum to
+    i omega h^2 (to zero when omega = 0; with eta_y = 0 the y-couplings are
+    real and negative, and with neumann_x the rows at x = 0 and x = 1 drop
+    the missing coupling from the diagonal, so the strips that do not touch
+    y = 0 or y = 1 float).  phase_seed
+    applies the unitary change of variables diag(exp(i theta)) A
+    diag(exp(-i theta)), theta uniform in [0, 2 pi) from that seed, which
+    keeps every modulus and makes each off-diagonal entry genuinely complex
+    (use it with omega > 0: it moves the null vector of a floating splitting
+    off the constant)."""
+    n = m * m
+    h = 1.0 / (m + 1)
+    i, j = _grid2(m)
+    idx = i + m * j
+    x = (i + 1) * h
+    y = (j + 1) * h
+    vx = np.cos(2 * np.pi * y)
+    vy = np.sin(2 * np.pi * x)
+    dx = nu * (1.0 + 1j * eta)
+    dy = nu * (1.0 + 1j * (eta if eta_y is None else eta_y))
+    diag = 2.0 * dx + 2.0 * dy + h * (np.abs(vx) + np.abs(vy)) + 1j * omega * h * h
+    west = -dx - h * np.maximum(vx, 0.0)
+    east = -dx - h * np.maximum(-vx, 0.0)
+    south = -dy - h * np.maximum(vy, 0.0)
+    north = -dy - h * np.maximum(-vy, 0.0)
+    if neumann_x:
+        diag = diag + np.where(i == 0, west, 0.0) + np.where(i == m - 1, east, 0.0)
+    ent = [(idx, idx, diag)]
+    mk = i > 0
+    ent.append((idx[mk], idx[mk] - 1, west[mk]))
+    mk = i < m - 1
+    ent.append((idx[mk], idx[mk] + 1, east[mk]))
+    mk = j > 0
+    ent.append((idx[mk], idx[mk] - m, south[mk]))
+    mk = j < m - 1
+    ent.append((idx[mk], idx[mk] + m, north[mk]))
+    A = _assemble(n, ent)
+    if phase_seed is not None:
+        ph = np.exp(1j * np.random.default_rng(phase_seed).uniform(0.0, 2 * np.pi, n))
+        rows = np.repeat(np.arange(n), np.diff(A.indptr))
+        A.data = A.data * ph[rows] * np.conj(ph[A.indices])
+    return A
+
+
+def magnetic_laplace2d(m: int, flux: float, shift: float = 0.0) -> CSR:
+    """Hermitian 5-point magnetic Laplacian (Landau gauge): diagonal 4 + shift,
+    -1 on x-edges, -exp(+-2 pi i flux x) on y-edges (x of the lower node),
+    rows scaled by h^2.  Hermitian positive definite and diagonally dominant
+    for shift >= 0 (strictly on the boundary rows)."""
+    n = m * m
+    h = 1.0 / (m + 1)
+    i, j = _grid2(m)
+    idx = i + m * j
+    ph = np.exp(2j * np.pi * flux * (i + 1) * h)
+    ent = [(idx, idx, np.full(n, 4.0 + shift, dtype=complex))]
+    mk = i > 0
+    ent.append((idx[mk], idx[mk] - 1, np.full(mk.sum(), -1.0 + 0j)))
+    mk = i < m - 1
+    ent.append((idx[mk], idx[mk] + 1, np.full(mk.sum(), -1.0 + 0j)))
+    mk = j < m - 1
+    ent.append((idx[mk], idx[mk] + m, -ph[mk]))
+    mk = j > 0
+    ent.append((idx[mk], idx[mk] - m, -np.conj(ph[mk])))
     return _assemble(n, ent)
 
 
