@@ -3,8 +3,9 @@
  * overlapping Schwarz preconditioner of Al Daas, Jolivet and Rees,
  * "Efficient algebraic two-level Schwarz preconditioner for sparse matrices".
  *
- * The library solves A x = b for a real sparse A (Section 1, problem
- * statement) with right-preconditioned restarted (F)GMRES (Section 4) and the
+ * The library solves A x = b for a real or complex sparse A (Section 1,
+ * problem statement; the Notation paragraph takes A complex) with
+ * right-preconditioned restarted (F)GMRES (Section 4) and the
  * restricted two-level preconditioner with deflated coarse correction (eq. 4,
  * Section 2), whose coarse space comes from local generalized eigenproblems
  * (eq. 5, eq. 6, Section 3.2) on the local block splitting matrices of
@@ -16,8 +17,10 @@
  *    ADS_ERR_* code on error, or a positive solver outcome (ADS_KSP_*).  No
  *    C++ exception or abort crosses this interface.  ads_last_error() returns
  *    a thread-local message describing the last error of the calling thread.
- *  - Real FP64 values only.  Column indices must be sorted and unique within
- *    each row; an explicitly stored zero counts as an edge of the graph.
+ *  - FP64 values: real (ads_setup, ads_setup_batched) or complex as
+ *    interleaved (re, im) pairs (ads_setup_complex).  Column indices must be
+ *    sorted and unique within each row; an explicitly stored zero counts as
+ *    an edge of the graph.
  *  - Ownership: the caller keeps ownership of every pointer it passes in.
  *    ads_setup* copies what it needs into context-owned device memory; the
  *    context owns all device memory it allocates and ads_destroy frees it.
@@ -35,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ADS_ABI_VERSION 4
+#define ADS_ABI_VERSION 5
 #define ADS_MAX_RESULTS 64 /* entries of ads_ksp_result: nsys * nrhs <= 64 */
 
 /* status codes */
@@ -201,6 +204,11 @@ typedef struct {
   double local_resid;        /* largest relative residual ||t - A_ii x|| / ||t|| of one
                                 local solve with the stored factors (pseudo-random t):
                                 what the factor precision costs each local solve     */
+  int32_t is_complex;        /* 1 for a context of ads_setup_complex: n, omega_total,
+                                n0, nev_i, n_i, n_interior, block, the exports and
+                                the vectors of ads_apply / ads_solve are then those of
+                                the real form (2 real rows per complex unknown, 2 real
+                                coarse vectors per complex one)                      */
 } ads_info;
 
 /* Setup for one system (Sections 2 and 3): overlapping subdomains from the
@@ -217,6 +225,29 @@ int ads_setup(const ads_csr* A, const int32_t* part, int32_t nparts, const ads_o
  * (host int32[A[s].n]) of nparts[s] parts, all set up together, one launch per
  * phase.  Vectors of a batched context concatenate the systems in order. */
 int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part,
+                      const int32_t* nparts, const ads_options* opts, void* hip_stream,
+                      ads_ctx** out);
+
+/* Complex A (the Notation paragraph of the paper takes A in C^{n x n}): the
+ * same setup as ads_setup_batched for nsys complex systems.  A[s].val holds
+ * 2 * nnz doubles, entry k as (re, im) at [2k], [2k + 1] (C99 double complex
+ * / std::complex<double> layout); row_ptr, col, part and nparts as for real
+ * systems.  The method is that of the paper for complex A: moduli in the
+ * lumped sums of Definition 1, the adjoint R_0^H in the coarse operator
+ * E = R_0 A R_0^H, complex eigenvectors of eq. 5 spanning the coarse space,
+ * GMRES with complex inner products.  It runs on the real form of A, in
+ * which complex unknown j is real rows 2j (re) and 2j + 1 (im) and entry
+ * a_jk the 2 x 2 block [[re, -im], [im, re]]: complex vectors are then the
+ * interleaved arrays themselves, ads_apply takes and returns them as they
+ * are (2n doubles per column), and ads_solve runs complex GMRES on them.
+ * Each eigenvalue mu of eq. 5 appears as the pair (mu, conj(mu)) of the real
+ * form, whose invariant subspace is the real form of the complex eigenvector;
+ * nev counts complex vectors (at most 15, or 30 as the cap of the tau rule)
+ * and the selection keeps whole pairs.  Refused with ADS_ERR_UNSUPPORTED: a
+ * splitting with a kernel (a floating subdomain, R6's constant null vector:
+ * two-dimensional in the real form) and warm_start != 0.  2n and 4 nnz must
+ * stay below 2^31.  ads_info.is_complex = 1. */
+int ads_setup_complex(int32_t nsys, const ads_csr* A, const int32_t* const* part,
                       const int32_t* nparts, const ads_options* opts, void* hip_stream,
                       ads_ctx** out);
 

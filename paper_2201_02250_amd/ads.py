@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libads.so")
 
-ADS_ABI_VERSION = 4
+ADS_ABI_VERSION = 5
 ADS_MAX_RESULTS = 64
 ADS_OK, ADS_KSP_MAXIT, ADS_KSP_BREAKDOWN = 0, 1, 2
 ADS_ERR_ARG, ADS_ERR_HIP, ADS_ERR_OOM, ADS_ERR_SINGULAR = -1, -2, -3, -4
@@ -26,7 +26,7 @@ ADS_PREC_FP64, ADS_PREC_FP32, ADS_PREC_BF16 = 0, 1, 2
 ADS_EIG_KRYLOV_SCHUR, ADS_EIG_SUBSPACE = 0, 1
 
 # every symbol declared in include/ads.h
-SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_apply", "ads_apply_noalloc", "ads_solve",
+SYMBOLS = ["ads_setup", "ads_setup_batched", "ads_setup_complex", "ads_apply", "ads_apply_noalloc", "ads_solve",
            "ads_get_info",
            "ads_export_maps", "ads_export_splitting", "ads_export_coarse", "ads_partition_bfs",
            "ads_set_graphs", "ads_destroy", "ads_status_string", "ads_last_error",
@@ -85,7 +85,8 @@ class ads_info(C.Structure):
                 ("eig_resid", C.c_void_p), ("eig_solver", C.c_int32),
                 ("tile_factor", C.c_double), ("tile_tuned", C.c_int32),
                 ("t_mfma_update_ms", C.c_double), ("n_mfma_update", C.c_int64),
-                ("mfma_update_flops", C.c_double), ("local_resid", C.c_double)]
+                ("mfma_update_flops", C.c_double), ("local_resid", C.c_double),
+                ("is_complex", C.c_int32)]
 
 
 class DeviceCSR:
@@ -113,6 +114,8 @@ def lib():
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         L.ads_setup.argtypes = [C.POINTER(ads_csr), P, I32, C.POINTER(ads_options), P, C.POINTER(P)]
         L.ads_setup_batched.argtypes = [I32, C.POINTER(ads_csr), P, P, C.POINTER(ads_options), P,
+                                        C.POINTER(P)]
+        L.ads_setup_complex.argtypes = [I32, C.POINTER(ads_csr), P, P, C.POINTER(ads_options), P,
                                         C.POINTER(P)]
         L.ads_apply.argtypes = [P, P, P, I32, P]
         L.ads_apply_noalloc.argtypes = [P, P, P, I32, P]
@@ -183,15 +186,15 @@ def make_csr(A):
     if hasattr(A, "tocsr"):
         A = A.tocsr()
         A.sort_indices()
-        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
-        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
-        v = np.ascontiguousarray(A.data, dtype=np.float64)
         n = A.shape[0]
     else:
-        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
-        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
-        v = np.ascontiguousarray(A.data, dtype=np.float64)
         n = A.n
+    rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+    if np.iscomplexobj(A.data):  # (re, im) pairs, the layout ads_setup_complex reads
+        v = np.ascontiguousarray(A.data, dtype=np.complex128).view(np.float64)
+    else:
+        v = np.ascontiguousarray(A.data, dtype=np.float64)
     s = ads_csr(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 0)
     return s, (rp, ci, v)
 
@@ -207,8 +210,18 @@ def ads_setup(A, part, nparts, opts, stream=None):
     return ads_setup_batched([A], [part], [nparts], opts, stream)
 
 
-def ads_setup_batched(As, parts, nparts, opts, stream=None):
+def _is_complex(A):
+    return not isinstance(A, DeviceCSR) and np.iscomplexobj(A.data)
+
+
+def ads_setup_batched(As, parts, nparts, opts, stream=None, complex_values=None):
+    """ads_setup_batched, or ads_setup_complex when the matrices hold complex
+    values (complex_values=None: taken from the first matrix)."""
     nsys = len(As)
+    if complex_values is None:
+        complex_values = _is_complex(As[0])
+    if any(_is_complex(A) != complex_values for A in As):
+        raise ValueError("all systems of a context must be real, or all complex")
     arr = (ads_csr * nsys)()
     keep = []
     pp = (C.c_void_p * nsys)()
@@ -222,9 +235,14 @@ def ads_setup_batched(As, parts, nparts, opts, stream=None):
         pp[k] = pc.ctypes.data
     npc = np.ascontiguousarray(nparts, dtype=np.int32)
     out = C.c_void_p()
-    _check(lib().ads_setup_batched(nsys, arr, C.cast(pp, C.c_void_p), npc.ctypes.data,
-                                   C.byref(opts), stream, C.byref(out)))
+    fn = lib().ads_setup_complex if complex_values else lib().ads_setup_batched
+    _check(fn(nsys, arr, C.cast(pp, C.c_void_p), npc.ctypes.data, C.byref(opts), stream,
+              C.byref(out)))
     return out
+
+
+def ads_setup_complex(As, parts, nparts, opts, stream=None):
+    return ads_setup_batched(As, parts, nparts, opts, stream, complex_values=True)
 
 
 def ads_apply(ctx, r_ptr, z_ptr, nrhs, stream=None):
@@ -311,7 +329,8 @@ def ksp_options(restart=30, flexible=False, rtol=1e-8, maxit=1000, fixed_iters=0
 
 
 class Context:
-    """Owns an ads context; apply/solve take torch CUDA tensors (FP64)."""
+    """Owns an ads context; apply/solve take torch CUDA tensors (FP64, or
+    complex128 for complex matrices, passed as their interleaved real views)."""
 
     def __init__(self, As, parts, nparts, overlap, nev, variant=ADS_VARIANT_DEFLATED,
                  precision=ADS_PREC_FP64, tau=0.0, eig_tol=0.0, eig_max_sweeps=0, stream=None,
@@ -326,24 +345,34 @@ class Context:
         self.stream = stream
         self.ctx = ads_setup_batched(As, parts, nparts, self.opts, stream)
         self.info = ads_get_info(self.ctx)
-        self.n = self.info["n"]
+        self.is_complex = bool(self.info["is_complex"])
+        self.n = self.info["n"] // (2 if self.is_complex else 1)  # unknowns
         self.nsys = self.info["nsys"]
+
+    def _dtype(self):
+        import torch
+        return torch.complex128 if self.is_complex else torch.float64
+
+    def _ptr(self, t):
+        import torch
+        return (torch.view_as_real(t) if self.is_complex else t).data_ptr()
 
     def apply(self, r, z=None):
         import torch
         nrhs = 1 if r.dim() == 1 else r.shape[1]
-        assert r.dtype == torch.float64 and r.is_cuda
-        rr = r if r.dim() == 1 else r.t().contiguous()  # column-major n x nrhs
+        assert r.dtype == self._dtype() and r.is_cuda and r.shape[0] == self.n
+        rr = r.contiguous() if r.dim() == 1 else r.t().contiguous()  # column-major n x nrhs
         zz = torch.empty_like(rr)
-        ads_apply(self.ctx, rr.data_ptr(), zz.data_ptr(), nrhs, self.stream)
+        ads_apply(self.ctx, self._ptr(rr), self._ptr(zz), nrhs, self.stream)
         return zz if r.dim() == 1 else zz.reshape(nrhs, self.n).t()
 
     def solve(self, b, restart=30, flexible=False, rtol=1e-8, maxit=1000, fixed_iters=0):
         import torch
         nrhs = 1 if b.dim() == 1 else b.shape[1]
-        bb = b if b.dim() == 1 else b.t().contiguous()
+        assert b.dtype == self._dtype() and b.is_cuda and b.shape[0] == self.n
+        bb = b.contiguous() if b.dim() == 1 else b.t().contiguous()
         xx = torch.empty_like(bb)
-        st, res = ads_solve(self.ctx, bb.data_ptr(), xx.data_ptr(), nrhs,
+        st, res = ads_solve(self.ctx, self._ptr(bb), self._ptr(xx), nrhs,
                             ksp_options(restart, flexible, rtol, maxit, fixed_iters), self.stream)
         q = self.nsys * nrhs
         out = dict(status=st, its=list(res.its[:q]), relres=list(res.relres[:q]),

@@ -191,19 +191,70 @@ __global__ void k_check_symmetric(const int32_t* rowptr, const int32_t* col, con
   }
 }
 
+// complex CSR (entry k as (re, im) at v[2k], v[2k + 1]) into the real form:
+// unknown r -> rows 2r (re) and 2r + 1 (im) at row offset r0, entry (c, z) ->
+// columns 2c, 2c + 1 holding (re, -im) in row 2r and (im, re) in row 2r + 1,
+// so that a complex vector stored interleaved is multiplied as it is; flags
+// as k_import_csr
+__global__ void k_import_csr_complex(const int64_t* rp, const int32_t* ci, const double* v,
+                                     int64_t n, int64_t nnz, int64_t r0, int64_t k0,
+                                     int32_t* rowptr, int32_t* col, double* val, int32_t* bad) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n) return;
+  if (r == n) {
+    if (rp[0] != 0 || rp[n] != nnz) atomicOr(bad, 1);
+    rowptr[r0 + 2 * n] = (int32_t)(k0 + 4 * nnz);
+    return;
+  }
+  const int64_t a = rp[r], b = rp[r + 1];
+  if (b < a || a < 0 || b > nnz) {
+    atomicOr(bad, 1);
+    rowptr[r0 + 2 * r] = rowptr[r0 + 2 * r + 1] = (int32_t)k0;
+    return;
+  }
+  const int64_t L = b - a;
+  const int64_t e_re = k0 + 4 * a, e_im = e_re + 2 * L;
+  rowptr[r0 + 2 * r] = (int32_t)e_re;
+  rowptr[r0 + 2 * r + 1] = (int32_t)e_im;
+  int prev = -1;
+  for (int64_t k = a; k < b; ++k) {
+    const int c = ci[k];
+    if (c < 0 || c >= n) atomicOr(bad, 2);
+    if (c <= prev) atomicOr(bad, 4);
+    prev = c;
+    const double re = v[2 * k], im = v[2 * k + 1];
+    if (!isfinite(re) || !isfinite(im)) atomicOr(bad, 8);
+    const int32_t c0 = (int32_t)(r0 + 2 * (int64_t)c);
+    const int64_t t = 2 * (k - a);
+    col[e_re + t] = c0;
+    col[e_re + t + 1] = c0 + 1;
+    val[e_re + t] = re;
+    val[e_re + t + 1] = -im;
+    col[e_im + t] = c0;
+    col[e_im + t + 1] = c0 + 1;
+    val[e_im + t] = im;
+    val[e_im + t + 1] = re;
+  }
+}
+
 static void import_csr(Ctx& c, const ads_csr& A, int64_t r0, int64_t k0, int32_t* bad,
                        hipStream_t st) {
   const int64_t* rp = A.row_ptr;
   const int32_t* ci = A.col;
   const double* v = A.val;
+  const int64_t vlen = c.cplx ? 2 * A.nnz : A.nnz;
   Arena tmp(st);
   if (!A.on_device) {
     rp = upload(tmp, A.row_ptr, A.n + 1, st);
     ci = upload(tmp, A.col, A.nnz, st);
-    v = upload(tmp, A.val, A.nnz, st);
+    v = upload(tmp, A.val, vlen, st);
   }
-  ADS_LAUNCH(k_import_csr, dim3((unsigned)((A.n + 256) / 256)), dim3(256), 0, st, rp, ci, v, A.n,
-             A.nnz, r0, k0, c.rowptr, c.col, c.val, bad);
+  if (c.cplx)
+    ADS_LAUNCH(k_import_csr_complex, dim3((unsigned)((A.n + 256) / 256)), dim3(256), 0, st, rp, ci,
+               v, A.n, A.nnz, r0, k0, c.rowptr, c.col, c.val, bad);
+  else
+    ADS_LAUNCH(k_import_csr, dim3((unsigned)((A.n + 256) / 256)), dim3(256), 0, st, rp, ci, v, A.n,
+               A.nnz, r0, k0, c.rowptr, c.col, c.val, bad);
   ADS_HIP(hipStreamSynchronize(st));
 }
 
@@ -211,15 +262,21 @@ static void import_csr(Ctx& c, const ads_csr& A, int64_t r0, int64_t k0, int32_t
 static constexpr double BF16_MAX_LOCAL_RESID = 0.25;
 
 static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, const int32_t* nparts,
-                       const ads_options* opts, hipStream_t st) {
+                       const ads_options* opts, hipStream_t st, bool cplx) {
   if (nsys <= 0) fail(ADS_ERR_ARG, "nsys must be positive");
   if (!A || !part || !nparts || !opts) fail(ADS_ERR_ARG, "null argument");
   if (opts->abi_version != ADS_ABI_VERSION) fail(ADS_ERR_ARG, "abi_version mismatch");
   if (opts->overlap < 0 || opts->overlap > 16) fail(ADS_ERR_ARG, "overlap must be in [0, 16]");
   // nev is the coarse vectors per subdomain, or with the tau rule of eq. 6
-  // their cap (the paper's setting: tau = 0.3, at most 60)
-  if (opts->nev < 0 || opts->nev > (opts->tau > 0 ? 60 : 30))
-    fail(ADS_ERR_ARG, "nev must be in [0, 30] (in [0, 60] as the cap of the tau rule)");
+  // their cap (the paper's setting: tau = 0.3, at most 60); a complex vector
+  // is two real ones of the real form
+  const int nev_max = (opts->tau > 0 ? 60 : 30) / (cplx ? 2 : 1);
+  if (opts->nev < 0 || opts->nev > nev_max)
+    fail(ADS_ERR_ARG, cplx ? "nev must be in [0, 15] for complex A (in [0, 30] as the cap of the "
+                             "tau rule)"
+                           : "nev must be in [0, 30] (in [0, 60] as the cap of the tau rule)");
+  if (cplx && opts->warm_start != 0)
+    fail(ADS_ERR_UNSUPPORTED, "the learned warm start is for real A only");
   if (opts->variant < ADS_VARIANT_DEFLATED || opts->variant > ADS_VARIANT_ADDITIVE_RAS)
     fail(ADS_ERR_ARG, "unknown variant");
   if (opts->precision < ADS_PREC_FP64 || opts->precision > ADS_PREC_BF16)
@@ -230,9 +287,11 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
   if (opts->eig_solver != ADS_EIG_KRYLOV_SCHUR && opts->eig_solver != ADS_EIG_SUBSPACE)
     fail(ADS_ERR_ARG, "unknown eig_solver");
   // every system's arguments, before any device call
+  const int64_t rf = cplx ? 2 : 1;  // real rows per unknown
   for (int s = 0; s < nsys; ++s) {
-    if (A[s].n <= 0 || A[s].n >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "n out of range");
-    if (A[s].nnz < 0 || A[s].nnz >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "nnz out of range");
+    if (A[s].n <= 0 || rf * A[s].n >= (int64_t(1) << 31)) fail(ADS_ERR_ARG, "n out of range");
+    if (A[s].nnz < 0 || rf * rf * A[s].nnz >= (int64_t(1) << 31))
+      fail(ADS_ERR_ARG, "nnz out of range");
     if (!A[s].row_ptr || !A[s].col || !A[s].val) fail(ADS_ERR_ARG, "null CSR array");
     if (!part[s]) fail(ADS_ERR_ARG, "null partition");
     if (nparts[s] <= 0) fail(ADS_ERR_ARG, "nparts must be positive");
@@ -247,6 +306,8 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->stream = st;
     c->mem.stream = st;
     c->opt = *opts;
+    c->cplx = cplx ? 1 : 0;
+    c->opt.nev = (int32_t)(rf * opts->nev);  // real coarse vectors of the real form
     c->prec = opts->precision;
     c->nsys = nsys;
     Timer tm(st);
@@ -257,9 +318,9 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     c->sys_sub.assign(nsys + 1, 0);
     std::vector<int64_t> sys_nnz(nsys + 1, 0);
     for (int s = 0; s < nsys; ++s) {
-      c->sys_row[s + 1] = c->sys_row[s] + A[s].n;
+      c->sys_row[s + 1] = c->sys_row[s] + rf * A[s].n;
       c->sys_sub[s + 1] = c->sys_sub[s] + nparts[s];
-      sys_nnz[s + 1] = sys_nnz[s] + A[s].nnz;
+      sys_nnz[s + 1] = sys_nnz[s] + rf * rf * A[s].nnz;
     }
     c->n = c->sys_row[nsys];
     c->nnz = sys_nnz[nsys];
@@ -279,7 +340,7 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
         const int32_t p = part[s][r];
         if (p < 0 || p >= nparts[s])
           fail(ADS_ERR_ARG, "part value out of range in system " + std::to_string(s));
-        pg[c->sys_row[s] + r] = p + c->sys_sub[s];
+        for (int64_t t = 0; t < rf; ++t) pg[c->sys_row[s] + rf * r + t] = p + c->sys_sub[s];
       }
       for (int q = c->sys_sub[s]; q < c->sys_sub[s + 1]; ++q) c->sub_sys[q] = s;
     }
@@ -300,6 +361,13 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     build_maps(*c, pg);
     c->t_phase_ms[0] = tm.lap();
     extract_local(*c);
+    if (c->cplx)
+      for (int i = 0; i < c->nsub; ++i)
+        if (c->h_kdim[i])
+          fail(ADS_ERR_UNSUPPORTED,
+               "complex A: the splitting of subdomain " + std::to_string(i) +
+                   " has the constant null vector (a floating subdomain), whose real form is "
+                   "two-dimensional; only one-dimensional kernels are implemented");
     c->t_phase_ms[1] = tm.lap();
     tune_tiles(*c);
     c->t_phase_ms[7] = tm.lap();
@@ -372,16 +440,16 @@ int ads_setup(const ads_csr* A, const int32_t* part, int32_t nparts, const ads_o
   return ads_setup_batched(1, A, &part, &nparts, opts, hip_stream, out);
 }
 
-int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part,
-                      const int32_t* nparts, const ads_options* opts, void* hip_stream,
-                      ads_ctx** out) {
+static int setup_entry(int32_t nsys, const ads_csr* A, const int32_t* const* part,
+                       const int32_t* nparts, const ads_options* opts, void* hip_stream,
+                       ads_ctx** out, bool cplx) {
   if (!out) {
     g_last_error = "out is NULL";
     return ADS_ERR_ARG;
   }
   *out = nullptr;
   try {
-    Ctx* c = setup_impl(nsys, A, part, nparts, opts, (hipStream_t)hip_stream);
+    Ctx* c = setup_impl(nsys, A, part, nparts, opts, (hipStream_t)hip_stream, cplx);
     *out = new ads_ctx{c};
     return ADS_OK;
   } catch (const Error& e) {
@@ -393,6 +461,18 @@ int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part
     g_last_error = "unknown error";
     return ADS_ERR_HIP;
   }
+}
+
+int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part,
+                      const int32_t* nparts, const ads_options* opts, void* hip_stream,
+                      ads_ctx** out) {
+  return setup_entry(nsys, A, part, nparts, opts, hip_stream, out, false);
+}
+
+int ads_setup_complex(int32_t nsys, const ads_csr* A, const int32_t* const* part,
+                      const int32_t* nparts, const ads_options* opts, void* hip_stream,
+                      ads_ctx** out) {
+  return setup_entry(nsys, A, part, nparts, opts, hip_stream, out, true);
 }
 
 int ads_apply(ads_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, void* hip_stream) {
@@ -480,6 +560,7 @@ int ads_get_info(const ads_ctx* ctx, ads_info* info) {
       info->n_kernel[k] = c.prof_n[k];
     }
     info->local_resid = c.local_resid;
+    info->is_complex = c.cplx;
     info->t_mfma_update_ms = c.prof_gj_ms;
     info->n_mfma_update = c.prof_gj_n;
     info->mfma_update_flops = c.prof_gj_flops;

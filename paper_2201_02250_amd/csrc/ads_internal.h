@@ -125,8 +125,12 @@ struct Ctx {
   ads_options opt{};
   int nsys = 0;
   int nsub = 0;
-  int64_t n = 0;    // total unknowns
+  int64_t n = 0;    // total unknowns (of the real form for a complex context)
   int64_t nnz = 0;  // total entries
+  // complex A: the matrix is held in its real form (unknown j -> rows 2j, 2j+1,
+  // entry a_jk -> the block [[re, -im], [im, re]]); lumping, kernel detection,
+  // the eigenvalue selection and GMRES take the pairs into account
+  int cplx = 0;
   std::vector<int64_t> sys_row;  // [nsys+1] row offsets of the systems
   std::vector<int32_t> sys_sub;  // [nsys+1] subdomain offsets of the systems
   std::vector<int32_t> sub_sys;  // [nsub] system of each subdomain

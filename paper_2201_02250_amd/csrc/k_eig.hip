@@ -115,7 +115,8 @@ struct SmallEigLds {
 // orthonormal basis of the selected invariant subspace).  ok = 0 on failure.
 __device__ int small_eig_select(int p, const double* H, int count, double tau, SmallEigLds& L,
                                 double* lam_re, double* lam_im, int* ok_out, double* cut_gap,
-                                int count2 = 0, int* m2_out = nullptr, double* V2 = nullptr) {
+                                int count2 = 0, int* m2_out = nullptr, double* V2 = nullptr,
+                                int pair = 0) {
   const int lane = threadIdx.x;  // wave 0 only
   // leading dimension of the work matrices: odd, so that a column access by
   // the lanes of a wave spreads over the LDS banks
@@ -419,6 +420,17 @@ __device__ int small_eig_select(int p, const double* H, int count, double tau, S
     m += sel;
     mk += keep;
     if (count > 0 && !(L.mag[j] >= (1.0 - CLUSTER_RTOL) * cut)) next = fmax(next, L.mag[j]);
+  }
+  if (pair) {
+    // the real form of a complex matrix: every eigenvalue has even
+    // multiplicity (mu with conj(mu), a real mu twice), and both sets are
+    // prefixes in |lambda| order, so a count left odd by rounding takes the
+    // next eigenvalue, the partner
+    if ((m & 1) && m < p) ++m;
+    if (mk < m) mk = m;
+    if ((mk & 1) && mk < p) ++mk;
+    if (lane == 0)
+      for (int j = 0; j < p; ++j) L.selected[j] = L.rank[j] < mk;
   }
   *cut_gap = (cut > 0) ? (cut - next) / cut : 1.0;
   if (m2_out) *m2_out = mk;
@@ -936,6 +948,8 @@ struct EigArgs {
   double tau;
   double tol;
   int sym;          // A symmetric: the splitting is too, its left null vector is the constant
+  int pair;         // complex A in its real form: eigenvalues come in pairs, local rows
+                    // (2t, 2t + 1) are the real and imaginary parts of one unknown
   const int32_t* order;  // subdomain of each block of the operator launches (longest first)
 };
 
@@ -1218,7 +1232,14 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
     if (r < n) {
       if (a.x0 && j < a.x0_cols)  // learned start: interior rows of the network's block
         v = a.om_int[base + r] ? (double)a.x0[(base + r) * a.x0_cols + j] : 0.0;
-      else
+      else if (a.pair && (j & 1)) {
+        // complex A: the odd columns are i times the even ones (J x: rows
+        // (2t, 2t + 1) <- (-x_{2t+1}, x_{2t})), so that the start block, and
+        // with it the Krylov space, is closed under multiplication by i
+        const double h = adsd::hash_unit(((uint64_t)i << 40) ^ ((uint64_t)(j - 1) << 24) ^
+                                         (uint64_t)(r ^ 1));
+        v = (r & 1) ? h : -h;
+      } else
         v = adsd::hash_unit(((uint64_t)i << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)r);
     }
     X[r + j * ld] = v;
@@ -1833,7 +1854,8 @@ __global__ void __launch_bounds__(EIG_T) k_eig_rr(EigArgs a) {
   if (threadIdx.x < 64) {
     int ok = 1;
     double gap = 1.0;
-    const int m = small_eig_select(p, H, count, a.tau, se, lam_re, lam_im, &ok, &gap);
+    const int m = small_eig_select(p, H, count, a.tau, se, lam_re, lam_im, &ok, &gap, 0, nullptr,
+                                   nullptr, a.pair);
     if (threadIdx.x == 0) {
       flag[0] = m;
       flag[1] = ok;
@@ -2214,7 +2236,7 @@ __global__ void __launch_bounds__(EIG_T) k_ks_rr(EigArgs a, int final_cycle) {
     int ok = 1, mk = 0;
     double gap = 1.0;
     const int m1 = small_eig_select(m, H, a.nev - a.kdim[i], a.tau, se, lam_re, lam_im, &ok, &gap,
-                                    a.kkeepi[i] - a.kdim[i], &mk, V2);
+                                    a.kkeepi[i] - a.kdim[i], &mk, V2, a.pair);
     if (t == 0) {
       flag[0] = m1;
       flag[1] = ok;
@@ -2970,6 +2992,7 @@ void eigensolve(Ctx& c) {
   a.tau = c.opt.tau;
   a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
   a.sym = c.sym ? 1 : 0;
+  a.pair = c.cplx;
   a.order = c.sub_order;
   ADS_HIP(hipMemsetAsync(a.done, 0, nsub * 4, st));
   ADS_HIP(hipMemsetAsync(a.sweeps, 0, nsub * 4, st));

@@ -8,6 +8,13 @@
 // for bit.  The same walk gives the local bandwidth (block size of the
 // factorization) and the row sums of the splitting used to detect floating
 // subdomains (kernel K_i = span{1}, Section 3.2).
+//
+// Complex A is held in its real form (unknown j -> rows 2j, 2j + 1; entry z
+// -> columns 2c, 2c + 1 holding (re z, -im z) in the even row, (im z, re z)
+// in the odd one).  There the walk takes the entries in pairs: s_i sums the
+// moduli |z| (Definition 1's absolute values of complex entries), and the
+// kernel test uses the complex row sum; both rows of an unknown get the same
+// s_i, subtracted from their real diagonal entries (re a_jj - s_j).
 #include <algorithm>
 
 #include "ads_internal.h"
@@ -28,7 +35,7 @@ __global__ void k_extract_count(const int32_t* rowptr, const int32_t* col, const
                                 const uint8_t* om_int, const int64_t* om_off, const int64_t* wlo,
                                 const int64_t* whi, const int64_t* woff, const int32_t* wpos,
                                 int64_t total, int32_t* cnt, double* lsum, int32_t* bw,
-                                int32_t* nfail) {
+                                int32_t* nfail, int pair) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int maxd = 0, bad = 0, i = -1;
   if (f < total) {
@@ -41,29 +48,60 @@ __global__ void k_extract_count(const int32_t* rowptr, const int32_t* col, const
     int count = 0;
     double s = 0.0, rs = 0.0, ars = 0.0;
     double diag = 0.0;
-    for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
-      const int c = col[k];
-      const double a = val[k];
-      const int p = local_pos(wpos, wl, wh, wo, c);
-      if (p >= 0) {
-        ++count;
-        maxd = max(maxd, abs(p - r));
-        if (c == g)
-          diag = a;
-        else {
-          rs += a;
-          ars += fabs(a);
+    if (!pair) {
+      for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+        const int c = col[k];
+        const double a = val[k];
+        const int p = local_pos(wpos, wl, wh, wo, c);
+        if (p >= 0) {
+          ++count;
+          maxd = max(maxd, abs(p - r));
+          if (c == g)
+            diag = a;
+          else {
+            rs += a;
+            ars += fabs(a);
+          }
+        } else if (overlap_row) {
+          s += fabs(a);
         }
-      } else if (overlap_row) {
-        s += fabs(a);
       }
+      const double dt = diag - s;  // diagonal of the splitting
+      rs += dt;
+      ars += fabs(dt);
+      bad = !(fabs(rs) <= KERNEL_ROWSUM_TOL * ars);
+    } else {
+      const bool odd = g & 1;
+      double rsi = 0.0, dim = 0.0;  // imaginary parts of the row sum and diagonal
+      for (int k = rowptr[g]; k < rowptr[g + 1]; k += 2) {
+        const int c = col[k];  // even: the pair (c, c + 1) is one complex entry
+        const double a0 = val[k], a1 = val[k + 1];
+        const double zr = odd ? a1 : a0, zi = odd ? a0 : -a1;
+        const double mod = hypot(zr, zi);  // same arguments in both rows of the unknown
+        const int p = local_pos(wpos, wl, wh, wo, c);
+        if (p >= 0) {
+          count += 2;
+          maxd = max(maxd, max(abs(p - r), abs(p + 1 - r)));
+          if (c == (g & ~1)) {
+            diag = zr;
+            dim = zi;
+          } else {
+            rs += zr;
+            rsi += zi;
+            ars += mod;
+          }
+        } else if (overlap_row) {
+          s += mod;
+        }
+      }
+      const double dt = diag - s;  // real part of the splitting's diagonal
+      rs += dt;
+      rsi += dim;
+      ars += hypot(dt, dim);
+      bad = !(hypot(rs, rsi) <= KERNEL_ROWSUM_TOL * ars);
     }
-    const double dt = diag - s;  // diagonal of the splitting
-    rs += dt;
-    ars += fabs(dt);
     cnt[f] = count;
     lsum[f] = overlap_row ? s : 0.0;
-    bad = !(fabs(rs) <= KERNEL_ROWSUM_TOL * ars);
   }
   // one atomic per run of equal subdomains in the wavefront
   const int lane = threadIdx.x & 63;
@@ -212,7 +250,7 @@ void extract_local(Ctx& c) {
   unsigned gb = (unsigned)((T + 255) / 256);
   ADS_LAUNCH(k_extract_count, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
              c.om_sub, c.om_int, c.om_off, c.wlo, c.whi, c.woff, c.wpos, T, cnt, c.lsum, bw,
-             nfail);
+             nfail, c.cplx);
   int64_t* lrow = c.mem.alloc<int64_t>(T + 1);
   exclusive_scan_i64(cnt, lrow, T + 1, c.mem, s);
   std::vector<int64_t> hl;

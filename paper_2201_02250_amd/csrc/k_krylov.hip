@@ -12,6 +12,15 @@
 // A cycle ends when the Arnoldi estimate reaches rtol, at m steps, at maxit,
 // or on breakdown; the true residual is then recomputed in FP64 and decides
 // convergence or restart.
+//
+// Complex A (a context of ads_setup_complex) is held in its real form and its
+// vectors interleaved: (re, im) of unknown t at rows (2t, 2t + 1).  GMRES is
+// then the complex method on those arrays: <v, w> = v^H w has real part
+// sum v_r w_r and imaginary part sum (J v)_r w_r with J = multiplication by i
+// ((J v)_{2t} = -v_{2t+1}, (J v)_{2t+1} = v_{2t}), h v = re(h) v + im(h) J v,
+// and the Hessenberg matrix, the rotations [[conj c, conj s], [-s, c]] and
+// the least-squares solve are complex.  Segments start at even rows and have
+// even length, so the partner row r ^ 1 is always in the same segment.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -51,12 +60,14 @@ typedef const double __attribute__((address_space(1)))* gcdptr;
 
 // partial inner products <V_i, w> for i <= jq[q] over one row chunk: every
 // thread keeps its 4 rows of w in registers and streams V_i; one wavefront
-// sum per vector, the 4 wavefront sums added in order
+// sum per vector, the 4 wavefront sums added in order.  CPLX: (re, im) of
+// each product at [2i], [2i + 1]
+template <bool CPLX>
 __global__ void __launch_bounds__(KR_T)
 k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w, KInst I,
                const int32_t* __restrict__ jq, const int32_t* __restrict__ act, double* part,
                int stride) {
-  __shared__ double wsum[KR_T / 64][66];
+  __shared__ double wsum[KR_T / 64][2 * 66];
   const int q = blockIdx.y, ch = blockIdx.x;
   if (!act[q]) return;
   const int J = jq[q];
@@ -65,7 +76,7 @@ k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w
   if (a >= len) return;
   const int64_t off = (int64_t)I.colj[q] * I.n + r0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double wr[4];
+  double wr[4], wj[4];
   int64_t rr[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -74,18 +85,30 @@ k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w
     rr[k] = ok ? r : a;  // clamped (its w is zeroed)
     const double x = w[off + rr[k]];
     wr[k] = ok ? x : 0.0;
+    if (CPLX) {  // the partner row of w, signed so that sum v_r wj_r = im <v, w>
+      const double y = w[off + (rr[k] ^ 1)];
+      wj[k] = ok ? ((rr[k] & 1) ? -y : y) : 0.0;
+    }
   }
 #pragma unroll 2
   for (int i = 0; i <= J; ++i) {
     const gcdptr vi = (gcdptr)(V[i] + off);
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc += vi[rr[k]] * wr[k];
+    for (int k = 0; k < 4; ++k) {
+      const double v = vi[rr[k]];
+      acc += v * wr[k];
+      if (CPLX) acc2 += v * wj[k];
+    }
     acc = adsd::wave_sum(acc);
-    if (lane == 0) wsum[wv][i] = acc;
+    if (CPLX) acc2 = adsd::wave_sum(acc2);
+    if (lane == 0) {
+      wsum[wv][CPLX ? 2 * i : i] = acc;
+      if (CPLX) wsum[wv][2 * i + 1] = acc2;
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= J; i += blockDim.x) {
+  for (int i = threadIdx.x; i < (CPLX ? 2 : 1) * (J + 1); i += blockDim.x) {
     double s = 0.0;
     for (int k = 0; k < KR_T / 64; ++k) s += wsum[k][i];
     part[((int64_t)q * I.nch + ch) * stride + i] = s;
@@ -93,15 +116,16 @@ k_mdot_partial(const double* const* __restrict__ V, const double* __restrict__ w
 }
 
 // h[q][i] = sum over chunks (lanes stride the chunks, then a wavefront sum:
-// fixed order); mode 1 accumulates into h.  One wavefront per i.
+// fixed order); mode 1 accumulates into h.  One wavefront per i; mult = 2
+// for the (re, im) entries of complex products.
 __global__ void k_mdot_final(const double* part, KInst I, const int32_t* jq, const int32_t* act,
-                             double* h, int stride, int accumulate) {
+                             double* h, int stride, int accumulate, int mult) {
   const int q = blockIdx.x;
   if (!act[q]) return;
   const int64_t len = I.rows[q];
   const int nch = (int)((len + CH_ROWS - 1) / CH_ROWS);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wv; i <= jq[q]; i += nw) {
+  for (int i = wv; i < mult * (jq[q] + 1); i += nw) {
     double s = 0.0;
     for (int ch = lane; ch < nch; ch += 64) s += part[((int64_t)q * I.nch + ch) * stride + i];
     s = adsd::wave_sum(s);
@@ -114,7 +138,8 @@ __global__ void k_mdot_final(const double* part, KInst I, const int32_t* jq, con
   }
 }
 
-// w -= sum_i h_i V_i (h from the last CGS pass)
+// w -= sum_i h_i V_i (h from the last CGS pass; CPLX: complex h_i)
+template <bool CPLX>
 __global__ void k_cgs_update(const double* const* __restrict__ V, double* __restrict__ w, KInst I,
                              const int32_t* __restrict__ jq, const int32_t* __restrict__ act,
                              const double* __restrict__ h, int stride) {
@@ -126,7 +151,13 @@ __global__ void k_cgs_update(const double* const* __restrict__ V, double* __rest
   const int J = jq[q];
   const double* hq = h + (int64_t)q * stride;
   double v = w[idx];
-  for (int i = 0; i <= J; ++i) v -= hq[i] * V[i][idx];
+  if (!CPLX) {
+    for (int i = 0; i <= J; ++i) v -= hq[i] * V[i][idx];
+  } else {
+    const int64_t pj = idx ^ 1;                 // partner row
+    const double sg = (idx & 1) ? 1.0 : -1.0;   // (J V)_idx = sg * V_pj
+    for (int i = 0; i <= J; ++i) v -= hq[2 * i] * V[i][idx] + hq[2 * i + 1] * sg * V[i][pj];
+  }
   w[idx] = v;
 }
 
@@ -203,6 +234,7 @@ struct KState {
   int32_t* brk;   // [Q] breakdown flag
   int m;
   int stride;
+  int cplx;       // complex: H, cs, sn, g, h, h2 hold (re, im) pairs
 };
 
 __global__ void k_arnoldi_finish(KState S, const int32_t* act, int Q) {
@@ -241,6 +273,81 @@ __global__ void k_arnoldi_finish(KState S, const int32_t* act, int Q) {
   S.brk[q] = (hn <= 1e-14 * sqrt(hc2)) ? 1 : 0;
 }
 
+// complex Arnoldi bookkeeping (S.cplx): the same steps in complex arithmetic,
+// every array entry a (re, im) pair
+__global__ void k_arnoldi_finish_c(KState S, const int32_t* act, int Q) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q || !act[q]) return;
+  const int m = S.m, j = S.jq[q];
+  double* H = S.H + (int64_t)q * 2 * (m + 1) * m;  // entry (i, c) at 2 (i + c (m + 1))
+  double* cs = S.cs + (int64_t)q * 2 * m;
+  double* sn = S.sn + (int64_t)q * 2 * m;
+  double* g = S.g + (int64_t)q * 2 * (m + 1);
+  const double* h = S.h + (int64_t)q * S.stride;
+  const double* h2 = S.h2 + (int64_t)q * S.stride;
+  const int64_t cj = (int64_t)j * (m + 1);
+  double hc2 = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    const double re = h[2 * i] + h2[2 * i], im = h[2 * i + 1] + h2[2 * i + 1];
+    H[2 * (i + cj)] = re;
+    H[2 * (i + cj) + 1] = im;
+    hc2 += re * re + im * im;
+  }
+  const double hn = S.hn[q];
+  hc2 += hn * hn;
+  for (int i = 0; i < j; ++i) {
+    const double ar = H[2 * (i + cj)], ai = H[2 * (i + cj) + 1];
+    const double br = H[2 * (i + 1 + cj)], bi = H[2 * (i + 1 + cj) + 1];
+    const double cr = cs[2 * i], ci = cs[2 * i + 1], sr = sn[2 * i], si = sn[2 * i + 1];
+    // conj(c) a + conj(s) b ;  -s a + c b
+    H[2 * (i + cj)] = cr * ar + ci * ai + sr * br + si * bi;
+    H[2 * (i + cj) + 1] = cr * ai - ci * ar + sr * bi - si * br;
+    H[2 * (i + 1 + cj)] = -(sr * ar - si * ai) + (cr * br - ci * bi);
+    H[2 * (i + 1 + cj) + 1] = -(sr * ai + si * ar) + (cr * bi + ci * br);
+  }
+  const double ar = H[2 * (j + cj)], ai = H[2 * (j + cj) + 1];
+  const double den = hypot(hypot(ar, ai), hn);
+  const double cr = den > 0 ? ar / den : 1.0, ci = den > 0 ? ai / den : 0.0;
+  const double sr = den > 0 ? hn / den : 0.0;  // s = h_{j+1,j} / rho is real
+  cs[2 * j] = cr;
+  cs[2 * j + 1] = ci;
+  sn[2 * j] = sr;
+  sn[2 * j + 1] = 0.0;
+  H[2 * (j + cj)] = den;
+  H[2 * (j + cj) + 1] = 0.0;
+  H[2 * (j + 1 + cj)] = 0.0;
+  H[2 * (j + 1 + cj) + 1] = 0.0;
+  const double gr = g[2 * j], gi = g[2 * j + 1];
+  g[2 * (j + 1)] = -sr * gr;
+  g[2 * (j + 1) + 1] = -sr * gi;
+  g[2 * j] = cr * gr + ci * gi;  // conj(c) g_j
+  g[2 * j + 1] = cr * gi - ci * gr;
+  S.est[q] = hypot(g[2 * (j + 1)], g[2 * (j + 1) + 1]);
+  S.brk[q] = (hn <= 1e-14 * sqrt(hc2)) ? 1 : 0;
+}
+
+// complex y = H^{-1} g (size j+1), pairs in S.h
+__global__ void k_cycle_solve_c(KState S, const int32_t* endm, const int32_t* jend, int Q) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q || !endm[q]) return;
+  const int m = S.m, k = jend[q];
+  const double* H = S.H + (int64_t)q * 2 * (m + 1) * m;
+  const double* g = S.g + (int64_t)q * 2 * (m + 1);
+  double* y = S.h + (int64_t)q * S.stride;
+  for (int r = k - 1; r >= 0; --r) {
+    double vr = g[2 * r], vi = g[2 * r + 1];
+    for (int c = r + 1; c < k; ++c) {
+      const int64_t e = 2 * (r + (int64_t)c * (m + 1));
+      vr -= H[e] * y[2 * c] - H[e + 1] * y[2 * c + 1];
+      vi -= H[e] * y[2 * c + 1] + H[e + 1] * y[2 * c];
+    }
+    const int64_t d = 2 * (r + (int64_t)r * (m + 1));
+    const double dr = H[d], di = H[d + 1], dd = dr * dr + di * di;
+    y[2 * r] = (vr * dr + vi * di) / dd;
+    y[2 * r + 1] = (vi * dr - vr * di) / dd;
+  }
+}
+
 // y = H^{-1} g (size j+1), stored in S.h for the update
 __global__ void k_cycle_solve(KState S, const int32_t* endm, const int32_t* jend, int Q) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,7 +363,9 @@ __global__ void k_cycle_solve(KState S, const int32_t* endm, const int32_t* jend
   }
 }
 
-// x(q) += sum_{i<jend} y_i B_i(q)  (B = Zf for flexible, V otherwise into u)
+// x(q) += sum_{i<jend} y_i B_i(q)  (B = Zf for flexible, V otherwise into u;
+// CPLX: complex y_i)
+template <bool CPLX>
 __global__ void k_combine(const double* const* __restrict__ B, double* __restrict__ out, KInst I,
                           const int32_t* __restrict__ endm, const int32_t* __restrict__ jend,
                           const double* __restrict__ y, int stride, int accumulate) {
@@ -270,7 +379,13 @@ __global__ void k_combine(const double* const* __restrict__ B, double* __restric
   }
   const double* yq = y + (int64_t)q * stride;
   double v = accumulate ? out[idx] : 0.0;
-  for (int i = 0; i < jend[q]; ++i) v += yq[i] * B[i][idx];
+  if (!CPLX) {
+    for (int i = 0; i < jend[q]; ++i) v += yq[i] * B[i][idx];
+  } else {
+    const int64_t pj = idx ^ 1;
+    const double sg = (idx & 1) ? 1.0 : -1.0;
+    for (int i = 0; i < jend[q]; ++i) v += yq[2 * i] * B[i][idx] + yq[2 * i + 1] * sg * B[i][pj];
+  }
   out[idx] = v;
 }
 
@@ -300,8 +415,9 @@ __global__ void k_add_masked(double* __restrict__ x, const double* __restrict__ 
 __global__ void k_cycle_start(KState S, const int32_t* mask, const double* beta, int Q) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Q || !mask[q]) return;
-  double* g = S.g + (int64_t)q * (S.m + 1);
-  for (int i = 0; i <= S.m; ++i) g[i] = 0.0;
+  const int gw = S.cplx ? 2 : 1;
+  double* g = S.g + (int64_t)q * gw * (S.m + 1);
+  for (int i = 0; i < gw * (S.m + 1); ++i) g[i] = 0.0;
   g[0] = beta[q];
   S.jq[q] = 0;
 }
@@ -356,7 +472,9 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   I.Q = Q;
   I.n = n;
   I.nch = (int)((maxlen + CH_ROWS - 1) / CH_ROWS);
-  const int stride = m + 2;
+  const bool cx = c.cplx != 0;
+  const int cw = cx ? 2 : 1;  // doubles per scalar of the Hessenberg bookkeeping
+  const int stride = cw * (m + 2);
   const size_t vsz = (size_t)n * nrhs;
   std::vector<double*> hV(m + 1), hZ(flex ? m : 0);
   for (int i = 0; i <= m; ++i) hV[i] = mem.alloc<double>(vsz);
@@ -369,10 +487,11 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   KState S;
   S.m = m;
   S.stride = stride;
-  S.H = mem.alloc<double>((size_t)Q * (m + 1) * m);
-  S.cs = mem.alloc<double>((size_t)Q * m);
-  S.sn = mem.alloc<double>((size_t)Q * m);
-  S.g = mem.alloc<double>((size_t)Q * (m + 1));
+  S.cplx = cx ? 1 : 0;
+  S.H = mem.alloc<double>((size_t)Q * cw * (m + 1) * m);
+  S.cs = mem.alloc<double>((size_t)Q * cw * m);
+  S.sn = mem.alloc<double>((size_t)Q * cw * m);
+  S.g = mem.alloc<double>((size_t)Q * cw * (m + 1));
   S.h = mem.alloc<double>((size_t)Q * stride);
   S.h2 = mem.alloc<double>((size_t)Q * stride);
   // per-iteration status read by the host in one copy: est | hn | brk (int32)
@@ -494,19 +613,29 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
         ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dZ, z, I, S.jq, act_d, 1);
       ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, z, (const double*)nullptr,
                  w, n, nrhs, 0);
-      // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2
-      ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
-                 S.jq, act_d, part, stride);
-      ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h, stride, 0);
-      ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
-                 S.h, stride);
-      ADS_LAUNCH(k_mdot_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, (const double* const*)dV, w, I,
-                 S.jq, act_d, part, stride);
-      ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, S.h2, stride, 0);
-      ADS_LAUNCH(k_cgs_update, gseg, dim3(256), 0, st, (const double* const*)dV, w, I, S.jq, act_d,
-                 S.h2, stride);
+      // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, h = h1 + h2
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hp = pass ? S.h2 : S.h;
+        if (cx)
+          ADS_LAUNCH(k_mdot_partial<true>, dim3(I.nch, Q), dim3(KR_T), 0, st,
+                     (const double* const*)dV, w, I, S.jq, act_d, part, stride);
+        else
+          ADS_LAUNCH(k_mdot_partial<false>, dim3(I.nch, Q), dim3(KR_T), 0, st,
+                     (const double* const*)dV, w, I, S.jq, act_d, part, stride);
+        ADS_LAUNCH(k_mdot_final, dim3(Q), dim3(512), 0, st, part, I, S.jq, act_d, hp, stride, 0,
+                   cw);
+        if (cx)
+          ADS_LAUNCH(k_cgs_update<true>, gseg, dim3(256), 0, st, (const double* const*)dV, w, I,
+                     S.jq, act_d, hp, stride);
+        else
+          ADS_LAUNCH(k_cgs_update<false>, gseg, dim3(256), 0, st, (const double* const*)dV, w, I,
+                     S.jq, act_d, hp, stride);
+      }
       norms(w, act_d, S.hn);
-      ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
+      if (cx)
+        ADS_LAUNCH(k_arnoldi_finish_c, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
+      else
+        ADS_LAUNCH(k_arnoldi_finish, dim3((Q + 63) / 64), dim3(64), 0, st, S, act_d, Q);
     };
     auto update_and_step = [&]() {
       basis_update();
@@ -613,13 +742,22 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
     // end of cycle: x += Z y  (flexible)  or  x += M (V y)
     ADS_HIP(hipMemcpyAsync(endm_d, endm.data(), Q * 4, hipMemcpyHostToDevice, st));
     ADS_HIP(hipMemcpyAsync(jend_d, jend.data(), Q * 4, hipMemcpyHostToDevice, st));
-    ADS_LAUNCH(k_cycle_solve, dim3((Q + 63) / 64), dim3(64), 0, st, S, endm_d, jend_d, Q);
+    if (cx)
+      ADS_LAUNCH(k_cycle_solve_c, dim3((Q + 63) / 64), dim3(64), 0, st, S, endm_d, jend_d, Q);
+    else
+      ADS_LAUNCH(k_cycle_solve, dim3((Q + 63) / 64), dim3(64), 0, st, S, endm_d, jend_d, Q);
+    auto combine = [&](const double* const* B, double* out, int accumulate) {
+      if (cx)
+        ADS_LAUNCH(k_combine<true>, gseg, dim3(256), 0, st, B, out, I, endm_d, jend_d, S.h, stride,
+                   accumulate);
+      else
+        ADS_LAUNCH(k_combine<false>, gseg, dim3(256), 0, st, B, out, I, endm_d, jend_d, S.h, stride,
+                   accumulate);
+    };
     if (flex) {
-      ADS_LAUNCH(k_combine, gseg, dim3(256), 0, st, (const double* const*)dZ, x, I, endm_d, jend_d,
-                 S.h, stride, 1);
+      combine((const double* const*)dZ, x, 1);
     } else {
-      ADS_LAUNCH(k_combine, gseg, dim3(256), 0, st, (const double* const*)dV, u, I, endm_d, jend_d,
-                 S.h, stride, 0);
+      combine((const double* const*)dV, u, 0);
       apply_prec(c, u, z, nrhs, st);
       ADS_LAUNCH(k_add_masked, gseg, dim3(256), 0, st, x, z, I, endm_d);
     }

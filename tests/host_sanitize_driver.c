@@ -92,6 +92,38 @@ int main(int argc, char** argv) {
   expect(ads_setup(&An, part, 2, &o, NULL, &ctx), ADS_ERR_ARG, "setup null col");
   expect(ads_setup_batched(0, &A, NULL, NULL, &o, NULL, &ctx), ADS_ERR_ARG, "batched nsys 0");
 
+  /* complex systems: (re, im) pairs; nev counts complex vectors (<= 15) and
+   * the learned start is for real A only */
+  double zval[44];
+  for (int64_t q = 0; q < k; ++q) {
+    zval[2 * q] = val[q];
+    zval[2 * q + 1] = (col[q] == 0 && q == 0) ? 0.5 : 0.25 * (double)(q % 3);
+  }
+  ads_csr Z = {8, k, rp, col, zval, 0};
+  const int32_t* zparts[1] = {part};
+  int32_t znp = 2;
+  expect(ads_setup_complex(0, &Z, zparts, &znp, &o, NULL, &ctx), ADS_ERR_ARG, "complex nsys 0");
+  expect(ads_setup_complex(1, NULL, zparts, &znp, &o, NULL, &ctx), ADS_ERR_ARG, "complex null A");
+  bad = o; bad.nev = 16;
+  expect(ads_setup_complex(1, &Z, zparts, &znp, &bad, NULL, &ctx), ADS_ERR_ARG, "complex nev 16");
+  bad = o; bad.nev = 31; bad.tau = 0.3;
+  expect(ads_setup_complex(1, &Z, zparts, &znp, &bad, NULL, &ctx), ADS_ERR_ARG, "complex tau cap");
+  bad = o; bad.warm_start = 1; bad.gnn_weights_path = "unused";
+  expect(ads_setup_complex(1, &Z, zparts, &znp, &bad, NULL, &ctx), ADS_ERR_UNSUPPORTED,
+         "complex warm start");
+  {
+    int zs = ads_setup_complex(1, &Z, zparts, &znp, &o, NULL, &ctx);
+    if (zs == ADS_OK) {
+      ads_info zi;
+      memset(&zi, 0, sizeof zi);
+      expect(ads_get_info(ctx, &zi), ADS_OK, "complex get_info");
+      if (zi.is_complex != 1 || zi.n != 16) { fprintf(stderr, "FAIL complex info\n"); ++failures; }
+      expect(ads_destroy(ctx), ADS_OK, "complex destroy");
+    } else {
+      expect_error(zs, "complex setup without a device");
+    }
+  }
+
   /* weights files: missing, empty, wrong magic, bad shape, truncated body */
   bad = o; bad.warm_start = 1;
   snprintf(path, sizeof path, "%s/none.adsgnn", dir);
