@@ -116,10 +116,15 @@ typedef struct {
   int32_t variant;        /* ADS_VARIANT_*                                            */
   int32_t precision;      /* ADS_PREC_*                                               */
   int32_t warm_start;     /* 0: none; 1: learned warm start: the graph network's block
-                             (ads_gnn_*) starts a block subspace iteration that is run
-                             to eig_tol, with the cold exact eigensolve as fallback
+                             (ads_gnn_*) starts the exact eigensolve of eig_solver,
+                             run to eig_tol: Krylov-Schur takes as its start block
+                             fixed pseudo-random combinations of all the network's
+                             columns (the block is narrower than the network's
+                             output); the subspace iteration takes the columns
+                             themselves and falls back to the cold exact eigensolve
                              (ads_info.eig_fallbacks) if it misses the tolerance
-                             within 150 sweeps; 2: learned coarse space: the
+                             within 150 sweeps, Krylov-Schur if its start block has
+                             no full rank; 2: learned coarse space: the
                              network's block, with the kernel part (the constant)
                              in front on floating subdomains, orthonormalised on the
                              interior rows, is the coarse space itself (nev_i =

@@ -940,8 +940,10 @@ struct EigArgs {
   double* partK2;
   double* Ures;     // per subdomain kept Schur basis (order x kept, column-major)
   double* Racc;     // per subdomain two accumulated EIG_PC x EIG_PC triangular factors
-  const float* x0;  // learned start block (node rows x x0_cols), interior rows used
-  int x0_cols;
+  const float* x0;  // learned start block (node rows x x0_ld), interior rows used
+  int x0_cols;      // start columns taken from it (subspace iteration)
+  int x0_ld;        // columns of the network's block
+  int x0_mix;       // Krylov-Schur: every start column a fixed combination of all x0_ld
   int32_t* err;
   int p;
   int nev;
@@ -1230,8 +1232,20 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
     const int r = (int)(e % npad), j = (int)(e / npad);
     double v = 0.0;
     if (r < n) {
-      if (a.x0 && j < a.x0_cols)  // learned start: interior rows of the network's block
-        v = a.om_int[base + r] ? (double)a.x0[(base + r) * a.x0_cols + j] : 0.0;
+      if (a.x0 && a.x0_mix) {
+        // learned start for the block Krylov method: the block is narrower
+        // than the network's (x0_ld columns spanning an approximation of the
+        // wanted space), so each start column is a fixed pseudo-random
+        // combination of all of them; one expansion then reaches the rest
+        double acc = 0.0;
+        if (a.om_int[base + r])
+          for (int q = 0; q < a.x0_ld; ++q)
+            acc += (double)a.x0[(base + r) * a.x0_ld + q] *
+                   adsd::hash_unit((0x5EEDull << 40) ^ ((uint64_t)q << 8) ^ (uint64_t)j);
+        v = acc;
+      } else if (a.x0 && j < a.x0_cols) {  // interior rows of the network's block
+        v = a.om_int[base + r] ? (double)a.x0[(base + r) * a.x0_ld + j] : 0.0;
+      }
       else if (a.pair && (j & 1)) {
         // complex A: the odd columns are i times the even ones (J x: rows
         // (2t, 2t + 1) <- (-x_{2t+1}, x_{2t})), so that the start block, and
@@ -2837,8 +2851,9 @@ void eigensolve(Ctx& c) {
     c.eig_fallbacks = nsub;  // a rank-deficient prediction: exact eigensolve
     c.gnn_x = nullptr;
   }
-  // learned warm start: block subspace iteration started from the
-  // network's block, with the exact cold eigensolve as the fallback
+  // learned warm start: the exact eigensolve (Krylov-Schur or block
+  // subspace iteration) started from the network's block, with the exact
+  // cold eigensolve as the fallback
   const bool warm = c.gnn_x && c.opt.warm_start == 1;
   // block subspace iteration: block of p columns
   int p = std::min(PMAX, std::max(2 * nev, nev + 8));
@@ -2865,7 +2880,7 @@ void eigensolve(Ctx& c) {
     h_kkeep[i] = kk;
     ks_fits = ks_fits && ki >= nev + 2 * EIG_PC && kk >= nev && kk + EIG_PC <= ki;
   }
-  const bool ks = !warm && !c.eig_ks_lost_rank && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && ks_fits;
+  const bool ks = !c.eig_ks_lost_rank && c.opt.eig_solver == ADS_EIG_KRYLOV_SCHUR && ks_fits;
   if (!ks && p < nev + 1)
     fail(ADS_ERR_UNSUPPORTED, "nev too large for the smallest subdomain or for the eigensolver");
   c.eig_krylov_schur = ks;
@@ -2988,6 +3003,8 @@ void eigensolve(Ctx& c) {
   a.p = pw;
   a.x0 = warm ? c.gnn_x : nullptr;
   a.x0_cols = warm ? std::min(c.gnn_cols, pw) : 0;
+  a.x0_ld = c.gnn_cols;
+  a.x0_mix = (warm && ks) ? 1 : 0;
   a.nev = nev;
   a.tau = c.opt.tau;
   a.tol = c.opt.eig_tol > 0 ? c.opt.eig_tol : (c.prec == ADS_PREC_FP64 ? 1e-10 : 1e-3);
@@ -3027,9 +3044,13 @@ void eigensolve(Ctx& c) {
       if (q) c.mem.release(q);
   };
   if (warm) {
+    // subspace iteration: every subdomain must reach the tolerance within
+    // the warm budget; Krylov-Schur ends as a cold run does, and a start
+    // block without rank (a network that predicts nothing) is an error
     download(hdone, a.done, nsub, st);
     int missed = 0;
-    for (int i = 0; i < nsub; ++i) missed += hdone[i] != 1;
+    if (!ks)
+      for (int i = 0; i < nsub; ++i) missed += hdone[i] != 1;
     if (missed || herr[0]) {  // fallback: the exact eigensolve from a cold start
       release_all();
       c.eig_fallbacks = std::max(missed, 1);

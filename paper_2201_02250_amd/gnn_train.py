@@ -3,18 +3,21 @@ diffusion workload (2D -div(k grad u), 256 x 256, k = exp(2 g) with g a
 unit Gaussian field of correlation length 0.05, 8 x 8 blocks, overlap 1,
 nev 8).
 
-Data: for every training field the exact method itself (FP64 setup on the
-GPU) computes the coarse space W_i of every subdomain; the targets are those
-blocks and the inputs the subdomain graphs with their node features
+Data: the fields of numpy generator seeds 0 .. fields + val - 1 (the
+workload's own recipe); for every one the exact method itself (FP64 setup on
+the GPU) computes the coarse space W_i of every subdomain; the targets are
+those blocks and the inputs the subdomain graphs with their node features
 (ads_gnn_graph_build).  Training: Adam on the projection loss, one field (64
 subdomain graphs) per step, with the library's forward and backward kernels.
-Evaluation on held-out fields: GMRES(30) iterations to 1e-8 with the exact
-coarse space, with the learned coarse space (warm_start = 2), without a
-coarse space (RAS), and the eigensolver sweeps of the warm-started exact
-eigensolve (warm_start = 1) against the cold block subspace iteration.
+Evaluation on held-out fields (seeds from 100000): GMRES(30) iterations to
+1e-8 with the exact coarse space, with the learned coarse space
+(warm_start = 2) and without a coarse space (RAS), and the eigensolver work
+(block steps or sweeps, and time) of the warm-started exact eigensolve
+(warm_start = 1) against the cold one, for Krylov-Schur (the default) and
+the block subspace iteration.
 
     python -m paper_2201_02250_amd.gnn_train --fields 2000 --epochs 8 \
-        --out paper_2201_02250_amd/gnn/c4_lognormal_nev8.adsgnn
+        --eval 200 --out paper_2201_02250_amd/gnn/c4_lognormal_nev8.adsgnn
 
 Orchestration only: every arithmetic step runs in the library's kernels.
 """
@@ -59,7 +62,8 @@ def make_data(seeds, pattern, part, N, opts, stream):
     indptr, indices, n, m = pattern
     out, struct = [], None
     for k, s in enumerate(seeds):
-        vals = W.lognormal2d_values_torch(m, s, indptr, indices)
+        Ah = W.config(WORKLOAD, seed=s)[0]  # same pattern for every seed
+        vals = torch.tensor(Ah.data, dtype=torch.float64, device=indptr.device)
         A = field_csr(n, indptr, indices, vals)
         ctx = ads.Context(A, part, N, opts["overlap"], opts["nev"], stream=stream)
         g = G.Graph.from_context(ctx, stream)
@@ -159,8 +163,9 @@ def evaluate(weights, fields, first_seed=100000, precision=0):
         res = {}
         for label, kw in [("exact", dict()), ("learned", dict(warm_start=2)),
                           ("ras", dict(variant=ads.ADS_VARIANT_RAS)),
+                          ("warm", dict(warm_start=1)),
                           ("cold_subspace", dict(eig_solver=ads.ADS_EIG_SUBSPACE)),
-                          ("warm", dict(warm_start=1))]:
+                          ("warm_subspace", dict(warm_start=1, eig_solver=ads.ADS_EIG_SUBSPACE))]:
             ctx = ads.Context(Ad, part, N, o["overlap"], o["nev"], gnn_weights_path=weights,
                               precision=precision, **kw)
             x, info = ctx.solve(b, restart=o["restart"], rtol=1e-8)
@@ -170,12 +175,17 @@ def evaluate(weights, fields, first_seed=100000, precision=0):
                               eig_ms=ctx.info["t_phase_ms"][3], gnn_ms=ctx.info["t_phase_ms"][6])
             ctx.close()
         rows.append(res)
-        log(f"[eval] field {k}: " + ", ".join(f"{l} its {r['its']}" for l, r in res.items()) +
-            f"; sweeps cold {res['cold_subspace']['sweeps']} warm {res['warm']['sweeps']}")
+        if k < 5 or (k + 1) % 20 == 0:
+            log(f"[eval] field {k}: " + ", ".join(f"{l} its {r['its']}" for l, r in res.items()) +
+                f"; Krylov-Schur block steps cold {res['exact']['sweeps']} warm "
+                f"{res['warm']['sweeps']}; subspace sweeps cold {res['cold_subspace']['sweeps']} "
+                f"warm {res['warm_subspace']['sweeps']}")
     summ = {l: dict(its=float(np.mean([r[l]["its"] for r in rows])),
+                    its_max=int(np.max([r[l]["its"] for r in rows])),
                     sweeps=float(np.mean([r[l]["sweeps"] for r in rows])),
                     fallbacks=int(np.sum([r[l]["fallbacks"] for r in rows])),
-                    eig_ms=float(np.mean([r[l]["eig_ms"] for r in rows])))
+                    eig_ms=float(np.mean([r[l]["eig_ms"] for r in rows])),
+                    gnn_ms=float(np.mean([r[l]["gnn_ms"] for r in rows])))
             for l in rows[0]}
     log("[eval] mean over %d held-out fields: %s" % (fields, json.dumps(summ)))
     return summ
