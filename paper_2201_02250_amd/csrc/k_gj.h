@@ -434,27 +434,86 @@ __device__ inline void gj_tile_of(int h, int T, int nsys, int& sy, int& ti, int&
   ti = ib + (qq - tj * Gg);
 }
 
+// The lower triangle of T x T tiles (ti >= tj) in the order of gj_tile_of:
+// T (T + 1) / 2 tiles per system; within a group of GM_GROUP tile rows the
+// full columns left of the group first, then the group's own triangle, both
+// column-major.
+__device__ inline void gj_tile_of_lower(int h, int T, int nsys, int& sy, int& ti, int& tj) {
+  const int NT = T * (T + 1) / 2;
+  const int N = NT * nsys;
+  const int q = N >> 3, r = N & 7, x = h & 7, s = h >> 3;
+  const int L = x * q + min(x, r) + s;
+  sy = L / NT;
+  int p = L - sy * NT;
+  const int G = min(T, GM_GROUP);
+  int ib = 0, Gg = min(G, T);
+  for (;;) {  // the group holding p
+    const int cnt = ib * Gg + Gg * (Gg + 1) / 2;
+    if (p < cnt || ib + Gg >= T) break;
+    p -= cnt;
+    ib += G;
+    Gg = min(G, T - ib);
+  }
+  if (p < ib * Gg) {
+    tj = p / Gg;
+    ti = ib + p % Gg;
+    return;
+  }
+  p -= ib * Gg;
+  int c = 0;
+  while (p >= Gg - c) {
+    p -= Gg - c;
+    ++c;
+  }
+  tj = ib + c;
+  ti = tj + p;
+}
+
 // 64 x 64 tile (i0, j0) of the update, K = kb <= GM_KMAX columns of the
 // panel taken in passes of GM_K through LDS: the loads of the next pass are
 // issued before the matrix-core products of the current one, so they run
 // while it computes.  Grid: T * T * nsys workgroups (gj_tile_of).  At most
 // 128 registers per lane, so that four workgroups share a compute unit.
+//
+// sym = 1 (symmetric systems without interchanges): Gauss-Jordan keeps the
+// symmetry of the matrix up to the sign of its cross blocks: with p the
+// pivots done and u the others the matrix is [[X, Y], [-Y^T, Z]], X and Z
+// symmetric.  The grid covers the lower triangle of tiles only (T (T + 1) / 2
+// per system, gj_tile_of_lower), so the upper triangle of the output is
+// stale except where the next block reads it: its pivot rows right of it
+// (the update's source rows) and its columns above it (its panel and the
+// second panel's update).  The tiles below the diagonal in the next block's
+// tile rows or columns (mir_lo, mir_lo + nb / 64) are therefore also
+// written transposed into their mirrors, negated when exactly one of the
+// two index ranges is done after this block (tiles are 64-aligned and the
+// blocks 128-aligned: one sign per tile); the transpose goes through LDS so
+// that both stores are row-contiguous.  k_gj_mirror completes the upper
+// triangle once at the end.  Half the products and about two thirds of the
+// traffic of the full update.
 __global__ void __launch_bounds__(GM_T)
 k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff,
-                 int k0, int nb, const double* Sbuf, const int32_t* src_all, int T, int nsys) {
-  __shared__ double Ssh[64 * GM_SLD];
-  __shared__ double Rsh[GM_K * GM_RLD];
+                 int k0, int nb, const double* Sbuf, const int32_t* src_all, int T, int nsys,
+                 int sym, int mir_lo) {
+  __shared__ double lds[64 * GM_SLD + GM_K * GM_RLD];  // S' | R, then the transposed tile
+  double* Ssh = lds;
+  double* Rsh = lds + 64 * GM_SLD;
   __shared__ int srow[64];
   __shared__ int rsrc[GM_KMAX];
   int sy, ti, tj;
-  gj_tile_of((int)blockIdx.x, T, nsys, sy, ti, tj);
+  if (sym)
+    gj_tile_of_lower((int)blockIdx.x, T, nsys, sy, ti, tj);
+  else
+    gj_tile_of((int)blockIdx.x, T, nsys, sy, ti, tj);
   const int n = sys_coff[sy + 1] - sys_coff[sy];
   const int i0 = ti * 64, j0 = tj * 64;
   if (i0 >= n || j0 >= n) return;
   const double* A = Ain + E_off[sy];
   double* B = Aout + E_off[sy];
   const int t = threadIdx.x;
-  if (k0 >= n) {
+  const int nbt = nb / 64;
+  const bool mirror = sym && ti > tj && mir_lo >= 0 &&
+                      ((unsigned)(ti - mir_lo) < (unsigned)nbt || (unsigned)(tj - mir_lo) < (unsigned)nbt);
+  if (k0 >= n) {  // a finished system of the batch: its lower tiles as they are
     for (int e = t; e < 64 * 64; e += GM_T) {
       const int i = i0 + e / 64, j = j0 + e % 64;
       if (i < n && j < n) B[(int64_t)i * n + j] = A[(int64_t)i * n + j];
@@ -546,6 +605,57 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
       const int i = i0 + e / 64, j = j0 + e % 64;
       if (i < n && j < n && j >= k0 && j < k0 + kb) B[(int64_t)i * n + j] = S[(int64_t)i * nb + (j - k0)];
     }
+  if (!mirror) return;
+  // the mirror tile: Tl(ii, jj) = the value just stored at (i0 + ii, j0 + jj),
+  // written to (j0 + jj, i0 + ii), negated across the done / not-done border
+  constexpr int TLD = 65;
+  double* Tl = lds;
+  __syncthreads();  // every wave is done with S' and R
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = wr + bi * 16 + lk + 4 * r, jj = wc + bj * 16 + li;
+        Tl[ii * TLD + jj] = acc[bi][bj][r];
+      }
+  __syncthreads();
+  if (touch)
+    for (int e = t; e < 64 * 64; e += GM_T) {
+      const int ii = e / 64, jj = e % 64, i = i0 + ii, j = j0 + jj;
+      if (i < n && j < n && j >= k0 && j < k0 + kb) Tl[ii * TLD + jj] = S[(int64_t)i * nb + (j - k0)];
+    }
+  if (touch) __syncthreads();
+  const int done = k0 + kb;
+  const double sg = ((i0 < done) != (j0 < done)) ? -1.0 : 1.0;
+  for (int e = t; e < 64 * 64; e += GM_T) {
+    const int jj = e / 64, ii = e % 64, i = i0 + ii, j = j0 + jj;
+    if (i < n && j < n) B[(int64_t)j * n + i] = sg * Tl[ii * TLD + jj];
+  }
+}
+
+// The upper triangle of the symmetric result from its lower triangle (all
+// pivots done: no signs), one tile below the diagonal per workgroup
+// (gj_tile_of_lower order, diagonal tiles skipped), transposed through LDS.
+__global__ void __launch_bounds__(GM_T)
+k_gj_mirror(double* A_all, const int64_t* E_off, const int32_t* sys_coff, int T, int nsys) {
+  __shared__ double Tl[64 * 65];
+  int sy, ti, tj;
+  gj_tile_of_lower((int)blockIdx.x, T, nsys, sy, ti, tj);
+  const int n = sys_coff[sy + 1] - sys_coff[sy];
+  const int i0 = ti * 64, j0 = tj * 64;
+  if (ti == tj || i0 >= n || j0 >= n) return;
+  double* A = A_all + E_off[sy];
+  for (int e = threadIdx.x; e < 64 * 64; e += GM_T) {
+    const int ii = e / 64, jj = e % 64;
+    Tl[ii * 65 + jj] = (i0 + ii < n && j0 + jj < n) ? A[(int64_t)(i0 + ii) * n + j0 + jj] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += GM_T) {
+    const int jj = e / 64, ii = e % 64;
+    if (i0 + ii < n && j0 + jj < n) A[(int64_t)(j0 + jj) * n + i0 + ii] = Tl[ii * 65 + jj];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1145,9 +1255,13 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         ADS_HIP(hipEventCreate(&e1));
         ADS_HIP(hipEventRecord(e0, st));
       }
-      ADS_LAUNCH(k_gj_update_mfma, dim3(tiles * tiles * (unsigned)nsys), dim3(GM_T), 0, st,
+      // symmetric systems without interchanges: the lower triangle of tiles
+      const unsigned ntile = direct ? tiles * (tiles + 1) / 2 : tiles * tiles;
+      const int mir_lo = k0 + nb < maxs ? (int)((k0 + nb) / 64) : -1;  // the next block's tiles
+      ADS_LAUNCH(k_gj_update_mfma, dim3(ntile * (unsigned)nsys), dim3(GM_T), 0, st,
                  bufs[cur], bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S,
-                 direct ? (const int32_t*)nullptr : (const int32_t*)src, (int)tiles, nsys);
+                 direct ? (const int32_t*)nullptr : (const int32_t*)src, (int)tiles, nsys,
+                 direct ? 1 : 0, mir_lo);
       if (prof) {
         ADS_HIP(hipEventRecord(e1, st));
         c.prof_gj_ev.push_back({e0, e1});
@@ -1155,7 +1269,19 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
           const int64_t ns = h_orders[q];
           if (ns <= k0) continue;
           const int64_t kbq = std::min<int64_t>(nb, ns - k0);
-          c.prof_gj_flops += 2.0 * (double)ns * (double)(ns - kbq) * (double)kbq;
+          if (!direct) {
+            c.prof_gj_flops += 2.0 * (double)ns * (double)(ns - kbq) * (double)kbq;
+            continue;
+          }
+          // the products of the lower tiles outside the panel columns
+          double ent = 0.0;
+          for (int64_t a = 0; a < ns; a += 64) {
+            const int64_t rows = std::min<int64_t>(64, ns - a);
+            const int64_t cols = std::min<int64_t>(ns, a + 64);  // tile columns 0 .. a / 64
+            const int64_t pc = std::max<int64_t>(0, std::min<int64_t>(cols, k0 + kbq) - k0);
+            ent += (double)rows * (double)(cols - pc);
+          }
+          c.prof_gj_flops += 2.0 * ent * (double)kbq;
         }
       }
     } else
@@ -1166,6 +1292,8 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   double* result = nullptr;
   if (direct) {
     result = bufs[cur];  // identity row maps: nothing to un-permute
+    ADS_LAUNCH(k_gj_mirror, dim3(tiles * (tiles + 1) / 2 * (unsigned)nsys), dim3(GM_T), 0, st,
+               result, E_off, sys_coff, (int)tiles, nsys);
     int32_t h = 0;
     ADS_HIP(hipMemcpyAsync(&h, dflag, 4, hipMemcpyDeviceToHost, st));
     ADS_HIP(hipStreamSynchronize(st));
