@@ -1,11 +1,15 @@
 // Preconditioner apply, eq. 4 of Section 2 (restricted two-level Schwarz with
 // deflated coarse correction), or eq. 3 (RAS) without a coarse space:
 //
-//   c = R_0 r             k_coarse_restrict   (W_i^T r|Omega_Ii, partial sums per
-//                                              chunk of 512 rows of Omega_Ii)
+//   c = R_0 r             k_coarse_restrict_mf (W_i^T r|Omega_Ii on the matrix
+//                                              cores, partial sums per chunk of
+//                                              512 rows of Omega_Ii)
 //   y = A_00^{-1} c       k_coarse_prolong    (c summed from the partials, rows
 //   q = R_0^T y                                of the explicit inverse of E,
-//                                              then W_i y_i per chunk of rows)
+//                                              then W_i y_i per chunk of rows;
+//                                              a large E: k_coarse_csum,
+//                                              k_coarse_emul_mf on the matrix
+//                                              cores, k_coarse_prolong_all)
 //   t = r - A q           k_local_solve       (gathered on Omega_i from the CSR)
 //   x_i = A_ii^{-1} t|Omega_i                  (block-tridiagonal tiles)
 //   z = q + sum_i R_i^T D_i x_i               (Boolean D: owner rows only)
@@ -34,7 +38,7 @@ static constexpr int MAXNEV = 32;
 // rows of Omega_Ii per block of the coarse restriction and prolongation
 static constexpr int CO_CH = 2 * APPLY_T;
 
-// E^{-1} larger than 16 MB: y = E^{-1} c in a pass of its own (k_coarse_emul)
+// E^{-1} larger than 16 MB: y = E^{-1} c in a pass of its own (k_coarse_emul_mf)
 bool coarse_big(const Ctx& c) {
   return c.n0 > 0 && !c.h_E_off.empty() && c.h_E_off.back() * 8 > ((int64_t)16 << 20);
 }
@@ -94,33 +98,63 @@ __device__ __forceinline__ void co_block_sums(const double (&acc)[N], int m,
   }
 }
 
-// partial sums of c = W_i^T r|Omega_Ii over the rows of chunk ch:
-// part[(j n0 + coff_i + a) nch + ch]
+// Partial sums of c = W_i^T r|Omega_Ii over the rows of chunk ch,
+// part[(j n0 + coff_i + a) nch + ch], for up to 16 right-hand sides per
+// workgroup (blockIdx.z: the group of 16) on the matrix cores: c_i = W_i^T R_i over the
+// chunk's rows, the rows the K dimension.  Wave w takes rows k0 + 128 w ..
+// + 127 in steps of four (v_mfma_f64_16x16x4f64; lane l supplies
+// A(l % 16, l / 16) = W_i(row, a) and B(l / 16, l % 16) = r(row, j)), one
+// product per 16 coarse vectors; the four waves' 16 x 16 tiles are then
+// added in order through LDS.  W_i and r are read once per apply, whatever
+// the number of right-hand sides.
+typedef double co_d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(APPLY_T)
-k_coarse_restrict(const double* __restrict__ r, int64_t n, const int32_t* __restrict__ int_list,
-                  const int64_t* __restrict__ om_off, const int32_t* __restrict__ nI,
-                  const double* __restrict__ W, const int64_t* __restrict__ W_off,
-                  const int32_t* __restrict__ nev, const int32_t* __restrict__ coff,
-                  double* __restrict__ part, int n0, int nch) {
-  __shared__ double red[MAXNEV][APPLY_T / 64];
-  const int i = blockIdx.x, ch = blockIdx.y, j = blockIdx.z;
+k_coarse_restrict_mf(const double* __restrict__ r, int64_t n, const int32_t* __restrict__ int_list,
+                     const int64_t* __restrict__ om_off, const int32_t* __restrict__ nI,
+                     const double* __restrict__ W, const int64_t* __restrict__ W_off,
+                     const int32_t* __restrict__ nev, const int32_t* __restrict__ coff,
+                     double* __restrict__ part, int n0, int nch, int nrhs) {
+  __shared__ double red[APPLY_T / 64][2][16][17];
+  const int i = blockIdx.x, ch = blockIdx.y, j0 = blockIdx.z * 16;
   const int m = nev[i];
   if (m == 0) return;
-  const int k0 = ch * CO_CH, k1 = min(nI[i], k0 + CO_CH);
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int kc0 = ch * CO_CH, kc1 = min(nI[i], kc0 + CO_CH);
+  const int kw0 = kc0 + wv * (CO_CH / 4), kw1 = min(kc1, kw0 + CO_CH / 4);
   const int32_t* rows = int_list + om_off[i];
   const double* Wi = W + W_off[i];
-  const double* rj = r + (int64_t)j * n;
-  double acc[MAXNEV];
-#pragma unroll
-  for (int a = 0; a < MAXNEV; ++a) acc[a] = 0.0;
-  for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) {
-    const double rv = rj[rows[k]];
-    const double* w = Wi + (int64_t)k * m;
-#pragma unroll
-    for (int a = 0; a < MAXNEV; ++a)
-      if (a < m) acc[a] += w[a] * rv;
+  const int j = j0 + li;
+  const double* rj = r + (int64_t)min(j, nrhs - 1) * n;
+  co_d4 acc[2];
+  acc[0] = co_d4{0.0, 0.0, 0.0, 0.0};
+  acc[1] = co_d4{0.0, 0.0, 0.0, 0.0};
+  const int ntile = (m + 15) / 16;
+  for (int kk = kw0; kk < kw1; kk += 4) {
+    const int k = kk + lk;
+    const bool ok = k < kw1;
+    const int g = rows[ok ? k : kw0];
+    const double bv = (ok && j < nrhs) ? rj[g] : 0.0;
+    const double* wr = Wi + (int64_t)(ok ? k : kw0) * m;
+    const double a0 = (ok && li < m) ? wr[li] : 0.0;
+    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
+    if (ntile > 1) {
+      const double a1 = (ok && 16 + li < m) ? wr[16 + li] : 0.0;
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1], 0, 0, 0);
+    }
   }
-  co_block_sums(acc, m, red, part + ((int64_t)j * n0 + coff[i]) * nch + ch, nch);
+  // accumulator register q of lane l: D(l / 16 + 4 q, l % 16) = c(a, j)
+  for (int tt = 0; tt < ntile; ++tt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[wv][tt][lk + 4 * q][li] = acc[tt][q];
+  __syncthreads();
+  for (int e = t; e < ntile * 256; e += APPLY_T) {
+    const int tt = e >> 8, a = 16 * tt + ((e >> 4) & 15), jj = e & 15;
+    if (a >= m || j0 + jj >= nrhs) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < APPLY_T / 64; ++w) v += red[w][tt][a - 16 * tt][jj];
+    part[((int64_t)(j0 + jj) * n0 + coff[i] + a) * nch + ch] = v;
+  }
 }
 
 // Large coarse systems (E^{-1} beyond the caches): y = E^{-1} c is formed once
@@ -136,55 +170,106 @@ __global__ void k_coarse_csum(const double* __restrict__ part, int n0, int nch, 
   cy[e] = v;
 }
 
-// ... then y[j n0 + c0 + r] = sum_b E_s^{-1}(r, b) c[j n0 + c0 + b] for 32 rows
-// (blockIdx.x) of system s (blockIdx.y) and 16 right-hand sides (blockIdx.z)
-// per workgroup, over LDS tiles of 64 columns (fixed summation order)
-static constexpr int EM_R = 32, EM_B = 64, EM_J = 16;
+// ... then y = E^{-1} c on the matrix cores: a 16-row tile of E^{-1} (blockIdx.x) of
+// system blockIdx.y by 16 right-hand sides (blockIdx.z); the four waves take
+// four contiguous quarters of the columns (multiples of 64) and add their
+// tiles in order at the end.  Per 64 columns a lane loads 16 consecutive
+// entries of its row of E^{-1} and of its column of c (one 128-byte line
+// each); in step s of the 16 products lane l supplies column
+// k0 + 16 (l / 16) + s, the same for both operands, so every column is
+// taken once.  E^{-1} streams from HBM once per apply.
 __global__ void __launch_bounds__(256)
-k_coarse_emul(const double* __restrict__ cy, int n0, int nrhs, const double* __restrict__ Einv,
-              const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
-              double* __restrict__ y) {
-  __shared__ double Es[EM_R][EM_B + 1];
-  __shared__ double Cs[EM_J][EM_B + 1];
+k_coarse_emul_mf(const double* __restrict__ cy, int n0, int nrhs, const double* __restrict__ Einv,
+                 const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
+                 double* __restrict__ y) {
+  __shared__ double red[4][16][17];
   const int sy = blockIdx.y;
   const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
-  const int r0 = blockIdx.x * EM_R, j0 = blockIdx.z * EM_J;
+  const int r0 = blockIdx.x * 16, j0 = blockIdx.z * 16;
   if (r0 >= ns) return;
-  const double* E = Einv + E_off[sy];
-  const int t = threadIdx.x, r = t >> 3, jj = t & 7;
-  double acc0 = 0.0, acc1 = 0.0;
-  for (int b0 = 0; b0 < ns; b0 += EM_B) {
-    for (int e = t; e < EM_R * EM_B; e += 256) {
-      const int rr = e / EM_B, bb = e % EM_B;
-      const int gr = r0 + rr, gb = b0 + bb;
-      Es[rr][bb] = (gr < ns && gb < ns) ? E[(int64_t)gr * ns + gb] : 0.0;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int nk = (ns + 63) / 64, per = (nk + 3) / 4;
+  const int kb0 = min(ns, wv * per * 64), kb1 = min(ns, (wv + 1) * per * 64);
+  const int row = r0 + li, col = j0 + li;
+  const double* er = Einv + E_off[sy] + (int64_t)min(row, ns - 1) * ns;
+  const double* cc = cy + (int64_t)min(col, nrhs - 1) * n0 + c0;
+  const bool rok = row < ns, cok = col < nrhs;
+  co_d4 acc = co_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb0; k0 < kb1; k0 += 64) {
+    const int kl = k0 + 16 * lk;
+    double ev[16], cv[16];
+    if (kl + 16 <= ns) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        ev[q] = rok ? er[kl + q] : 0.0;
+        cv[q] = cok ? cc[kl + q] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const bool kin = kl + q < ns;
+        ev[q] = (rok && kin) ? er[min(kl + q, ns - 1)] : 0.0;
+        cv[q] = (cok && kin) ? cc[min(kl + q, ns - 1)] : 0.0;
+      }
     }
-    for (int e = t; e < EM_J * EM_B; e += 256) {
-      const int j = e / EM_B, bb = e % EM_B;
-      const int gj = j0 + j, gb = b0 + bb;
-      Cs[j][bb] = (gj < nrhs && gb < ns) ? cy[(int64_t)gj * n0 + c0 + gb] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int bb = 0; bb < EM_B; ++bb) {
-      const double ev = Es[r][bb];
-      acc0 += ev * Cs[jj][bb];
-      acc1 += ev * Cs[jj + 8][bb];
-    }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ev[q], cv[q], acc, 0, 0, 0);
   }
-  const int gr = r0 + r;
-  if (gr < ns) {
-    if (j0 + jj < nrhs) y[(int64_t)(j0 + jj) * n0 + c0 + gr] = acc0;
-    if (j0 + jj + 8 < nrhs) y[(int64_t)(j0 + jj + 8) * n0 + c0 + gr] = acc1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[wv][lk + 4 * q][li] = acc[q];
+  __syncthreads();
+  {
+    const int a = t >> 4, jj = t & 15;  // 256 threads: the 16 x 16 tile
+    if (r0 + a < ns && j0 + jj < nrhs) {
+      const double v = red[0][a][jj] + red[1][a][jj] + red[2][a][jj] + red[3][a][jj];
+      y[(int64_t)(j0 + jj) * n0 + c0 + r0 + a] = v;
+    }
   }
 }
 
-// y_i = rows coff_i .. coff_i + m of E^{-1} times c (c summed from the
-// restriction's partials in a fixed order; or, when yfull is given, the rows
-// of y that k_coarse_emul formed), then q = W_i y_i on the rows of chunk ch
+// q = W_i y_i on the rows of chunk ch for every right-hand side (y from
+// k_coarse_emul_mf): y_i in LDS, the row of W_i in registers, read once
 __global__ void __launch_bounds__(APPLY_T)
-k_coarse_prolong(const double* __restrict__ part, const double* __restrict__ yfull, int n0,
+k_coarse_prolong_all(const double* __restrict__ yfull, int n0, int nrhs,
+                     const int32_t* __restrict__ int_list, const int64_t* __restrict__ om_off,
+                     const int32_t* __restrict__ nI, const double* __restrict__ W,
+                     const int64_t* __restrict__ W_off, const int32_t* __restrict__ nev,
+                     const int32_t* __restrict__ coff, double* __restrict__ q, int64_t n) {
+  __shared__ double ys[64][MAXNEV];
+  const int i = blockIdx.x, ch = blockIdx.y;
+  const int m = nev[i];
+  const int k0 = ch * CO_CH, k1 = min(nI[i], k0 + CO_CH);
+  if (k0 >= k1) return;
+  const int32_t* rows = int_list + om_off[i];
+  if (m == 0) {
+    for (int e = threadIdx.x; e < (k1 - k0) * nrhs; e += APPLY_T)
+      q[(int64_t)(e / (k1 - k0)) * n + rows[k0 + e % (k1 - k0)]] = 0.0;
+    return;
+  }
+  for (int e = threadIdx.x; e < nrhs * m; e += APPLY_T)
+    ys[e / m][e % m] = yfull[(int64_t)(e / m) * n0 + coff[i] + e % m];
+  __syncthreads();
+  const double* Wi = W + W_off[i];
+  for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) {
+    double wr[MAXNEV];
+#pragma unroll
+    for (int a = 0; a < MAXNEV; ++a) wr[a] = a < m ? Wi[(int64_t)k * m + a] : 0.0;
+    const int g = rows[k];
+    for (int j = 0; j < nrhs; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < MAXNEV; ++a)
+        if (a < m) v += wr[a] * ys[j][a];
+      q[(int64_t)j * n + g] = v;
+    }
+  }
+}
+
+// Small E: y_i = rows coff_i .. coff_i + m of E^{-1} times c (c summed from
+// the restriction's partials in a fixed order), then q = W_i y_i on the rows
+// of chunk ch
+__global__ void __launch_bounds__(APPLY_T)
+k_coarse_prolong(const double* __restrict__ part, int n0,
                  int nch, const double* __restrict__ Einv,
                  const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
                  const int32_t* __restrict__ sub_sys, const int32_t* __restrict__ int_list,
@@ -204,9 +289,7 @@ k_coarse_prolong(const double* __restrict__ part, const double* __restrict__ yfu
     for (int k = k0 + threadIdx.x; k < k1; k += APPLY_T) qj[rows[k]] = 0.0;
     return;
   }
-  if (yfull) {
-    if (threadIdx.x < m) y[threadIdx.x] = yfull[(int64_t)j * n0 + coff[i] + threadIdx.x];
-  } else {
+  {
     const int sy = sub_sys[i];
     const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
     const double* pj = part + ((int64_t)j * n0 + c0) * nch;
@@ -820,8 +903,9 @@ static void apply_kernels(Ctx& c, const ApplyWs& w, const double* r, double* z, 
     const int nch = coarse_chunks(c);
     {
       ProfScope p1(c, 1, s);
-      ADS_LAUNCH(k_coarse_restrict, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, r, c.n,
-                 c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, w.cvec, c.n0, nch);
+      ADS_LAUNCH(k_coarse_restrict_mf, dim3(c.nsub, nch, (nrhs + 15) / 16), dim3(APPLY_T), 0, s,
+                 r, c.n, c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, w.cvec, c.n0,
+                 nch, nrhs);
     }
     double* yfull = nullptr;
     {
@@ -834,14 +918,16 @@ static void apply_kernels(Ctx& c, const ApplyWs& w, const double* r, double* z, 
                    c.n0, nch, nrhs, cy);
         int maxs = 0;
         for (int v : c.h_n0s) maxs = std::max(maxs, v);
-        ADS_LAUNCH(k_coarse_emul,
-                   dim3((unsigned)((maxs + EM_R - 1) / EM_R), (unsigned)c.nsys,
-                        (unsigned)((nrhs + EM_J - 1) / EM_J)),
+        ADS_LAUNCH(k_coarse_emul_mf,
+                   dim3((unsigned)((maxs + 15) / 16), (unsigned)c.nsys, (unsigned)((nrhs + 15) / 16)),
                    dim3(256), 0, s, cy, c.n0, nrhs, c.Einv, c.E_off, c.sys_coff, yfull);
+        ADS_LAUNCH(k_coarse_prolong_all, dim3(c.nsub, nch), dim3(APPLY_T), 0, s, yfull, c.n0, nrhs,
+                   c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, w.qvec, c.n);
+      } else {
+        ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, w.cvec,
+                   c.n0, nch, c.Einv, c.E_off, c.sys_coff, c.sub_sys_d,
+                   c.int_list, c.om_off, c.nI, c.W, c.W_off, c.nev, c.coff, w.qvec, c.n);
       }
-      ADS_LAUNCH(k_coarse_prolong, dim3(c.nsub, nch, nrhs), dim3(APPLY_T), 0, s, w.cvec, yfull,
-                 c.n0, nch, c.Einv, c.E_off, c.sys_coff, c.sub_sys_d, c.int_list, c.om_off, c.nI, c.W,
-                 c.W_off, c.nev, c.coff, w.qvec, c.n);
     }
     q = w.qvec;
   }
