@@ -173,15 +173,19 @@ __global__ void k_coarse_csum(const double* __restrict__ part, int n0, int nch, 
 // ... then y = E^{-1} c on the matrix cores: a 16-row tile of E^{-1} (blockIdx.x) of
 // system blockIdx.y by 16 right-hand sides (blockIdx.z); the four waves take
 // four contiguous quarters of the columns (multiples of 64) and add their
-// tiles in order at the end.  Per 64 columns a lane loads 16 consecutive
-// entries of its row of E^{-1} and of its column of c (one 128-byte line
-// each); in step s of the 16 products lane l supplies column
-// k0 + 16 (l / 16) + s, the same for both operands, so every column is
-// taken once.  E^{-1} streams from HBM once per apply.
+// tiles in order at the end.  Per 64 columns a wave loads its 16 rows of
+// E^{-1} and 16 columns of c row by row (64 consecutive doubles per load,
+// one 512-byte line run) into a wave-private LDS tile, the next chunk's
+// loads in flight during the products; lane l then takes column
+// k0 + 16 (l / 16) + s of both tiles in product s (the same column for both
+// operands, each column once).  E^{-1} streams from HBM once per apply.
+static constexpr int EM_LD = 64 + 1;
 __global__ void __launch_bounds__(256)
 k_coarse_emul_mf(const double* __restrict__ cy, int n0, int nrhs, const double* __restrict__ Einv,
                  const int64_t* __restrict__ E_off, const int32_t* __restrict__ sys_coff,
                  double* __restrict__ y) {
+  __shared__ double Es[4][16 * EM_LD];
+  __shared__ double Cs[4][16 * EM_LD];
   __shared__ double red[4][16][17];
   const int sy = blockIdx.y;
   const int c0 = sys_coff[sy], ns = sys_coff[sy + 1] - c0;
@@ -190,30 +194,40 @@ k_coarse_emul_mf(const double* __restrict__ cy, int n0, int nrhs, const double* 
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int nk = (ns + 63) / 64, per = (nk + 3) / 4;
   const int kb0 = min(ns, wv * per * 64), kb1 = min(ns, (wv + 1) * per * 64);
-  const int row = r0 + li, col = j0 + li;
-  const double* er = Einv + E_off[sy] + (int64_t)min(row, ns - 1) * ns;
-  const double* cc = cy + (int64_t)min(col, nrhs - 1) * n0 + c0;
-  const bool rok = row < ns, cok = col < nrhs;
-  co_d4 acc = co_d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb0; k0 < kb1; k0 += 64) {
-    const int kl = k0 + 16 * lk;
-    double ev[16], cv[16];
-    if (kl + 16 <= ns) {
+  const double* E = Einv + E_off[sy];
+  double* es = Es[wv];
+  double* cs = Cs[wv];
+  double ev[16], cv[16];
+  // row rho of the E tile and column rho of the c tile, entry k0 + lane
+  auto load = [&](int k0) {
+    const int k = k0 + lane;
+    const bool kin = k < ns;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        ev[q] = rok ? er[kl + q] : 0.0;
-        cv[q] = cok ? cc[kl + q] : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const bool kin = kl + q < ns;
-        ev[q] = (rok && kin) ? er[min(kl + q, ns - 1)] : 0.0;
-        cv[q] = (cok && kin) ? cc[min(kl + q, ns - 1)] : 0.0;
-      }
+    for (int rho = 0; rho < 16; ++rho) {
+      const int row = r0 + rho, col = j0 + rho;
+      ev[rho] = (kin && row < ns) ? E[(int64_t)row * ns + k] : 0.0;
+      cv[rho] = (kin && col < nrhs) ? cy[(int64_t)col * n0 + c0 + k] : 0.0;
     }
+  };
+  co_d4 acc = co_d4{0.0, 0.0, 0.0, 0.0};
+  if (kb0 < kb1) load(kb0);
+  // every wave runs the same number of chunks (barriers inside)
+  for (int c = 0; c < per; ++c) {
+    const int k0 = kb0 + 64 * c;
+    __syncthreads();  // the previous chunk's reads of the tiles are done
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ev[q], cv[q], acc, 0, 0, 0);
+    for (int rho = 0; rho < 16; ++rho) {
+      es[rho * EM_LD + lane] = ev[rho];
+      cs[rho * EM_LD + lane] = cv[rho];
+    }
+    __syncthreads();
+    if (k0 + 64 < kb1) load(k0 + 64);  // in flight during the products
+    if (k0 < kb1) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(es[li * EM_LD + 16 * lk + q],
+                                                   cs[li * EM_LD + 16 * lk + q], acc, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) red[wv][lk + 4 * q][li] = acc[q];

@@ -824,30 +824,46 @@ k_gj_block_inv(GjPanel in, const int32_t* sys_coff, int kp, const int32_t* picks
   }
   bool sing = false;
   for (int m = 0; m < kb; ++m) {
-    const int b = m & 1;
-    if (br == m / Q)
+    const int b = m & 1, mq = m / Q, mr = m % Q;
+    // the owners publish row m and column m of their block: the entry of
+    // the block is chosen by selects (no branch per register), the Q values
+    // go out as one contiguous store
+    if (br == mq) {
+      double v[Q];
 #pragma unroll
-      for (int ii = 0; ii < Q; ++ii)
-        if (Q * br + ii == m)
+      for (int jj = 0; jj < Q; ++jj) {
+        v[jj] = a[0][jj];
 #pragma unroll
-          for (int jj = 0; jj < Q; ++jj) prow[b][Q * bc + jj] = a[ii][jj];
-    if (bc == m / Q)
+        for (int ii = 1; ii < Q; ++ii) v[jj] = mr == ii ? a[ii][jj] : v[jj];
+      }
 #pragma unroll
-      for (int jj = 0; jj < Q; ++jj)
-        if (Q * bc + jj == m)
+      for (int jj = 0; jj < Q; ++jj) prow[b][Q * bc + jj] = v[jj];
+    }
+    if (bc == mq) {
+      double v[Q];
 #pragma unroll
-          for (int ii = 0; ii < Q; ++ii) pcol[b][Q * br + ii] = a[ii][jj];
+      for (int ii = 0; ii < Q; ++ii) {
+        v[ii] = a[ii][0];
+#pragma unroll
+        for (int jj = 1; jj < Q; ++jj) v[ii] = mr == jj ? a[ii][jj] : v[ii];
+      }
+#pragma unroll
+      for (int ii = 0; ii < Q; ++ii) pcol[b][Q * br + ii] = v[ii];
+    }
     __syncthreads();
+    // every read of the step issued before the first use
     const double piv = prow[b][m];
-    sing |= !(fabs(piv) < INFINITY) || (spd ? !(piv > 0.0) : !(piv != 0.0));
-    const double inv = piv != 0.0 ? 1.0 / piv : 1.0;
-    double pr[Q];
+    double pr[Q], pc[Q];
 #pragma unroll
     for (int jj = 0; jj < Q; ++jj) pr[jj] = prow[b][Q * bc + jj];
 #pragma unroll
+    for (int ii = 0; ii < Q; ++ii) pc[ii] = pcol[b][Q * br + ii];
+    sing |= !(fabs(piv) < INFINITY) || (spd ? !(piv > 0.0) : !(piv != 0.0));
+    const double inv = piv != 0.0 ? 1.0 / piv : 1.0;
+#pragma unroll
     for (int ii = 0; ii < Q; ++ii) {
       const int i = Q * br + ii;
-      const double f = pcol[b][i] * inv;
+      const double f = pc[ii] * inv;
 #pragma unroll
       for (int jj = 0; jj < Q; ++jj) {
         const int j = Q * bc + jj;
