@@ -469,6 +469,28 @@ __device__ inline void gj_tile_of_lower(int h, int T, int nsys, int& sy, int& ti
   ti = tj + p;
 }
 
+// The band of the next block (sym = 1): the lower tiles in tile rows or
+// tile columns bl .. bl + bq - 1, bl + bq <= T, enumerated compactly (the
+// rows first, then the columns below them), nb_tiles per system.
+__host__ __device__ inline int gj_band_tiles(int T, int bl, int bq) {
+  int cnt = 0;
+  for (int r = 0; r < bq && bl + r < T; ++r) cnt += bl + r + 1;
+  return cnt + bq * max(0, T - bl - bq);
+}
+__device__ inline void gj_band_tile_of(int h, int T, int bl, int bq, int& ti, int& tj) {
+  for (int r = 0; r < bq && bl + r < T; ++r) {
+    if (h < bl + r + 1) {
+      ti = bl + r;
+      tj = h;
+      return;
+    }
+    h -= bl + r + 1;
+  }
+  const int below = max(1, T - bl - bq);
+  tj = bl + h / below;
+  ti = bl + bq + h % below;
+}
+
 // 64 x 64 tile (i0, j0) of the update, K = kb <= GM_KMAX columns of the
 // panel taken in passes of GM_K through LDS: the loads of the next pass are
 // issued before the matrix-core products of the current one, so they run
@@ -490,29 +512,40 @@ __device__ inline void gj_tile_of_lower(int h, int T, int nsys, int& sy, int& ti
 // that both stores are row-contiguous.  k_gj_mirror completes the upper
 // triangle once at the end.  Half the products and about two thirds of the
 // traffic of the full update.
+//
+// part (sym = 1): 0 every lower tile; 1 only the band of the next block (the
+// tiles the next block's panel kernels read, which can then start while
+// part 2 runs), 2 every lower tile outside that band.
 __global__ void __launch_bounds__(GM_T)
 k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff,
                  int k0, int nb, const double* Sbuf, const int32_t* src_all, int T, int nsys,
-                 int sym, int mir_lo) {
+                 int sym, int mir_lo, int part) {
   __shared__ double lds[64 * GM_SLD + GM_K * GM_RLD];  // S' | R, then the transposed tile
   double* Ssh = lds;
   double* Rsh = lds + 64 * GM_SLD;
   __shared__ int srow[64];
   __shared__ int rsrc[GM_KMAX];
   int sy, ti, tj;
-  if (sym)
+  const int nbt = nb / 64;
+  if (sym && part == 1) {
+    const int nbd = gj_band_tiles(T, mir_lo, nbt);
+    sy = (int)blockIdx.x / nbd;
+    gj_band_tile_of((int)blockIdx.x - sy * nbd, T, mir_lo, nbt, ti, tj);
+  } else if (sym) {
     gj_tile_of_lower((int)blockIdx.x, T, nsys, sy, ti, tj);
-  else
+  } else {
     gj_tile_of((int)blockIdx.x, T, nsys, sy, ti, tj);
+  }
+  const bool band = mir_lo >= 0 && ((unsigned)(ti - mir_lo) < (unsigned)nbt ||
+                                    (unsigned)(tj - mir_lo) < (unsigned)nbt);
+  if (part == 2 && band) return;
   const int n = sys_coff[sy + 1] - sys_coff[sy];
   const int i0 = ti * 64, j0 = tj * 64;
   if (i0 >= n || j0 >= n) return;
   const double* A = Ain + E_off[sy];
   double* B = Aout + E_off[sy];
   const int t = threadIdx.x;
-  const int nbt = nb / 64;
-  const bool mirror = sym && ti > tj && mir_lo >= 0 &&
-                      ((unsigned)(ti - mir_lo) < (unsigned)nbt || (unsigned)(tj - mir_lo) < (unsigned)nbt);
+  const bool mirror = sym && ti > tj && band;
   if (k0 >= n) {  // a finished system of the batch: its lower tiles as they are
     for (int e = t; e < 64 * 64; e += GM_T) {
       const int i = i0 + e / 64, j = j0 + e % 64;
@@ -986,8 +1019,10 @@ k_gj_panel_form(GjPanel in, const int32_t* sys_coff, int kp, const double* Pinv,
 __global__ void __launch_bounds__(256)
 k_gj_narrow(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, int k0,
             const double* Wbuf, double* Cbuf) {
-  __shared__ double Ssh[64 * 65];
-  __shared__ double Rsh[64 * GM_RLD];
+  // the 64 panel columns in two passes of 32 through LDS (34 KB: the
+  // kernel fits beside the update's workgroups when they run together)
+  __shared__ double Ssh[64 * 33];
+  __shared__ double Rsh[32 * GM_RLD];
   const int sy = blockIdx.y, t = threadIdx.x;
   const int base = sys_coff[sy], n = sys_coff[sy + 1] - base;
   const int i0 = blockIdx.x * 64;
@@ -1000,14 +1035,6 @@ k_gj_narrow(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, in
   const int w = t >> 6, lane = t & 63;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  double sv[16], rv[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int r = (t >> 6) + 4 * q, c = t & 63;  // row r, column c of both tiles
-    const int i = i0 + r;
-    sv[q] = gj_keep(W[(int64_t)min(i, n - 1) * 64 + c], i < n);
-    rv[q] = gj_keep(A[(int64_t)(k0 + r) * n + jc + min(c, m - 1)], c < m);
-  }
   gj_d4 acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -1018,22 +1045,29 @@ k_gj_narrow(const double* Ain, const int64_t* E_off, const int32_t* sys_coff, in
         const int i = i0 + wr + bi * 16 + lk + 4 * r, c = wc + bj * 16 + li;
         acc[bi][bj][r] = gj_keep(A[(int64_t)min(i, n - 1) * n + jc + min(c, m - 1)], i < n && c < m);
       }
+  for (int h = 0; h < 2; ++h) {
+    if (h) __syncthreads();  // the first pass's reads are done
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int r = (t >> 6) + 4 * q, c = t & 63;
-    Ssh[r * 65 + c] = sv[q] - (i0 + r == k0 + c ? 1.0 : 0.0);
-    Rsh[r * GM_RLD + c] = rv[q];
-  }
-  __syncthreads();
-  for (int kk = 0; kk < 64; kk += 4) {
-    const double a0 = Ssh[(wr + li) * 65 + kk + lk];
-    const double a1 = Ssh[(wr + 16 + li) * 65 + kk + lk];
-    const double b0 = Rsh[(kk + lk) * GM_RLD + wc + li];
-    const double b1 = Rsh[(kk + lk) * GM_RLD + wc + 16 + li];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      const int sr = e >> 5, sc = e & 31;  // S' tile: 64 rows x 32 panel columns
+      const int i = i0 + sr, l = 32 * h + sc;
+      Ssh[sr * 33 + sc] =
+          gj_keep(W[(int64_t)min(i, n - 1) * 64 + l], i < n) - (i == k0 + l ? 1.0 : 0.0);
+      const int rr = e >> 6, rc = e & 63;  // source rows: 32 panel rows x 64 columns
+      Rsh[rr * GM_RLD + rc] = gj_keep(A[(int64_t)(k0 + 32 * h + rr) * n + jc + min(rc, m - 1)], rc < m);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double a0 = Ssh[(wr + li) * 33 + kk + lk];
+      const double a1 = Ssh[(wr + 16 + li) * 33 + kk + lk];
+      const double b0 = Rsh[(kk + lk) * GM_RLD + wc + li];
+      const double b1 = Rsh[(kk + lk) * GM_RLD + wc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -1125,6 +1159,26 @@ __global__ void k_gj_unpermute(const double* Win, double* Out, const int64_t* E_
 }
 
 
+// Algorithmic flops of one part of the symmetric update of an order-n system
+// (2 kb per entry of the lower 64 x 64 tiles outside the panel columns
+// [k0, k0 + kb)): part 0 every lower tile, 1 the band of tiles bl .. bl + bq
+// - 1 in rows or columns, 2 the others.
+static double gj_sym_update_flops(int64_t n, int64_t k0, int64_t kb, int part, int bl, int bq) {
+  const int64_t T = (n + 63) / 64;
+  double ent = 0.0;
+  for (int64_t ti = 0; ti < T; ++ti) {
+    const int64_t rows = std::min<int64_t>(64, n - 64 * ti);
+    for (int64_t tj = 0; tj <= ti; ++tj) {
+      const bool band = bl >= 0 && ((ti >= bl && ti < bl + bq) || (tj >= bl && tj < bl + bq));
+      if ((part == 1 && !band) || (part == 2 && band)) continue;
+      const int64_t c0 = 64 * tj, c1 = std::min<int64_t>(n, c0 + 64);
+      const int64_t pc = std::max<int64_t>(0, std::min(c1, k0 + kb) - std::max(c0, k0));
+      ent += (double)rows * (double)(c1 - c0 - pc);
+    }
+  }
+  return 2.0 * ent * (double)kb;
+}
+
 // Inverts the nsys row-major matrices of A in place of a ping-pong pair: system
 // sy has order sys_coff[sy + 1] - sys_coff[sy] (device arrays) and starts at
 // E_off[sy]; B has the size of A.  Returns A or B, whichever holds the
@@ -1201,26 +1255,110 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
   if (wide && (int64_t)tiles * tiles * nsys > INT32_MAX)
     fail(ADS_ERR_UNSUPPORTED, "dense inversion batch too large for one launch");
   int cur = 0;
-  for (int64_t k0 = 0; k0 < maxs; k0 += nb) {
-    if (direct) {
-      // P^{-1} of the pivot block without interchanges, then S = P^{-1} on
-      // the pivot rows and -in(i, panel) P^{-1} on the others on the matrix
-      // cores (the row maps are the identity)
-      const GjPanel p1{bufs[cur], E_off, 0, (int)k0};
-      const dim3 slabs((unsigned)((maxs + 63) / 64), (unsigned)nsys);
-      // the 128-column block from two panels of 64
-      ADS_LAUNCH(k_gj_block_inv<DNB>, dim3(nsys), dim3(256), 0, st, p1, sys_coff, (int)k0,
-                 (const int32_t*)nullptr, 0, 1, Pinv, dflag);
-      ADS_LAUNCH(k_gj_panel_form<DNB>, slabs, dim3(256), 0, st, p1, sys_coff, (int)k0, Pinv,
-                 (const int32_t*)nullptr, W1, DNB, 0);
-      ADS_LAUNCH(k_gj_narrow, slabs, dim3(256), 0, st, bufs[cur], E_off, sys_coff, (int)k0, W1, Cn);
-      const GjPanel p2{Cn, nullptr, DNB, 0};
-      ADS_LAUNCH(k_gj_block_inv<DNB>, dim3(nsys), dim3(256), 0, st, p2, sys_coff, (int)k0 + DNB,
-                 (const int32_t*)nullptr, 0, 1, Pinv, dflag);
-      ADS_LAUNCH(k_gj_panel_form<DNB>, slabs, dim3(256), 0, st, p2, sys_coff, (int)k0 + DNB, Pinv,
-                 (const int32_t*)nullptr, S, nb, DNB);
-      ADS_LAUNCH(k_gj_combine, slabs, dim3(256), 0, st, sys_coff, (int)k0, W1, S);
-    } else if (multi) {
+  if (direct) {
+    // Lookahead: the update of block b runs in two launches, first the band
+    // of tiles that block b + 1's panel kernels read, then the rest; block
+    // b + 1's panel kernels run on a second stream during the rest (their
+    // panel, pivot-block and transform buffers alternate between two slots,
+    // so they never touch what the running update reads).  The stream of the
+    // call waits for them before the next update.
+    // (only where the panel kernels leave most of the GPU to the update: a
+    // few large systems such as the coarse operator; batches of many small
+    // systems keep one stream, their panel kernels filling the GPU anyway)
+    const dim3 slabs((unsigned)((maxs + 63) / 64), (unsigned)nsys);
+    const bool lookahead = (int64_t)slabs.x * nsys <= 2048;
+    double* Sb[2] = {S, lookahead ? c.mem.alloc<double>(n0t * nb) : S};
+    double* Pb[2] = {Pinv, lookahead ? c.mem.alloc<double>((size_t)nsys * DNB * DNB) : Pinv};
+    double* Wb[2] = {W1, lookahead ? c.mem.alloc<double>(n0t * DNB) : W1};
+    double* Cb[2] = {Cn, lookahead ? c.mem.alloc<double>(n0t * DNB) : Cn};
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_band = nullptr, ev_chain = nullptr;
+    struct LaGuard {
+      hipStream_t& s;
+      hipEvent_t& a;
+      hipEvent_t& b;
+      ~LaGuard() {
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } la_guard{aux, ev_band, ev_chain};
+    if (lookahead) {
+      ADS_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+      ADS_HIP(hipEventCreateWithFlags(&ev_band, hipEventDisableTiming));
+      ADS_HIP(hipEventCreateWithFlags(&ev_chain, hipEventDisableTiming));
+    }
+    // P^{-1} of each pivot block without interchanges, then S = P^{-1} on
+    // the pivot rows and -in(i, panel) P^{-1} on the others on the matrix
+    // cores (the row maps are the identity); the 128-column block from two
+    // panels of 64
+    auto chain = [&](int64_t k0, int sl, const double* src, hipStream_t s2) {
+      const GjPanel p1{src, E_off, 0, (int)k0};
+      ADS_LAUNCH(k_gj_block_inv<DNB>, dim3(nsys), dim3(256), 0, s2, p1, sys_coff, (int)k0,
+                 (const int32_t*)nullptr, 0, 1, Pb[sl], dflag);
+      ADS_LAUNCH(k_gj_panel_form<DNB>, slabs, dim3(256), 0, s2, p1, sys_coff, (int)k0, Pb[sl],
+                 (const int32_t*)nullptr, Wb[sl], DNB, 0);
+      ADS_LAUNCH(k_gj_narrow, slabs, dim3(256), 0, s2, src, E_off, sys_coff, (int)k0, Wb[sl],
+                 Cb[sl]);
+      const GjPanel p2{Cb[sl], nullptr, DNB, 0};
+      ADS_LAUNCH(k_gj_block_inv<DNB>, dim3(nsys), dim3(256), 0, s2, p2, sys_coff, (int)k0 + DNB,
+                 (const int32_t*)nullptr, 0, 1, Pb[sl], dflag);
+      ADS_LAUNCH(k_gj_panel_form<DNB>, slabs, dim3(256), 0, s2, p2, sys_coff, (int)k0 + DNB,
+                 Pb[sl], (const int32_t*)nullptr, Sb[sl], nb, DNB);
+      ADS_LAUNCH(k_gj_combine, slabs, dim3(256), 0, s2, sys_coff, (int)k0, Wb[sl], Sb[sl]);
+    };
+    const bool prof = (c.opt.profile & 2) && h_orders;
+    auto update = [&](int64_t k0, int sl, int part, int mir_lo) {
+      unsigned grid = tiles * (tiles + 1) / 2 * (unsigned)nsys;
+      if (part == 1) grid = (unsigned)gj_band_tiles((int)tiles, mir_lo, nb / 64) * (unsigned)nsys;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof) {
+        ADS_HIP(hipEventCreate(&e0));
+        ADS_HIP(hipEventCreate(&e1));
+        ADS_HIP(hipEventRecord(e0, st));
+      }
+      ADS_LAUNCH(k_gj_update_mfma, dim3(grid), dim3(GM_T), 0, st, bufs[cur], bufs[1 - cur], E_off,
+                 sys_coff, (int)k0, nb, Sb[sl], (const int32_t*)nullptr, (int)tiles, nsys, 1,
+                 mir_lo, part);
+      if (prof) {
+        ADS_HIP(hipEventRecord(e1, st));
+        c.prof_gj_ev.push_back({e0, e1});
+        for (int q = 0; q < nsys; ++q) {
+          const int64_t ns = h_orders[q];
+          if (ns <= k0) continue;
+          c.prof_gj_flops += gj_sym_update_flops(ns, k0, std::min<int64_t>(nb, ns - k0), part,
+                                                 mir_lo, nb / 64);
+        }
+      }
+    };
+    chain(0, 0, bufs[0], st);
+    int b = 0;
+    for (int64_t k0 = 0; k0 < maxs; k0 += nb, ++b) {
+      const int sl = lookahead ? (b & 1) : 0;
+      const bool next = k0 + nb < maxs;
+      const int mir_lo = next ? (int)((k0 + nb) / 64) : -1;  // the next block's tiles
+      if (next && lookahead) {
+        update(k0, sl, 1, mir_lo);
+        ADS_HIP(hipEventRecord(ev_band, st));
+        ADS_HIP(hipStreamWaitEvent(aux, ev_band, 0));
+        chain(k0 + nb, 1 - sl, bufs[1 - cur], aux);
+        ADS_HIP(hipEventRecord(ev_chain, aux));
+        update(k0, sl, 2, mir_lo);
+        ADS_HIP(hipStreamWaitEvent(st, ev_chain, 0));
+      } else {
+        update(k0, sl, 0, mir_lo);
+        if (next) chain(k0 + nb, 0, bufs[1 - cur], st);
+      }
+      cur = 1 - cur;
+    }
+    if (lookahead)
+      for (void* q : {(void*)Sb[1], (void*)Pb[1], (void*)Wb[1], (void*)Cb[1]}) c.mem.release(q);
+  }
+  for (int64_t k0 = 0; k0 < maxs && !direct; k0 += nb) {
+    if (multi) {
       const unsigned mrows = (unsigned)(((maxs + R - 1) / R + 63) / 64 * 64);
       if (R == 2)
         ADS_LAUNCH((k_gj_panel_rows<8, 2>), dim3(nsys), dim3(mrows), 0, st, bufs[cur], E_off,
@@ -1271,13 +1409,9 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         ADS_HIP(hipEventCreate(&e1));
         ADS_HIP(hipEventRecord(e0, st));
       }
-      // symmetric systems without interchanges: the lower triangle of tiles
-      const unsigned ntile = direct ? tiles * (tiles + 1) / 2 : tiles * tiles;
-      const int mir_lo = k0 + nb < maxs ? (int)((k0 + nb) / 64) : -1;  // the next block's tiles
-      ADS_LAUNCH(k_gj_update_mfma, dim3(ntile * (unsigned)nsys), dim3(GM_T), 0, st,
+      ADS_LAUNCH(k_gj_update_mfma, dim3(tiles * tiles * (unsigned)nsys), dim3(GM_T), 0, st,
                  bufs[cur], bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S,
-                 direct ? (const int32_t*)nullptr : (const int32_t*)src, (int)tiles, nsys,
-                 direct ? 1 : 0, mir_lo);
+                 (const int32_t*)src, (int)tiles, nsys, 0, -1, 0);
       if (prof) {
         ADS_HIP(hipEventRecord(e1, st));
         c.prof_gj_ev.push_back({e0, e1});
@@ -1285,19 +1419,7 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
           const int64_t ns = h_orders[q];
           if (ns <= k0) continue;
           const int64_t kbq = std::min<int64_t>(nb, ns - k0);
-          if (!direct) {
-            c.prof_gj_flops += 2.0 * (double)ns * (double)(ns - kbq) * (double)kbq;
-            continue;
-          }
-          // the products of the lower tiles outside the panel columns
-          double ent = 0.0;
-          for (int64_t a = 0; a < ns; a += 64) {
-            const int64_t rows = std::min<int64_t>(64, ns - a);
-            const int64_t cols = std::min<int64_t>(ns, a + 64);  // tile columns 0 .. a / 64
-            const int64_t pc = std::max<int64_t>(0, std::min<int64_t>(cols, k0 + kbq) - k0);
-            ent += (double)rows * (double)(cols - pc);
-          }
-          c.prof_gj_flops += 2.0 * ent * (double)kbq;
+          c.prof_gj_flops += 2.0 * (double)ns * (double)(ns - kbq) * (double)kbq;
         }
       }
     } else
