@@ -2867,7 +2867,10 @@ void eigensolve(Ctx& c) {
   // operator (interior rows) of every subdomain
   // (a larger basis means fewer restarts, each with one dense Schur
   // decomposition per subdomain: on 2D convection-diffusion subdomains with
-  // nev 8, order 32 keeping 16 converges in the fewest block steps)
+  // nev 8, order 32 keeping 16 converges in the fewest block steps; with
+  // nev 12 on 3D coefficient-jump subdomains, keeping nev + 4 = 16 instead of
+  // 2 nev = 24 halves the restarts and their Schur decompositions for a few
+  // more block steps, a net saving)
   // per subdomain, so that a small subdomain does not shorten the basis of
   // the others (the storage takes the largest order)
   const int km = std::min(PMAX, std::max(4 * nev, nev + 24));
@@ -2875,7 +2878,7 @@ void eigensolve(Ctx& c) {
   bool ks_fits = true;
   for (int i = 0; i < nsub; ++i) {
     const int ki = std::min(km, std::min(c.h_nI[i], c.h_ni[i] - EIG_PC) - c.h_kdim[i] - 1);
-    const int kk = std::min(std::max(2 * nev, ki / 2), ki - 2 * EIG_PC);
+    const int kk = std::min(std::max(nev + 4, ki / 2), ki - 2 * EIG_PC);
     h_km[i] = ki;
     h_kkeep[i] = kk;
     ks_fits = ks_fits && ki >= nev + 2 * EIG_PC && kk >= nev && kk + EIG_PC <= ki;
