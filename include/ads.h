@@ -192,7 +192,8 @@ typedef struct {
   int64_t n_kernel[4];    /* number of timed launches of each                         */
   /* optional caller-owned host arrays of length nsub (NULL to skip): */
   int32_t* nev_i;         /* coarse vectors per subdomain                             */
-  int32_t* kernel_dim;    /* dim ker(splitting) per subdomain (0 or 1)                */
+  int32_t* kernel_dim;    /* dim ker(splitting) per subdomain (0 or 1; complex A:
+                             0 or 2, the real form of span{1})                      */
   int32_t* n_i;           /* |Omega_i|                                                */
   int32_t* n_interior;    /* |Omega_Ii|                                               */
   int32_t* sweeps;        /* eigensolver sweeps (Krylov-Schur: block steps) per subdomain */
@@ -248,10 +249,12 @@ int ads_setup_batched(int32_t nsys, const ads_csr* A, const int32_t* const* part
  * Each eigenvalue mu of eq. 5 appears as the pair (mu, conj(mu)) of the real
  * form, whose invariant subspace is the real form of the complex eigenvector;
  * nev counts complex vectors (at most 15, or 30 as the cap of the tau rule)
- * and the selection keeps whole pairs.  Refused with ADS_ERR_UNSUPPORTED: a
- * splitting with a kernel (a floating subdomain, R6's constant null vector:
- * two-dimensional in the real form) and warm_start != 0.  2n and 4 nnz must
- * stay below 2^31.  ads_info.is_complex = 1. */
+ * and the selection keeps whole pairs.  A floating subdomain (the splitting
+ * has the complex constant as null vector) has the two-dimensional kernel
+ * span{1, i 1} in the real form: two leading coarse vectors, the projections
+ * with the complex left null vector l and i l.  Refused with
+ * ADS_ERR_UNSUPPORTED: warm_start != 0.  2n and 4 nnz must stay below 2^31.
+ * ads_info.is_complex = 1. */
 int ads_setup_complex(int32_t nsys, const ads_csr* A, const int32_t* const* part,
                       const int32_t* nparts, const ads_options* opts, void* hip_stream,
                       ads_ctx** out);

@@ -361,13 +361,6 @@ static Ctx* setup_impl(int nsys, const ads_csr* A, const int32_t* const* part, c
     build_maps(*c, pg);
     c->t_phase_ms[0] = tm.lap();
     extract_local(*c);
-    if (c->cplx)
-      for (int i = 0; i < c->nsub; ++i)
-        if (c->h_kdim[i])
-          fail(ADS_ERR_UNSUPPORTED,
-               "complex A: the splitting of subdomain " + std::to_string(i) +
-                   " has the constant null vector (a floating subdomain), whose real form is "
-                   "two-dimensional; only one-dimensional kernels are implemented");
     c->t_phase_ms[1] = tm.lap();
     tune_tiles(*c);
     c->t_phase_ms[7] = tm.lap();

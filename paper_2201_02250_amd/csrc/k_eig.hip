@@ -901,8 +901,9 @@ struct EigArgs {
   double* ell;      // per subdomain npad (unit left null vector; floating only)
   double* bell;     // B * ell
   double* btl;      // B^T * ell
-  double* gam;      // per subdomain ell^T B ell
-  double* colsum;   // per (subdomain, column chunk, half) PC partial column sums of Y
+  double* gam;      // per subdomain (ell^T B ell, ell^T J B ell)
+  double* colsum;   // per (subdomain, column chunk, half, row parity) PC partial column
+                    // sums of Y (parity 1 only for complex A)
   int defer;        // 1: the projection onto 1^perp is applied by k_eig_gram
   int32_t* done;    // converged flag
   int32_t* sweeps;
@@ -955,14 +956,23 @@ struct EigArgs {
   const int32_t* order;  // subdomain of each block of the operator launches (longest first)
 };
 
+// (J v)_r in the real form of a complex vector (J multiplies by i: rows
+// (2t, 2t + 1) <- (-v_{2t+1}, v_{2t})); r < n, n even
+__device__ __forceinline__ double jrot(const double* v, int r) {
+  return (r & 1) ? v[r - 1] : -v[r + 1];
+}
+
 // transposed solve with the splitting tiles for the left null vector:
-// Atilde_reg^T l = e_last.  One-off per floating subdomain, single column.
+// Atilde_reg^T l = e_er, er the last row (real A) or the real row of the last
+// unknown (complex A; l is then the real form of the complex left null
+// vector and J l the second one).  One-off per floating subdomain, single
+// column.
 template <class FT>
-__device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const int64_t* lrow,
-                                      const int32_t* lcol, const double* lval,
-                                      const int32_t* urow, const double* uval,
-                                      const int32_t* drow, const double* dval, double* x,
-                                      double* tmp) {
+__device__ void transposed_solve_last(const FT* fac, int s, int K, int n, int er,
+                                      const int64_t* lrow, const int32_t* lcol,
+                                      const double* lval, const int32_t* urow,
+                                      const double* uval, const int32_t* drow,
+                                      const double* dval, double* x, double* tmp) {
   // urow / uval: A_k-1,k by column, drow / dval: A_k+1,k by column (NCPL
   // slots per padded column, rows ascending), or null: one thread then walks
   // the CSR rows (the same order of the sums)
@@ -972,7 +982,7 @@ __device__ void transposed_solve_last(const FT* fac, int s, int K, int n, const 
   constexpr int NC = adsd::NCPL;
   const int64_t TS = adsd::tile_size(s, V);
   const int npad = K * s;
-  for (int r = t; r < npad; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
+  for (int r = t; r < npad; r += T) x[r] = (r == er) ? 1.0 : 0.0;
   __syncthreads();
   // tmp[r] = sum_cc G(cc, r) v[cc] over cc ascending (G^T v)
   auto gt_product = [&](const FT* G, const double* v) {
@@ -1079,7 +1089,7 @@ __device__ __forceinline__ void tile_tmatvec(const FT* G, int s, const double* y
   __syncthreads();
 }
 
-// l solves Atilde_reg^T l = e_last with the two-ended splitting tiles: the
+// l solves Atilde_reg^T l = e_er with the two-ended splitting tiles: the
 // transposed system has the transposed two-ended factorization, so
 //   forward top    w_k = G_k^T (f_k - A_k-1,k^T w_{k-1})      k = 0 .. M-1
 //   forward bottom v_k = G_k^T (f_k - A_k+1,k^T v_{k+1})      k = K-1 .. M+1
@@ -1088,10 +1098,10 @@ __device__ __forceinline__ void tile_tmatvec(const FT* G, int s, const double* y
 //   backward bottom l_k = v_k - G_k^T (A_k-1,k^T l_{k-1})     k = M+1 .. K-1
 // with A_k-1,k^T and A_k+1,k^T applied by column from the coupling lists.
 // In three phases (separate launches, so that the two halves run on two
-// workgroups): 0 the forward half `half` (with its rows of e_last), 1 the
+// workgroups): 0 the forward half `half` (with its rows of e_er), 1 the
 // middle block, 2 the backward half `half`.  LDS: s (y) + T (partials).
 template <class FT>
-__device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const int32_t* urow,
+__device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, int er, const int32_t* urow,
                                      const double* uval, const int32_t* lrw, const double* lvl,
                                      double* x, double* lds, int phase, int half) {
   const int t = threadIdx.x, T = blockDim.x;
@@ -1125,7 +1135,7 @@ __device__ void transposed_solve_cpl(const FT* fac, int s, int K, int n, const i
   };
   if (phase == 0) {
     const int lo = half ? M * s : 0, hi = half ? npad : M * s;
-    for (int r = lo + t; r < hi; r += T) x[r] = (r == n - 1) ? 1.0 : 0.0;
+    for (int r = lo + t; r < hi; r += T) x[r] = (r == er) ? 1.0 : 0.0;
     __syncthreads();
     if (!half) {
       for (int k = 0; k < M; ++k) {
@@ -1167,7 +1177,8 @@ __global__ void __launch_bounds__(EIG_T) k_eig_ell(const FT* fac, EigArgs a, int
   const int i = blockIdx.x;
   if (!a.kdim[i]) return;
   const int64_t po = a.pad_off[i] * adsd::NCPL;
-  transposed_solve_cpl<FT>(fac + a.fac_off[i], a.bs[i], a.nb[i], a.ni[i], a.ucpl_row + po,
+  transposed_solve_cpl<FT>(fac + a.fac_off[i], a.bs[i], a.nb[i], a.ni[i], a.ni[i] - a.kdim[i],
+                           a.ucpl_row + po,
                            a.ucpl_val + po, a.lcpl_row + po, a.lcpl_val + po,
                            a.ell + a.pad_off[i], dyn, phase, blockIdx.y);
 }
@@ -1214,10 +1225,20 @@ __global__ void k_eig_btl(EigArgs a, const int32_t* om_sorted, const int32_t* ro
     bt[c] = v;
   }
   if (blockIdx.y != 0) return;
-  double g = 0.0;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) g += l[r] * a.bell[a.pad_off[i] + r];
+  // gam = (l^T B l, l^T J B l): the 2 x 2 matrix [l, J l]^T B [l, J l] of a
+  // complex splitting is [[g, h], [-h, g]] (B and B^T commute with J)
+  const double* bl = a.bell + a.pad_off[i];
+  double g = 0.0, h = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) g += l[r] * bl[r];
   g = adsd::block_sum(g, red);
-  if (threadIdx.x == 0) a.gam[i] = g;
+  if (a.kdim[i] == 2) {
+    for (int r = threadIdx.x; r < n; r += blockDim.x) h += l[r] * jrot(bl, r);
+    h = adsd::block_sum(h, red);
+  }
+  if (threadIdx.x == 0) {
+    a.gam[2 * i] = g;
+    a.gam[2 * i + 1] = h;
+  }
 }
 
 template <class FT, bool CPL>
@@ -1260,15 +1281,19 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
   }
   __syncthreads();
   if (a.kdim[i]) {
+    const int kd = a.kdim[i];
     double* l = a.ell + a.pad_off[i];
     extern __shared__ double dyn[];
     if (a.sym) {
       // symmetric splitting: its left null vector is its right one, the
-      // constant (exact, no solve with the ill-conditioned regularised matrix)
-      for (int r = threadIdx.x; r < npad; r += blockDim.x) l[r] = r < n ? 1.0 : 0.0;
+      // constant (exact, no solve with the ill-conditioned regularised matrix);
+      // complex A: the real form of the complex constant, 1 on the real rows
+      for (int r = threadIdx.x; r < npad; r += blockDim.x)
+        l[r] = (r < n && (kd == 1 || !(r & 1))) ? 1.0 : 0.0;
       __syncthreads();
     } else if constexpr (!CPL) {  // (with the coupling lists, k_eig_ell has formed l)
-      transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol, a.lval,
+      transposed_solve_last<FT>(fac + a.fac_off[i], s, K, n, n - kd, a.lrow + base, a.lcol,
+                                a.lval,
                                 a.cpl_ok ? a.ucpl_row + a.pad_off[i] * adsd::NCPL : nullptr,
                                 a.cpl_ok ? a.ucpl_val + a.pad_off[i] * adsd::NCPL : nullptr,
                                 a.cpl_ok ? a.lcpl_row + a.pad_off[i] * adsd::NCPL : nullptr,
@@ -1290,13 +1315,28 @@ __global__ void __launch_bounds__(EIG_T) k_eig_init(const FT* fac, EigArgs a, do
           if (a.om_int[base + a.lcol[q]]) v += a.lval[q] * l[a.lcol[q]];
       bl[r] = v;
     }
-    // X <- projection onto 1^perp, column j by wave j mod (number of waves)
+    // X <- projection onto K^perp, column j by wave j mod (number of waves):
+    // minus the column mean (complex A: the means of the real and of the
+    // imaginary rows, K being span{1, J 1} in the real form)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int j = wv; j < p; j += nw) {
-      double sm = 0.0;
-      for (int r = lane; r < n; r += 64) sm += X[r + j * ld];
-      sm = adsd::wave_sum(sm) / n;
-      for (int r = lane; r < n; r += 64) X[r + j * ld] -= sm;
+      if (kd == 2) {
+        double se = 0.0, so = 0.0;
+        for (int r = lane; r < n; r += 64) {
+          if (r & 1)
+            so += X[r + j * ld];
+          else
+            se += X[r + j * ld];
+        }
+        se = adsd::wave_sum(se) / (n / 2);
+        so = adsd::wave_sum(so) / (n / 2);
+        for (int r = lane; r < n; r += 64) X[r + j * ld] -= (r & 1) ? so : se;
+      } else {
+        double sm = 0.0;
+        for (int r = lane; r < n; r += 64) sm += X[r + j * ld];
+        sm = adsd::wave_sum(sm) / n;
+        for (int r = lane; r < n; r += 64) X[r + j * ld] -= sm;
+      }
     }
   }
 }
@@ -1330,11 +1370,15 @@ __device__ __forceinline__ void block_sum_cols(double (&v)[PC], double (*red)[16
 // forward chain in place in W.  k_eig_op_bwd: the middle block and the
 // backward chain from W into Y, and on floating subdomains the per-half
 // column sums of Y; the projection onto 1^perp is applied by k_eig_gram.
+// Complex A (kernel dimension 2): Pi = I - l l^T - (J l)(J l)^T, with
+// alpha2 = (J l)^T X, beta2 = (J l)^T B Pi X = (J btl)^T X + alpha h -
+// alpha2 g and beta = btl^T X - alpha g - alpha2 h ((g, h) = gam), and the
+// column sums split into real and imaginary rows.
 template <class FT, int PC, int D>
 __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[PC][16];
-  __shared__ double alpha[PC], beta[PC];
+  __shared__ double alpha[PC], beta[PC], alpha2[PC], beta2[PC];
   const int i = adsd::sub_of(a.order, blockIdx.x), half = blockIdx.z;
   if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
@@ -1353,6 +1397,7 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
   const double* bl = a.bell + a.pad_off[i];
   const uint8_t* oi = a.om_int + base;
   const int64_t* lrow = a.lrow + base;
+  const bool cpair = a.kdim[i] == 2;
   double acc[PC], acc2[PC];
   if (floating) {  // alpha = l^T X, delta = btl^T X over all rows
     const double* bt = a.btl + a.pad_off[i];
@@ -1370,7 +1415,30 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
     }
     block_sum_cols<PC>(acc, red, alpha, pc);
     block_sum_cols<PC>(acc2, red, beta, pc);
-    if (t < pc) beta[t] -= alpha[t] * a.gam[i];
+    if (cpair) {  // the same with J l and J btl
+#pragma unroll
+      for (int j = 0; j < PC; ++j) acc[j] = acc2[j] = 0.0;
+      for (int r = t; r < n; r += T) {
+        const double lr = jrot(l, r), br = jrot(bt, r);
+#pragma unroll
+        for (int j = 0; j < PC; ++j)
+          if (j < pc) {
+            const double x = X[r + j * ld];
+            acc[j] += lr * x;
+            acc2[j] += br * x;
+          }
+      }
+      block_sum_cols<PC>(acc, red, alpha2, pc);
+      block_sum_cols<PC>(acc2, red, beta2, pc);
+      if (t < pc) {
+        const double g = a.gam[2 * i], h = a.gam[2 * i + 1];
+        const double a1 = alpha[t], a2 = alpha2[t];
+        beta[t] -= a1 * g + a2 * h;
+        beta2[t] += a1 * h - a2 * g;
+      }
+    } else if (t < pc) {
+      beta[t] -= alpha[t] * a.gam[2 * i];
+    }
     __syncthreads();
   }
   const int lo = half ? (M + 1) * s : 0, hi = half ? npad : (M + 1) * s;
@@ -1395,6 +1463,14 @@ __global__ void __launch_bounds__(1024) k_eig_op_fwd(const FT* fac, EigArgs a) {
       for (int j = 0; j < PC; ++j) {
         const int jj = j < pc ? j : 0;
         v[j] -= alpha[jj] * br + beta[jj] * lr;
+      }
+      if (cpair) {
+        const double jbr = jrot(bl, r), jlr = jrot(l, r);
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+          const int jj = j < pc ? j : 0;
+          v[j] -= alpha2[jj] * jbr + beta2[jj] * jlr;
+        }
       }
     }
 #pragma unroll
@@ -1439,19 +1515,25 @@ __global__ void __launch_bounds__(1024) k_eig_op_bwd(const FT* fac, EigArgs a) {
                                       half ? K - 1 - M : M, nullptr, nullptr, Wv, Y, ld, pc, lds,
                                       dummy);
   if (a.kdim[i]) {  // partial column sums of this half's rows (padding rows are zero)
+    // slots (subdomain, chunk, half, row parity): all rows in parity 0 for
+    // real A, real and imaginary rows apart for complex A
     __syncthreads();
     const int lo = half ? (M + 1) * s : 0, hi = min(n, half ? npad : (M + 1) * s);
-    double acc[PC];
+    double* cs = a.colsum + (((int64_t)i * gridDim.y + blockIdx.y) * 2 + half) * 2 * PC;
+    const int npar = a.kdim[i];
+    for (int par = 0; par < npar; ++par) {
+      double acc[PC];
 #pragma unroll
-    for (int j = 0; j < PC; ++j) acc[j] = 0.0;
-    for (int r = lo + t; r < hi; r += T) {
+      for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+      for (int r = lo + t; r < hi; r += T) {
+        if (npar == 2 && (r & 1) != par) continue;
 #pragma unroll
-      for (int j = 0; j < PC; ++j)
-        if (j < pc) acc[j] += Y[r + j * ld];
+        for (int j = 0; j < PC; ++j)
+          if (j < pc) acc[j] += Y[r + j * ld];
+      }
+      block_sum_cols<PC>(acc, red, sums, pc);
+      if (t < pc) cs[par * PC + t] = sums[t];
     }
-    block_sum_cols<PC>(acc, red, sums, pc);
-    if (t < pc)
-      a.colsum[(((int64_t)i * gridDim.y + blockIdx.y) * 2 + half) * PC + t] = sums[t];
   }
 }
 
@@ -1463,7 +1545,7 @@ template <class FT, int PC>
 __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[PC][16];
-  __shared__ double alpha[PC], beta[PC];
+  __shared__ double alpha[PC], beta[PC], alpha2[PC], beta2[PC];
   const int i = adsd::sub_of(a.order, blockIdx.x);
   if (a.done[i] || (a.ks && a.jcur[i] + a.p > a.kmi[i])) return;
   const int j0 = blockIdx.y * PC;
@@ -1482,7 +1564,10 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   const double* bl = a.bell + a.pad_off[i];
   const uint8_t* oi = a.om_int + base;
   const int64_t* lrow = a.lrow + base;
-  double acc[PC];
+  // complex A (kernel dimension 2): Pi = I - l l^T - (J l)(J l)^T, the
+  // second term through alpha2 = (J l)^T X, B J l = J B l and beta2
+  const bool cpair = a.kdim[i] == 2;
+  double acc[PC], acc2[PC];
   if (floating) {  // alpha = l^T X
 #pragma unroll
     for (int j = 0; j < PC; ++j) acc[j] = 0.0;
@@ -1493,11 +1578,22 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
         if (j < pc) acc[j] += lr * X[r + j * ld];
     }
     block_sum_cols<PC>(acc, red, alpha, pc);
+    if (cpair) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+      for (int r = t; r < n; r += T) {
+        const double lr = jrot(l, r);
+#pragma unroll
+        for (int j = 0; j < PC; ++j)
+          if (j < pc) acc[j] += lr * X[r + j * ld];
+      }
+      block_sum_cols<PC>(acc, red, alpha2, pc);
+    }
   }
   // F = B (Pi X) = B X - alpha B l, row-parallel over all PC columns;
   // beta = l^T F on the way
 #pragma unroll
-  for (int j = 0; j < PC; ++j) acc[j] = 0.0;
+  for (int j = 0; j < PC; ++j) acc[j] = acc2[j] = 0.0;
   for (int r = t; r < npad; r += T) {
     double v[PC];
 #pragma unroll
@@ -1514,10 +1610,21 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
       }
       if (floating) {
         const double br = bl[r], lr = l[r];
+        if (cpair) {
+          const double jbr = jrot(bl, r), jlr = jrot(l, r);
 #pragma unroll
-        for (int j = 0; j < PC; ++j) {
-          v[j] -= alpha[j < pc ? j : 0] * br;
-          acc[j] += lr * v[j];
+          for (int j = 0; j < PC; ++j) {
+            const int jj = j < pc ? j : 0;
+            v[j] -= alpha[jj] * br + alpha2[jj] * jbr;
+            acc[j] += lr * v[j];
+            acc2[j] += jlr * v[j];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < PC; ++j) {
+            v[j] -= alpha[j < pc ? j : 0] * br;
+            acc[j] += lr * v[j];
+          }
         }
       }
     }
@@ -1527,11 +1634,12 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   }
   if (floating) {  // F <- Pi F
     block_sum_cols<PC>(acc, red, beta, pc);
+    if (cpair) block_sum_cols<PC>(acc2, red, beta2, pc);
     for (int r = t; r < n; r += T) {
-      const double lr = l[r];
+      const double lr = l[r], jlr = cpair ? jrot(l, r) : 0.0;
 #pragma unroll
       for (int j = 0; j < PC; ++j)
-        if (j < pc) Y[r + j * ld] -= beta[j] * lr;
+        if (j < pc) Y[r + j * ld] -= cpair ? beta[j] * lr + beta2[j] * jlr : beta[j] * lr;
     }
   }
   __syncthreads();
@@ -1540,7 +1648,7 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
                                            a.lval, a.cpl_ok ? a.cpl_col + cb : nullptr,
                                            a.cpl_ok ? a.cpl_val + cb : nullptr, Y,
                                     ld, pc, lds);
-  if (floating) {  // projection onto 1^perp
+  if (floating && !cpair) {  // projection onto 1^perp
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PC; ++j) acc[j] = 0.0;
@@ -1554,6 +1662,28 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
 #pragma unroll
       for (int j = 0; j < PC; ++j)
         if (j < pc) Y[r + j * ld] -= alpha[j] / n;
+    }
+  } else if (floating) {  // onto K^perp: the means of the real and imaginary rows apart
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PC; ++j) acc[j] = acc2[j] = 0.0;
+    for (int r = t; r < n; r += T) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) {
+          if (r & 1)
+            acc2[j] += Y[r + j * ld];
+          else
+            acc[j] += Y[r + j * ld];
+        }
+    }
+    block_sum_cols<PC>(acc, red, alpha, pc);
+    block_sum_cols<PC>(acc2, red, alpha2, pc);
+    const int nh = n / 2;
+    for (int r = t; r < n; r += T) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < pc) Y[r + j * ld] -= ((r & 1) ? alpha2[j] : alpha[j]) / nh;
     }
   }
 }
@@ -1741,20 +1871,23 @@ __global__ void __launch_bounds__(EIG_T) k_eig_gram(EigArgs a, int rr) {
   stage_rows(Y, ld, r0, rows, p, pq, lrb, Ys);
   if (rr) stage_rows(a.X + a.pad_off[i] * p, ld, r0, rows, p, pq, lrb, Xs);
   if (a.defer && a.kdim[i]) {
-    // projection onto 1^perp left by the two-ended operator: subtract the
-    // column means (from the per-half sums) from this block's rows
-    __shared__ double mu[PMAX];
-    const int nch = (p + EIG_PC - 1) / EIG_PC;
-    if (threadIdx.x < p) {
-      const int j = threadIdx.x, ch = j / EIG_PC, jj = j % EIG_PC;
-      const double* cs = a.colsum + (int64_t)i * nch * 2 * EIG_PC;
-      mu[j] = (cs[(ch * 2 + 0) * EIG_PC + jj] + cs[(ch * 2 + 1) * EIG_PC + jj]) / a.ni[i];
+    // projection onto K^perp left by the two-ended operator: subtract the
+    // column means (from the per-half sums) from this block's rows (complex
+    // A: the means of the real and of the imaginary rows)
+    __shared__ double mu[2][PMAX];
+    const int nch = (p + EIG_PC - 1) / EIG_PC, kd = a.kdim[i];
+    if ((int)threadIdx.x < kd * p) {
+      const int par = threadIdx.x / p, j = threadIdx.x % p, ch = j / EIG_PC, jj = j % EIG_PC;
+      const double* cs = a.colsum + (int64_t)i * nch * 4 * EIG_PC;
+      mu[par][j] = (cs[((ch * 2 + 0) * 2 + par) * EIG_PC + jj] +
+                    cs[((ch * 2 + 1) * 2 + par) * EIG_PC + jj]) /
+                   (a.ni[i] / kd);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < RB * p; e += EIG_T) {
       const int r = e & (RB - 1), c = e >> lrb;
       if (r < rows) {
-        const double v = Ys[e] - mu[c];
+        const double v = Ys[e] - mu[kd == 2 ? ((r0 + r) & 1) : 0][c];
         Ys[e] = v;
         Y[r0 + r + c * ld] = v;
       }
@@ -2004,7 +2137,7 @@ __device__ __forceinline__ bool ks_active(const EigArgs& a, int i) {
 // deferred projection onto 1^perp; pass 1: the block Q1 of the first pass)
 __global__ void __launch_bounds__(EIG_T) k_ks_dots(EigArgs a, int pass) {
   extern __shared__ double rbuf[];
-  __shared__ double mu[EIG_PC];
+  __shared__ double mu[2][EIG_PC];
   const int b = blockIdx.x, i = a.blk_sub[b];
   if (!ks_active(a, i)) return;
   const int p = a.p, J = a.jcur[i] + p, lrb = a.lrb, RB = 1 << lrb;
@@ -2018,16 +2151,20 @@ __global__ void __launch_bounds__(EIG_T) k_ks_dots(EigArgs a, int pass) {
   stage_rows(Wg, ld, r0, rows, p, EIG_PC, lrb, Ws);
   stage_rows(Vg, ld, r0, rows, J, (J + 3) & ~3, lrb, Vs);
   if (pass == 0 && a.defer && a.kdim[i]) {
-    // projection onto 1^perp left by the two-ended operator (one column chunk)
-    if ((int)threadIdx.x < p)
-      mu[threadIdx.x] = (a.colsum[(int64_t)i * 2 * EIG_PC + threadIdx.x] +
-                         a.colsum[(int64_t)i * 2 * EIG_PC + EIG_PC + threadIdx.x]) /
-                        a.ni[i];
+    // projection onto K^perp left by the two-ended operator (one column
+    // chunk; slots (half, row parity) as k_eig_op_bwd writes them)
+    const int kd = a.kdim[i];
+    if ((int)threadIdx.x < kd * p) {
+      const int par = threadIdx.x / p, j = threadIdx.x % p;
+      const double* cs = a.colsum + (int64_t)i * 4 * EIG_PC;
+      mu[par][j] = (cs[(0 * 2 + par) * EIG_PC + j] + cs[(1 * 2 + par) * EIG_PC + j]) /
+                   (a.ni[i] / kd);
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < RB * p; e += EIG_T) {
       const int r = e & (RB - 1), c = e >> lrb;
       if (r < rows) {
-        const double v = Ws[e] - mu[c];
+        const double v = Ws[e] - mu[kd == 2 ? ((r0 + r) & 1) : 0][c];
         Ws[e] = v;
         Wg[r0 + r + c * ld] = v;
       }
@@ -2379,7 +2516,7 @@ k_eig_rayleigh(EigArgs a, const double* __restrict__ lsum, double* __restrict__ 
   __shared__ double Ub[RR_B][PMAX + 1], Vb[RR_B][PMAX + 1], YA[RR_B][PMAX + 1], YB[RR_B][PMAX + 1];
   __shared__ double G[PMAX][2 * PMAX + 1];
   __shared__ double M[PMAX * PMAX];
-  __shared__ double pu[PMAX], red[PMAX][EIG_T / 64];
+  __shared__ double pu[2][PMAX], red[PMAX][EIG_T / 64];
   __shared__ double lam_re[PMAX], lam_im[PMAX];
   __shared__ int flag[2];
   const int i = blockIdx.x, t = threadIdx.x;
@@ -2401,14 +2538,14 @@ k_eig_rayleigh(EigArgs a, const double* __restrict__ lsum, double* __restrict__ 
     U[r + c * ld] = v;
   }
   __syncthreads();
-  // pu = ell^T U (floating subdomains)
-  if (t < PMAX) pu[t] = 0.0;
-  if (kd) {
+  // pu = ell^T U (floating subdomains), and (J ell)^T U for complex A
+  if (t < PMAX) pu[0][t] = pu[1][t] = 0.0;
+  for (int q = 0; q < kd; ++q) {
     double acc[PMAX];
 #pragma unroll
     for (int c = 0; c < PMAX; ++c) acc[c] = 0.0;
     for (int r = t; r < ni; r += EIG_T) {
-      const double l = ell[r];
+      const double l = q ? jrot(ell, r) : ell[r];
 #pragma unroll
       for (int c = 0; c < PMAX; ++c)
         if (c < m) acc[c] += l * U[r + c * ld];
@@ -2423,8 +2560,9 @@ k_eig_rayleigh(EigArgs a, const double* __restrict__ lsum, double* __restrict__ 
     if (t < m) {
       double v = 0.0;
       for (int w = 0; w < EIG_T / 64; ++w) v += red[t][w];
-      pu[t] = v;
+      pu[q][t] = v;
     }
+    __syncthreads();
   }
   __syncthreads();
   const int aa = t / PMAX, bb = t % PMAX;
@@ -2434,15 +2572,20 @@ k_eig_rayleigh(EigArgs a, const double* __restrict__ lsum, double* __restrict__ 
       const int rr = t / PMAX, c = t % PMAX, r = r0 + rr;  // one (row, column) per thread
       double u = 0.0, v = 0.0, ya = 0.0, yb = 0.0;
       if (r < ni && c < m) {
-        const double pc = kd ? pu[c] : 0.0;
+        const double pc = kd ? pu[0][c] : 0.0, pc2 = kd == 2 ? pu[1][c] : 0.0;
         u = U[r + c * ld];
         v = u - (kd ? ell[r] * pc : 0.0);
+        if (kd == 2) v -= jrot(ell, r) * pc2;
         const bool ri = isint[r];
         for (int64_t q = a.lrow[f0 + r]; q < a.lrow[f0 + r + 1]; ++q) {
           const int cc = a.lcol[q];
           const double av = a.lval[q], uc = U[cc + c * ld];
           ya += av * uc;
-          if (ri && isint[cc]) yb += av * (uc - (kd ? ell[cc] * pc : 0.0));
+          if (ri && isint[cc]) {
+            double w = uc - (kd ? ell[cc] * pc : 0.0);
+            if (kd == 2) w -= jrot(ell, cc) * pc2;
+            yb += av * w;
+          }
         }
         if (!ri) ya -= lsum[f0 + r] * u;
       }
@@ -2510,7 +2653,8 @@ k_eig_rayleigh(EigArgs a, const double* __restrict__ lsum, double* __restrict__ 
   }
 }
 
-// W_i = orth([1_I (floating) | (X V)_I]) stored row-major nI x nev_i
+// W_i = orth([1_I (floating; complex A: 1_I and J 1_I) | (X V)_I]) stored
+// row-major nI x nev_i
 // Z = [1 | X V] on the interior rows of every subdomain, column-major nint x
 // cols in the Y buffer (leading dimension npad): one thread per interior row
 // (its local row from the window map), the row of X in registers, the Ritz
@@ -2538,7 +2682,11 @@ k_eig_z(EigArgs a, const int32_t* __restrict__ int_list, const int64_t* __restri
 #pragma unroll
   for (int j = 0; j < KS_W; ++j) xr[j] = j < p ? X[r + j * ld] : 0.0;
   double* Z = a.Y + a.pad_off[i] * p;
-  if (kd) Z[k] = 1.0;
+  if (kd == 1) Z[k] = 1.0;
+  if (kd == 2) {  // complex A: the real form of 1 and of i 1 (real, imaginary rows)
+    Z[k] = (g & 1) ? 0.0 : 1.0;
+    Z[k + ld] = (g & 1) ? 1.0 : 0.0;
+  }
   for (int c = 0; c < m; ++c) {
     const double* vc = Vsh + c * p;
     double v = 0.0;
@@ -2926,10 +3074,10 @@ void eigensolve(Ctx& c) {
   a.ell = c.mem.alloc<double>(c.npad_total);
   a.bell = c.mem.alloc<double>(c.npad_total);
   a.btl = c.mem.alloc<double>(c.npad_total);
-  a.gam = c.mem.alloc<double>(nsub);
-  a.colsum = c.mem.alloc<double>((size_t)nsub * nch * 2 * EIG_PC);
+  a.gam = c.mem.alloc<double>(2 * (size_t)nsub);
+  a.colsum = c.mem.alloc<double>((size_t)nsub * nch * 4 * EIG_PC);
   a.defer = c.solve_fast ? 1 : 0;
-  ADS_HIP(hipMemsetAsync(a.colsum, 0, (size_t)nsub * nch * 2 * EIG_PC * 8, st));
+  ADS_HIP(hipMemsetAsync(a.colsum, 0, (size_t)nsub * nch * 4 * EIG_PC * 8, st));
   // what the host reads back, in one block (one copy per read):
   // doubles rres | lam, then int32 err | done | sweeps | msel | jcur | next_rr
   const size_t rep_d = (size_t)nsub * (1 + 2 * PMAX), rep_i = 1 + 5 * (size_t)nsub;
@@ -3115,7 +3263,7 @@ void eigensolve(Ctx& c) {
   c.h_lam_re.clear();
   c.h_lam_im.clear();
   for (int i = 0; i < nsub; ++i) {
-    if (c.h_kdim[i]) {
+    for (int q = 0; q < c.h_kdim[i]; ++q) {  // the kernel columns
       c.h_lam_re.push_back(0.0);
       c.h_lam_im.push_back(0.0);
     }

@@ -143,9 +143,11 @@ __global__ void k_extract_fill(const int32_t* rowptr, const int32_t* col, const 
   }
 }
 
-__global__ void k_kernel_dim(const int32_t* nfail, int nsub, int32_t* kdim) {
+// K_i = span{1} when no row failed the zero-sum test; for complex A its real
+// form is span{constant real parts, constant imaginary parts}, dimension 2
+__global__ void k_kernel_dim(const int32_t* nfail, int nsub, int32_t* kdim, int pair) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nsub) kdim[i] = (nfail[i] == 0) ? 1 : 0;
+  if (i < nsub) kdim[i] = (nfail[i] == 0) ? (pair ? 2 : 1) : 0;
 }
 
 // per padded local row of block k: the (column in block k + dk, value)
@@ -262,7 +264,7 @@ void extract_local(Ctx& c) {
   ADS_LAUNCH(k_extract_fill, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
              c.om_sub, c.wlo, c.whi, c.woff, c.wpos, T, lrow, c.lcol, c.lval);
   c.kdim = kb;
-  ADS_LAUNCH(k_kernel_dim, dim3((nsub + 255) / 256), dim3(256), 0, s, nfail, nsub, c.kdim);
+  ADS_LAUNCH(k_kernel_dim, dim3((nsub + 255) / 256), dim3(256), 0, s, nfail, nsub, c.kdim, c.cplx);
   std::vector<int32_t> hkb;
   download(hkb, kb, 2 * (size_t)nsub, s);
   c.h_kdim.assign(hkb.begin(), hkb.begin() + nsub);

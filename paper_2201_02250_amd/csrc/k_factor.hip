@@ -17,6 +17,10 @@
 // first.  For f in range(splitting) the solution u of the regularised system
 // satisfies u_n = 0 and hence solves the singular system exactly (the left
 // null vector has a nonzero last entry), which is all the eigensolver needs.
+// For complex A (kernel dimension 2 in the real form) both real diagonal
+// entries of the last unknown are doubled: the real form of adding the real
+// part of its complex diagonal entry there, a complex rank-one change of the
+// same kind (any nonzero one gives the same solutions in range(splitting)).
 //
 // One workgroup per subdomain; the block D_k and the previous P tile live in
 // LDS when 2 s^2 doubles fit, otherwise in a per-workgroup global scratch.
@@ -84,7 +88,7 @@ k_block_factor(const int64_t* lrow, const int32_t* lcol, const double* lval, con
         double a = lval[q];
         if (cc == rr && splitting) {
           if (!om_int[f]) a -= lsum[f];
-          if (regularise && r == n - 1) a *= 2.0;
+          if (regularise && r >= n - kdim[i]) a *= 2.0;
         }
         D[(int64_t)rr * s + cc] = a;
       }
@@ -249,7 +253,7 @@ struct BlockFac {
         double x = a.lval[q];
         if (cc == rr && splitting) {
           if (!a.om_int[f]) x -= a.lsum[f];
-          if (regularise && r == n - 1) x *= 2.0;
+          if (regularise && r >= n - a.kdim[i]) x *= 2.0;
         }
         D[rr * s + cc] = x;
       }
@@ -580,7 +584,7 @@ k_bf_build(BfArgs a, int k, int splitting, double* D, const double* Pp) {
         double x = a.lval[q];
         if (j == rr && splitting) {
           if (!a.om_int[f]) x -= a.lsum[f];
-          if (regularise && r == n - 1) x *= 2.0;
+          if (regularise && r >= n - a.kdim[i]) x *= 2.0;
         }
         v = x;
       }

@@ -11,6 +11,8 @@ oracle's with their conjugates (relative 1e-8); the apply of eq. 4 (and the
 other variants) on complex vectors within 1e-9 of the oracle's; complex
 GMRES iterations within +-1 and solutions within 1e-8 (or the residual
 bound), fixed-iteration iterates within 1e-10."""
+import re
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -86,6 +88,28 @@ CASES = [
     ("zcd64-2x2-d2-general", lambda: W.convdiff2d_complex(64, 0.01, eta=0.5, omega=1.0,
                                                             phase_seed=2),
      lambda: W.block_partition_2d(64, 2), 4, 2, 3),
+    # floating subdomains (the splitting has the complex constant as null
+    # vector, span{1, i 1} in the real form): Neumann at x = 0, 1 and real
+    # y-couplings, so the strips away from y = 0, 1 float (their lumped
+    # couplings are real and negative); nonsymmetric, so the left null vector
+    # comes from the transposed solve.  Strips m wide have real-form block
+    # size 2 m + 1: 25 (two-ended register-resident factors), 97 (batched
+    # block-step factors) and 265 (one-ended factors, general solves)
+    ("zcd12-strips3-d1-float", lambda: W.convdiff2d_complex(12, 0.02, eta=0.5, eta_y=0.0,
+                                                              neumann_x=True),
+     lambda: W.strip_partition(12, 3), 4, 1, 3),
+    ("zcd48-strips6-d1-float-s97", lambda: W.convdiff2d_complex(48, 0.02, eta=0.5, eta_y=0.0,
+                                                                  neumann_x=True),
+     lambda: W.strip_partition(48, 6), 8, 1, 3),
+    # (nu 0.1: at nu 0.02 the adjoint null vector of these wide strips is
+    # 4e-11 at the last unknown, where the splitting is regularised, and the
+    # regularised solves of both sides keep only about 6 digits)
+    ("zcd132-strips12-d1-float-s265", lambda: W.convdiff2d_complex(132, 0.1, eta=0.5, eta_y=0.0,
+                                                                     neumann_x=True),
+     lambda: W.strip_partition(132, 12), 11, 1, 3),
+    # Hermitian (zero flux): the left null vector is the constant itself
+    ("mag24-4x4-d2-float-hermitian", lambda: W.magnetic_laplace2d(24, 0.0),
+     lambda: W.block_partition_2d(24, 4), 16, 2, 4),
 ]
 
 
@@ -114,8 +138,17 @@ def test_complex_setup_apply_solve_match_oracle(case):
         s_g = s_gpu[off[i]:off[i + 1]][2 * sub.n_interior:]
         np.testing.assert_allclose(s_g[0::2], s_or, rtol=1e-15, atol=0)  # hypot rounding
         np.testing.assert_array_equal(s_g[0::2], s_g[1::2])
-    # coarse space: twice the complex count, the real form of the span
-    assert list(info["kernel_dim"]) == [0] * N
+    # coarse space: twice the complex count, the real form of the span (a
+    # floating subdomain's kernel: the real form of the constant, 2 columns)
+    kd = [2 * int(e["kernel"]) for e in P.eig]
+    assert list(info["kernel_dim"]) == kd
+    if "float" in name:
+        assert sum(kd) > 0
+        blocks = sorted(set(int(b) for b in info["block"]))
+        print(f"{name}: {sum(kd) // 2} floating subdomains, blocks {blocks}", flush=True)
+        want = re.search(r"-s(\d+)$", name)
+        if want:  # the factor / solve path the case is for
+            assert max(blocks) == int(want.group(1)), blocks
     np.testing.assert_array_equal(info["nev_i"], 2 * P.nev_i)
     assert info["n0"] == 2 * P.n0
     Wg, woff, lam, _ = ads.ads_export_coarse(ctx.ctx)
@@ -128,7 +161,8 @@ def test_complex_setup_apply_solve_match_oracle(case):
         worst = max(worst, ang)
         assert ang < 1e-7, (i, ang)
         lo = P.eig[i]["lam_sel"]
-        same_eigs(lam[k0:k0 + mi], np.concatenate([lo, lo.conj()]), 1e-8)
+        assert not np.any(lam[k0:k0 + kd[i]])  # the kernel columns lead, eigenvalue 0
+        same_eigs(lam[k0 + kd[i]:k0 + mi], np.concatenate([lo, lo.conj()]), 1e-8)
         k0 += mi
     print(f"{name}: n0 {info['n0']} real ({P.n0} complex), largest span angle {worst:.1e}",
           flush=True)
@@ -250,14 +284,3 @@ def test_complex_full_size_convection_diffusion():
     print(f"complex 256^2: n0 {P.n0} complex, span angle {worst:.1e}, its {inf['its'][0]} "
           f"(oracle {io['its']}), setup {info['t_phase_ms']}", flush=True)
     ctx.close()
-
-
-def test_complex_floating_subdomain_is_refused():
-    """A complex splitting with the constant null vector (two-dimensional in
-    the real form) is refused, naming the subdomain."""
-    A = W.convdiff2d_complex(24, 0.02, eta=0.5, eta_y=0.0, neumann_x=True)
-    part = W.strip_partition(24, 6)
-    with pytest.raises(ads.AdsError) as e:
-        ads.Context(A, part, 4, 1, 3)
-    assert e.value.status == ads.ADS_ERR_UNSUPPORTED and "subdomain 1" in str(e.value)
-    print(e.value, flush=True)
