@@ -42,18 +42,37 @@ struct KInst {
   int nch;               // chunks over the longest segment
 };
 
-// y = b - A x (mode 1) or y = A x (mode 0), all columns
-__global__ void k_spmv(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                       const double* __restrict__ val, const double* __restrict__ x,
-                       const double* __restrict__ b, double* __restrict__ y, int64_t n, int nrhs,
-                       int mode) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * nrhs) return;
-  const int64_t r = e % n, j = e / n;
-  const double* xj = x + j * n;
-  double acc = 0.0;
-  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) acc += val[k] * xj[col[k]];
-  y[e] = mode ? b[e] - acc : acc;
+// y = b - A x (mode 1) or y = A x (mode 0) for the columns [j0, j0 + CH)
+// (j0 = CH blockIdx.y) of every row: one thread per row reads the row's
+// entries once for all CH columns, and the lanes of a wavefront take
+// consecutive rows, so that every column's loads of x and stores of y are
+// coalesced; each row is summed in CSR order
+template <int CH>
+__global__ void __launch_bounds__(256)
+k_spmv(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+       const double* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
+       double* __restrict__ y, int64_t n, int nrhs, int mode) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int j0 = blockIdx.y * CH;
+  const int nc = min(CH, nrhs - j0);
+  double acc[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) acc[j] = 0.0;
+  const int k1 = rowptr[r + 1];
+  for (int k = rowptr[r]; k < k1; ++k) {
+    const double v = val[k];
+    const int64_t c = col[k];
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if (j < nc) acc[j] += v * x[(j0 + j) * n + c];
+  }
+#pragma unroll
+  for (int j = 0; j < CH; ++j)
+    if (j < nc) {
+      const int64_t e = (j0 + j) * n + r;
+      y[e] = mode ? b[e] - acc[j] : acc[j];
+    }
 }
 
 typedef const double __attribute__((address_space(1)))* gcdptr;
@@ -525,7 +544,20 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   ADS_HIP(hipMemcpyAsync(all_d, ones.data(), Q * 4, hipMemcpyHostToDevice, st));
   ADS_HIP(hipMemsetAsync(S.jq, 0, Q * 4, st));
   const dim3 gseg((unsigned)((maxlen + 255) / 256), Q);
-  const unsigned gv = (unsigned)((vsz + 255) / 256);
+  // y = b - A x (mode 1) or A x (mode 0) over all nrhs columns, in chunks of
+  // 1, 4 or 16 columns per thread
+  auto spmv = [&](const double* xv, const double* bv, double* yv, int mode) {
+    const unsigned gr = (unsigned)((n + 255) / 256);
+    if (nrhs == 1)
+      ADS_LAUNCH(k_spmv<1>, dim3(gr, 1), dim3(256), 0, st, c.rowptr, c.col, c.val, xv, bv, yv, n,
+                 nrhs, mode);
+    else if (nrhs <= 4)
+      ADS_LAUNCH(k_spmv<4>, dim3(gr, 1), dim3(256), 0, st, c.rowptr, c.col, c.val, xv, bv, yv, n,
+                 nrhs, mode);
+    else
+      ADS_LAUNCH(k_spmv<16>, dim3(gr, (unsigned)((nrhs + 15) / 16)), dim3(256), 0, st, c.rowptr,
+                 c.col, c.val, xv, bv, yv, n, nrhs, mode);
+  };
   auto norms = [&](const double* v, const int32_t* mask, double* out) {
     ADS_LAUNCH(k_norm_partial, dim3(I.nch, Q), dim3(KR_T), 0, st, v, I, mask, part);
     ADS_LAUNCH(k_norm_final, dim3(Q), dim3(64), 0, st, part, I, mask, out);
@@ -549,7 +581,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
   // residual r = b - A x into w, start cycles for all active instances
   auto start_cycles = [&](const std::vector<int32_t>& mask_h) {
     ADS_HIP(hipMemcpyAsync(endm_d, mask_h.data(), Q * 4, hipMemcpyHostToDevice, st));
-    ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, x, b, w, n, nrhs, 1);
+    spmv(x, b, w, 1);
     norms(w, endm_d, beta_d);
     std::vector<double> hb;
     download(hb, beta_d, Q, st);
@@ -611,8 +643,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
       apply_prec(c, u, z, nrhs, st);
       if (flex)
         ADS_LAUNCH(k_seg_pick, gseg, dim3(256), 0, st, (const double* const*)dZ, z, I, S.jq, act_d, 1);
-      ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, z, (const double*)nullptr,
-                 w, n, nrhs, 0);
+      spmv(z, nullptr, w, 0);
       // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, h = h1 + h2
       for (int pass = 0; pass < 2; ++pass) {
         double* hp = pass ? S.h2 : S.h;
@@ -764,7 +795,7 @@ int gmres_solve(Ctx& c, const double* b, double* x, int nrhs, const ads_ksp_opti
     // true residual and restart decision
     std::vector<int32_t> restart(Q, 0);
     {
-      ADS_LAUNCH(k_spmv, dim3(gv), dim3(256), 0, st, c.rowptr, c.col, c.val, x, b, w, n, nrhs, 1);
+      spmv(x, b, w, 1);
       norms(w, endm_d, beta_d);
       std::vector<double> tr;
       download(tr, beta_d, Q, st);
