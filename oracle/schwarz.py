@@ -22,8 +22,12 @@ Readings taken where the paper is silent (shared with the dense tier):
   R3  ascending global index inside Omega_Ii and inside Omega_Gamma_i.
   R4  Boolean partition of unity: D_i = diag(1 on Omega_Ii, 0 on Omega_Gamma_i).
   R5  s_i sums rows (not columns); sum taken in ascending column order.
-  R6  kernel of the splitting: K_i = span{1} when every row of the splitting
-      satisfies |row sum| <= 1e-13 * (sum of |entries|), else {0}.
+  R6  kernel of the splitting: K_i is spanned by the indicator vectors of the
+      connected components of the splitting's graph (stored entries of the
+      splitting and its transpose) whose rows all satisfy |row sum| <= 1e-13 *
+      (sum of |entries|) -- for a connected subdomain span{1} or {0}.  The
+      splitting is block diagonal over the components, so its kernel is the
+      sum of theirs.
   R7  eq. 5 is solved on the domain K_i^perp with codomain range(splitting);
       Pi_i = orthogonal projector onto range(splitting).
   R8  selection: finite eigenvalues by |lambda| descending; a cut that falls
@@ -53,6 +57,7 @@ import time
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.csgraph as csgraph
 import scipy.sparse.linalg as spla
 
 KERNEL_ROWSUM_TOL = 1e-13
@@ -209,15 +214,28 @@ def block_splitting(A: sp.csr_matrix, sub: Subdomain):
     return A_ii, s, At
 
 
-def kernel_dimension(At: sp.csr_matrix) -> int:
-    """Reading R6: 1 when every row of the splitting sums to zero relative to its
-    absolute row sum (floating subdomain of a zero-row-sum M-matrix), else 0."""
-    rows = np.repeat(np.arange(At.shape[0]), np.diff(At.indptr))
-    rs = np.zeros(At.shape[0], dtype=At.dtype)
-    ars = np.zeros(At.shape[0])
+def floating_components(At: sp.csr_matrix) -> list:
+    """Reading R6: the connected components of the splitting's graph (stored
+    entries of At and At^T) whose rows all sum to zero relative to their
+    absolute row sums (floating pieces of a zero-row-sum M-matrix), as
+    ascending local index arrays, ordered by their smallest index."""
+    n = At.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(At.indptr))
+    rs = np.zeros(n, dtype=At.dtype)
+    ars = np.zeros(n)
     np.add.at(rs, rows, At.data)
     np.add.at(ars, rows, np.abs(At.data))
-    return int(np.all(np.abs(rs) <= KERNEL_ROWSUM_TOL * ars))
+    ok = np.abs(rs) <= KERNEL_ROWSUM_TOL * ars
+    G = sp.csr_matrix((np.ones(At.nnz), At.indices, At.indptr), shape=(n, n))
+    ncomp, lab = csgraph.connected_components(G + G.T, directed=False)
+    comps = [np.flatnonzero(lab == c) for c in range(ncomp)]
+    return sorted((idx for idx in comps if ok[idx].all()), key=lambda idx: idx[0])
+
+
+def kernel_dimension(At: sp.csr_matrix) -> int:
+    """Reading R6: dim K_i, the number of floating components of the splitting
+    (0 or 1 for a connected subdomain)."""
+    return len(floating_components(At))
 
 
 # ---------------------------------------------------------------------------
@@ -271,35 +289,55 @@ def local_eigenproblem(A_ii: sp.csr_matrix, At: sp.csr_matrix, n_interior: int, 
 
     T = Atilde_reg^{-1} Pi B Pi followed by the projection onto K^perp, where
     B = D A_ii D = diag(A_I, 0) under the Boolean D and Atilde_reg is the
-    splitting with its last diagonal entry doubled when K = span{1}.  The
-    nonzero eigenpairs of T are exactly the eigenpairs of the pencil restricted
-    to K^perp.  Returns dict(lam_all, lam_sel, Z, kernel) with Z = [Y, U_sel]
-    (nev_i real columns, the kernel part first)."""
+    splitting with the last diagonal entry of each floating component doubled
+    (K spanned by their indicators, reading R6; one component with the whole
+    subdomain: K = span{1}).  The nonzero eigenpairs of T are exactly the
+    eigenpairs of the pencil restricted to K^perp.  Returns dict(lam_all,
+    lam_sel, Z, kernel) with Z = [Y, U_sel] (nev_i real columns, the kernel
+    part first)."""
     ni = A_ii.shape[0]
     cplx = np.iscomplexobj(A_ii.data)
+    comps = floating_components(At)
     if kdim is None:
-        kdim = kernel_dimension(At)
+        kdim = len(comps)
+    assert kdim == len(comps)
     d = np.zeros(ni)
     d[:n_interior] = 1.0
     B = sp.diags(d) @ A_ii @ sp.diags(d)
-    if kdim == 1:
-        k = np.ones(ni) / np.sqrt(ni)
+    if kdim >= 1:
+        # the splitting is block diagonal over its components, so each doubled
+        # entry regularises its own component, and the solve with the unit
+        # vector of that entry gives that component's left null vector (zero
+        # elsewhere)
         Areg = At.tolil(copy=True)
-        Areg[ni - 1, ni - 1] = 2.0 * At[ni - 1, ni - 1]
+        for idx in comps:
+            Areg[idx[-1], idx[-1]] = 2.0 * At[idx[-1], idx[-1]]
         lu = spla.splu(Areg.tocsc())
-        e_last = np.eye(1, ni, ni - 1).ravel().astype(A_ii.dtype)
-        ell = lu.solve(e_last, trans="H" if cplx else "T")  # null(Atilde^H)
-        ell /= np.linalg.norm(ell)
+        ells, ks = [], []
+        for idx in comps:
+            e_last = np.eye(1, ni, idx[-1]).ravel().astype(A_ii.dtype)
+            ell = lu.solve(e_last, trans="H" if cplx else "T")  # null(Atilde^H)
+            ell /= np.linalg.norm(ell)
+            ells.append(ell)
+            k = np.zeros(ni)
+            k[idx] = 1.0 / np.sqrt(len(idx))
+            ks.append(k)
 
         def Pi(x):
-            return x - ell * (ell.conj() @ x)
+            for ell in ells:
+                x = x - ell * (ell.conj() @ x)
+            return x
 
         def T(x):
             y = lu.solve(Pi(B @ Pi(x)))
-            return y - k * (k @ y)
-        # kernel part (L cap K)^{perp_K}: L = ker(B) contains no multiple of 1 as
-        # 1 has a nonzero interior part and A_I is nonsingular, so it is K itself.
-        Y = k[:, None]
+            for k in ks:
+                y = y - k * (k @ y)
+            return y
+        # kernel part (L cap K)^{perp_K}: every component holds interior rows
+        # (the overlap layers are grown from the interior through entries
+        # inside Omega_i), B maps its indicator to a nonzero vector on it (A_I
+        # is nonsingular), so L cap K = {0} and the part is K itself.
+        Y = np.column_stack(ks)
     else:
         lu = spla.splu(At.tocsc())
 
@@ -312,7 +350,7 @@ def local_eigenproblem(A_ii: sp.csr_matrix, At: sp.csr_matrix, n_interior: int, 
         return dict(lam_all=lam, lam_sel=lam, Z=Y[:, :max(nev, 0)], kernel=kdim)
     op = spla.LinearOperator((ni, ni), matvec=T, dtype=A_ii.dtype)
     v0 = (np.ones(ni) + np.linspace(0.0, 1.0, ni)).astype(A_ii.dtype)
-    if kdim == 1:
+    for k in (ks if kdim >= 1 else []):
         v0 -= k * (k @ v0)
     extra = 6
     while True:

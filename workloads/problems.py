@@ -69,12 +69,15 @@ def laplace2d(m: int) -> CSR:
     return convdiff2d(m, nu=1.0, velocity=None)
 
 
-def convdiff2d(m: int, nu: float, velocity="cos-sin") -> CSR:
+def convdiff2d(m: int, nu: float, velocity="cos-sin", neumann_x: bool = False) -> CSR:
     """-nu*Lap(u) + V.grad(u), first-order upwind, 5 points, rows scaled by h^2.
 
     velocity: None (pure diffusion) or "cos-sin": V(x, y) = (cos 2 pi y, sin 2 pi x)
     evaluated at the nodes.  Off-diagonals are -nu - h*max(+-V, 0), so every
     interior row sums to zero and the matrix is a nonsymmetric M-matrix.
+    neumann_x: the rows at x = 0 and x = 1 drop the missing coupling from the
+    diagonal (they sum to zero too), so a subdomain away from y = 0 and y = 1
+    floats.
     """
     n = m * m
     h = 1.0 / (m + 1)
@@ -95,6 +98,8 @@ def convdiff2d(m: int, nu: float, velocity="cos-sin") -> CSR:
     east = -nu - h * np.maximum(-vx, 0.0)
     south = -nu - h * np.maximum(vy, 0.0)
     north = -nu - h * np.maximum(-vy, 0.0)
+    if neumann_x:
+        diag = diag + np.where(i == 0, west, 0.0) + np.where(i == m - 1, east, 0.0)
     ent = [(idx, idx, diag)]
     mk = i > 0
     ent.append((idx[mk], idx[mk] - 1, west[mk]))
