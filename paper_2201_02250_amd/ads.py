@@ -110,6 +110,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch ships its own HIP and HSA runtimes under the same sonames as
+        # the system's: loading torch first makes the library bind to the
+        # runtime that torch's tensors live in (one runtime per process);
+        # loaded the other way round, torch finds no GPU
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         L.ads_setup.argtypes = [C.POINTER(ads_csr), P, I32, C.POINTER(ads_options), P, C.POINTER(P)]

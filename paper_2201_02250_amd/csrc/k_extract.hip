@@ -35,7 +35,7 @@ __global__ void k_extract_count(const int32_t* rowptr, const int32_t* col, const
                                 const uint8_t* om_int, const int64_t* om_off, const int64_t* wlo,
                                 const int64_t* whi, const int64_t* woff, const int32_t* wpos,
                                 int64_t total, int32_t* cnt, double* lsum, int32_t* bw,
-                                int32_t* nfail, int pair) {
+                                int32_t* nfail, uint8_t* rbad, int pair) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int maxd = 0, bad = 0, i = -1;
   if (f < total) {
@@ -102,6 +102,7 @@ __global__ void k_extract_count(const int32_t* rowptr, const int32_t* col, const
     }
     cnt[f] = count;
     lsum[f] = overlap_row ? s : 0.0;
+    rbad[f] = (uint8_t)bad;
   }
   // one atomic per run of equal subdomains in the wavefront
   const int lane = threadIdx.x & 63;
@@ -143,11 +144,86 @@ __global__ void k_extract_fill(const int32_t* rowptr, const int32_t* col, const 
   }
 }
 
-// K_i = span{1} when no row failed the zero-sum test; for complex A its real
-// form is span{constant real parts, constant imaginary parts}, dimension 2
-__global__ void k_kernel_dim(const int32_t* nfail, int nsub, int32_t* kdim, int pair) {
+// Connected components of each splitting's graph (stored local entries and
+// their transposes; complex A in its real form: the two rows of an unknown are
+// one vertex), one workgroup per subdomain: every row starts with its own
+// index as label, and sweeps of min-label propagation along the edges (both
+// directions) plus pointer jumping run until a sweep changes nothing, leaving
+// each row with the smallest row index of its component.  A component floats
+// when none of its rows failed the zero-sum test.  Labels and flags live in
+// global memory and are read with device-scope atomic loads (the updates are
+// atomics performed in L2).  Out: ncomp[i], nfloat[i].
+__device__ __forceinline__ int ld_l2(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(1024) k_components(const int64_t* om_off, const int64_t* lrow,
+                                                     const int32_t* lcol, const uint8_t* rbad,
+                                                     int32_t* lab, int32_t* cbad, int pair,
+                                                     int32_t* ncomp, int32_t* nfloat) {
+  __shared__ int cnt[2];
+  const int i = blockIdx.x, t = threadIdx.x, T = blockDim.x;
+  const int64_t base = om_off[i];
+  const int n = (int)(om_off[i + 1] - base);
+  int32_t* L = lab + base;
+  int32_t* cb = cbad + base;
+  for (int r = t; r < n; r += T) {
+    atomicExch(&L[r], pair ? (r & ~1) : r);
+    atomicExch(&cb[r], 0);
+  }
+  __syncthreads();
+  for (;;) {
+    int changed = 0;
+    for (int r = t; r < n; r += T) {
+      int m = ld_l2(&L[r]);
+      const int m0 = m;
+      for (int64_t q = lrow[base + r]; q < lrow[base + r + 1]; ++q) m = min(m, ld_l2(&L[lcol[q]]));
+      if (pair) m = min(m, ld_l2(&L[r ^ 1]));
+      if (m < m0) {
+        atomicMin(&L[r], m);
+        changed = 1;
+      }
+      for (int64_t q = lrow[base + r]; q < lrow[base + r + 1]; ++q)
+        if (ld_l2(&L[lcol[q]]) > m) {
+          atomicMin(&L[lcol[q]], m);
+          changed = 1;
+        }
+    }
+    __syncthreads();
+    for (int r = t; r < n; r += T) {  // pointer jumping (labels only decrease)
+      const int m0 = ld_l2(&L[r]);
+      int m = m0;
+      for (int x = ld_l2(&L[m]); x < m; x = ld_l2(&L[m])) m = x;
+      if (m < m0) atomicMin(&L[r], m);
+    }
+    if (!__syncthreads_or(changed)) break;
+  }
+  for (int r = t; r < n; r += T)
+    if (rbad[base + r]) atomicExch(&cb[ld_l2(&L[r])], 1);
+  if (t < 2) cnt[t] = 0;
+  __syncthreads();
+  int nc = 0, nf = 0;
+  for (int r = t; r < n; r += T)
+    if (ld_l2(&L[r]) == r) {
+      ++nc;
+      nf += !ld_l2(&cb[r]);
+    }
+  if (nc) atomicAdd(&cnt[0], nc);
+  if (nf) atomicAdd(&cnt[1], nf);
+  __syncthreads();
+  if (t == 0) {
+    ncomp[i] = cnt[0];
+    nfloat[i] = cnt[1];
+  }
+}
+
+// K_i (reading of Section 3.2): the indicator of the subdomain when it is one
+// connected component whose rows all pass the zero-sum test (complex A: its
+// real form span{constant real parts, constant imaginary parts}, dimension 2);
+// {0} when no component floats
+__global__ void k_kernel_dim(const int32_t* nfloat, int nsub, int32_t* kdim, int pair) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nsub) kdim[i] = (nfail[i] == 0) ? (pair ? 2 : 1) : 0;
+  if (i < nsub) kdim[i] = nfloat[i] ? (pair ? 2 : 1) : 0;
 }
 
 // per padded local row of block k: the (column in block k + dk, value)
@@ -245,14 +321,18 @@ void extract_local(Ctx& c) {
   // kernel dimension | bandwidth in one block (one copy back)
   int32_t* kb = c.mem.alloc<int32_t>(2 * (size_t)nsub);
   int32_t* bw = kb + nsub;
-  int32_t* nfail = c.mem.alloc<int32_t>(nsub);
+  int32_t* nfail = c.mem.alloc<int32_t>(3 * (size_t)nsub);  // | ncomp | nfloat
+  int32_t* ncomp = nfail + nsub;
+  int32_t* nfloat = ncomp + nsub;
+  uint8_t* rbad = c.mem.alloc<uint8_t>(T);
+  int32_t* lab = c.mem.alloc<int32_t>(2 * T);  // | component has a failing row
   ADS_HIP(hipMemsetAsync(bw, 0, nsub * 4, s));
   ADS_HIP(hipMemsetAsync(nfail, 0, nsub * 4, s));
   ADS_HIP(hipMemsetAsync(cnt + T, 0, 4, s));
   unsigned gb = (unsigned)((T + 255) / 256);
   ADS_LAUNCH(k_extract_count, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
              c.om_sub, c.om_int, c.om_off, c.wlo, c.whi, c.woff, c.wpos, T, cnt, c.lsum, bw,
-             nfail, c.cplx);
+             nfail, rbad, c.cplx);
   int64_t* lrow = c.mem.alloc<int64_t>(T + 1);
   exclusive_scan_i64(cnt, lrow, T + 1, c.mem, s);
   std::vector<int64_t> hl;
@@ -263,10 +343,22 @@ void extract_local(Ctx& c) {
   c.lval = c.mem.alloc<double>(c.lnnz);
   ADS_LAUNCH(k_extract_fill, dim3(gb), dim3(256), 0, s, c.rowptr, c.col, c.val, c.om_sorted,
              c.om_sub, c.wlo, c.whi, c.woff, c.wpos, T, lrow, c.lcol, c.lval);
+  ADS_LAUNCH(k_components, dim3(nsub), dim3(1024), 0, s, c.om_off, lrow, c.lcol, rbad, lab,
+             lab + T, c.cplx, ncomp, nfloat);
   c.kdim = kb;
-  ADS_LAUNCH(k_kernel_dim, dim3((nsub + 255) / 256), dim3(256), 0, s, nfail, nsub, c.kdim, c.cplx);
-  std::vector<int32_t> hkb;
+  ADS_LAUNCH(k_kernel_dim, dim3((nsub + 255) / 256), dim3(256), 0, s, nfloat, nsub, c.kdim, c.cplx);
+  std::vector<int32_t> hkb, hcf;
   download(hkb, kb, 2 * (size_t)nsub, s);
+  download(hcf, ncomp, 2 * (size_t)nsub, s);
+  c.mem.release(lab);
+  c.mem.release(rbad);
+  c.mem.release(nfail);
+  for (int i = 0; i < nsub; ++i)
+    if (hcf[nsub + i] && hcf[i] > 1)
+      fail(ADS_ERR_UNSUPPORTED,
+           "subdomain " + std::to_string(i) + ": its splitting has " + std::to_string(hcf[i]) +
+               " connected components, " + std::to_string(hcf[nsub + i]) +
+               " of them floating; a kernel spanned by piecewise constants is not supported");
   c.h_kdim.assign(hkb.begin(), hkb.begin() + nsub);
   c.h_bw.resize(nsub);
   for (int i = 0; i < nsub; ++i) c.h_bw[i] = std::max(1, hkb[nsub + i]);

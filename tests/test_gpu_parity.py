@@ -99,6 +99,12 @@ def small_cases():
     # factors and general solves) with a floating centre subdomain
     A = W.convdiff3d(21, nu=0.02)
     out.append(("cd3d21-3x3x3-d2-general", A, W.block_partition_3d(21, 3, 3, 3), 27, 2, 6, 30, True))
+    # disconnected subdomains: each part is two strips of three grid rows,
+    # twelve rows apart, so every splitting has two connected components;
+    # every strip touches x = 0 and x = 1, so none floats (K_i = {0})
+    A = W.convdiff2d(24, 0.05)
+    out.append(("cd24-strips-mod4-disconnected", A, W.strip_partition(24, 3) % 4, 4, 2, 5, 30,
+                True))
     A, part, N, o = W.config("c4_lognormal2d_256_blocks64")  # the full-size learned-start workload
     out.append(("c4-lognormal256-blocks64", A, part, N, o["overlap"], o["nev"], o["restart"],
                 o["flexible"]))
@@ -489,6 +495,28 @@ def test_overlap0_coarse_space_is_unsupported():
     with pytest.raises(ads.AdsError) as e:
         ads.Context(A, W.block_partition_2d(20, 2), 4, 0, 3)
     assert e.value.status == ads.ADS_ERR_UNSUPPORTED
+
+
+def test_floating_components_of_disconnected_subdomains_are_refused():
+    """Parts of two strips four grid rows apart with Neumann rows at x = 0, 1:
+    the strips away from y = 0 and y = 1 float, so the kernel of a splitting
+    is spanned by the indicators of its floating components (dimensions 1, 2
+    and 1 in the oracle).  The library finds the components and refuses the
+    subdomains whose kernel is not the constant, naming the first one."""
+    part = (W.strip_partition(12, 2) % 3).astype(np.int32)
+    A = W.convdiff2d(12, 0.05, neumann_x=True)
+    As = A.to_scipy()
+    kd = [OS.kernel_dimension(OS.block_splitting(As, sub)[2])
+          for sub in OS.subdomains(As, part, 3, 1)]
+    assert kd == [1, 2, 1]
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(A, part, 3, 1, 4)
+    print(e.value, flush=True)
+    assert e.value.status == ads.ADS_ERR_UNSUPPORTED
+    assert "subdomain 0" in str(e.value) and "2 connected components" in str(e.value)
+    ok = ads.Context(W.convdiff2d(12, 0.05), part, 3, 1, 4)  # Dirichlet: nothing floats
+    assert list(ok.info["kernel_dim"]) == [0, 0, 0]
+    ok.close()
 
 
 def test_errors_are_reported_not_raised():
