@@ -555,46 +555,78 @@ struct BfArgs {
   const int64_t* d_off;     // per subdomain: start of its s_i x s_i FP64 work matrices
 };
 
-static constexpr int BF_RB = 8;  // rows of D_k per workgroup of the build pass
+static constexpr int BF_U = 4;  // independent elements per thread and pass (loads in flight)
 
+// D_k rows rr0 .. rr0 + rb - 1 of every subdomain (grid: subdomain x row
+// groups; rb * (largest s) doubles of LDS).  Each wave takes rows rr0 + w,
+// rr0 + w + (waves), ...: first its lanes scatter the row's entries of A_kk
+// (the splitting's diagonal changes included; the columns of a row are
+// unique) into LDS, then every element takes its entry and subtracts the
+// Schur terms of the row's A_k,k-1 couplings (uniform per row), BF_U
+// elements per lane at a time so that their loads of P_{k-1} are in flight
+// together.
 __global__ void __launch_bounds__(256)
-k_bf_build(BfArgs a, int k, int splitting, double* D, const double* Pp) {
+k_bf_build(BfArgs a, int k, int splitting, double* D, const double* Pp, int rb) {
+  extern __shared__ double Ls[];
   const int i = blockIdx.x;
   const int s = a.bs[i], K = a.nb[i], n = a.ni[i];
-  const int rr0 = blockIdx.y * BF_RB;
+  const int rr0 = blockIdx.y * rb;
   if (rr0 >= s) return;
-  double* Di = D + a.d_off[i];
+  const int nr = min(rb, s - rr0), tot = nr * s;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* Di = D + a.d_off[i] + (int64_t)rr0 * s;
   const double* Pi = Pp + a.d_off[i];
   const int r0 = k * s;
   const bool regularise = splitting && a.kdim[i];
-  for (int rr = rr0; rr < min(s, rr0 + BF_RB); ++rr) {
-    const int r = r0 + rr;
-    double* Drow = Di + (int64_t)rr * s;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) Ls[e] = 0.0;
+  __syncthreads();
+  for (int rr = w; rr < nr; rr += nw) {
+    const int row = rr0 + rr, r = r0 + row;
+    double* L = Ls + rr * s;
     if (k >= K || r >= n) {  // identity rows: past the last block, or padding
-      for (int j = threadIdx.x; j < s; j += blockDim.x) Drow[j] = j == rr ? 1.0 : 0.0;
+      if (lane == 0) L[row] = 1.0;
       continue;
     }
     const int64_t f = a.om_off[i] + r;
-    const int64_t q0 = a.lrow[f], q1 = a.lrow[f + 1];
-    const int64_t fp = (a.pad_off[i] + r) * adsd::NCPL;  // coupling slots of this row
-    for (int j = threadIdx.x; j < s; j += blockDim.x) {
-      double v = 0.0;
-      for (int64_t q = q0; q < q1; ++q) {
-        if (a.lcol[q] - r0 != j) continue;
-        double x = a.lval[q];
-        if (j == rr && splitting) {
-          if (!a.om_int[f]) x -= a.lsum[f];
-          if (regularise && r >= n - a.kdim[i]) x *= 2.0;
-        }
-        v = x;
+    for (int64_t q = a.lrow[f] + lane; q < a.lrow[f + 1]; q += 64) {
+      const int j = a.lcol[q] - r0;
+      if (j < 0 || j >= s) continue;
+      double x = a.lval[q];
+      if (j == row && splitting) {
+        if (!a.om_int[f]) x -= a.lsum[f];
+        if (regularise && r >= n - a.kdim[i]) x *= 2.0;
       }
-      if (k > 0)
+      L[j] = x;
+    }
+  }
+  __syncthreads();
+  for (int rr = w; rr < nr; rr += nw) {
+    const int r = r0 + rr0 + rr;
+    int cc[adsd::NCPL];
+    double cv[adsd::NCPL];
+    const bool schur = k > 0 && k < K && r < n;
+    const int64_t fp = (a.pad_off[i] + (schur ? r : 0)) * adsd::NCPL;  // coupling slots of this row
 #pragma unroll
-        for (int m = 0; m < adsd::NCPL; ++m) {
-          const int cc = a.cpl_col[fp + m];
-          if (cc >= 0) v -= a.cpl_val[fp + m] * Pi[(int64_t)cc * s + j];
-        }
-      Drow[j] = v;
+    for (int m = 0; m < adsd::NCPL; ++m) {
+      cc[m] = schur ? a.cpl_col[fp + m] : -1;
+      cv[m] = schur ? a.cpl_val[fp + m] : 0.0;
+    }
+    const double* L = Ls + rr * s;
+    double* Dr = Di + (int64_t)rr * s;
+    for (int j0 = lane; j0 < s; j0 += 64 * BF_U) {
+      double v[BF_U];
+#pragma unroll
+      for (int u = 0; u < BF_U; ++u) {
+        const int j = min(j0 + 64 * u, s - 1);
+        double x = L[j];
+#pragma unroll
+        for (int m = 0; m < adsd::NCPL; ++m)
+          if (cc[m] >= 0) x -= cv[m] * Pi[(int64_t)cc[m] * s + j];
+        v[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < BF_U; ++u)
+        if (j0 + 64 * u < s) Dr[j0 + 64 * u] = v[u];
     }
   }
 }
@@ -621,23 +653,39 @@ k_bf_store(BfArgs a, int k, const double* Ginv, double* Pp, FT* fac, int rb) {
   double* Gs = sh;
   double* Ps = sh + (int64_t)rb * s;
   const double* G = Ginv + a.d_off[i] + (int64_t)r0 * s;
-  for (int e = threadIdx.x; e < nr * s; e += blockDim.x) Gs[e] = G[e];
+  const int tot = nr * s;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += BF_U * blockDim.x) {  // BF_U loads in flight
+    double v[BF_U];
+#pragma unroll
+    for (int u = 0; u < BF_U; ++u) v[u] = G[min(e0 + u * (int)blockDim.x, tot - 1)];
+#pragma unroll
+    for (int u = 0; u < BF_U; ++u)
+      if (e0 + u * (int)blockDim.x < tot) Gs[e0 + u * blockDim.x] = v[u];
+  }
   __syncthreads();
   const bool more = k + 1 < K;
   if (more) {
+    // one column of A_k,k+1 per thread: its coupling list once, then its
+    // entries of the nr rows of P_k
     const int64_t cbase = a.pad_off[i] + (int64_t)(k + 1) * s;  // padded columns of block k + 1
     double* P = Pp + a.d_off[i] + (int64_t)r0 * s;
-    for (int e = threadIdx.x; e < nr * s; e += blockDim.x) {
-      const int rr = e / s, cidx = e % s;
+    for (int cidx = threadIdx.x; cidx < s; cidx += blockDim.x) {
       const int64_t fc = (cbase + cidx) * adsd::NCPL;
-      double pv = 0.0;
+      int rw[adsd::NCPL];
+      double uv[adsd::NCPL];
 #pragma unroll
       for (int m = 0; m < adsd::NCPL; ++m) {
-        const int rw = a.ucpl_row[fc + m];
-        if (rw >= 0) pv += Gs[rr * s + rw] * a.ucpl_val[fc + m];
+        rw[m] = a.ucpl_row[fc + m];
+        uv[m] = a.ucpl_val[fc + m];
       }
-      Ps[e] = pv;
-      P[e] = pv;
+      for (int rr = 0; rr < nr; ++rr) {
+        double pv = 0.0;
+#pragma unroll
+        for (int m = 0; m < adsd::NCPL; ++m)
+          if (rw[m] >= 0) pv += Gs[rr * s + rw[m]] * uv[m];
+        Ps[rr * s + cidx] = pv;
+        P[(int64_t)rr * s + cidx] = pv;
+      }
     }
     __syncthreads();
   }
@@ -674,7 +722,10 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
   double* Pp = c.mem.alloc<double>(hd[nsub]);
   BfArgs a{c.lptr_off, c.lcol, c.lval, c.lsum, c.om_int, c.om_off, c.ni, c.bs, c.nb, c.fac_off,
            c.kdim, c.pad_off, c.cpl_col, c.cpl_val, c.ucpl_row, c.ucpl_val, d_off};
-  const dim3 gb(nsub, (unsigned)((smax + BF_RB - 1) / BF_RB));
+  // rows of D_k per workgroup of the build pass (their A_kk entries in LDS)
+  const int rbb = std::max(1, std::min(8, 4096 / std::max(smax, 1)));
+  const dim3 gb(nsub, (unsigned)((smax + rbb - 1) / rbb));
+  const size_t bd_lds = (size_t)rbb * smax * 8;
   // rows of G_k per workgroup of the store pass: G and P rows in LDS
   const int rb = std::max(1, std::min(8, 10240 / std::max(smax, 1)));
   const dim3 gs(nsub, (unsigned)((smax + rb - 1) / rb));
@@ -719,14 +770,14 @@ static void factor_batched(Ctx& c, int splitting, void** out) {
     const int64_t* ek = eoff + at_e[k];
     const int32_t* sk = soff + at_s[k];
     const int64_t nrow = h_soff[at_s[k] + na];
-    ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
+    ADS_LAUNCH(k_bf_build, gb, dim3(256), bd_lds, st, a, k, splitting, D, Pp, rbb);
     // symmetric A: the D_k are symmetric positive definite (Schur complements
     // of the SPD local matrices), inverted without interchanges; a pivot that
     // is not positive sends this block step back to partial pivoting
     double* inv =
         gj_invert_batched(c, st, na, smx, nrow, tot, D, F, ek, sk, bads + k, c.sym, orders.data());
     if (!inv) {
-      ADS_LAUNCH(k_bf_build, gb, dim3(256), 0, st, a, k, splitting, D, Pp);
+      ADS_LAUNCH(k_bf_build, gb, dim3(256), bd_lds, st, a, k, splitting, D, Pp, rbb);
       inv = gj_invert_batched(c, st, na, smx, nrow, tot, D, F, ek, sk, bads + k, false,
                               orders.data());
     }
