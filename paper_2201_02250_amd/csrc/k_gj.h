@@ -822,12 +822,16 @@ struct GjPanel {
 // = picks[l] (the tournament's pick order, in which every multiplier is at
 // most 1 in magnitude) or, with picks = nullptr, row kp + l (symmetric
 // positive definite systems, whose pivots stay positive without
-// interchanges).  256
-// threads; thread t owns the NBK/16 x NBK/16 block (t / 16, t % 16) in
-// registers; per step the pivot row and column go through a double-buffered
-// LDS slot (one barrier per step).  Rows and columns past kb are the
-// identity.  A pivot that is not finite, zero, or (spd = 1) not positive sets
-// *bad to sy + 1.  Pinv[sy] is NBK x NBK, row-major.
+// interchanges).  256 threads; thread t owns the entries (br + 16 ii, bc +
+// 16 jj), br = t / 16, bc = t % 16, ii, jj < NBK / 16, in registers, so the
+// register holding row or column m is the same in every thread (m / 16) and
+// only the owners (br or bc = m % 16) differ.  Per step the pivot row and
+// column go through a double-buffered LDS slot (one barrier per step); every
+// entry takes the rank-one update, then the owners of column m and of row m
+// overwrite theirs with -a(i, m) / p and a(m, j) / p (1 / p at the pivot).
+// Rows and columns past kb are the identity.  A pivot that is not finite,
+// zero, or (spd = 1) not positive sets *bad to sy + 1.  Pinv[sy] is NBK x
+// NBK, row-major.
 template <int NBK>
 __global__ void __launch_bounds__(256)
 k_gj_block_inv(GjPanel in, const int32_t* sys_coff, int kp, const int32_t* picks, int pstride,
@@ -844,12 +848,12 @@ k_gj_block_inv(GjPanel in, const int32_t* sys_coff, int kp, const int32_t* picks
   double a[Q][Q];
 #pragma unroll
   for (int ii = 0; ii < Q; ++ii) {
-    const int l = Q * br + ii;
+    const int l = br + 16 * ii;
     int row = -1;
     if (l < kb) row = picks ? picks[(int64_t)sy * pstride + l] : kp + l;
 #pragma unroll
     for (int jj = 0; jj < Q; ++jj) {
-      const int j = Q * bc + jj;
+      const int j = bc + 16 * jj;
       const bool inb = l < kb && j < kb;
       const double x = gj_keep(A[(int64_t)max(row, 0) * ld + c0 + min(j, kb - 1)], inb && row >= 0);
       a[ii][jj] = inb ? x : (l == j ? 1.0 : 0.0);
@@ -857,64 +861,58 @@ k_gj_block_inv(GjPanel in, const int32_t* sys_coff, int kp, const int32_t* picks
   }
   bool sing = false;
   for (int m = 0; m < kb; ++m) {
-    const int b = m & 1, mq = m / Q, mr = m % Q;
-    // the owners publish row m and column m of their block: the entry of
-    // the block is chosen by selects (no branch per register), the Q values
-    // go out as one contiguous store
-    if (br == mq) {
-      double v[Q];
+    const int b = m & 1, mq = m >> 4, mr = m & 15;  // register index mq is uniform
+    if (br == mr) {
 #pragma unroll
-      for (int jj = 0; jj < Q; ++jj) {
-        v[jj] = a[0][jj];
+      for (int ii = 0; ii < Q; ++ii)
+        if (ii == mq)
 #pragma unroll
-        for (int ii = 1; ii < Q; ++ii) v[jj] = mr == ii ? a[ii][jj] : v[jj];
-      }
-#pragma unroll
-      for (int jj = 0; jj < Q; ++jj) prow[b][Q * bc + jj] = v[jj];
+          for (int jj = 0; jj < Q; ++jj) prow[b][bc + 16 * jj] = a[ii][jj];
     }
-    if (bc == mq) {
-      double v[Q];
+    if (bc == mr) {
 #pragma unroll
-      for (int ii = 0; ii < Q; ++ii) {
-        v[ii] = a[ii][0];
+      for (int jj = 0; jj < Q; ++jj)
+        if (jj == mq)
 #pragma unroll
-        for (int jj = 1; jj < Q; ++jj) v[ii] = mr == jj ? a[ii][jj] : v[ii];
-      }
-#pragma unroll
-      for (int ii = 0; ii < Q; ++ii) pcol[b][Q * br + ii] = v[ii];
+          for (int ii = 0; ii < Q; ++ii) pcol[b][br + 16 * ii] = a[ii][jj];
     }
     __syncthreads();
     // every read of the step issued before the first use
     const double piv = prow[b][m];
     double pr[Q], pc[Q];
 #pragma unroll
-    for (int jj = 0; jj < Q; ++jj) pr[jj] = prow[b][Q * bc + jj];
+    for (int jj = 0; jj < Q; ++jj) pr[jj] = prow[b][bc + 16 * jj];
 #pragma unroll
-    for (int ii = 0; ii < Q; ++ii) pc[ii] = pcol[b][Q * br + ii];
+    for (int ii = 0; ii < Q; ++ii) pc[ii] = pcol[b][br + 16 * ii];
     sing |= !(fabs(piv) < INFINITY) || (spd ? !(piv > 0.0) : !(piv != 0.0));
     const double inv = piv != 0.0 ? 1.0 / piv : 1.0;
+    double f[Q];
 #pragma unroll
     for (int ii = 0; ii < Q; ++ii) {
-      const int i = Q * br + ii;
-      const double f = pc[ii] * inv;
+      f[ii] = pc[ii] * inv;
 #pragma unroll
-      for (int jj = 0; jj < Q; ++jj) {
-        const int j = Q * bc + jj;
-        const double x = a[ii][jj];
-        double y;
-        if (i == m)
-          y = j == m ? inv : x * inv;
-        else
-          y = j == m ? -f : x - f * pr[jj];
-        a[ii][jj] = y;
-      }
+      for (int jj = 0; jj < Q; ++jj) a[ii][jj] = a[ii][jj] - f[ii] * pr[jj];
+    }
+    if (bc == mr) {  // column m: -a(i, m) / p
+#pragma unroll
+      for (int jj = 0; jj < Q; ++jj)
+        if (jj == mq)
+#pragma unroll
+          for (int ii = 0; ii < Q; ++ii) a[ii][jj] = -f[ii];
+    }
+    if (br == mr) {  // row m: a(m, j) / p, and 1 / p at the pivot
+#pragma unroll
+      for (int ii = 0; ii < Q; ++ii)
+        if (ii == mq)
+#pragma unroll
+          for (int jj = 0; jj < Q; ++jj) a[ii][jj] = (bc == mr && jj == mq) ? inv : pr[jj] * inv;
     }
   }
   double* out = Pinv + (int64_t)sy * NBK * NBK;
 #pragma unroll
   for (int ii = 0; ii < Q; ++ii)
 #pragma unroll
-    for (int jj = 0; jj < Q; ++jj) out[(Q * br + ii) * NBK + Q * bc + jj] = a[ii][jj];
+    for (int jj = 0; jj < Q; ++jj) out[(br + 16 * ii) * NBK + bc + 16 * jj] = a[ii][jj];
   if (t == 0 && sing) atomicMax(bad, sy + 1);
 }
 
