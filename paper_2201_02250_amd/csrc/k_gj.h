@@ -569,6 +569,10 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
   // a pass: S' rows i0 .. i0 + 63 by panel columns kc .. kc + GM_K - 1
   // (element e = t + GM_T q: row e / GM_K, column e % GM_K) and the source
   // rows of those columns by the tile's 64 columns (row e / 64, column e % 64)
+  // the values are loaded raw from clamped addresses and masked only when
+  // they go to LDS, so no arithmetic on them sits between the prefetch of
+  // the next pass and the products of the current one (which would make the
+  // wave wait for the loads before its products)
   constexpr int NQ = 64 * GM_K / GM_T;
   double sv[NQ], rv[NQ];
   auto load_pass = [&](int kc) {
@@ -577,10 +581,9 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
       const int e = t + GM_T * q;
       const int sr = e / GM_K, sc = e % GM_K, rr = e / 64, rc = e % 64;
       const int i = i0 + sr, j = j0 + rc;
-      sv[q] = gj_keep(S[(int64_t)min(i, n - 1) * nb + min(kc + sc, kb - 1)], i < n && kc + sc < kb);
+      sv[q] = S[(int64_t)min(i, n - 1) * nb + min(kc + sc, kb - 1)];
       const int kr = min(kc + rr, kb - 1);
-      rv[q] = gj_keep(A[(int64_t)(ident ? k0 + kr : rsrc[kr]) * n + min(j, n - 1)],
-                      kc + rr < kb && j < n);
+      rv[q] = A[(int64_t)(ident ? k0 + kr : rsrc[kr]) * n + min(j, n - 1)];
     }
   };
   load_pass(0);
@@ -601,12 +604,15 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = t + GM_T * q;
-      const int sr = e / GM_K, sc = e % GM_K;
-      Ssh[sr * GM_SLD + sc] = sv[q] - ((kc + sc < kb && i0 + sr == k0 + kc + sc) ? 1.0 : 0.0);
-      Rsh[(e / 64) * GM_RLD + e % 64] = rv[q];
+      const int sr = e / GM_K, sc = e % GM_K, rr = e / 64, rc = e % 64;
+      const bool incol = kc + sc < kb;
+      Ssh[sr * GM_SLD + sc] = gj_keep(sv[q], i0 + sr < n && incol) -
+                              ((incol && i0 + sr == k0 + kc + sc) ? 1.0 : 0.0);
+      Rsh[rr * GM_RLD + rc] = gj_keep(rv[q], kc + rr < kb && j0 + rc < n);
     }
     __syncthreads();
     if (kc + GM_K < kb) load_pass(kc + GM_K);  // in flight during the products below
+    __builtin_amdgcn_sched_barrier(0);
     const int kp = min(GM_K, (kb - kc + 3) & ~3);
     for (int kk = 0; kk < kp; kk += 4) {
       const double a0 = Ssh[(wr + li) * GM_SLD + kk + lk];
@@ -680,9 +686,17 @@ k_gj_mirror(double* A_all, const int64_t* E_off, const int32_t* sys_coff, int T,
   const int i0 = ti * 64, j0 = tj * 64;
   if (ti == tj || i0 >= n || j0 >= n) return;
   double* A = A_all + E_off[sy];
-  for (int e = threadIdx.x; e < 64 * 64; e += GM_T) {
-    const int ii = e / 64, jj = e % 64;
-    Tl[ii * 65 + jj] = (i0 + ii < n && j0 + jj < n) ? A[(int64_t)(i0 + ii) * n + j0 + jj] : 0.0;
+  double v[64 * 64 / GM_T];  // every load in flight before the first store
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / GM_T; ++q) {
+    const int e = threadIdx.x + GM_T * q, ii = e / 64, jj = e % 64;
+    v[q] = A[(int64_t)min(i0 + ii, n - 1) * n + min(j0 + jj, n - 1)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / GM_T; ++q) {
+    const int e = threadIdx.x + GM_T * q, ii = e / 64, jj = e % 64;
+    Tl[ii * 65 + jj] = gj_keep(v[q], i0 + ii < n && j0 + jj < n);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * 64; e += GM_T) {
@@ -959,7 +973,11 @@ k_gj_panel_form(GjPanel in, const int32_t* sys_coff, int kp, const double* Pinv,
   if (kp >= n || i0 >= n) return;
   const int kb = min(NBK, n - kp);
   const double* Pi = Pinv + (int64_t)sy * NBK * NBK;
-  for (int e = t; e < NBK * 64; e += 256) Ps[(e >> 6) * LD + (e & 63)] = Pi[(e >> 6) * NBK + c0 + (e & 63)];
+#pragma unroll
+  for (int q = 0; q < NBK / 4; ++q) {  // all loads of the slab in flight together
+    const int e = t + 256 * q;
+    Ps[(e >> 6) * LD + (e & 63)] = Pi[(e >> 6) * NBK + c0 + (e & 63)];
+  }
   const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int ia = i0 + 16 * w + li;  // this lane's row of the A operand
   const int ra = ia < n ? (src_all ? src_all[base + ia] : ia) : 0;
@@ -1098,23 +1116,40 @@ k_gj_combine(const int32_t* sys_coff, int k0, const double* Wbuf, double* Sbuf) 
     }
     return;
   }
-  for (int e = t; e < 64 * 64; e += 256) {  // X = W(P2, :), zero past the matrix
-    const int mm = e >> 6, l = e & 63;
-    Xs[mm * LD + l] = gj_keep(W[(int64_t)min(k0 + 64 + mm, n - 1) * 64 + l], mm < kb2);
-  }
+  // every load first (raw, from clamped addresses), the masks afterwards, so
+  // that all of them are in flight together
   const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int ia = i0 + 16 * w + li;  // this lane's row of the S2 operand
   const double* s2 = S + (int64_t)min(ia, n - 1) * 128 + 64;
-  double av[16], wv[4][4];
+  double xl[16], av[16], wv[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) av[q] = gj_keep(s2[4 * q + lk], ia < n);
+  for (int q = 0; q < 16; ++q) {  // X = W(P2, :), zero past the matrix
+    const int e = t + 256 * q;
+    xl[q] = W[(int64_t)min(k0 + 64 + (e >> 6), n - 1) * 64 + (e & 63)];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) av[q] = s2[4 * q + lk];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      wv[c][r] = W[(int64_t)min(i0 + 16 * w + lk + 4 * r, n - 1) * 64 + 16 * c + li];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + 256 * q;
+    const int mm = e >> 6, l = e & 63;
+    Xs[mm * LD + l] = gj_keep(xl[q], mm < kb2);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) av[q] = gj_keep(av[q], ia < n);
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + 16 * w + lk + 4 * r;
       const bool p2 = i >= k0 + 64 && i < k0 + 64 + kb2;
-      wv[c][r] = gj_keep(W[(int64_t)min(i, n - 1) * 64 + 16 * c + li], i < n && !p2);
+      wv[c][r] = gj_keep(wv[c][r], i < n && !p2);
     }
   __syncthreads();
   gj_d4 acc[4];
