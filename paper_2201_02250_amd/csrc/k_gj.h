@@ -411,6 +411,17 @@ static constexpr int GM_SLD = GM_K + 1;
 static constexpr int GM_RLD = 64 + 4;
 
 static constexpr int GM_GROUP = 16;  // tile rows per column-major sweep
+static constexpr int GM_O32_MAX = 23170;  // largest order whose n^2 doubles stay below 2^32 bytes
+
+// base[idx], with a 32-bit unsigned byte offset when O32 (0 <= idx and 8 idx
+// < 2^32)
+template <bool O32>
+__device__ __forceinline__ double gj_ld(const double* base, int64_t idx) {
+  if constexpr (O32)
+    return *(const double*)((const char*)base + (size_t)(8u * (unsigned)idx));
+  else
+    return base[idx];
+}
 
 // Tile of workgroup h in a one-dimensional grid of T x T tiles per system
 // times nsys.  Workgroups are dispatched to the eight XCDs (each with its
@@ -516,7 +527,13 @@ __device__ inline void gj_band_tile_of(int h, int T, int bl, int bq, int& ti, in
 // part (sym = 1): 0 every lower tile; 1 only the band of the next block (the
 // tiles the next block's panel kernels read, which can then start while
 // part 2 runs), 2 every lower tile outside that band.
-__global__ void __launch_bounds__(GM_T)
+//
+// O32 (every system of order <= GM_O32_MAX): the loads address their
+// system's matrix and panel with 32-bit byte offsets from a uniform base
+// (one register per address instead of two), which fits the kernel in 128
+// registers, four waves per SIMD.
+template <bool O32>
+__global__ void __launch_bounds__(GM_T, O32 ? 4 : 1)
 k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const int32_t* sys_coff,
                  int k0, int nb, const double* Sbuf, const int32_t* src_all, int T, int nsys,
                  int sym, int mir_lo, int part) {
@@ -581,9 +598,9 @@ k_gj_update_mfma(const double* Ain, double* Aout, const int64_t* E_off, const in
       const int e = t + GM_T * q;
       const int sr = e / GM_K, sc = e % GM_K, rr = e / 64, rc = e % 64;
       const int i = i0 + sr, j = j0 + rc;
-      sv[q] = S[(int64_t)min(i, n - 1) * nb + min(kc + sc, kb - 1)];
+      sv[q] = gj_ld<O32>(S, (int64_t)min(i, n - 1) * nb + min(kc + sc, kb - 1));
       const int kr = min(kc + rr, kb - 1);
-      rv[q] = A[(int64_t)(ident ? k0 + kr : rsrc[kr]) * n + min(j, n - 1)];
+      rv[q] = gj_ld<O32>(A, (int64_t)(ident ? k0 + kr : rsrc[kr]) * n + min(j, n - 1));
     }
   };
   load_pass(0);
@@ -1353,9 +1370,14 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         ADS_HIP(hipEventCreate(&e1));
         ADS_HIP(hipEventRecord(e0, st));
       }
-      ADS_LAUNCH(k_gj_update_mfma, dim3(grid), dim3(GM_T), 0, st, bufs[cur], bufs[1 - cur], E_off,
-                 sys_coff, (int)k0, nb, Sb[sl], (const int32_t*)nullptr, (int)tiles, nsys, 1,
-                 mir_lo, part);
+      if (maxs <= GM_O32_MAX)
+        ADS_LAUNCH(k_gj_update_mfma<true>, dim3(grid), dim3(GM_T), 0, st, bufs[cur], bufs[1 - cur],
+                   E_off, sys_coff, (int)k0, nb, Sb[sl], (const int32_t*)nullptr, (int)tiles, nsys,
+                   1, mir_lo, part);
+      else
+        ADS_LAUNCH(k_gj_update_mfma<false>, dim3(grid), dim3(GM_T), 0, st, bufs[cur], bufs[1 - cur],
+                   E_off, sys_coff, (int)k0, nb, Sb[sl], (const int32_t*)nullptr, (int)tiles, nsys,
+                   1, mir_lo, part);
       if (prof) {
         ADS_HIP(hipEventRecord(e1, st));
         c.prof_gj_ev.push_back({e0, e1});
@@ -1442,9 +1464,14 @@ double* gj_invert_batched(Ctx& c, hipStream_t st, int nsys, int64_t maxs, int64_
         ADS_HIP(hipEventCreate(&e1));
         ADS_HIP(hipEventRecord(e0, st));
       }
-      ADS_LAUNCH(k_gj_update_mfma, dim3(tiles * tiles * (unsigned)nsys), dim3(GM_T), 0, st,
-                 bufs[cur], bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S,
-                 (const int32_t*)src, (int)tiles, nsys, 0, -1, 0);
+      if (maxs <= GM_O32_MAX)
+        ADS_LAUNCH(k_gj_update_mfma<true>, dim3(tiles * tiles * (unsigned)nsys), dim3(GM_T), 0, st,
+                   bufs[cur], bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S,
+                   (const int32_t*)src, (int)tiles, nsys, 0, -1, 0);
+      else
+        ADS_LAUNCH(k_gj_update_mfma<false>, dim3(tiles * tiles * (unsigned)nsys), dim3(GM_T), 0, st,
+                   bufs[cur], bufs[1 - cur], E_off, sys_coff, (int)k0, nb, S,
+                   (const int32_t*)src, (int)tiles, nsys, 0, -1, 0);
       if (prof) {
         ADS_HIP(hipEventRecord(e1, st));
         c.prof_gj_ev.push_back({e0, e1});
