@@ -1644,7 +1644,11 @@ __global__ void __launch_bounds__(1024) k_eig_op(const FT* fac, EigArgs a) {
   }
   __syncthreads();
   const int64_t cb = a.pad_off[i] * adsd::NCPL;
-  adsd::block_solve_general<FT, PC, false>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol,
+  // eight tile loads in flight per thread: the registers then allow one
+  // workgroup per compute unit, which streams the tiles faster than two with
+  // two loads each (the dependent block chain leaves each workgroup's loads
+  // as the only source of parallelism)
+  adsd::block_solve_general<FT, PC, true>(fac + a.fac_off[i], s, K, n, a.lrow + base, a.lcol,
                                            a.lval, a.cpl_ok ? a.cpl_col + cb : nullptr,
                                            a.cpl_ok ? a.cpl_val + cb : nullptr, Y,
                                     ld, pc, lds);
