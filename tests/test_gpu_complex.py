@@ -284,3 +284,31 @@ def test_complex_full_size_convection_diffusion():
     print(f"complex 256^2: n0 {P.n0} complex, span angle {worst:.1e}, its {inf['its'][0]} "
           f"(oracle {io['its']}), setup {info['t_phase_ms']}", flush=True)
     ctx.close()
+
+
+def test_complex_disconnected_subdomains():
+    """Disconnected subdomains of complex A (each part two strips four grid
+    rows apart, overlap 1; in the real form both rows of an unknown are one
+    vertex of the component search).  Dirichlet rows: nothing floats, the
+    kernel dimensions are 0 as in the oracle and the apply matches it.
+    Neumann rows at x = 0, 1: strips away from y = 0, 1 float, and the
+    subdomains whose kernel is not the complex constant are refused."""
+    part = (W.strip_partition(12, 2) % 3).astype(np.int32)
+    A = W.convdiff2d_complex(12, 0.02, eta=0.5, eta_y=0.0)
+    As = A.to_scipy()
+    P = OS.TwoLevelSchwarz(As, part, 3, 1, 4)
+    assert [e["kernel"] for e in P.eig] == [0, 0, 0]
+    ctx = ads.Context(A, part, 3, 1, 4, eig_tol=1e-12)
+    assert list(ctx.info["kernel_dim"]) == [0, 0, 0]
+    R = crand(A.n, 5, 2)
+    Z = ctx.apply(torch.tensor(R, device=DEV)).cpu().numpy()
+    Zo = P.apply(R)
+    err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    print(f"disconnected complex apply vs oracle {err:.1e}", flush=True)
+    assert err <= 1e-9
+    ctx.close()
+    An = W.convdiff2d_complex(12, 0.02, eta=0.5, eta_y=0.0, neumann_x=True)
+    with pytest.raises(ads.AdsError) as e:
+        ads.Context(An, part, 3, 1, 4)
+    print(e.value, flush=True)
+    assert e.value.status == ads.ADS_ERR_UNSUPPORTED and "subdomain 0" in str(e.value)
