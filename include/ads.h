@@ -192,8 +192,9 @@ typedef struct {
   int64_t n_kernel[4];    /* number of timed launches of each                         */
   /* optional caller-owned host arrays of length nsub (NULL to skip): */
   int32_t* nev_i;         /* coarse vectors per subdomain                             */
-  int32_t* kernel_dim;    /* dim ker(splitting) per subdomain (0 or 1; complex A:
-                             0 or 2, the real form of span{1})                      */
+  int32_t* kernel_dim;    /* dim ker(splitting) per subdomain (0, or 1 for a connected
+                             floating subdomain; complex A: 0 or 2, the real form
+                             of span{1})                                           */
   int32_t* n_i;           /* |Omega_i|                                                */
   int32_t* n_interior;    /* |Omega_Ii|                                               */
   int32_t* sweeps;        /* eigensolver sweeps (Krylov-Schur: block steps) per subdomain */
@@ -223,6 +224,10 @@ typedef struct {
  * local factorizations, local eigenproblems (eq. 5) and coarse space (eq. 6),
  * coarse operator E = Z^T A Z and its exact inverse (Gauss-Jordan elimination
  * with partial pivoting).
+ * The kernel of each splitting (Section 3.2) is spanned by the indicators of
+ * the connected components of its graph whose rows all sum to zero; a
+ * subdomain of several components of which at least one floats (a kernel of
+ * piecewise constants) returns ADS_ERR_UNSUPPORTED naming the subdomain.
  * *out receives a new context (NULL on error). */
 int ads_setup(const ads_csr* A, const int32_t* part, int32_t nparts, const ads_options* opts,
               void* hip_stream, ads_ctx** out);
